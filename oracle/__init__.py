@@ -1,0 +1,238 @@
+"""FP64 direct-summation oracle for the Pointing SelfCal hot path.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg may import this package; the product library never does.  It
+shares no code with the HIP path.  The C source (psc_oracle.c) is compiled
+with gcc into ``oracle/_build/liboracle.so`` by :func:`build`.
+
+Every function here is a thin ctypes marshaller around the C oracle, which
+evaluates the measurement equation (Sec. 2, Eq. ME / Eq. MEDD) by direct
+summation over sky pixels, its analytic offset derivative (Eq. DA), the
+per-antenna sums of Eq. DCHIDD and the damped update of Sec. 2.2.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "psc_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "_build", "liboracle.so")
+_lib = None
+_lock = threading.Lock()
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, FP64, no fast-math)."""
+    os.makedirs(os.path.dirname(_LIB_PATH), exist_ok=True)
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC", "-shared",
+               "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Problem(C.Structure):
+    _fields_ = [
+        ("n_src", C.c_int32),
+        ("src_l", C.POINTER(C.c_double)),
+        ("src_m", C.POINTER(C.c_double)),
+        ("src_flux", C.POINTER(C.c_double)),
+        ("n_ant", C.c_int32), ("n_chan", C.c_int32), ("n_pol", C.c_int32), ("n_int", C.c_int32),
+        ("n_row", C.c_int64),
+        ("int_row_ptr", C.POINTER(C.c_int64)),
+        ("ant1", C.POINTER(C.c_int32)),
+        ("ant2", C.POINTER(C.c_int32)),
+        ("uv_m", C.POINTER(C.c_double)),
+        ("freq_hz", C.POINTER(C.c_double)),
+        ("dish_diam_m", C.c_double),
+        ("illum", C.c_int32),
+        ("gauss_sigma_ld", C.c_double),
+        ("squint_frac", C.c_double),
+        ("snap_scale", C.c_double),
+    ]
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB_PATH):
+                build(force=False)
+            lib = C.CDLL(_LIB_PATH)
+            P = C.POINTER(_Problem)
+            dp = C.POINTER(C.c_double)
+            ip = C.POINTER(C.c_int32)
+            lib.oracle_efp.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
+                                       C.c_double, dp]
+            lib.oracle_hpbw.argtypes = [C.c_double, C.c_double]
+            lib.oracle_hpbw.restype = C.c_double
+            lib.oracle_snap_uv.argtypes = [P, C.c_int64, C.c_int, dp]
+            lib.oracle_predict.argtypes = [P, dp, dp, dp]
+            lib.oracle_gradient.argtypes = [P, dp, dp, dp, dp, dp]
+            lib.oracle_solve_step.argtypes = [C.c_int, C.c_int, C.c_int, dp, C.c_double, dp, ip, dp, ip]
+            lib.oracle_solve.argtypes = [P, dp, dp, dp, C.c_double, C.c_int, C.c_double, ip]
+            for name in ("oracle_predict", "oracle_gradient", "oracle_solve_step", "oracle_solve",
+                         "oracle_num_threads"):
+                getattr(lib, name).restype = C.c_int
+            _lib = lib
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32)) if a is not None else None
+
+
+class Problem:
+    """Plain-array description of a data set for the oracle.
+
+    ``src_l, src_m, src_flux``: non-zero sky pixels; ``uv_m``: [n_row, 2];
+    ``int_row_ptr``: [n_int+1]; ``freq_hz``: [n_chan].  ``snap_scale`` > 0
+    rounds uv (in wavelengths) to the lattice 1/snap_scale.
+    """
+
+    def __init__(self, src_l, src_m, src_flux, n_ant, ant1, ant2, uv_m, int_row_ptr, freq_hz,
+                 n_pol=1, dish_diam_m=25.0, illum=0, gauss_sigma_ld=1.0, squint_frac=0.0,
+                 snap_scale=0.0):
+        self.src_l = np.ascontiguousarray(src_l, np.float64)
+        self.src_m = np.ascontiguousarray(src_m, np.float64)
+        self.src_flux = np.ascontiguousarray(src_flux, np.float64)
+        self.ant1 = np.ascontiguousarray(ant1, np.int32)
+        self.ant2 = np.ascontiguousarray(ant2, np.int32)
+        self.uv_m = np.ascontiguousarray(uv_m, np.float64).reshape(-1, 2)
+        self.int_row_ptr = np.ascontiguousarray(int_row_ptr, np.int64)
+        self.freq_hz = np.ascontiguousarray(freq_hz, np.float64)
+        self.n_ant = int(n_ant)
+        self.n_pol = int(n_pol)
+        self.n_int = int(self.int_row_ptr.shape[0] - 1)
+        self.n_row = int(self.ant1.shape[0])
+        self.n_chan = int(self.freq_hz.shape[0])
+        self._s = _Problem(
+            int(self.src_flux.shape[0]), _dp(self.src_l), _dp(self.src_m), _dp(self.src_flux),
+            self.n_ant, self.n_chan, self.n_pol, self.n_int, self.n_row,
+            self.int_row_ptr.ctypes.data_as(C.POINTER(C.c_int64)), _ip(self.ant1), _ip(self.ant2),
+            _dp(self.uv_m), _dp(self.freq_hz), float(dish_diam_m), int(illum), float(gauss_sigma_ld),
+            float(squint_frac), float(snap_scale))
+
+    @classmethod
+    def from_observation(cls, obs, snap=True, **kw):
+        l, m, f = obs.sky_lm()
+        args = dict(n_pol=obs.n_pol, dish_diam_m=obs.wl.dish_diam_m, squint_frac=obs.wl.squint_frac,
+                    snap_scale=obs.snap_scale if snap else 0.0)
+        args.update(kw)
+        return cls(l, m, f, obs.n_ant, obs.ant1, obs.ant2, obs.uv_m, obs.int_row_ptr, obs.freq_hz,
+                   **args)
+
+    @property
+    def ref(self):
+        return C.byref(self._s)
+
+    def offsets_shape(self):
+        return (self.n_int, self.n_pol, self.n_ant, 2)
+
+    def vis_shape(self):
+        return (self.n_row, self.n_chan, self.n_pol)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with status {rc}")
+
+
+def efp(illum, dish_diam_m, gauss_sigma_ld, freq_hz, dl, dm):
+    """(E, dE/dp_l, dE/dp_m) of one antenna at sky offset (dl, dm) = l - p."""
+    lib = _load()
+    out = np.zeros(3)
+    lib.oracle_efp(int(illum), float(dish_diam_m), float(gauss_sigma_ld), float(freq_hz),
+                   float(dl), float(dm), _dp(out))
+    return out
+
+
+def hpbw(freq_hz, dish_diam_m):
+    return _load().oracle_hpbw(float(freq_hz), float(dish_diam_m))
+
+
+def snap_uv(prob: Problem, row: int, chan: int):
+    out = np.zeros(2)
+    _load().oracle_snap_uv(prob.ref, int(row), int(chan), _dp(out))
+    return out
+
+
+def _offs(prob, offsets):
+    o = np.ascontiguousarray(offsets, np.float64)
+    if o.shape != prob.offsets_shape():
+        raise ValueError(f"offsets shape {o.shape} != {prob.offsets_shape()}")
+    return o
+
+
+def predict(prob: Problem, offsets, want_grad=False):
+    """Model visibilities [n_row, n_chan, n_pol] complex128 and, if asked, their
+    derivatives [n_row, n_chan, n_pol, 4] (d/dl_i, d/dm_i, d/dl_j, d/dm_j)."""
+    lib = _load()
+    o = _offs(prob, offsets)
+    vis = np.zeros(prob.vis_shape() + (2,))
+    dvis = np.zeros(prob.vis_shape() + (4, 2)) if want_grad else None
+    _check(lib.oracle_predict(prob.ref, _dp(o), _dp(vis), _dp(dvis)), "predict")
+    v = vis[..., 0] + 1j * vis[..., 1]
+    if want_grad:
+        return v, dvis[..., 0] + 1j * dvis[..., 1]
+    return v
+
+
+def gradient(prob: Problem, offsets, vis_obs, weight, want_model=False):
+    """Per-antenna sums [n_int, n_pol, n_ant, 6] = chi, g_l, g_m, H_ll, H_lm, H_mm."""
+    lib = _load()
+    o = _offs(prob, offsets)
+    vo = np.ascontiguousarray(np.broadcast_to(vis_obs, prob.vis_shape()), np.complex128)
+    vo2 = np.ascontiguousarray(vo.view(np.float64))
+    w = np.ascontiguousarray(np.broadcast_to(weight, prob.vis_shape()), np.float64)
+    acc = np.zeros(prob.offsets_shape()[:3] + (6,))
+    vm = np.zeros(prob.vis_shape() + (2,)) if want_model else None
+    _check(lib.oracle_gradient(prob.ref, _dp(o), _dp(vo2), _dp(w), _dp(acc), _dp(vm)), "gradient")
+    if want_model:
+        return acc, vm[..., 0] + 1j * vm[..., 1]
+    return acc
+
+
+def solve_step(acc, gain, offsets, done=None):
+    """Returns (new offsets, not_updated [n_int,n_pol,n_ant], max_step [n_int])."""
+    lib = _load()
+    acc = np.ascontiguousarray(acc, np.float64)
+    n_int, n_pol, n_ant = acc.shape[:3]
+    o = np.array(offsets, dtype=np.float64, copy=True, order="C")
+    nu = np.zeros((n_int, n_pol, n_ant), np.int32)
+    mx = np.zeros(n_int)
+    d = None if done is None else np.ascontiguousarray(done, np.int32)
+    _check(lib.oracle_solve_step(n_int, n_pol, n_ant, _dp(acc), float(gain), _dp(o), _ip(nu),
+                                 _dp(mx), _ip(d)), "solve_step")
+    return o, nu, mx
+
+
+def solve(prob: Problem, vis_obs, weight, offsets0, gain=0.5, n_max=10, tol_rad=None):
+    """Algorithm 1: returns (offsets, iterations per interval)."""
+    from math import pi
+    lib = _load()
+    if tol_rad is None:
+        tol_rad = 1e-3 * pi / (180 * 3600)
+    o = np.array(_offs(prob, offsets0), dtype=np.float64, copy=True, order="C")
+    vo = np.ascontiguousarray(np.broadcast_to(vis_obs, prob.vis_shape()), np.complex128)
+    vo2 = np.ascontiguousarray(vo.view(np.float64))
+    w = np.ascontiguousarray(np.broadcast_to(weight, prob.vis_shape()), np.float64)
+    its = np.zeros(prob.n_int, np.int32)
+    _check(lib.oracle_solve(prob.ref, _dp(vo2), _dp(w), _dp(o), float(gain), int(n_max),
+                            float(tol_rad), _ip(its)), "solve")
+    return o, its
+
+
+def num_threads():
+    return _load().oracle_num_threads()

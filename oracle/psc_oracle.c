@@ -1,0 +1,415 @@
+/*
+ * psc_oracle.c -- plain FP64 CPU oracle for the Pointing SelfCal predict,
+ * gradient and update (Bhatnagar & Cornwell 2017, arXiv:1709.08681).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
+ * includes this file; only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark load it.  It shares no code, header, table or
+ * constant generator with the HIP path.
+ *
+ * What it computes (everything in double precision, by definition, with no
+ * gridding, tables, tapers or FFTs):
+ *
+ *  - predict: the measurement equation (Sec. 2, Eq. ME) with the
+ *    direction-independent term set to one, evaluated by direct summation over
+ *    the non-zero sky pixels.  The direction-dependent term of baseline (i,j)
+ *    is the product of the two antennas' far-field patterns (Eq. MEDD), each
+ *    shifted by that antenna's pointing offset (Sec. 3):
+ *        V_ij(u) = sum_p I_p E_i(l_p) E_j(l_p) exp(+2 pi i u.l_p)
+ *    E is the voltage pattern of a uniformly illuminated circular dish,
+ *    2 J1(x)/x with x = pi D |l| / lambda, or, in the Gaussian test mode, the
+ *    main-lobe model of Sec. 3, exp(-|l|^2 alpha^2) with alpha^2 = 1/(2 s^2).
+ *  - gradient: the analytic derivative of V with respect to the two offsets
+ *    of each end of the baseline (Eq. DA with a = (l_i, m_i)), and the
+ *    per-antenna sums of Eq. DCHIDD together with chi^2 (Eq. Chisq) and the
+ *    2x2 Gauss-Newton normal matrix.
+ *  - solve step: the damped update of Sec. 2.2 (a_n = a_{n-1} + f(grad)),
+ *    read as a per-antenna 2x2 Gauss-Newton step scaled by the loop gain
+ *    0 < gamma < 1 of Eq. SelfCal.
+ *
+ * Readings taken where the paper is silent or garbled (all listed in the
+ * design notes):
+ *  - Algorithm 1 accumulates into antenna j but updates antenna i; here every
+ *    stored baseline (i<j) contributes to both of its antennas.
+ *  - chi^2 is summed over stored baselines once; g_a = sum Re(conj(R) w dV/dp_a)
+ *    is minus one half of d chi^2 / d p_a, so p <- p + gamma H^-1 g descends.
+ *  - All antennas are updated together (Jacobi) from sums taken at the
+ *    previous iterate.
+ *  - Visibility uv coordinates (in wavelengths) are rounded to the lattice of
+ *    spacing 1/snap_scale before evaluation when snap_scale > 0; this is the
+ *    nearest-sample lookup of an oversampled A-Projection kernel.
+ *  - Polarisation p of antenna i has its beam centred at
+ *    offset + sgn(p) * squint_frac * HPBW(nu) along +l, sgn = (+1, -1),
+ *    HPBW = 1.02899 lambda / D.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#include "psc_oracle.h"
+
+#define ORC_C_LIGHT 299792458.0
+#define ORC_PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------ */
+/* Far-field pattern of one antenna and its derivative with respect to the  */
+/* antenna's pointing offset.                                               */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Airy voltage pattern of a uniformly illuminated circular aperture of
+ * diameter D: E = 2 J1(x)/x, x = k rho, k = pi D / lambda, rho = |l - p|.
+ * dE/dx = -2 J2(x)/x (Bessel recurrence), so
+ *   dE/dp_l = 2 J2(x)/x * k * (l - p_l)/rho = k^2 (l - p_l) * 2 J2(x)/x^2.
+ * 2 J2(x)/x^2 tends to 1/4 at x = 0.
+ */
+static void efp_airy(double k, double dl, double dm, double* e, double* de_dpl, double* de_dpm)
+{
+    double rho = sqrt(dl * dl + dm * dm);
+    double x = k * rho;
+    double e0, j2x2;
+    if (x == 0.0) {
+        e0 = 1.0;
+        j2x2 = 0.25;
+    } else if (x < 1e-4) {
+        /* leading terms of the power series of J1 and J2 */
+        e0 = 1.0 - x * x / 8.0;
+        j2x2 = 0.25 - x * x / 48.0;
+    } else {
+        e0 = 2.0 * j1(x) / x;
+        j2x2 = 2.0 * jn(2, x) / (x * x);
+    }
+    *e = e0;
+    *de_dpl = k * k * dl * j2x2;
+    *de_dpm = k * k * dm * j2x2;
+}
+
+/* Gaussian main-lobe model E = exp(-(dl^2+dm^2) alpha^2), alpha^2 = 1/(2 s^2). */
+static void efp_gauss(double s, double dl, double dm, double* e, double* de_dpl, double* de_dpm)
+{
+    double a2 = 1.0 / (2.0 * s * s);
+    double e0 = exp(-(dl * dl + dm * dm) * a2);
+    *e = e0;
+    *de_dpl = 2.0 * a2 * dl * e0;
+    *de_dpm = 2.0 * a2 * dm * e0;
+}
+
+static double hpbw_rad(double lambda, double dish)
+{
+    return 1.02899 * lambda / dish;
+}
+
+void oracle_efp(int illum, double dish_diam_m, double gauss_sigma_ld, double freq_hz,
+                double dl, double dm, double* out3)
+{
+    double lambda = ORC_C_LIGHT / freq_hz;
+    if (illum == 1)
+        efp_gauss(gauss_sigma_ld * lambda / dish_diam_m, dl, dm, &out3[0], &out3[1], &out3[2]);
+    else
+        efp_airy(ORC_PI * dish_diam_m / lambda, dl, dm, &out3[0], &out3[1], &out3[2]);
+}
+
+double oracle_hpbw(double freq_hz, double dish_diam_m)
+{
+    return hpbw_rad(ORC_C_LIGHT / freq_hz, dish_diam_m);
+}
+
+/* uv in wavelengths of one row at one frequency, optionally snapped. */
+static void row_uv(const orc_problem* p, int64_t r, int c, double* u, double* v)
+{
+    double f = p->freq_hz[c];
+    double uu = p->uv_m[2 * r] * f / ORC_C_LIGHT;
+    double vv = p->uv_m[2 * r + 1] * f / ORC_C_LIGHT;
+    if (p->snap_scale > 0.0) {
+        uu = (double)llround(uu * p->snap_scale) / p->snap_scale;
+        vv = (double)llround(vv * p->snap_scale) / p->snap_scale;
+    }
+    *u = uu;
+    *v = vv;
+}
+
+void oracle_snap_uv(const orc_problem* p, int64_t row, int chan, double* uv_out)
+{
+    row_uv(p, row, chan, &uv_out[0], &uv_out[1]);
+}
+
+/*
+ * Beam values of every antenna towards every source, for one interval:
+ * tab[((pol*n_ant + a)*n_chan + c)*n_src + s][3] = (E, dE/dl_a, dE/dm_a).
+ */
+static double* beam_table(const orc_problem* p, const double* offs_int /* [n_pol][n_ant][2] */)
+{
+    size_t n = (size_t)p->n_pol * p->n_ant * p->n_chan * p->n_src;
+    double* tab = (double*)malloc(n * 3 * sizeof(double));
+    if (!tab) return NULL;
+    for (int pol = 0; pol < p->n_pol; ++pol) {
+        double sgn = (pol == 0) ? 1.0 : -1.0;
+        for (int a = 0; a < p->n_ant; ++a) {
+            for (int c = 0; c < p->n_chan; ++c) {
+                double lambda = ORC_C_LIGHT / p->freq_hz[c];
+                double sq = sgn * p->squint_frac * hpbw_rad(lambda, p->dish_diam_m);
+                double pl = offs_int[(pol * p->n_ant + a) * 2 + 0] + sq;
+                double pm = offs_int[(pol * p->n_ant + a) * 2 + 1];
+                for (int s = 0; s < p->n_src; ++s) {
+                    double* t = tab + 3 * ((((size_t)pol * p->n_ant + a) * p->n_chan + c) * p->n_src + s);
+                    oracle_efp(p->illum, p->dish_diam_m, p->gauss_sigma_ld, p->freq_hz[c],
+                               p->src_l[s] - pl, p->src_m[s] - pm, t);
+                }
+            }
+        }
+    }
+    return tab;
+}
+
+/*
+ * Model visibility and its four offset derivatives for one (row, chan, pol):
+ * out[0..1] = V, out[2..9] = dV/dl_i, dV/dm_i, dV/dl_j, dV/dm_j (re, im each).
+ */
+static void vis_one(const orc_problem* p, const double* tab, int pol, int ai, int aj, int c,
+                    double u, double v, double* out, int want_grad)
+{
+    const double* ti = tab + 3 * ((((size_t)pol * p->n_ant + ai) * p->n_chan + c) * p->n_src);
+    const double* tj = tab + 3 * ((((size_t)pol * p->n_ant + aj) * p->n_chan + c) * p->n_src);
+    double acc[10] = {0};
+    for (int s = 0; s < p->n_src; ++s) {
+        double ph = 2.0 * ORC_PI * (u * p->src_l[s] + v * p->src_m[s]);
+        double cr = cos(ph), ci = sin(ph);
+        double fi = p->src_flux[s];
+        double ei = ti[3 * s], ej = tj[3 * s];
+        double a0 = fi * ei * ej;
+        acc[0] += a0 * cr;
+        acc[1] += a0 * ci;
+        if (want_grad) {
+            double d[4] = {fi * ti[3 * s + 1] * ej, fi * ti[3 * s + 2] * ej,
+                           fi * ei * tj[3 * s + 1], fi * ei * tj[3 * s + 2]};
+            for (int k = 0; k < 4; ++k) {
+                acc[2 + 2 * k] += d[k] * cr;
+                acc[3 + 2 * k] += d[k] * ci;
+            }
+        }
+    }
+    memcpy(out, acc, sizeof(acc));
+}
+
+static int check_problem(const orc_problem* p)
+{
+    if (!p || p->n_ant < 2 || p->n_chan < 1 || p->n_pol < 1 || p->n_pol > 2 || p->n_int < 1)
+        return -1;
+    if (p->n_row < 0 || p->n_src < 0) return -1;
+    if (p->int_row_ptr[0] != 0 || p->int_row_ptr[p->n_int] != p->n_row) return -1;
+    for (int s = 0; s < p->n_int; ++s)
+        if (p->int_row_ptr[s + 1] < p->int_row_ptr[s]) return -1;
+    for (int64_t r = 0; r < p->n_row; ++r) {
+        if (p->ant1[r] < 0 || p->ant2[r] < 0 || p->ant1[r] >= p->n_ant || p->ant2[r] >= p->n_ant ||
+            p->ant1[r] == p->ant2[r])
+            return -1;
+    }
+    return 0;
+}
+
+int oracle_predict(const orc_problem* p, const double* offsets, double* vis_out, double* dvis_out)
+{
+    if (check_problem(p)) return -1;
+    for (int s = 0; s < p->n_int; ++s) {
+        const double* offs_int = offsets + (size_t)s * p->n_pol * p->n_ant * 2;
+        double* tab = beam_table(p, offs_int);
+        if (!tab) return -2;
+        int64_t r0 = p->int_row_ptr[s], r1 = p->int_row_ptr[s + 1];
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t r = r0; r < r1; ++r) {
+            for (int c = 0; c < p->n_chan; ++c) {
+                double u, v;
+                row_uv(p, r, c, &u, &v);
+                for (int pol = 0; pol < p->n_pol; ++pol) {
+                    double out[10];
+                    vis_one(p, tab, pol, p->ant1[r], p->ant2[r], c, u, v, out, dvis_out != NULL);
+                    size_t idx = ((size_t)r * p->n_chan + c) * p->n_pol + pol;
+                    vis_out[2 * idx] = out[0];
+                    vis_out[2 * idx + 1] = out[1];
+                    if (dvis_out) memcpy(dvis_out + 8 * idx, out + 2, 8 * sizeof(double));
+                }
+            }
+        }
+        free(tab);
+    }
+    return 0;
+}
+
+/*
+ * Per-antenna accumulation of Eq. DCHIDD for every interval and polarisation:
+ * acc[((s*n_pol + pol)*n_ant + a)*6 + k], k = chi, g_l, g_m, H_ll, H_lm, H_mm.
+ * Also returns the model visibilities when vis_model_out is not NULL.
+ */
+int oracle_gradient(const orc_problem* p, const double* offsets, const double* vis_obs,
+                    const double* weight, double* acc, double* vis_model_out)
+{
+    if (check_problem(p)) return -1;
+    size_t n_acc = (size_t)p->n_int * p->n_pol * p->n_ant * 6;
+    memset(acc, 0, n_acc * sizeof(double));
+    int nthr = 1;
+#ifdef _OPENMP
+    nthr = omp_get_max_threads();
+#endif
+    size_t per = (size_t)p->n_pol * p->n_ant * 6;
+    double* part = (double*)calloc((size_t)nthr * per, sizeof(double));
+    if (!part) return -2;
+    for (int s = 0; s < p->n_int; ++s) {
+        const double* offs_int = offsets + (size_t)s * p->n_pol * p->n_ant * 2;
+        double* tab = beam_table(p, offs_int);
+        if (!tab) {
+            free(part);
+            return -2;
+        }
+        memset(part, 0, (size_t)nthr * per * sizeof(double));
+        int64_t r0 = p->int_row_ptr[s], r1 = p->int_row_ptr[s + 1];
+#pragma omp parallel
+        {
+            int tid = 0;
+#ifdef _OPENMP
+            tid = omp_get_thread_num();
+#endif
+            double* mine = part + (size_t)tid * per;
+#pragma omp for schedule(static)
+            for (int64_t r = r0; r < r1; ++r) {
+                int ai = p->ant1[r], aj = p->ant2[r];
+                for (int c = 0; c < p->n_chan; ++c) {
+                    double u, v;
+                    row_uv(p, r, c, &u, &v);
+                    for (int pol = 0; pol < p->n_pol; ++pol) {
+                        size_t idx = ((size_t)r * p->n_chan + c) * p->n_pol + pol;
+                        double out[10];
+                        vis_one(p, tab, pol, ai, aj, c, u, v, out, 1);
+                        if (vis_model_out) {
+                            vis_model_out[2 * idx] = out[0];
+                            vis_model_out[2 * idx + 1] = out[1];
+                        }
+                        double w = weight[idx];
+                        double rr = vis_obs[2 * idx] - out[0];
+                        double ri = vis_obs[2 * idx + 1] - out[1];
+                        double chi = w * (rr * rr + ri * ri);
+                        for (int end = 0; end < 2; ++end) {
+                            int a = end ? aj : ai;
+                            const double* dl = out + 2 + 4 * end; /* dV/dl_a */
+                            const double* dm = out + 4 + 4 * end; /* dV/dm_a */
+                            double* t = mine + ((size_t)pol * p->n_ant + a) * 6;
+                            t[0] += chi;
+                            t[1] += w * (rr * dl[0] + ri * dl[1]);
+                            t[2] += w * (rr * dm[0] + ri * dm[1]);
+                            t[3] += w * (dl[0] * dl[0] + dl[1] * dl[1]);
+                            t[4] += w * (dl[0] * dm[0] + dl[1] * dm[1]);
+                            t[5] += w * (dm[0] * dm[0] + dm[1] * dm[1]);
+                        }
+                    }
+                }
+            }
+        }
+        double* dst = acc + (size_t)s * per;
+        for (int t = 0; t < nthr; ++t)
+            for (size_t k = 0; k < per; ++k) dst[k] += part[(size_t)t * per + k];
+        free(tab);
+    }
+    free(part);
+    return 0;
+}
+
+/*
+ * Damped per-antenna update.  For each (interval, pol, antenna) with sums
+ * (chi, g, H): delta = gamma H^-1 g when H is well conditioned
+ * (det > 1e-12 tr^2), else gamma g_k / H_kk per axis with H_kk > 0; an
+ * antenna with tr H <= 0 (no unflagged data) or non-finite sums is left as is
+ * and marked in not_updated.  max_step_out[s] receives the largest |delta| of
+ * interval s.  Intervals whose done[s] is non-zero are skipped.
+ */
+int oracle_solve_step(int n_int, int n_pol, int n_ant, const double* acc, double gain,
+                      double* offsets_io, int32_t* not_updated, double* max_step_out,
+                      const int32_t* done)
+{
+    if (n_int < 1 || n_pol < 1 || n_ant < 1 || !(gain > 0.0)) return -1;
+    for (int s = 0; s < n_int; ++s) {
+        double mx = 0.0;
+        for (int pol = 0; pol < n_pol; ++pol) {
+            for (int a = 0; a < n_ant; ++a) {
+                size_t k = ((size_t)s * n_pol + pol) * n_ant + a;
+                const double* t = acc + 6 * k;
+                double gl = t[1], gm = t[2], hll = t[3], hlm = t[4], hmm = t[5];
+                int skip = (done && done[s]);
+                double tr = hll + hmm;
+                int bad = !(isfinite(gl) && isfinite(gm) && isfinite(hll) && isfinite(hlm) &&
+                            isfinite(hmm)) || !(tr > 0.0);
+                if (not_updated) not_updated[k] = (bad && !skip) ? 1 : 0;
+                if (skip || bad) continue;
+                double det = hll * hmm - hlm * hlm;
+                double dl, dm;
+                if (det > 1e-12 * tr * tr) {
+                    dl = (hmm * gl - hlm * gm) / det;
+                    dm = (hll * gm - hlm * gl) / det;
+                } else {
+                    dl = hll > 0.0 ? gl / hll : 0.0;
+                    dm = hmm > 0.0 ? gm / hmm : 0.0;
+                }
+                dl *= gain;
+                dm *= gain;
+                offsets_io[2 * k] += dl;
+                offsets_io[2 * k + 1] += dm;
+                double st = sqrt(dl * dl + dm * dm);
+                if (st > mx) mx = st;
+            }
+        }
+        if (max_step_out) max_step_out[s] = (done && done[s]) ? 0.0 : mx;
+    }
+    return 0;
+}
+
+/*
+ * Algorithm 1 for every interval: at most n_max iterations of
+ * (accumulate at current offsets, damped update); an interval stops once its
+ * largest step is below tol_rad.  iters_out[s] gets the iterations it ran.
+ */
+int oracle_solve(const orc_problem* p, const double* vis_obs, const double* weight,
+                 double* offsets_io, double gain, int n_max, double tol_rad, int32_t* iters_out)
+{
+    if (check_problem(p) || n_max < 0) return -1;
+    size_t n_acc = (size_t)p->n_int * p->n_pol * p->n_ant * 6;
+    double* acc = (double*)malloc(n_acc * sizeof(double));
+    double* mx = (double*)malloc(p->n_int * sizeof(double));
+    int32_t* done = (int32_t*)calloc(p->n_int, sizeof(int32_t));
+    if (!acc || !mx || !done) {
+        free(acc);
+        free(mx);
+        free(done);
+        return -2;
+    }
+    for (int s = 0; s < p->n_int; ++s) iters_out[s] = 0;
+    int rc = 0;
+    for (int it = 0; it < n_max; ++it) {
+        rc = oracle_gradient(p, offsets_io, vis_obs, weight, acc, NULL);
+        if (rc) break;
+        rc = oracle_solve_step(p->n_int, p->n_pol, p->n_ant, acc, gain, offsets_io, NULL, mx, done);
+        if (rc) break;
+        int all = 1;
+        for (int s = 0; s < p->n_int; ++s) {
+            if (done[s]) continue;
+            iters_out[s] += 1;
+            if (mx[s] < tol_rad) done[s] = 1;
+            else all = 0;
+        }
+        if (all) break;
+    }
+    free(acc);
+    free(mx);
+    free(done);
+    return rc;
+}
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

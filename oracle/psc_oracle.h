@@ -1,0 +1,45 @@
+/*
+ * psc_oracle.h -- interface of the FP64 direct-summation oracle.
+ * TEST INFRASTRUCTURE ONLY; see psc_oracle.c.  Host pointers throughout.
+ */
+#ifndef PSC_ORACLE_H
+#define PSC_ORACLE_H
+#include <stdint.h>
+
+typedef struct {
+    /* sky: non-zero pixels of the model image (direction cosines, Jy) */
+    int32_t n_src;
+    const double* src_l;
+    const double* src_m;
+    const double* src_flux;
+    /* array and data layout */
+    int32_t n_ant, n_chan, n_pol, n_int;
+    int64_t n_row;
+    const int64_t* int_row_ptr; /* [n_int+1] rows of interval s: [ptr[s], ptr[s+1]) */
+    const int32_t* ant1;        /* [n_row] */
+    const int32_t* ant2;        /* [n_row] */
+    const double* uv_m;         /* [n_row][2] baseline (u,v) in metres */
+    const double* freq_hz;      /* [n_chan] */
+    /* antenna model */
+    double dish_diam_m;
+    int32_t illum;          /* 0 = uniform circular (Airy), 1 = Gaussian main lobe */
+    double gauss_sigma_ld;  /* Gaussian mode: sigma of E in units of lambda/D */
+    double squint_frac;     /* beam squint of pol 0 (+) and pol 1 (-), in HPBW */
+    double snap_scale;      /* >0: uv (wavelengths) rounded to multiples of 1/snap_scale */
+} orc_problem;
+
+void oracle_efp(int illum, double dish_diam_m, double gauss_sigma_ld, double freq_hz,
+                double dl, double dm, double* out3);
+double oracle_hpbw(double freq_hz, double dish_diam_m);
+void oracle_snap_uv(const orc_problem* p, int64_t row, int chan, double* uv_out);
+int oracle_predict(const orc_problem* p, const double* offsets, double* vis_out, double* dvis_out);
+int oracle_gradient(const orc_problem* p, const double* offsets, const double* vis_obs,
+                    const double* weight, double* acc, double* vis_model_out);
+int oracle_solve_step(int n_int, int n_pol, int n_ant, const double* acc, double gain,
+                      double* offsets_io, int32_t* not_updated, double* max_step_out,
+                      const int32_t* done);
+int oracle_solve(const orc_problem* p, const double* vis_obs, const double* weight,
+                 double* offsets_io, double gain, int n_max, double tol_rad, int32_t* iters_out);
+int oracle_num_threads(void);
+
+#endif
