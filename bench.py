@@ -1,0 +1,165 @@
+"""Benchmark: predict+gradient visibilities per second on one MI355X.
+
+One step is one pass of the hot path over the whole workload: kernel
+construction, degridding of V^M and its four offset derivatives, residual,
+float64 per-antenna chi^2 / gradient / normal-matrix sums (psc_gradient), and
+the damped per-antenna update (psc_solve_step).  The default workload is the
+single-interval configuration: 27 antennas in a Y (351 baselines, arms to
+21 km), 360 x 10 s, 16 channels over 1-2 GHz, one polarisation, a 1024^2
+model grid with 200 point sources, support 16, oversampling 4.
+
+Prints one JSON line (see the repository's benchmark contract).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP32_VECTOR_PEAK = 157.3e12  # MI355X published FP32 vector rate (FLOP/s)
+HBM_PEAK = 8.0e12
+
+
+def describe(obs):
+    wl = obs.wl
+    return {
+        "workload": f"{wl.name}: {obs.n_ant} antennas ({wl.layout}), {wl.n_bl} baselines, "
+                    f"{wl.n_time} x {wl.dt_s:g} s, {obs.n_chan} channels, {obs.n_pol} pol, "
+                    f"{obs.n_int} interval(s), {obs.grid_n}^2 grid, support {wl.support}, "
+                    f"oversampling {wl.oversample}",
+        "n_vis": int(obs.n_vis),
+        "n_intervals": int(obs.n_int),
+        "grid_n": int(obs.grid_n),
+        "support": int(wl.support),
+        "oversample": int(wl.oversample),
+        "step": "psc_gradient + psc_solve_step",
+    }
+
+
+def cpu_baseline(obs, start, seconds):
+    import oracle
+    prob = oracle.Problem.from_observation(obs)
+    v_obs_np = oracle.predict(prob, obs.offsets_true)  # untimed: the oracle's own data
+    off = start.copy()
+    t0 = time.perf_counter()
+    iters = 0
+    while True:
+        acc = oracle.gradient(prob, off, v_obs_np, 1.0)
+        off, _, _ = oracle.solve_step(acc, 0.5, off)
+        iters += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {
+        "value": obs.n_vis * iters / dt,
+        "unit": "vis/s",
+        "cores": int(oracle.num_threads()),
+        "kind": "oracle",
+        "sample": f"full workload ({obs.n_vis} visibilities x {prob.n_src} sky pixels), "
+                  f"{iters} gradient+update iteration(s) in {dt:.1f} s, FP64 direct summation",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only; the hot path is sharded by solution "
+              "interval or channel block across GPUs (see DESIGN.md), which is not built here.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1709_08681_amd import synth
+    from paper_1709_08681_amd.psc import Session, psc_gradient, psc_solve_step
+
+    obs = synth.make_config(args.config)
+    print(f"bench: workload {obs.wl.name}, {obs.n_vis} visibilities", file=sys.stderr, flush=True)
+    s = Session(obs, device=0)
+    stream = torch.cuda.current_stream()
+    off_true = s.offsets(obs.offsets_true)
+    v_obs = s.predict(off_true)
+    w = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+    start = synth.perturbed_offsets(obs, 30.0, 99)
+    off = s.offsets(start)
+    acc = torch.empty(s.off_shape[:3] + (6,), dtype=torch.float64, device=s.dev)
+    mx = torch.empty(obs.n_int, dtype=torch.float64, device=s.dev)
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        psc_gradient(s.ctx, s.handle, off, v_obs, w, acc, None, stream)
+        if ev is not None:
+            ev[1].record(stream)
+        psc_solve_step(s.ctx, obs.n_int, obs.n_pol, obs.n_ant, acc, 0.5, off, None, mx, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for k in range(args.steps):
+        step(evs[k])
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    ms_total = t_start.elapsed_time(t_end)
+    ms_step = ms_total / args.steps
+    grad_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
+    value = obs.n_vis / (ms_step * 1e-3)
+
+    S = obs.wl.support
+    flops = obs.n_vis * 40.0 * S * S  # five complex multiply-adds per tap
+    achieved = flops / (grad_ms * 1e-3)
+    roof = {
+        "bound": "alu",
+        "achieved": achieved / 1e12,
+        "peak": FP32_VECTOR_PEAK / 1e12,
+        "unit": "TFLOP/s",
+        "frac": achieved / FP32_VECTOR_PEAK,
+        "traffic": None,
+        "kernel": "k_item<16,grad> (+ k_reduce)",
+        "launch_ms": grad_ms,
+    }
+    out = {
+        "metric": "predict+gradient visibilities/s",
+        "value": value,
+        "unit": "vis/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (f64 accumulation)",
+        "data": "synthetic",
+        "config": describe(obs),
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
+        s.close()
+        out["cpu_baseline"] = cpu_baseline(obs, start, args.cpu_seconds)
+    else:
+        s.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,235 @@
+/*
+ * psc.h -- C ABI of libpsc, the MI355X (gfx950) implementation of the
+ * Pointing SelfCal predict / gradient / update hot path
+ * (Bhatnagar & Cornwell 2017, "The Pointing Self Calibration algorithm for
+ * aperture synthesis radio telescopes", arXiv:1709.08681).
+ *
+ * General rules
+ *  - Every call returns a psc_status; nothing throws or prints.  On failure
+ *    psc_last_error() describes the first problem found.
+ *  - Array arguments named *_dev are DEVICE pointers on the context's GPU,
+ *    owned by the caller and only borrowed for the duration of the call
+ *    (asynchronous calls: until the work queued on `stream` has finished).
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls marked
+ *    "async" only enqueue work; calls marked "sync" block until done.
+ *  - One context/observation pair must not be used from two streams at once:
+ *    they own scratch memory that concurrent calls would share.
+ *  - Units: angles and direction cosines in radians, baselines in metres,
+ *    frequencies in Hz, flux in Jy.  Complex arrays are interleaved
+ *    (re, im) float32 pairs ("complex64") unless stated otherwise.
+ *
+ * Symbols follow the paper: V^{M0} is the Fourier transform of the model
+ * image on the grid (Sec. 2.2, Eq. MEDD), A_ij the aperture-plane kernel of
+ * baseline (i,j) (Eq. ME), l_i = (l_i, m_i) the pointing offset of antenna i
+ * (Sec. 3), R = V^Obs - V^M the residual (Eq. Res), W the inverse-variance
+ * weights (Eq. Chisq).
+ */
+#ifndef PSC_H
+#define PSC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PSC_API __attribute__((visibility("default")))
+
+typedef enum {
+    PSC_OK = 0,
+    PSC_E_ARG = -1,          /* invalid argument (shape, range, null pointer) */
+    PSC_E_HIP = -2,          /* a HIP runtime call failed */
+    PSC_E_OOM = -3,          /* device or host allocation failed */
+    PSC_E_UNSUPPORTED = -4,  /* valid request outside what this build implements */
+    PSC_E_STATE = -5         /* call out of order (e.g. predict before set_model) */
+} psc_status;
+
+typedef struct psc_ctx psc_ctx;
+typedef struct psc_obs psc_obs;
+
+/*
+ * Geometry of the model grid and of the antenna model; fixed per context.
+ *
+ *  grid_n        N, edge of the N x N model grid V^{M0}; power of two, 64..8192.
+ *  cell_rad      pixel size of the model image (direction cosine per pixel);
+ *                FoV = N * cell_rad, uv cell = 1 / FoV wavelengths.
+ *  support       S, width of every baseline kernel in uv cells (16 or 32).
+ *                The kernel of baseline (i,j) is the convolution of the two
+ *                antennas' aperture functions (Eq. MEDD), whose width is
+ *                2 D / lambda, with the anti-aliasing taper (taper_width
+ *                cells); it must fit: 2 D FoV / lambda + taper_width < S.
+ *  oversample    O, kernel samples per uv cell (1..16, S*O <= 512).  Each
+ *                visibility's uv is rounded to the nearest 1/O cell.
+ *  image_samples M, image-plane samples per axis used to build kernels, at
+ *                spacing FoV/S (0 = default 3S/2; even, S..2S).
+ *  dish_diam_m   D of the uniformly illuminated circular dishes.
+ *  illum         0: far-field voltage pattern 2 J1(x)/x, x = pi D |l| / lambda;
+ *                1: the Gaussian main-lobe model of Sec. 3,
+ *                   exp(-|l|^2 / (2 s^2)), s = gauss_sigma_ld * lambda / D.
+ *  squint_frac   beam squint: polarisation 0 (1) is centred at
+ *                +(-) squint_frac * HPBW(nu) along +l, HPBW = 1.02899 lambda/D
+ *                (Sec. 4.2: the two parallel hands are solved separately).
+ *  taper_width   width W of the exponential-of-semicircle anti-aliasing taper
+ *                in uv cells (0 = default 8); taper_beta its shape
+ *                (0 = default 2.30 * W).
+ *  device        HIP device ordinal.
+ */
+typedef struct {
+    int32_t grid_n;
+    int32_t support;
+    int32_t oversample;
+    int32_t image_samples;
+    double cell_rad;
+    double dish_diam_m;
+    int32_t illum;
+    double gauss_sigma_ld;
+    double squint_frac;
+    int32_t taper_width;
+    double taper_beta;
+    int32_t device;
+} psc_config;
+
+/*
+ * Description of the visibility data (read once by psc_obs_create).
+ * Rows are (time, baseline) samples.  Every pointer is a DEVICE pointer.
+ *
+ *  int_row_ptr [n_int+1] int64: rows of solution interval s are
+ *              [int_row_ptr[s], int_row_ptr[s+1]); intervals may be uneven
+ *              or empty (Algorithm 1 solves each interval separately).
+ *  ant1, ant2  [n_row] int32 antenna indices, 0 <= ant1 < ant2 < n_ant.
+ *  uv_m        [n_row][2] float64 baseline (u, v) in metres, w ignored.
+ *  freq_hz     [n_chan] float64 channel frequencies.
+ *  n_pol       1 or 2 parallel-hand polarisations.
+ *
+ * Visibility-shaped arrays used by the calls below are laid out
+ * [n_row][n_chan][n_pol]; offsets are [n_int][n_pol][n_ant][2] float64 (l, m).
+ */
+typedef struct {
+    int32_t n_ant;
+    int32_t n_chan;
+    int32_t n_pol;
+    int32_t n_int;
+    int64_t n_row;
+    const int64_t* int_row_ptr;
+    const int32_t* ant1;
+    const int32_t* ant2;
+    const double* uv_m;
+    const double* freq_hz;
+} psc_obs_desc;
+
+/* Library version string. */
+PSC_API const char* psc_version(void);
+
+/* Create a context (sync).  Fails with PSC_E_ARG on an invalid config. */
+PSC_API psc_status psc_create(const psc_config* cfg, psc_ctx** out);
+
+/* Destroy a context and free its device memory (sync).  NULL is allowed. */
+PSC_API psc_status psc_destroy(psc_ctx* ctx);
+
+/* Message describing the last failure on this context ("" if none); valid
+ * until the next call on the context.  ctx may be NULL (creation errors). */
+PSC_API const char* psc_last_error(const psc_ctx* ctx);
+
+/*
+ * Model transform, Algorithm 1 step 1 (V^{M0} = F[I^M], Eq. MEDD) (sync).
+ * image_dev: [N][N] float64 real model image, pixel (ix, iy) at direction
+ * cosines ((ix - N/2) cell, (iy - N/2) cell).  The library divides by the
+ * taper's image-plane response, transforms in float64 and keeps V^{M0} as a
+ * complex64 grid.  Emission must lie in the central N/2 x N/2 pixels.
+ */
+PSC_API psc_status psc_set_model(psc_ctx* ctx, const double* image_dev, void* stream);
+
+/*
+ * Plan the visibility data (sync).  Copies the geometry, rounds every
+ * (row, channel) uv to the kernel lattice, groups samples into work items
+ * (interval, baseline, channel) and allocates the observation's scratch.
+ * Returns PSC_E_ARG for inconsistent indices (ant1 >= ant2, out of range,
+ * non-monotone int_row_ptr).
+ */
+PSC_API psc_status psc_obs_create(psc_ctx* ctx, const psc_obs_desc* desc, psc_obs** out);
+PSC_API psc_status psc_obs_destroy(psc_obs* obs);
+
+/* Sizes of a planned observation (host pointers, each nullable). */
+PSC_API psc_status psc_obs_info(const psc_obs* obs, int64_t* n_items, int64_t* n_groups,
+                                int64_t* n_vis);
+
+/*
+ * Predict (async): V^M_ij = [A_i (x) A_j*] * V^{M0} (Eq. MEDD, Eq. ME with the
+ * direction-independent term equal to one), where A_i carries antenna i's
+ * pointing offset as an aperture phase gradient (Sec. 3, Eq. AIJPOINTING
+ * generalised to the exact two-aperture kernel).
+ *  offsets_dev [n_int][n_pol][n_ant][2] float64
+ *  vis_out_dev [n_row][n_chan][n_pol] complex64 (written)
+ */
+PSC_API psc_status psc_predict(psc_ctx* ctx, psc_obs* obs, const double* offsets_dev,
+                               void* vis_out_dev, void* stream);
+
+/*
+ * Residual, chi^2, gradient and 2x2 normal matrix per antenna (async):
+ * Eq. DCHIDD with a = (l_i, m_i) and Algorithm 1's accumulation step.  For
+ * every visibility of baseline (i, j) and both ends a in {i, j}:
+ *   chi_a += w |R|^2,  g_a += w Re(conj(R) dV/dp_a),
+ *   H_a   += w Re(conj(dV/dp_a) dV/dp_a^T)        (R = V^Obs - V^M)
+ * so g_a = -1/2 d chi^2 / d p_a, and chi_a counts each visibility once per end.
+ *  vis_obs_dev  [n_row][n_chan][n_pol] complex64
+ *  weight_dev   [n_row][n_chan][n_pol] float32 inverse variance, 0 = flagged
+ *  acc_out_dev  [n_int][n_pol][n_ant][6] float64: chi, g_l, g_m, H_ll, H_lm, H_mm
+ *  vis_model_dev nullable [n_row][n_chan][n_pol] complex64: V^M if not NULL
+ * The sums are accumulated in float64 in a fixed order: repeated calls give
+ * bit-identical results.
+ */
+PSC_API psc_status psc_gradient(psc_ctx* ctx, psc_obs* obs, const double* offsets_dev,
+                                const void* vis_obs_dev, const float* weight_dev,
+                                double* acc_out_dev, void* vis_model_dev, void* stream);
+
+/*
+ * Vector-Jacobian product of psc_predict (async), the adjoint used by
+ * automatic differentiation: for every (interval, pol, antenna a)
+ *   grad[a] = sum over visibilities touching a of Re(conj(G) dV/dp_a)
+ * with G = grad_vis (the gradient of a real loss with respect to Re V + i Im V).
+ * Kernels are rebuilt from the offsets; nothing is kept from the forward call.
+ *  grad_vis_dev  [n_row][n_chan][n_pol] complex64
+ *  grad_offsets_out_dev [n_int][n_pol][n_ant][2] float64 (written)
+ */
+PSC_API psc_status psc_predict_vjp(psc_ctx* ctx, psc_obs* obs, const double* offsets_dev,
+                                   const void* grad_vis_dev, double* grad_offsets_out_dev,
+                                   void* stream);
+
+/*
+ * Damped per-antenna update (async), Sec. 2.2 (a_n = a_{n-1} + f(grad)) with
+ * f read as a 2x2 Gauss-Newton step scaled by the loop gain 0 < gain <= 1 of
+ * Eq. SelfCal:  p_a += gain * H_a^-1 g_a  when det H_a > 1e-12 (tr H_a)^2,
+ * else p_a += gain * g_k / H_kk per axis with H_kk > 0.  Antennas with
+ * tr H_a <= 0 or non-finite sums keep their offsets and get not_updated = 1.
+ *  acc_dev        [n_int][n_pol][n_ant][6] float64 (from psc_gradient)
+ *  offsets_io_dev [n_int][n_pol][n_ant][2] float64 (updated in place)
+ *  not_updated_dev nullable [n_int][n_pol][n_ant] int32
+ *  max_step_dev    nullable [n_int] float64: largest |delta p| per interval
+ */
+PSC_API psc_status psc_solve_step(psc_ctx* ctx, int32_t n_int, int32_t n_pol, int32_t n_ant,
+                                  const double* acc_dev, double gain, double* offsets_io_dev,
+                                  int32_t* not_updated_dev, double* max_step_dev, void* stream);
+
+/* Execution forms of psc_solve. */
+#define PSC_SOLVE_PLAIN 0    /* host loop over intervals, one launch set per interval */
+#define PSC_SOLVE_BATCHED 1  /* every interval in one launch set per iteration */
+#define PSC_SOLVE_GRAPH 2    /* BATCHED, with the n_max iterations captured in one HIP graph */
+
+/*
+ * Algorithm 1 (sync): for every solution interval, up to n_max iterations of
+ * (gradient at the current offsets, damped update); an interval stops
+ * iterating after the first step whose largest |delta p| is below tol_rad.
+ *  offsets_io_dev [n_int][n_pol][n_ant][2] float64: start values in, solutions out
+ *  iters_out_dev  nullable [n_int] int32: iterations run per interval
+ * All three forms give bit-identical offsets.
+ */
+PSC_API psc_status psc_solve(psc_ctx* ctx, psc_obs* obs, const void* vis_obs_dev,
+                             const float* weight_dev, double* offsets_io_dev, double gain,
+                             int32_t n_max, double tol_rad, int32_t form, int32_t* iters_out_dev,
+                             void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSC_H */

@@ -1,0 +1,756 @@
+// psc_api.hip -- host side of libpsc: the C ABI declared in include/psc.h,
+// argument checking, the anti-aliasing taper, observation planning and the
+// three execution forms of the solver loop (Algorithm 1).
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/psc.h"
+#include "psc_internal.h"
+
+using namespace psc;
+
+struct psc_ctx {
+    psc_config cfg{};
+    int n = 0, s = 0, o = 0, m = 0;
+    double fov = 0, h = 0, snap = 0;
+    float2* grid = nullptr;        // V^{M0}, N x N complex64
+    double* taper_pix = nullptr;   // [N]
+    double* taper_img = nullptr;   // [M]
+    float2* tw = nullptr;          // [S*O]
+    bool model_set = false;
+    std::string err;
+};
+
+struct psc_obs {
+    psc_ctx* ctx = nullptr;
+    int32_t n_ant = 0, n_chan = 0, n_pol = 0, n_int = 0;
+    int64_t n_row = 0;
+    std::vector<int32_t> int_item_ptr;  // host copy, [n_int+1]
+    int64_t n_items = 0, n_groups = 0, n_vis = 0;
+    Item* items = nullptr;
+    Group* groups = nullptr;
+    VisEnt* vis = nullptr;
+    uint32_t* ant_ptr = nullptr;
+    uint32_t* ant_ent = nullptr;
+    double* freq = nullptr;
+    double4* airy = nullptr;
+    int32_t n_tab = 0;
+    double inv_dx = 0;
+    double* partials = nullptr;  // [n_items][n_pol][12]
+    double* acc = nullptr;       // [n_int][n_pol][n_ant][6]
+    double* max_step = nullptr;  // [n_int]
+    int32_t* done = nullptr;     // [n_int]
+    int32_t* iters = nullptr;    // [n_int]
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph = nullptr;
+    // arguments the captured graph was built with
+    const void* g_vis = nullptr;
+    const float* g_w = nullptr;
+    double* g_off = nullptr;
+    double g_gain = 0, g_tol = 0;
+    int32_t g_nmax = -1;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+psc_status fail(psc_ctx* ctx, psc_status st, const std::string& msg)
+{
+    if (ctx)
+        ctx->err = msg;
+    else
+        g_create_err = msg;
+    return st;
+}
+
+psc_status hip_fail(psc_ctx* ctx, hipError_t e, const char* what)
+{
+    return fail(ctx, PSC_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define PSC_HIP(ctx, call)                                  \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+    } while (0)
+
+template <class T>
+hipError_t dmalloc(T** p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc((void**)p, sizeof(T) * count);
+}
+
+template <class T>
+void dfree(T*& p)
+{
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on P_n).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double z = cos(kPi * (i + 0.75) / (n + 0.5));
+        double dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = 0.0;
+            for (int k = 1; k <= n; ++k) {
+                const double p2 = p1;
+                p1 = p0;
+                p0 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p2) / k;
+            }
+            dp = n * (z * p0 - p1) / (z * z - 1.0);
+            const double dz = p0 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// Image-plane response of the exponential-of-semicircle taper
+// phi(z) = exp(beta (sqrt(1 - z^2) - 1)), |z| <= 1, spanning W uv cells:
+//   c(x) = (W/2) int_{-1}^{1} phi(z) cos(pi W x z) dz,  x = l / FoV,
+// integrated with z = sin(theta), which removes the end-point square root.
+struct Taper {
+    int width;
+    double beta;
+    std::vector<double> gx, gw;
+    Taper(int w, double b) : width(w), beta(b) { gauss_legendre(256, gx, gw); }
+    double operator()(double x) const
+    {
+        double acc = 0.0;
+        for (size_t i = 0; i < gx.size(); ++i) {
+            const double th = 0.5 * kPi * gx[i];
+            const double z = sin(th);
+            acc += gw[i] * exp(beta * (cos(th) - 1.0)) * cos(kPi * width * x * z) * cos(th);
+        }
+        return 0.5 * width * 0.5 * kPi * acc;
+    }
+};
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int floor_div(long long a, int b)
+{
+    long long q = a / b;
+    if ((a % b) != 0 && ((a < 0) != (b < 0))) --q;
+    return (int)q;
+}
+
+}  // namespace
+
+extern "C" {
+
+PSC_API const char* psc_version(void) { return "psc 0.1 (gfx950)"; }
+
+PSC_API const char* psc_last_error(const psc_ctx* ctx)
+{
+    return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+PSC_API psc_status psc_create(const psc_config* cfg, psc_ctx** out)
+{
+    g_create_err.clear();
+    if (!cfg || !out) return fail(nullptr, PSC_E_ARG, "null config or output pointer");
+    *out = nullptr;
+    const psc_config& c = *cfg;
+    if (!is_pow2(c.grid_n) || c.grid_n < 64 || c.grid_n > 8192)
+        return fail(nullptr, PSC_E_ARG, "grid_n must be a power of two in [64, 8192]");
+    if (c.support != 16 && c.support != 32)
+        return fail(nullptr, PSC_E_ARG, "support must be 16 or 32");
+    if (c.oversample < 1 || c.oversample > 16 || c.support * c.oversample > 512)
+        return fail(nullptr, PSC_E_ARG, "oversample must be in [1, 16] with support*oversample <= 512");
+    const int m = c.image_samples ? c.image_samples : 3 * c.support / 2;
+    if (m < c.support || m > 2 * c.support || (m & 1))
+        return fail(nullptr, PSC_E_ARG, "image_samples must be even and in [support, 2*support]");
+    const int tw = c.taper_width ? c.taper_width : 8;
+    const double tb = c.taper_beta > 0 ? c.taper_beta : 2.30 * tw;
+    if (tw < 2 || tw >= c.support) return fail(nullptr, PSC_E_ARG, "taper_width must be in [2, support)");
+    if (!(c.cell_rad > 0) || !(c.dish_diam_m > 0) || !isfinite(c.cell_rad))
+        return fail(nullptr, PSC_E_ARG, "cell_rad and dish_diam_m must be positive");
+    if (c.illum != 0 && c.illum != 1) return fail(nullptr, PSC_E_ARG, "illum must be 0 or 1");
+    if (c.illum == 1 && !(c.gauss_sigma_ld > 0))
+        return fail(nullptr, PSC_E_ARG, "gauss_sigma_ld must be positive in Gaussian mode");
+    if (!isfinite(c.squint_frac)) return fail(nullptr, PSC_E_ARG, "squint_frac must be finite");
+    if (c.support != 16)
+        return fail(nullptr, PSC_E_UNSUPPORTED, "this build implements support 16 only");
+    if (hipSetDevice(c.device) != hipSuccess) return fail(nullptr, PSC_E_ARG, "invalid device");
+
+    psc_ctx* ctx = new psc_ctx();
+    ctx->cfg = c;
+    ctx->cfg.image_samples = m;
+    ctx->cfg.taper_width = tw;
+    ctx->cfg.taper_beta = tb;
+    ctx->n = c.grid_n;
+    ctx->s = c.support;
+    ctx->o = c.oversample;
+    ctx->m = m;
+    ctx->fov = (double)c.grid_n * c.cell_rad;
+    ctx->h = ctx->fov / c.support;
+    ctx->snap = (double)c.oversample * ctx->fov;
+
+    Taper taper(tw, tb);
+    std::vector<double> tp(ctx->n), ti(m);
+    for (int i = 0; i < ctx->n; ++i) tp[i] = taper((double)(i - ctx->n / 2) / ctx->n);
+    for (int i = 0; i < m; ++i) ti[i] = taper((double)(i - m / 2) / c.support);
+    const int so = c.support * c.oversample;
+    std::vector<float2> twh(so);
+    for (int t = 0; t < so; ++t) {
+        double sv, cv;
+        if ((4 * t) % so == 0) {  // exact on the axes
+            const int q = (4 * t) / so;
+            cv = (q == 0) ? 1 : (q == 2) ? -1 : 0;
+            sv = (q == 1) ? 1 : (q == 3) ? -1 : 0;
+        } else {
+            cv = cos(2.0 * kPi * t / so);
+            sv = sin(2.0 * kPi * t / so);
+        }
+        twh[t] = make_float2((float)cv, (float)sv);
+    }
+    hipError_t e = set_fft_twiddles();
+    if (e == hipSuccess) e = dmalloc(&ctx->grid, (size_t)ctx->n * ctx->n);
+    if (e == hipSuccess) e = dmalloc(&ctx->taper_pix, ctx->n);
+    if (e == hipSuccess) e = dmalloc(&ctx->taper_img, m);
+    if (e == hipSuccess) e = dmalloc(&ctx->tw, so);
+    if (e == hipSuccess) e = hipMemcpy(ctx->taper_pix, tp.data(), sizeof(double) * ctx->n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->taper_img, ti.data(), sizeof(double) * m, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->tw, twh.data(), sizeof(float2) * so, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        std::string msg = std::string("context allocation: ") + hipGetErrorString(e);
+        psc_destroy(ctx);
+        return fail(nullptr, e == hipErrorOutOfMemory ? PSC_E_OOM : PSC_E_HIP, msg);
+    }
+    *out = ctx;
+    return PSC_OK;
+}
+
+PSC_API psc_status psc_destroy(psc_ctx* ctx)
+{
+    if (!ctx) return PSC_OK;
+    (void)hipSetDevice(ctx->cfg.device);
+    dfree(ctx->grid);
+    dfree(ctx->taper_pix);
+    dfree(ctx->taper_img);
+    dfree(ctx->tw);
+    delete ctx;
+    return PSC_OK;
+}
+
+PSC_API psc_status psc_set_model(psc_ctx* ctx, const double* image_dev, void* stream)
+{
+    if (!ctx) return fail(nullptr, PSC_E_ARG, "null context");
+    if (!image_dev) return fail(ctx, PSC_E_ARG, "null image");
+    ctx->err.clear();
+    PSC_HIP(ctx, hipSetDevice(ctx->cfg.device));
+    hipStream_t st = (hipStream_t)stream;
+    const int n = ctx->n;
+    int log2n = 0;
+    while ((1 << log2n) < n) ++log2n;
+    double2 *a = nullptr, *b = nullptr;
+    hipError_t e = dmalloc(&a, (size_t)n * n);
+    if (e == hipSuccess) e = dmalloc(&b, (size_t)n * n);
+    if (e == hipSuccess) e = launch_taper_image(image_dev, ctx->taper_pix, a, n, st);
+    if (e == hipSuccess) e = launch_fft_rows(a, n, log2n, st);
+    if (e == hipSuccess) e = launch_transpose(a, b, n, st);
+    if (e == hipSuccess) e = launch_fft_rows(b, n, log2n, st);
+    if (e == hipSuccess) e = launch_transpose(b, a, n, st);
+    if (e == hipSuccess) e = launch_finish_grid(a, ctx->grid, n, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    dfree(a);
+    dfree(b);
+    if (e != hipSuccess) return hip_fail(ctx, e, "psc_set_model");
+    ctx->model_set = true;
+    return PSC_OK;
+}
+
+PSC_API psc_status psc_obs_destroy(psc_obs* obs)
+{
+    if (!obs) return PSC_OK;
+    if (obs->ctx) (void)hipSetDevice(obs->ctx->cfg.device);
+    if (obs->graph) (void)hipGraphExecDestroy(obs->graph);
+    if (obs->cap_stream) (void)hipStreamDestroy(obs->cap_stream);
+    dfree(obs->items);
+    dfree(obs->groups);
+    dfree(obs->vis);
+    dfree(obs->ant_ptr);
+    dfree(obs->ant_ent);
+    dfree(obs->freq);
+    dfree(obs->airy);
+    dfree(obs->partials);
+    dfree(obs->acc);
+    dfree(obs->max_step);
+    dfree(obs->done);
+    dfree(obs->iters);
+    delete obs;
+    return PSC_OK;
+}
+
+PSC_API psc_status psc_obs_create(psc_ctx* ctx, const psc_obs_desc* d, psc_obs** out)
+{
+    if (!ctx) return fail(nullptr, PSC_E_ARG, "null context");
+    ctx->err.clear();
+    if (!d || !out) return fail(ctx, PSC_E_ARG, "null descriptor or output pointer");
+    *out = nullptr;
+    if (d->n_ant < 2 || d->n_chan < 1 || d->n_pol < 1 || d->n_pol > 2 || d->n_int < 1 || d->n_row < 0)
+        return fail(ctx, PSC_E_ARG, "bad sizes (need n_ant >= 2, n_chan >= 1, n_pol in {1,2}, n_int >= 1)");
+    if (d->n_ant > 4096) return fail(ctx, PSC_E_UNSUPPORTED, "n_ant above 4096");
+    if ((d->n_row > 0 && (!d->ant1 || !d->ant2 || !d->uv_m)) || !d->int_row_ptr || !d->freq_hz)
+        return fail(ctx, PSC_E_ARG, "null array in descriptor");
+    if ((double)d->n_row * d->n_chan >= 4294967295.0)
+        return fail(ctx, PSC_E_UNSUPPORTED, "n_row * n_chan must stay below 2^32");
+    PSC_HIP(ctx, hipSetDevice(ctx->cfg.device));
+
+    const int n_ant = d->n_ant, n_chan = d->n_chan, n_int = d->n_int;
+    const int64_t n_row = d->n_row;
+    std::vector<int64_t> rp(n_int + 1);
+    std::vector<int32_t> a1(n_row), a2(n_row);
+    std::vector<double> uv(2 * n_row), fr(n_chan);
+    PSC_HIP(ctx, hipMemcpy(rp.data(), d->int_row_ptr, sizeof(int64_t) * (n_int + 1), hipMemcpyDeviceToHost));
+    if (n_row > 0) {
+        PSC_HIP(ctx, hipMemcpy(a1.data(), d->ant1, sizeof(int32_t) * n_row, hipMemcpyDeviceToHost));
+        PSC_HIP(ctx, hipMemcpy(a2.data(), d->ant2, sizeof(int32_t) * n_row, hipMemcpyDeviceToHost));
+        PSC_HIP(ctx, hipMemcpy(uv.data(), d->uv_m, sizeof(double) * 2 * n_row, hipMemcpyDeviceToHost));
+    }
+    PSC_HIP(ctx, hipMemcpy(fr.data(), d->freq_hz, sizeof(double) * n_chan, hipMemcpyDeviceToHost));
+    if (rp[0] != 0 || rp[n_int] != n_row) return fail(ctx, PSC_E_ARG, "int_row_ptr must run from 0 to n_row");
+    for (int s = 0; s < n_int; ++s)
+        if (rp[s + 1] < rp[s]) return fail(ctx, PSC_E_ARG, "int_row_ptr must be non-decreasing");
+    for (int64_t r = 0; r < n_row; ++r)
+        if (a1[r] < 0 || a2[r] >= n_ant || a1[r] >= a2[r])
+            return fail(ctx, PSC_E_ARG, "antenna indices must satisfy 0 <= ant1 < ant2 < n_ant");
+    double fmax = 0;
+    for (int c = 0; c < n_chan; ++c) {
+        if (!(fr[c] > 0) || !isfinite(fr[c])) return fail(ctx, PSC_E_ARG, "frequencies must be positive");
+        fmax = std::max(fmax, fr[c]);
+    }
+    for (int64_t i = 0; i < 2 * n_row; ++i)
+        if (!isfinite(uv[i])) return fail(ctx, PSC_E_ARG, "uv_m must be finite");
+    // the kernel support must hold both apertures plus the taper
+    const double lam_min = kCLight / fmax;
+    const double need = 2.0 * ctx->cfg.dish_diam_m * ctx->fov / lam_min + ctx->cfg.taper_width;
+    if (ctx->cfg.illum == 0 && need > ctx->s)
+        return fail(ctx, PSC_E_ARG, "support too small for the dish at the highest frequency "
+                                    "(need 2 D FoV / lambda + taper_width <= support)");
+
+    const int S = ctx->s, O = ctx->o, N = ctx->n;
+    const int n_bl = n_ant * (n_ant - 1) / 2;
+    auto bl_of = [n_ant](int i, int j) { return i * (2 * n_ant - i - 1) / 2 + (j - i - 1); };
+
+    std::vector<Item> items;
+    std::vector<Group> groups;
+    std::vector<VisEnt> vis;
+    vis.reserve((size_t)n_row * n_chan);
+    std::vector<int32_t> item_ptr(n_int + 1, 0);
+    std::vector<int64_t> bl_count(n_bl + 1), bl_start(n_bl + 1);
+    std::vector<int64_t> bl_rows;
+    std::vector<int32_t> fcount(O * O), fpos(O * O);
+    std::vector<int32_t> fq(0);
+    std::vector<uint32_t> kq(0);
+    for (int s = 0; s < n_int; ++s) {
+        const int64_t r0 = rp[s], r1 = rp[s + 1];
+        std::fill(bl_count.begin(), bl_count.end(), 0);
+        for (int64_t r = r0; r < r1; ++r) bl_count[bl_of(a1[r], a2[r]) + 1]++;
+        bl_start[0] = 0;
+        for (int b = 0; b < n_bl; ++b) bl_start[b + 1] = bl_start[b] + bl_count[b + 1];
+        bl_rows.assign(r1 - r0, 0);
+        {
+            std::vector<int64_t> pos(bl_start.begin(), bl_start.end());
+            for (int64_t r = r0; r < r1; ++r) bl_rows[pos[bl_of(a1[r], a2[r])]++] = r;
+        }
+        for (int b = 0; b < n_bl; ++b) {
+            const int64_t nb = bl_start[b + 1] - bl_start[b];
+            if (nb == 0) continue;
+            const int64_t* rows = bl_rows.data() + bl_start[b];
+            fq.resize(nb);
+            kq.resize(nb);
+            for (int c = 0; c < n_chan; ++c) {
+                Item it;
+                it.interval = s;
+                it.ai = a1[rows[0]];
+                it.aj = a2[rows[0]];
+                it.chan = c;
+                it.grp_begin = (int32_t)groups.size();
+                std::fill(fcount.begin(), fcount.end(), 0);
+                for (int64_t k = 0; k < nb; ++k) {
+                    const int64_t r = rows[k];
+                    // uv in wavelengths, rounded to the 1/O lattice
+                    const double uu = uv[2 * r] * fr[c] / kCLight;
+                    const double vv = uv[2 * r + 1] * fr[c] / kCLight;
+                    const long long ql = llround(uu * ctx->snap);
+                    const long long qm = llround(vv * ctx->snap);
+                    const int bl_l = floor_div(ql, O), bl_m = floor_div(qm, O);
+                    const int f = (int)(ql - (long long)bl_l * O) * O + (int)(qm - (long long)bl_m * O);
+                    int kl = (bl_l - S / 2 + 1) % N;
+                    int km = (bl_m - S / 2 + 1) % N;
+                    kl += kl < 0 ? N : 0;
+                    km += km < 0 ? N : 0;
+                    fq[k] = f;
+                    kq[k] = ((uint32_t)kl << 16) | (uint32_t)km;
+                    fcount[f]++;
+                }
+                const size_t base = vis.size();
+                int32_t acc = 0;
+                for (int f = 0; f < O * O; ++f) {
+                    fpos[f] = acc;
+                    if (fcount[f] > 0) {
+                        Group g;
+                        g.f = f;
+                        g.vis_begin = (uint32_t)(base + acc);
+                        g.n_vis = fcount[f];
+                        g.pad = 0;
+                        groups.push_back(g);
+                    }
+                    acc += fcount[f];
+                }
+                vis.resize(base + nb);
+                for (int64_t k = 0; k < nb; ++k) {
+                    VisEnt ve;
+                    ve.vidx = (uint32_t)(rows[k] * n_chan + c);
+                    ve.klo = kq[k];
+                    vis[base + fpos[fq[k]]++] = ve;
+                }
+                it.grp_end = (int32_t)groups.size();
+                items.push_back(it);
+            }
+        }
+        item_ptr[s + 1] = (int32_t)items.size();
+    }
+    if (groups.size() > 2147483647u || vis.size() > 4294967295u)
+        return fail(ctx, PSC_E_UNSUPPORTED, "too many samples for one observation");
+
+    // per (interval, antenna) list of (item, end) in item order
+    std::vector<uint32_t> ant_ptr((size_t)n_int * n_ant + 1, 0), ant_ent(2 * items.size());
+    for (const Item& it : items) {
+        ant_ptr[(size_t)it.interval * n_ant + it.ai + 1]++;
+        ant_ptr[(size_t)it.interval * n_ant + it.aj + 1]++;
+    }
+    for (size_t k = 0; k < (size_t)n_int * n_ant; ++k) ant_ptr[k + 1] += ant_ptr[k];
+    {
+        std::vector<uint32_t> pos(ant_ptr.begin(), ant_ptr.end() - 1);
+        for (size_t i = 0; i < items.size(); ++i) {
+            const Item& it = items[i];
+            ant_ent[pos[(size_t)it.interval * n_ant + it.ai]++] = (uint32_t)(2 * i);
+            ant_ent[pos[(size_t)it.interval * n_ant + it.aj]++] = (uint32_t)(2 * i + 1);
+        }
+    }
+
+    // Airy table range: largest x = pi D nu |l - p| over the image samples,
+    // with room for offsets and squint up to a quarter of the field of view.
+    const double rho_max = sqrt(2.0) * (ctx->m / 2) * ctx->h + 0.25 * ctx->fov;
+    const double x_max = kPi * ctx->cfg.dish_diam_m / lam_min * rho_max;
+    const double dx = 1.0 / 256.0;
+    const int n_tab = (int)ceil(x_max / dx) + 3;
+
+    psc_obs* obs = new psc_obs();
+    obs->ctx = ctx;
+    obs->n_ant = n_ant;
+    obs->n_chan = n_chan;
+    obs->n_pol = d->n_pol;
+    obs->n_int = n_int;
+    obs->n_row = n_row;
+    obs->int_item_ptr = item_ptr;
+    obs->n_items = (int64_t)items.size();
+    obs->n_groups = (int64_t)groups.size();
+    obs->n_vis = (int64_t)vis.size();
+    obs->n_tab = n_tab;
+    obs->inv_dx = 1.0 / dx;
+    hipError_t e = dmalloc(&obs->items, items.size());
+    if (e == hipSuccess) e = dmalloc(&obs->groups, groups.size());
+    if (e == hipSuccess) e = dmalloc(&obs->vis, vis.size());
+    if (e == hipSuccess) e = dmalloc(&obs->ant_ptr, ant_ptr.size());
+    if (e == hipSuccess) e = dmalloc(&obs->ant_ent, ant_ent.size());
+    if (e == hipSuccess) e = dmalloc(&obs->freq, n_chan);
+    if (e == hipSuccess) e = dmalloc(&obs->airy, n_tab);
+    if (e == hipSuccess) e = dmalloc(&obs->partials, items.size() * d->n_pol * 12);
+    if (e == hipSuccess) e = dmalloc(&obs->acc, (size_t)n_int * d->n_pol * n_ant * 6);
+    if (e == hipSuccess) e = dmalloc(&obs->max_step, n_int);
+    if (e == hipSuccess) e = dmalloc(&obs->done, n_int);
+    if (e == hipSuccess) e = dmalloc(&obs->iters, n_int);
+    if (e == hipSuccess && !items.empty())
+        e = hipMemcpy(obs->items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !groups.empty())
+        e = hipMemcpy(obs->groups, groups.data(), sizeof(Group) * groups.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !vis.empty())
+        e = hipMemcpy(obs->vis, vis.data(), sizeof(VisEnt) * vis.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(obs->ant_ptr, ant_ptr.data(), sizeof(uint32_t) * ant_ptr.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !ant_ent.empty())
+        e = hipMemcpy(obs->ant_ent, ant_ent.data(), sizeof(uint32_t) * ant_ent.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(obs->freq, fr.data(), sizeof(double) * n_chan, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_airy_table(obs->airy, n_tab, dx, nullptr);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&obs->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        psc_status st = e == hipErrorOutOfMemory ? PSC_E_OOM : PSC_E_HIP;
+        std::string msg = std::string("psc_obs_create: ") + hipGetErrorString(e);
+        psc_obs_destroy(obs);
+        return fail(ctx, st, msg);
+    }
+    *out = obs;
+    return PSC_OK;
+}
+
+PSC_API psc_status psc_obs_info(const psc_obs* obs, int64_t* n_items, int64_t* n_groups, int64_t* n_vis)
+{
+    if (!obs) return fail(nullptr, PSC_E_ARG, "null observation");
+    if (n_items) *n_items = obs->n_items;
+    if (n_groups) *n_groups = obs->n_groups;
+    if (n_vis) *n_vis = obs->n_vis;
+    return PSC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+ItemArgs item_args(psc_ctx* ctx, psc_obs* obs, const double* offsets, int item_begin, int n_items,
+                   const int32_t* done)
+{
+    ItemArgs a{};
+    a.items = obs->items;
+    a.groups = obs->groups;
+    a.vis = obs->vis;
+    a.item_begin = item_begin;
+    a.n_items = n_items;
+    a.n_ant = obs->n_ant;
+    a.n_pol = obs->n_pol;
+    a.offsets = offsets;
+    a.freq = obs->freq;
+    a.grid = ctx->grid;
+    a.grid_n = ctx->n;
+    a.oversample = ctx->o;
+    a.m = ctx->m;
+    a.h = ctx->h;
+    a.taper_img = ctx->taper_img;
+    a.tw = ctx->tw;
+    a.dish = ctx->cfg.dish_diam_m;
+    a.illum = ctx->cfg.illum;
+    a.gauss_sigma_ld = ctx->cfg.gauss_sigma_ld;
+    a.squint_frac = ctx->cfg.squint_frac;
+    a.airy = obs->airy;
+    a.n_tab = obs->n_tab;
+    a.inv_dx = obs->inv_dx;
+    a.partials = obs->partials;
+    a.done = done;
+    return a;
+}
+
+ReduceArgs reduce_args(psc_obs* obs, int int_begin, int int_end, double* out, const int32_t* done)
+{
+    ReduceArgs r{};
+    r.ant_ptr = obs->ant_ptr;
+    r.ant_ent = obs->ant_ent;
+    r.items = obs->items;
+    r.partials = obs->partials;
+    r.n_int = obs->n_int;
+    r.n_pol = obs->n_pol;
+    r.n_ant = obs->n_ant;
+    r.int_begin = int_begin;
+    r.int_end = int_end;
+    r.out = out;
+    r.done = done;
+    return r;
+}
+
+psc_status check_call(psc_ctx* ctx, psc_obs* obs, const double* offsets)
+{
+    if (!ctx) return fail(nullptr, PSC_E_ARG, "null context");
+    ctx->err.clear();
+    if (!obs || obs->ctx != ctx) return fail(ctx, PSC_E_ARG, "observation missing or from another context");
+    if (!offsets) return fail(ctx, PSC_E_ARG, "null offsets");
+    if (!ctx->model_set) return fail(ctx, PSC_E_STATE, "psc_set_model has not been called");
+    if (hipSetDevice(ctx->cfg.device) != hipSuccess) return fail(ctx, PSC_E_HIP, "hipSetDevice");
+    return PSC_OK;
+}
+
+// One iteration of the solver over intervals [s0, s1): gradient sums, reduce, step.
+hipError_t enqueue_iteration(psc_ctx* ctx, psc_obs* obs, const void* vis_obs, const float* w,
+                             double* offsets, double gain, double tol, int s0, int s1,
+                             const int32_t* done_for_items, hipStream_t st)
+{
+    const int i0 = obs->int_item_ptr[s0], i1 = obs->int_item_ptr[s1];
+    ItemArgs a = item_args(ctx, obs, offsets, i0, i1 - i0, done_for_items);
+    a.vis_in = (const float2*)vis_obs;
+    a.weight = w;
+    hipError_t e = launch_items(kGrad, ctx->s, a, st);
+    if (e != hipSuccess) return e;
+    e = launch_reduce(12, reduce_args(obs, s0, s1, obs->acc, done_for_items), st);
+    if (e != hipSuccess) return e;
+    SolveArgs sa{};
+    sa.n_int = obs->n_int;
+    sa.n_pol = obs->n_pol;
+    sa.n_ant = obs->n_ant;
+    sa.int_begin = s0;
+    sa.int_end = s1;
+    sa.acc = obs->acc;
+    sa.gain = gain;
+    sa.offsets = offsets;
+    sa.max_step = obs->max_step;
+    sa.done = obs->done;
+    sa.iters = obs->iters;
+    sa.tol = tol;
+    return launch_solve(sa, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+PSC_API psc_status psc_predict(psc_ctx* ctx, psc_obs* obs, const double* offsets_dev, void* vis_out_dev,
+                               void* stream)
+{
+    psc_status st = check_call(ctx, obs, offsets_dev);
+    if (st != PSC_OK) return st;
+    if (!vis_out_dev && obs->n_vis > 0) return fail(ctx, PSC_E_ARG, "null output");
+    ItemArgs a = item_args(ctx, obs, offsets_dev, 0, (int)obs->n_items, nullptr);
+    a.vis_out = (float2*)vis_out_dev;
+    PSC_HIP(ctx, launch_items(kPredict, ctx->s, a, (hipStream_t)stream));
+    return PSC_OK;
+}
+
+PSC_API psc_status psc_gradient(psc_ctx* ctx, psc_obs* obs, const double* offsets_dev,
+                                const void* vis_obs_dev, const float* weight_dev, double* acc_out_dev,
+                                void* vis_model_dev, void* stream)
+{
+    psc_status st = check_call(ctx, obs, offsets_dev);
+    if (st != PSC_OK) return st;
+    if (!acc_out_dev || ((!vis_obs_dev || !weight_dev) && obs->n_vis > 0))
+        return fail(ctx, PSC_E_ARG, "null data or output");
+    hipStream_t s = (hipStream_t)stream;
+    ItemArgs a = item_args(ctx, obs, offsets_dev, 0, (int)obs->n_items, nullptr);
+    a.vis_in = (const float2*)vis_obs_dev;
+    a.weight = weight_dev;
+    a.vis_out = (float2*)vis_model_dev;
+    PSC_HIP(ctx, launch_items(kGrad, ctx->s, a, s));
+    PSC_HIP(ctx, launch_reduce(12, reduce_args(obs, 0, obs->n_int, acc_out_dev, nullptr), s));
+    return PSC_OK;
+}
+
+PSC_API psc_status psc_predict_vjp(psc_ctx* ctx, psc_obs* obs, const double* offsets_dev,
+                                   const void* grad_vis_dev, double* grad_offsets_out_dev, void* stream)
+{
+    psc_status st = check_call(ctx, obs, offsets_dev);
+    if (st != PSC_OK) return st;
+    if (!grad_offsets_out_dev || (!grad_vis_dev && obs->n_vis > 0))
+        return fail(ctx, PSC_E_ARG, "null data or output");
+    hipStream_t s = (hipStream_t)stream;
+    ItemArgs a = item_args(ctx, obs, offsets_dev, 0, (int)obs->n_items, nullptr);
+    a.vis_in = (const float2*)grad_vis_dev;
+    PSC_HIP(ctx, launch_items(kVjp, ctx->s, a, s));
+    PSC_HIP(ctx, launch_reduce(4, reduce_args(obs, 0, obs->n_int, grad_offsets_out_dev, nullptr), s));
+    return PSC_OK;
+}
+
+PSC_API psc_status psc_solve_step(psc_ctx* ctx, int32_t n_int, int32_t n_pol, int32_t n_ant,
+                                  const double* acc_dev, double gain, double* offsets_io_dev,
+                                  int32_t* not_updated_dev, double* max_step_dev, void* stream)
+{
+    if (!ctx) return fail(nullptr, PSC_E_ARG, "null context");
+    ctx->err.clear();
+    if (n_int < 1 || n_pol < 1 || n_pol > 2 || n_ant < 1) return fail(ctx, PSC_E_ARG, "bad sizes");
+    if (!acc_dev || !offsets_io_dev) return fail(ctx, PSC_E_ARG, "null array");
+    if (!(gain > 0.0) || !(gain <= 1.0)) return fail(ctx, PSC_E_ARG, "gain must be in (0, 1]");
+    PSC_HIP(ctx, hipSetDevice(ctx->cfg.device));
+    SolveArgs sa{};
+    sa.n_int = n_int;
+    sa.n_pol = n_pol;
+    sa.n_ant = n_ant;
+    sa.int_begin = 0;
+    sa.int_end = n_int;
+    sa.acc = acc_dev;
+    sa.gain = gain;
+    sa.offsets = offsets_io_dev;
+    sa.not_updated = not_updated_dev;
+    sa.max_step = max_step_dev;
+    PSC_HIP(ctx, launch_solve(sa, (hipStream_t)stream));
+    return PSC_OK;
+}
+
+PSC_API psc_status psc_solve(psc_ctx* ctx, psc_obs* obs, const void* vis_obs_dev, const float* weight_dev,
+                             double* offsets_io_dev, double gain, int32_t n_max, double tol_rad,
+                             int32_t form, int32_t* iters_out_dev, void* stream)
+{
+    psc_status st = check_call(ctx, obs, offsets_io_dev);
+    if (st != PSC_OK) return st;
+    if ((!vis_obs_dev || !weight_dev) && obs->n_vis > 0) return fail(ctx, PSC_E_ARG, "null data");
+    if (!(gain > 0.0) || !(gain <= 1.0)) return fail(ctx, PSC_E_ARG, "gain must be in (0, 1]");
+    if (n_max < 0 || !(tol_rad >= 0.0)) return fail(ctx, PSC_E_ARG, "n_max must be >= 0 and tol_rad >= 0");
+    if (form != PSC_SOLVE_PLAIN && form != PSC_SOLVE_BATCHED && form != PSC_SOLVE_GRAPH)
+        return fail(ctx, PSC_E_ARG, "unknown solve form");
+    hipStream_t s = (hipStream_t)stream;
+    PSC_HIP(ctx, launch_init_state(obs->done, obs->iters, obs->n_int, s));
+    if (form == PSC_SOLVE_PLAIN) {
+        for (int iv = 0; iv < obs->n_int; ++iv) {
+            for (int it = 0; it < n_max; ++it) {
+                PSC_HIP(ctx, enqueue_iteration(ctx, obs, vis_obs_dev, weight_dev, offsets_io_dev, gain,
+                                               tol_rad, iv, iv + 1, nullptr, s));
+                double mx = 0.0;
+                PSC_HIP(ctx, hipMemcpyAsync(&mx, obs->max_step + iv, sizeof(double), hipMemcpyDeviceToHost, s));
+                PSC_HIP(ctx, hipStreamSynchronize(s));
+                if (mx < tol_rad) break;
+            }
+        }
+    } else if (form == PSC_SOLVE_BATCHED) {
+        for (int it = 0; it < n_max; ++it)
+            PSC_HIP(ctx, enqueue_iteration(ctx, obs, vis_obs_dev, weight_dev, offsets_io_dev, gain, tol_rad,
+                                           0, obs->n_int, obs->done, s));
+    } else {
+        const bool same = obs->graph && obs->g_vis == vis_obs_dev && obs->g_w == weight_dev &&
+                          obs->g_off == offsets_io_dev && obs->g_gain == gain && obs->g_tol == tol_rad &&
+                          obs->g_nmax == n_max;
+        if (!same) {
+            if (obs->graph) {
+                (void)hipGraphExecDestroy(obs->graph);
+                obs->graph = nullptr;
+            }
+            PSC_HIP(ctx, hipStreamBeginCapture(obs->cap_stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e = hipSuccess;
+            for (int it = 0; it < n_max && e == hipSuccess; ++it)
+                e = enqueue_iteration(ctx, obs, vis_obs_dev, weight_dev, offsets_io_dev, gain, tol_rad, 0,
+                                      obs->n_int, obs->done, obs->cap_stream);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(obs->cap_stream, &g);
+            if (e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return hip_fail(ctx, e, "graph capture");
+            }
+            if (e2 != hipSuccess) return hip_fail(ctx, e2, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&obs->graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                obs->graph = nullptr;
+                return hip_fail(ctx, e, "hipGraphInstantiate");
+            }
+            obs->g_vis = vis_obs_dev;
+            obs->g_w = weight_dev;
+            obs->g_off = offsets_io_dev;
+            obs->g_gain = gain;
+            obs->g_tol = tol_rad;
+            obs->g_nmax = n_max;
+        }
+        // the graph runs on the capture stream after the caller's queued work
+        PSC_HIP(ctx, hipStreamSynchronize(s));
+        PSC_HIP(ctx, hipGraphLaunch(obs->graph, obs->cap_stream));
+        PSC_HIP(ctx, hipStreamSynchronize(obs->cap_stream));
+    }
+    if (iters_out_dev)
+        PSC_HIP(ctx, hipMemcpyAsync(iters_out_dev, obs->iters, sizeof(int32_t) * obs->n_int,
+                                    hipMemcpyDeviceToDevice, s));
+    PSC_HIP(ctx, hipStreamSynchronize(s));
+    return PSC_OK;
+}
+
+}  // extern "C"

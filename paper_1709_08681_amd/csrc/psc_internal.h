@@ -1,0 +1,110 @@
+// psc_internal.h -- types shared by the host API and the kernels of libpsc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace psc {
+
+constexpr double kCLight = 299792458.0;
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kBlock = 256;  // threads per work-item block (4 wavefronts)
+constexpr int kWaves = kBlock / 64;
+
+// One work item: the samples of one baseline in one solution interval at one
+// channel.  Its samples are split into groups by sub-lattice offset f.
+struct Item {
+    int32_t interval;
+    int32_t ai, aj;  // antennas, ai < aj
+    int32_t chan;
+    int32_t grp_begin, grp_end;  // [begin, end) into the group array
+};
+
+// Samples of an item sharing the sub-lattice offset f = fl * O + fm, which
+// selects one S x S sub-table of the oversampled kernel.
+struct Group {
+    int32_t f;
+    uint32_t vis_begin;  // into the sample array
+    int32_t n_vis;
+    int32_t pad;
+};
+
+// One visibility sample: vidx = row * n_chan + chan (vis arrays are
+// [vidx][pol]), klo = first grid row/column of its S x S window, packed as
+// (row << 16) | column, both already reduced modulo N.
+struct VisEnt {
+    uint32_t vidx;
+    uint32_t klo;
+};
+
+enum Mode { kPredict = 0, kGrad = 1, kVjp = 2 };
+
+// Arguments of the fused kernel-build + degrid kernel.
+struct ItemArgs {
+    const Item* items;
+    const Group* groups;
+    const VisEnt* vis;
+    int32_t item_begin, n_items;
+    int32_t n_ant, n_pol;
+    const double* offsets;      // [n_int][n_pol][n_ant][2]
+    const double* freq;         // [n_chan]
+    const float2* grid;         // V^{M0}, [N][N]
+    int32_t grid_n;
+    int32_t oversample;
+    int32_t m;                  // image samples per axis
+    double h;                   // image sample spacing (FoV / S)
+    const double* taper_img;    // [m] taper response at the image samples
+    const float2* tw;           // [S*O] exp(+2 pi i t / (S O))
+    double dish;
+    int32_t illum;
+    double gauss_sigma_ld;
+    double squint_frac;
+    const double4* airy;        // [n_tab] (A, A', B, B') at x = i * dx
+    int32_t n_tab;
+    double inv_dx;
+    // mode-specific
+    float2* vis_out;            // predict: V^M; grad: optional V^M
+    const float2* vis_in;       // grad: V^Obs; vjp: G
+    const float* weight;        // grad
+    double* partials;           // [item][pol][ncontrib]
+    const int32_t* done;        // nullable: per-interval skip flags
+};
+
+struct ReduceArgs {
+    const uint32_t* ant_ptr;    // [(n_int * n_ant) + 1]
+    const uint32_t* ant_ent;    // item * 2 + end
+    const Item* items;
+    const double* partials;
+    int32_t n_int, n_pol, n_ant;
+    int32_t int_begin, int_end;
+    double* out;                // [n_int][n_pol][n_ant][ncontrib/2]
+    const int32_t* done;
+};
+
+struct SolveArgs {
+    int32_t n_int, n_pol, n_ant;
+    int32_t int_begin, int_end;
+    const double* acc;          // [n_int][n_pol][n_ant][6]
+    double gain;
+    double* offsets;
+    int32_t* not_updated;       // nullable
+    double* max_step;           // nullable
+    int32_t* done;              // nullable (solve loop state)
+    int32_t* iters;             // nullable
+    double tol;
+};
+
+// Kernel launchers (psc_kernels.hip).  Each returns the launch's hipError_t.
+hipError_t launch_taper_image(const double* img, const double* taper_pix, double2* out, int n,
+                              hipStream_t s);
+hipError_t launch_fft_rows(double2* data, int n, int log2n, hipStream_t s);
+hipError_t launch_transpose(const double2* in, double2* out, int n, hipStream_t s);
+hipError_t launch_finish_grid(const double2* in, float2* out, int n, hipStream_t s);
+hipError_t launch_airy_table(double4* tab, int n_tab, double dx, hipStream_t s);
+hipError_t launch_items(int mode, int support, const ItemArgs& a, hipStream_t s);
+hipError_t launch_reduce(int ncontrib, const ReduceArgs& a, hipStream_t s);
+hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
+hipError_t launch_init_state(int32_t* done, int32_t* iters, int n, hipStream_t s);
+hipError_t set_fft_twiddles();
+
+}  // namespace psc

@@ -1,0 +1,652 @@
+// psc_kernels.hip -- gfx950 kernels of the Pointing SelfCal hot path.
+//
+// Notation (Bhatnagar & Cornwell 2017): V^{M0} is the gridded transform of
+// the model image (Eq. MEDD), A_ij the uv kernel of baseline (i,j) -- the
+// convolution of the two antennas' aperture functions, each carrying its
+// pointing offset as a phase gradient (Eq. MEDD, Sec. 3) -- and dA_ij/dp its
+// derivative (Eq. DA).  Degridding evaluates V = A_ij * V^{M0} and dV/dp
+// (Algorithm 1, "use A-Projection") at every sample; the residual sums of
+// Eq. DCHIDD are accumulated per antenna in float64.
+//
+// Kernel construction.  With an anti-aliasing taper c(l) (exponential of a
+// semicircle in the uv plane, W cells wide), the grid holds V^{M0} = F[I/c]
+// and the kernel of baseline (i,j) is the transform of E_i E_j c, sampled on
+// the 1/O lattice.  E_i E_j c is band-limited to S cells, so its transform is
+// exactly the DFT of image-plane samples at spacing FoV/S; the samples reach
+// |l| < M/2 * FoV/S, beyond which c is negligible.  Writing a lattice index
+// as f + O b (0 <= f < O), the DFT splits into a twiddle by exp(2 pi i f n/(SO)),
+// a fold of n modulo S, and an S-point DFT over b: each S x S sub-table is one
+// small 2-D FFT.  Only sub-tables that some sample of the item uses are built.
+#include "psc_internal.h"
+
+namespace psc {
+
+__constant__ float2 c_tw64[64];  // exp(+2 pi i t / 64)
+
+hipError_t set_fft_twiddles()
+{
+    float2 h[64];
+    for (int t = 0; t < 64; ++t) {
+        // exact values on the axes, libm elsewhere
+        double c, s;
+        switch (t) {
+        case 0: c = 1; s = 0; break;
+        case 16: c = 0; s = 1; break;
+        case 32: c = -1; s = 0; break;
+        case 48: c = 0; s = -1; break;
+        default: c = cos(2.0 * kPi * t / 64.0); s = sin(2.0 * kPi * t / 64.0);
+        }
+        h[t] = make_float2((float)c, (float)s);
+    }
+    return hipMemcpyToSymbol(HIP_SYMBOL(c_tw64), h, sizeof(h));
+}
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
+{
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__device__ __forceinline__ void cmac(float2& acc, float2 a, float2 b)
+{
+    acc.x = fmaf(a.x, b.x, acc.x);
+    acc.x = fmaf(-a.y, b.y, acc.x);
+    acc.y = fmaf(a.x, b.y, acc.y);
+    acc.y = fmaf(a.y, b.x, acc.y);
+}
+
+// Orders LDS traffic between the lanes of one wavefront.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int LOG>
+__host__ __device__ constexpr int bitrev(int i)
+{
+    int r = 0;
+    for (int b = 0; b < LOG; ++b)
+        if (i & (1 << b)) r |= 1 << (LOG - 1 - b);
+    return r;
+}
+
+// In-register radix-2 DFT X[b] = sum_r x[r] exp(+2 pi i b r / S), S <= 64.
+template <int S>
+__device__ __forceinline__ void fft_reg(float2 (&x)[S])
+{
+    constexpr int LOG = (S == 8) ? 3 : (S == 16) ? 4 : (S == 32) ? 5 : 6;
+    float2 y[S];
+#pragma unroll
+    for (int i = 0; i < S; ++i) y[bitrev<LOG>(i)] = x[i];
+#pragma unroll
+    for (int st = 1; st <= LOG; ++st) {
+        const int mlen = 1 << st, half = mlen >> 1;
+#pragma unroll
+        for (int k = 0; k < S; k += mlen) {
+#pragma unroll
+            for (int j = 0; j < half; ++j) {
+                const float2 w = c_tw64[j * (64 / mlen)];
+                const float2 t = cmul(w, y[k + j + half]);
+                const float2 u = y[k + j];
+                y[k + j] = make_float2(u.x + t.x, u.y + t.y);
+                y[k + j + half] = make_float2(u.x - t.x, u.y - t.y);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < S; ++i) x[i] = y[i];
+}
+
+// ---------------------------------------------------------------------------
+// Model transform (setup): V^{M0}[k] = sum_n I[n]/c[n] exp(+2 pi i k.(n - N/2)/N)
+// ---------------------------------------------------------------------------
+__global__ void k_taper_image(const double* __restrict__ img, const double* __restrict__ tp,
+                              double2* __restrict__ out, int n)
+{
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)n * n) return;
+    const int ix = (int)(idx / n), iy = (int)(idx % n);
+    out[idx] = make_double2(img[idx] / (tp[ix] * tp[iy]), 0.0);
+}
+
+// In-place radix-2 DFT with exponent +2 pi i along each row (one block per row).
+__global__ void k_fft_rows(double2* __restrict__ data, int n, int log2n)
+{
+    extern __shared__ double2 sh[];
+    double2* row = data + (size_t)blockIdx.x * n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        int r = 0;
+        for (int b = 0; b < log2n; ++b)
+            if (i & (1 << b)) r |= 1 << (log2n - 1 - b);
+        sh[r] = row[i];
+    }
+    __syncthreads();
+    for (int st = 1; st <= log2n; ++st) {
+        const int mlen = 1 << st, half = mlen >> 1;
+        for (int b = threadIdx.x; b < n / 2; b += blockDim.x) {
+            const int grp = b / half, j = b % half;
+            const int i0 = grp * mlen + j, i1 = i0 + half;
+            double s, c;
+            sincospi(2.0 * (double)j / (double)mlen, &s, &c);
+            const double2 v = sh[i1];
+            const double2 t = make_double2(c * v.x - s * v.y, c * v.y + s * v.x);
+            const double2 u = sh[i0];
+            sh[i0] = make_double2(u.x + t.x, u.y + t.y);
+            sh[i1] = make_double2(u.x - t.x, u.y - t.y);
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) row[i] = sh[i];
+}
+
+__global__ void k_transpose(const double2* __restrict__ in, double2* __restrict__ out, int n)
+{
+    __shared__ double2 tile[32][33];
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    for (int j = threadIdx.y; j < 32; j += blockDim.y)
+        tile[j][threadIdx.x] = in[(size_t)(by + j) * n + bx + threadIdx.x];
+    __syncthreads();
+    for (int j = threadIdx.y; j < 32; j += blockDim.y)
+        out[(size_t)(bx + j) * n + by + threadIdx.x] = tile[threadIdx.x][j];
+}
+
+__global__ void k_finish_grid(const double2* __restrict__ in, float2* __restrict__ out, int n)
+{
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)n * n) return;
+    const int kx = (int)(idx / n), ky = (int)(idx % n);
+    const double sgn = ((kx + ky) & 1) ? -1.0 : 1.0;  // exp(-i pi (kx + ky)) from the N/2 shift
+    const double2 v = in[idx];
+    out[idx] = make_float2((float)(sgn * v.x), (float)(sgn * v.y));
+}
+
+// ---------------------------------------------------------------------------
+// Airy pattern table: A(x) = 2 J1(x)/x, B(x) = 2 J2(x)/x^2 and their slopes
+// (A' = -x B, B' = (A - 4B)/x), for cubic Hermite interpolation.
+// ---------------------------------------------------------------------------
+__global__ void k_airy_table(double4* __restrict__ tab, int n_tab, double dx)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_tab) return;
+    const double x = i * dx;
+    double A, B, Bp;
+    if (x < 1e-2) {
+        const double x2 = x * x;
+        A = 1.0 - x2 / 8.0 + x2 * x2 / 192.0;
+        B = 0.25 - x2 / 48.0 + x2 * x2 / 1536.0;
+        Bp = -x / 24.0 + x * x2 / 384.0;
+    } else {
+        A = 2.0 * j1(x) / x;
+        B = 2.0 * jn(2, x) / (x * x);
+        Bp = (A - 4.0 * B) / x;
+    }
+    tab[i] = make_double4(A, -x * B, B, Bp);
+}
+
+// Far-field voltage pattern of one antenna at sky offset (dl, dm) = l - p and
+// its derivatives with respect to the pointing offset p.
+__device__ __forceinline__ void efp(const ItemArgs& a, double kk, double sigma, double dl, double dm,
+                                    double& e, double& el, double& em)
+{
+    if (a.illum == 1) {
+        const double inv2 = 1.0 / (sigma * sigma);
+        e = exp(-0.5 * (dl * dl + dm * dm) * inv2);
+        el = e * dl * inv2;
+        em = e * dm * inv2;
+        return;
+    }
+    const double x = kk * sqrt(dl * dl + dm * dm);
+    double u = x * a.inv_dx;
+    int i;
+    if (!(u < (double)(a.n_tab - 2))) {  // beyond the table, or not finite: clamp
+        i = a.n_tab - 2;
+        u = (double)i + 1.0;
+    } else {
+        i = (int)u;
+    }
+    const double t = u - (double)i;
+    const double dx = 1.0 / a.inv_dx;
+    const double4 p0 = a.airy[i], p1 = a.airy[i + 1];
+    const double t2 = t * t, t3 = t2 * t;
+    const double h00 = 2 * t3 - 3 * t2 + 1, h10 = t3 - 2 * t2 + t, h01 = -2 * t3 + 3 * t2,
+                 h11 = t3 - t2;
+    const double A = h00 * p0.x + h10 * dx * p0.y + h01 * p1.x + h11 * dx * p1.y;
+    const double B = h00 * p0.z + h10 * dx * p0.w + h01 * p1.z + h11 * dx * p1.w;
+    e = A;
+    const double k2 = kk * kk * B;
+    el = k2 * dl;
+    em = k2 * dm;
+}
+
+// ---------------------------------------------------------------------------
+// Fused kernel build + degrid + per-item float64 partial sums.
+// One block (4 wavefronts) per item; the wavefronts share the image-plane
+// products and take the item's sub-table groups in turn.  Inside a group, a
+// wavefront holds the S x S sub-table column by column in registers (lane
+// a_m of each S-lane slot keeps column a_m), and degrids 64/S samples at a
+// time, each slot reading one S x S window of V^{M0}.
+// ---------------------------------------------------------------------------
+template <int S, int MODE>
+__global__ void __launch_bounds__(kBlock, 2) k_item(ItemArgs a)
+{
+    constexpr int NV = (MODE == kPredict) ? 1 : (MODE == kGrad) ? 5 : 4;
+    constexpr int NC = (MODE == kGrad) ? 12 : (MODE == kVjp) ? 4 : 0;
+    constexpr int SP = S + 1;
+    constexpr int SPW = 64 / S;
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[kWaves][16];
+
+    const int m = a.m, half_m = m >> 1, m2 = m * m;
+    const int m2p = (m2 + 3) & ~3;
+    float* gsh = reinterpret_cast<float*>(smem);
+    float2* ush = reinterpret_cast<float2*>(smem + sizeof(float) * NV * m2p);
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int per_xcd = gridDim.x >> 3;
+    const int li = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (li >= a.n_items) return;
+    const int item_idx = a.item_begin + li;
+    const Item it = a.items[item_idx];
+    if (a.done != nullptr && a.done[it.interval]) return;
+
+    const int N = a.grid_n, nmask = N - 1;
+    const int O = a.oversample, so = S * O;
+    const double nu = a.freq[it.chan];
+    const double lam = kCLight / nu;
+    const double kk = kPi * a.dish / lam;
+    const double sigma = a.gauss_sigma_ld * lam / a.dish;
+    const double hp = 1.02899 * lam / a.dish;
+    const float inv_s = 1.0f / (float)S;
+
+    for (int pol = 0; pol < a.n_pol; ++pol) {
+        // ---- image-plane products E_i E_j c and their offset derivatives
+        const double sq = (pol == 0 ? 1.0 : -1.0) * a.squint_frac * hp;
+        const double* oi = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.ai) * 2;
+        const double* oj = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.aj) * 2;
+        const double pil = oi[0] + sq, pim = oi[1], pjl = oj[0] + sq, pjm = oj[1];
+        for (int idx = tid; idx < m2; idx += kBlock) {
+            const int il = idx / m, im = idx - il * m;
+            const double l = (il - half_m) * a.h, mm = (im - half_m) * a.h;
+            double ei, eil, eim, ej, ejl, ejm;
+            efp(a, kk, sigma, l - pil, mm - pim, ei, eil, eim);
+            efp(a, kk, sigma, l - pjl, mm - pjm, ej, ejl, ejm);
+            const double c = a.taper_img[il] * a.taper_img[im];
+            if (MODE == kPredict) {
+                gsh[idx] = (float)(ei * ej * c);
+            } else {
+                constexpr int o = (MODE == kGrad) ? 1 : 0;
+                if (MODE == kGrad) gsh[idx] = (float)(ei * ej * c);
+                gsh[(o + 0) * m2p + idx] = (float)(eil * ej * c);
+                gsh[(o + 1) * m2p + idx] = (float)(eim * ej * c);
+                gsh[(o + 2) * m2p + idx] = (float)(ei * ejl * c);
+                gsh[(o + 3) * m2p + idx] = (float)(ei * ejm * c);
+            }
+        }
+        __syncthreads();
+
+        double acc64 = 0.0;
+        float2* uw = ush + (size_t)wave * NV * S * SP;
+        for (int gi = it.grp_begin + wave; gi < it.grp_end; gi += kWaves) {
+            const Group g = a.groups[gi];
+            const int fl = g.f / O, fm = g.f - fl * O;
+
+            // ---- twiddle and fold: U[r] = sum_{n = r mod S} (-1)^n w^{f.n} g[n] / S^2
+            for (int r = lane; r < S * S; r += 64) {
+                const int rl = r / S, rm = r - rl * S;
+                float2 u[NV];
+#pragma unroll
+                for (int k = 0; k < NV; ++k) u[k] = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int el = 0; el < 2; ++el) {
+                    const int nl = rl - el * S;
+                    if (nl < -half_m || nl >= half_m) continue;
+                    int tl = (fl * nl) % so;
+                    tl += (tl < 0) ? so : 0;
+                    float2 pl = a.tw[tl];
+                    const float sl = (nl & 1) ? -inv_s : inv_s;
+                    pl.x *= sl;
+                    pl.y *= sl;
+#pragma unroll
+                    for (int em = 0; em < 2; ++em) {
+                        const int nmv = rm - em * S;
+                        if (nmv < -half_m || nmv >= half_m) continue;
+                        int tm = (fm * nmv) % so;
+                        tm += (tm < 0) ? so : 0;
+                        float2 pm = a.tw[tm];
+                        const float sm = (nmv & 1) ? -inv_s : inv_s;
+                        pm.x *= sm;
+                        pm.y *= sm;
+                        const float2 ph = cmul(pl, pm);
+                        const int gidx = (nl + half_m) * m + (nmv + half_m);
+#pragma unroll
+                        for (int k = 0; k < NV; ++k) {
+                            const float gv = gsh[k * m2p + gidx];
+                            u[k].x = fmaf(gv, ph.x, u[k].x);
+                            u[k].y = fmaf(gv, ph.y, u[k].y);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < NV; ++k) uw[(k * S + rl) * SP + rm] = u[k];
+            }
+            wave_sync();
+
+            // ---- 2-D DFT of each sub-table: rows, then columns
+            for (int t = lane; t < NV * S; t += 64) {
+                const int k = t / S, row = t - k * S;
+                float2 x[S];
+#pragma unroll
+                for (int i = 0; i < S; ++i) x[i] = uw[(k * S + row) * SP + i];
+                fft_reg<S>(x);
+#pragma unroll
+                for (int i = 0; i < S; ++i) uw[(k * S + row) * SP + i] = x[i];
+            }
+            wave_sync();
+            for (int t = lane; t < NV * S; t += 64) {
+                const int k = t / S, col = t - k * S;
+                float2 x[S];
+#pragma unroll
+                for (int i = 0; i < S; ++i) x[i] = uw[(k * S + i) * SP + col];
+                fft_reg<S>(x);
+#pragma unroll
+                for (int i = 0; i < S; ++i) uw[(k * S + i) * SP + col] = x[i];
+            }
+            wave_sync();
+
+            // ---- this lane's kernel column: tap a <-> lattice index b = S-1-a
+            const int am = lane % S;
+            float2 tk[NV][S];
+#pragma unroll
+            for (int k = 0; k < NV; ++k)
+#pragma unroll
+                for (int al = 0; al < S; ++al)
+                    tk[k][al] = uw[(k * S + (S - 1 - al)) * SP + (S - 1 - am)];
+            wave_sync();
+
+            // ---- degrid the group's samples, 64/S at a time
+            const int slot = lane / S;
+            for (int v0 = 0; v0 < g.n_vis; v0 += SPW) {
+                const int v = v0 + slot;
+                const bool active = v < g.n_vis;
+                const VisEnt e = a.vis[g.vis_begin + (active ? v : 0)];
+                const int row0 = (int)(e.klo >> 16);
+                const int col = ((int)(e.klo & 0xffffu) + am) & nmask;
+                float2 s[NV];
+#pragma unroll
+                for (int k = 0; k < NV; ++k) s[k] = make_float2(0.f, 0.f);
+                // window rows in chunks of CH to bound the registers in flight
+                constexpr int CH = 4;
+#pragma unroll
+                for (int a0 = 0; a0 < S; a0 += CH) {
+                    float2 vg[CH];
+#pragma unroll
+                    for (int c = 0; c < CH; ++c)
+                        vg[c] = a.grid[(size_t)((row0 + a0 + c) & nmask) * N + col];
+#pragma unroll
+                    for (int c = 0; c < CH; ++c)
+#pragma unroll
+                        for (int k = 0; k < NV; ++k) cmac(s[k], tk[k][a0 + c], vg[c]);
+                }
+#pragma unroll
+                for (int off = S / 2; off > 0; off >>= 1)
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) {
+                        s[k].x += __shfl_xor(s[k].x, off);
+                        s[k].y += __shfl_xor(s[k].y, off);
+                    }
+                if (!active) continue;
+                const size_t o = (size_t)e.vidx * a.n_pol + pol;
+                const int t = lane - slot * S;
+                if (MODE == kPredict) {
+                    if (t == 0) a.vis_out[o] = s[0];
+                } else if (MODE == kGrad) {
+                    if (a.vis_out != nullptr && t == 0) a.vis_out[o] = s[0];
+                    const float2 vo = a.vis_in[o];
+                    const double w = (double)a.weight[o];
+                    const double rr = (double)vo.x - (double)s[0].x;
+                    const double ri = (double)vo.y - (double)s[0].y;
+                    const int end = (t >= 6) ? 1 : 0;
+                    const int c = t - 6 * end;
+                    const float2 dlf = end ? s[3] : s[1];
+                    const float2 dmf = end ? s[4] : s[2];
+                    const double dlr = dlf.x, dli = dlf.y, dmr = dmf.x, dmi = dmf.y;
+                    double val;
+                    switch (c) {
+                    case 0: val = rr * rr + ri * ri; break;
+                    case 1: val = rr * dlr + ri * dli; break;
+                    case 2: val = rr * dmr + ri * dmi; break;
+                    case 3: val = dlr * dlr + dli * dli; break;
+                    case 4: val = dlr * dmr + dli * dmi; break;
+                    default: val = dmr * dmr + dmi * dmi; break;
+                    }
+                    if (t < 12) acc64 += w * val;
+                } else {
+                    const float2 gv = a.vis_in[o];
+                    const int tt = t < 4 ? t : 0;
+                    float2 dv = s[0];
+#pragma unroll
+                    for (int k = 1; k < 4; ++k)
+                        if (tt == k) dv = s[k];
+                    if (t < 4) acc64 += (double)gv.x * (double)dv.x + (double)gv.y * (double)dv.y;
+                }
+            }
+        }
+
+        // ---- per-item partial sums (fixed reduction order)
+        if (NC > 0) {
+#pragma unroll
+            for (int off = S; off < 64; off <<= 1) acc64 += __shfl_xor(acc64, off);
+            if (lane < NC) red[wave][lane] = acc64;
+            __syncthreads();
+            if (tid < NC) {
+                double sum = red[0][tid];
+#pragma unroll
+                for (int w = 1; w < kWaves; ++w) sum += red[w][tid];
+                a.partials[((size_t)item_idx * a.n_pol + pol) * NC + tid] = sum;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Per (interval, pol, antenna): sum the partials of every item touching the
+// antenna, in a fixed order.  One wavefront each.
+template <int NC>
+__global__ void __launch_bounds__(64) k_reduce(ReduceArgs a)
+{
+    constexpr int NH = NC / 2;
+    const int b = blockIdx.x;
+    const int ant = b % a.n_ant;
+    const int pol = (b / a.n_ant) % a.n_pol;
+    const int s = a.int_begin + b / (a.n_ant * a.n_pol);
+    if (a.done != nullptr && a.done[s]) return;
+    const int lane = threadIdx.x;
+    double sum[NH];
+#pragma unroll
+    for (int c = 0; c < NH; ++c) sum[c] = 0.0;
+    const uint32_t e0 = a.ant_ptr[(size_t)s * a.n_ant + ant];
+    const uint32_t e1 = a.ant_ptr[(size_t)s * a.n_ant + ant + 1];
+    for (uint32_t e = e0 + lane; e < e1; e += 64) {
+        const uint32_t ent = a.ant_ent[e];
+        const uint32_t item = ent >> 1, end = ent & 1u;
+        const double* p = a.partials + ((size_t)item * a.n_pol + pol) * NC + end * NH;
+#pragma unroll
+        for (int c = 0; c < NH; ++c) sum[c] += p[c];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int c = 0; c < NH; ++c) sum[c] += __shfl_xor(sum[c], off);
+    if (lane == 0) {
+        double* o = a.out + (((size_t)s * a.n_pol + pol) * a.n_ant + ant) * NH;
+#pragma unroll
+        for (int c = 0; c < NH; ++c) o[c] = sum[c];
+    }
+}
+
+// Damped 2x2 Gauss-Newton step per antenna, one block per interval.
+__global__ void __launch_bounds__(256) k_solve(SolveArgs a)
+{
+    __shared__ double smax[256];
+    const int s = a.int_begin + blockIdx.x;
+    const int tid = threadIdx.x;
+    if (a.done != nullptr && a.done[s]) {
+        if (tid == 0 && a.max_step != nullptr) a.max_step[s] = 0.0;
+        return;
+    }
+    double mx = 0.0;
+    const int npa = a.n_pol * a.n_ant;
+    for (int pa = tid; pa < npa; pa += blockDim.x) {
+        const size_t k = (size_t)s * npa + pa;
+        const double* t = a.acc + 6 * k;
+        const double gl = t[1], gm = t[2], hll = t[3], hlm = t[4], hmm = t[5];
+        const double tr = hll + hmm;
+        const bool bad = !(isfinite(gl) && isfinite(gm) && isfinite(hll) && isfinite(hlm) &&
+                           isfinite(hmm)) || !(tr > 0.0);
+        if (a.not_updated != nullptr) a.not_updated[k] = bad ? 1 : 0;
+        if (bad) continue;
+        const double det = hll * hmm - hlm * hlm;
+        double dl, dm;
+        if (det > 1e-12 * tr * tr) {
+            dl = (hmm * gl - hlm * gm) / det;
+            dm = (hll * gm - hlm * gl) / det;
+        } else {
+            dl = hll > 0.0 ? gl / hll : 0.0;
+            dm = hmm > 0.0 ? gm / hmm : 0.0;
+        }
+        dl *= a.gain;
+        dm *= a.gain;
+        a.offsets[2 * k] += dl;
+        a.offsets[2 * k + 1] += dm;
+        mx = fmax(mx, sqrt(dl * dl + dm * dm));
+    }
+    smax[tid] = mx;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (tid < w) smax[tid] = fmax(smax[tid], smax[tid + w]);
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const double m = smax[0];
+        if (a.max_step != nullptr) a.max_step[s] = m;
+        if (a.iters != nullptr) a.iters[s] += 1;
+        if (a.done != nullptr) a.done[s] = (m < a.tol) ? 1 : 0;
+    }
+}
+
+__global__ void k_init_state(int32_t* done, int32_t* iters, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        done[i] = 0;
+        iters[i] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_taper_image(const double* img, const double* taper_pix, double2* out, int n,
+                              hipStream_t s)
+{
+    const size_t tot = (size_t)n * n;
+    k_taper_image<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(img, taper_pix, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_rows(double2* data, int n, int log2n, hipStream_t s)
+{
+    const size_t sh = sizeof(double2) * (size_t)n;
+    hipError_t e = hipFuncSetAttribute((const void*)k_fft_rows,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    if (e != hipSuccess) return e;
+    k_fft_rows<<<n, 256, sh, s>>>(data, n, log2n);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose(const double2* in, double2* out, int n, hipStream_t s)
+{
+    dim3 grid(n / 32, n / 32), block(32, 8);
+    k_transpose<<<grid, block, 0, s>>>(in, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_grid(const double2* in, float2* out, int n, hipStream_t s)
+{
+    const size_t tot = (size_t)n * n;
+    k_finish_grid<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(in, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_airy_table(double4* tab, int n_tab, double dx, hipStream_t s)
+{
+    k_airy_table<<<(n_tab + 255) / 256, 256, 0, s>>>(tab, n_tab, dx);
+    return hipGetLastError();
+}
+
+template <int S, int MODE>
+static hipError_t launch_items_t(const ItemArgs& a, hipStream_t s)
+{
+    constexpr int NV = (MODE == kPredict) ? 1 : (MODE == kGrad) ? 5 : 4;
+    const int m2p = (a.m * a.m + 3) & ~3;
+    const size_t sh = sizeof(float) * NV * m2p + sizeof(float2) * kWaves * NV * S * (S + 1);
+    // raise the dynamic LDS limit once, to the largest size any image_samples can need
+    static const hipError_t attr = [] {
+        const int mmax = 2 * S;
+        const size_t shmax = sizeof(float) * NV * ((mmax * mmax + 3) & ~3) +
+                             sizeof(float2) * kWaves * NV * S * (S + 1);
+        return hipFuncSetAttribute((const void*)k_item<S, MODE>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmax);
+    }();
+    if (attr != hipSuccess) return attr;
+    const int blocks = 8 * ((a.n_items + 7) / 8);
+    k_item<S, MODE><<<blocks, kBlock, sh, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_items(int mode, int support, const ItemArgs& a, hipStream_t s)
+{
+    if (a.n_items <= 0) return hipSuccess;
+    if (support != 16) return hipErrorInvalidValue;
+    switch (mode) {
+    case kPredict: return launch_items_t<16, kPredict>(a, s);
+    case kGrad: return launch_items_t<16, kGrad>(a, s);
+    case kVjp: return launch_items_t<16, kVjp>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_reduce(int ncontrib, const ReduceArgs& a, hipStream_t s)
+{
+    const int nb = (a.int_end - a.int_begin) * a.n_pol * a.n_ant;
+    if (nb <= 0) return hipSuccess;
+    if (ncontrib == 12)
+        k_reduce<12><<<nb, 64, 0, s>>>(a);
+    else if (ncontrib == 4)
+        k_reduce<4><<<nb, 64, 0, s>>>(a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_solve(const SolveArgs& a, hipStream_t s)
+{
+    const int nb = a.int_end - a.int_begin;
+    if (nb <= 0) return hipSuccess;
+    k_solve<<<nb, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_state(int32_t* done, int32_t* iters, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_init_state<<<(n + 255) / 256, 256, 0, s>>>(done, iters, n);
+    return hipGetLastError();
+}
+
+}  // namespace psc

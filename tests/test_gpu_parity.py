@@ -1,0 +1,288 @@
+"""GPU parity: libpsc (HIP, gfx950) against the FP64 direct-summation oracle.
+
+Tolerances (per result):
+  visibilities  ||dV|| / ||V||        <= 1e-5
+  chi, g, H     ||d acc|| / ||acc||   <= 1e-4 (at perturbed offsets, |g| >> 0)
+  offsets       max |p_gpu - p_oracle| <= 0.1 arcsec after the same iterations
+Integer/plan work (iteration counts, flags) must match exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1709_08681_amd import synth
+
+pytestmark = pytest.mark.gpu
+ARCSEC = math.pi / 180 / 3600
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1709_08681_amd import psc
+    psc.load()
+    return torch
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def session(obs, **kw):
+    from paper_1709_08681_amd.psc import Session
+    return Session(obs, device=0, **kw)
+
+
+def c64(torch, s, a):
+    return torch.as_tensor(np.ascontiguousarray(a).astype(np.complex64), device=s.dev)
+
+
+def f32(torch, s, a, shape):
+    return torch.as_tensor(np.ascontiguousarray(np.broadcast_to(a, shape)).astype(np.float32),
+                           device=s.dev)
+
+
+# ---------------------------------------------------------------------------
+# tiny array (config 1), every result
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def cfg1(torch_dev):
+    obs = synth.make_config(1)
+    prob = oracle.Problem.from_observation(obs)
+    s = session(obs)
+    yield obs, prob, s
+    s.close()
+
+
+def test_predict_cfg1(torch_dev, cfg1):
+    obs, prob, s = cfg1
+    print("case: predict cfg1", flush=True)
+    for seed in (1, 2):
+        off = synth.perturbed_offsets(obs, 20.0, seed)
+        ref = oracle.predict(prob, off)
+        got = s.predict(off).cpu().numpy()
+        assert rel(got, ref) <= 1e-5
+        assert np.abs(got - ref).max() / np.abs(ref).max() <= 1e-5
+
+
+def test_gradient_cfg1(torch_dev, cfg1):
+    torch = torch_dev
+    obs, prob, s = cfg1
+    print("case: gradient cfg1", flush=True)
+    v = oracle.predict(prob, obs.offsets_true)
+    nz, w = synth.noise(v, 100.0, 3)
+    vo = v + nz
+    start = synth.perturbed_offsets(obs, 20.0, 4)
+    ref, vm_ref = oracle.gradient(prob, start, vo, w, want_model=True)
+    acc, vm = s.gradient(s.offsets(start), c64(torch, s, vo), f32(torch, s, w, s.vis_shape),
+                         want_model=True)
+    acc = acc.cpu().numpy()
+    assert rel(vm.cpu().numpy(), vm_ref) <= 1e-5
+    for k, name in enumerate(["chi", "g_l", "g_m", "H_ll", "H_lm", "H_mm"]):
+        assert rel(acc[..., k], ref[..., k]) <= 1e-4, name
+
+
+def test_gradient_is_deterministic(torch_dev, cfg1):
+    torch = torch_dev
+    obs, prob, s = cfg1
+    v = s.predict(obs.offsets_true)
+    w = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+    off = s.offsets(synth.perturbed_offsets(obs, 20.0, 5))
+    a1 = s.gradient(off, v, w)
+    a2 = s.gradient(off, v, w)
+    assert torch.equal(a1, a2)
+
+
+def test_hermitian_symmetry_gpu(torch_dev, cfg1):
+    """V_ji(-u) = conj V_ij(u): rows reversed and negated give conjugates."""
+    obs, prob, s = cfg1
+    from paper_1709_08681_amd.psc import Session
+    flip = synth.Observation(obs.wl, obs.ant_pos, obs.ant1, obs.ant2, obs.time_idx, -obs.uv_m,
+                             obs.int_row_ptr, obs.freq_hz, obs.grid_n, obs.cell_rad, obs.src_pix,
+                             obs.src_flux, obs.offsets_true)
+    # a baseline with its antennas swapped is the same baseline with uv negated
+    # and the model conjugated; with equal offsets at both ends the products
+    # E_i E_j are symmetric, so V(-u) must be conj V(u).
+    off = np.repeat(obs.offsets_true[:, :, :1, :], obs.n_ant, axis=2)
+    s2 = Session(flip, device=0)
+    try:
+        a = s.predict(off).cpu().numpy()
+        b = s2.predict(off).cpu().numpy()
+    finally:
+        s2.close()
+    assert rel(b, np.conj(a)) <= 1e-5
+
+
+def test_vjp_matches_oracle(torch_dev, cfg1):
+    torch = torch_dev
+    obs, prob, s = cfg1
+    print("case: vjp cfg1", flush=True)
+    off = synth.perturbed_offsets(obs, 20.0, 6)
+    rng = np.random.default_rng(7)
+    G = rng.normal(size=s.vis_shape) + 1j * rng.normal(size=s.vis_shape)
+    G = G.astype(np.complex64)
+    _, dv = oracle.predict(prob, off, want_grad=True)
+    ref = np.zeros(s.off_shape)
+    for r in range(obs.n_row):
+        i, j = obs.ant1[r], obs.ant2[r]
+        for c in range(obs.n_chan):
+            for p in range(obs.n_pol):
+                g = G[r, c, p].astype(np.complex128)
+                for ax in range(2):
+                    ref[0, p, i, ax] += (np.conj(g) * dv[r, c, p, ax]).real
+                    ref[0, p, j, ax] += (np.conj(g) * dv[r, c, p, 2 + ax]).real
+    got = s.vjp(s.offsets(off), torch.as_tensor(G, device=s.dev)).cpu().numpy()
+    assert rel(got, ref) <= 1e-4
+
+
+def test_autograd_chi2_gradient(torch_dev, cfg1):
+    """d chi^2 / d p through the autograd Function equals -2 g of psc_gradient
+    and the oracle's."""
+    torch = torch_dev
+    from paper_1709_08681_amd.autograd import predict
+    obs, prob, s = cfg1
+    v = oracle.predict(prob, obs.offsets_true)
+    vo = c64(torch, s, v)
+    start = synth.perturbed_offsets(obs, 20.0, 8)
+    off = s.offsets(start).requires_grad_(True)
+    model = predict(off, s)
+    loss = ((vo - model).abs() ** 2).sum()
+    loss.backward()
+    ref = oracle.gradient(prob, start, v, 1.0)
+    assert rel(off.grad.cpu().numpy(), -2 * ref[..., 1:3]) <= 1e-4
+
+
+def test_solve_step_matches_oracle(torch_dev, cfg1):
+    torch = torch_dev
+    obs, prob, s = cfg1
+    rng = np.random.default_rng(9)
+    acc = np.zeros((3, 2, 5, 6))
+    acc[..., 1:3] = rng.normal(size=(3, 2, 5, 2))
+    A = rng.normal(size=(3, 2, 5, 2, 2))
+    H = A @ np.swapaxes(A, -1, -2) + 0.1 * np.eye(2)
+    acc[..., 3], acc[..., 4], acc[..., 5] = H[..., 0, 0], H[..., 0, 1], H[..., 1, 1]
+    acc[1, 0, 2, 3:] = 0.0  # no data
+    acc[2, 1, 4, 3:] = [1.0, 1.0, 1.0]  # singular
+    off0 = rng.normal(size=(3, 2, 5, 2)) * 1e-4
+    ref, nu_ref, mx_ref = oracle.solve_step(acc, 0.5, off0)
+    from paper_1709_08681_amd import psc
+    offs = torch.as_tensor(off0, device=s.dev)
+    nu = torch.empty((3, 2, 5), dtype=torch.int32, device=s.dev)
+    mx = torch.empty(3, dtype=torch.float64, device=s.dev)
+    psc.psc_solve_step(s.ctx, 3, 2, 5, torch.as_tensor(acc, device=s.dev), 0.5, offs, nu, mx)
+    np.testing.assert_allclose(offs.cpu().numpy(), ref, rtol=1e-12, atol=1e-18)
+    assert np.array_equal(nu.cpu().numpy(), nu_ref)
+    np.testing.assert_allclose(mx.cpu().numpy(), mx_ref, rtol=1e-12)
+
+
+def test_solve_forms_match_oracle(torch_dev, cfg1):
+    """Algorithm 1 at SNR 100: GPU offsets within 0.1 arcsec of the oracle's
+    after the same iterations, and the three execution forms bit-identical."""
+    torch = torch_dev
+    from paper_1709_08681_amd import psc
+    obs, prob, s = cfg1
+    print("case: solve cfg1", flush=True)
+    v = oracle.predict(prob, obs.offsets_true)
+    nz, w = synth.noise(v, 100.0, 10)
+    vo = v + nz
+    start = synth.perturbed_offsets(obs, 20.0, 11)
+    ref, its_ref = oracle.solve(prob, vo, w, start, gain=0.5, n_max=10, tol_rad=1e-3 * ARCSEC)
+    vo_d = c64(torch, s, vo)
+    w_d = f32(torch, s, w, s.vis_shape)
+    outs = []
+    for form in (psc.SOLVE_PLAIN, psc.SOLVE_BATCHED, psc.SOLVE_GRAPH, psc.SOLVE_GRAPH):
+        off = s.offsets(start)
+        its = s.solve(vo_d, w_d, off, gain=0.5, n_max=10, tol_rad=1e-3 * ARCSEC, form=form)
+        outs.append((off.cpu().numpy(), its.cpu().numpy()))
+    for o, its in outs:
+        assert np.array_equal(its, its_ref)
+        assert np.abs(o - ref).max() / ARCSEC <= 0.1
+    for o, its in outs[1:]:
+        assert np.array_equal(o, outs[0][0])
+
+
+def test_recovers_injected_offsets(torch_dev, cfg1):
+    torch = torch_dev
+    obs, prob, s = cfg1
+    v = oracle.predict(prob, obs.offsets_true)
+    vo = c64(torch, s, v)
+    w = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+    off = s.offsets(synth.perturbed_offsets(obs, 20.0, 12))
+    s.solve(vo, w, off, gain=0.5, n_max=80, tol_rad=1e-5 * ARCSEC)
+    err = np.abs(off.cpu().numpy() - obs.offsets_true).max() / ARCSEC
+    assert err <= 0.05, err
+
+
+# ---------------------------------------------------------------------------
+# ragged intervals, two polarisations with squint, flagged data, empty interval
+# ---------------------------------------------------------------------------
+
+def test_ragged_intervals_two_pols(torch_dev):
+    torch = torch_dev
+    from paper_1709_08681_amd import psc
+    print("case: ragged intervals, 2 pols", flush=True)
+    lengths = [3, 0, 7, 1, 5]
+    wl = synth.workload(1, n_ant=7, n_time=sum(lengths), interval_lengths=lengths, n_pol=2,
+                        squint_frac=0.03, freqs_hz=np.array([1.2e9, 1.45e9, 1.7e9]), n_src=5)
+    obs = synth.make_observation(wl, 77)
+    prob = oracle.Problem.from_observation(obs)
+    s = session(obs)
+    try:
+        start = synth.perturbed_offsets(obs, 25.0, 13)
+        ref = oracle.predict(prob, start)
+        got = s.predict(start).cpu().numpy()
+        assert rel(got, ref) <= 1e-5
+        v = oracle.predict(prob, obs.offsets_true)
+        w = np.ones(s.vis_shape)
+        # flag every sample of antenna 3 in interval 2
+        r0, r1 = obs.int_row_ptr[2], obs.int_row_ptr[3]
+        rows = np.arange(r0, r1)
+        flag = rows[(obs.ant1[rows] == 3) | (obs.ant2[rows] == 3)]
+        w[flag] = 0.0
+        acc_ref = oracle.gradient(prob, start, v, w)
+        acc = s.gradient(s.offsets(start), c64(torch, s, v), f32(torch, s, w, s.vis_shape))
+        acc = acc.cpu().numpy()
+        assert rel(acc, acc_ref) <= 1e-4
+        assert np.all(acc[1] == 0.0)  # empty interval
+        assert np.all(acc[2, :, 3] == 0.0)  # flagged antenna
+        ref_off, its_ref = oracle.solve(prob, v, w, start, gain=0.5, n_max=8, tol_rad=1e-3 * ARCSEC)
+        for form in (psc.SOLVE_PLAIN, psc.SOLVE_GRAPH):
+            off = s.offsets(start)
+            its = s.solve(c64(torch, s, v), f32(torch, s, w, s.vis_shape), off, gain=0.5, n_max=8,
+                          tol_rad=1e-3 * ARCSEC, form=form)
+            assert np.array_equal(its.cpu().numpy(), its_ref)
+            o = off.cpu().numpy()
+            assert np.abs(o - ref_off).max() / ARCSEC <= 0.1
+            assert np.array_equal(o[2, :, 3], start[2, :, 3])  # not updated
+    finally:
+        s.close()
+
+
+# ---------------------------------------------------------------------------
+# single interval at full size (config 2: 2,021,760 visibilities)
+# ---------------------------------------------------------------------------
+
+def test_cfg2_full_size_parity(torch_dev):
+    torch = torch_dev
+    print("case: cfg2 full size", flush=True)
+    obs = synth.make_config(2)
+    prob = oracle.Problem.from_observation(obs)
+    s = session(obs)
+    try:
+        start = synth.perturbed_offsets(obs, 30.0, 14)
+        v_true = oracle.predict(prob, obs.offsets_true)
+        ref_acc, ref_vm = oracle.gradient(prob, start, v_true, 1.0, want_model=True)
+        w = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+        acc, vm = s.gradient(s.offsets(start), c64(torch, s, v_true), w, want_model=True)
+        e_v = rel(vm.cpu().numpy(), ref_vm)
+        e_a = [rel(acc.cpu().numpy()[..., k], ref_acc[..., k]) for k in range(6)]
+        print(f"cfg2: vis rel {e_v:.2e}, acc rel {max(e_a):.2e}", flush=True)
+        assert e_v <= 1e-5
+        assert max(e_a) <= 1e-4
+    finally:
+        s.close()
