@@ -60,7 +60,7 @@ def cpu_baseline(obs, start, seconds):
         "unit": "vis/s",
         "cores": int(oracle.num_threads()),
         "kind": "oracle",
-        "sample": f"full workload ({obs.n_vis} visibilities x {prob.n_src} sky pixels), "
+        "sample": f"full workload ({obs.n_vis} visibilities x {len(prob.src_flux)} sky pixels), "
                   f"{iters} gradient+update iteration(s) in {dt:.1f} s, FP64 direct summation",
     }
 

@@ -17,9 +17,9 @@ struct psc_ctx {
     psc_config cfg{};
     int n = 0, s = 0, o = 0, m = 0;
     double fov = 0, h = 0, snap = 0;
-    float2* grid = nullptr;        // V^{M0}, N x N complex64
+    float2* grid = nullptr;        // V^{M0}, (N+S) x (N+S) complex64, periodic padding
     double* taper_pix = nullptr;   // [N]
-    double* taper_img = nullptr;   // [M]
+    float* taper_img = nullptr;    // [M]
     float2* tw = nullptr;          // [S*O]
     bool model_set = false;
     std::string err;
@@ -37,7 +37,7 @@ struct psc_obs {
     uint32_t* ant_ptr = nullptr;
     uint32_t* ant_ent = nullptr;
     double* freq = nullptr;
-    double4* airy = nullptr;
+    float4* airy = nullptr;
     int32_t n_tab = 0;
     double inv_dx = 0;
     double* partials = nullptr;  // [n_items][n_pol][12]
@@ -203,9 +203,10 @@ PSC_API psc_status psc_create(const psc_config* cfg, psc_ctx** out)
     ctx->snap = (double)c.oversample * ctx->fov;
 
     Taper taper(tw, tb);
-    std::vector<double> tp(ctx->n), ti(m);
+    std::vector<double> tp(ctx->n);
+    std::vector<float> ti(m);
     for (int i = 0; i < ctx->n; ++i) tp[i] = taper((double)(i - ctx->n / 2) / ctx->n);
-    for (int i = 0; i < m; ++i) ti[i] = taper((double)(i - m / 2) / c.support);
+    for (int i = 0; i < m; ++i) ti[i] = (float)taper((double)(i - m / 2) / c.support);
     const int so = c.support * c.oversample;
     std::vector<float2> twh(so);
     for (int t = 0; t < so; ++t) {
@@ -221,12 +222,12 @@ PSC_API psc_status psc_create(const psc_config* cfg, psc_ctx** out)
         twh[t] = make_float2((float)cv, (float)sv);
     }
     hipError_t e = set_fft_twiddles();
-    if (e == hipSuccess) e = dmalloc(&ctx->grid, (size_t)ctx->n * ctx->n);
+    if (e == hipSuccess) e = dmalloc(&ctx->grid, (size_t)(ctx->n + ctx->s) * (ctx->n + ctx->s));
     if (e == hipSuccess) e = dmalloc(&ctx->taper_pix, ctx->n);
     if (e == hipSuccess) e = dmalloc(&ctx->taper_img, m);
     if (e == hipSuccess) e = dmalloc(&ctx->tw, so);
     if (e == hipSuccess) e = hipMemcpy(ctx->taper_pix, tp.data(), sizeof(double) * ctx->n, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(ctx->taper_img, ti.data(), sizeof(double) * m, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->taper_img, ti.data(), sizeof(float) * m, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->tw, twh.data(), sizeof(float2) * so, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         std::string msg = std::string("context allocation: ") + hipGetErrorString(e);
@@ -267,7 +268,7 @@ PSC_API psc_status psc_set_model(psc_ctx* ctx, const double* image_dev, void* st
     if (e == hipSuccess) e = launch_transpose(a, b, n, st);
     if (e == hipSuccess) e = launch_fft_rows(b, n, log2n, st);
     if (e == hipSuccess) e = launch_transpose(b, a, n, st);
-    if (e == hipSuccess) e = launch_finish_grid(a, ctx->grid, n, st);
+    if (e == hipSuccess) e = launch_finish_grid(a, ctx->grid, n, ctx->s, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     dfree(a);
     dfree(b);
@@ -542,7 +543,7 @@ ItemArgs item_args(psc_ctx* ctx, psc_obs* obs, const double* offsets, int item_b
     a.squint_frac = ctx->cfg.squint_frac;
     a.airy = obs->airy;
     a.n_tab = obs->n_tab;
-    a.inv_dx = obs->inv_dx;
+    a.inv_dx = (float)obs->inv_dx;
     a.partials = obs->partials;
     a.done = done;
     return a;

@@ -48,20 +48,20 @@ struct ItemArgs {
     int32_t n_ant, n_pol;
     const double* offsets;      // [n_int][n_pol][n_ant][2]
     const double* freq;         // [n_chan]
-    const float2* grid;         // V^{M0}, [N][N]
+    const float2* grid;         // V^{M0}, [N+S][N+S], last S rows/columns repeat the first
     int32_t grid_n;
     int32_t oversample;
     int32_t m;                  // image samples per axis
     double h;                   // image sample spacing (FoV / S)
-    const double* taper_img;    // [m] taper response at the image samples
+    const float* taper_img;     // [m] taper response at the image samples
     const float2* tw;           // [S*O] exp(+2 pi i t / (S O))
     double dish;
     int32_t illum;
     double gauss_sigma_ld;
     double squint_frac;
-    const double4* airy;        // [n_tab] (A, A', B, B') at x = i * dx
+    const float4* airy;         // [n_tab] (A, dx A', B, dx B') at x = i * dx
     int32_t n_tab;
-    double inv_dx;
+    float inv_dx;
     // mode-specific
     float2* vis_out;            // predict: V^M; grad: optional V^M
     const float2* vis_in;       // grad: V^Obs; vjp: G
@@ -99,8 +99,8 @@ hipError_t launch_taper_image(const double* img, const double* taper_pix, double
                               hipStream_t s);
 hipError_t launch_fft_rows(double2* data, int n, int log2n, hipStream_t s);
 hipError_t launch_transpose(const double2* in, double2* out, int n, hipStream_t s);
-hipError_t launch_finish_grid(const double2* in, float2* out, int n, hipStream_t s);
-hipError_t launch_airy_table(double4* tab, int n_tab, double dx, hipStream_t s);
+hipError_t launch_finish_grid(const double2* in, float2* out, int n, int pad, hipStream_t s);
+hipError_t launch_airy_table(float4* tab, int n_tab, double dx, hipStream_t s);
 hipError_t launch_items(int mode, int support, const ItemArgs& a, hipStream_t s);
 hipError_t launch_reduce(int ncontrib, const ReduceArgs& a, hipStream_t s);
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s);

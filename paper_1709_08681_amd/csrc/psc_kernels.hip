@@ -21,25 +21,36 @@
 
 namespace psc {
 
-__constant__ float2 c_tw64[64];  // exp(+2 pi i t / 64)
-
-hipError_t set_fft_twiddles()
-{
-    float2 h[64];
-    for (int t = 0; t < 64; ++t) {
-        // exact values on the axes, libm elsewhere
-        double c, s;
-        switch (t) {
-        case 0: c = 1; s = 0; break;
-        case 16: c = 0; s = 1; break;
-        case 32: c = -1; s = 0; break;
-        case 48: c = 0; s = -1; break;
-        default: c = cos(2.0 * kPi * t / 64.0); s = sin(2.0 * kPi * t / 64.0);
+// exp(+2 pi i j / 64), j = 0..63, evaluated at compile time (Taylor series on
+// [-pi, pi], exact on the axes) so that the unrolled FFT sees literal twiddles.
+struct TwTable {
+    float re[64];
+    float im[64];
+    constexpr TwTable() : re(), im()
+    {
+        for (int j = 0; j < 64; ++j) {
+            const int jj = j > 32 ? j - 64 : j;
+            const double x = kPi * jj / 32.0;
+            double sn = x, cs = 1.0, ts = x, tc = 1.0;
+            for (int k = 1; k < 30; ++k) {
+                ts *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+                sn += ts;
+                tc *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+                cs += tc;
+            }
+            if (j % 16 == 0) {
+                const int q = j / 16;
+                cs = (q == 0) ? 1.0 : (q == 2) ? -1.0 : 0.0;
+                sn = (q == 1) ? 1.0 : (q == 3) ? -1.0 : 0.0;
+            }
+            re[j] = (float)cs;
+            im[j] = (float)sn;
         }
-        h[t] = make_float2((float)c, (float)s);
     }
-    return hipMemcpyToSymbol(HIP_SYMBOL(c_tw64), h, sizeof(h));
-}
+};
+constexpr TwTable kTw{};
+
+hipError_t set_fft_twiddles() { return hipSuccess; }
 
 // ---------------------------------------------------------------------------
 // small helpers
@@ -65,6 +76,24 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Sum over each row of 16 lanes with DPP moves (quad swaps, then half-row and
+// row mirrors); every lane of the row ends with the row's total.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
+                                                                 0xF, 0xF, true));
+}
+
+__device__ __forceinline__ float row16_sum(float v)
+{
+    v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141>(v);  // row_half_mirror
+    v += dpp_mov<0x140>(v);  // row_mirror
+    return v;
+}
+
 template <int LOG>
 __host__ __device__ constexpr int bitrev(int i)
 {
@@ -72,6 +101,18 @@ __host__ __device__ constexpr int bitrev(int i)
     for (int b = 0; b < LOG; ++b)
         if (i & (1 << b)) r |= 1 << (LOG - 1 - b);
     return r;
+}
+
+// t = w * v for the twiddle w = exp(+2 pi i j / 64) (j known after unrolling);
+// multiplications by 1, i, -1, -i are dropped.
+__device__ __forceinline__ float2 twmul(int j, float2 v)
+{
+    if (j == 0) return v;
+    if (j == 16) return make_float2(-v.y, v.x);
+    if (j == 32) return make_float2(-v.x, -v.y);
+    if (j == 48) return make_float2(v.y, -v.x);
+    const float wr = kTw.re[j], wi = kTw.im[j];
+    return make_float2(v.x * wr - v.y * wi, v.x * wi + v.y * wr);
 }
 
 // In-register radix-2 DFT X[b] = sum_r x[r] exp(+2 pi i b r / S), S <= 64.
@@ -89,8 +130,7 @@ __device__ __forceinline__ void fft_reg(float2 (&x)[S])
         for (int k = 0; k < S; k += mlen) {
 #pragma unroll
             for (int j = 0; j < half; ++j) {
-                const float2 w = c_tw64[j * (64 / mlen)];
-                const float2 t = cmul(w, y[k + j + half]);
+                const float2 t = twmul(j * (64 / mlen), y[k + j + half]);
                 const float2 u = y[k + j];
                 y[k + j] = make_float2(u.x + t.x, u.y + t.y);
                 y[k + j + half] = make_float2(u.x - t.x, u.y - t.y);
@@ -154,13 +194,17 @@ __global__ void k_transpose(const double2* __restrict__ in, double2* __restrict_
         out[(size_t)(bx + j) * n + by + threadIdx.x] = tile[threadIdx.x][j];
 }
 
-__global__ void k_finish_grid(const double2* __restrict__ in, float2* __restrict__ out, int n)
+// Writes V^{M0} into a (N+pad) x (N+pad) array whose last `pad` rows and
+// columns repeat the first ones (V^{M0} is N-periodic because the sky lies on
+// the pixel lattice), so an S x S window starting anywhere in [0, N) never wraps.
+__global__ void k_finish_grid(const double2* __restrict__ in, float2* __restrict__ out, int n, int pad)
 {
+    const int p = n + pad;
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (size_t)n * n) return;
-    const int kx = (int)(idx / n), ky = (int)(idx % n);
+    if (idx >= (size_t)p * p) return;
+    const int kx = (int)(idx / p) % n, ky = (int)(idx % p) % n;
     const double sgn = ((kx + ky) & 1) ? -1.0 : 1.0;  // exp(-i pi (kx + ky)) from the N/2 shift
-    const double2 v = in[idx];
+    const double2 v = in[(size_t)kx * n + ky];
     out[idx] = make_float2((float)(sgn * v.x), (float)(sgn * v.y));
 }
 
@@ -168,7 +212,7 @@ __global__ void k_finish_grid(const double2* __restrict__ in, float2* __restrict
 // Airy pattern table: A(x) = 2 J1(x)/x, B(x) = 2 J2(x)/x^2 and their slopes
 // (A' = -x B, B' = (A - 4B)/x), for cubic Hermite interpolation.
 // ---------------------------------------------------------------------------
-__global__ void k_airy_table(double4* __restrict__ tab, int n_tab, double dx)
+__global__ void k_airy_table(float4* __restrict__ tab, int n_tab, double dx)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_tab) return;
@@ -184,40 +228,40 @@ __global__ void k_airy_table(double4* __restrict__ tab, int n_tab, double dx)
         B = 2.0 * jn(2, x) / (x * x);
         Bp = (A - 4.0 * B) / x;
     }
-    tab[i] = make_double4(A, -x * B, B, Bp);
+    // slopes pre-multiplied by the spacing, as the Hermite form uses them
+    tab[i] = make_float4((float)A, (float)(-x * B * dx), (float)B, (float)(Bp * dx));
 }
 
 // Far-field voltage pattern of one antenna at sky offset (dl, dm) = l - p and
-// its derivatives with respect to the pointing offset p.
-__device__ __forceinline__ void efp(const ItemArgs& a, double kk, double sigma, double dl, double dm,
-                                    double& e, double& el, double& em)
+// its derivatives with respect to the pointing offset p (float32; the Airy
+// pattern from the cubic Hermite table, the Gaussian in closed form).
+__device__ __forceinline__ void efp(const ItemArgs& a, float kk, float inv_s2, float dl, float dm,
+                                    float& e, float& el, float& em)
 {
     if (a.illum == 1) {
-        const double inv2 = 1.0 / (sigma * sigma);
-        e = exp(-0.5 * (dl * dl + dm * dm) * inv2);
-        el = e * dl * inv2;
-        em = e * dm * inv2;
+        e = expf(-0.5f * (dl * dl + dm * dm) * inv_s2);
+        el = e * dl * inv_s2;
+        em = e * dm * inv_s2;
         return;
     }
-    const double x = kk * sqrt(dl * dl + dm * dm);
-    double u = x * a.inv_dx;
+    const float x = kk * sqrtf(dl * dl + dm * dm);
+    float u = x * a.inv_dx;
     int i;
-    if (!(u < (double)(a.n_tab - 2))) {  // beyond the table, or not finite: clamp
+    if (!(u < (float)(a.n_tab - 2))) {  // beyond the table, or not finite: clamp
         i = a.n_tab - 2;
-        u = (double)i + 1.0;
+        u = (float)i + 1.0f;
     } else {
         i = (int)u;
     }
-    const double t = u - (double)i;
-    const double dx = 1.0 / a.inv_dx;
-    const double4 p0 = a.airy[i], p1 = a.airy[i + 1];
-    const double t2 = t * t, t3 = t2 * t;
-    const double h00 = 2 * t3 - 3 * t2 + 1, h10 = t3 - 2 * t2 + t, h01 = -2 * t3 + 3 * t2,
-                 h11 = t3 - t2;
-    const double A = h00 * p0.x + h10 * dx * p0.y + h01 * p1.x + h11 * dx * p1.y;
-    const double B = h00 * p0.z + h10 * dx * p0.w + h01 * p1.z + h11 * dx * p1.w;
+    const float t = u - (float)i;
+    const float4 p0 = a.airy[i], p1 = a.airy[i + 1];
+    const float t2 = t * t, t3 = t2 * t;
+    const float h00 = 2.f * t3 - 3.f * t2 + 1.f, h10 = t3 - 2.f * t2 + t, h01 = -2.f * t3 + 3.f * t2,
+                h11 = t3 - t2;
+    const float A = h00 * p0.x + h10 * p0.y + h01 * p1.x + h11 * p1.y;
+    const float B = h00 * p0.z + h10 * p0.w + h01 * p1.z + h11 * p1.w;
     e = A;
-    const double k2 = kk * kk * B;
+    const float k2 = kk * kk * B;
     el = k2 * dl;
     em = k2 * dm;
 }
@@ -230,7 +274,7 @@ __device__ __forceinline__ void efp(const ItemArgs& a, double kk, double sigma, 
 // a_m of each S-lane slot keeps column a_m), and degrids 64/S samples at a
 // time, each slot reading one S x S window of V^{M0}.
 // ---------------------------------------------------------------------------
-template <int S, int MODE>
+template <int S, int MODE, int SPL>
 __global__ void __launch_bounds__(kBlock, 2) k_item(ItemArgs a)
 {
     constexpr int NV = (MODE == kPredict) ? 1 : (MODE == kGrad) ? 5 : 4;
@@ -239,12 +283,16 @@ __global__ void __launch_bounds__(kBlock, 2) k_item(ItemArgs a)
     constexpr int SPW = 64 / S;
 
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[kWaves][16];
+    __shared__ float2 twsh[S * 16];  // exp(+2 pi i t / (S O)), O <= 16
+    __shared__ int next_group;
 
     const int m = a.m, half_m = m >> 1, m2 = m * m;
     const int m2p = (m2 + 3) & ~3;
-    float* gsh = reinterpret_cast<float*>(smem);
-    float2* ush = reinterpret_cast<float2*>(smem + sizeof(float) * NV * m2p);
+    // dynamic LDS: per-group float64 sums | image-plane products | sub-tables
+    double* gpart = reinterpret_cast<double*>(smem);
+    const int O2 = a.oversample * a.oversample;
+    float* gsh = reinterpret_cast<float*>(smem + sizeof(double) * (NC > 0 ? NC : 1) * O2);
+    float2* ush = reinterpret_cast<float2*>(reinterpret_cast<unsigned char*>(gsh) + sizeof(float) * NV * m2p);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int per_xcd = gridDim.x >> 3;
@@ -254,45 +302,74 @@ __global__ void __launch_bounds__(kBlock, 2) k_item(ItemArgs a)
     const Item it = a.items[item_idx];
     if (a.done != nullptr && a.done[it.interval]) return;
 
-    const int N = a.grid_n, nmask = N - 1;
+    const int N = a.grid_n;
     const int O = a.oversample, so = S * O;
     const double nu = a.freq[it.chan];
     const double lam = kCLight / nu;
-    const double kk = kPi * a.dish / lam;
+    const float kk = (float)(kPi * a.dish / lam);
     const double sigma = a.gauss_sigma_ld * lam / a.dish;
+    const float inv_s2 = (float)(1.0 / (sigma * sigma));
     const double hp = 1.02899 * lam / a.dish;
+    const float hstep = (float)a.h;
     const float inv_s = 1.0f / (float)S;
+    const int P = N + S;  // pitch of the padded grid
+    const int rowbytes = P * (int)sizeof(float2);
+    const __amdgpu_buffer_rsrc_t grsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)a.grid, (short)0, P * P * (int)sizeof(float2), 0x00020000);
+
+    for (int t = tid; t < so; t += kBlock) twsh[t] = a.tw[t];
 
     for (int pol = 0; pol < a.n_pol; ++pol) {
+        if (tid == 0) next_group = it.grp_begin + kWaves;
         // ---- image-plane products E_i E_j c and their offset derivatives
         const double sq = (pol == 0 ? 1.0 : -1.0) * a.squint_frac * hp;
         const double* oi = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.ai) * 2;
         const double* oj = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.aj) * 2;
-        const double pil = oi[0] + sq, pim = oi[1], pjl = oj[0] + sq, pjm = oj[1];
+        const float pil = (float)(oi[0] + sq), pim = (float)oi[1];
+        const float pjl = (float)(oj[0] + sq), pjm = (float)oj[1];
         for (int idx = tid; idx < m2; idx += kBlock) {
             const int il = idx / m, im = idx - il * m;
-            const double l = (il - half_m) * a.h, mm = (im - half_m) * a.h;
-            double ei, eil, eim, ej, ejl, ejm;
-            efp(a, kk, sigma, l - pil, mm - pim, ei, eil, eim);
-            efp(a, kk, sigma, l - pjl, mm - pjm, ej, ejl, ejm);
-            const double c = a.taper_img[il] * a.taper_img[im];
+            const float l = (float)(il - half_m) * hstep, mm = (float)(im - half_m) * hstep;
+            float ei, eil, eim, ej, ejl, ejm;
+            efp(a, kk, inv_s2, l - pil, mm - pim, ei, eil, eim);
+            efp(a, kk, inv_s2, l - pjl, mm - pjm, ej, ejl, ejm);
+            const float c = a.taper_img[il] * a.taper_img[im];
             if (MODE == kPredict) {
-                gsh[idx] = (float)(ei * ej * c);
+                gsh[idx] = ei * ej * c;
             } else {
                 constexpr int o = (MODE == kGrad) ? 1 : 0;
-                if (MODE == kGrad) gsh[idx] = (float)(ei * ej * c);
-                gsh[(o + 0) * m2p + idx] = (float)(eil * ej * c);
-                gsh[(o + 1) * m2p + idx] = (float)(eim * ej * c);
-                gsh[(o + 2) * m2p + idx] = (float)(ei * ejl * c);
-                gsh[(o + 3) * m2p + idx] = (float)(ei * ejm * c);
+                if (MODE == kGrad) gsh[idx] = ei * ej * c;
+                gsh[(o + 0) * m2p + idx] = eil * ej * c;
+                gsh[(o + 1) * m2p + idx] = eim * ej * c;
+                gsh[(o + 2) * m2p + idx] = ei * ejl * c;
+                gsh[(o + 3) * m2p + idx] = ei * ejm * c;
             }
         }
         __syncthreads();
 
         double acc64 = 0.0;
         float2* uw = ush + (size_t)wave * NV * S * SP;
-        for (int gi = it.grp_begin + wave; gi < it.grp_end; gi += kWaves) {
-            const Group g = a.groups[gi];
+        // groups are handed out to wavefronts dynamically, first one each
+        const int slot = lane / S;
+        const int am = lane - slot * S;
+        int gi = it.grp_begin + wave;
+        Group g = a.groups[gi < it.grp_end ? gi : it.grp_begin];
+        while (gi < it.grp_end) {
+            // claim the next group and start fetching its descriptor and this
+            // group's first samples; both loads complete behind the fold/FFT
+            int nxt_g = 0;
+            if (lane == 0) nxt_g = atomicAdd(&next_group, 1);
+            nxt_g = __shfl(nxt_g, 0);
+            const Group gnext = a.groups[nxt_g < it.grp_end ? nxt_g : gi];
+            constexpr int STEP = SPW * SPL;
+            const int nv = g.n_vis;
+            const uint32_t vb = g.vis_begin;
+            VisEnt ent[SPL];
+#pragma unroll
+            for (int j = 0; j < SPL; ++j) {
+                const int v = slot + SPW * j;
+                ent[j] = a.vis[vb + (v < nv ? v : nv - 1)];
+            }
             const int fl = g.f / O, fm = g.f - fl * O;
 
             // ---- twiddle and fold: U[r] = sum_{n = r mod S} (-1)^n w^{f.n} g[n] / S^2
@@ -307,7 +384,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_item(ItemArgs a)
                     if (nl < -half_m || nl >= half_m) continue;
                     int tl = (fl * nl) % so;
                     tl += (tl < 0) ? so : 0;
-                    float2 pl = a.tw[tl];
+                    float2 pl = twsh[tl];
                     const float sl = (nl & 1) ? -inv_s : inv_s;
                     pl.x *= sl;
                     pl.y *= sl;
@@ -317,7 +394,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_item(ItemArgs a)
                         if (nmv < -half_m || nmv >= half_m) continue;
                         int tm = (fm * nmv) % so;
                         tm += (tm < 0) ? so : 0;
-                        float2 pm = a.tw[tm];
+                        float2 pm = twsh[tm];
                         const float sm = (nmv & 1) ? -inv_s : inv_s;
                         pm.x *= sm;
                         pm.y *= sm;
@@ -358,97 +435,118 @@ __global__ void __launch_bounds__(kBlock, 2) k_item(ItemArgs a)
             }
             wave_sync();
 
-            // ---- this lane's kernel column: tap a <-> lattice index b = S-1-a
-            const int am = lane % S;
-            float2 tk[NV][S];
+            // ---- degrid.  Lane (slot, a_m) of the wavefront reads column a_m of
+            // every S x S window it handles; tap (a_l, a_m) uses lattice index
+            // b = (S-1-a_l, S-1-a_m) of the sub-tables, read from LDS (the four
+            // slots read the same addresses).  Each lane carries SPL samples.
+            const int t = am;
+            for (int v0 = 0; v0 < nv; v0 += STEP) {
+                // re-read the sub-tables from LDS every iteration instead of
+                // letting the compiler keep all S*NV values in registers
+                int kofs = S - 1 - am;
+                asm volatile("" : "+v"(kofs));
+                const float2* kcol = uw + kofs;
+                VisEnt nxt[SPL];
+                int voff[SPL];
+                float2 vin[SPL];
+                float wgt[SPL];
 #pragma unroll
-            for (int k = 0; k < NV; ++k)
+                for (int j = 0; j < SPL; ++j) {
+                    const int vn = v0 + STEP + slot + SPW * j;
+                    nxt[j] = a.vis[vb + (vn < nv ? vn : nv - 1)];  // next iteration, early
+                    const int row0 = (int)(ent[j].klo >> 16);
+                    const int col0 = (int)(ent[j].klo & 0xffffu);
+                    voff[j] = (row0 * P + col0 + am) * (int)sizeof(float2);
+                    // this iteration's data, fetched before the multiply-adds
+                    const size_t o = (size_t)ent[j].vidx * a.n_pol + pol;
+                    if (MODE != kPredict) vin[j] = a.vis_in[o];
+                    if (MODE == kGrad) wgt[j] = a.weight[o];
+                }
+                float2 s[SPL][NV];
 #pragma unroll
-                for (int al = 0; al < S; ++al)
-                    tk[k][al] = uw[(k * S + (S - 1 - al)) * SP + (S - 1 - am)];
-            wave_sync();
-
-            // ---- degrid the group's samples, 64/S at a time
-            const int slot = lane / S;
-            for (int v0 = 0; v0 < g.n_vis; v0 += SPW) {
-                const int v = v0 + slot;
-                const bool active = v < g.n_vis;
-                const VisEnt e = a.vis[g.vis_begin + (active ? v : 0)];
-                const int row0 = (int)(e.klo >> 16);
-                const int col = ((int)(e.klo & 0xffffu) + am) & nmask;
-                float2 s[NV];
+                for (int j = 0; j < SPL; ++j)
 #pragma unroll
-                for (int k = 0; k < NV; ++k) s[k] = make_float2(0.f, 0.f);
-                // window rows in chunks of CH to bound the registers in flight
-                constexpr int CH = 4;
+                    for (int k = 0; k < NV; ++k) s[j][k] = make_float2(0.f, 0.f);
 #pragma unroll
-                for (int a0 = 0; a0 < S; a0 += CH) {
-                    float2 vg[CH];
+                for (int al = 0; al < S; ++al) {
+                    float2 kv[NV];
 #pragma unroll
-                    for (int c = 0; c < CH; ++c)
-                        vg[c] = a.grid[(size_t)((row0 + a0 + c) & nmask) * N + col];
+                    for (int k = 0; k < NV; ++k) kv[k] = kcol[(k * S + (S - 1 - al)) * SP];
 #pragma unroll
-                    for (int c = 0; c < CH; ++c)
+                    for (int j = 0; j < SPL; ++j) {
+                        const float2 gv = __builtin_bit_cast(
+                            float2, __builtin_amdgcn_raw_buffer_load_b64(grsrc, voff[j], al * rowbytes, 0));
 #pragma unroll
-                        for (int k = 0; k < NV; ++k) cmac(s[k], tk[k][a0 + c], vg[c]);
+                        for (int k = 0; k < NV; ++k) cmac(s[j][k], kv[k], gv);
+                    }
                 }
 #pragma unroll
-                for (int off = S / 2; off > 0; off >>= 1)
+                for (int j = 0; j < SPL; ++j)
 #pragma unroll
                     for (int k = 0; k < NV; ++k) {
-                        s[k].x += __shfl_xor(s[k].x, off);
-                        s[k].y += __shfl_xor(s[k].y, off);
+                        s[j][k].x = row16_sum(s[j][k].x);
+                        s[j][k].y = row16_sum(s[j][k].y);
                     }
-                if (!active) continue;
-                const size_t o = (size_t)e.vidx * a.n_pol + pol;
-                const int t = lane - slot * S;
-                if (MODE == kPredict) {
-                    if (t == 0) a.vis_out[o] = s[0];
-                } else if (MODE == kGrad) {
-                    if (a.vis_out != nullptr && t == 0) a.vis_out[o] = s[0];
-                    const float2 vo = a.vis_in[o];
-                    const double w = (double)a.weight[o];
-                    const double rr = (double)vo.x - (double)s[0].x;
-                    const double ri = (double)vo.y - (double)s[0].y;
-                    const int end = (t >= 6) ? 1 : 0;
-                    const int c = t - 6 * end;
-                    const float2 dlf = end ? s[3] : s[1];
-                    const float2 dmf = end ? s[4] : s[2];
-                    const double dlr = dlf.x, dli = dlf.y, dmr = dmf.x, dmi = dmf.y;
-                    double val;
-                    switch (c) {
-                    case 0: val = rr * rr + ri * ri; break;
-                    case 1: val = rr * dlr + ri * dli; break;
-                    case 2: val = rr * dmr + ri * dmi; break;
-                    case 3: val = dlr * dlr + dli * dli; break;
-                    case 4: val = dlr * dmr + dli * dmi; break;
-                    default: val = dmr * dmr + dmi * dmi; break;
-                    }
-                    if (t < 12) acc64 += w * val;
-                } else {
-                    const float2 gv = a.vis_in[o];
-                    const int tt = t < 4 ? t : 0;
-                    float2 dv = s[0];
 #pragma unroll
-                    for (int k = 1; k < 4; ++k)
-                        if (tt == k) dv = s[k];
-                    if (t < 4) acc64 += (double)gv.x * (double)dv.x + (double)gv.y * (double)dv.y;
+                for (int j = 0; j < SPL; ++j) {
+                    const int v = v0 + slot + SPW * j;
+                    if (v >= nv) continue;
+                    const size_t o = (size_t)ent[j].vidx * a.n_pol + pol;
+                    if (MODE == kPredict) {
+                        if (t == 0) a.vis_out[o] = s[j][0];
+                    } else if (MODE == kGrad) {
+                        if (a.vis_out != nullptr && t == 0) a.vis_out[o] = s[j][0];
+                        const float2 vo = vin[j];
+                        const double w = (double)wgt[j];
+                        const double rr = (double)vo.x - (double)s[j][0].x;
+                        const double ri = (double)vo.y - (double)s[j][0].y;
+                        const int end = (t >= 6) ? 1 : 0;
+                        const int c = t - 6 * end;
+                        const float2 dlf = end ? s[j][3] : s[j][1];
+                        const float2 dmf = end ? s[j][4] : s[j][2];
+                        const double dlr = dlf.x, dli = dlf.y, dmr = dmf.x, dmi = dmf.y;
+                        double val;
+                        switch (c) {
+                        case 0: val = rr * rr + ri * ri; break;
+                        case 1: val = rr * dlr + ri * dli; break;
+                        case 2: val = rr * dmr + ri * dmi; break;
+                        case 3: val = dlr * dlr + dli * dli; break;
+                        case 4: val = dlr * dmr + dli * dmi; break;
+                        default: val = dmr * dmr + dmi * dmi; break;
+                        }
+                        if (t < 12) acc64 += w * val;
+                    } else {
+                        const float2 gv = vin[j];
+                        const int tt = t < 4 ? t : 0;
+                        float2 dv = s[j][0];
+#pragma unroll
+                        for (int k = 1; k < 4; ++k)
+                            if (tt == k) dv = s[j][k];
+                        if (t < 4) acc64 += (double)gv.x * (double)dv.x + (double)gv.y * (double)dv.y;
+                    }
                 }
+#pragma unroll
+                for (int j = 0; j < SPL; ++j) ent[j] = nxt[j];
             }
+            wave_sync();  // the sub-table buffer is rewritten by the next group
+            if (NC > 0) {
+                // the group's own sums, in a fixed order, kept per group so the
+                // item total does not depend on which wavefront took the group
+#pragma unroll
+                for (int off = S; off < 64; off <<= 1) acc64 += __shfl_xor(acc64, off);
+                if (lane < NC) gpart[(gi - it.grp_begin) * NC + lane] = acc64;
+                acc64 = 0.0;
+            }
+            gi = nxt_g;
+            g = gnext;
         }
 
-        // ---- per-item partial sums (fixed reduction order)
-        if (NC > 0) {
-#pragma unroll
-            for (int off = S; off < 64; off <<= 1) acc64 += __shfl_xor(acc64, off);
-            if (lane < NC) red[wave][lane] = acc64;
-            __syncthreads();
-            if (tid < NC) {
-                double sum = red[0][tid];
-#pragma unroll
-                for (int w = 1; w < kWaves; ++w) sum += red[w][tid];
-                a.partials[((size_t)item_idx * a.n_pol + pol) * NC + tid] = sum;
-            }
+        // ---- per-item partial sums: groups added in group order
+        __syncthreads();
+        if (NC > 0 && tid < NC) {
+            double sum = 0.0;
+            for (int gg = 0; gg < it.grp_end - it.grp_begin; ++gg) sum += gpart[gg * NC + tid];
+            a.partials[((size_t)item_idx * a.n_pol + pol) * NC + tid] = sum;
         }
         __syncthreads();
     }
@@ -576,36 +674,38 @@ hipError_t launch_transpose(const double2* in, double2* out, int n, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_finish_grid(const double2* in, float2* out, int n, hipStream_t s)
+hipError_t launch_finish_grid(const double2* in, float2* out, int n, int pad, hipStream_t s)
 {
-    const size_t tot = (size_t)n * n;
-    k_finish_grid<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(in, out, n);
+    const size_t tot = (size_t)(n + pad) * (n + pad);
+    k_finish_grid<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(in, out, n, pad);
     return hipGetLastError();
 }
 
-hipError_t launch_airy_table(double4* tab, int n_tab, double dx, hipStream_t s)
+hipError_t launch_airy_table(float4* tab, int n_tab, double dx, hipStream_t s)
 {
     k_airy_table<<<(n_tab + 255) / 256, 256, 0, s>>>(tab, n_tab, dx);
     return hipGetLastError();
 }
 
-template <int S, int MODE>
+template <int S, int MODE, int SPL>
 static hipError_t launch_items_t(const ItemArgs& a, hipStream_t s)
 {
     constexpr int NV = (MODE == kPredict) ? 1 : (MODE == kGrad) ? 5 : 4;
+    constexpr int NC = (MODE == kGrad) ? 12 : (MODE == kVjp) ? 4 : 1;
     const int m2p = (a.m * a.m + 3) & ~3;
-    const size_t sh = sizeof(float) * NV * m2p + sizeof(float2) * kWaves * NV * S * (S + 1);
+    const size_t gp = sizeof(double) * NC * a.oversample * a.oversample;
+    const size_t sh = gp + sizeof(float) * NV * m2p + sizeof(float2) * kWaves * NV * S * (S + 1);
     // raise the dynamic LDS limit once, to the largest size any image_samples can need
     static const hipError_t attr = [] {
         const int mmax = 2 * S;
-        const size_t shmax = sizeof(float) * NV * ((mmax * mmax + 3) & ~3) +
+        const size_t shmax = sizeof(double) * NC * 256 + sizeof(float) * NV * ((mmax * mmax + 3) & ~3) +
                              sizeof(float2) * kWaves * NV * S * (S + 1);
-        return hipFuncSetAttribute((const void*)k_item<S, MODE>,
+        return hipFuncSetAttribute((const void*)k_item<S, MODE, SPL>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmax);
     }();
     if (attr != hipSuccess) return attr;
     const int blocks = 8 * ((a.n_items + 7) / 8);
-    k_item<S, MODE><<<blocks, kBlock, sh, s>>>(a);
+    k_item<S, MODE, SPL><<<blocks, kBlock, sh, s>>>(a);
     return hipGetLastError();
 }
 
@@ -614,9 +714,9 @@ hipError_t launch_items(int mode, int support, const ItemArgs& a, hipStream_t s)
     if (a.n_items <= 0) return hipSuccess;
     if (support != 16) return hipErrorInvalidValue;
     switch (mode) {
-    case kPredict: return launch_items_t<16, kPredict>(a, s);
-    case kGrad: return launch_items_t<16, kGrad>(a, s);
-    case kVjp: return launch_items_t<16, kVjp>(a, s);
+    case kPredict: return launch_items_t<16, kPredict, 2>(a, s);
+    case kGrad: return launch_items_t<16, kGrad, 2>(a, s);
+    case kVjp: return launch_items_t<16, kVjp, 2>(a, s);
     default: return hipErrorInvalidValue;
     }
 }
