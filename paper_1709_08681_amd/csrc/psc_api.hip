@@ -171,8 +171,8 @@ PSC_API psc_status psc_create(const psc_config* cfg, psc_ctx** out)
         return fail(nullptr, PSC_E_ARG, "grid_n must be a power of two in [64, 8192]");
     if (c.support != 16 && c.support != 32)
         return fail(nullptr, PSC_E_ARG, "support must be 16 or 32");
-    if (c.oversample < 1 || c.oversample > 16 || c.support * c.oversample > 512)
-        return fail(nullptr, PSC_E_ARG, "oversample must be in [1, 16] with support*oversample <= 512");
+    if (c.oversample < 1 || c.oversample > 16 || !is_pow2(c.oversample) || c.support * c.oversample > 512)
+        return fail(nullptr, PSC_E_ARG, "oversample must be a power of two in [1, 16] with support*oversample <= 512");
     const int m = c.image_samples ? c.image_samples : 3 * c.support / 2;
     if (m < c.support || m > 2 * c.support || (m & 1))
         return fail(nullptr, PSC_E_ARG, "image_samples must be even and in [support, 2*support]");
@@ -402,19 +402,31 @@ PSC_API psc_status psc_obs_create(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
                     kq[k] = ((uint32_t)kl << 16) | (uint32_t)km;
                     fcount[f]++;
                 }
+                // one group per pair of opposite offsets {f, -f}
                 const size_t base = vis.size();
                 int32_t acc = 0;
                 for (int f = 0; f < O * O; ++f) {
-                    fpos[f] = acc;
-                    if (fcount[f] > 0) {
-                        Group g;
-                        g.f = f;
-                        g.vis_begin = (uint32_t)(base + acc);
-                        g.n_vis = fcount[f];
-                        g.pad = 0;
-                        groups.push_back(g);
+                    const int fl = f / O, fm = f % O;
+                    const int pf = ((O - fl) % O) * O + (O - fm) % O;
+                    if (pf < f) continue;  // handled with its partner
+                    int prim = f, sec = (pf != f) ? pf : -1;
+                    if (fcount[prim] == 0) {
+                        if (sec < 0 || fcount[sec] == 0) continue;
+                        prim = sec;
+                        sec = -1;
                     }
-                    acc += fcount[f];
+                    Group g;
+                    g.f = prim;
+                    g.vis_begin = (uint32_t)(base + acc);
+                    g.n_vis = fcount[prim];
+                    g.n_vis2 = (sec >= 0) ? fcount[sec] : 0;
+                    fpos[prim] = acc;
+                    acc += g.n_vis;
+                    if (g.n_vis2 > 0) {
+                        fpos[sec] = acc;
+                        acc += g.n_vis2;
+                    }
+                    groups.push_back(g);
                 }
                 vis.resize(base + nb);
                 for (int64_t k = 0; k < nb; ++k) {

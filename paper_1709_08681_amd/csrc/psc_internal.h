@@ -21,12 +21,14 @@ struct Item {
 };
 
 // Samples of an item sharing the sub-lattice offset f = fl * O + fm, which
-// selects one S x S sub-table of the oversampled kernel.
+// selects one S x S sub-table of the oversampled kernel, followed by the
+// samples of the opposite offset -f (mod O per axis), whose sub-table is the
+// reflected conjugate of f's because the image-plane products are real.
 struct Group {
     int32_t f;
     uint32_t vis_begin;  // into the sample array
-    int32_t n_vis;
-    int32_t pad;
+    int32_t n_vis;       // samples at offset f
+    int32_t n_vis2;      // samples at offset -f that follow them (0 if -f == f)
 };
 
 // One visibility sample: vidx = row * n_chan + chan (vis arrays are

@@ -274,8 +274,10 @@ __device__ __forceinline__ void efp(const ItemArgs& a, float kk, float inv_s2, f
 // a_m of each S-lane slot keeps column a_m), and degrids 64/S samples at a
 // time, each slot reading one S x S window of V^{M0}.
 // ---------------------------------------------------------------------------
+// LDS holds two blocks per CU, i.e. two wavefronts per SIMD; telling the
+// compiler so lets it keep every window load of an iteration in flight.
 template <int S, int MODE, int SPL>
-__global__ void __launch_bounds__(kBlock, 2) k_item(ItemArgs a)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) k_item(ItemArgs a)
 {
     constexpr int NV = (MODE == kPredict) ? 1 : (MODE == kGrad) ? 5 : 4;
     constexpr int NC = (MODE == kGrad) ? 12 : (MODE == kVjp) ? 4 : 0;
@@ -284,6 +286,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_item(ItemArgs a)
 
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ float2 twsh[S * 16];  // exp(+2 pi i t / (S O)), O <= 16
+    __shared__ float2 phsh[kWaves][64];  // per-wave phase vectors of the current group
     __shared__ int next_group;
 
     const int m = a.m, half_m = m >> 1, m2 = m * m;
@@ -349,6 +352,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_item(ItemArgs a)
 
         double acc64 = 0.0;
         float2* uw = ush + (size_t)wave * NV * S * SP;
+        float2* phw = phsh[wave];
         // groups are handed out to wavefronts dynamically, first one each
         const int slot = lane / S;
         const int am = lane - slot * S;
@@ -372,7 +376,21 @@ __global__ void __launch_bounds__(kBlock, 2) k_item(ItemArgs a)
             }
             const int fl = g.f / O, fm = g.f - fl * O;
 
-            // ---- twiddle and fold: U[r] = sum_{n = r mod S} (-1)^n w^{f.n} g[n] / S^2
+            // ---- per-axis phases (-1)^n exp(2 pi i f n / (S O)) / S, n in [-M/2, M/2)
+            if (lane < m) {
+                const int n = lane - half_m;
+                float2 p = twsh[(fl * n) & (so - 1)];
+                const float sg = (n & 1) ? -inv_s : inv_s;
+                phw[lane] = make_float2(p.x * sg, p.y * sg);
+            } else if (lane >= 32 && lane - 32 < m) {
+                const int n = lane - 32 - half_m;
+                float2 p = twsh[(fm * n) & (so - 1)];
+                const float sg = (n & 1) ? -inv_s : inv_s;
+                phw[lane] = make_float2(p.x * sg, p.y * sg);
+            }
+            wave_sync();
+
+            // ---- twiddle and fold: U[r] = sum_{n = r mod S} phase_l(n_l) phase_m(n_m) g[n]
             for (int r = lane; r < S * S; r += 64) {
                 const int rl = r / S, rm = r - rl * S;
                 float2 u[NV];
@@ -382,31 +400,26 @@ __global__ void __launch_bounds__(kBlock, 2) k_item(ItemArgs a)
                 for (int el = 0; el < 2; ++el) {
                     const int nl = rl - el * S;
                     if (nl < -half_m || nl >= half_m) continue;
-                    int tl = (fl * nl) % so;
-                    tl += (tl < 0) ? so : 0;
-                    float2 pl = twsh[tl];
-                    const float sl = (nl & 1) ? -inv_s : inv_s;
-                    pl.x *= sl;
-                    pl.y *= sl;
+                    // inner fold along m for this n_l, then one complex twiddle
+                    float2 x[NV];
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) x[k] = make_float2(0.f, 0.f);
 #pragma unroll
                     for (int em = 0; em < 2; ++em) {
                         const int nmv = rm - em * S;
                         if (nmv < -half_m || nmv >= half_m) continue;
-                        int tm = (fm * nmv) % so;
-                        tm += (tm < 0) ? so : 0;
-                        float2 pm = twsh[tm];
-                        const float sm = (nmv & 1) ? -inv_s : inv_s;
-                        pm.x *= sm;
-                        pm.y *= sm;
-                        const float2 ph = cmul(pl, pm);
+                        const float2 pm = phw[32 + nmv + half_m];
                         const int gidx = (nl + half_m) * m + (nmv + half_m);
 #pragma unroll
                         for (int k = 0; k < NV; ++k) {
                             const float gv = gsh[k * m2p + gidx];
-                            u[k].x = fmaf(gv, ph.x, u[k].x);
-                            u[k].y = fmaf(gv, ph.y, u[k].y);
+                            x[k].x = fmaf(gv, pm.x, x[k].x);
+                            x[k].y = fmaf(gv, pm.y, x[k].y);
                         }
                     }
+                    const float2 pl = phw[nl + half_m];
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) cmac(u[k], pl, x[k]);
                 }
 #pragma unroll
                 for (int k = 0; k < NV; ++k) uw[(k * S + rl) * SP + rm] = u[k];
@@ -440,6 +453,12 @@ __global__ void __launch_bounds__(kBlock, 2) k_item(ItemArgs a)
             // b = (S-1-a_l, S-1-a_m) of the sub-tables, read from LDS (the four
             // slots read the same addresses).  Each lane carries SPL samples.
             const int t = am;
+            // which term lane t accumulates (see the gradient branch below)
+            const int t_c = t % 6;
+            const bool t_end = t >= 6 && t < 12;
+            const bool t_xr = t_c < 3, t_xl = t_c == 3 || t_c == 4;
+            const bool t_yr = t_c == 0, t_yl = t_c == 1 || t_c == 3;
+            auto degrid = [&](uint32_t vb, int nv, VisEnt (&ent)[SPL]) {
             for (int v0 = 0; v0 < nv; v0 += STEP) {
                 // re-read the sub-tables from LDS every iteration instead of
                 // letting the compiler keep all S*NV values in registers
@@ -467,18 +486,30 @@ __global__ void __launch_bounds__(kBlock, 2) k_item(ItemArgs a)
                 for (int j = 0; j < SPL; ++j)
 #pragma unroll
                     for (int k = 0; k < NV; ++k) s[j][k] = make_float2(0.f, 0.f);
+                // every window row of the iteration is requested up front
+                float2 gwin[SPL][S];
+#pragma unroll
+                for (int j = 0; j < SPL; ++j)
+#pragma unroll
+                    for (int al = 0; al < S; ++al)
+                        gwin[j][al] = __builtin_bit_cast(
+                            float2, __builtin_amdgcn_raw_buffer_load_b64(grsrc, voff[j], al * rowbytes, 0));
+                // kernel rows from LDS, one row ahead of the multiply-adds
+                float2 kv[NV], kvn[NV];
+#pragma unroll
+                for (int k = 0; k < NV; ++k) kv[k] = kcol[(k * S + (S - 1)) * SP];
 #pragma unroll
                 for (int al = 0; al < S; ++al) {
-                    float2 kv[NV];
+                    if (al + 1 < S) {
 #pragma unroll
-                    for (int k = 0; k < NV; ++k) kv[k] = kcol[(k * S + (S - 1 - al)) * SP];
-#pragma unroll
-                    for (int j = 0; j < SPL; ++j) {
-                        const float2 gv = __builtin_bit_cast(
-                            float2, __builtin_amdgcn_raw_buffer_load_b64(grsrc, voff[j], al * rowbytes, 0));
-#pragma unroll
-                        for (int k = 0; k < NV; ++k) cmac(s[j][k], kv[k], gv);
+                        for (int k = 0; k < NV; ++k) kvn[k] = kcol[(k * S + (S - 2 - al)) * SP];
                     }
+#pragma unroll
+                    for (int j = 0; j < SPL; ++j)
+#pragma unroll
+                        for (int k = 0; k < NV; ++k) cmac(s[j][k], kv[k], gwin[j][al]);
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) kv[k] = kvn[k];
                 }
 #pragma unroll
                 for (int j = 0; j < SPL; ++j)
@@ -496,25 +527,22 @@ __global__ void __launch_bounds__(kBlock, 2) k_item(ItemArgs a)
                         if (t == 0) a.vis_out[o] = s[j][0];
                     } else if (MODE == kGrad) {
                         if (a.vis_out != nullptr && t == 0) a.vis_out[o] = s[j][0];
+                        // lane t < 12 adds term t = (end, c) of the sums:
+                        // c = chi, g_l, g_m, H_ll, H_lm, H_mm = Re(conj(x) y)
+                        // with (x, y) = (R,R) (R,dl) (R,dm) (dl,dl) (dl,dm) (dm,dm);
+                        // the residual is formed exactly, the product in float32
+                        // and the running sum in float64
                         const float2 vo = vin[j];
-                        const double w = (double)wgt[j];
-                        const double rr = (double)vo.x - (double)s[j][0].x;
-                        const double ri = (double)vo.y - (double)s[j][0].y;
-                        const int end = (t >= 6) ? 1 : 0;
-                        const int c = t - 6 * end;
-                        const float2 dlf = end ? s[j][3] : s[j][1];
-                        const float2 dmf = end ? s[j][4] : s[j][2];
-                        const double dlr = dlf.x, dli = dlf.y, dmr = dmf.x, dmi = dmf.y;
-                        double val;
-                        switch (c) {
-                        case 0: val = rr * rr + ri * ri; break;
-                        case 1: val = rr * dlr + ri * dli; break;
-                        case 2: val = rr * dmr + ri * dmi; break;
-                        case 3: val = dlr * dlr + dli * dli; break;
-                        case 4: val = dlr * dmr + dli * dmi; break;
-                        default: val = dmr * dmr + dmi * dmi; break;
-                        }
-                        if (t < 12) acc64 += w * val;
+                        const float rr = (float)((double)vo.x - (double)s[j][0].x);
+                        const float ri = (float)((double)vo.y - (double)s[j][0].y);
+                        const float2 dl = t_end ? s[j][3] : s[j][1];
+                        const float2 dm = t_end ? s[j][4] : s[j][2];
+                        const float xr = t_xr ? rr : (t_xl ? dl.x : dm.x);
+                        const float xi = t_xr ? ri : (t_xl ? dl.y : dm.y);
+                        const float yr = t_yr ? rr : (t_yl ? dl.x : dm.x);
+                        const float yi = t_yr ? ri : (t_yl ? dl.y : dm.y);
+                        const float val = fmaf(xr, yr, xi * yi);
+                        if (t < 12) acc64 = fma((double)wgt[j], (double)val, acc64);
                     } else {
                         const float2 gv = vin[j];
                         const int tt = t < 4 ? t : 0;
@@ -527,6 +555,42 @@ __global__ void __launch_bounds__(kBlock, 2) k_item(ItemArgs a)
                 }
 #pragma unroll
                 for (int j = 0; j < SPL; ++j) ent[j] = nxt[j];
+            }
+            };  // degrid
+
+            degrid(vb, nv, ent);
+            if (g.n_vis2 > 0) {
+                // partner offset f' = -f: its sub-tables are the conjugates of
+                // these, reflected (b -> S-1-b on an axis with f != 0, b -> -b mod S
+                // on an axis with f = 0); rewrite them in place and degrid f'
+                const uint32_t vb2 = vb + (uint32_t)nv;
+                const int nv2 = g.n_vis2;
+#pragma unroll
+                for (int j = 0; j < SPL; ++j) {
+                    const int v = slot + SPW * j;
+                    ent[j] = a.vis[vb2 + (v < nv2 ? v : nv2 - 1)];
+                }
+                constexpr int PER = (NV * S * S) / 64;
+                float2 tmp[PER];
+#pragma unroll
+                for (int q = 0; q < PER; ++q) {
+                    const int e = lane + 64 * q;
+                    const int k = e / (S * S), b = e - k * S * S;
+                    const int bl = b / S, bm = b - bl * S;
+                    const int sl = fl ? (S - 1 - bl) : ((S - bl) & (S - 1));
+                    const int sm = fm ? (S - 1 - bm) : ((S - bm) & (S - 1));
+                    tmp[q] = uw[(k * S + sl) * SP + sm];
+                }
+                wave_sync();
+#pragma unroll
+                for (int q = 0; q < PER; ++q) {
+                    const int e = lane + 64 * q;
+                    const int k = e / (S * S), b = e - k * S * S;
+                    const int bl = b / S, bm = b - bl * S;
+                    uw[(k * S + bl) * SP + bm] = make_float2(tmp[q].x, -tmp[q].y);
+                }
+                wave_sync();
+                degrid(vb2, nv2, ent);
             }
             wave_sync();  // the sub-table buffer is rewritten by the next group
             if (NC > 0) {
