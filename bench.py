@@ -25,6 +25,22 @@ FP32_VECTOR_PEAK = 157.3e12  # MI355X published FP32 vector rate (FLOP/s)
 HBM_PEAK = 8.0e12
 
 
+def measured_traffic():
+    """HBM bytes per launch of the gradient kernel from the committed rocprofv3
+    summary, or None when the kernel source has changed since it was taken."""
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_1709_08681_amd", "csrc", "psc_kernels.hip")
+    prof = os.path.join(ROOT, "profiles", "k_item_grad_single_interval.md")
+    try:
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        txt = open(prof).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes=(\d+) kernel_source_sha256_16=([0-9a-f]+)", txt)
+    return int(m.group(1)) if m and m.group(2) == h else None
+
+
 def describe(obs):
     wl = obs.wl
     return {
@@ -132,7 +148,8 @@ def main():
         "peak": FP32_VECTOR_PEAK / 1e12,
         "unit": "TFLOP/s",
         "frac": achieved / FP32_VECTOR_PEAK,
-        "traffic": None,
+        "traffic": measured_traffic() if args.config == 2 else None,
+        "traffic_unit": "bytes per launch (FETCH_SIZE x2 + WRITE_SIZE, copy-calibrated)",
         "kernel": "k_item<16,grad> (+ k_reduce)",
         "launch_ms": grad_ms,
     }
