@@ -57,6 +57,49 @@ def describe(obs):
     }
 
 
+def batched_vs_plain(cfg, iters, device=0):
+    """Algorithm 1 over every solution interval of workload `cfg` for a fixed
+    number of iterations (tol = 0), in the three execution forms: PLAIN (host
+    loop over intervals, launches per interval, host check per iteration),
+    BATCHED (every interval in one launch set per iteration) and GRAPH
+    (BATCHED, all iterations captured in one HIP graph and replayed)."""
+    import torch
+    from paper_1709_08681_amd import synth
+    from paper_1709_08681_amd import psc as P
+    obs = synth.make_config(cfg)
+    s = P.Session(obs, device=device)
+    try:
+        v_obs = s.predict(s.offsets(obs.offsets_true))
+        w = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+        start = s.offsets(synth.perturbed_offsets(obs, 30.0, 98))
+        res = {}
+        for name, form in (("plain", P.SOLVE_PLAIN), ("batched", P.SOLVE_BATCHED),
+                           ("graph", P.SOLVE_GRAPH)):
+            off = start.clone()
+            s.solve(v_obs, w, off, gain=0.5, n_max=1, tol_rad=0.0, form=form)  # warm-up
+            off = start.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.solve(v_obs, w, off, gain=0.5, n_max=iters, tol_rad=0.0, form=form)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            res[name] = {"vis_per_s": obs.n_vis * iters / dt, "ms_per_iteration": dt * 1e3 / iters}
+            res[name + "_offsets"] = off
+        same = bool(torch.equal(res["plain_offsets"], res["graph_offsets"]) and
+                    torch.equal(res["batched_offsets"], res["graph_offsets"]))
+        out = {k: v for k, v in res.items() if not k.endswith("_offsets")}
+        out.update({
+            "workload": describe(obs)["workload"],
+            "n_vis": int(obs.n_vis),
+            "iterations": iters,
+            "graph_over_plain": out["graph"]["vis_per_s"] / out["plain"]["vis_per_s"],
+            "bit_identical_offsets": same,
+        })
+        return out
+    finally:
+        s.close()
+
+
 def cpu_baseline(obs, start, seconds):
     import oracle
     prob = oracle.Problem.from_observation(obs)
@@ -89,6 +132,9 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched-config", type=int, default=3)
+    ap.add_argument("--batched-iters", type=int, default=3)
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only; the hot path is sharded by solution "
@@ -169,12 +215,14 @@ def main():
         "config": describe(obs),
         "roofline": roof,
     }
+    s.close()
+    if not args.no_batched:
+        print(f"bench: batched vs plain on workload {args.batched_config}", file=sys.stderr,
+              flush=True)
+        out["batched_vs_plain"] = batched_vs_plain(args.batched_config, args.batched_iters)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
-        s.close()
         out["cpu_baseline"] = cpu_baseline(obs, start, args.cpu_seconds)
-    else:
-        s.close()
     print(json.dumps(out), flush=True)
 
 

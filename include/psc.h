@@ -66,6 +66,8 @@ typedef struct psc_obs psc_obs;
  *  illum         0: far-field voltage pattern 2 J1(x)/x, x = pi D |l| / lambda;
  *                1: the Gaussian main-lobe model of Sec. 3,
  *                   exp(-|l|^2 / (2 s^2)), s = gauss_sigma_ld * lambda / D.
+ *                   Its aperture is not compactly supported: the kernel fits
+ *                   the S-cell window only for gauss_sigma_ld >~ 1.5.
  *  squint_frac   beam squint: polarisation 0 (1) is centred at
  *                +(-) squint_frac * HPBW(nu) along +l, HPBW = 1.02899 lambda/D
  *                (Sec. 4.2: the two parallel hands are solved separately).

@@ -286,3 +286,97 @@ def test_cfg2_full_size_parity(torch_dev):
         assert max(e_a) <= 1e-4
     finally:
         s.close()
+
+
+# ---------------------------------------------------------------------------
+# subsets of the batched and differentiation workloads
+# ---------------------------------------------------------------------------
+
+def test_cfg3_subset_ragged_intervals(torch_dev):
+    """Batched workload (2048^2 grid, uneven intervals): 6 antennas, the first
+    five intervals, all 16 channels; gradient sums and Algorithm 1."""
+    torch = torch_dev
+    from paper_1709_08681_amd import psc
+    print("case: cfg3 subset", flush=True)
+    full = synth.make_config(3)
+    nt = sum(full.wl.interval_lengths[:5])
+    obs = full.subset(ants=range(6), times=range(nt))
+    prob = oracle.Problem.from_observation(obs)
+    s = session(obs)
+    try:
+        start = synth.perturbed_offsets(obs, 30.0, 15)
+        v = oracle.predict(prob, obs.offsets_true)
+        ref = oracle.gradient(prob, start, v, 1.0)
+        w1 = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+        acc = s.gradient(s.offsets(start), c64(torch, s, v), w1).cpu().numpy()
+        live = obs.int_row_ptr[1:] > obs.int_row_ptr[:-1]
+        for k in range(6):
+            assert rel(acc[live][..., k], ref[live][..., k]) <= 1e-4, k
+        ref_off, its_ref = oracle.solve(prob, v, 1.0, start, gain=0.5, n_max=6, tol_rad=1e-3 * ARCSEC)
+        outs = []
+        for form in (psc.SOLVE_PLAIN, psc.SOLVE_BATCHED, psc.SOLVE_GRAPH):
+            off = s.offsets(start)
+            its = s.solve(c64(torch, s, v), w1, off, gain=0.5, n_max=6, tol_rad=1e-3 * ARCSEC,
+                          form=form)
+            assert np.array_equal(its.cpu().numpy(), its_ref)
+            outs.append(off.cpu().numpy())
+            assert np.abs(outs[-1] - ref_off).max() / ARCSEC <= 0.1
+        assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    finally:
+        s.close()
+
+
+def test_cfg4_subset_with_diffuse_emission(torch_dev):
+    """Differentiation workload (1000 sources plus a 5 arcmin Gaussian of
+    ~3.7e5 pixels): 4 antennas, every 8th timestep, every 8th channel."""
+    torch = torch_dev
+    print("case: cfg4 subset", flush=True)
+    full = synth.make_config(4)
+    obs = full.subset(ants=[0, 1, 2, 3], times=range(0, 240, 8), chans=range(0, 64, 8))
+    prob = oracle.Problem.from_observation(obs)
+    s = session(obs)
+    try:
+        start = synth.perturbed_offsets(obs, 30.0, 16)
+        v_true = oracle.predict(prob, obs.offsets_true)
+        ref_acc, ref_vm = oracle.gradient(prob, start, v_true, 1.0, want_model=True)
+        w1 = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+        acc, vm = s.gradient(s.offsets(start), c64(torch, s, v_true), w1, want_model=True)
+        assert rel(vm.cpu().numpy(), ref_vm) <= 1e-5
+        acc = acc.cpu().numpy()
+        for k in range(6):
+            assert rel(acc[..., k], ref_acc[..., k]) <= 1e-4, k
+    finally:
+        s.close()
+
+
+def test_gaussian_mode_parity(torch_dev):
+    """The Gaussian main-lobe model of Sec. 3 on both sides (illum = 1).  A
+    Gaussian aperture has no compact support; its kernel fits the S-cell window
+    (to e^-23 at the edge) for sigma >= 1.5 lambda/D."""
+    torch = torch_dev
+    obs = synth.make_config(1)
+    prob = oracle.Problem.from_observation(obs, illum=1, gauss_sigma_ld=1.5)
+    s = session(obs, illum=1, gauss_sigma_ld=1.5)
+    try:
+        start = synth.perturbed_offsets(obs, 20.0, 17)
+        v_true = oracle.predict(prob, obs.offsets_true)
+        ref_acc, ref_vm = oracle.gradient(prob, start, v_true, 1.0, want_model=True)
+        w1 = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+        acc, vm = s.gradient(s.offsets(start), c64(torch, s, v_true), w1, want_model=True)
+        assert rel(vm.cpu().numpy(), ref_vm) <= 1e-5
+        assert rel(acc.cpu().numpy(), ref_acc) <= 1e-4
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("m", [20, 32])
+def test_image_sample_counts(torch_dev, m):
+    """Kernel construction with fewer / more image-plane samples per axis."""
+    obs = synth.make_config(1)
+    prob = oracle.Problem.from_observation(obs)
+    s = session(obs, image_samples=m)
+    try:
+        off = synth.perturbed_offsets(obs, 20.0, 18)
+        assert rel(s.predict(off).cpu().numpy(), oracle.predict(prob, off)) <= 1e-5
+    finally:
+        s.close()
