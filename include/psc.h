@@ -212,6 +212,30 @@ PSC_API psc_status psc_solve_step(psc_ctx* ctx, int32_t n_int, int32_t n_pol, in
                                   const double* acc_dev, double gain, double* offsets_io_dev,
                                   int32_t* not_updated_dev, double* max_step_dev, void* stream);
 
+/*
+ * Degrid variants for the gradient and its adjoint (results agree to float32
+ * rounding; each is deterministic on its own):
+ *  PSC_DEGRID_VALU  vector FP32 multiply-adds, sub-tables read from LDS;
+ *  PSC_DEGRID_MFMA  FP32 matrix cores (16x16x4), 16 samples of one sub-table
+ *                   per tile.
+ * A new observation starts with PSC_DEGRID_VALU (the faster on every workload
+ * measured so far).  Prediction always uses VALU.
+ */
+#define PSC_DEGRID_VALU 0
+#define PSC_DEGRID_MFMA 1
+PSC_API psc_status psc_set_degrid(psc_obs* obs, int32_t variant);
+PSC_API psc_status psc_get_degrid(const psc_obs* obs, int32_t* variant);
+
+/*
+ * Autotuner (sync): times psc_gradient on the caller's data with every degrid
+ * variant (`repeats` launches each, after one warm-up) and keeps the fastest
+ * for this observation.  times_us_out (host, nullable) receives the mean
+ * launch time of each variant, indexed by PSC_DEGRID_*.
+ */
+PSC_API psc_status psc_tune(psc_ctx* ctx, psc_obs* obs, const double* offsets_dev,
+                            const void* vis_obs_dev, const float* weight_dev, int32_t repeats,
+                            double* times_us_out, void* stream);
+
 /* Execution forms of psc_solve. */
 #define PSC_SOLVE_PLAIN 0    /* host loop over intervals, one launch set per interval */
 #define PSC_SOLVE_BATCHED 1  /* every interval in one launch set per iteration */

@@ -45,6 +45,7 @@ struct psc_obs {
     double* max_step = nullptr;  // [n_int]
     int32_t* done = nullptr;     // [n_int]
     int32_t* iters = nullptr;    // [n_int]
+    int32_t degrid = PSC_DEGRID_VALU;  // variant for gradient / adjoint
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph = nullptr;
     // arguments the captured graph was built with
@@ -558,6 +559,7 @@ ItemArgs item_args(psc_ctx* ctx, psc_obs* obs, const double* offsets, int item_b
     a.inv_dx = (float)obs->inv_dx;
     a.partials = obs->partials;
     a.done = done;
+    a.use_mfma = obs->degrid == PSC_DEGRID_MFMA ? 1 : 0;
     return a;
 }
 
@@ -690,6 +692,66 @@ PSC_API psc_status psc_solve_step(psc_ctx* ctx, int32_t n_int, int32_t n_pol, in
     sa.max_step = max_step_dev;
     PSC_HIP(ctx, launch_solve(sa, (hipStream_t)stream));
     return PSC_OK;
+}
+
+PSC_API psc_status psc_set_degrid(psc_obs* obs, int32_t variant)
+{
+    if (!obs) return fail(nullptr, PSC_E_ARG, "null observation");
+    if (variant != PSC_DEGRID_VALU && variant != PSC_DEGRID_MFMA)
+        return fail(obs->ctx, PSC_E_ARG, "unknown degrid variant");
+    if (obs->graph) {  // a captured solve graph holds the old kernels
+        (void)hipGraphExecDestroy(obs->graph);
+        obs->graph = nullptr;
+    }
+    obs->degrid = variant;
+    return PSC_OK;
+}
+
+PSC_API psc_status psc_get_degrid(const psc_obs* obs, int32_t* variant)
+{
+    if (!obs || !variant) return fail(nullptr, PSC_E_ARG, "null argument");
+    *variant = obs->degrid;
+    return PSC_OK;
+}
+
+PSC_API psc_status psc_tune(psc_ctx* ctx, psc_obs* obs, const double* offsets_dev, const void* vis_obs_dev,
+                            const float* weight_dev, int32_t repeats, double* times_us_out, void* stream)
+{
+    psc_status st = check_call(ctx, obs, offsets_dev);
+    if (st != PSC_OK) return st;
+    if ((!vis_obs_dev || !weight_dev) && obs->n_vis > 0) return fail(ctx, PSC_E_ARG, "null data");
+    if (repeats < 1 || repeats > 1000) return fail(ctx, PSC_E_ARG, "repeats must be in [1, 1000]");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    PSC_HIP(ctx, hipEventCreate(&e0));
+    hipError_t e = hipEventCreate(&e1);
+    double best = 1e300;
+    int32_t best_v = obs->degrid;
+    const int32_t keep = obs->degrid;
+    for (int32_t v = PSC_DEGRID_VALU; v <= PSC_DEGRID_MFMA && e == hipSuccess; ++v) {
+        obs->degrid = v;
+        ItemArgs a = item_args(ctx, obs, offsets_dev, 0, (int)obs->n_items, nullptr);
+        a.vis_in = (const float2*)vis_obs_dev;
+        a.weight = weight_dev;
+        e = launch_items(kGrad, ctx->s, a, s);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int r = 0; r < repeats && e == hipSuccess; ++r) e = launch_items(kGrad, ctx->s, a, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        const double us = 1e3 * ms / repeats;
+        if (times_us_out) times_us_out[v] = us;
+        if (e == hipSuccess && us < best) {
+            best = us;
+            best_v = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    obs->degrid = keep;
+    if (e != hipSuccess) return hip_fail(ctx, e, "psc_tune");
+    return psc_set_degrid(obs, best_v);
 }
 
 PSC_API psc_status psc_solve(psc_ctx* ctx, psc_obs* obs, const void* vis_obs_dev, const float* weight_dev,

@@ -70,6 +70,7 @@ struct ItemArgs {
     const float* weight;        // grad
     double* partials;           // [item][pol][ncontrib]
     const int32_t* done;        // nullable: per-interval skip flags
+    int32_t use_mfma;           // degrid on the matrix cores (gradient and adjoint)
 };
 
 struct ReduceArgs {

@@ -68,6 +68,8 @@ __device__ __forceinline__ void cmac(float2& acc, float2 a, float2 b)
     acc.y = fmaf(a.y, b.x, acc.y);
 }
 
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
 // Orders LDS traffic between the lanes of one wavefront.
 __device__ __forceinline__ void wave_sync()
 {
@@ -276,7 +278,7 @@ __device__ __forceinline__ void efp(const ItemArgs& a, float kk, float inv_s2, f
 // ---------------------------------------------------------------------------
 // LDS holds two blocks per CU, i.e. two wavefronts per SIMD; telling the
 // compiler so lets it keep every window load of an iteration in flight.
-template <int S, int MODE, int SPL>
+template <int S, int MODE, int SPL, bool MX>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) k_item(ItemArgs a)
 {
     constexpr int NV = (MODE == kPredict) ? 1 : (MODE == kGrad) ? 5 : 4;
@@ -288,6 +290,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
     __shared__ float2 twsh[S * 16];  // exp(+2 pi i t / (S O)), O <= 16
     __shared__ float2 phsh[kWaves][64];  // per-wave phase vectors of the current group
     __shared__ int next_group;
+    __shared__ float2 zrow[4];  // zero kernel coefficients for unused MFMA columns
 
     const int m = a.m, half_m = m >> 1, m2 = m * m;
     const int m2p = (m2 + 3) & ~3;
@@ -321,6 +324,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
         (void*)a.grid, (short)0, P * P * (int)sizeof(float2), 0x00020000);
 
     for (int t = tid; t < so; t += kBlock) twsh[t] = a.tw[t];
+    if (tid < 4) zrow[tid] = make_float2(0.f, 0.f);
 
     for (int pol = 0; pol < a.n_pol; ++pol) {
         if (tid == 0) next_group = it.grp_begin + kWaves;
@@ -437,14 +441,56 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
                 for (int i = 0; i < S; ++i) uw[(k * S + row) * SP + i] = x[i];
             }
             wave_sync();
-            for (int t = lane; t < NV * S; t += 64) {
-                const int k = t / S, col = t - k * S;
-                float2 x[S];
+            if constexpr (!MX) {
+                for (int t = lane; t < NV * S; t += 64) {
+                    const int k = t / S, col = t - k * S;
+                    float2 x[S];
 #pragma unroll
-                for (int i = 0; i < S; ++i) x[i] = uw[(k * S + i) * SP + col];
-                fft_reg<S>(x);
+                    for (int i = 0; i < S; ++i) x[i] = uw[(k * S + i) * SP + col];
+                    fft_reg<S>(x);
 #pragma unroll
-                for (int i = 0; i < S; ++i) uw[(k * S + i) * SP + col] = x[i];
+                    for (int i = 0; i < S; ++i) uw[(k * S + i) * SP + col] = x[i];
+                }
+            } else {
+                // column DFTs written in the order the MFMA B operand reads them:
+                // entry (b_l, b_m) of variant k goes to tap row a_l = S-1-b_l,
+                // column group g = (S-1-b_m)/4, position m = (S-1-b_m)%4 of
+                //   [a_l][g][k][m]
+                // so a lane's four coefficients of a tap row are 32 contiguous
+                // bytes and the lanes of a row read one contiguous block.  Every
+                // column is read before any is rewritten (NV*S > 64 tasks).
+                static_assert(NV * S <= 128, "two column tasks per lane at most");
+                const int t0 = lane, t1 = lane + 64;
+                const bool has1 = t1 < NV * S;
+                float2 x0[S], x1[S];
+                {
+                    const int k = t0 / S, col = t0 - k * S;
+#pragma unroll
+                    for (int i = 0; i < S; ++i) x0[i] = uw[(k * S + i) * SP + col];
+                }
+                if (has1) {
+                    const int k = t1 / S, col = t1 - k * S;
+#pragma unroll
+                    for (int i = 0; i < S; ++i) x1[i] = uw[(k * S + i) * SP + col];
+                }
+                // one wavefront's LDS operations run in issue order, so every
+                // column above is read before the first write below lands
+                fft_reg<S>(x0);
+                {
+                    const int k = t0 / S, col = t0 - k * S;
+                    const int gq = (S - 1 - col) >> 2, mq = (S - 1 - col) & 3;
+#pragma unroll
+                    for (int i = 0; i < S; ++i)
+                        uw[(((S - 1 - i) * (S / 4) + gq) * NV + k) * 4 + mq] = x0[i];
+                }
+                if (has1) fft_reg<S>(x1);
+                if (has1) {
+                    const int k = t1 / S, col = t1 - k * S;
+                    const int gq = (S - 1 - col) >> 2, mq = (S - 1 - col) & 3;
+#pragma unroll
+                    for (int i = 0; i < S; ++i)
+                        uw[(((S - 1 - i) * (S / 4) + gq) * NV + k) * 4 + mq] = x1[i];
+                }
             }
             wave_sync();
 
@@ -458,6 +504,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
             const bool t_end = t >= 6 && t < 12;
             const bool t_xr = t_c < 3, t_xl = t_c == 3 || t_c == 4;
             const bool t_yr = t_c == 0, t_yl = t_c == 1 || t_c == 3;
+            // D columns (MFMA path): V = 0,1; d/dl_i = 2,3; d/dm_i = 4,5; d/dl_j = 6,7; d/dm_j = 8,9
+            const int t_dl = t_end ? 6 : 2, t_dm = t_end ? 8 : 4;
+            const int t_xcol = t_xr ? 0 : (t_xl ? t_dl : t_dm);
+            const int t_ycol = t_yr ? 0 : (t_yl ? t_dl : t_dm);
             auto degrid = [&](uint32_t vb, int nv, VisEnt (&ent)[SPL]) {
             for (int v0 = 0; v0 < nv; v0 += STEP) {
                 // re-read the sub-tables from LDS every iteration instead of
@@ -558,39 +608,222 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
             }
             };  // degrid
 
-            degrid(vb, nv, ent);
-            if (g.n_vis2 > 0) {
-                // partner offset f' = -f: its sub-tables are the conjugates of
-                // these, reflected (b -> S-1-b on an axis with f != 0, b -> -b mod S
-                // on an axis with f = 0); rewrite them in place and degrid f'
-                const uint32_t vb2 = vb + (uint32_t)nv;
-                const int nv2 = g.n_vis2;
+            if constexpr (MX) {
+                // ---- degrid on the matrix cores.  A tile is 16 samples of the
+                // group (offset f, then offset -f); per tile the wavefront runs
+                // 128 MFMA 16x16x4 f32 over k = (tap, re/im) with
+                //   A[sample][k] = window value, B[k][n] = kernel coefficient,
+                //   n = 2v + c: real (c = 0) / imaginary (c = 1) part of variant v.
+                // Lane (g4, i16) feeds sample i16 at the 4 tap columns 4 g4 .. 4 g4 + 3
+                // of each tap row, and gets D columns n = i16 for samples 4 g4 + r.
+                // A sample at -f reads its window reflected (b -> S-1-b on an axis
+                // with f != 0, b -> -b mod S with f = 0) and conjugated, which is
+                // the same as using -f's conjugate-reflected sub-tables; its
+                // result is conjugated back.
+                const int i16 = lane & 15, g4 = lane >> 4;
+                const int ntot = nv + g.n_vis2;
+                const bool bzero = i16 >= 2 * NV;
+                const bool bd = (i16 & 1) != 0;
+                // [a_l][g][k][m] layout (see the column DFTs): tap row a_l starts at
+                // a_l * (S/4) * NV * 4; this lane's 4 coefficients are contiguous
+                const float2* bbase = bzero ? zrow : uw + (size_t)(g4 * NV + (i16 >> 1)) * 4;
+                const int bstride = bzero ? 0 : (S / 4) * NV * 4;
+                // Tiles are software-pipelined: while tile t runs its MFMAs, the
+                // sample entries of tile t+1 arrive and, during t's last chunk,
+                // t+1's first window rows are requested.
+                struct TileAddr {
+                    bool partner, wrapc;
+                    int cbase, wbase;
+                    float csg;
+                };
+                constexpr int HR = 4;  // tap rows per chunk
+                typedef float f4v __attribute__((ext_vector_type(4)));
+                auto tile_addr = [&](int t0, const VisEnt& e) {
+                    const int q = t0 + i16;
+                    TileAddr ta;
+                    ta.partner = q < ntot && q >= nv;
+                    const int row0 = (int)(e.klo >> 16);
+                    const int col0 = (int)(e.klo & 0xffffu);
+                    // this lane's 4 tap columns 4 g4 .. 4 g4 + 3 as one 32-byte chunk of
+                    // the window row (reversed for a sample at -f; with f_m = 0 the last
+                    // column of the last group wraps to window column S-1)
+                    const int lo = ta.partner ? (fm ? (S - 4 - 4 * g4) : (S - 5 - 4 * g4)) : 4 * g4;
+                    ta.wrapc = ta.partner && fm == 0 && g4 == 3;
+                    ta.cbase = (row0 * P + col0 + lo) * (int)sizeof(float2);
+                    ta.wbase = (row0 * P + col0 + (S - 1)) * (int)sizeof(float2);
+                    ta.csg = ta.partner ? -1.f : 1.f;
+                    return ta;
+                };
+                auto load_chunk = [&](const TileAddr& ta, int a0, float2 (&wv)[HR][4]) {
 #pragma unroll
-                for (int j = 0; j < SPL; ++j) {
-                    const int v = slot + SPW * j;
-                    ent[j] = a.vis[vb2 + (v < nv2 ? v : nv2 - 1)];
-                }
-                constexpr int PER = (NV * S * S) / 64;
-                float2 tmp[PER];
+                    for (int ah = 0; ah < HR; ++ah) {
+                        const int al = a0 + ah;
+                        const int wr = ta.partner ? (fl ? (S - 1 - al) : ((S - 2 - al) & (S - 1))) : al;
+                        const int roff = wr * rowbytes;
+                        const f4v c01 = __builtin_bit_cast(
+                            f4v, __builtin_amdgcn_raw_buffer_load_b128(grsrc, ta.cbase + roff, 0, 0));
+                        const f4v c23 = __builtin_bit_cast(
+                            f4v, __builtin_amdgcn_raw_buffer_load_b128(grsrc, ta.cbase + roff + 16, 0, 0));
+                        float2 ch[4] = {make_float2(c01[0], c01[1]), make_float2(c01[2], c01[3]),
+                                        make_float2(c23[0], c23[1]), make_float2(c23[2], c23[3])};
+                        if (ta.wrapc)
+                            ch[0] = __builtin_bit_cast(
+                                float2, __builtin_amdgcn_raw_buffer_load_b64(grsrc, ta.wbase + roff, 0, 0));
 #pragma unroll
-                for (int q = 0; q < PER; ++q) {
-                    const int e = lane + 64 * q;
-                    const int k = e / (S * S), b = e - k * S * S;
-                    const int bl = b / S, bm = b - bl * S;
-                    const int sl = fl ? (S - 1 - bl) : ((S - bl) & (S - 1));
-                    const int sm = fm ? (S - 1 - bm) : ((S - bm) & (S - 1));
-                    tmp[q] = uw[(k * S + sl) * SP + sm];
-                }
-                wave_sync();
+                        for (int mm = 0; mm < 4; ++mm) wv[ah][mm] = ta.partner ? ch[3 - mm] : ch[mm];
+                    }
+                };
+                auto tile_entries = [&](int t0, VisEnt& e, VisEnt (&es)[4]) {
+                    const int q = t0 + i16;
+                    e = a.vis[vb + (q < ntot ? q : 0)];
 #pragma unroll
-                for (int q = 0; q < PER; ++q) {
-                    const int e = lane + 64 * q;
-                    const int k = e / (S * S), b = e - k * S * S;
-                    const int bl = b / S, bm = b - bl * S;
-                    uw[(k * S + bl) * SP + bm] = make_float2(tmp[q].x, -tmp[q].y);
+                    for (int r = 0; r < 4; ++r) {
+                        const int qs = t0 + 4 * g4 + r;
+                        es[r] = a.vis[vb + (qs < ntot ? qs : 0)];
+                    }
+                };
+                auto tile_data = [&](const VisEnt (&es)[4], float2 (&tv)[4], float (&tw)[4]) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const size_t o = (size_t)es[r].vidx * a.n_pol + pol;
+                        tv[r] = a.vis_in[o];
+                        tw[r] = (MODE == kGrad) ? a.weight[o] : 0.f;
+                    }
+                };
+                VisEnt e_cur, es[4];
+                tile_entries(0, e_cur, es);
+                TileAddr ta = tile_addr(0, e_cur);
+                float2 cur[HR][4], nxt[HR][4];
+                load_chunk(ta, 0, cur);
+                float2 tv[4];
+                float tw[4];
+                tile_data(es, tv, tw);
+                for (int t0 = 0; t0 < ntot; t0 += 16) {
+                    const int t1 = t0 + 16;
+                    const bool more = t1 < ntot;
+                    VisEnt e_nx = e_cur, es_nx[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) es_nx[r] = es[r];
+                    if (more) tile_entries(t1, e_nx, es_nx);
+                    TileAddr ta_nx = ta;
+                    mfma_f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+                    for (int a0 = 0; a0 < S; a0 += HR) {
+                        if (a0 + HR < S) {
+                            load_chunk(ta, a0 + HR, nxt);
+                        } else if (more) {
+                            ta_nx = tile_addr(t1, e_nx);
+                            load_chunk(ta_nx, 0, nxt);
+                        }
+#pragma unroll
+                        for (int ah = 0; ah < HR; ++ah) {
+                            const int al = a0 + ah;
+                            const float2* br = bbase + al * bstride;
+                            float2 kk[4];
+#pragma unroll
+                            for (int mm = 0; mm < 4; ++mm) kk[mm] = br[mm];
+#pragma unroll
+                            for (int mm = 0; mm < 4; ++mm) {
+                                const float ar = cur[ah][mm].x, ai = ta.csg * cur[ah][mm].y;
+                                const float b0 = bd ? kk[mm].y : kk[mm].x;
+                                const float b1 = bd ? kk[mm].x : -kk[mm].y;
+                                acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, b0, acc0, 0, 0, 0);
+                                acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, b1, acc1, 0, 0, 0);
+                            }
+                        }
+#pragma unroll
+                        for (int ah = 0; ah < HR; ++ah)
+#pragma unroll
+                            for (int mm = 0; mm < 4; ++mm) cur[ah][mm] = nxt[ah][mm];
+                    }
+                    float2 tv_nx[4];
+                    float tw_nx[4];
+                    if (more) tile_data(es_nx, tv_nx, tw_nx);
+                    const mfma_f4 acc = acc0 + acc1;
+                    // ---- per-sample terms: lane n < NC of row group g4 adds term n
+                    const int src0 = 16 * g4;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int qs = t0 + 4 * g4 + r;
+                        const bool vr = qs < ntot;
+                        const bool pr = vr && qs >= nv;
+                        const float cval = (pr && bd) ? -acc[r] : acc[r];
+                        const size_t o = (size_t)es[r].vidx * a.n_pol + pol;
+                        if (MODE == kGrad) {
+                            const int t = i16;
+                            const float v_re = __shfl(cval, src0 + 0);
+                            const float v_im = __shfl(cval, src0 + 1);
+                            const float xr0 = __shfl(cval, src0 + t_xcol);
+                            const float xi0 = __shfl(cval, src0 + t_xcol + 1);
+                            const float yr0 = __shfl(cval, src0 + t_ycol);
+                            const float yi0 = __shfl(cval, src0 + t_ycol + 1);
+                            if (vr) {
+                                if (a.vis_out != nullptr && t == 0) a.vis_out[o] = make_float2(v_re, v_im);
+                                const float2 vo = tv[r];
+                                const float rr = (float)((double)vo.x - (double)v_re);
+                                const float ri = (float)((double)vo.y - (double)v_im);
+                                const float xr = t_xr ? rr : xr0, xi = t_xr ? ri : xi0;
+                                const float yr = t_yr ? rr : yr0, yi = t_yr ? ri : yi0;
+                                const float val = fmaf(xr, yr, xi * yi);
+                                if (t < 12) acc64 = fma((double)tw[r], (double)val, acc64);
+                            }
+                        } else {
+                            const int t = i16 < 4 ? i16 : 0;
+                            const float dr = __shfl(cval, src0 + 2 * t);
+                            const float di = __shfl(cval, src0 + 2 * t + 1);
+                            if (vr && i16 < 4) {
+                                const float2 gv = tv[r];
+                                acc64 += (double)gv.x * (double)dr + (double)gv.y * (double)di;
+                            }
+                        }
+                    }
+                    // the next tile's state becomes current
+                    if (more) {
+                        e_cur = e_nx;
+                        ta = ta_nx;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            es[r] = es_nx[r];
+                            tv[r] = tv_nx[r];
+                            tw[r] = tw_nx[r];
+                        }
+                    }
                 }
-                wave_sync();
-                degrid(vb2, nv2, ent);
+            } else {
+                degrid(vb, nv, ent);
+                if (g.n_vis2 > 0) {
+                    // partner offset f' = -f: its sub-tables are the conjugates of
+                    // these, reflected (b -> S-1-b on an axis with f != 0, b -> -b mod S
+                    // on an axis with f = 0); rewrite them in place and degrid f'
+                    const uint32_t vb2 = vb + (uint32_t)nv;
+                    const int nv2 = g.n_vis2;
+    #pragma unroll
+                    for (int j = 0; j < SPL; ++j) {
+                        const int v = slot + SPW * j;
+                        ent[j] = a.vis[vb2 + (v < nv2 ? v : nv2 - 1)];
+                    }
+                    constexpr int PER = (NV * S * S) / 64;
+                    float2 tmp[PER];
+    #pragma unroll
+                    for (int q = 0; q < PER; ++q) {
+                        const int e = lane + 64 * q;
+                        const int k = e / (S * S), b = e - k * S * S;
+                        const int bl = b / S, bm = b - bl * S;
+                        const int sl = fl ? (S - 1 - bl) : ((S - bl) & (S - 1));
+                        const int sm = fm ? (S - 1 - bm) : ((S - bm) & (S - 1));
+                        tmp[q] = uw[(k * S + sl) * SP + sm];
+                    }
+                    wave_sync();
+    #pragma unroll
+                    for (int q = 0; q < PER; ++q) {
+                        const int e = lane + 64 * q;
+                        const int k = e / (S * S), b = e - k * S * S;
+                        const int bl = b / S, bm = b - bl * S;
+                        uw[(k * S + bl) * SP + bm] = make_float2(tmp[q].x, -tmp[q].y);
+                    }
+                    wave_sync();
+                    degrid(vb2, nv2, ent);
+                }
             }
             wave_sync();  // the sub-table buffer is rewritten by the next group
             if (NC > 0) {
@@ -751,7 +984,7 @@ hipError_t launch_airy_table(float4* tab, int n_tab, double dx, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int S, int MODE, int SPL>
+template <int S, int MODE, int SPL, bool MX>
 static hipError_t launch_items_t(const ItemArgs& a, hipStream_t s)
 {
     constexpr int NV = (MODE == kPredict) ? 1 : (MODE == kGrad) ? 5 : 4;
@@ -764,12 +997,12 @@ static hipError_t launch_items_t(const ItemArgs& a, hipStream_t s)
         const int mmax = 2 * S;
         const size_t shmax = sizeof(double) * NC * 256 + sizeof(float) * NV * ((mmax * mmax + 3) & ~3) +
                              sizeof(float2) * kWaves * NV * S * (S + 1);
-        return hipFuncSetAttribute((const void*)k_item<S, MODE, SPL>,
+        return hipFuncSetAttribute((const void*)k_item<S, MODE, SPL, MX>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmax);
     }();
     if (attr != hipSuccess) return attr;
     const int blocks = 8 * ((a.n_items + 7) / 8);
-    k_item<S, MODE, SPL><<<blocks, kBlock, sh, s>>>(a);
+    k_item<S, MODE, SPL, MX><<<blocks, kBlock, sh, s>>>(a);
     return hipGetLastError();
 }
 
@@ -777,10 +1010,13 @@ hipError_t launch_items(int mode, int support, const ItemArgs& a, hipStream_t s)
 {
     if (a.n_items <= 0) return hipSuccess;
     if (support != 16) return hipErrorInvalidValue;
+    const bool mx = a.use_mfma != 0;
     switch (mode) {
-    case kPredict: return launch_items_t<16, kPredict, 2>(a, s);
-    case kGrad: return launch_items_t<16, kGrad, 2>(a, s);
-    case kVjp: return launch_items_t<16, kVjp, 2>(a, s);
+    case kPredict: return launch_items_t<16, kPredict, 2, false>(a, s);
+    case kGrad:
+        return mx ? launch_items_t<16, kGrad, 2, true>(a, s) : launch_items_t<16, kGrad, 2, false>(a, s);
+    case kVjp:
+        return mx ? launch_items_t<16, kVjp, 2, true>(a, s) : launch_items_t<16, kVjp, 2, false>(a, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -22,11 +22,13 @@ PSC_OK = 0
 STATUS = {0: "PSC_OK", -1: "PSC_E_ARG", -2: "PSC_E_HIP", -3: "PSC_E_OOM", -4: "PSC_E_UNSUPPORTED",
           -5: "PSC_E_STATE"}
 SOLVE_PLAIN, SOLVE_BATCHED, SOLVE_GRAPH = 0, 1, 2
+DEGRID_VALU, DEGRID_MFMA = 0, 1
 ARCSEC = math.pi / (180.0 * 3600.0)
 
 EXPORTS = ["psc_version", "psc_create", "psc_destroy", "psc_last_error", "psc_set_model",
            "psc_obs_create", "psc_obs_destroy", "psc_obs_info", "psc_predict", "psc_gradient",
-           "psc_predict_vjp", "psc_solve_step", "psc_solve"]
+           "psc_predict_vjp", "psc_solve_step", "psc_solve", "psc_set_degrid", "psc_get_degrid",
+           "psc_tune"]
 
 
 class PscError(RuntimeError):
@@ -81,6 +83,9 @@ def load():
             "psc_predict_vjp": ([vp, vp, vp, vp, vp, vp], C.c_int),
             "psc_solve_step": ([vp, i32, i32, i32, vp, dbl, vp, vp, vp, vp], C.c_int),
             "psc_solve": ([vp, vp, vp, vp, vp, dbl, i32, dbl, i32, vp, vp], C.c_int),
+            "psc_set_degrid": ([vp, i32], C.c_int),
+            "psc_get_degrid": ([vp, C.POINTER(i32)], C.c_int),
+            "psc_tune": ([vp, vp, vp, vp, vp, i32, C.POINTER(dbl), vp], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -172,6 +177,25 @@ def psc_solve(ctx, obs, vis_obs_dev, weight_dev, offsets_dev, gain, n_max, tol_r
     _check(load().psc_solve(ctx, obs, _ptr(vis_obs_dev), _ptr(weight_dev), _ptr(offsets_dev),
                             float(gain), int(n_max), float(tol_rad), int(form), _ptr(iters_dev),
                             _stream(stream)), ctx)
+
+
+def psc_set_degrid(obs, variant):
+    _check(load().psc_set_degrid(obs, int(variant)))
+
+
+def psc_get_degrid(obs):
+    v = C.c_int32()
+    _check(load().psc_get_degrid(obs, C.byref(v)))
+    return v.value
+
+
+def psc_tune(ctx, obs, offsets_dev, vis_obs_dev, weight_dev, repeats=3, stream=None):
+    """Returns the mean launch time (us) of each degrid variant; the observation
+    keeps the fastest."""
+    t = (C.c_double * 2)()
+    _check(load().psc_tune(ctx, obs, _ptr(offsets_dev), _ptr(vis_obs_dev), _ptr(weight_dev),
+                           int(repeats), t, _stream(stream)), ctx)
+    return list(t)
 
 
 # ---------------------------------------------------------------------------

@@ -380,3 +380,63 @@ def test_image_sample_counts(torch_dev, m):
         assert rel(s.predict(off).cpu().numpy(), oracle.predict(prob, off)) <= 1e-5
     finally:
         s.close()
+
+
+# ---------------------------------------------------------------------------
+# both degrid variants (vector FP32 and matrix-core FP32)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_degrid_variants_gradient_and_vjp(torch_dev, variant):
+    """Gradient sums and the adjoint with each degrid variant, on ragged
+    intervals with two polarisations (offset pairs f, -f in every item)."""
+    torch = torch_dev
+    from paper_1709_08681_amd import psc
+    lengths = [6, 2, 9]
+    wl = synth.workload(1, n_ant=8, n_time=sum(lengths), interval_lengths=lengths, n_pol=2,
+                        squint_frac=0.03, freqs_hz=np.array([1.1e9, 1.6e9]), n_src=6)
+    obs = synth.make_observation(wl, 91)
+    prob = oracle.Problem.from_observation(obs)
+    s = session(obs)
+    try:
+        psc.psc_set_degrid(s.handle, variant)
+        assert psc.psc_get_degrid(s.handle) == variant
+        start = synth.perturbed_offsets(obs, 25.0, 19)
+        v = oracle.predict(prob, obs.offsets_true)
+        ref, vm_ref = oracle.gradient(prob, start, v, 1.0, want_model=True)
+        w1 = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+        acc, vm = s.gradient(s.offsets(start), c64(torch, s, v), w1, want_model=True)
+        assert rel(vm.cpu().numpy(), vm_ref) <= 1e-5
+        acc = acc.cpu().numpy()
+        for k in range(6):
+            assert rel(acc[..., k], ref[..., k]) <= 1e-4, k
+        rng = np.random.default_rng(20)
+        G = (rng.normal(size=s.vis_shape) + 1j * rng.normal(size=s.vis_shape)).astype(np.complex64)
+        _, dv = oracle.predict(prob, start, want_grad=True)
+        gref = np.zeros(s.off_shape)
+        for r in range(obs.n_row):
+            it = np.searchsorted(obs.int_row_ptr, r, side="right") - 1
+            i, j = obs.ant1[r], obs.ant2[r]
+            for c in range(obs.n_chan):
+                for p in range(obs.n_pol):
+                    g = np.complex128(G[r, c, p])
+                    for ax in range(2):
+                        gref[it, p, i, ax] += (np.conj(g) * dv[r, c, p, ax]).real
+                        gref[it, p, j, ax] += (np.conj(g) * dv[r, c, p, 2 + ax]).real
+        got = s.vjp(s.offsets(start), torch.as_tensor(G, device=s.dev)).cpu().numpy()
+        assert rel(got, gref) <= 1e-4
+    finally:
+        s.close()
+
+
+def test_autotuner_picks_a_variant(torch_dev, cfg1):
+    torch = torch_dev
+    from paper_1709_08681_amd import psc
+    obs, prob, s = cfg1
+    v = s.predict(obs.offsets_true)
+    w = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+    off = s.offsets(synth.perturbed_offsets(obs, 20.0, 21))
+    t = psc.psc_tune(s.ctx, s.handle, off, v, w, repeats=2)
+    assert len(t) == 2 and min(t) > 0
+    assert psc.psc_get_degrid(s.handle) == int(np.argmin(t))
+    psc.psc_set_degrid(s.handle, psc.DEGRID_VALU)
