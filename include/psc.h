@@ -61,7 +61,9 @@ typedef struct psc_obs psc_obs;
  *  oversample    O, kernel samples per uv cell (1..16, S*O <= 512).  Each
  *                visibility's uv is rounded to the nearest 1/O cell.
  *  image_samples M, image-plane samples per axis used to build kernels, at
- *                spacing FoV/S (0 = default 3S/2; even, S..2S).
+ *                spacing FoV/S (0 = default 3S/2; even, S..2S).  At
+ *                support 32 the window form must fit one compute unit's
+ *                LDS: M <= 62 at O = 8 (PSC_E_UNSUPPORTED beyond).
  *  dish_diam_m   D of the uniformly illuminated circular dishes.
  *  illum         0: far-field voltage pattern 2 J1(x)/x, x = pi D |l| / lambda;
  *                1: the Gaussian main-lobe model of Sec. 3,
@@ -213,16 +215,28 @@ PSC_API psc_status psc_solve_step(psc_ctx* ctx, int32_t n_int, int32_t n_pol, in
                                   int32_t* not_updated_dev, double* max_step_dev, void* stream);
 
 /*
- * Degrid variants for the gradient and its adjoint (results agree to float32
- * rounding; each is deterministic on its own):
- *  PSC_DEGRID_VALU  vector FP32 multiply-adds, sub-tables read from LDS;
- *  PSC_DEGRID_MFMA  FP32 matrix cores (16x16x4), 16 samples of one sub-table
- *                   per tile.
- * A new observation starts with PSC_DEGRID_VALU (the faster on every workload
- * measured so far).  Prediction always uses VALU.
+ * Degrid variants (results agree to float32 rounding; each is deterministic
+ * on its own):
+ *  PSC_DEGRID_VALU    table form: per sub-lattice offset, the five S x S
+ *                     sub-tables (kernel and its four offset derivatives,
+ *                     Eq. MEDD and Eq. DA) are built by FFT in LDS and read by
+ *                     vector FP32 multiply-adds; support 16;
+ *  PSC_DEGRID_MFMA    table form on the FP32 matrix cores (16x16x4), 16
+ *                     samples of one sub-table per tile (gradient and adjoint;
+ *                     prediction uses VALU); support 16;
+ *  PSC_DEGRID_WINDOW  window form: each sample's S x S window of V^{M0} is
+ *                     transformed instead of the kernels, and the sum runs
+ *                     over the image-plane samples; no sub-table is stored.
+ *                     Cheaper when sub-tables serve few samples each; the only
+ *                     form for support 32.
+ * A new observation starts with PSC_DEGRID_VALU at support 16 and
+ * PSC_DEGRID_WINDOW at support 32; psc_set_degrid returns PSC_E_UNSUPPORTED
+ * for a table form at support 32.  The variant applies to psc_predict,
+ * psc_gradient, psc_predict_vjp and psc_solve.
  */
 #define PSC_DEGRID_VALU 0
 #define PSC_DEGRID_MFMA 1
+#define PSC_DEGRID_WINDOW 2
 PSC_API psc_status psc_set_degrid(psc_obs* obs, int32_t variant);
 PSC_API psc_status psc_get_degrid(const psc_obs* obs, int32_t* variant);
 
@@ -230,7 +244,8 @@ PSC_API psc_status psc_get_degrid(const psc_obs* obs, int32_t* variant);
  * Autotuner (sync): times psc_gradient on the caller's data with every degrid
  * variant (`repeats` launches each, after one warm-up) and keeps the fastest
  * for this observation.  times_us_out (host, nullable) receives the mean
- * launch time of each variant, indexed by PSC_DEGRID_*.
+ * launch time of each variant, indexed by PSC_DEGRID_* (-1 for a variant the
+ * support does not allow; 3 entries).
  */
 PSC_API psc_status psc_tune(psc_ctx* ctx, psc_obs* obs, const double* offsets_dev,
                             const void* vis_obs_dev, const float* weight_dev, int32_t repeats,

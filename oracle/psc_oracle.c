@@ -148,6 +148,7 @@ static double* beam_table(const orc_problem* p, const double* offs_int /* [n_pol
     if (!tab) return NULL;
     for (int pol = 0; pol < p->n_pol; ++pol) {
         double sgn = (pol == 0) ? 1.0 : -1.0;
+#pragma omp parallel for schedule(dynamic, 1)
         for (int a = 0; a < p->n_ant; ++a) {
             for (int c = 0; c < p->n_chan; ++c) {
                 double lambda = ORC_C_LIGHT / p->freq_hz[c];
@@ -215,10 +216,11 @@ int oracle_predict(const orc_problem* p, const double* offsets, double* vis_out,
 {
     if (check_problem(p)) return -1;
     for (int s = 0; s < p->n_int; ++s) {
+        int64_t r0 = p->int_row_ptr[s], r1 = p->int_row_ptr[s + 1];
+        if (r0 == r1) continue; /* an empty interval predicts nothing */
         const double* offs_int = offsets + (size_t)s * p->n_pol * p->n_ant * 2;
         double* tab = beam_table(p, offs_int);
         if (!tab) return -2;
-        int64_t r0 = p->int_row_ptr[s], r1 = p->int_row_ptr[s + 1];
 #pragma omp parallel for schedule(dynamic, 16)
         for (int64_t r = r0; r < r1; ++r) {
             for (int c = 0; c < p->n_chan; ++c) {
@@ -258,6 +260,8 @@ int oracle_gradient(const orc_problem* p, const double* offsets, const double* v
     double* part = (double*)calloc((size_t)nthr * per, sizeof(double));
     if (!part) return -2;
     for (int s = 0; s < p->n_int; ++s) {
+        int64_t r0 = p->int_row_ptr[s], r1 = p->int_row_ptr[s + 1];
+        if (r0 == r1) continue; /* no samples: every sum of the interval stays 0 */
         const double* offs_int = offsets + (size_t)s * p->n_pol * p->n_ant * 2;
         double* tab = beam_table(p, offs_int);
         if (!tab) {
@@ -265,7 +269,6 @@ int oracle_gradient(const orc_problem* p, const double* offsets, const double* v
             return -2;
         }
         memset(part, 0, (size_t)nthr * per * sizeof(double));
-        int64_t r0 = p->int_row_ptr[s], r1 = p->int_row_ptr[s + 1];
 #pragma omp parallel
         {
             int tid = 0;

@@ -186,8 +186,10 @@ PSC_API psc_status psc_create(const psc_config* cfg, psc_ctx** out)
     if (c.illum == 1 && !(c.gauss_sigma_ld > 0))
         return fail(nullptr, PSC_E_ARG, "gauss_sigma_ld must be positive in Gaussian mode");
     if (!isfinite(c.squint_frac)) return fail(nullptr, PSC_E_ARG, "squint_frac must be finite");
-    if (c.support != 16)
-        return fail(nullptr, PSC_E_UNSUPPORTED, "this build implements support 16 only");
+    if (c.support == 32 && win_lds_bytes(32, kGrad, 4, m, c.oversample) > kWinLdsBudget)
+        return fail(nullptr, PSC_E_UNSUPPORTED,
+                    "support 32: image_samples and oversample exceed the LDS of one compute unit "
+                    "(image_samples <= 62 at oversample 8)");
     if (hipSetDevice(c.device) != hipSuccess) return fail(nullptr, PSC_E_ARG, "invalid device");
 
     psc_ctx* ctx = new psc_ctx();
@@ -222,8 +224,7 @@ PSC_API psc_status psc_create(const psc_config* cfg, psc_ctx** out)
         }
         twh[t] = make_float2((float)cv, (float)sv);
     }
-    hipError_t e = set_fft_twiddles();
-    if (e == hipSuccess) e = dmalloc(&ctx->grid, (size_t)(ctx->n + ctx->s) * (ctx->n + ctx->s));
+    hipError_t e = dmalloc(&ctx->grid, (size_t)(ctx->n + ctx->s) * (ctx->n + ctx->s));
     if (e == hipSuccess) e = dmalloc(&ctx->taper_pix, ctx->n);
     if (e == hipSuccess) e = dmalloc(&ctx->taper_img, m);
     if (e == hipSuccess) e = dmalloc(&ctx->tw, so);
@@ -470,6 +471,7 @@ PSC_API psc_status psc_obs_create(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
 
     psc_obs* obs = new psc_obs();
     obs->ctx = ctx;
+    obs->degrid = (S == 16) ? PSC_DEGRID_VALU : PSC_DEGRID_WINDOW;
     obs->n_ant = n_ant;
     obs->n_chan = n_chan;
     obs->n_pol = d->n_pol;
@@ -591,6 +593,13 @@ psc_status check_call(psc_ctx* ctx, psc_obs* obs, const double* offsets)
     return PSC_OK;
 }
 
+// Degrid launch in the observation's current form.
+hipError_t launch_degrid(int mode, const psc_ctx* ctx, const psc_obs* obs, const ItemArgs& a, hipStream_t st)
+{
+    if (obs->degrid == PSC_DEGRID_WINDOW) return launch_win(mode, ctx->s, a, st);
+    return launch_items(mode, ctx->s, a, st);
+}
+
 // One iteration of the solver over intervals [s0, s1): gradient sums, reduce, step.
 hipError_t enqueue_iteration(psc_ctx* ctx, psc_obs* obs, const void* vis_obs, const float* w,
                              double* offsets, double gain, double tol, int s0, int s1,
@@ -600,7 +609,7 @@ hipError_t enqueue_iteration(psc_ctx* ctx, psc_obs* obs, const void* vis_obs, co
     ItemArgs a = item_args(ctx, obs, offsets, i0, i1 - i0, done_for_items);
     a.vis_in = (const float2*)vis_obs;
     a.weight = w;
-    hipError_t e = launch_items(kGrad, ctx->s, a, st);
+    hipError_t e = launch_degrid(kGrad, ctx, obs, a, st);
     if (e != hipSuccess) return e;
     e = launch_reduce(12, reduce_args(obs, s0, s1, obs->acc, done_for_items), st);
     if (e != hipSuccess) return e;
@@ -632,7 +641,7 @@ PSC_API psc_status psc_predict(psc_ctx* ctx, psc_obs* obs, const double* offsets
     if (!vis_out_dev && obs->n_vis > 0) return fail(ctx, PSC_E_ARG, "null output");
     ItemArgs a = item_args(ctx, obs, offsets_dev, 0, (int)obs->n_items, nullptr);
     a.vis_out = (float2*)vis_out_dev;
-    PSC_HIP(ctx, launch_items(kPredict, ctx->s, a, (hipStream_t)stream));
+    PSC_HIP(ctx, launch_degrid(kPredict, ctx, obs, a, (hipStream_t)stream));
     return PSC_OK;
 }
 
@@ -649,7 +658,7 @@ PSC_API psc_status psc_gradient(psc_ctx* ctx, psc_obs* obs, const double* offset
     a.vis_in = (const float2*)vis_obs_dev;
     a.weight = weight_dev;
     a.vis_out = (float2*)vis_model_dev;
-    PSC_HIP(ctx, launch_items(kGrad, ctx->s, a, s));
+    PSC_HIP(ctx, launch_degrid(kGrad, ctx, obs, a, s));
     PSC_HIP(ctx, launch_reduce(12, reduce_args(obs, 0, obs->n_int, acc_out_dev, nullptr), s));
     return PSC_OK;
 }
@@ -664,7 +673,7 @@ PSC_API psc_status psc_predict_vjp(psc_ctx* ctx, psc_obs* obs, const double* off
     hipStream_t s = (hipStream_t)stream;
     ItemArgs a = item_args(ctx, obs, offsets_dev, 0, (int)obs->n_items, nullptr);
     a.vis_in = (const float2*)grad_vis_dev;
-    PSC_HIP(ctx, launch_items(kVjp, ctx->s, a, s));
+    PSC_HIP(ctx, launch_degrid(kVjp, ctx, obs, a, s));
     PSC_HIP(ctx, launch_reduce(4, reduce_args(obs, 0, obs->n_int, grad_offsets_out_dev, nullptr), s));
     return PSC_OK;
 }
@@ -697,8 +706,10 @@ PSC_API psc_status psc_solve_step(psc_ctx* ctx, int32_t n_int, int32_t n_pol, in
 PSC_API psc_status psc_set_degrid(psc_obs* obs, int32_t variant)
 {
     if (!obs) return fail(nullptr, PSC_E_ARG, "null observation");
-    if (variant != PSC_DEGRID_VALU && variant != PSC_DEGRID_MFMA)
+    if (variant != PSC_DEGRID_VALU && variant != PSC_DEGRID_MFMA && variant != PSC_DEGRID_WINDOW)
         return fail(obs->ctx, PSC_E_ARG, "unknown degrid variant");
+    if (obs->ctx->s != 16 && variant != PSC_DEGRID_WINDOW)
+        return fail(obs->ctx, PSC_E_UNSUPPORTED, "support 32 degrids in the window form only");
     if (obs->graph) {  // a captured solve graph holds the old kernels
         (void)hipGraphExecDestroy(obs->graph);
         obs->graph = nullptr;
@@ -728,14 +739,18 @@ PSC_API psc_status psc_tune(psc_ctx* ctx, psc_obs* obs, const double* offsets_de
     double best = 1e300;
     int32_t best_v = obs->degrid;
     const int32_t keep = obs->degrid;
-    for (int32_t v = PSC_DEGRID_VALU; v <= PSC_DEGRID_MFMA && e == hipSuccess; ++v) {
+    for (int32_t v = PSC_DEGRID_VALU; v <= PSC_DEGRID_WINDOW && e == hipSuccess; ++v) {
+        if (ctx->s != 16 && v != PSC_DEGRID_WINDOW) {
+            if (times_us_out) times_us_out[v] = -1.0;  // not available at this support
+            continue;
+        }
         obs->degrid = v;
         ItemArgs a = item_args(ctx, obs, offsets_dev, 0, (int)obs->n_items, nullptr);
         a.vis_in = (const float2*)vis_obs_dev;
         a.weight = weight_dev;
-        e = launch_items(kGrad, ctx->s, a, s);  // warm-up
+        e = launch_degrid(kGrad, ctx, obs, a, s);  // warm-up
         if (e == hipSuccess) e = hipEventRecord(e0, s);
-        for (int r = 0; r < repeats && e == hipSuccess; ++r) e = launch_items(kGrad, ctx->s, a, s);
+        for (int r = 0; r < repeats && e == hipSuccess; ++r) e = launch_degrid(kGrad, ctx, obs, a, s);
         if (e == hipSuccess) e = hipEventRecord(e1, s);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.f;

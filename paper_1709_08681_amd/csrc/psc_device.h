@@ -1,0 +1,254 @@
+// psc_device.h -- device helpers shared by the kernels of libpsc: complex
+// arithmetic, wavefront-level ordering and reductions, the in-register FFT and
+// the antenna voltage pattern.
+#pragma once
+
+#include "psc_internal.h"
+
+namespace psc {
+
+// exp(+2 pi i j / 64), j = 0..63, evaluated at compile time (Taylor series on
+// [-pi, pi], exact on the axes) so that the unrolled FFT sees literal twiddles.
+struct TwTable {
+    float re[64];
+    float im[64];
+    constexpr TwTable() : re(), im()
+    {
+        for (int j = 0; j < 64; ++j) {
+            const int jj = j > 32 ? j - 64 : j;
+            const double x = kPi * jj / 32.0;
+            double sn = x, cs = 1.0, ts = x, tc = 1.0;
+            for (int k = 1; k < 30; ++k) {
+                ts *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+                sn += ts;
+                tc *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+                cs += tc;
+            }
+            if (j % 16 == 0) {
+                const int q = j / 16;
+                cs = (q == 0) ? 1.0 : (q == 2) ? -1.0 : 0.0;
+                sn = (q == 1) ? 1.0 : (q == 3) ? -1.0 : 0.0;
+            }
+            re[j] = (float)cs;
+            im[j] = (float)sn;
+        }
+    }
+};
+constexpr TwTable kTw{};
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
+{
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__device__ __forceinline__ void cmac(float2& acc, float2 a, float2 b)
+{
+    acc.x = fmaf(a.x, b.x, acc.x);
+    acc.x = fmaf(-a.y, b.y, acc.x);
+    acc.y = fmaf(a.x, b.y, acc.y);
+    acc.y = fmaf(a.y, b.x, acc.y);
+}
+
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+// Orders LDS traffic between the lanes of one wavefront.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sum over each row of 16 lanes with DPP moves (quad swaps, then half-row and
+// row mirrors); every lane of the row ends with the row's total.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
+                                                                 0xF, 0xF, true));
+}
+
+__device__ __forceinline__ float row16_sum(float v)
+{
+    v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141>(v);  // row_half_mirror
+    v += dpp_mov<0x140>(v);  // row_mirror
+    return v;
+}
+
+template <int LOG>
+__host__ __device__ constexpr int bitrev(int i)
+{
+    int r = 0;
+    for (int b = 0; b < LOG; ++b)
+        if (i & (1 << b)) r |= 1 << (LOG - 1 - b);
+    return r;
+}
+
+// t = w * v for the twiddle w = exp(+2 pi i j / 64) (j known after unrolling);
+// multiplications by 1, i, -1, -i are dropped.
+__device__ __forceinline__ float2 twmul(int j, float2 v)
+{
+    if (j == 0) return v;
+    if (j == 16) return make_float2(-v.y, v.x);
+    if (j == 32) return make_float2(-v.x, -v.y);
+    if (j == 48) return make_float2(v.y, -v.x);
+    const float wr = kTw.re[j], wi = kTw.im[j];
+    return make_float2(v.x * wr - v.y * wi, v.x * wi + v.y * wr);
+}
+
+// In-register radix-2 DFT X[b] = sum_r x[r] exp(+2 pi i b r / S), S <= 64.
+template <int S>
+__device__ __forceinline__ void fft_reg(float2 (&x)[S])
+{
+    constexpr int LOG = (S == 8) ? 3 : (S == 16) ? 4 : (S == 32) ? 5 : 6;
+    float2 y[S];
+#pragma unroll
+    for (int i = 0; i < S; ++i) y[bitrev<LOG>(i)] = x[i];
+#pragma unroll
+    for (int st = 1; st <= LOG; ++st) {
+        const int mlen = 1 << st, half = mlen >> 1;
+#pragma unroll
+        for (int k = 0; k < S; k += mlen) {
+#pragma unroll
+            for (int j = 0; j < half; ++j) {
+                const float2 t = twmul(j * (64 / mlen), y[k + j + half]);
+                const float2 u = y[k + j];
+                y[k + j] = make_float2(u.x + t.x, u.y + t.y);
+                y[k + j + half] = make_float2(u.x - t.x, u.y - t.y);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < S; ++i) x[i] = y[i];
+}
+
+// Far-field voltage pattern of one antenna at sky offset (dl, dm) = l - p and
+// its derivatives with respect to the pointing offset p (float32; the Airy
+// pattern from the cubic Hermite table, the Gaussian in closed form).
+__device__ __forceinline__ void efp(const ItemArgs& a, float kk, float inv_s2, float dl, float dm,
+                                    float& e, float& el, float& em)
+{
+    if (a.illum == 1) {
+        e = expf(-0.5f * (dl * dl + dm * dm) * inv_s2);
+        el = e * dl * inv_s2;
+        em = e * dm * inv_s2;
+        return;
+    }
+    const float x = kk * sqrtf(dl * dl + dm * dm);
+    float u = x * a.inv_dx;
+    int i;
+    if (!(u < (float)(a.n_tab - 2))) {  // beyond the table, or not finite: clamp
+        i = a.n_tab - 2;
+        u = (float)i + 1.0f;
+    } else {
+        i = (int)u;
+    }
+    const float t = u - (float)i;
+    const float4 p0 = a.airy[i], p1 = a.airy[i + 1];
+    const float t2 = t * t, t3 = t2 * t;
+    const float h00 = 2.f * t3 - 3.f * t2 + 1.f, h10 = t3 - 2.f * t2 + t, h01 = -2.f * t3 + 3.f * t2,
+                h11 = t3 - t2;
+    const float A = h00 * p0.x + h10 * p0.y + h01 * p1.x + h11 * p1.y;
+    const float B = h00 * p0.z + h10 * p0.w + h01 * p1.z + h11 * p1.w;
+    e = A;
+    const float k2 = kk * kk * B;
+    el = k2 * dl;
+    em = k2 * dm;
+}
+
+// Image-plane products E_i E_j c at the M x M samples (spacing FoV/S, centred)
+// for one item and polarisation, and for the gradient and adjoint the offset
+// derivatives dE_i/dp_i E_j c and E_i dE_j/dp_j c (Eq. DA).  Variant k goes to
+// gsh[k * m2p + n]; threads tid, tid + nthr, ... of the block share the work.
+template <int MODE>
+__device__ __forceinline__ void image_products(const ItemArgs& a, const Item& it, int pol, float* gsh,
+                                               int m2p, int tid, int nthr)
+{
+    const int m = a.m, half_m = m >> 1, m2 = m * m;
+    const double lam = kCLight / a.freq[it.chan];
+    const float kk = (float)(kPi * a.dish / lam);
+    const double sigma = a.gauss_sigma_ld * lam / a.dish;
+    const float inv_s2 = (float)(1.0 / (sigma * sigma));
+    const double hp = 1.02899 * lam / a.dish;
+    const float hstep = (float)a.h;
+    // beam squint: opposite shifts along l for the two polarisations
+    const double sq = (pol == 0 ? 1.0 : -1.0) * a.squint_frac * hp;
+    const double* oi = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.ai) * 2;
+    const double* oj = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.aj) * 2;
+    const float pil = (float)(oi[0] + sq), pim = (float)oi[1];
+    const float pjl = (float)(oj[0] + sq), pjm = (float)oj[1];
+    for (int idx = tid; idx < m2; idx += nthr) {
+        const int il = idx / m, im = idx - il * m;
+        const float l = (float)(il - half_m) * hstep, mm = (float)(im - half_m) * hstep;
+        float ei, eil, eim, ej, ejl, ejm;
+        efp(a, kk, inv_s2, l - pil, mm - pim, ei, eil, eim);
+        efp(a, kk, inv_s2, l - pjl, mm - pjm, ej, ejl, ejm);
+        const float c = a.taper_img[il] * a.taper_img[im];
+        if (MODE == kPredict) {
+            gsh[idx] = ei * ej * c;
+        } else {
+            constexpr int o = (MODE == kGrad) ? 1 : 0;
+            if (MODE == kGrad) gsh[idx] = ei * ej * c;
+            gsh[(o + 0) * m2p + idx] = eil * ej * c;
+            gsh[(o + 1) * m2p + idx] = eim * ej * c;
+            gsh[(o + 2) * m2p + idx] = ei * ejl * c;
+            gsh[(o + 3) * m2p + idx] = ei * ejm * c;
+        }
+    }
+}
+
+// Per-sample terms of the float64 sums.  Gradient: lane t < 12 of a sample's
+// lane group adds term t = 6 * end + c, end 0 for antenna i and 1 for j, c
+// indexing chi, g_l, g_m, H_ll, H_lm, H_mm = w Re(conj(x) y) with
+// (x, y) = (R,R) (R,dl) (R,dm) (dl,dl) (dl,dm) (dm,dm) (Eq. DCHIDD and the
+// 2 x 2 normal matrix); the residual R = V^Obs - V^M is formed exactly, the
+// product in float32 and the running sum in float64.
+struct TermSel {
+    bool on, end, xr, xl, yr, yl;
+    __device__ explicit TermSel(int t)
+    {
+        const int c = t % 6;
+        on = t < 12;
+        end = t >= 6 && t < 12;
+        xr = c < 3;
+        xl = c == 3 || c == 4;
+        yr = c == 0;
+        yl = c == 1 || c == 3;
+    }
+};
+
+// s[0] = V^M, s[1..4] = dV/d(l_i, m_i, l_j, m_j).
+template <int NV>
+__device__ __forceinline__ void grad_term(const TermSel& ts, const float2 (&s)[NV], float2 vo, float wgt,
+                                          double& acc)
+{
+    const float rr = (float)((double)vo.x - (double)s[0].x);
+    const float ri = (float)((double)vo.y - (double)s[0].y);
+    const float2 dl = ts.end ? s[3] : s[1];
+    const float2 dm = ts.end ? s[4] : s[2];
+    const float xr = ts.xr ? rr : (ts.xl ? dl.x : dm.x);
+    const float xi = ts.xr ? ri : (ts.xl ? dl.y : dm.y);
+    const float yr = ts.yr ? rr : (ts.yl ? dl.x : dm.x);
+    const float yi = ts.yr ? ri : (ts.yl ? dl.y : dm.y);
+    const float val = fmaf(xr, yr, xi * yi);
+    if (ts.on) acc = fma((double)wgt, (double)val, acc);
+}
+
+// Adjoint: lane t < 4 adds Re(conj(G) dV/dp_t), s[0..3] = dV/d(l_i, m_i, l_j, m_j).
+template <int NV>
+__device__ __forceinline__ void vjp_term(int t, const float2 (&s)[NV], float2 gv, double& acc)
+{
+    const int tt = t < 4 ? t : 0;
+    float2 dv = s[0];
+#pragma unroll
+    for (int k = 1; k < 4; ++k)
+        if (tt == k) dv = s[k];
+    if (t < 4) acc += (double)gv.x * (double)dv.x + (double)gv.y * (double)dv.y;
+}
+
+}  // namespace psc

@@ -105,9 +105,14 @@ hipError_t launch_transpose(const double2* in, double2* out, int n, hipStream_t 
 hipError_t launch_finish_grid(const double2* in, float2* out, int n, int pad, hipStream_t s);
 hipError_t launch_airy_table(float4* tab, int n_tab, double dx, hipStream_t s);
 hipError_t launch_items(int mode, int support, const ItemArgs& a, hipStream_t s);
+// Window-form degrid (psc_window.hip), supports 16 and 32, 4 wavefronts per
+// block; win_lds_bytes is its dynamic LDS per block.
+hipError_t launch_win(int mode, int support, const ItemArgs& a, hipStream_t s);
+size_t win_lds_bytes(int support, int mode, int waves, int m, int oversample);
+// dynamic LDS the window form may use: 160 KiB per CU less its static arrays
+constexpr size_t kWinLdsBudget = 160 * 1024 - 9 * 1024;
 hipError_t launch_reduce(int ncontrib, const ReduceArgs& a, hipStream_t s);
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
 hipError_t launch_init_state(int32_t* done, int32_t* iters, int n, hipStream_t s);
-hipError_t set_fft_twiddles();
 
 }  // namespace psc

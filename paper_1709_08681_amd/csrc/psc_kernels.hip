@@ -17,131 +17,9 @@
 // as f + O b (0 <= f < O), the DFT splits into a twiddle by exp(2 pi i f n/(SO)),
 // a fold of n modulo S, and an S-point DFT over b: each S x S sub-table is one
 // small 2-D FFT.  Only sub-tables that some sample of the item uses are built.
-#include "psc_internal.h"
+#include "psc_device.h"
 
 namespace psc {
-
-// exp(+2 pi i j / 64), j = 0..63, evaluated at compile time (Taylor series on
-// [-pi, pi], exact on the axes) so that the unrolled FFT sees literal twiddles.
-struct TwTable {
-    float re[64];
-    float im[64];
-    constexpr TwTable() : re(), im()
-    {
-        for (int j = 0; j < 64; ++j) {
-            const int jj = j > 32 ? j - 64 : j;
-            const double x = kPi * jj / 32.0;
-            double sn = x, cs = 1.0, ts = x, tc = 1.0;
-            for (int k = 1; k < 30; ++k) {
-                ts *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
-                sn += ts;
-                tc *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
-                cs += tc;
-            }
-            if (j % 16 == 0) {
-                const int q = j / 16;
-                cs = (q == 0) ? 1.0 : (q == 2) ? -1.0 : 0.0;
-                sn = (q == 1) ? 1.0 : (q == 3) ? -1.0 : 0.0;
-            }
-            re[j] = (float)cs;
-            im[j] = (float)sn;
-        }
-    }
-};
-constexpr TwTable kTw{};
-
-hipError_t set_fft_twiddles() { return hipSuccess; }
-
-// ---------------------------------------------------------------------------
-// small helpers
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ float2 cmul(float2 a, float2 b)
-{
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-
-__device__ __forceinline__ void cmac(float2& acc, float2 a, float2 b)
-{
-    acc.x = fmaf(a.x, b.x, acc.x);
-    acc.x = fmaf(-a.y, b.y, acc.x);
-    acc.y = fmaf(a.x, b.y, acc.y);
-    acc.y = fmaf(a.y, b.x, acc.y);
-}
-
-typedef float mfma_f4 __attribute__((ext_vector_type(4)));
-
-// Orders LDS traffic between the lanes of one wavefront.
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Sum over each row of 16 lanes with DPP moves (quad swaps, then half-row and
-// row mirrors); every lane of the row ends with the row's total.
-template <int CTRL>
-__device__ __forceinline__ float dpp_mov(float v)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
-                                                                 0xF, 0xF, true));
-}
-
-__device__ __forceinline__ float row16_sum(float v)
-{
-    v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
-    v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
-    v += dpp_mov<0x141>(v);  // row_half_mirror
-    v += dpp_mov<0x140>(v);  // row_mirror
-    return v;
-}
-
-template <int LOG>
-__host__ __device__ constexpr int bitrev(int i)
-{
-    int r = 0;
-    for (int b = 0; b < LOG; ++b)
-        if (i & (1 << b)) r |= 1 << (LOG - 1 - b);
-    return r;
-}
-
-// t = w * v for the twiddle w = exp(+2 pi i j / 64) (j known after unrolling);
-// multiplications by 1, i, -1, -i are dropped.
-__device__ __forceinline__ float2 twmul(int j, float2 v)
-{
-    if (j == 0) return v;
-    if (j == 16) return make_float2(-v.y, v.x);
-    if (j == 32) return make_float2(-v.x, -v.y);
-    if (j == 48) return make_float2(v.y, -v.x);
-    const float wr = kTw.re[j], wi = kTw.im[j];
-    return make_float2(v.x * wr - v.y * wi, v.x * wi + v.y * wr);
-}
-
-// In-register radix-2 DFT X[b] = sum_r x[r] exp(+2 pi i b r / S), S <= 64.
-template <int S>
-__device__ __forceinline__ void fft_reg(float2 (&x)[S])
-{
-    constexpr int LOG = (S == 8) ? 3 : (S == 16) ? 4 : (S == 32) ? 5 : 6;
-    float2 y[S];
-#pragma unroll
-    for (int i = 0; i < S; ++i) y[bitrev<LOG>(i)] = x[i];
-#pragma unroll
-    for (int st = 1; st <= LOG; ++st) {
-        const int mlen = 1 << st, half = mlen >> 1;
-#pragma unroll
-        for (int k = 0; k < S; k += mlen) {
-#pragma unroll
-            for (int j = 0; j < half; ++j) {
-                const float2 t = twmul(j * (64 / mlen), y[k + j + half]);
-                const float2 u = y[k + j];
-                y[k + j] = make_float2(u.x + t.x, u.y + t.y);
-                y[k + j + half] = make_float2(u.x - t.x, u.y - t.y);
-            }
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < S; ++i) x[i] = y[i];
-}
 
 // ---------------------------------------------------------------------------
 // Model transform (setup): V^{M0}[k] = sum_n I[n]/c[n] exp(+2 pi i k.(n - N/2)/N)
@@ -234,40 +112,6 @@ __global__ void k_airy_table(float4* __restrict__ tab, int n_tab, double dx)
     tab[i] = make_float4((float)A, (float)(-x * B * dx), (float)B, (float)(Bp * dx));
 }
 
-// Far-field voltage pattern of one antenna at sky offset (dl, dm) = l - p and
-// its derivatives with respect to the pointing offset p (float32; the Airy
-// pattern from the cubic Hermite table, the Gaussian in closed form).
-__device__ __forceinline__ void efp(const ItemArgs& a, float kk, float inv_s2, float dl, float dm,
-                                    float& e, float& el, float& em)
-{
-    if (a.illum == 1) {
-        e = expf(-0.5f * (dl * dl + dm * dm) * inv_s2);
-        el = e * dl * inv_s2;
-        em = e * dm * inv_s2;
-        return;
-    }
-    const float x = kk * sqrtf(dl * dl + dm * dm);
-    float u = x * a.inv_dx;
-    int i;
-    if (!(u < (float)(a.n_tab - 2))) {  // beyond the table, or not finite: clamp
-        i = a.n_tab - 2;
-        u = (float)i + 1.0f;
-    } else {
-        i = (int)u;
-    }
-    const float t = u - (float)i;
-    const float4 p0 = a.airy[i], p1 = a.airy[i + 1];
-    const float t2 = t * t, t3 = t2 * t;
-    const float h00 = 2.f * t3 - 3.f * t2 + 1.f, h10 = t3 - 2.f * t2 + t, h01 = -2.f * t3 + 3.f * t2,
-                h11 = t3 - t2;
-    const float A = h00 * p0.x + h10 * p0.y + h01 * p1.x + h11 * p1.y;
-    const float B = h00 * p0.z + h10 * p0.w + h01 * p1.z + h11 * p1.w;
-    e = A;
-    const float k2 = kk * kk * B;
-    el = k2 * dl;
-    em = k2 * dm;
-}
-
 // ---------------------------------------------------------------------------
 // Fused kernel build + degrid + per-item float64 partial sums.
 // One block (4 wavefronts) per item; the wavefronts share the image-plane
@@ -310,13 +154,6 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
 
     const int N = a.grid_n;
     const int O = a.oversample, so = S * O;
-    const double nu = a.freq[it.chan];
-    const double lam = kCLight / nu;
-    const float kk = (float)(kPi * a.dish / lam);
-    const double sigma = a.gauss_sigma_ld * lam / a.dish;
-    const float inv_s2 = (float)(1.0 / (sigma * sigma));
-    const double hp = 1.02899 * lam / a.dish;
-    const float hstep = (float)a.h;
     const float inv_s = 1.0f / (float)S;
     const int P = N + S;  // pitch of the padded grid
     const int rowbytes = P * (int)sizeof(float2);
@@ -328,30 +165,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
 
     for (int pol = 0; pol < a.n_pol; ++pol) {
         if (tid == 0) next_group = it.grp_begin + kWaves;
-        // ---- image-plane products E_i E_j c and their offset derivatives
-        const double sq = (pol == 0 ? 1.0 : -1.0) * a.squint_frac * hp;
-        const double* oi = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.ai) * 2;
-        const double* oj = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.aj) * 2;
-        const float pil = (float)(oi[0] + sq), pim = (float)oi[1];
-        const float pjl = (float)(oj[0] + sq), pjm = (float)oj[1];
-        for (int idx = tid; idx < m2; idx += kBlock) {
-            const int il = idx / m, im = idx - il * m;
-            const float l = (float)(il - half_m) * hstep, mm = (float)(im - half_m) * hstep;
-            float ei, eil, eim, ej, ejl, ejm;
-            efp(a, kk, inv_s2, l - pil, mm - pim, ei, eil, eim);
-            efp(a, kk, inv_s2, l - pjl, mm - pjm, ej, ejl, ejm);
-            const float c = a.taper_img[il] * a.taper_img[im];
-            if (MODE == kPredict) {
-                gsh[idx] = ei * ej * c;
-            } else {
-                constexpr int o = (MODE == kGrad) ? 1 : 0;
-                if (MODE == kGrad) gsh[idx] = ei * ej * c;
-                gsh[(o + 0) * m2p + idx] = eil * ej * c;
-                gsh[(o + 1) * m2p + idx] = eim * ej * c;
-                gsh[(o + 2) * m2p + idx] = ei * ejl * c;
-                gsh[(o + 3) * m2p + idx] = ei * ejm * c;
-            }
-        }
+        image_products<MODE>(a, it, pol, gsh, m2p, tid, kBlock);
         __syncthreads();
 
         double acc64 = 0.0;
@@ -500,10 +314,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
             // slots read the same addresses).  Each lane carries SPL samples.
             const int t = am;
             // which term lane t accumulates (see the gradient branch below)
-            const int t_c = t % 6;
-            const bool t_end = t >= 6 && t < 12;
-            const bool t_xr = t_c < 3, t_xl = t_c == 3 || t_c == 4;
-            const bool t_yr = t_c == 0, t_yl = t_c == 1 || t_c == 3;
+            const TermSel tsel(t);
+            const bool t_end = tsel.end, t_xr = tsel.xr, t_xl = tsel.xl, t_yr = tsel.yr, t_yl = tsel.yl;
             // D columns (MFMA path): V = 0,1; d/dl_i = 2,3; d/dm_i = 4,5; d/dl_j = 6,7; d/dm_j = 8,9
             const int t_dl = t_end ? 6 : 2, t_dm = t_end ? 8 : 4;
             const int t_xcol = t_xr ? 0 : (t_xl ? t_dl : t_dm);
@@ -577,30 +389,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
                         if (t == 0) a.vis_out[o] = s[j][0];
                     } else if (MODE == kGrad) {
                         if (a.vis_out != nullptr && t == 0) a.vis_out[o] = s[j][0];
-                        // lane t < 12 adds term t = (end, c) of the sums:
-                        // c = chi, g_l, g_m, H_ll, H_lm, H_mm = Re(conj(x) y)
-                        // with (x, y) = (R,R) (R,dl) (R,dm) (dl,dl) (dl,dm) (dm,dm);
-                        // the residual is formed exactly, the product in float32
-                        // and the running sum in float64
-                        const float2 vo = vin[j];
-                        const float rr = (float)((double)vo.x - (double)s[j][0].x);
-                        const float ri = (float)((double)vo.y - (double)s[j][0].y);
-                        const float2 dl = t_end ? s[j][3] : s[j][1];
-                        const float2 dm = t_end ? s[j][4] : s[j][2];
-                        const float xr = t_xr ? rr : (t_xl ? dl.x : dm.x);
-                        const float xi = t_xr ? ri : (t_xl ? dl.y : dm.y);
-                        const float yr = t_yr ? rr : (t_yl ? dl.x : dm.x);
-                        const float yi = t_yr ? ri : (t_yl ? dl.y : dm.y);
-                        const float val = fmaf(xr, yr, xi * yi);
-                        if (t < 12) acc64 = fma((double)wgt[j], (double)val, acc64);
+                        grad_term(tsel, s[j], vin[j], wgt[j], acc64);
                     } else {
-                        const float2 gv = vin[j];
-                        const int tt = t < 4 ? t : 0;
-                        float2 dv = s[j][0];
-#pragma unroll
-                        for (int k = 1; k < 4; ++k)
-                            if (tt == k) dv = s[j][k];
-                        if (t < 4) acc64 += (double)gv.x * (double)dv.x + (double)gv.y * (double)dv.y;
+                        vjp_term(t, s[j], vin[j], acc64);
                     }
                 }
 #pragma unroll

@@ -1,0 +1,261 @@
+// psc_window.hip -- degridding in the window form (supports 16 and 32).
+//
+// The table form (psc_kernels.hip) evaluates each sample as
+//     V = sum_a V^{M0}[k_lo + a] T_f[S-1-a],
+// where the sub-table T_f is the S-point 2-D DFT of the folded, twiddled
+// image-plane products U_f[r] = sum_{n = r mod S} phi_f(n) g[n], with the
+// per-axis phase phi_f(n) = exp(2 pi i f n / (S O)) (-1)^n / S.  Moving the DFT
+// from the kernel onto the window (Parseval) and undoing the fold gives
+//     V = sum_n g[n] phi_f(n) What[n mod S],
+//     What[b] = sum_a' V^{M0}[k_lo + S-1-a'] exp(+2 pi i a'.b / S),
+// the sum running over the M x M image samples.  This is the same quantity,
+// term for term, as the A-projection degrid of Algorithm 1 with the kernel of
+// Eq. MEDD; only the order of the sums differs.  Per sample it costs one S x S
+// FFT of the window and an M x M dot product for all derivative variants
+// (Eq. DA) at once, instead of NV S x S FFTs per sub-table, and it stores no
+// sub-table: the form for few samples per sub-table (fine oversampling, short
+// solution intervals) and for support 32, whose five sub-tables would not fit
+// in LDS beside the image-plane products.
+#include <algorithm>
+
+#include "psc_device.h"
+
+namespace psc {
+
+// One block (W wavefronts) per item, as in the table form: the wavefronts
+// share the item's image-plane products in LDS and take its sample groups in
+// turn.  A wavefront handles 64/S samples of a group at a time, one per S-lane
+// slot: lane (slot, c) loads column c of the sample's reversed window, the
+// slot transforms it through a private S x (S+1) LDS tile (columns, then
+// rows), and lane c then sums over the image samples n whose m index is
+// congruent to c modulo S.
+template <int S, int MODE, int W>
+__global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
+{
+    constexpr int NV = (MODE == kPredict) ? 1 : (MODE == kGrad) ? 5 : 4;
+    constexpr int NC = (MODE == kGrad) ? 12 : (MODE == kVjp) ? 4 : 0;
+    constexpr int SP = S + 1;
+    constexpr int SPW = 64 / S;
+    constexpr int kBlock = 64 * W;
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ float2 twsh[S * 16];     // exp(+2 pi i t / (S O)), S O <= 16 S
+    __shared__ float2 phsh[W][128];     // per-wave phases: l axis at [0, M), m axis at [64, 64 + M)
+    __shared__ int next_group;
+
+    const int m = a.m, half_m = m >> 1;
+    const int m2p = (m * m + 3) & ~3;
+    // dynamic LDS: per-group float64 sums | image-plane products | window tiles
+    double* gpart = reinterpret_cast<double*>(smem);
+    const int O2 = a.oversample * a.oversample;
+    float* gsh = reinterpret_cast<float*>(smem + sizeof(double) * (NC > 0 ? NC : 1) * O2);
+    float2* wtile = reinterpret_cast<float2*>(reinterpret_cast<unsigned char*>(gsh) + sizeof(float) * NV * m2p);
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int per_xcd = gridDim.x >> 3;
+    const int li = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (li >= a.n_items) return;
+    const int item_idx = a.item_begin + li;
+    const Item it = a.items[item_idx];
+    if (a.done != nullptr && a.done[it.interval]) return;
+
+    const int N = a.grid_n;
+    const int O = a.oversample, so = S * O;
+    const float inv_s = 1.0f / (float)S;
+    const int P = N + S;  // pitch of the padded grid
+    const int rowbytes = P * (int)sizeof(float2);
+    const __amdgpu_buffer_rsrc_t grsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)a.grid, (short)0, P * P * (int)sizeof(float2), 0x00020000);
+
+    for (int t = tid; t < so; t += kBlock) twsh[t] = a.tw[t];
+
+    const int slot = lane / S;
+    const int c = lane - slot * S;
+    float2* wt = wtile + ((size_t)wave * SPW + slot) * S * SP;  // this slot's tile
+    float2* phw = phsh[wave];
+    const TermSel tsel(c);
+    // the two image-sample m indices congruent to c modulo S: c and c - S
+    const bool m0_ok = c < half_m, m1_ok = c >= S - half_m;
+    const int jm0 = m0_ok ? c + half_m : 0;
+    const int jm1 = m1_ok ? c - S + half_m : 0;
+
+    for (int pol = 0; pol < a.n_pol; ++pol) {
+        if (tid == 0) next_group = it.grp_begin + W;
+        image_products<MODE>(a, it, pol, gsh, m2p, tid, kBlock);
+        __syncthreads();
+
+        double acc64 = 0.0;
+        int gi = it.grp_begin + wave;
+        Group g = a.groups[gi < it.grp_end ? gi : it.grp_begin];
+        while (gi < it.grp_end) {
+            int nxt_g = 0;
+            if (lane == 0) nxt_g = atomicAdd(&next_group, 1);
+            nxt_g = __shfl(nxt_g, 0);
+            const Group gnext = a.groups[nxt_g < it.grp_end ? nxt_g : gi];
+
+            // the group's samples at offset f, then those at -f
+            for (int part = 0; part < 2; ++part) {
+                const int nv = part ? g.n_vis2 : g.n_vis;
+                if (nv <= 0) continue;
+                const uint32_t vb = g.vis_begin + (part ? (uint32_t)g.n_vis : 0u);
+                int fl = g.f / O, fm = g.f - (g.f / O) * O;
+                if (part) {
+                    fl = (O - fl) & (O - 1);
+                    fm = (O - fm) & (O - 1);
+                }
+                // ---- per-axis phases (-1)^n exp(2 pi i f n / (S O)) / S, n in [-M/2, M/2)
+                wave_sync();  // the previous pass has finished reading phw
+                if (lane < m) {
+                    const int n = lane - half_m;
+                    const float sg = (n & 1) ? -inv_s : inv_s;
+                    const float2 pl = twsh[(fl * n) & (so - 1)];
+                    const float2 pm = twsh[(fm * n) & (so - 1)];
+                    phw[lane] = make_float2(pl.x * sg, pl.y * sg);
+                    phw[64 + lane] = make_float2(pm.x * sg, pm.y * sg);
+                }
+                wave_sync();
+                const float2 zero = make_float2(0.f, 0.f);
+                const float2 pm0 = m0_ok ? phw[64 + jm0] : zero;
+                const float2 pm1 = m1_ok ? phw[64 + jm1] : zero;
+
+                for (int v0 = 0; v0 < nv; v0 += SPW) {
+                    const int v = v0 + slot;
+                    const bool valid = v < nv;
+                    const VisEnt e = a.vis[vb + (valid ? v : nv - 1)];
+                    const size_t o = (size_t)e.vidx * a.n_pol + pol;
+                    float2 vin = zero;
+                    float wgt = 0.f;
+                    if (MODE != kPredict) vin = a.vis_in[o];
+                    if (MODE == kGrad) wgt = a.weight[o];
+                    // ---- reversed window column c: x[i] = V^{M0}[k_lo_l + S-1-i][k_lo_m + S-1-c]
+                    const int row0 = (int)(e.klo >> 16);
+                    const int col0 = (int)(e.klo & 0xffffu);
+                    const int voff = (row0 * P + col0 + (S - 1 - c)) * (int)sizeof(float2);
+                    float2 x[S];
+#pragma unroll
+                    for (int i = 0; i < S; ++i)
+                        x[i] = __builtin_bit_cast(
+                            float2, __builtin_amdgcn_raw_buffer_load_b64(grsrc, voff, (S - 1 - i) * rowbytes, 0));
+                    // ---- 2-D DFT of the window: along l in registers, then along m
+                    fft_reg<S>(x);
+                    wave_sync();  // the previous sample's tile has been read
+#pragma unroll
+                    for (int i = 0; i < S; ++i) wt[i * SP + c] = x[i];
+                    wave_sync();
+#pragma unroll
+                    for (int i = 0; i < S; ++i) x[i] = wt[c * SP + i];
+                    fft_reg<S>(x);
+#pragma unroll
+                    for (int i = 0; i < S; ++i) wt[c * SP + i] = x[i];
+                    wave_sync();
+
+                    // ---- V_k = sum_n g_k[n] phi_l(n_l) phi_m(n_m) What[n_l mod S][n_m mod S]
+                    float2 s[NV];
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) s[k] = zero;
+                    for (int jl = 0; jl < m; ++jl) {
+                        const int bl = (jl - half_m) & (S - 1);
+                        const float2 t = cmul(phw[jl], wt[bl * SP + c]);
+                        const float2 z0 = cmul(t, pm0), z1 = cmul(t, pm1);
+                        const float* gr = gsh + jl * m;
+#pragma unroll
+                        for (int k = 0; k < NV; ++k) {
+                            const float g0 = gr[k * m2p + jm0], g1 = gr[k * m2p + jm1];
+                            s[k].x = fmaf(g0, z0.x, fmaf(g1, z1.x, s[k].x));
+                            s[k].y = fmaf(g0, z0.y, fmaf(g1, z1.y, s[k].y));
+                        }
+                    }
+                    // sum over the slot's S lanes
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) {
+                        s[k].x = row16_sum(s[k].x);
+                        s[k].y = row16_sum(s[k].y);
+                        if constexpr (S == 32) {
+                            s[k].x += __shfl_xor(s[k].x, 16);
+                            s[k].y += __shfl_xor(s[k].y, 16);
+                        }
+                    }
+                    if (valid) {
+                        if (MODE == kPredict) {
+                            if (c == 0) a.vis_out[o] = s[0];
+                        } else if (MODE == kGrad) {
+                            if (a.vis_out != nullptr && c == 0) a.vis_out[o] = s[0];
+                            grad_term(tsel, s, vin, wgt, acc64);
+                        } else {
+                            vjp_term(c, s, vin, acc64);
+                        }
+                    }
+                }
+            }
+            if (NC > 0) {
+                // the group's own sums, kept per group so that the item total
+                // does not depend on which wavefront took the group
+#pragma unroll
+                for (int off = S; off < 64; off <<= 1) acc64 += __shfl_xor(acc64, off);
+                if (lane < NC) gpart[(gi - it.grp_begin) * NC + lane] = acc64;
+                acc64 = 0.0;
+            }
+            gi = nxt_g;
+            g = gnext;
+        }
+
+        // ---- per-item partial sums: groups added in group order
+        __syncthreads();
+        if (NC > 0 && tid < NC) {
+            double sum = 0.0;
+            for (int gg = 0; gg < it.grp_end - it.grp_begin; ++gg) sum += gpart[gg * NC + tid];
+            a.partials[((size_t)item_idx * a.n_pol + pol) * NC + tid] = sum;
+        }
+        __syncthreads();
+    }
+}
+
+template <int S, int MODE, int W>
+static hipError_t launch_win_t(const ItemArgs& a, hipStream_t s)
+{
+    const size_t sh = win_lds_bytes(S, MODE, W, a.m, a.oversample);
+    if (sh > kWinLdsBudget) return hipErrorInvalidValue;
+    // raise the dynamic LDS limit once, to the largest size a valid setting needs
+    static const hipError_t attr = [] {
+        const size_t shmax = std::min(win_lds_bytes(S, MODE, W, 2 * S, 16), kWinLdsBudget);
+        return hipFuncSetAttribute((const void*)k_win<S, MODE, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)shmax);
+    }();
+    if (attr != hipSuccess) return attr;
+    const int blocks = 8 * ((a.n_items + 7) / 8);
+    k_win<S, MODE, W><<<blocks, 64 * W, sh, s>>>(a);
+    return hipGetLastError();
+}
+
+size_t win_lds_bytes(int support, int mode, int waves, int m, int oversample)
+{
+    const int nv = (mode == kPredict) ? 1 : (mode == kGrad) ? 5 : 4;
+    const int nc = (mode == kGrad) ? 12 : (mode == kVjp) ? 4 : 1;
+    const int m2p = (m * m + 3) & ~3;
+    return sizeof(double) * nc * oversample * oversample + sizeof(float) * nv * m2p +
+           sizeof(float2) * (size_t)waves * 64 * (support + 1);
+}
+
+hipError_t launch_win(int mode, int support, const ItemArgs& a, hipStream_t s)
+{
+    if (a.n_items <= 0) return hipSuccess;
+    if (support == 16) {
+        switch (mode) {
+        case kPredict: return launch_win_t<16, kPredict, 4>(a, s);
+        case kGrad: return launch_win_t<16, kGrad, 4>(a, s);
+        case kVjp: return launch_win_t<16, kVjp, 4>(a, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (support == 32) {
+        switch (mode) {
+        case kPredict: return launch_win_t<32, kPredict, 4>(a, s);
+        case kGrad: return launch_win_t<32, kGrad, 4>(a, s);
+        case kVjp: return launch_win_t<32, kVjp, 4>(a, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace psc

@@ -22,7 +22,7 @@ PSC_OK = 0
 STATUS = {0: "PSC_OK", -1: "PSC_E_ARG", -2: "PSC_E_HIP", -3: "PSC_E_OOM", -4: "PSC_E_UNSUPPORTED",
           -5: "PSC_E_STATE"}
 SOLVE_PLAIN, SOLVE_BATCHED, SOLVE_GRAPH = 0, 1, 2
-DEGRID_VALU, DEGRID_MFMA = 0, 1
+DEGRID_VALU, DEGRID_MFMA, DEGRID_WINDOW = 0, 1, 2
 ARCSEC = math.pi / (180.0 * 3600.0)
 
 EXPORTS = ["psc_version", "psc_create", "psc_destroy", "psc_last_error", "psc_set_model",
@@ -190,9 +190,9 @@ def psc_get_degrid(obs):
 
 
 def psc_tune(ctx, obs, offsets_dev, vis_obs_dev, weight_dev, repeats=3, stream=None):
-    """Returns the mean launch time (us) of each degrid variant; the observation
-    keeps the fastest."""
-    t = (C.c_double * 2)()
+    """Returns the mean launch time (us) of each degrid variant (-1 where the
+    support does not allow it); the observation keeps the fastest."""
+    t = (C.c_double * 3)()
     _check(load().psc_tune(ctx, obs, _ptr(offsets_dev), _ptr(vis_obs_dev), _ptr(weight_dev),
                            int(repeats), t, _stream(stream)), ctx)
     return list(t)

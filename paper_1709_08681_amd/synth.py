@@ -63,6 +63,9 @@ class Workload:
     flux_model: str = "unit"  # "unit" (1 Jy each) or "lognormal" (median 10 mJy)
     src_radius: str = "safe"  # "hpbw2": within HPBW/2 at the first channel; "safe": central half
     offset_sigma_arcsec: float = 20.0
+    # if set, offsets drift as a per-antenna random walk (arcsec per axis per
+    # sqrt(minute)) and each interval's true offset is the walk's mean over it
+    offset_walk_arcsec_per_min: float | None = None
     squint_frac: float = 0.0
     snr: float | None = None
     diffuse_fwhm_arcmin: float | None = None
@@ -100,7 +103,8 @@ def workload(k: int, **overrides) -> Workload:
     elif k == 5:
         w = Workload("large", n_ant=128, layout="disk", layout_radius_m=5000.0, n_time=600, dt_s=10.0,
                      freqs_hz=_chan_freqs(256), n_pol=2, grid_n=4096, support=32, oversample=8,
-                     n_src=1000, flux_model="lognormal", offset_sigma_arcsec=30.0, squint_frac=0.03)
+                     n_src=1000, flux_model="lognormal", offset_walk_arcsec_per_min=5.0,
+                     squint_frac=0.03)
         rng = np.random.default_rng(1000 + k)
         cuts = np.sort(rng.choice(np.arange(1, 600), size=63, replace=False))
         w.interval_lengths = [int(x) for x in np.diff(np.concatenate([[0], cuts, [600]]))]
@@ -305,7 +309,13 @@ def make_observation(wl: Workload, seed: int) -> Observation:
         extra_pix = np.stack([gx[ok], gy[ok]], axis=1).astype(np.int64) + n // 2
         extra_flux = val[ok]
     n_int = len(lengths)
-    offs = rng.normal(0.0, wl.offset_sigma_arcsec * ARCSEC, size=(n_int, 1, wl.n_ant, 2))
+    if wl.offset_walk_arcsec_per_min:
+        step = wl.offset_walk_arcsec_per_min * ARCSEC * math.sqrt(wl.dt_s / 60.0)
+        walk = np.cumsum(rng.normal(0.0, step, size=(wl.n_time, wl.n_ant, 2)), axis=0)
+        t_ptr = np.concatenate([[0], np.cumsum(lengths)])
+        offs = np.stack([walk[t_ptr[s]:t_ptr[s + 1]].mean(axis=0) for s in range(n_int)])[:, None]
+    else:
+        offs = rng.normal(0.0, wl.offset_sigma_arcsec * ARCSEC, size=(n_int, 1, wl.n_ant, 2))
     offs = np.repeat(offs, wl.n_pol, axis=1)  # mechanical offsets: same for both pols
     return Observation(wl, ant_pos, ant1, ant2, tidx, uv, ptr, np.asarray(wl.freqs_hz, np.float64),
                        n, cell, pix, flux, np.ascontiguousarray(offs), extra_pix, extra_flux, seed)

@@ -64,9 +64,11 @@ def test_create_rejects_invalid_config(psc, bad):
     assert ei.value.status == -1
 
 
-def test_create_reports_unsupported_support(psc):
+def test_create_reports_unsupported_lds(psc):
+    """Support 32 with 64 image samples at oversampling 8 needs more LDS than
+    one compute unit has (valid request, not implemented)."""
     with pytest.raises(psc.PscError) as ei:
-        psc.psc_create(_cfg(psc, support=32, oversample=8))
+        psc.psc_create(_cfg(psc, support=32, oversample=8, image_samples=64))
     assert ei.value.status == -4
 
 

@@ -383,13 +383,14 @@ def test_image_sample_counts(torch_dev, m):
 
 
 # ---------------------------------------------------------------------------
-# both degrid variants (vector FP32 and matrix-core FP32)
+# every degrid variant: table form on the vector units and on the matrix
+# cores, and the window form
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_degrid_variants_gradient_and_vjp(torch_dev, variant):
-    """Gradient sums and the adjoint with each degrid variant, on ragged
-    intervals with two polarisations (offset pairs f, -f in every item)."""
+    """Prediction, gradient sums and the adjoint with each degrid variant, on
+    ragged intervals with two polarisations (offset pairs f, -f in every item)."""
     torch = torch_dev
     from paper_1709_08681_amd import psc
     lengths = [6, 2, 9]
@@ -403,6 +404,7 @@ def test_degrid_variants_gradient_and_vjp(torch_dev, variant):
         assert psc.psc_get_degrid(s.handle) == variant
         start = synth.perturbed_offsets(obs, 25.0, 19)
         v = oracle.predict(prob, obs.offsets_true)
+        assert rel(s.predict(obs.offsets_true).cpu().numpy(), v) <= 1e-5
         ref, vm_ref = oracle.gradient(prob, start, v, 1.0, want_model=True)
         w1 = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
         acc, vm = s.gradient(s.offsets(start), c64(torch, s, v), w1, want_model=True)
@@ -437,6 +439,95 @@ def test_autotuner_picks_a_variant(torch_dev, cfg1):
     w = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
     off = s.offsets(synth.perturbed_offsets(obs, 20.0, 21))
     t = psc.psc_tune(s.ctx, s.handle, off, v, w, repeats=2)
-    assert len(t) == 2 and min(t) > 0
+    assert len(t) == 3 and min(t) > 0
     assert psc.psc_get_degrid(s.handle) == int(np.argmin(t))
     psc.psc_set_degrid(s.handle, psc.DEGRID_VALU)
+
+
+# ---------------------------------------------------------------------------
+# the window form at full size and at support 32 (large workload)
+# ---------------------------------------------------------------------------
+
+def test_cfg2_full_size_window_form(torch_dev):
+    """Window-form gradient at the full single-interval size against the
+    oracle, on every visibility and every per-antenna sum."""
+    torch = torch_dev
+    from paper_1709_08681_amd import psc
+    print("case: cfg2 full size, window form", flush=True)
+    obs = synth.make_config(2)
+    prob = oracle.Problem.from_observation(obs)
+    s = session(obs)
+    try:
+        psc.psc_set_degrid(s.handle, psc.DEGRID_WINDOW)
+        start = synth.perturbed_offsets(obs, 30.0, 14)
+        v_true = oracle.predict(prob, obs.offsets_true)
+        ref_acc, ref_vm = oracle.gradient(prob, start, v_true, 1.0, want_model=True)
+        w = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+        acc, vm = s.gradient(s.offsets(start), c64(torch, s, v_true), w, want_model=True)
+        e_v = rel(vm.cpu().numpy(), ref_vm)
+        e_a = [rel(acc.cpu().numpy()[..., k], ref_acc[..., k]) for k in range(6)]
+        print(f"cfg2 window: vis rel {e_v:.2e}, acc rel {max(e_a):.2e}", flush=True)
+        assert e_v <= 1e-5
+        assert max(e_a) <= 1e-4
+    finally:
+        s.close()
+
+
+@pytest.fixture(scope="module")
+def cfg5_subset(torch_dev):
+    """Large workload (4096^2 grid, support 32, oversampling 8, two
+    polarisations with opposite squint, random-walk offsets): 6 antennas, the
+    first four solution intervals, every 32nd channel."""
+    full = synth.make_config(5)
+    nt = sum(full.wl.interval_lengths[:4])
+    obs = full.subset(ants=range(6), times=range(nt), chans=range(0, 256, 32))
+    prob = oracle.Problem.from_observation(obs)
+    s = session(obs)
+    yield obs, prob, s
+    s.close()
+
+
+def test_cfg5_subset_predict_gradient(torch_dev, cfg5_subset):
+    torch = torch_dev
+    from paper_1709_08681_amd import psc
+    obs, prob, s = cfg5_subset
+    print("case: cfg5 subset predict/gradient", flush=True)
+    assert psc.psc_get_degrid(s.handle) == psc.DEGRID_WINDOW
+    for variant in (psc.DEGRID_VALU, psc.DEGRID_MFMA):
+        with pytest.raises(psc.PscError) as ei:
+            psc.psc_set_degrid(s.handle, variant)
+        assert ei.value.status == -4
+    start = synth.perturbed_offsets(obs, 30.0, 22)
+    ref = oracle.predict(prob, start)
+    got = s.predict(start).cpu().numpy()
+    assert rel(got, ref) <= 1e-5
+    v = oracle.predict(prob, obs.offsets_true)
+    ref_acc, ref_vm = oracle.gradient(prob, start, v, 1.0, want_model=True)
+    w1 = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+    acc, vm = s.gradient(s.offsets(start), c64(torch, s, v), w1, want_model=True)
+    assert rel(vm.cpu().numpy(), ref_vm) <= 1e-5
+    acc = acc.cpu().numpy()
+    live = obs.int_row_ptr[1:] > obs.int_row_ptr[:-1]
+    for k in range(6):
+        assert rel(acc[live][..., k], ref_acc[live][..., k]) <= 1e-4, k
+
+
+def test_cfg5_subset_solve(torch_dev, cfg5_subset):
+    """Algorithm 1 on the support-32 workload: offsets within 0.1 arcsec of the
+    oracle's, iteration counts equal, plain and graph forms bit-identical."""
+    torch = torch_dev
+    from paper_1709_08681_amd import psc
+    obs, prob, s = cfg5_subset
+    print("case: cfg5 subset solve", flush=True)
+    v = oracle.predict(prob, obs.offsets_true)
+    start = synth.perturbed_offsets(obs, 30.0, 23)
+    ref_off, its_ref = oracle.solve(prob, v, 1.0, start, gain=0.5, n_max=5, tol_rad=1e-3 * ARCSEC)
+    w1 = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+    outs = []
+    for form in (psc.SOLVE_PLAIN, psc.SOLVE_GRAPH):
+        off = s.offsets(start)
+        its = s.solve(c64(torch, s, v), w1, off, gain=0.5, n_max=5, tol_rad=1e-3 * ARCSEC, form=form)
+        assert np.array_equal(its.cpu().numpy(), its_ref)
+        outs.append(off.cpu().numpy())
+        assert np.abs(outs[-1] - ref_off).max() / ARCSEC <= 0.1
+    assert np.array_equal(outs[0], outs[1])
