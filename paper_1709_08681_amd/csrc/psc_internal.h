@@ -106,11 +106,20 @@ hipError_t launch_finish_grid(const double2* in, float2* out, int n, int pad, hi
 hipError_t launch_airy_table(float4* tab, int n_tab, double dx, hipStream_t s);
 hipError_t launch_items(int mode, int support, const ItemArgs& a, hipStream_t s);
 // Window-form degrid (psc_window.hip), supports 16 and 32, 4 wavefronts per
-// block; win_lds_bytes is its dynamic LDS per block.
+// block.  win_lds_bytes is its dynamic LDS per block, win_lds_budget the most
+// it may use (160 KiB per compute unit less the kernel's static arrays).
+constexpr int kWinWaves = 4;
+// Work units of the window form per sample group, and the most units an item
+// can have: the groups pair offsets f and -f, so an item has at most
+// O^2/2 + 2 of them (the four self-paired offsets on their own).
+constexpr int kWinChunks = 4;
+__host__ __device__ inline int win_max_units(int oversample)
+{
+    return (oversample == 1 ? 1 : oversample * oversample / 2 + 2) * kWinChunks;
+}
 hipError_t launch_win(int mode, int support, const ItemArgs& a, hipStream_t s);
 size_t win_lds_bytes(int support, int mode, int waves, int m, int oversample);
-// dynamic LDS the window form may use: 160 KiB per CU less its static arrays
-constexpr size_t kWinLdsBudget = 160 * 1024 - 9 * 1024;
+size_t win_lds_budget(int support);
 hipError_t launch_reduce(int ncontrib, const ReduceArgs& a, hipStream_t s);
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
 hipError_t launch_init_state(int32_t* done, int32_t* iters, int n, hipStream_t s);

@@ -23,12 +23,16 @@
 namespace psc {
 
 // One block (W wavefronts) per item, as in the table form: the wavefronts
-// share the item's image-plane products in LDS and take its sample groups in
-// turn.  A wavefront handles 64/S samples of a group at a time, one per S-lane
-// slot: lane (slot, c) loads column c of the sample's reversed window, the
-// slot transforms it through a private S x (S+1) LDS tile (columns, then
-// rows), and lane c then sums over the image samples n whose m index is
-// congruent to c modulo S.
+// share the item's image-plane products in LDS.  Each S-lane slot of a
+// wavefront is an independent worker.  The item's work is cut into units of
+// kChunks per sample group (unit u: group u / kChunks, chunk u % kChunks of
+// its samples, both offsets f and -f counted), which the slots claim in turn
+// and whose samples they handle one at a time; groups of one or two samples
+// (fine oversampling, short intervals) and large groups both keep every slot
+// busy.  For a sample, lane c of the slot loads column c of the reversed
+// window, the slot transforms it through its own S x (S+1) LDS tile (columns,
+// then rows), and lane c then sums over the image samples n whose m index is
+// congruent to c modulo S.  Sums are kept per unit and added in unit order.
 template <int S, int MODE, int W>
 __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
 {
@@ -37,18 +41,20 @@ __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
     constexpr int SP = S + 1;
     constexpr int SPW = 64 / S;
     constexpr int kBlock = 64 * W;
+    static_assert(NC <= S, "one term per lane of a slot");
 
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ float2 twsh[S * 16];     // exp(+2 pi i t / (S O)), S O <= 16 S
-    __shared__ float2 phsh[W][128];     // per-wave phases: l axis at [0, M), m axis at [64, 64 + M)
+    __shared__ float2 twsh[S * 16];       // exp(+2 pi i t / (S O)), S O <= 16 S
+    constexpr int NW = W * SPW;            // workers (slots) per block
+    __shared__ float2 phsh[128][NW];       // slot w's l-axis phases at [0, M)[w], m axis at [64, 64 + M)[w]
     __shared__ int next_group;
 
     const int m = a.m, half_m = m >> 1;
     const int m2p = (m * m + 3) & ~3;
     // dynamic LDS: per-group float64 sums | image-plane products | window tiles
-    double* gpart = reinterpret_cast<double*>(smem);
-    const int O2 = a.oversample * a.oversample;
-    float* gsh = reinterpret_cast<float*>(smem + sizeof(double) * (NC > 0 ? NC : 1) * O2);
+    constexpr int kChunks = kWinChunks;
+    double* gpart = reinterpret_cast<double*>(smem);  // [unit][NC]
+    float* gsh = reinterpret_cast<float*>(smem + sizeof(double) * (NC > 0 ? NC : 1) * win_max_units(a.oversample));
     float2* wtile = reinterpret_cast<float2*>(reinterpret_cast<unsigned char*>(gsh) + sizeof(float) * NV * m2p);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -71,139 +77,159 @@ __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
 
     const int slot = lane / S;
     const int c = lane - slot * S;
-    float2* wt = wtile + ((size_t)wave * SPW + slot) * S * SP;  // this slot's tile
-    float2* phw = phsh[wave];
+    const int worker = wave * SPW + slot;
+    float2* wt = wtile + (size_t)worker * S * SP;  // this slot's tile
+    float2* ph = &phsh[0][worker];  // phase j of this slot at ph[j * NW]
     const TermSel tsel(c);
+    const float2 zero = make_float2(0.f, 0.f);
     // the two image-sample m indices congruent to c modulo S: c and c - S
     const bool m0_ok = c < half_m, m1_ok = c >= S - half_m;
     const int jm0 = m0_ok ? c + half_m : 0;
     const int jm1 = m1_ok ? c - S + half_m : 0;
+    float2 pm0 = zero, pm1 = zero;
+
+    // per-axis phases (-1)^n exp(2 pi i f n / (S O)) / S, n in [-M/2, M/2), of
+    // the group's offset f (part 0) or of -f (part 1), written by the slot
+    auto set_phases = [&](int f, int part) {
+        int fl = f / O, fm = f - (f / O) * O;
+        if (part) {
+            fl = (O - fl) & (O - 1);
+            fm = (O - fm) & (O - 1);
+        }
+        wave_sync();  // earlier readers of this slot's phases are done
+        for (int j = c; j < m; j += S) {
+            const int n = j - half_m;
+            const float sg = (n & 1) ? -inv_s : inv_s;
+            const float2 pl = twsh[(fl * n) & (so - 1)];
+            const float2 pm = twsh[(fm * n) & (so - 1)];
+            ph[j * NW] = make_float2(pl.x * sg, pl.y * sg);
+            ph[(64 + j) * NW] = make_float2(pm.x * sg, pm.y * sg);
+        }
+        wave_sync();
+        pm0 = m0_ok ? ph[(64 + jm0) * NW] : zero;
+        pm1 = m1_ok ? ph[(64 + jm1) * NW] : zero;
+    };
 
     for (int pol = 0; pol < a.n_pol; ++pol) {
-        if (tid == 0) next_group = it.grp_begin + W;
+        if (tid == 0) next_group = NW;
         image_products<MODE>(a, it, pol, gsh, m2p, tid, kBlock);
         __syncthreads();
 
+        const int n_units = (it.grp_end - it.grp_begin) * kChunks;
         double acc64 = 0.0;
-        int gi = it.grp_begin + wave;
-        Group g = a.groups[gi < it.grp_end ? gi : it.grp_begin];
-        while (gi < it.grp_end) {
-            int nxt_g = 0;
-            if (lane == 0) nxt_g = atomicAdd(&next_group, 1);
-            nxt_g = __shfl(nxt_g, 0);
-            const Group gnext = a.groups[nxt_g < it.grp_end ? nxt_g : gi];
-
-            // the group's samples at offset f, then those at -f
-            for (int part = 0; part < 2; ++part) {
-                const int nv = part ? g.n_vis2 : g.n_vis;
-                if (nv <= 0) continue;
-                const uint32_t vb = g.vis_begin + (part ? (uint32_t)g.n_vis : 0u);
-                int fl = g.f / O, fm = g.f - (g.f / O) * O;
-                if (part) {
-                    fl = (O - fl) & (O - 1);
-                    fm = (O - fm) & (O - 1);
+        // claim units until one has samples; v in [v, v_end) of group g, part
+        // = whether the current sample is at -f
+        int u = -1, v = 0, v_end = 0, part = 0;
+        Group g;
+        bool active = true;
+        auto next_unit = [&]() {
+            while (true) {
+                if (u >= 0) {  // close the finished (or empty) unit, claim the next
+                    if (NC > 0 && c < NC) gpart[u * NC + c] = acc64;
+                    acc64 = 0.0;
+                    int nx = 0;
+                    if (c == 0) nx = atomicAdd(&next_group, 1);
+                    u = __shfl(nx, slot * S);
+                } else {
+                    u = worker;  // units 0 .. NW-1 go to the slots in order
                 }
-                // ---- per-axis phases (-1)^n exp(2 pi i f n / (S O)) / S, n in [-M/2, M/2)
-                wave_sync();  // the previous pass has finished reading phw
-                if (lane < m) {
-                    const int n = lane - half_m;
-                    const float sg = (n & 1) ? -inv_s : inv_s;
-                    const float2 pl = twsh[(fl * n) & (so - 1)];
-                    const float2 pm = twsh[(fm * n) & (so - 1)];
-                    phw[lane] = make_float2(pl.x * sg, pl.y * sg);
-                    phw[64 + lane] = make_float2(pm.x * sg, pm.y * sg);
+                if (u >= n_units) {
+                    active = false;
+                    return;
                 }
+                g = a.groups[it.grp_begin + u / kChunks];
+                const int total = g.n_vis + g.n_vis2;
+                const int len = (total + kChunks - 1) / kChunks;
+                v = (u % kChunks) * len;
+                v_end = min(total, v + len);
+                if (v < v_end) break;
+            }
+            part = v >= g.n_vis;
+            set_phases(g.f, part);
+        };
+        next_unit();
+        while (__any(active)) {
+            if (active) {
+                const uint32_t vb = g.vis_begin;
+                const VisEnt e = a.vis[vb + v];
+                const size_t o = (size_t)e.vidx * a.n_pol + pol;
+                float2 vin = zero;
+                float wgt = 0.f;
+                if (MODE != kPredict) vin = a.vis_in[o];
+                if (MODE == kGrad) wgt = a.weight[o];
+                // ---- reversed window column c: x[i] = V^{M0}[k_lo_l + S-1-i][k_lo_m + S-1-c]
+                const int row0 = (int)(e.klo >> 16);
+                const int col0 = (int)(e.klo & 0xffffu);
+                const int voff = (row0 * P + col0 + (S - 1 - c)) * (int)sizeof(float2);
+                float2 x[S];
+#pragma unroll
+                for (int i = 0; i < S; ++i)
+                    x[i] = __builtin_bit_cast(
+                        float2, __builtin_amdgcn_raw_buffer_load_b64(grsrc, voff, (S - 1 - i) * rowbytes, 0));
+                // ---- 2-D DFT of the window: along l in registers, then along m
+                fft_reg<S>(x);
+                wave_sync();  // the previous sample's tile has been read
+#pragma unroll
+                for (int i = 0; i < S; ++i) wt[i * SP + c] = x[i];
                 wave_sync();
-                const float2 zero = make_float2(0.f, 0.f);
-                const float2 pm0 = m0_ok ? phw[64 + jm0] : zero;
-                const float2 pm1 = m1_ok ? phw[64 + jm1] : zero;
+#pragma unroll
+                for (int i = 0; i < S; ++i) x[i] = wt[c * SP + i];
+                fft_reg<S>(x);
+#pragma unroll
+                for (int i = 0; i < S; ++i) wt[c * SP + i] = x[i];
+                wave_sync();
 
-                for (int v0 = 0; v0 < nv; v0 += SPW) {
-                    const int v = v0 + slot;
-                    const bool valid = v < nv;
-                    const VisEnt e = a.vis[vb + (valid ? v : nv - 1)];
-                    const size_t o = (size_t)e.vidx * a.n_pol + pol;
-                    float2 vin = zero;
-                    float wgt = 0.f;
-                    if (MODE != kPredict) vin = a.vis_in[o];
-                    if (MODE == kGrad) wgt = a.weight[o];
-                    // ---- reversed window column c: x[i] = V^{M0}[k_lo_l + S-1-i][k_lo_m + S-1-c]
-                    const int row0 = (int)(e.klo >> 16);
-                    const int col0 = (int)(e.klo & 0xffffu);
-                    const int voff = (row0 * P + col0 + (S - 1 - c)) * (int)sizeof(float2);
-                    float2 x[S];
+                // ---- V_k = sum_n g_k[n] phi_l(n_l) phi_m(n_m) What[n_l mod S][n_m mod S]
+                float2 s[NV];
 #pragma unroll
-                    for (int i = 0; i < S; ++i)
-                        x[i] = __builtin_bit_cast(
-                            float2, __builtin_amdgcn_raw_buffer_load_b64(grsrc, voff, (S - 1 - i) * rowbytes, 0));
-                    // ---- 2-D DFT of the window: along l in registers, then along m
-                    fft_reg<S>(x);
-                    wave_sync();  // the previous sample's tile has been read
-#pragma unroll
-                    for (int i = 0; i < S; ++i) wt[i * SP + c] = x[i];
-                    wave_sync();
-#pragma unroll
-                    for (int i = 0; i < S; ++i) x[i] = wt[c * SP + i];
-                    fft_reg<S>(x);
-#pragma unroll
-                    for (int i = 0; i < S; ++i) wt[c * SP + i] = x[i];
-                    wave_sync();
-
-                    // ---- V_k = sum_n g_k[n] phi_l(n_l) phi_m(n_m) What[n_l mod S][n_m mod S]
-                    float2 s[NV];
-#pragma unroll
-                    for (int k = 0; k < NV; ++k) s[k] = zero;
-                    for (int jl = 0; jl < m; ++jl) {
-                        const int bl = (jl - half_m) & (S - 1);
-                        const float2 t = cmul(phw[jl], wt[bl * SP + c]);
-                        const float2 z0 = cmul(t, pm0), z1 = cmul(t, pm1);
-                        const float* gr = gsh + jl * m;
-#pragma unroll
-                        for (int k = 0; k < NV; ++k) {
-                            const float g0 = gr[k * m2p + jm0], g1 = gr[k * m2p + jm1];
-                            s[k].x = fmaf(g0, z0.x, fmaf(g1, z1.x, s[k].x));
-                            s[k].y = fmaf(g0, z0.y, fmaf(g1, z1.y, s[k].y));
-                        }
-                    }
-                    // sum over the slot's S lanes
+                for (int k = 0; k < NV; ++k) s[k] = zero;
+#pragma unroll 4
+                for (int jl = 0; jl < m; ++jl) {
+                    const int bl = (jl - half_m) & (S - 1);
+                    const float2 t = cmul(ph[jl * NW], wt[bl * SP + c]);
+                    const float2 z0 = cmul(t, pm0), z1 = cmul(t, pm1);
+                    const float* gr = gsh + jl * m;
 #pragma unroll
                     for (int k = 0; k < NV; ++k) {
-                        s[k].x = row16_sum(s[k].x);
-                        s[k].y = row16_sum(s[k].y);
-                        if constexpr (S == 32) {
-                            s[k].x += __shfl_xor(s[k].x, 16);
-                            s[k].y += __shfl_xor(s[k].y, 16);
-                        }
-                    }
-                    if (valid) {
-                        if (MODE == kPredict) {
-                            if (c == 0) a.vis_out[o] = s[0];
-                        } else if (MODE == kGrad) {
-                            if (a.vis_out != nullptr && c == 0) a.vis_out[o] = s[0];
-                            grad_term(tsel, s, vin, wgt, acc64);
-                        } else {
-                            vjp_term(c, s, vin, acc64);
-                        }
+                        const float g0 = gr[k * m2p + jm0], g1 = gr[k * m2p + jm1];
+                        s[k].x = fmaf(g0, z0.x, fmaf(g1, z1.x, s[k].x));
+                        s[k].y = fmaf(g0, z0.y, fmaf(g1, z1.y, s[k].y));
                     }
                 }
-            }
-            if (NC > 0) {
-                // the group's own sums, kept per group so that the item total
-                // does not depend on which wavefront took the group
+                // sum over the slot's S lanes
 #pragma unroll
-                for (int off = S; off < 64; off <<= 1) acc64 += __shfl_xor(acc64, off);
-                if (lane < NC) gpart[(gi - it.grp_begin) * NC + lane] = acc64;
-                acc64 = 0.0;
+                for (int k = 0; k < NV; ++k) {
+                    s[k].x = row16_sum(s[k].x);
+                    s[k].y = row16_sum(s[k].y);
+                    if constexpr (S == 32) {
+                        s[k].x += __shfl_xor(s[k].x, 16);
+                        s[k].y += __shfl_xor(s[k].y, 16);
+                    }
+                }
+                if (MODE == kPredict) {
+                    if (c == 0) a.vis_out[o] = s[0];
+                } else if (MODE == kGrad) {
+                    if (a.vis_out != nullptr && c == 0) a.vis_out[o] = s[0];
+                    grad_term(tsel, s, vin, wgt, acc64);
+                } else {
+                    vjp_term(c, s, vin, acc64);
+                }
+
+                // ---- next sample: same part, the partner part, or the next unit
+                if (++v == v_end) {
+                    next_unit();
+                } else if (part == 0 && v == g.n_vis) {
+                    part = 1;
+                    set_phases(g.f, 1);
+                }
             }
-            gi = nxt_g;
-            g = gnext;
         }
 
-        // ---- per-item partial sums: groups added in group order
+        // ---- per-item partial sums: units added in unit order
         __syncthreads();
         if (NC > 0 && tid < NC) {
             double sum = 0.0;
-            for (int gg = 0; gg < it.grp_end - it.grp_begin; ++gg) sum += gpart[gg * NC + tid];
+            for (int uu = 0; uu < n_units; ++uu) sum += gpart[uu * NC + tid];
             a.partials[((size_t)item_idx * a.n_pol + pol) * NC + tid] = sum;
         }
         __syncthreads();
@@ -214,10 +240,10 @@ template <int S, int MODE, int W>
 static hipError_t launch_win_t(const ItemArgs& a, hipStream_t s)
 {
     const size_t sh = win_lds_bytes(S, MODE, W, a.m, a.oversample);
-    if (sh > kWinLdsBudget) return hipErrorInvalidValue;
+    if (sh > win_lds_budget(S)) return hipErrorInvalidValue;
     // raise the dynamic LDS limit once, to the largest size a valid setting needs
     static const hipError_t attr = [] {
-        const size_t shmax = std::min(win_lds_bytes(S, MODE, W, 2 * S, 16), kWinLdsBudget);
+        const size_t shmax = std::min(win_lds_bytes(S, MODE, W, 2 * S, 16), win_lds_budget(S));
         return hipFuncSetAttribute((const void*)k_win<S, MODE, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)shmax);
     }();
@@ -232,8 +258,15 @@ size_t win_lds_bytes(int support, int mode, int waves, int m, int oversample)
     const int nv = (mode == kPredict) ? 1 : (mode == kGrad) ? 5 : 4;
     const int nc = (mode == kGrad) ? 12 : (mode == kVjp) ? 4 : 1;
     const int m2p = (m * m + 3) & ~3;
-    return sizeof(double) * nc * oversample * oversample + sizeof(float) * nv * m2p +
+    return sizeof(double) * nc * win_max_units(oversample) + sizeof(float) * nv * m2p +
            sizeof(float2) * (size_t)waves * 64 * (support + 1);
+}
+
+size_t win_lds_budget(int support)
+{
+    // static LDS of k_win: twiddles, per-slot phases, the group counter
+    const size_t stat = sizeof(float2) * support * 16 + sizeof(float2) * kWinWaves * (64 / support) * 128 + 16;
+    return 160 * 1024 - stat;
 }
 
 hipError_t launch_win(int mode, int support, const ItemArgs& a, hipStream_t s)
@@ -241,17 +274,17 @@ hipError_t launch_win(int mode, int support, const ItemArgs& a, hipStream_t s)
     if (a.n_items <= 0) return hipSuccess;
     if (support == 16) {
         switch (mode) {
-        case kPredict: return launch_win_t<16, kPredict, 4>(a, s);
-        case kGrad: return launch_win_t<16, kGrad, 4>(a, s);
-        case kVjp: return launch_win_t<16, kVjp, 4>(a, s);
+        case kPredict: return launch_win_t<16, kPredict, kWinWaves>(a, s);
+        case kGrad: return launch_win_t<16, kGrad, kWinWaves>(a, s);
+        case kVjp: return launch_win_t<16, kVjp, kWinWaves>(a, s);
         default: return hipErrorInvalidValue;
         }
     }
     if (support == 32) {
         switch (mode) {
-        case kPredict: return launch_win_t<32, kPredict, 4>(a, s);
-        case kGrad: return launch_win_t<32, kGrad, 4>(a, s);
-        case kVjp: return launch_win_t<32, kVjp, 4>(a, s);
+        case kPredict: return launch_win_t<32, kPredict, kWinWaves>(a, s);
+        case kGrad: return launch_win_t<32, kGrad, kWinWaves>(a, s);
+        case kVjp: return launch_win_t<32, kVjp, kWinWaves>(a, s);
         default: return hipErrorInvalidValue;
         }
     }
