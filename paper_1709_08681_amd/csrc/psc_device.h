@@ -163,12 +163,15 @@ __device__ __forceinline__ void efp(const ItemArgs& a, float kk, float inv_s2, f
 
 // Image-plane products E_i E_j c at the M x M samples (spacing FoV/S, centred)
 // for one item and polarisation, and for the gradient and adjoint the offset
-// derivatives dE_i/dp_i E_j c and E_i dE_j/dp_j c (Eq. DA).  Variant k goes to
-// gsh[k * m2p + n]; threads tid, tid + nthr, ... of the block share the work.
-template <int MODE>
+// derivatives dE_i/dp_i E_j c and E_i dE_j/dp_j c (Eq. DA).  Variant k of
+// sample n goes to gsh[k * m2p + n] (variant-major) or, with INTERLEAVED, to
+// gsh[n * NV + k]; threads tid, tid + nthr, ... of the block share the work.
+template <int MODE, bool INTERLEAVED = false>
 __device__ __forceinline__ void image_products(const ItemArgs& a, const Item& it, int pol, float* gsh,
                                                int m2p, int tid, int nthr)
 {
+    constexpr int NV = (MODE == kPredict) ? 1 : (MODE == kGrad) ? 5 : 4;
+    const int ks = INTERLEAVED ? 1 : m2p;  // stride between variants
     const int m = a.m, half_m = m >> 1, m2 = m * m;
     const double lam = kCLight / a.freq[it.chan];
     const float kk = (float)(kPi * a.dish / lam);
@@ -189,15 +192,16 @@ __device__ __forceinline__ void image_products(const ItemArgs& a, const Item& it
         efp(a, kk, inv_s2, l - pil, mm - pim, ei, eil, eim);
         efp(a, kk, inv_s2, l - pjl, mm - pjm, ej, ejl, ejm);
         const float c = a.taper_img[il] * a.taper_img[im];
+        float* gn = gsh + (INTERLEAVED ? idx * NV : idx);
         if (MODE == kPredict) {
-            gsh[idx] = ei * ej * c;
+            gn[0] = ei * ej * c;
         } else {
             constexpr int o = (MODE == kGrad) ? 1 : 0;
-            if (MODE == kGrad) gsh[idx] = ei * ej * c;
-            gsh[(o + 0) * m2p + idx] = eil * ej * c;
-            gsh[(o + 1) * m2p + idx] = eim * ej * c;
-            gsh[(o + 2) * m2p + idx] = ei * ejl * c;
-            gsh[(o + 3) * m2p + idx] = ei * ejm * c;
+            if (MODE == kGrad) gn[0] = ei * ej * c;
+            gn[(o + 0) * ks] = eil * ej * c;
+            gn[(o + 1) * ks] = eim * ej * c;
+            gn[(o + 2) * ks] = ei * ejl * c;
+            gn[(o + 3) * ks] = ei * ejm * c;
         }
     }
 }

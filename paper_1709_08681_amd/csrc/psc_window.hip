@@ -42,6 +42,11 @@ __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
     constexpr int SPW = 64 / S;
     constexpr int kBlock = 64 * W;
     static_assert(NC <= S, "one term per lane of a slot");
+    // image-plane products variant-interleaved ([n][NV], one base address per
+    // sample and immediate offsets) at support 32, variant-major at 16: the
+    // faster layout of each when measured on the large and single-interval
+    // workloads
+    constexpr bool kInterleave = (S == 32);
 
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ float2 twsh[S * 16];       // exp(+2 pi i t / (S O)), S O <= 16 S
@@ -51,7 +56,7 @@ __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
 
     const int m = a.m, half_m = m >> 1;
     const int m2p = (m * m + 3) & ~3;
-    // dynamic LDS: per-group float64 sums | image-plane products | window tiles
+    // dynamic LDS: per-unit float64 sums | image-plane products | window tiles
     constexpr int kChunks = kWinChunks;
     double* gpart = reinterpret_cast<double*>(smem);  // [unit][NC]
     float* gsh = reinterpret_cast<float*>(smem + sizeof(double) * (NC > 0 ? NC : 1) * win_max_units(a.oversample));
@@ -112,7 +117,7 @@ __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
 
     for (int pol = 0; pol < a.n_pol; ++pol) {
         if (tid == 0) next_group = NW;
-        image_products<MODE>(a, it, pol, gsh, m2p, tid, kBlock);
+        image_products<MODE, kInterleave>(a, it, pol, gsh, m2p, tid, kBlock);
         __syncthreads();
 
         const int n_units = (it.grp_end - it.grp_begin) * kChunks;
@@ -188,10 +193,13 @@ __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
                     const int bl = (jl - half_m) & (S - 1);
                     const float2 t = cmul(ph[jl * NW], wt[bl * SP + c]);
                     const float2 z0 = cmul(t, pm0), z1 = cmul(t, pm1);
-                    const float* gr = gsh + jl * m;
+                    // variant k of samples (jl, jm0) and (jl, jm1)
+                    const float* g0p = gsh + (kInterleave ? (jl * m + jm0) * NV : jl * m + jm0);
+                    const float* g1p = gsh + (kInterleave ? (jl * m + jm1) * NV : jl * m + jm1);
+                    const int ks = kInterleave ? 1 : m2p;
 #pragma unroll
                     for (int k = 0; k < NV; ++k) {
-                        const float g0 = gr[k * m2p + jm0], g1 = gr[k * m2p + jm1];
+                        const float g0 = g0p[k * ks], g1 = g1p[k * ks];
                         s[k].x = fmaf(g0, z0.x, fmaf(g1, z1.x, s[k].x));
                         s[k].y = fmaf(g0, z0.y, fmaf(g1, z1.y, s[k].y));
                     }
