@@ -25,15 +25,27 @@ FP32_VECTOR_PEAK = 157.3e12  # MI355X published FP32 vector rate (FLOP/s)
 HBM_PEAK = 8.0e12
 
 
+KERNEL_SOURCES = ("psc_kernels.hip", "psc_device.h", "psc_internal.h")
+
+
+def kernel_source_hash():
+    """sha256 (first 16 hex digits) over the sources the table-form kernel is
+    built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1709_08681_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic():
     """HBM bytes per launch of the gradient kernel from the committed rocprofv3
-    summary, or None when the kernel source has changed since it was taken."""
-    import hashlib
+    summary, or None when the kernel sources have changed since it was taken."""
     import re
-    src = os.path.join(ROOT, "paper_1709_08681_amd", "csrc", "psc_kernels.hip")
     prof = os.path.join(ROOT, "profiles", "k_item_grad_single_interval.md")
     try:
-        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        h = kernel_source_hash()
         txt = open(prof).read()
     except OSError:
         return None
@@ -101,7 +113,17 @@ def batched_vs_plain(cfg, iters, device=0):
 
 
 def cpu_baseline(obs, start, seconds):
+    """The oracle (FP64 direct sum) on the host cores: gradient + update
+    iterations for about `seconds`, over the whole workload or, when one
+    iteration would take far longer, over its first timesteps."""
+    import numpy as np
     import oracle
+    n_src = len(obs.src_flux) + (0 if obs.extra_flux is None else len(obs.extra_flux))
+    budget = 5e8  # visibility x pixel terms, about 10 s of the oracle on 16 cores
+    if obs.n_vis * n_src > budget:
+        per_t = obs.n_vis / max(1, len(np.unique(obs.time_idx)))
+        n_t = max(1, int(budget / (per_t * n_src)))
+        obs = obs.subset(times=range(n_t))  # offsets keep their shape
     prob = oracle.Problem.from_observation(obs)
     v_obs_np = oracle.predict(prob, obs.offsets_true)  # untimed: the oracle's own data
     off = start.copy()
@@ -119,7 +141,8 @@ def cpu_baseline(obs, start, seconds):
         "unit": "vis/s",
         "cores": int(oracle.num_threads()),
         "kind": "oracle",
-        "sample": f"full workload ({obs.n_vis} visibilities x {len(prob.src_flux)} sky pixels), "
+        "sample": f"{obs.n_vis} visibilities x {len(prob.src_flux)} sky pixels "
+                  f"({'whole workload' if obs.n_vis * n_src <= budget else 'first timesteps'}), "
                   f"{iters} gradient+update iteration(s) in {dt:.1f} s, FP64 direct summation",
     }
 
@@ -130,6 +153,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--channels", type=int, default=0,
+                    help="keep the first N channels: one GPU's channel share of a larger workload")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-config", type=int, default=3)
@@ -145,9 +170,12 @@ def main():
     import numpy as np
     import torch
     from paper_1709_08681_amd import synth
+    from paper_1709_08681_amd import psc as P
     from paper_1709_08681_amd.psc import Session, psc_gradient, psc_solve_step
 
     obs = synth.make_config(args.config)
+    if args.channels:
+        obs = obs.subset(chans=range(args.channels))
     print(f"bench: workload {obs.wl.name}, {obs.n_vis} visibilities", file=sys.stderr, flush=True)
     s = Session(obs, device=0)
     stream = torch.cuda.current_stream()
@@ -158,6 +186,13 @@ def main():
     off = s.offsets(start)
     acc = torch.empty(s.off_shape[:3] + (6,), dtype=torch.float64, device=s.dev)
     mx = torch.empty(obs.n_int, dtype=torch.float64, device=s.dev)
+    # the autotuner times every degrid variant on this data and keeps the fastest
+    tune_us = P.psc_tune(s.ctx, s.handle, off, v_obs, w, 3, stream)
+    variant = P.psc_get_degrid(s.handle)
+    S = obs.wl.support
+    kernel = {P.DEGRID_VALU: f"k_item<{S},grad> (table form, vector FP32)",
+              P.DEGRID_MFMA: f"k_item<{S},grad> (table form, FP32 matrix cores)",
+              P.DEGRID_WINDOW: f"k_win<{S},grad> (window form)"}[variant]
 
     def step(ev=None):
         if ev is not None:
@@ -185,7 +220,6 @@ def main():
     grad_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
     value = obs.n_vis / (ms_step * 1e-3)
 
-    S = obs.wl.support
     flops = obs.n_vis * 40.0 * S * S  # five complex multiply-adds per tap
     achieved = flops / (grad_ms * 1e-3)
     roof = {
@@ -194,9 +228,9 @@ def main():
         "peak": FP32_VECTOR_PEAK / 1e12,
         "unit": "TFLOP/s",
         "frac": achieved / FP32_VECTOR_PEAK,
-        "traffic": measured_traffic() if args.config == 2 else None,
+        "traffic": measured_traffic() if (args.config == 2 and variant == P.DEGRID_VALU) else None,
         "traffic_unit": "bytes per launch (FETCH_SIZE x2 + WRITE_SIZE, copy-calibrated)",
-        "kernel": "k_item<16,grad> (+ k_reduce)",
+        "kernel": kernel + " + k_reduce",
         "launch_ms": grad_ms,
     }
     out = {
@@ -210,9 +244,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (f64 accumulation)",
+        "dtype": "f32",
+        "accumulate_dtype": "f64",
         "data": "synthetic",
-        "config": describe(obs),
+        "config": dict(describe(obs), degrid=kernel,
+                       tune_us={name: t for name, t in zip(("vector", "matrix_core", "window"), tune_us)}),
         "roofline": roof,
     }
     s.close()
