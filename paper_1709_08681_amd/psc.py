@@ -19,6 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpsc.so")
 
 PSC_OK = 0
+PSC_E_ARG, PSC_E_HIP, PSC_E_OOM, PSC_E_UNSUPPORTED, PSC_E_STATE = -1, -2, -3, -4, -5
 STATUS = {0: "PSC_OK", -1: "PSC_E_ARG", -2: "PSC_E_HIP", -3: "PSC_E_OOM", -4: "PSC_E_UNSUPPORTED",
           -5: "PSC_E_STATE"}
 SOLVE_PLAIN, SOLVE_BATCHED, SOLVE_GRAPH = 0, 1, 2
