@@ -113,12 +113,12 @@ __global__ void k_airy_table(float4* __restrict__ tab, int n_tab, double dx)
 }
 
 // ---------------------------------------------------------------------------
-// Fused kernel build + degrid + per-item float64 partial sums.
+// Fused kernel build + degrid + per-item float64 partial sums (table form).
 // One block (4 wavefronts) per item; the wavefronts share the image-plane
 // products and take the item's sub-table groups in turn.  Inside a group, a
-// wavefront holds the S x S sub-table column by column in registers (lane
-// a_m of each S-lane slot keeps column a_m), and degrids 64/S samples at a
-// time, each slot reading one S x S window of V^{M0}.
+// wavefront builds the five S x S sub-tables in its own LDS buffer and
+// degrids SPL * 64/S samples at a time: lane a_m of each S-lane slot reads
+// column a_m of its samples' S x S windows of V^{M0} and of the sub-tables.
 // ---------------------------------------------------------------------------
 // LDS holds two blocks per CU, i.e. two wavefronts per SIMD; telling the
 // compiler so lets it keep every window load of an iteration in flight.
