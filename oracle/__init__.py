@@ -76,9 +76,11 @@ def _load():
             lib.oracle_snap_uv.argtypes = [P, C.c_int64, C.c_int, dp]
             lib.oracle_predict.argtypes = [P, dp, dp, dp]
             lib.oracle_gradient.argtypes = [P, dp, dp, dp, dp, dp]
+            lib.oracle_image_gradient.argtypes = [P, dp, dp, dp, C.c_int, dp, dp, dp]
             lib.oracle_solve_step.argtypes = [C.c_int, C.c_int, C.c_int, dp, C.c_double, dp, ip, dp, ip]
             lib.oracle_solve.argtypes = [P, dp, dp, dp, C.c_double, C.c_int, C.c_double, ip]
-            for name in ("oracle_predict", "oracle_gradient", "oracle_solve_step", "oracle_solve",
+            for name in ("oracle_predict", "oracle_gradient", "oracle_image_gradient",
+                         "oracle_solve_step", "oracle_solve",
                          "oracle_num_threads"):
                 getattr(lib, name).restype = C.c_int
             _lib = lib
@@ -202,6 +204,23 @@ def gradient(prob: Problem, offsets, vis_obs, weight, want_model=False):
     if want_model:
         return acc, vm[..., 0] + 1j * vm[..., 1]
     return acc
+
+
+def image_gradient(prob: Problem, offsets, vis_obs, weight, pix_l, pix_m):
+    """d chi^2 / d I at the sky positions (pix_l[k], pix_m[k]) (direction
+    cosines): minus twice the weighted residual seen through both offset
+    beams, summed over every visibility."""
+    lib = _load()
+    o = _offs(prob, offsets)
+    vo = np.ascontiguousarray(np.broadcast_to(vis_obs, prob.vis_shape()), np.complex128)
+    vo2 = np.ascontiguousarray(vo.view(np.float64))
+    w = np.ascontiguousarray(np.broadcast_to(weight, prob.vis_shape()), np.float64)
+    pl = np.ascontiguousarray(pix_l, np.float64).reshape(-1)
+    pm = np.ascontiguousarray(pix_m, np.float64).reshape(-1)
+    out = np.zeros(pl.shape[0])
+    _check(lib.oracle_image_gradient(prob.ref, _dp(o), _dp(vo2), _dp(w), int(pl.shape[0]), _dp(pl),
+                                     _dp(pm), _dp(out)), "image_gradient")
+    return out
 
 
 def solve_step(acc, gain, offsets, done=None):

@@ -23,6 +23,9 @@
  *    of each end of the baseline (Eq. DA with a = (l_i, m_i)), and the
  *    per-antenna sums of Eq. DCHIDD together with chi^2 (Eq. Chisq) and the
  *    2x2 Gauss-Newton normal matrix.
+ *  - image gradient: the derivative of chi^2 with respect to the flux of
+ *    chosen sky pixels, the residual image seen through both offset beams,
+ *    which drives the model update of the self-calibration loop (Sec. 2).
  *  - solve step: the damped update of Sec. 2.2 (a_n = a_{n-1} + f(grad)),
  *    read as a per-antenna 2x2 Gauss-Newton step scaled by the loop gain
  *    0 < gamma < 1 of Eq. SelfCal.
@@ -317,6 +320,76 @@ int oracle_gradient(const orc_problem* p, const double* offsets, const double* v
     }
     free(part);
     return 0;
+}
+
+/*
+ * d chi^2 / d I at each of n_pix sky positions (pix_l[k], pix_m[k]):
+ *   out[k] = -2 sum w Re( conj(R) E_i(l_k - p_i) E_j(l_k - p_j) exp(+2 pi i u.l_k) ),
+ * over every interval, row, channel and polarisation, R = V^Obs - V^M with
+ * V^M the direct sum of Eq. ME at the given offsets.  Each term is the
+ * derivative of one visibility with respect to one pixel's flux, so out is
+ * exact for pixels on or off the model's support.
+ */
+int oracle_image_gradient(const orc_problem* p, const double* offsets, const double* vis_obs,
+                          const double* weight, int n_pix, const double* pix_l, const double* pix_m,
+                          double* out)
+{
+    if (check_problem(p) || n_pix < 0) return -1;
+    size_t n_vis = (size_t)p->n_row * p->n_chan * p->n_pol;
+    double* vm = (double*)malloc((n_vis ? n_vis : 1) * 2 * sizeof(double));
+    double* ones = (double*)malloc((n_pix ? n_pix : 1) * sizeof(double));
+    if (!vm || !ones) {
+        free(vm);
+        free(ones);
+        return -2;
+    }
+    int rc = oracle_predict(p, offsets, vm, NULL);
+    for (int k = 0; k < n_pix; ++k) {
+        out[k] = 0.0;
+        ones[k] = 1.0;
+    }
+    /* the same problem with the requested pixels as its sky, for the beams */
+    orc_problem q = *p;
+    q.n_src = n_pix;
+    q.src_l = pix_l;
+    q.src_m = pix_m;
+    q.src_flux = ones;
+    for (int s = 0; s < p->n_int && rc == 0; ++s) {
+        int64_t r0 = p->int_row_ptr[s], r1 = p->int_row_ptr[s + 1];
+        if (r0 == r1) continue;
+        const double* offs_int = offsets + (size_t)s * p->n_pol * p->n_ant * 2;
+        double* tab = beam_table(&q, offs_int);
+        if (!tab) {
+            rc = -2;
+            break;
+        }
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int k = 0; k < n_pix; ++k) {
+            double acc = 0.0;
+            for (int64_t r = r0; r < r1; ++r) {
+                int ai = p->ant1[r], aj = p->ant2[r];
+                for (int c = 0; c < p->n_chan; ++c) {
+                    double u, v;
+                    row_uv(p, r, c, &u, &v);
+                    double ph = 2.0 * ORC_PI * (u * pix_l[k] + v * pix_m[k]);
+                    double cr = cos(ph), ci = sin(ph);
+                    for (int pol = 0; pol < p->n_pol; ++pol) {
+                        size_t idx = ((size_t)r * p->n_chan + c) * p->n_pol + pol;
+                        double ei = tab[3 * ((((size_t)pol * p->n_ant + ai) * p->n_chan + c) * n_pix + k)];
+                        double ej = tab[3 * ((((size_t)pol * p->n_ant + aj) * p->n_chan + c) * n_pix + k)];
+                        double rr = vis_obs[2 * idx] - vm[2 * idx];
+                        double ri = vis_obs[2 * idx + 1] - vm[2 * idx + 1];
+                        acc += weight[idx] * ei * ej * (rr * cr + ri * ci);
+                    }
+                }
+            }
+            out[k] += -2.0 * acc;
+        }
+        free(tab);
+    }
+    free(vm);
+    free(ones);
+    return rc;
 }
 
 /*

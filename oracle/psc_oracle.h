@@ -35,6 +35,9 @@ void oracle_snap_uv(const orc_problem* p, int64_t row, int chan, double* uv_out)
 int oracle_predict(const orc_problem* p, const double* offsets, double* vis_out, double* dvis_out);
 int oracle_gradient(const orc_problem* p, const double* offsets, const double* vis_obs,
                     const double* weight, double* acc, double* vis_model_out);
+int oracle_image_gradient(const orc_problem* p, const double* offsets, const double* vis_obs,
+                          const double* weight, int n_pix, const double* pix_l, const double* pix_m,
+                          double* out);
 int oracle_solve_step(int n_int, int n_pol, int n_ant, const double* acc, double gain,
                       double* offsets_io, int32_t* not_updated, double* max_step_out,
                       const int32_t* done);

@@ -345,3 +345,66 @@ def test_solver_noisy_recovery_within_expected_scatter(oracle_lib):
     z = np.array(z)
     assert np.sqrt(np.mean(z ** 2)) < 4.0, z
     assert np.abs(err).max() / ARCSEC < 20.0
+
+
+# --------------------------------------------------------------------------
+# Image gradient (the model-update direction of the self-calibration loop)
+# --------------------------------------------------------------------------
+
+def test_image_gradient_matches_chi2_differences(oracle_lib):
+    """d chi^2 / d I_p against central differences of chi^2 in the flux of
+    pixel p: for model pixels, and for empty pixels added to the sky with zero
+    flux.  chi^2 is quadratic in the fluxes, so central differences are exact
+    up to rounding.  Two pols with squint, two intervals."""
+    o = oracle_lib
+    rng = np.random.default_rng(21)
+    n_ant, n_time = 4, 3
+    i, j = np.triu_indices(n_ant, 1)
+    ant1, ant2 = np.tile(i, n_time), np.tile(j, n_time)
+    uv = rng.uniform(-2500.0, 2500.0, size=(ant1.size, 2))
+    src_l, src_m = rng.uniform(-0.01, 0.01, 5), rng.uniform(-0.01, 0.01, 5)
+    flux = rng.uniform(0.2, 1.5, 5)
+    # two empty pixels appended with zero flux
+    src_l = np.concatenate([src_l, [0.004, -0.007]])
+    src_m = np.concatenate([src_m, [-0.002, 0.006]])
+    flux = np.concatenate([flux, [0.0, 0.0]])
+    ptr = [0, 2 * 6, ant1.size]
+    freqs = [1.2e9, 1.7e9]
+
+    def prob_with(f):
+        return o.Problem(src_l, src_m, f, n_ant, ant1, ant2, uv, ptr, freqs, n_pol=2,
+                         squint_frac=0.03, snap_scale=0.0)
+
+    prob = prob_with(flux)
+    offs = rng.normal(0.0, 30 * ARCSEC, size=prob.offsets_shape())
+    truth = offs + rng.normal(0.0, 20 * ARCSEC, offs.shape)
+    vobs = o.predict(prob_with(flux * rng.uniform(0.8, 1.2, flux.size) + 0.05), truth)
+    w = rng.uniform(0.5, 2.0, size=vobs.shape)
+    g = o.image_gradient(prob, offs, vobs, w, src_l, src_m)
+
+    def chi2(f):
+        return float((w * np.abs(vobs - o.predict(prob_with(f), offs)) ** 2).sum())
+
+    h = 1e-3
+    for k in range(flux.size):
+        fp, fm = flux.copy(), flux.copy()
+        fp[k] += h
+        fm[k] -= h
+        fd = (chi2(fp) - chi2(fm)) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-8 * max(abs(fd), 1e-6), (k, fd, g[k])
+
+
+def test_image_gradient_vanishes_at_truth_and_is_linear_in_weight(oracle_lib):
+    """Noiseless data at the true offsets: the residual is zero, so is the
+    image gradient; with a residual, doubling every weight doubles it."""
+    o = oracle_lib
+    prob, offs = _tiny_problem(o, n_pol=1)
+    pl = np.array([0.0, 0.003, -0.008])
+    pm = np.array([0.0, -0.005, 0.002])
+    v = o.predict(prob, offs)
+    assert np.all(o.image_gradient(prob, offs, v, 1.0, pl, pm) == 0.0)
+    vobs = v + 0.1
+    g1 = o.image_gradient(prob, offs, vobs, 1.0, pl, pm)
+    g2 = o.image_gradient(prob, offs, vobs, 2.0, pl, pm)
+    assert np.all(g1 != 0.0)
+    np.testing.assert_allclose(g2, 2 * g1, rtol=1e-14)
