@@ -200,6 +200,30 @@ PSC_API psc_status psc_predict_vjp(psc_ctx* ctx, psc_obs* obs, const double* off
                                    void* stream);
 
 /*
+ * Gradient of chi^2 with respect to the model image (async): the direction of
+ * the model update that alternates with the antenna solve in the
+ * self-calibration loop (Sec. 2), i.e. the residual image seen through both
+ * offset beams of every baseline:
+ *   image_grad[n] = d chi^2 / d I[n]
+ *                 = -2 sum w Re( conj(R) E_i(l_n - p_i) E_j(l_n - p_j) exp(+2 pi i u.l_n) )
+ * with R = V^Obs - V^M at the given offsets.  Computed as the exact adjoint of
+ * this library's predict: w conj(R) is spread back over each sample's window
+ * with the kernel coefficients that produced V^M (float64 sums on a residual
+ * grid), transformed like the model (float64 FFT) and divided by the taper.
+ *  vis_obs_dev, weight_dev  as for psc_gradient
+ *  image_grad_out_dev [N][N] float64, indexed like the image of psc_set_model
+ *  vis_model_dev      nullable; receives V^M
+ * Table form at support 16 (PSC_E_UNSUPPORTED at 32).  The first call
+ * allocates the context's scratch: (N+S)^2 + 2 N^2 complex float64.  The
+ * residual grid is summed with float64 atomics, so results agree between runs
+ * to float64 rounding, not bit for bit.
+ */
+PSC_API psc_status psc_image_gradient(psc_ctx* ctx, psc_obs* obs, const double* offsets_dev,
+                                      const void* vis_obs_dev, const float* weight_dev,
+                                      double* image_grad_out_dev, void* vis_model_dev,
+                                      void* stream);
+
+/*
  * Damped per-antenna update (async), Sec. 2.2 (a_n = a_{n-1} + f(grad)) with
  * f read as a 2x2 Gauss-Newton step scaled by the loop gain 0 < gain <= 1 of
  * Eq. SelfCal:  p_a += gain * H_a^-1 g_a  when det H_a > 1e-12 (tr H_a)^2,

@@ -21,6 +21,10 @@ struct psc_ctx {
     double* taper_pix = nullptr;   // [N]
     float* taper_img = nullptr;    // [M]
     float2* tw = nullptr;          // [S*O]
+    // image-gradient scratch, allocated by its first call
+    double2* rgrid = nullptr;      // residual grid, (N+S) x (N+S)
+    double2* fa = nullptr;         // [N][N] transform work
+    double2* fb = nullptr;
     bool model_set = false;
     std::string err;
 };
@@ -248,6 +252,9 @@ PSC_API psc_status psc_destroy(psc_ctx* ctx)
     dfree(ctx->taper_pix);
     dfree(ctx->taper_img);
     dfree(ctx->tw);
+    dfree(ctx->rgrid);
+    dfree(ctx->fa);
+    dfree(ctx->fb);
     delete ctx;
     return PSC_OK;
 }
@@ -676,6 +683,49 @@ PSC_API psc_status psc_predict_vjp(psc_ctx* ctx, psc_obs* obs, const double* off
     a.vis_in = (const float2*)grad_vis_dev;
     PSC_HIP(ctx, launch_degrid(kVjp, ctx, obs, a, s));
     PSC_HIP(ctx, launch_reduce(4, reduce_args(obs, 0, obs->n_int, grad_offsets_out_dev, nullptr), s));
+    return PSC_OK;
+}
+
+PSC_API psc_status psc_image_gradient(psc_ctx* ctx, psc_obs* obs, const double* offsets_dev,
+                                      const void* vis_obs_dev, const float* weight_dev,
+                                      double* image_grad_out_dev, void* vis_model_dev, void* stream)
+{
+    psc_status st = check_call(ctx, obs, offsets_dev);
+    if (st != PSC_OK) return st;
+    if (!image_grad_out_dev || ((!vis_obs_dev || !weight_dev) && obs->n_vis > 0))
+        return fail(ctx, PSC_E_ARG, "null data or output");
+    if (ctx->s != 16) return fail(ctx, PSC_E_UNSUPPORTED, "the image gradient is built for support 16");
+    const int n = ctx->n;
+    const size_t np = (size_t)(n + ctx->s) * (n + ctx->s);
+    if (!ctx->rgrid) {
+        hipError_t e = dmalloc(&ctx->rgrid, np);
+        if (e == hipSuccess) e = dmalloc(&ctx->fa, (size_t)n * n);
+        if (e == hipSuccess) e = dmalloc(&ctx->fb, (size_t)n * n);
+        if (e != hipSuccess) {
+            dfree(ctx->rgrid);
+            dfree(ctx->fa);
+            dfree(ctx->fb);
+            ctx->rgrid = ctx->fa = ctx->fb = nullptr;
+            return fail(ctx, PSC_E_OOM, "image-gradient scratch");
+        }
+    }
+    int log2n = 0;
+    while ((1 << log2n) < n) ++log2n;
+    hipStream_t s = (hipStream_t)stream;
+    ItemArgs a = item_args(ctx, obs, offsets_dev, 0, (int)obs->n_items, nullptr);
+    a.vis_in = (const float2*)vis_obs_dev;
+    a.weight = weight_dev;
+    a.vis_out = (float2*)vis_model_dev;
+    a.grid_acc = ctx->rgrid;
+    a.use_mfma = 0;
+    PSC_HIP(ctx, launch_zero(ctx->rgrid, np, s));
+    PSC_HIP(ctx, launch_items(kGrid, ctx->s, a, s));
+    PSC_HIP(ctx, launch_unpad_grid(ctx->rgrid, ctx->fa, n, ctx->s, s));
+    PSC_HIP(ctx, launch_fft_rows(ctx->fa, n, log2n, s));
+    PSC_HIP(ctx, launch_transpose(ctx->fa, ctx->fb, n, s));
+    PSC_HIP(ctx, launch_fft_rows(ctx->fb, n, log2n, s));
+    PSC_HIP(ctx, launch_transpose(ctx->fb, ctx->fa, n, s));
+    PSC_HIP(ctx, launch_image_grad(ctx->fa, ctx->taper_pix, image_grad_out_dev, n, s));
     return PSC_OK;
 }
 

@@ -170,7 +170,7 @@ template <int MODE, bool INTERLEAVED = false>
 __device__ __forceinline__ void image_products(const ItemArgs& a, const Item& it, int pol, float* gsh,
                                                int m2p, int tid, int nthr)
 {
-    constexpr int NV = (MODE == kPredict) ? 1 : (MODE == kGrad) ? 5 : 4;
+    constexpr int NV = mode_nv(MODE);
     const int ks = INTERLEAVED ? 1 : m2p;  // stride between variants
     const int m = a.m, half_m = m >> 1, m2 = m * m;
     const double lam = kCLight / a.freq[it.chan];
@@ -193,7 +193,7 @@ __device__ __forceinline__ void image_products(const ItemArgs& a, const Item& it
         efp(a, kk, inv_s2, l - pjl, mm - pjm, ej, ejl, ejm);
         const float c = a.taper_img[il] * a.taper_img[im];
         float* gn = gsh + (INTERLEAVED ? idx * NV : idx);
-        if (MODE == kPredict) {
+        if (NV == 1) {
             gn[0] = ei * ej * c;
         } else {
             constexpr int o = (MODE == kGrad) ? 1 : 0;

@@ -39,7 +39,12 @@ struct VisEnt {
     uint32_t klo;
 };
 
-enum Mode { kPredict = 0, kGrad = 1, kVjp = 2 };
+enum Mode { kPredict = 0, kGrad = 1, kVjp = 2, kGrid = 3 };
+
+// Kernel variants a mode degrids (V, or V and its four offset derivatives)
+// and the float64 sums it keeps per item.
+__host__ __device__ constexpr int mode_nv(int mode) { return mode == kGrad ? 5 : mode == kVjp ? 4 : 1; }
+__host__ __device__ constexpr int mode_nc(int mode) { return mode == kGrad ? 12 : mode == kVjp ? 4 : 0; }
 
 // Arguments of the fused kernel-build + degrid kernel.
 struct ItemArgs {
@@ -70,6 +75,7 @@ struct ItemArgs {
     const float* weight;        // grad
     double* partials;           // [item][pol][ncontrib]
     const int32_t* done;        // nullable: per-interval skip flags
+    double2* grid_acc;          // grid mode: residual grid, (N+S) x (N+S), float64 sums
     int32_t use_mfma;           // degrid on the matrix cores (gradient and adjoint)
 };
 
@@ -104,6 +110,9 @@ hipError_t launch_fft_rows(double2* data, int n, int log2n, hipStream_t s);
 hipError_t launch_transpose(const double2* in, double2* out, int n, hipStream_t s);
 hipError_t launch_finish_grid(const double2* in, float2* out, int n, int pad, hipStream_t s);
 hipError_t launch_airy_table(float4* tab, int n_tab, double dx, hipStream_t s);
+hipError_t launch_zero(double2* p, size_t n, hipStream_t s);
+hipError_t launch_unpad_grid(const double2* g, double2* out, int n, int pad, hipStream_t s);
+hipError_t launch_image_grad(const double2* f, const double* taper_pix, double* out, int n, hipStream_t s);
 hipError_t launch_items(int mode, int support, const ItemArgs& a, hipStream_t s);
 // Window-form degrid (psc_window.hip), supports 16 and 32, 4 wavefronts per
 // block.  win_lds_bytes is its dynamic LDS per block, win_lds_budget the most

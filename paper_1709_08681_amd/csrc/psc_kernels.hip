@@ -89,6 +89,56 @@ __global__ void k_finish_grid(const double2* __restrict__ in, float2* __restrict
 }
 
 // ---------------------------------------------------------------------------
+// Image gradient (the adjoint of the model transform and degrid)
+// ---------------------------------------------------------------------------
+// Zero fill: a kernel rather than a memset, so that it can sit in a graph.
+__global__ void k_zero(double2* __restrict__ p, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = make_double2(0.0, 0.0);
+}
+
+// Folds the (N+pad)^2 residual grid back onto N x N (its last `pad` rows and
+// columns are the first ones again) and applies the sign of the N/2 shift:
+// out[k] = (-1)^(kx+ky) sum of the copies of cell k.
+__global__ void k_unpad_grid(const double2* __restrict__ g, double2* __restrict__ out, int n, int pad)
+{
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)n * n) return;
+    const int kx = (int)(idx / n), ky = (int)(idx % n);
+    const size_t p = (size_t)n + pad;
+    double2 v = g[kx * p + ky];
+    if (kx < pad) {
+        const double2 w = g[(kx + n) * p + ky];
+        v.x += w.x;
+        v.y += w.y;
+    }
+    if (ky < pad) {
+        const double2 w = g[kx * p + ky + n];
+        v.x += w.x;
+        v.y += w.y;
+    }
+    if (kx < pad && ky < pad) {
+        const double2 w = g[(kx + n) * p + ky + n];
+        v.x += w.x;
+        v.y += w.y;
+    }
+    const double sgn = ((kx + ky) & 1) ? -1.0 : 1.0;
+    out[idx] = make_double2(sgn * v.x, sgn * v.y);
+}
+
+// d chi^2 / d I[n] = -2 Re(F[n]) / c[n]: F is the transform of the unpadded
+// residual grid, c the taper response the model was divided by.
+__global__ void k_image_grad(const double2* __restrict__ f, const double* __restrict__ tp,
+                             double* __restrict__ out, int n)
+{
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)n * n) return;
+    const int ix = (int)(idx / n), iy = (int)(idx % n);
+    out[idx] = -2.0 * f[idx].x / (tp[ix] * tp[iy]);
+}
+
+// ---------------------------------------------------------------------------
 // Airy pattern table: A(x) = 2 J1(x)/x, B(x) = 2 J2(x)/x^2 and their slopes
 // (A' = -x B, B' = (A - 4B)/x), for cubic Hermite interpolation.
 // ---------------------------------------------------------------------------
@@ -125,8 +175,8 @@ __global__ void k_airy_table(float4* __restrict__ tab, int n_tab, double dx)
 template <int S, int MODE, int SPL, bool MX>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) k_item(ItemArgs a)
 {
-    constexpr int NV = (MODE == kPredict) ? 1 : (MODE == kGrad) ? 5 : 4;
-    constexpr int NC = (MODE == kGrad) ? 12 : (MODE == kVjp) ? 4 : 0;
+    constexpr int NV = mode_nv(MODE);
+    constexpr int NC = mode_nc(MODE);
     constexpr int SP = S + 1;
     constexpr int SPW = 64 / S;
 
@@ -341,7 +391,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
                     // this iteration's data, fetched before the multiply-adds
                     const size_t o = (size_t)ent[j].vidx * a.n_pol + pol;
                     if (MODE != kPredict) vin[j] = a.vis_in[o];
-                    if (MODE == kGrad) wgt[j] = a.weight[o];
+                    if (MODE == kGrad || MODE == kGrid) wgt[j] = a.weight[o];
                 }
                 float2 s[SPL][NV];
 #pragma unroll
@@ -390,8 +440,23 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
                     } else if (MODE == kGrad) {
                         if (a.vis_out != nullptr && t == 0) a.vis_out[o] = s[j][0];
                         grad_term(tsel, s[j], vin[j], wgt[j], acc64);
-                    } else {
+                    } else if (MODE == kVjp) {
                         vjp_term(t, s[j], vin[j], acc64);
+                    } else {
+                        // adjoint of the degrid: w conj(R) spread back over the
+                        // window with the coefficients that produced V, summed
+                        // in float64 on the residual grid
+                        if (a.vis_out != nullptr && t == 0) a.vis_out[o] = s[j][0];
+                        const float rr = (float)((double)vin[j].x - (double)s[j][0].x);
+                        const float ri = (float)((double)vin[j].y - (double)s[j][0].y);
+                        const float cr = wgt[j] * rr, ci = -wgt[j] * ri;
+                        double2* gdst = a.grid_acc + voff[j] / (int)sizeof(float2);
+#pragma unroll
+                        for (int al = 0; al < S; ++al) {
+                            const float2 kv = kcol[(S - 1 - al) * SP];
+                            unsafeAtomicAdd(&gdst[(size_t)al * P].x, (double)(cr * kv.x - ci * kv.y));
+                            unsafeAtomicAdd(&gdst[(size_t)al * P].y, (double)(cr * kv.y + ci * kv.x));
+                        }
                     }
                 }
 #pragma unroll
@@ -769,6 +834,27 @@ hipError_t launch_finish_grid(const double2* in, float2* out, int n, int pad, hi
     return hipGetLastError();
 }
 
+hipError_t launch_zero(double2* p, size_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    k_zero<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpad_grid(const double2* g, double2* out, int n, int pad, hipStream_t s)
+{
+    const size_t tot = (size_t)n * n;
+    k_unpad_grid<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(g, out, n, pad);
+    return hipGetLastError();
+}
+
+hipError_t launch_image_grad(const double2* f, const double* taper_pix, double* out, int n, hipStream_t s)
+{
+    const size_t tot = (size_t)n * n;
+    k_image_grad<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(f, taper_pix, out, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_airy_table(float4* tab, int n_tab, double dx, hipStream_t s)
 {
     k_airy_table<<<(n_tab + 255) / 256, 256, 0, s>>>(tab, n_tab, dx);
@@ -778,8 +864,8 @@ hipError_t launch_airy_table(float4* tab, int n_tab, double dx, hipStream_t s)
 template <int S, int MODE, int SPL, bool MX>
 static hipError_t launch_items_t(const ItemArgs& a, hipStream_t s)
 {
-    constexpr int NV = (MODE == kPredict) ? 1 : (MODE == kGrad) ? 5 : 4;
-    constexpr int NC = (MODE == kGrad) ? 12 : (MODE == kVjp) ? 4 : 1;
+    constexpr int NV = mode_nv(MODE);
+    constexpr int NC = mode_nc(MODE) > 0 ? mode_nc(MODE) : 1;
     const int m2p = (a.m * a.m + 3) & ~3;
     const size_t gp = sizeof(double) * NC * a.oversample * a.oversample;
     const size_t sh = gp + sizeof(float) * NV * m2p + sizeof(float2) * kWaves * NV * S * (S + 1);
@@ -804,6 +890,7 @@ hipError_t launch_items(int mode, int support, const ItemArgs& a, hipStream_t s)
     const bool mx = a.use_mfma != 0;
     switch (mode) {
     case kPredict: return launch_items_t<16, kPredict, 2, false>(a, s);
+    case kGrid: return launch_items_t<16, kGrid, 2, false>(a, s);
     case kGrad:
         return mx ? launch_items_t<16, kGrad, 2, true>(a, s) : launch_items_t<16, kGrad, 2, false>(a, s);
     case kVjp:

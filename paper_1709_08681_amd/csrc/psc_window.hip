@@ -36,8 +36,8 @@ namespace psc {
 template <int S, int MODE, int W>
 __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
 {
-    constexpr int NV = (MODE == kPredict) ? 1 : (MODE == kGrad) ? 5 : 4;
-    constexpr int NC = (MODE == kGrad) ? 12 : (MODE == kVjp) ? 4 : 0;
+    constexpr int NV = mode_nv(MODE);
+    constexpr int NC = mode_nc(MODE);
     constexpr int SP = S + 1;
     constexpr int SPW = 64 / S;
     constexpr int kBlock = 64 * W;
@@ -263,8 +263,8 @@ static hipError_t launch_win_t(const ItemArgs& a, hipStream_t s)
 
 size_t win_lds_bytes(int support, int mode, int waves, int m, int oversample)
 {
-    const int nv = (mode == kPredict) ? 1 : (mode == kGrad) ? 5 : 4;
-    const int nc = (mode == kGrad) ? 12 : (mode == kVjp) ? 4 : 1;
+    const int nv = mode_nv(mode);
+    const int nc = mode_nc(mode) > 0 ? mode_nc(mode) : 1;
     const int m2p = (m * m + 3) & ~3;
     return sizeof(double) * nc * win_max_units(oversample) + sizeof(float) * nv * m2p +
            sizeof(float2) * (size_t)waves * 64 * (support + 1);

@@ -29,7 +29,7 @@ ARCSEC = math.pi / (180.0 * 3600.0)
 EXPORTS = ["psc_version", "psc_create", "psc_destroy", "psc_last_error", "psc_set_model",
            "psc_obs_create", "psc_obs_destroy", "psc_obs_info", "psc_predict", "psc_gradient",
            "psc_predict_vjp", "psc_solve_step", "psc_solve", "psc_set_degrid", "psc_get_degrid",
-           "psc_tune"]
+           "psc_tune", "psc_image_gradient"]
 
 
 class PscError(RuntimeError):
@@ -87,6 +87,7 @@ def load():
             "psc_set_degrid": ([vp, i32], C.c_int),
             "psc_get_degrid": ([vp, C.POINTER(i32)], C.c_int),
             "psc_tune": ([vp, vp, vp, vp, vp, i32, C.POINTER(dbl), vp], C.c_int),
+            "psc_image_gradient": ([vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -190,6 +191,13 @@ def psc_get_degrid(obs):
     return v.value
 
 
+def psc_image_gradient(ctx, obs, offsets_dev, vis_obs_dev, weight_dev, image_grad_out_dev,
+                       vis_model_dev=None, stream=None):
+    _check(load().psc_image_gradient(ctx, obs, _ptr(offsets_dev), _ptr(vis_obs_dev), _ptr(weight_dev),
+                                     _ptr(image_grad_out_dev), _ptr(vis_model_dev), _stream(stream)),
+           ctx)
+
+
 def psc_tune(ctx, obs, offsets_dev, vis_obs_dev, weight_dev, repeats=3, stream=None):
     """Returns the mean launch time (us) of each degrid variant (-1 where the
     support does not allow it); the observation keeps the fastest."""
@@ -291,6 +299,15 @@ class Session:
         g = torch.empty(self.off_shape, dtype=torch.float64, device=self.dev)
         psc_predict_vjp(self.ctx, self.handle, off, grad_vis.contiguous(), g)
         return g
+
+    def image_gradient(self, offsets, vis_obs, weight):
+        """d chi^2 / d I on the model grid, [N][N] float64."""
+        torch = self.torch
+        off = offsets if isinstance(offsets, torch.Tensor) else self.offsets(offsets)
+        n = self.obs.grid_n
+        out = torch.empty((n, n), dtype=torch.float64, device=self.dev)
+        psc_image_gradient(self.ctx, self.handle, off, vis_obs, weight, out)
+        return out
 
     def solve_step(self, acc, gain, offsets):
         torch = self.torch

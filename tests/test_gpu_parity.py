@@ -570,3 +570,56 @@ def test_cfg5_subset_solve(torch_dev, cfg5_subset):
         outs.append(off.cpu().numpy())
         assert np.abs(outs[-1] - ref_off).max() / ARCSEC <= 0.1
     assert np.array_equal(outs[0], outs[1])
+
+
+# ---------------------------------------------------------------------------
+# image gradient: the adjoint of predict with respect to the model image
+# ---------------------------------------------------------------------------
+
+def _check_image_gradient(torch, obs, prob, s, start, vo, w, n_rand, seed, tol=1e-4):
+    n = obs.grid_n
+    rng = np.random.default_rng(seed)
+    ix, iy, _ = obs.sky_pixels()
+    rx = rng.integers(n // 4, 3 * n // 4, n_rand)
+    ry = rng.integers(n // 4, 3 * n // 4, n_rand)
+    px = np.concatenate([ix, rx])
+    py = np.concatenate([iy, ry])
+    l = (px - n // 2) * obs.cell_rad
+    m = (py - n // 2) * obs.cell_rad
+    ref = oracle.image_gradient(prob, start, vo, w, l, m)
+    G = s.image_gradient(s.offsets(start), c64(torch, s, vo), f32(torch, s, w, s.vis_shape))
+    got = G.cpu().numpy()[px, py]
+    err = rel(got, ref)
+    print(f"image gradient: rel {err:.2e} over {px.size} pixels", flush=True)
+    assert err <= tol
+    return G
+
+
+def test_image_gradient_cfg1(torch_dev, cfg1):
+    """d chi^2 / d I on the model grid against the oracle's direct sum, at
+    every model pixel and at random pixels of the central half; a second run
+    agrees to float64 rounding (float64 atomics)."""
+    torch = torch_dev
+    obs, prob, s = cfg1
+    print("case: image gradient cfg1", flush=True)
+    v = oracle.predict(prob, obs.offsets_true)
+    nz, w = synth.noise(v, 100.0, 25)
+    vo = v + nz
+    start = synth.perturbed_offsets(obs, 20.0, 26)
+    G1 = _check_image_gradient(torch, obs, prob, s, start, vo, w, 96, 27)
+    G2 = s.image_gradient(s.offsets(start), c64(torch, s, vo), f32(torch, s, w, s.vis_shape))
+    assert rel(G2.cpu().numpy(), G1.cpu().numpy()) <= 1e-12
+
+
+def test_image_gradient_cfg2_full_size(torch_dev):
+    torch = torch_dev
+    print("case: image gradient cfg2 full size", flush=True)
+    obs = synth.make_config(2)
+    prob = oracle.Problem.from_observation(obs)
+    s = session(obs)
+    try:
+        start = synth.perturbed_offsets(obs, 30.0, 28)
+        v = oracle.predict(prob, obs.offsets_true)
+        _check_image_gradient(torch, obs, prob, s, start, v, 1.0, 56, 29)
+    finally:
+        s.close()
