@@ -112,6 +112,27 @@ def batched_vs_plain(cfg, iters, device=0):
         s.close()
 
 
+def image_gradient_timing(s, obs, off, v_obs, w, reps, stream):
+    """psc_image_gradient (d chi^2 / d I on the model grid) on the same data:
+    V-only degrid, residual scatter with float64 atomics, float64 N^2 FFT."""
+    import torch
+    from paper_1709_08681_amd import psc as P
+    n = obs.grid_n
+    out = torch.empty((n, n), dtype=torch.float64, device=s.dev)
+    P.psc_image_gradient(s.ctx, s.handle, off, v_obs, w, out, None, stream)  # warm-up, scratch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        P.psc_image_gradient(s.ctx, s.handle, off, v_obs, w, out, None, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"ms_per_call": ms, "vis_per_s": obs.n_vis / (ms * 1e-3), "calls": reps,
+            "grid": f"{n}^2", "note": "table form, support 16"}
+
+
 def cpu_baseline(obs, start, seconds):
     """The oracle (FP64 direct sum) on the host cores: gradient + update
     iterations for about `seconds`, over the whole workload or, when one
@@ -160,6 +181,7 @@ def main():
     ap.add_argument("--batched-config", type=int, default=3)
     ap.add_argument("--batched-iters", type=int, default=3)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-image-gradient", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only; the hot path is sharded by solution "
@@ -251,6 +273,9 @@ def main():
                        tune_us={name: t for name, t in zip(("vector", "matrix_core", "window"), tune_us)}),
         "roofline": roof,
     }
+    if not args.no_image_gradient and S == 16:
+        print("bench: image gradient", file=sys.stderr, flush=True)
+        out["image_gradient"] = image_gradient_timing(s, obs, off, v_obs, w, 5, stream)
     s.close()
     if not args.no_batched:
         print(f"bench: batched vs plain on workload {args.batched_config}", file=sys.stderr,
