@@ -445,6 +445,14 @@ PSC_API psc_status psc_obs_create(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
                     vis[base + fpos[fq[k]]++] = ve;
                 }
                 it.grp_end = (int32_t)groups.size();
+                // largest groups first: the block's wavefronts claim groups in
+                // this order, so the long ones start early and the item's
+                // wavefronts finish together
+                std::stable_sort(groups.begin() + it.grp_begin, groups.end(), [](const Group& x, const Group& y) {
+                    const int cx = (x.n_vis + 7) / 8 + (x.n_vis2 + 7) / 8;
+                    const int cy = (y.n_vis + 7) / 8 + (y.n_vis2 + 7) / 8;
+                    return cx > cy;
+                });
                 items.push_back(it);
             }
         }
