@@ -17,6 +17,8 @@
 // as f + O b (0 <= f < O), the DFT splits into a twiddle by exp(2 pi i f n/(SO)),
 // a fold of n modulo S, and an S-point DFT over b: each S x S sub-table is one
 // small 2-D FFT.  Only sub-tables that some sample of the item uses are built.
+#include <type_traits>
+
 #include "psc_device.h"
 
 namespace psc {
@@ -370,21 +372,28 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
             const int t_dl = t_end ? 6 : 2, t_dm = t_end ? 8 : 4;
             const int t_xcol = t_xr ? 0 : (t_xl ? t_dl : t_dm);
             const int t_ycol = t_yr ? 0 : (t_yl ? t_dl : t_dm);
+            // A pass degrids L * 64/S samples from v0 on (L per lane).  Full
+            // passes (L = SPL) run while more than 64/S samples remain; a
+            // remainder of at most 64/S samples takes one pass with L = 1, so
+            // the partly filled last pass of a part costs half as much.
             auto degrid = [&](uint32_t vb, int nv, VisEnt (&ent)[SPL]) {
-            for (int v0 = 0; v0 < nv; v0 += STEP) {
+            auto pass = [&](int v0, auto l_const) {
+                constexpr int L = decltype(l_const)::value;
                 // re-read the sub-tables from LDS every iteration instead of
                 // letting the compiler keep all S*NV values in registers
                 int kofs = S - 1 - am;
                 asm volatile("" : "+v"(kofs));
                 const float2* kcol = uw + kofs;
-                VisEnt nxt[SPL];
-                int voff[SPL];
-                float2 vin[SPL];
-                float wgt[SPL];
+                VisEnt nxt[L];
+                int voff[L];
+                float2 vin[L];
+                float wgt[L];
 #pragma unroll
-                for (int j = 0; j < SPL; ++j) {
-                    const int vn = v0 + STEP + slot + SPW * j;
-                    nxt[j] = a.vis[vb + (vn < nv ? vn : nv - 1)];  // next iteration, early
+                for (int j = 0; j < L; ++j) {
+                    if (L == SPL) {  // the next full pass, early
+                        const int vn = v0 + STEP + slot + SPW * j;
+                        nxt[j] = a.vis[vb + (vn < nv ? vn : nv - 1)];
+                    }
                     const int row0 = (int)(ent[j].klo >> 16);
                     const int col0 = (int)(ent[j].klo & 0xffffu);
                     voff[j] = (row0 * P + col0 + am) * (int)sizeof(float2);
@@ -393,15 +402,15 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
                     if (MODE != kPredict) vin[j] = a.vis_in[o];
                     if (MODE == kGrad || MODE == kGrid) wgt[j] = a.weight[o];
                 }
-                float2 s[SPL][NV];
+                float2 s[L][NV];
 #pragma unroll
-                for (int j = 0; j < SPL; ++j)
+                for (int j = 0; j < L; ++j)
 #pragma unroll
                     for (int k = 0; k < NV; ++k) s[j][k] = make_float2(0.f, 0.f);
                 // every window row of the iteration is requested up front
-                float2 gwin[SPL][S];
+                float2 gwin[L][S];
 #pragma unroll
-                for (int j = 0; j < SPL; ++j)
+                for (int j = 0; j < L; ++j)
 #pragma unroll
                     for (int al = 0; al < S; ++al)
                         gwin[j][al] = __builtin_bit_cast(
@@ -417,21 +426,21 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
                         for (int k = 0; k < NV; ++k) kvn[k] = kcol[(k * S + (S - 2 - al)) * SP];
                     }
 #pragma unroll
-                    for (int j = 0; j < SPL; ++j)
+                    for (int j = 0; j < L; ++j)
 #pragma unroll
                         for (int k = 0; k < NV; ++k) cmac(s[j][k], kv[k], gwin[j][al]);
 #pragma unroll
                     for (int k = 0; k < NV; ++k) kv[k] = kvn[k];
                 }
 #pragma unroll
-                for (int j = 0; j < SPL; ++j)
+                for (int j = 0; j < L; ++j)
 #pragma unroll
                     for (int k = 0; k < NV; ++k) {
                         s[j][k].x = row16_sum(s[j][k].x);
                         s[j][k].y = row16_sum(s[j][k].y);
                     }
 #pragma unroll
-                for (int j = 0; j < SPL; ++j) {
+                for (int j = 0; j < L; ++j) {
                     const int v = v0 + slot + SPW * j;
                     if (v >= nv) continue;
                     const size_t o = (size_t)ent[j].vidx * a.n_pol + pol;
@@ -459,9 +468,14 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
                         }
                     }
                 }
+                if constexpr (L == SPL) {
 #pragma unroll
-                for (int j = 0; j < SPL; ++j) ent[j] = nxt[j];
-            }
+                    for (int j = 0; j < SPL; ++j) ent[j] = nxt[j];
+                }
+            };
+            int v0 = 0;
+            for (; nv - v0 > SPW * (SPL - 1); v0 += STEP) pass(v0, std::integral_constant<int, SPL>{});
+            if (v0 < nv) pass(v0, std::integral_constant<int, 1>{});
             };  // degrid
 
             if constexpr (MX) {
