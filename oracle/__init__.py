@@ -56,6 +56,7 @@ class _Problem(C.Structure):
         ("gauss_sigma_ld", C.c_double),
         ("squint_frac", C.c_double),
         ("snap_scale", C.c_double),
+        ("par_angle", C.POINTER(C.c_double)),
     ]
 
 
@@ -105,7 +106,7 @@ class Problem:
 
     def __init__(self, src_l, src_m, src_flux, n_ant, ant1, ant2, uv_m, int_row_ptr, freq_hz,
                  n_pol=1, dish_diam_m=25.0, illum=0, gauss_sigma_ld=1.0, squint_frac=0.0,
-                 snap_scale=0.0):
+                 snap_scale=0.0, par_angle=None):
         self.src_l = np.ascontiguousarray(src_l, np.float64)
         self.src_m = np.ascontiguousarray(src_m, np.float64)
         self.src_flux = np.ascontiguousarray(src_flux, np.float64)
@@ -119,18 +120,26 @@ class Problem:
         self.n_int = int(self.int_row_ptr.shape[0] - 1)
         self.n_row = int(self.ant1.shape[0])
         self.n_chan = int(self.freq_hz.shape[0])
+        # per-row parallactic angle: offsets are then in the mount frame
+        self.par_angle = None if par_angle is None else np.ascontiguousarray(par_angle, np.float64)
+        if self.par_angle is not None and self.par_angle.shape != (self.n_row,):
+            raise ValueError("par_angle must have one value per row")
         self._s = _Problem(
             int(self.src_flux.shape[0]), _dp(self.src_l), _dp(self.src_m), _dp(self.src_flux),
             self.n_ant, self.n_chan, self.n_pol, self.n_int, self.n_row,
             self.int_row_ptr.ctypes.data_as(C.POINTER(C.c_int64)), _ip(self.ant1), _ip(self.ant2),
             _dp(self.uv_m), _dp(self.freq_hz), float(dish_diam_m), int(illum), float(gauss_sigma_ld),
-            float(squint_frac), float(snap_scale))
+            float(squint_frac), float(snap_scale),
+            None if self.par_angle is None else _dp(self.par_angle))
 
     @classmethod
-    def from_observation(cls, obs, snap=True, **kw):
+    def from_observation(cls, obs, snap=True, mount_frame=False, **kw):
+        """mount_frame: offsets in the antenna mount frame, carried onto the
+        sky by each row's parallactic angle."""
         l, m, f = obs.sky_lm()
         args = dict(n_pol=obs.n_pol, dish_diam_m=obs.wl.dish_diam_m, squint_frac=obs.wl.squint_frac,
-                    snap_scale=obs.snap_scale if snap else 0.0)
+                    snap_scale=obs.snap_scale if snap else 0.0,
+                    par_angle=obs.par_angle if mount_frame else None)
         args.update(kw)
         return cls(l, m, f, obs.n_ant, obs.ant1, obs.ant2, obs.uv_m, obs.int_row_ptr, obs.freq_hz,
                    **args)

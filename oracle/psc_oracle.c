@@ -44,6 +44,11 @@
  *  - Polarisation p of antenna i has its beam centred at
  *    offset + sgn(p) * squint_frac * HPBW(nu) along +l, sgn = (+1, -1),
  *    HPBW = 1.02899 lambda / D.
+ *  - With parallactic angles (one per row, optional), offsets and squint are
+ *    in the antenna mount's frame and reach the sky rotated by the row's
+ *    angle chi: p_sky = R(chi) (offset + squint), R = [[cos, -sin],
+ *    [sin, cos]]; derivatives are taken with respect to the mount-frame
+ *    offsets.  The paper solves in this frame for its VLA data (Sec. 4).
  */
 #include <math.h>
 #include <stdint.h>
@@ -170,14 +175,39 @@ static double* beam_table(const orc_problem* p, const double* offs_int /* [n_pol
 }
 
 /*
- * Model visibility and its four offset derivatives for one (row, chan, pol):
+ * Beam values of antenna a towards every source for one row when offsets are
+ * given in the antenna frame: the offset plus squint q is carried onto the
+ * sky by the row's parallactic angle chi, p = R(chi) q with
+ * R = [[cos, -sin], [sin, cos]], and the derivatives are taken with respect
+ * to q, dE/dq = R^T dE/dp.  t[3 s .. 3 s + 2] = (E, dE/dq_l, dE/dq_m).
+ */
+static void beam_row(const orc_problem* p, const double* offs_int, int pol, int a, int c, double chi,
+                     double* t)
+{
+    double lambda = ORC_C_LIGHT / p->freq_hz[c];
+    double sq = (pol == 0 ? 1.0 : -1.0) * p->squint_frac * hpbw_rad(lambda, p->dish_diam_m);
+    double ql = offs_int[(pol * p->n_ant + a) * 2 + 0] + sq;
+    double qm = offs_int[(pol * p->n_ant + a) * 2 + 1];
+    double cs = cos(chi), sn = sin(chi);
+    double pl = cs * ql - sn * qm, pm = sn * ql + cs * qm;
+    for (int s = 0; s < p->n_src; ++s) {
+        double e[3];
+        oracle_efp(p->illum, p->dish_diam_m, p->gauss_sigma_ld, p->freq_hz[c], p->src_l[s] - pl,
+                   p->src_m[s] - pm, e);
+        t[3 * s] = e[0];
+        t[3 * s + 1] = cs * e[1] + sn * e[2];
+        t[3 * s + 2] = -sn * e[1] + cs * e[2];
+    }
+}
+
+/*
+ * Model visibility and its four offset derivatives for one (row, chan, pol)
+ * from the two antennas' beam values ti, tj ([n_src][3] each):
  * out[0..1] = V, out[2..9] = dV/dl_i, dV/dm_i, dV/dl_j, dV/dm_j (re, im each).
  */
-static void vis_one(const orc_problem* p, const double* tab, int pol, int ai, int aj, int c,
-                    double u, double v, double* out, int want_grad)
+static void vis_from_beams(const orc_problem* p, const double* ti, const double* tj, double u, double v,
+                           double* out, int want_grad)
 {
-    const double* ti = tab + 3 * ((((size_t)pol * p->n_ant + ai) * p->n_chan + c) * p->n_src);
-    const double* tj = tab + 3 * ((((size_t)pol * p->n_ant + aj) * p->n_chan + c) * p->n_src);
     double acc[10] = {0};
     for (int s = 0; s < p->n_src; ++s) {
         double ph = 2.0 * ORC_PI * (u * p->src_l[s] + v * p->src_m[s]);
@@ -197,6 +227,32 @@ static void vis_one(const orc_problem* p, const double* tab, int pol, int ai, in
         }
     }
     memcpy(out, acc, sizeof(acc));
+}
+
+/* The same from the interval's beam table (offsets in the sky frame). */
+static void vis_one(const orc_problem* p, const double* tab, int pol, int ai, int aj, int c,
+                    double u, double v, double* out, int want_grad)
+{
+    const double* ti = tab + 3 * ((((size_t)pol * p->n_ant + ai) * p->n_chan + c) * p->n_src);
+    const double* tj = tab + 3 * ((((size_t)pol * p->n_ant + aj) * p->n_chan + c) * p->n_src);
+    vis_from_beams(p, ti, tj, u, v, out, want_grad);
+}
+
+/*
+ * One (row, chan, pol): from the interval's beam table, or, when the problem
+ * carries parallactic angles, from beams evaluated for this row into the
+ * caller's scratch bi, bj ([n_src][3] each).
+ */
+static void vis_row(const orc_problem* p, const double* tab, const double* offs_int, int64_t r, int pol,
+                    int c, double u, double v, double* bi, double* bj, double* out, int want_grad)
+{
+    if (p->par_angle) {
+        beam_row(p, offs_int, pol, p->ant1[r], c, p->par_angle[r], bi);
+        beam_row(p, offs_int, pol, p->ant2[r], c, p->par_angle[r], bj);
+        vis_from_beams(p, bi, bj, u, v, out, want_grad);
+    } else {
+        vis_one(p, tab, pol, p->ant1[r], p->ant2[r], c, u, v, out, want_grad);
+    }
 }
 
 static int check_problem(const orc_problem* p)
@@ -222,22 +278,28 @@ int oracle_predict(const orc_problem* p, const double* offsets, double* vis_out,
         int64_t r0 = p->int_row_ptr[s], r1 = p->int_row_ptr[s + 1];
         if (r0 == r1) continue; /* an empty interval predicts nothing */
         const double* offs_int = offsets + (size_t)s * p->n_pol * p->n_ant * 2;
-        double* tab = beam_table(p, offs_int);
-        if (!tab) return -2;
-#pragma omp parallel for schedule(dynamic, 16)
-        for (int64_t r = r0; r < r1; ++r) {
-            for (int c = 0; c < p->n_chan; ++c) {
-                double u, v;
-                row_uv(p, r, c, &u, &v);
-                for (int pol = 0; pol < p->n_pol; ++pol) {
-                    double out[10];
-                    vis_one(p, tab, pol, p->ant1[r], p->ant2[r], c, u, v, out, dvis_out != NULL);
-                    size_t idx = ((size_t)r * p->n_chan + c) * p->n_pol + pol;
-                    vis_out[2 * idx] = out[0];
-                    vis_out[2 * idx + 1] = out[1];
-                    if (dvis_out) memcpy(dvis_out + 8 * idx, out + 2, 8 * sizeof(double));
+        double* tab = p->par_angle ? NULL : beam_table(p, offs_int);
+        if (!p->par_angle && !tab) return -2;
+#pragma omp parallel
+        {
+            double* bi = (double*)malloc(sizeof(double) * 6 * (p->n_src + 1));
+            double* bj = bi + 3 * (p->n_src + 1);
+#pragma omp for schedule(dynamic, 16)
+            for (int64_t r = r0; r < r1; ++r) {
+                for (int c = 0; c < p->n_chan; ++c) {
+                    double u, v;
+                    row_uv(p, r, c, &u, &v);
+                    for (int pol = 0; pol < p->n_pol; ++pol) {
+                        double out[10];
+                        vis_row(p, tab, offs_int, r, pol, c, u, v, bi, bj, out, dvis_out != NULL);
+                        size_t idx = ((size_t)r * p->n_chan + c) * p->n_pol + pol;
+                        vis_out[2 * idx] = out[0];
+                        vis_out[2 * idx + 1] = out[1];
+                        if (dvis_out) memcpy(dvis_out + 8 * idx, out + 2, 8 * sizeof(double));
+                    }
                 }
             }
+            free(bi);
         }
         free(tab);
     }
@@ -266,8 +328,8 @@ int oracle_gradient(const orc_problem* p, const double* offsets, const double* v
         int64_t r0 = p->int_row_ptr[s], r1 = p->int_row_ptr[s + 1];
         if (r0 == r1) continue; /* no samples: every sum of the interval stays 0 */
         const double* offs_int = offsets + (size_t)s * p->n_pol * p->n_ant * 2;
-        double* tab = beam_table(p, offs_int);
-        if (!tab) {
+        double* tab = p->par_angle ? NULL : beam_table(p, offs_int);
+        if (!p->par_angle && !tab) {
             free(part);
             return -2;
         }
@@ -279,6 +341,8 @@ int oracle_gradient(const orc_problem* p, const double* offsets, const double* v
             tid = omp_get_thread_num();
 #endif
             double* mine = part + (size_t)tid * per;
+            double* bi = (double*)malloc(sizeof(double) * 6 * (p->n_src + 1));
+            double* bj = bi + 3 * (p->n_src + 1);
 #pragma omp for schedule(static)
             for (int64_t r = r0; r < r1; ++r) {
                 int ai = p->ant1[r], aj = p->ant2[r];
@@ -288,7 +352,7 @@ int oracle_gradient(const orc_problem* p, const double* offsets, const double* v
                     for (int pol = 0; pol < p->n_pol; ++pol) {
                         size_t idx = ((size_t)r * p->n_chan + c) * p->n_pol + pol;
                         double out[10];
-                        vis_one(p, tab, pol, ai, aj, c, u, v, out, 1);
+                        vis_row(p, tab, offs_int, r, pol, c, u, v, bi, bj, out, 1);
                         if (vis_model_out) {
                             vis_model_out[2 * idx] = out[0];
                             vis_model_out[2 * idx + 1] = out[1];
@@ -312,6 +376,7 @@ int oracle_gradient(const orc_problem* p, const double* offsets, const double* v
                     }
                 }
             }
+            free(bi);
         }
         double* dst = acc + (size_t)s * per;
         for (int t = 0; t < nthr; ++t)
@@ -334,7 +399,7 @@ int oracle_image_gradient(const orc_problem* p, const double* offsets, const dou
                           const double* weight, int n_pix, const double* pix_l, const double* pix_m,
                           double* out)
 {
-    if (check_problem(p) || n_pix < 0) return -1;
+    if (check_problem(p) || n_pix < 0 || p->par_angle) return -1;
     size_t n_vis = (size_t)p->n_row * p->n_chan * p->n_pol;
     double* vm = (double*)malloc((n_vis ? n_vis : 1) * 2 * sizeof(double));
     double* ones = (double*)malloc((n_pix ? n_pix : 1) * sizeof(double));

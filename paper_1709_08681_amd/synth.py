@@ -170,6 +170,18 @@ class Observation:
         return self.grid_n * self.cell_rad
 
     @property
+    def par_angle(self) -> np.ndarray:
+        """Parallactic angle of every row (rad), from its hour angle, the
+        declination and the latitude (textbook spherical astronomy):
+        tan q = sin H cos(lat) / (sin(lat) cos(dec) - cos(lat) sin(dec) cos H)."""
+        wl = self.wl
+        t = (self.time_idx - 0.5 * (wl.n_time - 1)) * wl.dt_s
+        h = OMEGA_EARTH * t
+        lat, dec = np.radians(wl.lat_deg), np.radians(wl.dec_deg)
+        return np.arctan2(np.sin(h) * np.cos(lat),
+                          np.sin(lat) * np.cos(dec) - np.cos(lat) * np.sin(dec) * np.cos(h))
+
+    @property
     def snap_scale(self) -> float:
         """uv lattice density (per wavelength): oversample * FoV."""
         return self.wl.oversample * self.fov

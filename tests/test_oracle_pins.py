@@ -408,3 +408,106 @@ def test_image_gradient_vanishes_at_truth_and_is_linear_in_weight(oracle_lib):
     g2 = o.image_gradient(prob, offs, vobs, 2.0, pl, pm)
     assert np.all(g1 != 0.0)
     np.testing.assert_allclose(g2, 2 * g1, rtol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Offsets in the antenna mount frame (parallactic-angle rotation)
+# --------------------------------------------------------------------------
+
+def _mount_problem(oracle, par_angle, squint=0.03, seed=5):
+    rng = np.random.default_rng(seed)
+    n_ant, n_time = 4, 4
+    i, j = np.triu_indices(n_ant, 1)
+    ant1, ant2 = np.tile(i, n_time), np.tile(j, n_time)
+    uv = rng.uniform(-2500.0, 2500.0, size=(ant1.size, 2))
+    src_l, src_m = rng.uniform(-0.01, 0.01, 6), rng.uniform(-0.01, 0.01, 6)
+    flux = rng.uniform(0.2, 1.5, 6)
+    ptr = [0, 2 * 6, ant1.size]
+    pa = None if par_angle is None else np.broadcast_to(par_angle, ant1.shape).astype(np.float64)
+    return oracle.Problem(src_l, src_m, flux, n_ant, ant1, ant2, uv, ptr, [1.2e9, 1.7e9], n_pol=2,
+                          squint_frac=squint, par_angle=pa)
+
+
+def test_mount_frame_at_zero_angle_is_the_sky_frame(oracle_lib):
+    o = oracle_lib
+    sky = _mount_problem(o, None)
+    mnt = _mount_problem(o, 0.0)
+    rng = np.random.default_rng(6)
+    offs = rng.normal(0.0, 30 * ARCSEC, size=sky.offsets_shape())
+    v1, d1 = o.predict(sky, offs, want_grad=True)
+    v2, d2 = o.predict(mnt, offs, want_grad=True)
+    assert np.array_equal(v1, v2) and np.array_equal(d1, d2)
+
+
+def test_mount_frame_constant_angle_is_a_rotation(oracle_lib):
+    """A constant parallactic angle t: the mount-frame model at offsets q
+    equals the sky-frame model at R(t)(q + squint) - squint (squint along +l),
+    and the per-antenna sums transform as g -> R^T g, H -> R^T H R."""
+    o = oracle_lib
+    t = 0.7
+    sky = _mount_problem(o, None)
+    mnt = _mount_problem(o, t)
+    rng = np.random.default_rng(7)
+    q = rng.normal(0.0, 30 * ARCSEC, size=sky.offsets_shape())
+    c, s_ = math.cos(t), math.sin(t)
+    R = np.array([[c, -s_], [s_, c]])
+    # squint of each pol at each channel differs, so compare channel by channel
+    for ch, f in enumerate([1.2e9, 1.7e9]):
+        sq = 0.03 * o.hpbw(f, 25.0)
+        shift = np.zeros(q.shape)
+        shift[:, 0, :, 0] = sq
+        shift[:, 1, :, 0] = -sq
+        p_sky = np.einsum("ab,ipnb->ipna", R, q + shift) - shift
+        v_m = o.predict(mnt, q)[:, ch]
+        v_s = o.predict(sky, p_sky)[:, ch]
+        np.testing.assert_allclose(v_m, v_s, rtol=1e-12, atol=1e-14 * np.abs(v_s).max())
+    # sums on single-channel problems (same squint for every sample)
+    def one_chan(par_angle, f):
+        base = _mount_problem(o, par_angle)
+        return o.Problem(base.src_l, base.src_m, base.src_flux, base.n_ant, base.ant1, base.ant2,
+                         base.uv_m, base.int_row_ptr, [f], n_pol=2, squint_frac=0.03,
+                         par_angle=base.par_angle)
+    f = 1.45e9
+    sq = 0.03 * o.hpbw(f, 25.0)
+    shift = np.zeros(q.shape)
+    shift[:, 0, :, 0] = sq
+    shift[:, 1, :, 0] = -sq
+    p_sky = np.einsum("ab,ipnb->ipna", R, q + shift) - shift
+    pm, ps = one_chan(t, f), one_chan(None, f)
+    vobs = o.predict(ps, p_sky + rng.normal(0.0, 10 * ARCSEC, q.shape))
+    a_m = o.gradient(pm, q, vobs, 1.0)
+    a_s = o.gradient(ps, p_sky, vobs, 1.0)
+    np.testing.assert_allclose(a_m[..., 0], a_s[..., 0], rtol=1e-11)
+    g_rot = np.einsum("ba,ipnb->ipna", R, a_s[..., 1:3])
+    np.testing.assert_allclose(a_m[..., 1:3], g_rot, rtol=1e-9, atol=1e-12 * np.abs(g_rot).max())
+    H = np.stack([np.stack([a_s[..., 3], a_s[..., 4]], -1), np.stack([a_s[..., 4], a_s[..., 5]], -1)], -2)
+    Hm = np.einsum("ba,ipnbc,cd->ipnad", R, H, R)
+    np.testing.assert_allclose(a_m[..., 3], Hm[..., 0, 0], rtol=1e-9, atol=1e-12 * np.abs(Hm).max())
+    np.testing.assert_allclose(a_m[..., 4], Hm[..., 0, 1], rtol=1e-9, atol=1e-12 * np.abs(Hm).max())
+    np.testing.assert_allclose(a_m[..., 5], Hm[..., 1, 1], rtol=1e-9, atol=1e-12 * np.abs(Hm).max())
+
+
+def test_mount_frame_gradient_matches_chi2_differences(oracle_lib):
+    """Parallactic angle varying from row to row: the mount-frame sums against
+    central differences of chi^2 in the mount-frame offsets (h = 0.01 arcsec)."""
+    o = oracle_lib
+    rng = np.random.default_rng(8)
+    base = _mount_problem(o, None)
+    pa = rng.uniform(-1.2, 1.2, base.n_row)
+    prob = _mount_problem(o, pa)
+    offs = rng.normal(0.0, 30 * ARCSEC, size=prob.offsets_shape())
+    vobs = o.predict(prob, offs + rng.normal(0.0, 20 * ARCSEC, offs.shape))
+    w = rng.uniform(0.5, 2.0, size=vobs.shape)
+    acc = o.gradient(prob, offs, vobs, w)
+
+    def chi2(of):
+        return float((w * np.abs(vobs - o.predict(prob, of)) ** 2).sum())
+
+    h = 0.01 * ARCSEC
+    for s, pol, ant, ax in [(0, 0, 1, 0), (0, 1, 2, 1), (1, 0, 3, 1), (1, 1, 0, 0)]:
+        op, om = offs.copy(), offs.copy()
+        op[s, pol, ant, ax] += h
+        om[s, pol, ant, ax] -= h
+        fd = (chi2(op) - chi2(om)) / (2 * h)
+        g = acc[s, pol, ant, 1 + ax]
+        assert abs(-0.5 * fd - g) <= 1e-6 * abs(g) + 1e-9, (s, pol, ant, ax, fd, g)
