@@ -104,6 +104,16 @@ typedef struct {
  *  uv_m        [n_row][2] float64 baseline (u, v) in metres, w ignored.
  *  freq_hz     [n_chan] float64 channel frequencies.
  *  n_pol       1 or 2 parallel-hand polarisations.
+ *  par_angle   nullable [n_row] float64 parallactic angle chi of each row
+ *              (rad).  When given, offsets (and squint) are in the antenna
+ *              mount frame, as the paper solves its VLA data (Sec. 4): a
+ *              row's beam centre on the sky is R(chi) (offset + squint) with
+ *              R = [[cos, -sin], [sin, cos]], and every derivative, sum and
+ *              update is with respect to the mount-frame offsets.  The
+ *              kernels then differ from sample to sample: the observation
+ *              degrids in the window form with per-sample image-plane
+ *              products (psc_set_degrid refuses the table forms and
+ *              psc_image_gradient returns PSC_E_UNSUPPORTED).
  *
  * Visibility-shaped arrays used by the calls below are laid out
  * [n_row][n_chan][n_pol]; offsets are [n_int][n_pol][n_ant][2] float64 (l, m).
@@ -119,6 +129,7 @@ typedef struct {
     const int32_t* ant2;
     const double* uv_m;
     const double* freq_hz;
+    const double* par_angle;
 } psc_obs_desc;
 
 /* Library version string. */

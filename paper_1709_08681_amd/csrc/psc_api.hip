@@ -41,6 +41,7 @@ struct psc_obs {
     uint32_t* ant_ptr = nullptr;
     uint32_t* ant_ent = nullptr;
     double* freq = nullptr;
+    double* par_angle = nullptr;  // [n_row] or null (sky-frame offsets)
     float4* airy = nullptr;
     int32_t n_tab = 0;
     double inv_dx = 0;
@@ -298,6 +299,7 @@ PSC_API psc_status psc_obs_destroy(psc_obs* obs)
     dfree(obs->ant_ptr);
     dfree(obs->ant_ent);
     dfree(obs->freq);
+    dfree(obs->par_angle);
     dfree(obs->airy);
     dfree(obs->partials);
     dfree(obs->acc);
@@ -348,6 +350,13 @@ PSC_API psc_status psc_obs_create(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
     }
     for (int64_t i = 0; i < 2 * n_row; ++i)
         if (!isfinite(uv[i])) return fail(ctx, PSC_E_ARG, "uv_m must be finite");
+    std::vector<double> pa;
+    if (d->par_angle && n_row > 0) {
+        pa.resize(n_row);
+        PSC_HIP(ctx, hipMemcpy(pa.data(), d->par_angle, sizeof(double) * n_row, hipMemcpyDeviceToHost));
+        for (int64_t r = 0; r < n_row; ++r)
+            if (!isfinite(pa[r])) return fail(ctx, PSC_E_ARG, "par_angle must be finite");
+    }
     // the kernel support must hold both apertures plus the taper
     const double lam_min = kCLight / fmax;
     const double need = 2.0 * ctx->cfg.dish_diam_m * ctx->fov / lam_min + ctx->cfg.taper_width;
@@ -487,7 +496,7 @@ PSC_API psc_status psc_obs_create(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
 
     psc_obs* obs = new psc_obs();
     obs->ctx = ctx;
-    obs->degrid = (S == 16) ? PSC_DEGRID_VALU : PSC_DEGRID_WINDOW;
+    obs->degrid = (S == 16 && pa.empty()) ? PSC_DEGRID_VALU : PSC_DEGRID_WINDOW;
     obs->n_ant = n_ant;
     obs->n_chan = n_chan;
     obs->n_pol = d->n_pol;
@@ -505,6 +514,7 @@ PSC_API psc_status psc_obs_create(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
     if (e == hipSuccess) e = dmalloc(&obs->ant_ptr, ant_ptr.size());
     if (e == hipSuccess) e = dmalloc(&obs->ant_ent, ant_ent.size());
     if (e == hipSuccess) e = dmalloc(&obs->freq, n_chan);
+    if (e == hipSuccess && !pa.empty()) e = dmalloc(&obs->par_angle, pa.size());
     if (e == hipSuccess) e = dmalloc(&obs->airy, n_tab);
     if (e == hipSuccess) e = dmalloc(&obs->partials, items.size() * d->n_pol * 12);
     if (e == hipSuccess) e = dmalloc(&obs->acc, (size_t)n_int * d->n_pol * n_ant * 6);
@@ -522,6 +532,8 @@ PSC_API psc_status psc_obs_create(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
     if (e == hipSuccess && !ant_ent.empty())
         e = hipMemcpy(obs->ant_ent, ant_ent.data(), sizeof(uint32_t) * ant_ent.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(obs->freq, fr.data(), sizeof(double) * n_chan, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !pa.empty())
+        e = hipMemcpy(obs->par_angle, pa.data(), sizeof(double) * pa.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = launch_airy_table(obs->airy, n_tab, dx, nullptr);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&obs->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -559,6 +571,8 @@ ItemArgs item_args(psc_ctx* ctx, psc_obs* obs, const double* offsets, int item_b
     a.n_items = n_items;
     a.n_ant = obs->n_ant;
     a.n_pol = obs->n_pol;
+    a.n_chan = obs->n_chan;
+    a.par_angle = obs->par_angle;
     a.offsets = offsets;
     a.freq = obs->freq;
     a.grid = ctx->grid;
@@ -703,6 +717,8 @@ PSC_API psc_status psc_image_gradient(psc_ctx* ctx, psc_obs* obs, const double* 
     if (!image_grad_out_dev || ((!vis_obs_dev || !weight_dev) && obs->n_vis > 0))
         return fail(ctx, PSC_E_ARG, "null data or output");
     if (ctx->s != 16) return fail(ctx, PSC_E_UNSUPPORTED, "the image gradient is built for support 16");
+    if (obs->par_angle)
+        return fail(ctx, PSC_E_UNSUPPORTED, "the image gradient is built for sky-frame offsets");
     const int n = ctx->n;
     const size_t np = (size_t)(n + ctx->s) * (n + ctx->s);
     if (!ctx->rgrid) {
@@ -769,6 +785,9 @@ PSC_API psc_status psc_set_degrid(psc_obs* obs, int32_t variant)
         return fail(obs->ctx, PSC_E_ARG, "unknown degrid variant");
     if (obs->ctx->s != 16 && variant != PSC_DEGRID_WINDOW)
         return fail(obs->ctx, PSC_E_UNSUPPORTED, "support 32 degrids in the window form only");
+    if (obs->par_angle && variant != PSC_DEGRID_WINDOW)
+        return fail(obs->ctx, PSC_E_UNSUPPORTED,
+                    "mount-frame offsets (parallactic angles) degrid in the window form only");
     if (obs->graph) {  // a captured solve graph holds the old kernels
         (void)hipGraphExecDestroy(obs->graph);
         obs->graph = nullptr;
@@ -799,7 +818,7 @@ PSC_API psc_status psc_tune(psc_ctx* ctx, psc_obs* obs, const double* offsets_de
     int32_t best_v = obs->degrid;
     const int32_t keep = obs->degrid;
     for (int32_t v = PSC_DEGRID_VALU; v <= PSC_DEGRID_WINDOW && e == hipSuccess; ++v) {
-        if (ctx->s != 16 && v != PSC_DEGRID_WINDOW) {
+        if ((ctx->s != 16 || obs->par_angle) && v != PSC_DEGRID_WINDOW) {
             if (times_us_out) times_us_out[v] = -1.0;  // not available at this support
             continue;
         }

@@ -206,6 +206,28 @@ __device__ __forceinline__ void image_products(const ItemArgs& a, const Item& it
     }
 }
 
+// Image-plane products at one image sample for one visibility, from the two
+// antennas' offsets relative to the sample (dl_i, dm_i), (dl_j, dm_j) and the
+// taper value c there, in the variant order of image_products.
+template <int MODE>
+__device__ __forceinline__ void mf_products(const ItemArgs& a, float kk, float inv_s2, float dli, float dmi,
+                                            float dlj, float dmj, float c, float (&g)[mode_nv(MODE)])
+{
+    float ei, eil, eim, ej, ejl, ejm;
+    efp(a, kk, inv_s2, dli, dmi, ei, eil, eim);
+    efp(a, kk, inv_s2, dlj, dmj, ej, ejl, ejm);
+    if constexpr (mode_nv(MODE) == 1) {
+        g[0] = ei * ej * c;
+    } else {
+        constexpr int o = (MODE == kGrad) ? 1 : 0;
+        if constexpr (MODE == kGrad) g[0] = ei * ej * c;
+        g[o + 0] = eil * ej * c;
+        g[o + 1] = eim * ej * c;
+        g[o + 2] = ei * ejl * c;
+        g[o + 3] = ei * ejm * c;
+    }
+}
+
 // Per-sample terms of the float64 sums.  Gradient: lane t < 12 of a sample's
 // lane group adds term t = 6 * end + c, end 0 for antenna i and 1 for j, c
 // indexing chi, g_l, g_m, H_ll, H_lm, H_mm = w Re(conj(x) y) with

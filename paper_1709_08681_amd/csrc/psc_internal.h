@@ -52,7 +52,7 @@ struct ItemArgs {
     const Group* groups;
     const VisEnt* vis;
     int32_t item_begin, n_items;
-    int32_t n_ant, n_pol;
+    int32_t n_ant, n_pol, n_chan;
     const double* offsets;      // [n_int][n_pol][n_ant][2]
     const double* freq;         // [n_chan]
     const float2* grid;         // V^{M0}, [N+S][N+S], last S rows/columns repeat the first
@@ -76,6 +76,7 @@ struct ItemArgs {
     double* partials;           // [item][pol][ncontrib]
     const int32_t* done;        // nullable: per-interval skip flags
     double2* grid_acc;          // grid mode: residual grid, (N+S) x (N+S), float64 sums
+    const double* par_angle;    // nullable [n_row]: offsets in the mount frame (window form)
     int32_t use_mfma;           // degrid on the matrix cores (gradient and adjoint)
 };
 
@@ -127,7 +128,7 @@ __host__ __device__ inline int win_max_units(int oversample)
     return (oversample == 1 ? 1 : oversample * oversample / 2 + 2) * kWinChunks;
 }
 hipError_t launch_win(int mode, int support, const ItemArgs& a, hipStream_t s);
-size_t win_lds_bytes(int support, int mode, int waves, int m, int oversample);
+size_t win_lds_bytes(int support, int mode, int waves, int m, int oversample, bool mount_frame = false);
 size_t win_lds_budget(int support);
 hipError_t launch_reduce(int ncontrib, const ReduceArgs& a, hipStream_t s);
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s);

@@ -33,7 +33,13 @@ namespace psc {
 // window, the slot transforms it through its own S x (S+1) LDS tile (columns,
 // then rows), and lane c then sums over the image samples n whose m index is
 // congruent to c modulo S.  Sums are kept per unit and added in unit order.
-template <int S, int MODE, int W>
+//
+// MF: offsets in the antenna mount frame.  Each row has its own parallactic
+// angle chi, so each sample has its own beam centres p = R(chi) (q + squint)
+// and its own image-plane products: they are evaluated inside the image-sample
+// sum instead of once per item, and the offset derivatives are rotated back to
+// the mount frame, dV/dq = R(chi)^T dV/dp.
+template <int S, int MODE, int W, bool MF>
 __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
 {
     constexpr int NV = mode_nv(MODE);
@@ -60,7 +66,8 @@ __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
     constexpr int kChunks = kWinChunks;
     double* gpart = reinterpret_cast<double*>(smem);  // [unit][NC]
     float* gsh = reinterpret_cast<float*>(smem + sizeof(double) * (NC > 0 ? NC : 1) * win_max_units(a.oversample));
-    float2* wtile = reinterpret_cast<float2*>(reinterpret_cast<unsigned char*>(gsh) + sizeof(float) * NV * m2p);
+    float2* wtile = reinterpret_cast<float2*>(reinterpret_cast<unsigned char*>(gsh) +
+                                              (MF ? 0 : sizeof(float) * NV * m2p));
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int per_xcd = gridDim.x >> 3;
@@ -93,6 +100,17 @@ __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
     const int jm1 = m1_ok ? c - S + half_m : 0;
     float2 pm0 = zero, pm1 = zero;
 
+    // mount frame: beam constants of the item's channel, and the lane's two
+    // image-sample m coordinates with their taper values
+    const double lam = kCLight / a.freq[it.chan];
+    const float kk = (float)(kPi * a.dish / lam);
+    const double sigma = a.gauss_sigma_ld * lam / a.dish;
+    const float inv_s2 = (float)(1.0 / (sigma * sigma));
+    const float hstep = (float)a.h;
+    const float mm0 = (float)(jm0 - half_m) * hstep, mm1 = (float)(jm1 - half_m) * hstep;
+    const float ctm0 = a.taper_img[jm0], ctm1 = a.taper_img[jm1];
+    double qil = 0, qim = 0, qjl = 0, qjm = 0;
+
     // per-axis phases (-1)^n exp(2 pi i f n / (S O)) / S, n in [-M/2, M/2), of
     // the group's offset f (part 0) or of -f (part 1), written by the slot
     auto set_phases = [&](int f, int part) {
@@ -117,7 +135,18 @@ __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
 
     for (int pol = 0; pol < a.n_pol; ++pol) {
         if (tid == 0) next_group = NW;
-        image_products<MODE, kInterleave>(a, it, pol, gsh, m2p, tid, kBlock);
+        if constexpr (MF) {
+            // mount-frame offsets plus squint (along the mount's first axis)
+            const double sq = (pol == 0 ? 1.0 : -1.0) * a.squint_frac * 1.02899 * lam / a.dish;
+            const double* oi = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.ai) * 2;
+            const double* oj = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.aj) * 2;
+            qil = oi[0] + sq;
+            qim = oi[1];
+            qjl = oj[0] + sq;
+            qjm = oj[1];
+        } else {
+            image_products<MODE, kInterleave>(a, it, pol, gsh, m2p, tid, kBlock);
+        }
         __syncthreads();
 
         const int n_units = (it.grp_end - it.grp_begin) * kChunks;
@@ -188,6 +217,29 @@ __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
                 float2 s[NV];
 #pragma unroll
                 for (int k = 0; k < NV; ++k) s[k] = zero;
+                float cs = 1.f, sn = 0.f;
+                if constexpr (MF) {
+                    // this row's beam centres on the sky
+                    sincosf((float)a.par_angle[e.vidx / (uint32_t)a.n_chan], &sn, &cs);
+                    const float pil = (float)(cs * qil - sn * qim), pim = (float)(sn * qil + cs * qim);
+                    const float pjl = (float)(cs * qjl - sn * qjm), pjm = (float)(sn * qjl + cs * qjm);
+#pragma unroll 2
+                    for (int jl = 0; jl < m; ++jl) {
+                        const int bl = (jl - half_m) & (S - 1);
+                        const float2 t = cmul(ph[jl * NW], wt[bl * SP + c]);
+                        const float2 z0 = cmul(t, pm0), z1 = cmul(t, pm1);
+                        const float l = (float)(jl - half_m) * hstep;
+                        const float ctl = a.taper_img[jl];
+                        float g0[NV], g1[NV];
+                        mf_products<MODE>(a, kk, inv_s2, l - pil, mm0 - pim, l - pjl, mm0 - pjm, ctl * ctm0, g0);
+                        mf_products<MODE>(a, kk, inv_s2, l - pil, mm1 - pim, l - pjl, mm1 - pjm, ctl * ctm1, g1);
+#pragma unroll
+                        for (int k = 0; k < NV; ++k) {
+                            s[k].x = fmaf(g0[k], z0.x, fmaf(g1[k], z1.x, s[k].x));
+                            s[k].y = fmaf(g0[k], z0.y, fmaf(g1[k], z1.y, s[k].y));
+                        }
+                    }
+                } else {
 #pragma unroll 4
                 for (int jl = 0; jl < m; ++jl) {
                     const int bl = (jl - half_m) & (S - 1);
@@ -204,6 +256,7 @@ __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
                         s[k].y = fmaf(g0, z0.y, fmaf(g1, z1.y, s[k].y));
                     }
                 }
+                }
                 // sum over the slot's S lanes
 #pragma unroll
                 for (int k = 0; k < NV; ++k) {
@@ -212,6 +265,16 @@ __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
                     if constexpr (S == 32) {
                         s[k].x += __shfl_xor(s[k].x, 16);
                         s[k].y += __shfl_xor(s[k].y, 16);
+                    }
+                }
+                if constexpr (MF && MODE != kPredict) {
+                    // derivatives with respect to the mount-frame offsets
+                    constexpr int d0 = (MODE == kGrad) ? 1 : 0;
+#pragma unroll
+                    for (int end = 0; end < 2; ++end) {
+                        const float2 dl = s[d0 + 2 * end], dm = s[d0 + 2 * end + 1];
+                        s[d0 + 2 * end] = make_float2(cs * dl.x + sn * dm.x, cs * dl.y + sn * dm.y);
+                        s[d0 + 2 * end + 1] = make_float2(cs * dm.x - sn * dl.x, cs * dm.y - sn * dl.y);
                     }
                 }
                 if (MODE == kPredict) {
@@ -244,29 +307,29 @@ __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
     }
 }
 
-template <int S, int MODE, int W>
+template <int S, int MODE, int W, bool MF>
 static hipError_t launch_win_t(const ItemArgs& a, hipStream_t s)
 {
-    const size_t sh = win_lds_bytes(S, MODE, W, a.m, a.oversample);
+    const size_t sh = win_lds_bytes(S, MODE, W, a.m, a.oversample, MF);
     if (sh > win_lds_budget(S)) return hipErrorInvalidValue;
     // raise the dynamic LDS limit once, to the largest size a valid setting needs
     static const hipError_t attr = [] {
-        const size_t shmax = std::min(win_lds_bytes(S, MODE, W, 2 * S, 16), win_lds_budget(S));
-        return hipFuncSetAttribute((const void*)k_win<S, MODE, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)shmax);
+        const size_t shmax = std::min(win_lds_bytes(S, MODE, W, 2 * S, 16, MF), win_lds_budget(S));
+        return hipFuncSetAttribute((const void*)k_win<S, MODE, W, MF>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmax);
     }();
     if (attr != hipSuccess) return attr;
     const int blocks = 8 * ((a.n_items + 7) / 8);
-    k_win<S, MODE, W><<<blocks, 64 * W, sh, s>>>(a);
+    k_win<S, MODE, W, MF><<<blocks, 64 * W, sh, s>>>(a);
     return hipGetLastError();
 }
 
-size_t win_lds_bytes(int support, int mode, int waves, int m, int oversample)
+size_t win_lds_bytes(int support, int mode, int waves, int m, int oversample, bool mount_frame)
 {
     const int nv = mode_nv(mode);
     const int nc = mode_nc(mode) > 0 ? mode_nc(mode) : 1;
     const int m2p = (m * m + 3) & ~3;
-    return sizeof(double) * nc * win_max_units(oversample) + sizeof(float) * nv * m2p +
+    return sizeof(double) * nc * win_max_units(oversample) + (mount_frame ? 0 : sizeof(float) * nv * m2p) +
            sizeof(float2) * (size_t)waves * 64 * (support + 1);
 }
 
@@ -280,19 +343,20 @@ size_t win_lds_budget(int support)
 hipError_t launch_win(int mode, int support, const ItemArgs& a, hipStream_t s)
 {
     if (a.n_items <= 0) return hipSuccess;
+    const bool mf = a.par_angle != nullptr;
     if (support == 16) {
         switch (mode) {
-        case kPredict: return launch_win_t<16, kPredict, kWinWaves>(a, s);
-        case kGrad: return launch_win_t<16, kGrad, kWinWaves>(a, s);
-        case kVjp: return launch_win_t<16, kVjp, kWinWaves>(a, s);
+        case kPredict: return mf ? launch_win_t<16, kPredict, kWinWaves, true>(a, s) : launch_win_t<16, kPredict, kWinWaves, false>(a, s);
+        case kGrad: return mf ? launch_win_t<16, kGrad, kWinWaves, true>(a, s) : launch_win_t<16, kGrad, kWinWaves, false>(a, s);
+        case kVjp: return mf ? launch_win_t<16, kVjp, kWinWaves, true>(a, s) : launch_win_t<16, kVjp, kWinWaves, false>(a, s);
         default: return hipErrorInvalidValue;
         }
     }
     if (support == 32) {
         switch (mode) {
-        case kPredict: return launch_win_t<32, kPredict, kWinWaves>(a, s);
-        case kGrad: return launch_win_t<32, kGrad, kWinWaves>(a, s);
-        case kVjp: return launch_win_t<32, kVjp, kWinWaves>(a, s);
+        case kPredict: return mf ? launch_win_t<32, kPredict, kWinWaves, true>(a, s) : launch_win_t<32, kPredict, kWinWaves, false>(a, s);
+        case kGrad: return mf ? launch_win_t<32, kGrad, kWinWaves, true>(a, s) : launch_win_t<32, kGrad, kWinWaves, false>(a, s);
+        case kVjp: return mf ? launch_win_t<32, kVjp, kWinWaves, true>(a, s) : launch_win_t<32, kVjp, kWinWaves, false>(a, s);
         default: return hipErrorInvalidValue;
         }
     }

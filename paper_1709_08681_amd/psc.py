@@ -52,6 +52,7 @@ class ObsDesc(C.Structure):
         ("n_ant", C.c_int32), ("n_chan", C.c_int32), ("n_pol", C.c_int32), ("n_int", C.c_int32),
         ("n_row", C.c_int64), ("int_row_ptr", C.c_void_p), ("ant1", C.c_void_p),
         ("ant2", C.c_void_p), ("uv_m", C.c_void_p), ("freq_hz", C.c_void_p),
+        ("par_angle", C.c_void_p),
     ]
 
 
@@ -225,10 +226,12 @@ class Session:
     """Context + planned observation living on one GPU.
 
     ``obs`` is a :class:`paper_1709_08681_amd.synth.Observation`.  Device
-    tensors of the geometry are kept alive for the session's lifetime.
+    tensors of the geometry are kept alive for the session's lifetime.  With
+    ``mount_frame`` the offsets are in the antenna mount frame and every row's
+    parallactic angle (``obs.par_angle``) carries them onto the sky.
     """
 
-    def __init__(self, obs, device=0, image=None, **cfg_overrides):
+    def __init__(self, obs, device=0, image=None, mount_frame=False, **cfg_overrides):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libpsc needs a ROCm GPU; none is visible")
@@ -248,9 +251,12 @@ class Session:
             self.g_a2 = t(obs.ant2, torch.int32)
             self.g_uv = t(obs.uv_m, torch.float64)
             self.g_fr = t(obs.freq_hz, torch.float64)
+            # mount-frame offsets: every row's parallactic angle
+            self.g_pa = t(obs.par_angle, torch.float64) if mount_frame else None
             desc = ObsDesc(obs.n_ant, obs.n_chan, obs.n_pol, obs.n_int, obs.n_row,
                            self.g_ptr.data_ptr(), self.g_a1.data_ptr(), self.g_a2.data_ptr(),
-                           self.g_uv.data_ptr(), self.g_fr.data_ptr())
+                           self.g_uv.data_ptr(), self.g_fr.data_ptr(),
+                           self.g_pa.data_ptr() if mount_frame else None)
             self.handle = psc_obs_create(self.ctx, desc)
         except Exception:
             self.close()

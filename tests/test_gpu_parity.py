@@ -623,3 +623,110 @@ def test_image_gradient_cfg2_full_size(torch_dev):
         _check_image_gradient(torch, obs, prob, s, start, v, 1.0, 56, 29)
     finally:
         s.close()
+
+
+# ---------------------------------------------------------------------------
+# offsets in the antenna mount frame (per-row parallactic angle)
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def mount(torch_dev):
+    """Ten-minute timesteps over 2.3 hours (the parallactic angle sweeps
+    tens of degrees), two polarisations with squint, uneven intervals."""
+    lengths = [5, 3, 6]
+    wl = synth.workload(1, n_ant=7, n_time=sum(lengths), dt_s=600.0, interval_lengths=lengths, n_pol=2,
+                        squint_frac=0.03, freqs_hz=np.array([1.2e9, 1.6e9]), n_src=5)
+    obs = synth.make_observation(wl, 93)
+    prob = oracle.Problem.from_observation(obs, mount_frame=True)
+    s = session(obs, mount_frame=True)
+    yield obs, prob, s
+    s.close()
+
+
+def test_mount_frame_predict_gradient_vjp(torch_dev, mount):
+    torch = torch_dev
+    from paper_1709_08681_amd import psc
+    obs, prob, s = mount
+    print("case: mount frame predict/gradient/vjp", flush=True)
+    pa = obs.par_angle
+    assert np.ptp(pa) > 0.3
+    assert psc.psc_get_degrid(s.handle) == psc.DEGRID_WINDOW
+    for variant in (psc.DEGRID_VALU, psc.DEGRID_MFMA):
+        with pytest.raises(psc.PscError) as ei:
+            psc.psc_set_degrid(s.handle, variant)
+        assert ei.value.status == psc.PSC_E_UNSUPPORTED
+    start = synth.perturbed_offsets(obs, 25.0, 33)
+    assert rel(s.predict(start).cpu().numpy(), oracle.predict(prob, start)) <= 1e-5
+    v = oracle.predict(prob, obs.offsets_true)
+    ref, vm_ref = oracle.gradient(prob, start, v, 1.0, want_model=True)
+    w1 = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+    acc, vm = s.gradient(s.offsets(start), c64(torch, s, v), w1, want_model=True)
+    assert rel(vm.cpu().numpy(), vm_ref) <= 1e-5
+    acc = acc.cpu().numpy()
+    for k in range(6):
+        assert rel(acc[..., k], ref[..., k]) <= 1e-4, k
+    rng = np.random.default_rng(34)
+    G = (rng.normal(size=s.vis_shape) + 1j * rng.normal(size=s.vis_shape)).astype(np.complex64)
+    _, dv = oracle.predict(prob, start, want_grad=True)
+    gref = np.zeros(s.off_shape)
+    for r in range(obs.n_row):
+        it = np.searchsorted(obs.int_row_ptr, r, side="right") - 1
+        i, j = obs.ant1[r], obs.ant2[r]
+        for c in range(obs.n_chan):
+            for p in range(obs.n_pol):
+                g = np.complex128(G[r, c, p])
+                for ax in range(2):
+                    gref[it, p, i, ax] += (np.conj(g) * dv[r, c, p, ax]).real
+                    gref[it, p, j, ax] += (np.conj(g) * dv[r, c, p, 2 + ax]).real
+    got = s.vjp(s.offsets(start), torch.as_tensor(G, device=s.dev)).cpu().numpy()
+    assert rel(got, gref) <= 1e-4
+    out = torch.empty((obs.grid_n, obs.grid_n), dtype=torch.float64, device=s.dev)
+    with pytest.raises(psc.PscError) as ei:
+        psc.psc_image_gradient(s.ctx, s.handle, s.offsets(start), c64(torch, s, v), w1, out)
+    assert ei.value.status == psc.PSC_E_UNSUPPORTED
+
+
+def test_mount_frame_solve(torch_dev, mount):
+    """Algorithm 1 solving for mount-frame offsets: offsets within 0.1 arcsec
+    of the oracle's after the same iterations, plain and graph forms equal,
+    and noiseless recovery of the injected offsets."""
+    torch = torch_dev
+    from paper_1709_08681_amd import psc
+    obs, prob, s = mount
+    print("case: mount frame solve", flush=True)
+    v = oracle.predict(prob, obs.offsets_true)
+    start = synth.perturbed_offsets(obs, 25.0, 35)
+    ref_off, its_ref = oracle.solve(prob, v, 1.0, start, gain=0.5, n_max=8, tol_rad=1e-3 * ARCSEC)
+    w1 = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+    outs = []
+    for form in (psc.SOLVE_PLAIN, psc.SOLVE_GRAPH):
+        off = s.offsets(start)
+        its = s.solve(c64(torch, s, v), w1, off, gain=0.5, n_max=8, tol_rad=1e-3 * ARCSEC, form=form)
+        assert np.array_equal(its.cpu().numpy(), its_ref)
+        outs.append(off.cpu().numpy())
+        assert np.abs(outs[-1] - ref_off).max() / ARCSEC <= 0.1
+    assert np.array_equal(outs[0], outs[1])
+    off = s.offsets(start)
+    s.solve(c64(torch, s, v), w1, off, gain=0.5, n_max=80, tol_rad=1e-5 * ARCSEC)
+    assert np.abs(off.cpu().numpy() - obs.offsets_true).max() / ARCSEC <= 0.05
+
+
+def test_mount_frame_support32(torch_dev, cfg5_subset):
+    """Mount-frame offsets on the support-32 large-workload subset."""
+    torch = torch_dev
+    obs, _, s0 = cfg5_subset
+    print("case: mount frame support 32", flush=True)
+    prob = oracle.Problem.from_observation(obs, mount_frame=True)
+    s = session(obs, mount_frame=True)
+    try:
+        start = synth.perturbed_offsets(obs, 30.0, 36)
+        assert rel(s.predict(start).cpu().numpy(), oracle.predict(prob, start)) <= 1e-5
+        v = oracle.predict(prob, obs.offsets_true)
+        ref = oracle.gradient(prob, start, v, 1.0)
+        w1 = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+        acc = s.gradient(s.offsets(start), c64(torch, s, v), w1).cpu().numpy()
+        live = obs.int_row_ptr[1:] > obs.int_row_ptr[:-1]
+        for k in range(6):
+            assert rel(acc[live][..., k], ref[live][..., k]) <= 1e-4, k
+    finally:
+        s.close()
