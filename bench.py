@@ -17,6 +17,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -133,11 +135,40 @@ def image_gradient_timing(s, obs, off, v_obs, w, reps, stream):
             "grid": f"{n}^2", "note": "table form, support 16"}
 
 
+def mount_frame_timing(obs, start, reps, device=0):
+    """psc_gradient with offsets in the antenna mount frame (every row's
+    parallactic angle): window form with per-sample image-plane products."""
+    import torch
+    from paper_1709_08681_amd import psc as P
+    s = P.Session(obs, device=device, mount_frame=True)
+    try:
+        stream = torch.cuda.current_stream()
+        v = s.predict(s.offsets(obs.offsets_true))
+        w = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+        off = s.offsets(start)
+        acc = torch.empty(s.off_shape[:3] + (6,), dtype=torch.float64, device=s.dev)
+        P.psc_gradient(s.ctx, s.handle, off, v, w, acc, None, stream)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            P.psc_gradient(s.ctx, s.handle, off, v, w, acc, None, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        pa = obs.par_angle
+        return {"ms_per_gradient": ms, "vis_per_s": obs.n_vis / (ms * 1e-3), "calls": reps,
+                "par_angle_range_deg": [float(np.degrees(pa.min())), float(np.degrees(pa.max()))],
+                "note": "window form, per-sample image-plane products"}
+    finally:
+        s.close()
+
+
 def cpu_baseline(obs, start, seconds):
     """The oracle (FP64 direct sum) on the host cores: gradient + update
     iterations for about `seconds`, over the whole workload or, when one
     iteration would take far longer, over its first timesteps."""
-    import numpy as np
     import oracle
     n_src = len(obs.src_flux) + (0 if obs.extra_flux is None else len(obs.extra_flux))
     budget = 5e8  # visibility x pixel terms, about 10 s of the oracle on 16 cores
@@ -182,6 +213,7 @@ def main():
     ap.add_argument("--batched-iters", type=int, default=3)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-image-gradient", action="store_true")
+    ap.add_argument("--no-mount-frame", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only; the hot path is sharded by solution "
@@ -189,7 +221,6 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_1709_08681_amd import synth
     from paper_1709_08681_amd import psc as P
@@ -277,6 +308,9 @@ def main():
         print("bench: image gradient", file=sys.stderr, flush=True)
         out["image_gradient"] = image_gradient_timing(s, obs, off, v_obs, w, 5, stream)
     s.close()
+    if not args.no_mount_frame:
+        print("bench: mount-frame offsets", file=sys.stderr, flush=True)
+        out["mount_frame"] = mount_frame_timing(obs, start, 3)
     if not args.no_batched:
         print(f"bench: batched vs plain on workload {args.batched_config}", file=sys.stderr,
               flush=True)
