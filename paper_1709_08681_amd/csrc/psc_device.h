@@ -130,8 +130,8 @@ __device__ __forceinline__ void fft_reg(float2 (&x)[S])
 // Far-field voltage pattern of one antenna at sky offset (dl, dm) = l - p and
 // its derivatives with respect to the pointing offset p (float32; the Airy
 // pattern from the cubic Hermite table, the Gaussian in closed form).
-__device__ __forceinline__ void efp(const ItemArgs& a, float kk, float inv_s2, float dl, float dm,
-                                    float& e, float& el, float& em)
+__device__ __forceinline__ void efp(const ItemArgs& a, const float4* tab, float kk, float inv_s2, float dl,
+                                    float dm, float& e, float& el, float& em)
 {
     if (a.illum == 1) {
         e = expf(-0.5f * (dl * dl + dm * dm) * inv_s2);
@@ -149,7 +149,7 @@ __device__ __forceinline__ void efp(const ItemArgs& a, float kk, float inv_s2, f
         i = (int)u;
     }
     const float t = u - (float)i;
-    const float4 p0 = a.airy[i], p1 = a.airy[i + 1];
+    const float4 p0 = tab[i], p1 = tab[i + 1];
     const float t2 = t * t, t3 = t2 * t;
     const float h00 = 2.f * t3 - 3.f * t2 + 1.f, h10 = t3 - 2.f * t2 + t, h01 = -2.f * t3 + 3.f * t2,
                 h11 = t3 - t2;
@@ -189,8 +189,8 @@ __device__ __forceinline__ void image_products(const ItemArgs& a, const Item& it
         const int il = idx / m, im = idx - il * m;
         const float l = (float)(il - half_m) * hstep, mm = (float)(im - half_m) * hstep;
         float ei, eil, eim, ej, ejl, ejm;
-        efp(a, kk, inv_s2, l - pil, mm - pim, ei, eil, eim);
-        efp(a, kk, inv_s2, l - pjl, mm - pjm, ej, ejl, ejm);
+        efp(a, a.airy, kk, inv_s2, l - pil, mm - pim, ei, eil, eim);
+        efp(a, a.airy, kk, inv_s2, l - pjl, mm - pjm, ej, ejl, ejm);
         const float c = a.taper_img[il] * a.taper_img[im];
         float* gn = gsh + (INTERLEAVED ? idx * NV : idx);
         if (NV == 1) {
@@ -210,12 +210,13 @@ __device__ __forceinline__ void image_products(const ItemArgs& a, const Item& it
 // antennas' offsets relative to the sample (dl_i, dm_i), (dl_j, dm_j) and the
 // taper value c there, in the variant order of image_products.
 template <int MODE>
-__device__ __forceinline__ void mf_products(const ItemArgs& a, float kk, float inv_s2, float dli, float dmi,
-                                            float dlj, float dmj, float c, float (&g)[mode_nv(MODE)])
+__device__ __forceinline__ void mf_products(const ItemArgs& a, const float4* tab, float kk, float inv_s2,
+                                            float dli, float dmi, float dlj, float dmj, float c,
+                                            float (&g)[mode_nv(MODE)])
 {
     float ei, eil, eim, ej, ejl, ejm;
-    efp(a, kk, inv_s2, dli, dmi, ei, eil, eim);
-    efp(a, kk, inv_s2, dlj, dmj, ej, ejl, ejm);
+    efp(a, tab, kk, inv_s2, dli, dmi, ei, eil, eim);
+    efp(a, tab, kk, inv_s2, dlj, dmj, ej, ejl, ejm);
     if constexpr (mode_nv(MODE) == 1) {
         g[0] = ei * ej * c;
     } else {

@@ -128,7 +128,9 @@ __host__ __device__ inline int win_max_units(int oversample)
     return (oversample == 1 ? 1 : oversample * oversample / 2 + 2) * kWinChunks;
 }
 hipError_t launch_win(int mode, int support, const ItemArgs& a, hipStream_t s);
-size_t win_lds_bytes(int support, int mode, int waves, int m, int oversample, bool mount_frame = false);
+// mount_frame_tab: -1 for sky-frame offsets, else the Airy table length the
+// mount-frame kernel keeps in LDS
+size_t win_lds_bytes(int support, int mode, int waves, int m, int oversample, int mount_frame_tab = -1);
 size_t win_lds_budget(int support);
 hipError_t launch_reduce(int ncontrib, const ReduceArgs& a, hipStream_t s);
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s);

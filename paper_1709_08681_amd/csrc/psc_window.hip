@@ -68,6 +68,8 @@ __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
     float* gsh = reinterpret_cast<float*>(smem + sizeof(double) * (NC > 0 ? NC : 1) * win_max_units(a.oversample));
     float2* wtile = reinterpret_cast<float2*>(reinterpret_cast<unsigned char*>(gsh) +
                                               (MF ? 0 : sizeof(float) * NV * m2p));
+    // mount frame: the Airy table, read at every image sample of every sample
+    float4* airy_sh = reinterpret_cast<float4*>(wtile + (size_t)W * 64 * SP);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int per_xcd = gridDim.x >> 3;
@@ -86,6 +88,8 @@ __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
         (void*)a.grid, (short)0, P * P * (int)sizeof(float2), 0x00020000);
 
     for (int t = tid; t < so; t += kBlock) twsh[t] = a.tw[t];
+    if constexpr (MF)
+        for (int t = tid; t < a.n_tab; t += kBlock) airy_sh[t] = a.airy[t];
 
     const int slot = lane / S;
     const int c = lane - slot * S;
@@ -231,8 +235,10 @@ __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
                         const float l = (float)(jl - half_m) * hstep;
                         const float ctl = a.taper_img[jl];
                         float g0[NV], g1[NV];
-                        mf_products<MODE>(a, kk, inv_s2, l - pil, mm0 - pim, l - pjl, mm0 - pjm, ctl * ctm0, g0);
-                        mf_products<MODE>(a, kk, inv_s2, l - pil, mm1 - pim, l - pjl, mm1 - pjm, ctl * ctm1, g1);
+                        mf_products<MODE>(a, airy_sh, kk, inv_s2, l - pil, mm0 - pim, l - pjl, mm0 - pjm,
+                                          ctl * ctm0, g0);
+                        mf_products<MODE>(a, airy_sh, kk, inv_s2, l - pil, mm1 - pim, l - pjl, mm1 - pjm,
+                                          ctl * ctm1, g1);
 #pragma unroll
                         for (int k = 0; k < NV; ++k) {
                             s[k].x = fmaf(g0[k], z0.x, fmaf(g1[k], z1.x, s[k].x));
@@ -310,27 +316,25 @@ __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
 template <int S, int MODE, int W, bool MF>
 static hipError_t launch_win_t(const ItemArgs& a, hipStream_t s)
 {
-    const size_t sh = win_lds_bytes(S, MODE, W, a.m, a.oversample, MF);
+    const size_t sh = win_lds_bytes(S, MODE, W, a.m, a.oversample, MF ? a.n_tab : -1);
     if (sh > win_lds_budget(S)) return hipErrorInvalidValue;
-    // raise the dynamic LDS limit once, to the largest size a valid setting needs
-    static const hipError_t attr = [] {
-        const size_t shmax = std::min(win_lds_bytes(S, MODE, W, 2 * S, 16, MF), win_lds_budget(S));
-        return hipFuncSetAttribute((const void*)k_win<S, MODE, W, MF>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmax);
-    }();
+    // raise the dynamic LDS limit once, to what one compute unit allows
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void*)k_win<S, MODE, W, MF>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)win_lds_budget(S));
     if (attr != hipSuccess) return attr;
     const int blocks = 8 * ((a.n_items + 7) / 8);
     k_win<S, MODE, W, MF><<<blocks, 64 * W, sh, s>>>(a);
     return hipGetLastError();
 }
 
-size_t win_lds_bytes(int support, int mode, int waves, int m, int oversample, bool mount_frame)
+size_t win_lds_bytes(int support, int mode, int waves, int m, int oversample, int mount_frame_tab)
 {
     const int nv = mode_nv(mode);
     const int nc = mode_nc(mode) > 0 ? mode_nc(mode) : 1;
     const int m2p = (m * m + 3) & ~3;
-    return sizeof(double) * nc * win_max_units(oversample) + (mount_frame ? 0 : sizeof(float) * nv * m2p) +
-           sizeof(float2) * (size_t)waves * 64 * (support + 1);
+    const bool mf = mount_frame_tab >= 0;
+    return sizeof(double) * nc * win_max_units(oversample) + (mf ? 0 : sizeof(float) * nv * m2p) +
+           sizeof(float2) * (size_t)waves * 64 * (support + 1) + (mf ? sizeof(float4) * mount_frame_tab : 0);
 }
 
 size_t win_lds_budget(int support)
