@@ -167,7 +167,7 @@ PSC_API const char* psc_last_error(const psc_ctx* ctx)
     return ctx ? ctx->err.c_str() : g_create_err.c_str();
 }
 
-PSC_API psc_status psc_create(const psc_config* cfg, psc_ctx** out)
+static psc_status create_impl(const psc_config* cfg, psc_ctx** out)
 {
     g_create_err.clear();
     if (!cfg || !out) return fail(nullptr, PSC_E_ARG, "null config or output pointer");
@@ -310,7 +310,7 @@ PSC_API psc_status psc_obs_destroy(psc_obs* obs)
     return PSC_OK;
 }
 
-PSC_API psc_status psc_obs_create(psc_ctx* ctx, const psc_obs_desc* d, psc_obs** out)
+static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs** out)
 {
     if (!ctx) return fail(nullptr, PSC_E_ARG, "null context");
     ctx->err.clear();
@@ -847,7 +847,7 @@ PSC_API psc_status psc_tune(psc_ctx* ctx, psc_obs* obs, const double* offsets_de
     return psc_set_degrid(obs, best_v);
 }
 
-PSC_API psc_status psc_solve(psc_ctx* ctx, psc_obs* obs, const void* vis_obs_dev, const float* weight_dev,
+static psc_status solve_impl(psc_ctx* ctx, psc_obs* obs, const void* vis_obs_dev, const float* weight_dev,
                              double* offsets_io_dev, double gain, int32_t n_max, double tol_rad,
                              int32_t form, int32_t* iters_out_dev, void* stream)
 {
@@ -919,6 +919,47 @@ PSC_API psc_status psc_solve(psc_ctx* ctx, psc_obs* obs, const void* vis_obs_dev
                                     hipMemcpyDeviceToDevice, s));
     PSC_HIP(ctx, hipStreamSynchronize(s));
     return PSC_OK;
+}
+
+// Host allocations in planning and solving may throw; no exception crosses the
+// C boundary.
+static psc_status host_oom(psc_ctx* ctx)
+{
+    try {
+        return fail(ctx, PSC_E_OOM, "host memory allocation failed");
+    } catch (...) {
+        return PSC_E_OOM;
+    }
+}
+
+PSC_API psc_status psc_create(const psc_config* cfg, psc_ctx** out)
+{
+    try {
+        return create_impl(cfg, out);
+    } catch (...) {
+        return host_oom(nullptr);
+    }
+}
+
+PSC_API psc_status psc_obs_create(psc_ctx* ctx, const psc_obs_desc* d, psc_obs** out)
+{
+    try {
+        return obs_create_impl(ctx, d, out);
+    } catch (...) {
+        return host_oom(ctx);
+    }
+}
+
+PSC_API psc_status psc_solve(psc_ctx* ctx, psc_obs* obs, const void* vis_obs_dev, const float* weight_dev,
+                             double* offsets_io_dev, double gain, int32_t n_max, double tol_rad,
+                             int32_t form, int32_t* iters_out_dev, void* stream)
+{
+    try {
+        return solve_impl(ctx, obs, vis_obs_dev, weight_dev, offsets_io_dev, gain, n_max, tol_rad, form,
+                          iters_out_dev, stream);
+    } catch (...) {
+        return host_oom(ctx);
+    }
 }
 
 }  // extern "C"
