@@ -253,7 +253,7 @@ def main():
         psc_gradient(s.ctx, s.handle, off, v_obs, w, acc, None, stream)
         if ev is not None:
             ev[1].record(stream)
-        psc_solve_step(s.ctx, obs.n_int, obs.n_pol, obs.n_ant, acc, 0.5, off, None, mx, stream)
+        psc_solve_step(s.ctx, obs.n_int, obs.n_pol, obs.n_ant, acc, 0.5, 0.0, off, None, mx, stream)
 
     for _ in range(args.warmup):
         step()

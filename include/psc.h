@@ -237,17 +237,21 @@ PSC_API psc_status psc_image_gradient(psc_ctx* ctx, psc_obs* obs, const double* 
 /*
  * Damped per-antenna update (async), Sec. 2.2 (a_n = a_{n-1} + f(grad)) with
  * f read as a 2x2 Gauss-Newton step scaled by the loop gain 0 < gain <= 1 of
- * Eq. SelfCal:  p_a += gain * H_a^-1 g_a  when det H_a > 1e-12 (tr H_a)^2,
- * else p_a += gain * g_k / H_kk per axis with H_kk > 0.  Antennas with
+ * Eq. SelfCal, on the Levenberg-Marquardt damped normal matrix
+ * H'_a = H_a + lm_mu diag(H_a) (lm_mu >= 0; 0 is plain Gauss-Newton):
+ * p_a += gain * H'_a^-1 g_a  when det H'_a > 1e-12 (tr H'_a)^2, else
+ * p_a += gain * g_k / H'_kk per axis with H'_kk > 0.  Antennas with
  * tr H_a <= 0 or non-finite sums keep their offsets and get not_updated = 1.
+ * psc_solve uses lm_mu = 0.
  *  acc_dev        [n_int][n_pol][n_ant][6] float64 (from psc_gradient)
  *  offsets_io_dev [n_int][n_pol][n_ant][2] float64 (updated in place)
  *  not_updated_dev nullable [n_int][n_pol][n_ant] int32
  *  max_step_dev    nullable [n_int] float64: largest |delta p| per interval
  */
 PSC_API psc_status psc_solve_step(psc_ctx* ctx, int32_t n_int, int32_t n_pol, int32_t n_ant,
-                                  const double* acc_dev, double gain, double* offsets_io_dev,
-                                  int32_t* not_updated_dev, double* max_step_dev, void* stream);
+                                  const double* acc_dev, double gain, double lm_mu,
+                                  double* offsets_io_dev, int32_t* not_updated_dev,
+                                  double* max_step_dev, void* stream);
 
 /*
  * Degrid variants (results agree to float32 rounding; each is deterministic

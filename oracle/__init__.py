@@ -78,7 +78,8 @@ def _load():
             lib.oracle_predict.argtypes = [P, dp, dp, dp]
             lib.oracle_gradient.argtypes = [P, dp, dp, dp, dp, dp]
             lib.oracle_image_gradient.argtypes = [P, dp, dp, dp, C.c_int, dp, dp, dp]
-            lib.oracle_solve_step.argtypes = [C.c_int, C.c_int, C.c_int, dp, C.c_double, dp, ip, dp, ip]
+            lib.oracle_solve_step.argtypes = [C.c_int, C.c_int, C.c_int, dp, C.c_double, C.c_double, dp, ip,
+                                              dp, ip]
             lib.oracle_solve.argtypes = [P, dp, dp, dp, C.c_double, C.c_int, C.c_double, ip]
             for name in ("oracle_predict", "oracle_gradient", "oracle_image_gradient",
                          "oracle_solve_step", "oracle_solve",
@@ -232,8 +233,9 @@ def image_gradient(prob: Problem, offsets, vis_obs, weight, pix_l, pix_m):
     return out
 
 
-def solve_step(acc, gain, offsets, done=None):
-    """Returns (new offsets, not_updated [n_int,n_pol,n_ant], max_step [n_int])."""
+def solve_step(acc, gain, offsets, done=None, mu=0.0):
+    """Returns (new offsets, not_updated [n_int,n_pol,n_ant], max_step [n_int]).
+    mu >= 0 damps the diagonal of each 2x2 normal matrix (H + mu diag H)."""
     lib = _load()
     acc = np.ascontiguousarray(acc, np.float64)
     n_int, n_pol, n_ant = acc.shape[:3]
@@ -241,7 +243,7 @@ def solve_step(acc, gain, offsets, done=None):
     nu = np.zeros((n_int, n_pol, n_ant), np.int32)
     mx = np.zeros(n_int)
     d = None if done is None else np.ascontiguousarray(done, np.int32)
-    _check(lib.oracle_solve_step(n_int, n_pol, n_ant, _dp(acc), float(gain), _dp(o), _ip(nu),
+    _check(lib.oracle_solve_step(n_int, n_pol, n_ant, _dp(acc), float(gain), float(mu), _dp(o), _ip(nu),
                                  _dp(mx), _ip(d)), "solve_step")
     return o, nu, mx
 

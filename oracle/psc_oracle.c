@@ -459,24 +459,27 @@ int oracle_image_gradient(const orc_problem* p, const double* offsets, const dou
 
 /*
  * Damped per-antenna update.  For each (interval, pol, antenna) with sums
- * (chi, g, H): delta = gamma H^-1 g when H is well conditioned
- * (det > 1e-12 tr^2), else gamma g_k / H_kk per axis with H_kk > 0; an
+ * (chi, g, H), H' = H + mu diag(H) (mu >= 0, Levenberg-Marquardt damping; 0
+ * is the plain Gauss-Newton step): delta = gamma H'^-1 g when H' is well
+ * conditioned (det > 1e-12 tr^2), else gamma g_k / H'_kk per axis with
+ * H'_kk > 0; an
  * antenna with tr H <= 0 (no unflagged data) or non-finite sums is left as is
  * and marked in not_updated.  max_step_out[s] receives the largest |delta| of
  * interval s.  Intervals whose done[s] is non-zero are skipped.
  */
-int oracle_solve_step(int n_int, int n_pol, int n_ant, const double* acc, double gain,
+int oracle_solve_step(int n_int, int n_pol, int n_ant, const double* acc, double gain, double mu,
                       double* offsets_io, int32_t* not_updated, double* max_step_out,
                       const int32_t* done)
 {
-    if (n_int < 1 || n_pol < 1 || n_ant < 1 || !(gain > 0.0)) return -1;
+    if (n_int < 1 || n_pol < 1 || n_ant < 1 || !(gain > 0.0) || !(mu >= 0.0) || !isfinite(mu)) return -1;
     for (int s = 0; s < n_int; ++s) {
         double mx = 0.0;
         for (int pol = 0; pol < n_pol; ++pol) {
             for (int a = 0; a < n_ant; ++a) {
                 size_t k = ((size_t)s * n_pol + pol) * n_ant + a;
                 const double* t = acc + 6 * k;
-                double gl = t[1], gm = t[2], hll = t[3], hlm = t[4], hmm = t[5];
+                /* Levenberg-Marquardt damping of the diagonal: H + mu diag(H) */
+                double gl = t[1], gm = t[2], hll = t[3] * (1.0 + mu), hlm = t[4], hmm = t[5] * (1.0 + mu);
                 int skip = (done && done[s]);
                 double tr = hll + hmm;
                 int bad = !(isfinite(gl) && isfinite(gm) && isfinite(hll) && isfinite(hlm) &&
@@ -529,7 +532,7 @@ int oracle_solve(const orc_problem* p, const double* vis_obs, const double* weig
     for (int it = 0; it < n_max; ++it) {
         rc = oracle_gradient(p, offsets_io, vis_obs, weight, acc, NULL);
         if (rc) break;
-        rc = oracle_solve_step(p->n_int, p->n_pol, p->n_ant, acc, gain, offsets_io, NULL, mx, done);
+        rc = oracle_solve_step(p->n_int, p->n_pol, p->n_ant, acc, gain, 0.0, offsets_io, NULL, mx, done);
         if (rc) break;
         int all = 1;
         for (int s = 0; s < p->n_int; ++s) {

@@ -39,7 +39,7 @@ int oracle_gradient(const orc_problem* p, const double* offsets, const double* v
 int oracle_image_gradient(const orc_problem* p, const double* offsets, const double* vis_obs,
                           const double* weight, int n_pix, const double* pix_l, const double* pix_m,
                           double* out);
-int oracle_solve_step(int n_int, int n_pol, int n_ant, const double* acc, double gain,
+int oracle_solve_step(int n_int, int n_pol, int n_ant, const double* acc, double gain, double mu,
                       double* offsets_io, int32_t* not_updated, double* max_step_out,
                       const int32_t* done);
 int oracle_solve(const orc_problem* p, const double* vis_obs, const double* weight,

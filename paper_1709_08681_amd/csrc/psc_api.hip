@@ -754,7 +754,7 @@ PSC_API psc_status psc_image_gradient(psc_ctx* ctx, psc_obs* obs, const double* 
 }
 
 PSC_API psc_status psc_solve_step(psc_ctx* ctx, int32_t n_int, int32_t n_pol, int32_t n_ant,
-                                  const double* acc_dev, double gain, double* offsets_io_dev,
+                                  const double* acc_dev, double gain, double lm_mu, double* offsets_io_dev,
                                   int32_t* not_updated_dev, double* max_step_dev, void* stream)
 {
     if (!ctx) return fail(nullptr, PSC_E_ARG, "null context");
@@ -762,6 +762,7 @@ PSC_API psc_status psc_solve_step(psc_ctx* ctx, int32_t n_int, int32_t n_pol, in
     if (n_int < 1 || n_pol < 1 || n_pol > 2 || n_ant < 1) return fail(ctx, PSC_E_ARG, "bad sizes");
     if (!acc_dev || !offsets_io_dev) return fail(ctx, PSC_E_ARG, "null array");
     if (!(gain > 0.0) || !(gain <= 1.0)) return fail(ctx, PSC_E_ARG, "gain must be in (0, 1]");
+    if (!(lm_mu >= 0.0) || !isfinite(lm_mu)) return fail(ctx, PSC_E_ARG, "lm_mu must be finite and >= 0");
     PSC_HIP(ctx, hipSetDevice(ctx->cfg.device));
     SolveArgs sa{};
     sa.n_int = n_int;
@@ -771,6 +772,7 @@ PSC_API psc_status psc_solve_step(psc_ctx* ctx, int32_t n_int, int32_t n_pol, in
     sa.int_end = n_int;
     sa.acc = acc_dev;
     sa.gain = gain;
+    sa.lm_mu = lm_mu;
     sa.offsets = offsets_io_dev;
     sa.not_updated = not_updated_dev;
     sa.max_step = max_step_dev;

@@ -96,6 +96,7 @@ struct SolveArgs {
     int32_t int_begin, int_end;
     const double* acc;          // [n_int][n_pol][n_ant][6]
     double gain;
+    double lm_mu;               // Levenberg-Marquardt damping of diag(H), >= 0
     double* offsets;
     int32_t* not_updated;       // nullable
     double* max_step;           // nullable

@@ -769,7 +769,9 @@ __global__ void __launch_bounds__(256) k_solve(SolveArgs a)
     for (int pa = tid; pa < npa; pa += blockDim.x) {
         const size_t k = (size_t)s * npa + pa;
         const double* t = a.acc + 6 * k;
-        const double gl = t[1], gm = t[2], hll = t[3], hlm = t[4], hmm = t[5];
+        // H + mu diag(H) (mu = 0: the plain Gauss-Newton step)
+        const double gl = t[1], gm = t[2], hll = t[3] * (1.0 + a.lm_mu), hlm = t[4];
+        const double hmm = t[5] * (1.0 + a.lm_mu);
         const double tr = hll + hmm;
         const bool bad = !(isfinite(gl) && isfinite(gm) && isfinite(hll) && isfinite(hlm) &&
                            isfinite(hmm)) || !(tr > 0.0);

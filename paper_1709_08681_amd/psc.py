@@ -83,7 +83,7 @@ def load():
             "psc_predict": ([vp, vp, vp, vp, vp], C.c_int),
             "psc_gradient": ([vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
             "psc_predict_vjp": ([vp, vp, vp, vp, vp, vp], C.c_int),
-            "psc_solve_step": ([vp, i32, i32, i32, vp, dbl, vp, vp, vp, vp], C.c_int),
+            "psc_solve_step": ([vp, i32, i32, i32, vp, dbl, dbl, vp, vp, vp, vp], C.c_int),
             "psc_solve": ([vp, vp, vp, vp, vp, dbl, i32, dbl, i32, vp, vp], C.c_int),
             "psc_set_degrid": ([vp, i32], C.c_int),
             "psc_get_degrid": ([vp, C.POINTER(i32)], C.c_int),
@@ -168,9 +168,9 @@ def psc_predict_vjp(ctx, obs, offsets_dev, grad_vis_dev, grad_offsets_dev, strea
                                   _ptr(grad_offsets_dev), _stream(stream)), ctx)
 
 
-def psc_solve_step(ctx, n_int, n_pol, n_ant, acc_dev, gain, offsets_dev, not_updated_dev=None,
+def psc_solve_step(ctx, n_int, n_pol, n_ant, acc_dev, gain, lm_mu, offsets_dev, not_updated_dev=None,
                    max_step_dev=None, stream=None):
-    _check(load().psc_solve_step(ctx, n_int, n_pol, n_ant, _ptr(acc_dev), float(gain),
+    _check(load().psc_solve_step(ctx, n_int, n_pol, n_ant, _ptr(acc_dev), float(gain), float(lm_mu),
                                  _ptr(offsets_dev), _ptr(not_updated_dev), _ptr(max_step_dev),
                                  _stream(stream)), ctx)
 
@@ -315,12 +315,12 @@ class Session:
         psc_image_gradient(self.ctx, self.handle, off, vis_obs, weight, out)
         return out
 
-    def solve_step(self, acc, gain, offsets):
+    def solve_step(self, acc, gain, offsets, lm_mu=0.0):
         torch = self.torch
         nu = torch.empty(self.off_shape[:3], dtype=torch.int32, device=self.dev)
         mx = torch.empty(self.obs.n_int, dtype=torch.float64, device=self.dev)
-        psc_solve_step(self.ctx, self.obs.n_int, self.obs.n_pol, self.obs.n_ant, acc, gain, offsets,
-                       nu, mx)
+        psc_solve_step(self.ctx, self.obs.n_int, self.obs.n_pol, self.obs.n_ant, acc, gain, lm_mu,
+                       offsets, nu, mx)
         return nu, mx
 
     def solve(self, vis_obs, weight, offsets, gain=0.5, n_max=10, tol_rad=1e-3 * ARCSEC,

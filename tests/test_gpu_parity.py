@@ -169,15 +169,16 @@ def test_solve_step_matches_oracle(torch_dev, cfg1):
     acc[1, 0, 2, 3:] = 0.0  # no data
     acc[2, 1, 4, 3:] = [1.0, 1.0, 1.0]  # singular
     off0 = rng.normal(size=(3, 2, 5, 2)) * 1e-4
-    ref, nu_ref, mx_ref = oracle.solve_step(acc, 0.5, off0)
     from paper_1709_08681_amd import psc
-    offs = torch.as_tensor(off0, device=s.dev)
-    nu = torch.empty((3, 2, 5), dtype=torch.int32, device=s.dev)
-    mx = torch.empty(3, dtype=torch.float64, device=s.dev)
-    psc.psc_solve_step(s.ctx, 3, 2, 5, torch.as_tensor(acc, device=s.dev), 0.5, offs, nu, mx)
-    np.testing.assert_allclose(offs.cpu().numpy(), ref, rtol=1e-12, atol=1e-18)
-    assert np.array_equal(nu.cpu().numpy(), nu_ref)
-    np.testing.assert_allclose(mx.cpu().numpy(), mx_ref, rtol=1e-12)
+    for mu in (0.0, 0.3, 1e6):
+        ref, nu_ref, mx_ref = oracle.solve_step(acc, 0.5, off0, mu=mu)
+        offs = torch.as_tensor(off0, device=s.dev)
+        nu = torch.empty((3, 2, 5), dtype=torch.int32, device=s.dev)
+        mx = torch.empty(3, dtype=torch.float64, device=s.dev)
+        psc.psc_solve_step(s.ctx, 3, 2, 5, torch.as_tensor(acc, device=s.dev), 0.5, mu, offs, nu, mx)
+        np.testing.assert_allclose(offs.cpu().numpy(), ref, rtol=1e-12, atol=1e-18)
+        assert np.array_equal(nu.cpu().numpy(), nu_ref)
+        np.testing.assert_allclose(mx.cpu().numpy(), mx_ref, rtol=1e-12)
 
 
 def test_solve_forms_match_oracle(torch_dev, cfg1):

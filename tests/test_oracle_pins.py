@@ -511,3 +511,20 @@ def test_mount_frame_gradient_matches_chi2_differences(oracle_lib):
         fd = (chi2(op) - chi2(om)) / (2 * h)
         g = acc[s, pol, ant, 1 + ax]
         assert abs(-0.5 * fd - g) <= 1e-6 * abs(g) + 1e-9, (s, pol, ant, ax, fd, g)
+
+
+def test_solve_step_levenberg_marquardt_damping(oracle_lib):
+    """H' = H + mu diag(H): mu = 0 is the Gauss-Newton step; a worked 2x2
+    case; large mu tends to the per-axis step g_k / (H_kk (1 + mu))."""
+    o = oracle_lib
+    acc = np.zeros((1, 1, 1, 6))
+    acc[0, 0, 0, 1:] = [1.0, -2.0, 4.0, 1.0, 3.0]  # g = (1, -2), H = [[4, 1], [1, 3]]
+    zero = np.zeros((1, 1, 1, 2))
+    gn, _, _ = o.solve_step(acc, 1.0, zero)
+    np.testing.assert_allclose(gn[0, 0, 0], np.linalg.solve([[4.0, 1.0], [1.0, 3.0]], [1.0, -2.0]),
+                               rtol=1e-15)
+    # mu = 0.5: H' = [[6, 1], [1, 4.5]], det 26, step = (4.5 + 2, -12 - 1) / 26 = (6.5, -13) / 26
+    lm, _, _ = o.solve_step(acc, 1.0, zero, mu=0.5)
+    np.testing.assert_allclose(lm[0, 0, 0], [0.25, -0.5], rtol=1e-15)
+    big, _, _ = o.solve_step(acc, 1.0, zero, mu=1e8)
+    np.testing.assert_allclose(big[0, 0, 0] * (1 + 1e8), [1.0 / 4.0, -2.0 / 3.0], rtol=1e-7)
