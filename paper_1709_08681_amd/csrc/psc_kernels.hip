@@ -296,7 +296,33 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
             }
             wave_sync();
 
-            // ---- 2-D DFT of each sub-table: rows, then columns
+            // ---- 2-D DFT of each sub-table: rows, then columns.  For the five
+            // gradient variants the 80 row and 80 column transforms run as 160
+            // tasks in three passes of 64 lanes (a variant's columns start one
+            // pass after its rows end) instead of four passes, two of them a
+            // quarter full.
+            constexpr bool kPacked = !MX && NV * S == 80 && S == 16;
+            if constexpr (kPacked) {
+#pragma unroll 1
+                for (int pass = 0; pass < 3; ++pass) {
+                    const int t = pass * 64 + lane;
+                    if (t < 2 * NV * S) {
+                        const bool is_row = t < NV * S;
+                        const int tt = is_row ? t : t - NV * S;
+                        const int k = tt / S, rc = tt - k * S;
+                        // row task: x[i] = U[k][rc][i]; column task: x[i] = U[k][i][rc]
+                        float2* base = uw + (size_t)k * S * SP + (is_row ? rc * SP : rc);
+                        const int step = is_row ? 1 : SP;
+                        float2 x[S];
+#pragma unroll
+                        for (int i = 0; i < S; ++i) x[i] = base[i * step];
+                        fft_reg<S>(x);
+#pragma unroll
+                        for (int i = 0; i < S; ++i) base[i * step] = x[i];
+                    }
+                    wave_sync();
+                }
+            } else {
             for (int t = lane; t < NV * S; t += 64) {
                 const int k = t / S, row = t - k * S;
                 float2 x[S];
@@ -359,6 +385,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
                 }
             }
             wave_sync();
+            }  // kPacked
 
             // ---- degrid.  Lane (slot, a_m) of the wavefront reads column a_m of
             // every S x S window it handles; tap (a_l, a_m) uses lattice index
