@@ -61,9 +61,7 @@ typedef struct psc_obs psc_obs;
  *  oversample    O, kernel samples per uv cell (1..16, S*O <= 512).  Each
  *                visibility's uv is rounded to the nearest 1/O cell.
  *  image_samples M, image-plane samples per axis used to build kernels, at
- *                spacing FoV/S (0 = default 3S/2; even, S..2S).  At
- *                support 32 the window form must fit one compute unit's
- *                LDS: M <= 62 at O = 8 (PSC_E_UNSUPPORTED beyond).
+ *                spacing FoV/S (0 = default 3S/2; even, S..2S).
  *  dish_diam_m   D of the uniformly illuminated circular dishes.
  *  illum         0: far-field voltage pattern 2 J1(x)/x, x = pi D |l| / lambda;
  *                1: the Gaussian main-lobe model of Sec. 3,

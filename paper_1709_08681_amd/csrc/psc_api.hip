@@ -191,10 +191,8 @@ static psc_status create_impl(const psc_config* cfg, psc_ctx** out)
     if (c.illum == 1 && !(c.gauss_sigma_ld > 0))
         return fail(nullptr, PSC_E_ARG, "gauss_sigma_ld must be positive in Gaussian mode");
     if (!isfinite(c.squint_frac)) return fail(nullptr, PSC_E_ARG, "squint_frac must be finite");
-    if (c.support == 32 && win_lds_bytes(32, kGrad, kWinWaves, m, c.oversample) > win_lds_budget(32))
-        return fail(nullptr, PSC_E_UNSUPPORTED,
-                    "support 32: image_samples and oversample exceed the LDS of one compute unit "
-                    "(image_samples <= 62 at oversample 8)");
+    if (c.support == 32 && win_lds_bytes(32, kGrad, m, c.oversample) > win_lds_budget(32))
+        return fail(nullptr, PSC_E_UNSUPPORTED, "support 32: the window form exceeds the LDS of one compute unit");
     if (hipSetDevice(c.device) != hipSuccess) return fail(nullptr, PSC_E_ARG, "invalid device");
 
     psc_ctx* ctx = new psc_ctx();

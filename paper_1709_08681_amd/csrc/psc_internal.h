@@ -116,22 +116,26 @@ hipError_t launch_zero(double2* p, size_t n, hipStream_t s);
 hipError_t launch_unpad_grid(const double2* g, double2* out, int n, int pad, hipStream_t s);
 hipError_t launch_image_grad(const double2* f, const double* taper_pix, double* out, int n, hipStream_t s);
 hipError_t launch_items(int mode, int support, const ItemArgs& a, hipStream_t s);
-// Window-form degrid (psc_window.hip), supports 16 and 32, 4 wavefronts per
-// block.  win_lds_bytes is its dynamic LDS per block, win_lds_budget the most
-// it may use (160 KiB per compute unit less the kernel's static arrays).
+// Window-form degrid (psc_window.hip).  Support 16: k_win, kWinWaves
+// wavefronts per block whose S-lane slots are the workers.  Support 32:
+// k_winw, kWinwWaves wavefronts per block, a wavefront per sample.
+// win_lds_bytes is the dynamic LDS per block, win_lds_budget the most it may
+// use (160 KiB per compute unit less the kernel's static arrays).
 constexpr int kWinWaves = 4;
-// Work units of the window form per sample group, and the most units an item
-// can have: the groups pair offsets f and -f, so an item has at most
-// O^2/2 + 2 of them (the four self-paired offsets on their own).
-constexpr int kWinChunks = 4;
-__host__ __device__ inline int win_max_units(int oversample)
+constexpr int kWinwWaves = 8;
+// Groups of an item, at most: they pair offsets f and -f, so O^2/2 + 2 (the
+// four self-paired offsets on their own).  k_win cuts each into kWinChunks
+// work units.
+__host__ __device__ inline int win_max_groups(int oversample)
 {
-    return (oversample == 1 ? 1 : oversample * oversample / 2 + 2) * kWinChunks;
+    return oversample == 1 ? 1 : oversample * oversample / 2 + 2;
 }
+constexpr int kWinChunks = 4;
+__host__ __device__ inline int win_max_units(int oversample) { return win_max_groups(oversample) * kWinChunks; }
 hipError_t launch_win(int mode, int support, const ItemArgs& a, hipStream_t s);
 // mount_frame_tab: -1 for sky-frame offsets, else the Airy table length the
 // mount-frame kernel keeps in LDS
-size_t win_lds_bytes(int support, int mode, int waves, int m, int oversample, int mount_frame_tab = -1);
+size_t win_lds_bytes(int support, int mode, int m, int oversample, int mount_frame_tab = -1);
 size_t win_lds_budget(int support);
 hipError_t launch_reduce(int ncontrib, const ReduceArgs& a, hipStream_t s);
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s);

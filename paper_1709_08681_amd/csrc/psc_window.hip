@@ -22,6 +22,9 @@
 
 namespace psc {
 
+// ---------------------------------------------------------------------------
+// Support 16: S-lane workers.
+//
 // One block (W wavefronts) per item, as in the table form: the wavefronts
 // share the item's image-plane products in LDS.  Each S-lane slot of a
 // wavefront is an independent worker.  The item's work is cut into units of
@@ -48,11 +51,7 @@ __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
     constexpr int SPW = 64 / S;
     constexpr int kBlock = 64 * W;
     static_assert(NC <= S, "one term per lane of a slot");
-    // image-plane products variant-interleaved ([n][NV], one base address per
-    // sample and immediate offsets) at support 32, variant-major at 16: the
-    // faster layout of each when measured on the large and single-interval
-    // workloads
-    constexpr bool kInterleave = (S == 32);
+    static_assert(S == 16, "support 32 runs k_winw");
 
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ float2 twsh[S * 16];       // exp(+2 pi i t / (S O)), S O <= 16 S
@@ -149,7 +148,7 @@ __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
             qjl = oj[0] + sq;
             qjm = oj[1];
         } else {
-            image_products<MODE, kInterleave>(a, it, pol, gsh, m2p, tid, kBlock);
+            image_products<MODE>(a, it, pol, gsh, m2p, tid, kBlock);
         }
         __syncthreads();
 
@@ -252,12 +251,11 @@ __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
                     const float2 t = cmul(ph[jl * NW], wt[bl * SP + c]);
                     const float2 z0 = cmul(t, pm0), z1 = cmul(t, pm1);
                     // variant k of samples (jl, jm0) and (jl, jm1)
-                    const float* g0p = gsh + (kInterleave ? (jl * m + jm0) * NV : jl * m + jm0);
-                    const float* g1p = gsh + (kInterleave ? (jl * m + jm1) * NV : jl * m + jm1);
-                    const int ks = kInterleave ? 1 : m2p;
+                    const float* g0p = gsh + jl * m + jm0;
+                    const float* g1p = gsh + jl * m + jm1;
 #pragma unroll
                     for (int k = 0; k < NV; ++k) {
-                        const float g0 = g0p[k * ks], g1 = g1p[k * ks];
+                        const float g0 = g0p[k * m2p], g1 = g1p[k * m2p];
                         s[k].x = fmaf(g0, z0.x, fmaf(g1, z1.x, s[k].x));
                         s[k].y = fmaf(g0, z0.y, fmaf(g1, z1.y, s[k].y));
                     }
@@ -268,10 +266,6 @@ __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
                 for (int k = 0; k < NV; ++k) {
                     s[k].x = row16_sum(s[k].x);
                     s[k].y = row16_sum(s[k].y);
-                    if constexpr (S == 32) {
-                        s[k].x += __shfl_xor(s[k].x, 16);
-                        s[k].y += __shfl_xor(s[k].y, 16);
-                    }
                 }
                 if constexpr (MF && MODE != kPredict) {
                     // derivatives with respect to the mount-frame offsets
@@ -313,34 +307,359 @@ __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
     }
 }
 
-template <int S, int MODE, int W, bool MF>
+// ---------------------------------------------------------------------------
+// Support 32: a wavefront per sample.
+//
+// One block of eight wavefronts per item.  The item's samples, numbered group
+// by group (each group's samples at f, then those at -f), are dealt to the
+// wavefronts in turn: wavefront w takes samples w, w + 8, w + 16, ...  With
+// the assignment fixed, a wavefront loads its next sample's entry, window and
+// inputs while it transforms and sums the current one, so the chain of
+// dependent loads (entry, then window) stays off the critical path; the
+// float64 sums are kept per wavefront and added in wavefront order.
+//
+// Lane (h, c) loads rows [16h, 16h + 16) of column c of the reversed window.
+// Each 32-point transform is split in its first radix-2 step: the half h = 0
+// keeps the sum of the two halves' points, h = 1 their difference times
+// exp(+2 pi i r / 32), and each finishes with a 16-point transform, giving
+// the outputs 2b + h.  Along l the columns go through the wavefront's LDS
+// tile; along m lane (h, c) reads row c, and multiplies it by the l-axis phase
+// phi_l(n) of the image-sample index n in [-M/2, 32 - M/2) congruent to c
+// before writing it back, so the sum needs no phase per image sample: the
+// samples n + 32 carry the common factor exp(2 pi i f_l / O), and the m-axis
+// phase is the lane's own.  In the sum lane (h, c) takes the image-sample m
+// index n_m = c - 32 h (M/2 of the 32 lanes of each half have one).
+template <int MODE, bool MF>
+__global__ void __launch_bounds__(64 * kWinwWaves) k_winw(ItemArgs a)
+{
+    constexpr int S = 32, H = S / 2, SP = S + 1, W = kWinwWaves;
+    constexpr int NV = mode_nv(MODE);
+    constexpr int NC = mode_nc(MODE);
+    constexpr int NCP = NC > 0 ? NC : 1;
+    constexpr int kBlock = 64 * W;
+    static_assert(NC <= 64, "one term per lane");
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ float2 twsh[S * 16];  // exp(+2 pi i t / (S O)), S O <= 16 S
+
+    const int m = a.m, half_m = m >> 1;
+    const int m2p = (m * m + 3) & ~3;
+    const int O = a.oversample, so = S * O;
+    // dynamic LDS: per-wavefront float64 sums | the item's groups |
+    // image-plane products [n][NV] | window tiles | Airy table (MF)
+    double* gpart = reinterpret_cast<double*>(smem);  // [W][NCP]
+    Group* grp = reinterpret_cast<Group*>(gpart + W * NCP);
+    float* gsh = reinterpret_cast<float*>(grp + win_max_groups(O));
+    float2* wtile = reinterpret_cast<float2*>(gsh + (MF ? 0 : NV * m2p));
+    float4* airy_sh = reinterpret_cast<float4*>(wtile + (size_t)W * S * SP);
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int per_xcd = gridDim.x >> 3;
+    const int li = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (li >= a.n_items) return;
+    const int item_idx = a.item_begin + li;
+    const Item it = a.items[item_idx];
+    if (a.done != nullptr && a.done[it.interval]) return;
+
+    const int N = a.grid_n;
+    const float inv_s = 1.0f / (float)S;
+    const int P = N + S;  // pitch of the padded grid
+    const int rowbytes = P * (int)sizeof(float2);
+    const __amdgpu_buffer_rsrc_t grsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)a.grid, (short)0, P * P * (int)sizeof(float2), 0x00020000);
+
+    const int n_grp = it.grp_end - it.grp_begin;
+    for (int t = tid; t < so; t += kBlock) twsh[t] = a.tw[t];
+    for (int t = tid; t < n_grp; t += kBlock) grp[t] = a.groups[it.grp_begin + t];
+    if constexpr (MF)
+        for (int t = tid; t < a.n_tab; t += kBlock) airy_sh[t] = a.airy[t];
+    __syncthreads();
+
+    const int c = lane & (S - 1), hh = lane >> 5;
+    float2* wt = wtile + (size_t)wave * S * SP;  // this wavefront's tile
+    const TermSel tsel(lane);
+    const float2 zero = make_float2(0.f, 0.f);
+    // the lane's image-sample m index, and the l index its transform row c
+    // stands for
+    const int nm = c - hh * S;
+    const bool m_ok = nm >= -half_m && nm < half_m;
+    const int jm = m_ok ? nm + half_m : 0;
+    const int nl_row = ((c + half_m) & (S - 1)) - half_m;
+
+    // (-1)^n exp(2 pi i f n / (S O)) / S
+    auto phase = [&](int f, int n) {
+        const float2 t = twsh[(f * n) & (so - 1)];
+        const float sg = (n & 1) ? -inv_s : inv_s;
+        return make_float2(t.x * sg, t.y * sg);
+    };
+    // the sample v positions on from (gi, v) in the item's numbering
+    auto advance = [&](int& gi, int& v, int step) {
+        v += step;
+        while (gi < n_grp) {
+            const int tot = grp[gi].n_vis + grp[gi].n_vis2;
+            if (v < tot) break;
+            v -= tot;
+            ++gi;
+        }
+    };
+    // a sample's entry; past the end, the item's first (loads stay in bounds)
+    auto entry = [&](int gi, int v) {
+        return gi < n_grp ? a.vis[grp[gi].vis_begin + v] : a.vis[grp[0].vis_begin];
+    };
+    // rows H hh + r of the reversed column c: grid row k_lo_l + S-1-(H hh + r)
+    auto load_window = [&](const VisEnt& e, float2 (&x)[H]) {
+        const int row0 = (int)(e.klo >> 16);
+        const int col0 = (int)(e.klo & 0xffffu);
+        const int voff = (row0 * P + col0 + (S - 1 - c)) * (int)sizeof(float2) + (1 - hh) * H * rowbytes;
+#pragma unroll
+        for (int r = 0; r < H; ++r)
+            x[r] = __builtin_bit_cast(
+                float2, __builtin_amdgcn_raw_buffer_load_b64(grsrc, voff, (H - 1 - r) * rowbytes, 0));
+    };
+
+    // mount frame: beam constants of the item's channel, the lane's
+    // image-sample m coordinate and taper value
+    const double lam = kCLight / a.freq[it.chan];
+    const float kk = (float)(kPi * a.dish / lam);
+    const double sigma = a.gauss_sigma_ld * lam / a.dish;
+    const float inv_s2 = (float)(1.0 / (sigma * sigma));
+    const float hstep = (float)a.h;
+    const float mmy = (float)nm * hstep;
+    const float ctm = a.taper_img[jm];
+
+    for (int pol = 0; pol < a.n_pol; ++pol) {
+        // this wavefront's first two samples, their entries, the first window
+        int gi0 = 0, v0 = wave;
+        advance(gi0, v0, 0);
+        int gi1 = gi0, v1 = v0;
+        if (gi0 < n_grp) advance(gi1, v1, W);
+        float2 x0[H];
+        VisEnt e0 = {0u, 0u}, e1 = {0u, 0u};
+        float2 vin0 = zero;
+        float wgt0 = 0.f;
+        if (gi0 < n_grp) {
+            e0 = entry(gi0, v0);
+            e1 = entry(gi1, v1);
+            load_window(e0, x0);
+            const size_t o0 = (size_t)e0.vidx * a.n_pol + pol;
+            if (MODE != kPredict) vin0 = a.vis_in[o0];
+            if (MODE == kGrad) wgt0 = a.weight[o0];
+        }
+
+        double qil = 0, qim = 0, qjl = 0, qjm = 0;
+        if constexpr (MF) {
+            // mount-frame offsets plus squint (along the mount's first axis)
+            const double sq = (pol == 0 ? 1.0 : -1.0) * a.squint_frac * 1.02899 * lam / a.dish;
+            const double* oi = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.ai) * 2;
+            const double* oj = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.aj) * 2;
+            qil = oi[0] + sq;
+            qim = oi[1];
+            qjl = oj[0] + sq;
+            qjm = oj[1];
+        } else {
+            image_products<MODE, true>(a, it, pol, gsh, m2p, tid, kBlock);
+        }
+        __syncthreads();
+
+        double acc64 = 0.0;
+        while (gi0 < n_grp) {
+            // ---- fetch ahead: the next sample's window and inputs, the entry after it
+            float2 x1[H];
+            load_window(e1, x1);
+            const size_t o1 = (size_t)e1.vidx * a.n_pol + pol;
+            float2 vin1 = zero;
+            float wgt1 = 0.f;
+            if (MODE != kPredict) vin1 = a.vis_in[o1];
+            if (MODE == kGrad) wgt1 = a.weight[o1];
+            int gi2 = gi1, v2 = v1;
+            if (gi1 < n_grp) advance(gi2, v2, W);
+            const VisEnt e2 = entry(gi2, v2);
+
+            // ---- the current sample's offset per axis: f, or -f after the group's first part
+            const Group g0 = grp[gi0];
+            int fl = g0.f / O, fm = g0.f - (g0.f / O) * O;
+            if (v0 >= g0.n_vis) {
+                fl = (O - fl) & (O - 1);
+                fm = (O - fm) & (O - 1);
+            }
+
+            // ---- along l: first radix-2 step across the halves, then 16 points
+            float2 y[H];
+#pragma unroll
+            for (int r = 0; r < H; ++r) {
+                const float2 p = make_float2(__shfl_xor(x0[r].x, 32), __shfl_xor(x0[r].y, 32));
+                y[r] = hh == 0 ? make_float2(x0[r].x + p.x, x0[r].y + p.y)
+                               : twmul(2 * r, make_float2(p.x - x0[r].x, p.y - x0[r].y));
+            }
+            fft_reg<H>(y);
+            wave_sync();  // the previous sample's tile has been read
+#pragma unroll
+            for (int b = 0; b < H; ++b) wt[(2 * b + hh) * SP + c] = y[b];
+            wave_sync();
+            // ---- along m: row c, the same split; times the row's l-axis phase
+#pragma unroll
+            for (int r = 0; r < H; ++r) {
+                const float2 t0 = wt[c * SP + r], t1 = wt[c * SP + H + r];
+                y[r] = hh == 0 ? make_float2(t0.x + t1.x, t0.y + t1.y)
+                               : twmul(2 * r, make_float2(t0.x - t1.x, t0.y - t1.y));
+            }
+            fft_reg<H>(y);
+            const float2 prow = phase(fl, nl_row);
+#pragma unroll
+            for (int b = 0; b < H; ++b) wt[c * SP + 2 * b + hh] = cmul(y[b], prow);
+            wave_sync();
+
+            // ---- A_k, B_k: sums over l of g_k[n_l][n_m] T[n_l mod 32][c] for
+            // n_l below and above 32 - M/2
+            float2 A[NV], B[NV];
+#pragma unroll
+            for (int k = 0; k < NV; ++k) A[k] = B[k] = zero;
+            float cs = 1.f, sn = 0.f;
+            if constexpr (MF) {
+                // this row's beam centres on the sky
+                sincosf((float)a.par_angle[e0.vidx / (uint32_t)a.n_chan], &sn, &cs);
+                const float pil = (float)(cs * qil - sn * qim), pim = (float)(sn * qil + cs * qim);
+                const float pjl = (float)(cs * qjl - sn * qjm), pjm = (float)(sn * qjl + cs * qjm);
+                auto term = [&](int jl, float2 (&acc)[NV]) {
+                    const float2 t = wt[((jl - half_m) & (S - 1)) * SP + c];
+                    const float l = (float)(jl - half_m) * hstep;
+                    float g[NV];
+                    mf_products<MODE>(a, airy_sh, kk, inv_s2, l - pil, mmy - pim, l - pjl, mmy - pjm,
+                                      a.taper_img[jl] * ctm, g);
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) {
+                        acc[k].x = fmaf(g[k], t.x, acc[k].x);
+                        acc[k].y = fmaf(g[k], t.y, acc[k].y);
+                    }
+                };
+#pragma unroll 2
+                for (int jl = 0; jl < S; ++jl) term(jl, A);
+#pragma unroll 2
+                for (int jl = S; jl < m; ++jl) term(jl, B);
+            } else {
+                const float* gp = gsh + jm * NV;
+                // the halves read products S samples apart, S NV words: an odd
+                // multiple of 32 for NV odd, so they use disjoint banks
+                auto term = [&](int jl, float2 (&acc)[NV]) {
+                    const float2 t = wt[((jl - half_m) & (S - 1)) * SP + c];
+                    const float* g = gp + jl * m * NV;
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) {
+                        acc[k].x = fmaf(g[k], t.x, acc[k].x);
+                        acc[k].y = fmaf(g[k], t.y, acc[k].y);
+                    }
+                };
+#pragma unroll 4
+                for (int jl = 0; jl < S; ++jl) term(jl, A);
+#pragma unroll 4
+                for (int jl = S; jl < m; ++jl) term(jl, B);
+            }
+            // ---- s_k = phi_m(n_m) (A_k + exp(2 pi i f_l / O) B_k), summed over the wavefront
+            const float2 rho = twsh[(fl * S) & (so - 1)];
+            const float2 pm = m_ok ? phase(fm, nm) : zero;
+            float2 s[NV];
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                const float2 rb = cmul(rho, B[k]);
+                s[k] = cmul(pm, make_float2(A[k].x + rb.x, A[k].y + rb.y));
+                s[k].x = row16_sum(s[k].x);
+                s[k].y = row16_sum(s[k].y);
+                s[k].x += __shfl_xor(s[k].x, 16);
+                s[k].y += __shfl_xor(s[k].y, 16);
+                s[k].x += __shfl_xor(s[k].x, 32);
+                s[k].y += __shfl_xor(s[k].y, 32);
+            }
+            if constexpr (MF && MODE != kPredict) {
+                // derivatives with respect to the mount-frame offsets
+                constexpr int d0 = (MODE == kGrad) ? 1 : 0;
+#pragma unroll
+                for (int end = 0; end < 2; ++end) {
+                    const float2 dl = s[d0 + 2 * end], dm = s[d0 + 2 * end + 1];
+                    s[d0 + 2 * end] = make_float2(cs * dl.x + sn * dm.x, cs * dl.y + sn * dm.y);
+                    s[d0 + 2 * end + 1] = make_float2(cs * dm.x - sn * dl.x, cs * dm.y - sn * dl.y);
+                }
+            }
+            const size_t o0 = (size_t)e0.vidx * a.n_pol + pol;
+            if (MODE == kPredict) {
+                if (lane == 0) a.vis_out[o0] = s[0];
+            } else if (MODE == kGrad) {
+                if (a.vis_out != nullptr && lane == 0) a.vis_out[o0] = s[0];
+                grad_term(tsel, s, vin0, wgt0, acc64);
+            } else {
+                vjp_term(lane, s, vin0, acc64);
+            }
+
+            // ---- move on
+#pragma unroll
+            for (int r = 0; r < H; ++r) x0[r] = x1[r];
+            vin0 = vin1;
+            wgt0 = wgt1;
+            e0 = e1;
+            e1 = e2;
+            gi0 = gi1;
+            v0 = v1;
+            gi1 = gi2;
+            v1 = v2;
+        }
+
+        // ---- per-item partial sums: wavefronts added in order
+        if (NC > 0 && lane < NC) gpart[wave * NCP + lane] = acc64;
+        __syncthreads();
+        if (NC > 0 && tid < NC) {
+            double sum = 0.0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) sum += gpart[w * NCP + tid];
+            a.partials[((size_t)item_idx * a.n_pol + pol) * NC + tid] = sum;
+        }
+        __syncthreads();
+    }
+}
+
+template <int S, int MODE, bool MF>
 static hipError_t launch_win_t(const ItemArgs& a, hipStream_t s)
 {
-    const size_t sh = win_lds_bytes(S, MODE, W, a.m, a.oversample, MF ? a.n_tab : -1);
+    const size_t sh = win_lds_bytes(S, MODE, a.m, a.oversample, MF ? a.n_tab : -1);
     if (sh > win_lds_budget(S)) return hipErrorInvalidValue;
-    // raise the dynamic LDS limit once, to what one compute unit allows
-    static const hipError_t attr = hipFuncSetAttribute(
-        (const void*)k_win<S, MODE, W, MF>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)win_lds_budget(S));
-    if (attr != hipSuccess) return attr;
-    const int blocks = 8 * ((a.n_items + 7) / 8);
-    k_win<S, MODE, W, MF><<<blocks, 64 * W, sh, s>>>(a);
+    if constexpr (S == 16) {
+        constexpr int W = kWinWaves;
+        // raise the dynamic LDS limit once, to what one compute unit allows
+        static const hipError_t attr = hipFuncSetAttribute(
+            (const void*)k_win<S, MODE, W, MF>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)win_lds_budget(S));
+        if (attr != hipSuccess) return attr;
+        const int blocks = 8 * ((a.n_items + 7) / 8);
+        k_win<S, MODE, W, MF><<<blocks, 64 * W, sh, s>>>(a);
+    } else {
+        static const hipError_t attr = hipFuncSetAttribute(
+            (const void*)k_winw<MODE, MF>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)win_lds_budget(S));
+        if (attr != hipSuccess) return attr;
+        const int blocks = 8 * ((a.n_items + 7) / 8);
+        k_winw<MODE, MF><<<blocks, 64 * kWinwWaves, sh, s>>>(a);
+    }
     return hipGetLastError();
 }
 
-size_t win_lds_bytes(int support, int mode, int waves, int m, int oversample, int mount_frame_tab)
+size_t win_lds_bytes(int support, int mode, int m, int oversample, int mount_frame_tab)
 {
     const int nv = mode_nv(mode);
     const int nc = mode_nc(mode) > 0 ? mode_nc(mode) : 1;
-    const int m2p = (m * m + 3) & ~3;
+    const size_t m2p = (size_t)((m * m + 3) & ~3);
     const bool mf = mount_frame_tab >= 0;
-    return sizeof(double) * nc * win_max_units(oversample) + (mf ? 0 : sizeof(float) * nv * m2p) +
-           sizeof(float2) * (size_t)waves * 64 * (support + 1) + (mf ? sizeof(float4) * mount_frame_tab : 0);
+    const size_t prod = mf ? 0 : sizeof(float) * nv * m2p;
+    const size_t tab = mf ? sizeof(float4) * mount_frame_tab : 0;
+    if (support == 16)
+        return sizeof(double) * nc * win_max_units(oversample) + prod +
+               sizeof(float2) * (size_t)kWinWaves * 64 * (support + 1) + tab;
+    return sizeof(double) * nc * kWinwWaves + sizeof(Group) * win_max_groups(oversample) + prod +
+           sizeof(float2) * (size_t)kWinwWaves * support * (support + 1) + tab;
 }
 
 size_t win_lds_budget(int support)
 {
-    // static LDS of k_win: twiddles, per-slot phases, the group counter
-    const size_t stat = sizeof(float2) * support * 16 + sizeof(float2) * kWinWaves * (64 / support) * 128 + 16;
+    // static LDS: twiddles, and at support 16 the per-slot phases and the
+    // group counter
+    const size_t stat = support == 16
+        ? sizeof(float2) * support * 16 + sizeof(float2) * kWinWaves * (64 / support) * 128 + 16
+        : sizeof(float2) * support * 16;
     return 160 * 1024 - stat;
 }
 
@@ -350,17 +669,17 @@ hipError_t launch_win(int mode, int support, const ItemArgs& a, hipStream_t s)
     const bool mf = a.par_angle != nullptr;
     if (support == 16) {
         switch (mode) {
-        case kPredict: return mf ? launch_win_t<16, kPredict, kWinWaves, true>(a, s) : launch_win_t<16, kPredict, kWinWaves, false>(a, s);
-        case kGrad: return mf ? launch_win_t<16, kGrad, kWinWaves, true>(a, s) : launch_win_t<16, kGrad, kWinWaves, false>(a, s);
-        case kVjp: return mf ? launch_win_t<16, kVjp, kWinWaves, true>(a, s) : launch_win_t<16, kVjp, kWinWaves, false>(a, s);
+        case kPredict: return mf ? launch_win_t<16, kPredict, true>(a, s) : launch_win_t<16, kPredict, false>(a, s);
+        case kGrad: return mf ? launch_win_t<16, kGrad, true>(a, s) : launch_win_t<16, kGrad, false>(a, s);
+        case kVjp: return mf ? launch_win_t<16, kVjp, true>(a, s) : launch_win_t<16, kVjp, false>(a, s);
         default: return hipErrorInvalidValue;
         }
     }
     if (support == 32) {
         switch (mode) {
-        case kPredict: return mf ? launch_win_t<32, kPredict, kWinWaves, true>(a, s) : launch_win_t<32, kPredict, kWinWaves, false>(a, s);
-        case kGrad: return mf ? launch_win_t<32, kGrad, kWinWaves, true>(a, s) : launch_win_t<32, kGrad, kWinWaves, false>(a, s);
-        case kVjp: return mf ? launch_win_t<32, kVjp, kWinWaves, true>(a, s) : launch_win_t<32, kVjp, kWinWaves, false>(a, s);
+        case kPredict: return mf ? launch_win_t<32, kPredict, true>(a, s) : launch_win_t<32, kPredict, false>(a, s);
+        case kGrad: return mf ? launch_win_t<32, kGrad, true>(a, s) : launch_win_t<32, kGrad, false>(a, s);
+        case kVjp: return mf ? launch_win_t<32, kVjp, true>(a, s) : launch_win_t<32, kVjp, false>(a, s);
         default: return hipErrorInvalidValue;
         }
     }

@@ -64,12 +64,18 @@ def test_create_rejects_invalid_config(psc, bad):
     assert ei.value.status == -1
 
 
-def test_create_reports_unsupported_lds(psc):
-    """Support 32 with 64 image samples at oversampling 8 needs more LDS than
-    one compute unit has (valid request, not implemented)."""
-    with pytest.raises(psc.PscError) as ei:
-        psc.psc_create(_cfg(psc, support=32, oversample=8, image_samples=64))
-    assert ei.value.status == -4
+@pytest.mark.parametrize("over", [1, 2, 4, 8, 16])
+def test_support32_fits_every_image_sample_count(psc, over):
+    """Support 32 at the most image samples (M = 2S) fits the window form's LDS
+    at every oversampling: create gets past its configuration checks (here,
+    without a GPU, to the device selection)."""
+    try:
+        ctx = psc.psc_create(_cfg(psc, support=32, oversample=over, image_samples=64))
+    except psc.PscError as e:
+        assert e.status != -4, str(e)
+        assert "device" in str(e)
+    else:
+        psc.psc_destroy(ctx)
 
 
 def test_null_arguments(psc):

@@ -427,16 +427,40 @@ def test_image_sample_counts(torch_dev, m):
 # cores, and the window form
 # ---------------------------------------------------------------------------
 
+def vjp_reference(obs, prob, off, G, off_shape):
+    """Re(conj(G) dV/dp) summed per (interval, pol, antenna, axis), from the
+    oracle's analytic derivatives."""
+    _, dv = oracle.predict(prob, off, want_grad=True)
+    gref = np.zeros(off_shape)
+    for r in range(obs.n_row):
+        it = np.searchsorted(obs.int_row_ptr, r, side="right") - 1
+        i, j = obs.ant1[r], obs.ant2[r]
+        for c in range(obs.n_chan):
+            for p in range(obs.n_pol):
+                g = np.complex128(G[r, c, p])
+                for ax in range(2):
+                    gref[it, p, i, ax] += (np.conj(g) * dv[r, c, p, ax]).real
+                    gref[it, p, j, ax] += (np.conj(g) * dv[r, c, p, 2 + ax]).real
+    return gref
+
+
+def small_ragged_obs(seed, **overrides):
+    """8 antennas, intervals of 6, 2 and 9 times, two polarisations with
+    squint, two channels (workload fields overridable: the oracle rounds uv to
+    the workload's own oversampling lattice)."""
+    lengths = [6, 2, 9]
+    wl = synth.workload(1, n_ant=8, n_time=sum(lengths), interval_lengths=lengths, n_pol=2,
+                        squint_frac=0.03, freqs_hz=np.array([1.1e9, 1.6e9]), n_src=6, **overrides)
+    return synth.make_observation(wl, seed)
+
+
 @pytest.mark.parametrize("variant", [0, 1, 2])
 def test_degrid_variants_gradient_and_vjp(torch_dev, variant):
     """Prediction, gradient sums and the adjoint with each degrid variant, on
     ragged intervals with two polarisations (offset pairs f, -f in every item)."""
     torch = torch_dev
     from paper_1709_08681_amd import psc
-    lengths = [6, 2, 9]
-    wl = synth.workload(1, n_ant=8, n_time=sum(lengths), interval_lengths=lengths, n_pol=2,
-                        squint_frac=0.03, freqs_hz=np.array([1.1e9, 1.6e9]), n_src=6)
-    obs = synth.make_observation(wl, 91)
+    obs = small_ragged_obs(91)
     prob = oracle.Problem.from_observation(obs)
     s = session(obs)
     try:
@@ -454,19 +478,41 @@ def test_degrid_variants_gradient_and_vjp(torch_dev, variant):
             assert rel(acc[..., k], ref[..., k]) <= 1e-4, k
         rng = np.random.default_rng(20)
         G = (rng.normal(size=s.vis_shape) + 1j * rng.normal(size=s.vis_shape)).astype(np.complex64)
-        _, dv = oracle.predict(prob, start, want_grad=True)
-        gref = np.zeros(s.off_shape)
-        for r in range(obs.n_row):
-            it = np.searchsorted(obs.int_row_ptr, r, side="right") - 1
-            i, j = obs.ant1[r], obs.ant2[r]
-            for c in range(obs.n_chan):
-                for p in range(obs.n_pol):
-                    g = np.complex128(G[r, c, p])
-                    for ax in range(2):
-                        gref[it, p, i, ax] += (np.conj(g) * dv[r, c, p, ax]).real
-                        gref[it, p, j, ax] += (np.conj(g) * dv[r, c, p, 2 + ax]).real
+        gref = vjp_reference(obs, prob, start, G, s.off_shape)
         got = s.vjp(s.offsets(start), torch.as_tensor(G, device=s.dev)).cpu().numpy()
         assert rel(got, gref) <= 1e-4
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("m,over", [(32, 4), (64, 2), (48, 8)])
+def test_support32_image_sample_extremes(torch_dev, m, over):
+    """Support 32, where a wavefront handles each sample and its two halves
+    split the 32-point transforms and the image-sample m indices, at M = S
+    (half the lanes of each half idle), M = 2S (none idle) and the default
+    3S/2: prediction, gradient sums and the adjoint against the oracle."""
+    torch = torch_dev
+    from paper_1709_08681_amd import psc
+    obs = small_ragged_obs(93, support=32, oversample=over)
+    prob = oracle.Problem.from_observation(obs)
+    print(f"case: support 32, M {m}, O {over}", flush=True)
+    s = session(obs, image_samples=m)
+    try:
+        assert psc.psc_get_degrid(s.handle) == psc.DEGRID_WINDOW
+        start = synth.perturbed_offsets(obs, 25.0, 37)
+        v = oracle.predict(prob, obs.offsets_true)
+        assert rel(s.predict(obs.offsets_true).cpu().numpy(), v) <= 1e-5
+        ref, vm_ref = oracle.gradient(prob, start, v, 1.0, want_model=True)
+        w1 = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+        acc, vm = s.gradient(s.offsets(start), c64(torch, s, v), w1, want_model=True)
+        assert rel(vm.cpu().numpy(), vm_ref) <= 1e-5
+        acc = acc.cpu().numpy()
+        for k in range(6):
+            assert rel(acc[..., k], ref[..., k]) <= 1e-4, k
+        rng = np.random.default_rng(21)
+        G = (rng.normal(size=s.vis_shape) + 1j * rng.normal(size=s.vis_shape)).astype(np.complex64)
+        got = s.vjp(s.offsets(start), torch.as_tensor(G, device=s.dev)).cpu().numpy()
+        assert rel(got, vjp_reference(obs, prob, start, G, s.off_shape)) <= 1e-4
     finally:
         s.close()
 
