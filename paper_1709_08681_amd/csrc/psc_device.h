@@ -161,17 +161,46 @@ __device__ __forceinline__ void efp(const ItemArgs& a, const float4* tab, float 
     em = k2 * dm;
 }
 
+// The same pattern in factored form: E and the factor q of its gradient with
+// respect to the pointing offset, dE/dp = q (dl, dm) (the pattern depends on
+// |l - p| alone, so the gradient points along l - p).
+__device__ __forceinline__ void efq(const ItemArgs& a, const float4* tab, float kk, float inv_s2, float dl,
+                                    float dm, float& e, float& q)
+{
+    if (a.illum == 1) {
+        e = expf(-0.5f * (dl * dl + dm * dm) * inv_s2);
+        q = e * inv_s2;
+        return;
+    }
+    const float x = kk * sqrtf(dl * dl + dm * dm);
+    float u = x * a.inv_dx;
+    int i;
+    if (!(u < (float)(a.n_tab - 2))) {  // beyond the table, or not finite: clamp
+        i = a.n_tab - 2;
+        u = (float)i + 1.0f;
+    } else {
+        i = (int)u;
+    }
+    const float t = u - (float)i;
+    const float4 p0 = tab[i], p1 = tab[i + 1];
+    const float t2 = t * t, t3 = t2 * t;
+    const float h00 = 2.f * t3 - 3.f * t2 + 1.f, h10 = t3 - 2.f * t2 + t, h01 = -2.f * t3 + 3.f * t2,
+                h11 = t3 - t2;
+    e = h00 * p0.x + h10 * p0.y + h01 * p1.x + h11 * p1.y;
+    q = kk * kk * (h00 * p0.z + h10 * p0.w + h01 * p1.z + h11 * p1.w);
+}
+
 // Image-plane products E_i E_j c at the M x M samples (spacing FoV/S, centred)
 // for one item and polarisation, and for the gradient and adjoint the offset
 // derivatives dE_i/dp_i E_j c and E_i dE_j/dp_j c (Eq. DA).  Variant k of
-// sample n goes to gsh[k * m2p + n] (variant-major) or, with INTERLEAVED, to
-// gsh[n * NV + k]; threads tid, tid + nthr, ... of the block share the work.
-template <int MODE, bool INTERLEAVED = false>
+// sample n goes to gsh[k * m2p + n] (variant-major); threads tid, tid + nthr,
+// ... of the block share the work.
+template <int MODE>
 __device__ __forceinline__ void image_products(const ItemArgs& a, const Item& it, int pol, float* gsh,
                                                int m2p, int tid, int nthr)
 {
     constexpr int NV = mode_nv(MODE);
-    const int ks = INTERLEAVED ? 1 : m2p;  // stride between variants
+    const int ks = m2p;  // stride between variants
     const int m = a.m, half_m = m >> 1, m2 = m * m;
     const double lam = kCLight / a.freq[it.chan];
     const float kk = (float)(kPi * a.dish / lam);
@@ -192,7 +221,7 @@ __device__ __forceinline__ void image_products(const ItemArgs& a, const Item& it
         efp(a, a.airy, kk, inv_s2, l - pil, mm - pim, ei, eil, eim);
         efp(a, a.airy, kk, inv_s2, l - pjl, mm - pjm, ej, ejl, ejm);
         const float c = a.taper_img[il] * a.taper_img[im];
-        float* gn = gsh + (INTERLEAVED ? idx * NV : idx);
+        float* gn = gsh + idx;
         if (NV == 1) {
             gn[0] = ei * ej * c;
         } else {

@@ -137,6 +137,8 @@ hipError_t launch_win(int mode, int support, const ItemArgs& a, hipStream_t s);
 // mount-frame kernel keeps in LDS
 size_t win_lds_bytes(int support, int mode, int m, int oversample, int mount_frame_tab = -1);
 size_t win_lds_budget(int support);
+// k_winw with the given number of wavefronts per block
+size_t winw_lds_bytes(int waves, int mode, int m, int oversample, int mount_frame_tab = -1);
 hipError_t launch_reduce(int ncontrib, const ReduceArgs& a, hipStream_t s);
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
 hipError_t launch_init_state(int32_t* done, int32_t* iters, int n, hipStream_t s);

@@ -307,6 +307,36 @@ __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
     }
 }
 
+// Image-plane factors of an item at the M x M samples, [n][NG] with NG = 1, 2, 3
+// for predict, adjoint, gradient: g = E_i E_j c and, for the derivatives,
+// the gradient factors q_i E_j c and E_i q_j c (dE/dp = q (l - p)), from
+// which the sum forms the four derivative variants of Eq. DA.
+template <int MODE>
+__device__ __forceinline__ void image_factors(const ItemArgs& a, float* gsh, float kk, float inv_s2, float pil,
+                                              float pim, float pjl, float pjm, int tid, int nthr)
+{
+    constexpr int NG = MODE == kGrad ? 3 : MODE == kVjp ? 2 : 1;
+    const int m = a.m, half_m = m >> 1, m2 = m * m;
+    const float hstep = (float)a.h;
+    for (int idx = tid; idx < m2; idx += nthr) {
+        const int il = idx / m, im = idx - il * m;
+        const float l = (float)(il - half_m) * hstep, mm = (float)(im - half_m) * hstep;
+        float ei, qi, ej, qj;
+        efq(a, a.airy, kk, inv_s2, l - pil, mm - pim, ei, qi);
+        efq(a, a.airy, kk, inv_s2, l - pjl, mm - pjm, ej, qj);
+        const float c = a.taper_img[il] * a.taper_img[im];
+        float* gn = gsh + idx * NG;
+        if constexpr (MODE == kPredict) {
+            gn[0] = ei * ej * c;
+        } else {
+            constexpr int o = MODE == kGrad ? 1 : 0;
+            if constexpr (MODE == kGrad) gn[0] = ei * ej * c;
+            gn[o] = qi * ej * c;
+            gn[o + 1] = ei * qj * c;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Support 32: a wavefront per sample.
 //
@@ -329,13 +359,14 @@ __global__ void __launch_bounds__(64 * W) k_win(ItemArgs a)
 // samples n + 32 carry the common factor exp(2 pi i f_l / O), and the m-axis
 // phase is the lane's own.  In the sum lane (h, c) takes the image-sample m
 // index n_m = c - 32 h (M/2 of the 32 lanes of each half have one).
-template <int MODE, bool MF>
-__global__ void __launch_bounds__(64 * kWinwWaves) k_winw(ItemArgs a)
+template <int MODE, bool MF, int W>
+__global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
 {
-    constexpr int S = 32, H = S / 2, SP = S + 1, W = kWinwWaves;
+    constexpr int S = 32, H = S / 2, SP = S + 1;
     constexpr int NV = mode_nv(MODE);
     constexpr int NC = mode_nc(MODE);
     constexpr int NCP = NC > 0 ? NC : 1;
+    constexpr int NG = MODE == kGrad ? 3 : MODE == kVjp ? 2 : 1;  // image-plane factors per sample
     constexpr int kBlock = 64 * W;
     static_assert(NC <= 64, "one term per lane");
 
@@ -350,7 +381,7 @@ __global__ void __launch_bounds__(64 * kWinwWaves) k_winw(ItemArgs a)
     double* gpart = reinterpret_cast<double*>(smem);  // [W][NCP]
     Group* grp = reinterpret_cast<Group*>(gpart + W * NCP);
     float* gsh = reinterpret_cast<float*>(grp + win_max_groups(O));
-    float2* wtile = reinterpret_cast<float2*>(gsh + (MF ? 0 : NV * m2p));
+    float2* wtile = reinterpret_cast<float2*>(gsh + (MF ? 0 : NG * m2p));
     float4* airy_sh = reinterpret_cast<float4*>(wtile + (size_t)W * S * SP);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -446,19 +477,13 @@ __global__ void __launch_bounds__(64 * kWinwWaves) k_winw(ItemArgs a)
             if (MODE == kGrad) wgt0 = a.weight[o0];
         }
 
-        double qil = 0, qim = 0, qjl = 0, qjm = 0;
-        if constexpr (MF) {
-            // mount-frame offsets plus squint (along the mount's first axis)
-            const double sq = (pol == 0 ? 1.0 : -1.0) * a.squint_frac * 1.02899 * lam / a.dish;
-            const double* oi = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.ai) * 2;
-            const double* oj = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.aj) * 2;
-            qil = oi[0] + sq;
-            qim = oi[1];
-            qjl = oj[0] + sq;
-            qjm = oj[1];
-        } else {
-            image_products<MODE, true>(a, it, pol, gsh, m2p, tid, kBlock);
-        }
+        // offsets plus squint (along l, or along the mount's first axis)
+        const double sq = (pol == 0 ? 1.0 : -1.0) * a.squint_frac * 1.02899 * lam / a.dish;
+        const double* oi = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.ai) * 2;
+        const double* oj = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.aj) * 2;
+        const double qil = oi[0] + sq, qim = oi[1], qjl = oj[0] + sq, qjm = oj[1];
+        if constexpr (!MF)
+            image_factors<MODE>(a, gsh, kk, inv_s2, (float)qil, (float)qim, (float)qjl, (float)qjm, tid, kBlock);
         __syncthreads();
 
         double acc64 = 0.0;
@@ -537,16 +562,33 @@ __global__ void __launch_bounds__(64 * kWinwWaves) k_winw(ItemArgs a)
 #pragma unroll 2
                 for (int jl = S; jl < m; ++jl) term(jl, B);
             } else {
-                const float* gp = gsh + jm * NV;
-                // the halves read products S samples apart, S NV words: an odd
-                // multiple of 32 for NV odd, so they use disjoint banks
+                // factored sums: the value sum g T, and per antenna Q = sum q T
+                // and L = sum q l T, l the image-sample l coordinate (the
+                // variant dV/dp_l = L - p_l Q, dV/dp_m = (m - p_m) Q)
+                const float* gp = gsh + jm * NG;
+                // the halves read factors S samples apart, S NG words: an odd
+                // multiple of 32 for NG odd, so they use disjoint banks
                 auto term = [&](int jl, float2 (&acc)[NV]) {
                     const float2 t = wt[((jl - half_m) & (S - 1)) * SP + c];
-                    const float* g = gp + jl * m * NV;
+                    const float* g = gp + jl * m * NG;
+                    if constexpr (MODE != kVjp) {
+                        acc[0].x = fmaf(g[0], t.x, acc[0].x);
+                        acc[0].y = fmaf(g[0], t.y, acc[0].y);
+                    }
+                    if constexpr (MODE != kPredict) {
+                        constexpr int o = MODE == kGrad ? 1 : 0;
+                        const float l = (float)(jl - half_m) * hstep;
+                        const float2 tl = make_float2(t.x * l, t.y * l);
 #pragma unroll
-                    for (int k = 0; k < NV; ++k) {
-                        acc[k].x = fmaf(g[k], t.x, acc[k].x);
-                        acc[k].y = fmaf(g[k], t.y, acc[k].y);
+                        for (int end = 0; end < 2; ++end) {
+                            const float q = g[o + end];
+                            float2& L = acc[o + 2 * end];
+                            float2& Q = acc[o + 2 * end + 1];
+                            L.x = fmaf(q, tl.x, L.x);
+                            L.y = fmaf(q, tl.y, L.y);
+                            Q.x = fmaf(q, t.x, Q.x);
+                            Q.y = fmaf(q, t.y, Q.y);
+                        }
                     }
                 };
 #pragma unroll 4
@@ -562,6 +604,21 @@ __global__ void __launch_bounds__(64 * kWinwWaves) k_winw(ItemArgs a)
             for (int k = 0; k < NV; ++k) {
                 const float2 rb = cmul(rho, B[k]);
                 s[k] = cmul(pm, make_float2(A[k].x + rb.x, A[k].y + rb.y));
+            }
+            if constexpr (!MF && MODE != kPredict) {
+                // derivative variants from the factored sums (the lane's m coordinate is mmy)
+                constexpr int o = MODE == kGrad ? 1 : 0;
+                const float pl[2] = {(float)qil, (float)qjl}, pmm[2] = {(float)qim, (float)qjm};
+#pragma unroll
+                for (int end = 0; end < 2; ++end) {
+                    const float2 L = s[o + 2 * end], Q = s[o + 2 * end + 1];
+                    const float dm = mmy - pmm[end];
+                    s[o + 2 * end] = make_float2(fmaf(-pl[end], Q.x, L.x), fmaf(-pl[end], Q.y, L.y));
+                    s[o + 2 * end + 1] = make_float2(dm * Q.x, dm * Q.y);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
                 s[k].x = row16_sum(s[k].x);
                 s[k].y = row16_sum(s[k].y);
                 s[k].x += __shfl_xor(s[k].x, 16);
@@ -629,11 +686,19 @@ static hipError_t launch_win_t(const ItemArgs& a, hipStream_t s)
         const int blocks = 8 * ((a.n_items + 7) / 8);
         k_win<S, MODE, W, MF><<<blocks, 64 * W, sh, s>>>(a);
     } else {
-        static const hipError_t attr = hipFuncSetAttribute(
-            (const void*)k_winw<MODE, MF>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)win_lds_budget(S));
-        if (attr != hipSuccess) return attr;
+        static const hipError_t attr8 = hipFuncSetAttribute(
+            (const void*)k_winw<MODE, MF, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)win_lds_budget(S));
+        static const hipError_t attr4 = hipFuncSetAttribute(
+            (const void*)k_winw<MODE, MF, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)win_lds_budget(S));
+        if (attr8 != hipSuccess) return attr8;
+        if (attr4 != hipSuccess) return attr4;
         const int blocks = 8 * ((a.n_items + 7) / 8);
-        k_winw<MODE, MF><<<blocks, 64 * kWinwWaves, sh, s>>>(a);
+        // four wavefronts when two blocks fit a compute unit's LDS, else eight
+        const size_t sh4 = winw_lds_bytes(4, MODE, a.m, a.oversample, MF ? a.n_tab : -1);
+        if (2 * (sh4 + (160 * 1024 - win_lds_budget(S))) <= 160 * 1024)
+            k_winw<MODE, MF, 4><<<blocks, 64 * 4, sh4, s>>>(a);
+        else
+            k_winw<MODE, MF, 8><<<blocks, 64 * 8, sh, s>>>(a);
     }
     return hipGetLastError();
 }
@@ -649,8 +714,19 @@ size_t win_lds_bytes(int support, int mode, int m, int oversample, int mount_fra
     if (support == 16)
         return sizeof(double) * nc * win_max_units(oversample) + prod +
                sizeof(float2) * (size_t)kWinWaves * 64 * (support + 1) + tab;
-    return sizeof(double) * nc * kWinwWaves + sizeof(Group) * win_max_groups(oversample) + prod +
-           sizeof(float2) * (size_t)kWinwWaves * support * (support + 1) + tab;
+    return winw_lds_bytes(kWinwWaves, mode, m, oversample, mount_frame_tab);
+}
+
+size_t winw_lds_bytes(int waves, int mode, int m, int oversample, int mount_frame_tab)
+{
+    constexpr int S = 32;
+    const int nc = mode_nc(mode) > 0 ? mode_nc(mode) : 1;
+    const size_t m2p = (size_t)((m * m + 3) & ~3);
+    const bool mf = mount_frame_tab >= 0;
+    const int ng = mode == kGrad ? 3 : mode == kVjp ? 2 : 1;  // image-plane factors per sample
+    return sizeof(double) * nc * waves + sizeof(Group) * win_max_groups(oversample) +
+           (mf ? 0 : sizeof(float) * ng * m2p) + sizeof(float2) * (size_t)waves * S * (S + 1) +
+           (mf ? sizeof(float4) * mount_frame_tab : 0);
 }
 
 size_t win_lds_budget(int support)
