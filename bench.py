@@ -245,7 +245,8 @@ def main():
     S = obs.wl.support
     kernel = {P.DEGRID_VALU: f"k_item<{S},grad> (table form, vector FP32)",
               P.DEGRID_MFMA: f"k_item<{S},grad> (table form, FP32 matrix cores)",
-              P.DEGRID_WINDOW: f"k_win<{S},grad> (window form)"}[variant]
+              P.DEGRID_WINDOW: (f"k_win<{S},grad> (window form)" if S == 16 else
+                                "k_winw<grad> (window form, a wavefront per sample)")}[variant]
 
     def step(ev=None):
         if ev is not None:
