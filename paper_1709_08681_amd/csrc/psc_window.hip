@@ -337,6 +337,31 @@ __device__ __forceinline__ void image_factors(const ItemArgs& a, float* gsh, flo
     }
 }
 
+// Cross-half exchanges without the LDS crossbar.  v_permlane32_swap(v, v)
+// returns (lanes 0-31 of v in both halves, lanes 32-63 of v in both halves);
+// v_permlane16_swap(v, v) returns (rows 0 and 2 of v, each in its own and the
+// next row; rows 1 and 3 likewise), so the sum of its two results is the sum
+// of lane l and lane l ^ 16.
+__device__ __forceinline__ void halves32(float v, float& lo, float& hi)
+{
+    const unsigned u = __builtin_bit_cast(unsigned, v);
+    const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    lo = __builtin_bit_cast(float, (unsigned)r[0]);
+    hi = __builtin_bit_cast(float, (unsigned)r[1]);
+}
+__device__ __forceinline__ float sum_xor16(float v)
+{
+    const unsigned u = __builtin_bit_cast(unsigned, v);
+    const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    return __builtin_bit_cast(float, (unsigned)r[0]) + __builtin_bit_cast(float, (unsigned)r[1]);
+}
+__device__ __forceinline__ float sum_xor32(float v)
+{
+    float lo, hi;
+    halves32(v, lo, hi);
+    return lo + hi;
+}
+
 // ---------------------------------------------------------------------------
 // Support 32: a wavefront per sample.
 //
@@ -512,9 +537,11 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
             float2 y[H];
 #pragma unroll
             for (int r = 0; r < H; ++r) {
-                const float2 p = make_float2(__shfl_xor(x0[r].x, 32), __shfl_xor(x0[r].y, 32));
-                y[r] = hh == 0 ? make_float2(x0[r].x + p.x, x0[r].y + p.y)
-                               : twmul(2 * r, make_float2(p.x - x0[r].x, p.y - x0[r].y));
+                // the column's rows r (half 0) and 16 + r (half 1), in every lane
+                float tx, bx, ty, by;
+                halves32(x0[r].x, tx, bx);
+                halves32(x0[r].y, ty, by);
+                y[r] = hh == 0 ? make_float2(tx + bx, ty + by) : twmul(2 * r, make_float2(tx - bx, ty - by));
             }
             fft_reg<H>(y);
             wave_sync();  // the previous sample's tile has been read
@@ -621,10 +648,8 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
             for (int k = 0; k < NV; ++k) {
                 s[k].x = row16_sum(s[k].x);
                 s[k].y = row16_sum(s[k].y);
-                s[k].x += __shfl_xor(s[k].x, 16);
-                s[k].y += __shfl_xor(s[k].y, 16);
-                s[k].x += __shfl_xor(s[k].x, 32);
-                s[k].y += __shfl_xor(s[k].y, 32);
+                s[k].x = sum_xor32(sum_xor16(s[k].x));
+                s[k].y = sum_xor32(sum_xor16(s[k].y));
             }
             if constexpr (MF && MODE != kPredict) {
                 // derivatives with respect to the mount-frame offsets
