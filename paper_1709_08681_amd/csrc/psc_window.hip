@@ -441,6 +441,12 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
     const bool m_ok = nm >= -half_m && nm < half_m;
     const int jm = m_ok ? nm + half_m : 0;
     const int nl_row = ((c + half_m) & (S - 1)) - half_m;
+    // first radix-2 step of a 32-point transform: half h keeps
+    // (x_r + (-1)^h x_{16+r}) exp(+2 pi i h r / 32)
+    const float sgn = hh ? -1.f : 1.f;
+    float2 tw1[H];
+#pragma unroll
+    for (int r = 0; r < H; ++r) tw1[r] = hh ? make_float2(kTw.re[2 * r], kTw.im[2 * r]) : make_float2(1.f, 0.f);
 
     // (-1)^n exp(2 pi i f n / (S O)) / S
     auto phase = [&](int f, int n) {
@@ -541,7 +547,8 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
                 float tx, bx, ty, by;
                 halves32(x0[r].x, tx, bx);
                 halves32(x0[r].y, ty, by);
-                y[r] = hh == 0 ? make_float2(tx + bx, ty + by) : twmul(2 * r, make_float2(tx - bx, ty - by));
+                y[r] = make_float2(fmaf(sgn, bx, tx), fmaf(sgn, by, ty));
+                if (r > 0) y[r] = cmul(y[r], tw1[r]);
             }
             fft_reg<H>(y);
             wave_sync();  // the previous sample's tile has been read
@@ -552,8 +559,8 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
 #pragma unroll
             for (int r = 0; r < H; ++r) {
                 const float2 t0 = wt[c * SP + r], t1 = wt[c * SP + H + r];
-                y[r] = hh == 0 ? make_float2(t0.x + t1.x, t0.y + t1.y)
-                               : twmul(2 * r, make_float2(t0.x - t1.x, t0.y - t1.y));
+                y[r] = make_float2(fmaf(sgn, t1.x, t0.x), fmaf(sgn, t1.y, t0.y));
+                if (r > 0) y[r] = cmul(y[r], tw1[r]);
             }
             fft_reg<H>(y);
             const float2 prow = phase(fl, nl_row);
@@ -595,33 +602,40 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
                 const float* gp = gsh + jm * NG;
                 // the halves read factors S samples apart, S NG words: an odd
                 // multiple of 32 for NG odd, so they use disjoint banks
-                auto term = [&](int jl, float2 (&acc)[NV]) {
-                    const float2 t = wt[((jl - half_m) & (S - 1)) * SP + c];
-                    const float* g = gp + jl * m * NG;
-                    if constexpr (MODE != kVjp) {
-                        acc[0].x = fmaf(g[0], t.x, acc[0].x);
-                        acc[0].y = fmaf(g[0], t.y, acc[0].y);
-                    }
-                    if constexpr (MODE != kPredict) {
-                        constexpr int o = MODE == kGrad ? 1 : 0;
-                        const float l = (float)(jl - half_m) * hstep;
-                        const float2 tl = make_float2(t.x * l, t.y * l);
+                // image-sample rows [j0, j1) at tile rows b0, b0 + 1, ... (no wrap)
+                auto seg = [&](int j0, int j1, int b0, float2 (&acc)[NV]) {
+                    const float2* tp = wt + b0 * SP + c;
+                    const float* g = gp + j0 * m * NG;
+#pragma unroll 4
+                    for (int jl = j0; jl < j1; ++jl, tp += SP, g += m * NG) {
+                        const float2 t = *tp;
+                        if constexpr (MODE != kVjp) {
+                            acc[0].x = fmaf(g[0], t.x, acc[0].x);
+                            acc[0].y = fmaf(g[0], t.y, acc[0].y);
+                        }
+                        if constexpr (MODE != kPredict) {
+                            constexpr int o = MODE == kGrad ? 1 : 0;
+                            const float l = (float)(jl - half_m) * hstep;
+                            const float2 tl = make_float2(t.x * l, t.y * l);
 #pragma unroll
-                        for (int end = 0; end < 2; ++end) {
-                            const float q = g[o + end];
-                            float2& L = acc[o + 2 * end];
-                            float2& Q = acc[o + 2 * end + 1];
-                            L.x = fmaf(q, tl.x, L.x);
-                            L.y = fmaf(q, tl.y, L.y);
-                            Q.x = fmaf(q, t.x, Q.x);
-                            Q.y = fmaf(q, t.y, Q.y);
+                            for (int end = 0; end < 2; ++end) {
+                                const float q = g[o + end];
+                                float2& L = acc[o + 2 * end];
+                                float2& Q = acc[o + 2 * end + 1];
+                                L.x = fmaf(q, tl.x, L.x);
+                                L.y = fmaf(q, tl.y, L.y);
+                                Q.x = fmaf(q, t.x, Q.x);
+                                Q.y = fmaf(q, t.y, Q.y);
+                            }
                         }
                     }
                 };
-#pragma unroll 4
-                for (int jl = 0; jl < S; ++jl) term(jl, A);
-#pragma unroll 4
-                for (int jl = S; jl < m; ++jl) term(jl, B);
+                // n_l in [-M/2, 0) is tile row n_l + 32 and [0, 32 - M/2) row
+                // n_l (the A part); [32 - M/2, M/2) is row n_l, the row of
+                // n_l - 32 (the B part)
+                seg(0, half_m, S - half_m, A);
+                seg(half_m, S, 0, A);
+                seg(S, m, S - half_m, B);
             }
             // ---- s_k = phi_m(n_m) (A_k + exp(2 pi i f_l / O) B_k), summed over the wavefront
             const float2 rho = twsh[(fl * S) & (so - 1)];
