@@ -116,29 +116,23 @@ hipError_t launch_zero(double2* p, size_t n, hipStream_t s);
 hipError_t launch_unpad_grid(const double2* g, double2* out, int n, int pad, hipStream_t s);
 hipError_t launch_image_grad(const double2* f, const double* taper_pix, double* out, int n, hipStream_t s);
 hipError_t launch_items(int mode, int support, const ItemArgs& a, hipStream_t s);
-// Window-form degrid (psc_window.hip).  Support 16: k_win, kWinWaves
-// wavefronts per block whose S-lane slots are the workers.  Support 32:
-// k_winw, kWinwWaves wavefronts per block, a wavefront per sample.
-// win_lds_bytes is the dynamic LDS per block, win_lds_budget the most it may
-// use (160 KiB per compute unit less the kernel's static arrays).
-constexpr int kWinWaves = 4;
-constexpr int kWinwWaves = 8;
+// Window-form degrid (psc_window.hip), k_winw: workers of 2S lanes (a
+// wavefront at support 32, half a wavefront at 16), four or eight wavefronts
+// per block.  win_lds_bytes is the dynamic LDS of the larger block,
+// winw_lds_bytes that of a block of the given wavefronts, win_lds_budget the
+// most a block may use (160 KiB per compute unit less the static twiddles).
 // Groups of an item, at most: they pair offsets f and -f, so O^2/2 + 2 (the
-// four self-paired offsets on their own).  k_win cuts each into kWinChunks
-// work units.
+// four self-paired offsets on their own).
 __host__ __device__ inline int win_max_groups(int oversample)
 {
     return oversample == 1 ? 1 : oversample * oversample / 2 + 2;
 }
-constexpr int kWinChunks = 4;
-__host__ __device__ inline int win_max_units(int oversample) { return win_max_groups(oversample) * kWinChunks; }
 hipError_t launch_win(int mode, int support, const ItemArgs& a, hipStream_t s);
 // mount_frame_tab: -1 for sky-frame offsets, else the Airy table length the
 // mount-frame kernel keeps in LDS
 size_t win_lds_bytes(int support, int mode, int m, int oversample, int mount_frame_tab = -1);
+size_t winw_lds_bytes(int support, int waves, int mode, int m, int oversample, int mount_frame_tab = -1);
 size_t win_lds_budget(int support);
-// k_winw with the given number of wavefronts per block
-size_t winw_lds_bytes(int waves, int mode, int m, int oversample, int mount_frame_tab = -1);
 hipError_t launch_reduce(int ncontrib, const ReduceArgs& a, hipStream_t s);
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
 hipError_t launch_init_state(int32_t* done, int32_t* iters, int n, hipStream_t s);
