@@ -86,6 +86,9 @@ def batched_vs_plain(cfg, iters, device=0):
         v_obs = s.predict(s.offsets(obs.offsets_true))
         w = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
         start = s.offsets(synth.perturbed_offsets(obs, 30.0, 98))
+        # the autotuner keeps the fastest degrid variant for all three forms
+        tune_us = P.psc_tune(s.ctx, s.handle, start, v_obs, w, 2, None)
+        variant = P.psc_get_degrid(s.handle)
         res = {}
         for name, form in (("plain", P.SOLVE_PLAIN), ("batched", P.SOLVE_BATCHED),
                            ("graph", P.SOLVE_GRAPH)):
@@ -108,6 +111,9 @@ def batched_vs_plain(cfg, iters, device=0):
             "iterations": iters,
             "graph_over_plain": out["graph"]["vis_per_s"] / out["plain"]["vis_per_s"],
             "bit_identical_offsets": same,
+            "degrid": {P.DEGRID_VALU: "table, vector", P.DEGRID_MFMA: "table, matrix cores",
+                       P.DEGRID_WINDOW: "window"}[variant],
+            "tune_us": {"vector": tune_us[0], "matrix_core": tune_us[1], "window": tune_us[2]},
         })
         return out
     finally:
@@ -245,8 +251,7 @@ def main():
     S = obs.wl.support
     kernel = {P.DEGRID_VALU: f"k_item<{S},grad> (table form, vector FP32)",
               P.DEGRID_MFMA: f"k_item<{S},grad> (table form, FP32 matrix cores)",
-              P.DEGRID_WINDOW: (f"k_win<{S},grad> (window form)" if S == 16 else
-                                "k_winw<grad> (window form, a wavefront per sample)")}[variant]
+              P.DEGRID_WINDOW: f"k_winw<{S},grad> (window form, {2 * S}-lane workers)"}[variant]
 
     def step(ev=None):
         if ev is not None:
