@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -50,6 +51,8 @@ struct psc_obs {
     double* max_step = nullptr;  // [n_int]
     int32_t* done = nullptr;     // [n_int]
     int32_t* iters = nullptr;    // [n_int]
+    uint2* ig_ord = nullptr;     // image gradient: per item, samples in time order (built on first use)
+    float2* ig_vm = nullptr;     // image gradient: model visibilities when the caller passes none
     int32_t degrid = PSC_DEGRID_VALU;  // variant for gradient / adjoint
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph = nullptr;
@@ -304,6 +307,8 @@ PSC_API psc_status psc_obs_destroy(psc_obs* obs)
     dfree(obs->max_step);
     dfree(obs->done);
     dfree(obs->iters);
+    dfree(obs->ig_ord);
+    dfree(obs->ig_vm);
     delete obs;
     return PSC_OK;
 }
@@ -706,6 +711,47 @@ PSC_API psc_status psc_predict_vjp(psc_ctx* ctx, psc_obs* obs, const double* off
     return PSC_OK;
 }
 
+// Per item, its samples in time order (the sample index within a group
+// grows with the row, and rows grow with time within an interval), each with
+// its sub-table slot: 2 g + 0 for group g's offset f, 2 g + 1 for -f.  Built
+// on the host from the device plan on first use; entries of an item occupy
+// the item's own range of the sample array.
+static psc_status build_time_order(psc_ctx* ctx, psc_obs* obs)
+{
+    try {
+        std::vector<Item> items((size_t)obs->n_items);
+        std::vector<Group> groups((size_t)obs->n_groups);
+        std::vector<VisEnt> vis((size_t)obs->n_vis);
+        PSC_HIP(ctx, hipMemcpy(items.data(), obs->items, items.size() * sizeof(Item), hipMemcpyDeviceToHost));
+        PSC_HIP(ctx, hipMemcpy(groups.data(), obs->groups, groups.size() * sizeof(Group), hipMemcpyDeviceToHost));
+        PSC_HIP(ctx, hipMemcpy(vis.data(), obs->vis, vis.size() * sizeof(VisEnt), hipMemcpyDeviceToHost));
+        std::vector<uint2> ord(vis.size());
+        struct Ent {
+            uint32_t vidx, idx, slot;
+        };
+        std::vector<Ent> ents;
+        for (const Item& it : items) {
+            ents.clear();
+            uint32_t lo = UINT32_MAX;
+            for (int gl = 0; gl < it.grp_end - it.grp_begin; ++gl) {
+                const Group& g = groups[(size_t)it.grp_begin + gl];
+                lo = std::min(lo, g.vis_begin);
+                for (int v = 0; v < g.n_vis + g.n_vis2; ++v) {
+                    const uint32_t idx = g.vis_begin + (uint32_t)v;
+                    ents.push_back({vis[idx].vidx, idx, (uint32_t)(2 * gl + (v >= g.n_vis ? 1 : 0))});
+                }
+            }
+            std::sort(ents.begin(), ents.end(), [](const Ent& x, const Ent& y) { return x.vidx < y.vidx; });
+            for (size_t k = 0; k < ents.size(); ++k) ord[lo + k] = make_uint2(ents[k].idx, ents[k].slot);
+        }
+        if (dmalloc(&obs->ig_ord, ord.size()) != hipSuccess) return fail(ctx, PSC_E_OOM, "image-gradient order");
+        PSC_HIP(ctx, hipMemcpy(obs->ig_ord, ord.data(), ord.size() * sizeof(uint2), hipMemcpyHostToDevice));
+    } catch (const std::bad_alloc&) {
+        return fail(ctx, PSC_E_OOM, "host memory for the image-gradient order");
+    }
+    return PSC_OK;
+}
+
 PSC_API psc_status psc_image_gradient(psc_ctx* ctx, psc_obs* obs, const double* offsets_dev,
                                       const void* vis_obs_dev, const float* weight_dev,
                                       double* image_grad_out_dev, void* vis_model_dev, void* stream)
@@ -741,7 +787,28 @@ PSC_API psc_status psc_image_gradient(psc_ctx* ctx, psc_obs* obs, const double* 
     a.grid_acc = ctx->rgrid;
     a.use_mfma = 0;
     PSC_HIP(ctx, launch_zero(ctx->rgrid, np, s));
-    PSC_HIP(ctx, launch_items(kGrid, ctx->s, a, s));
+    if (grid_lds_bytes(ctx->s, ctx->m, ctx->o) <= kGridLdsMax) {
+        // predict, then the patch scatter over each item's samples in time order
+        if (!obs->ig_ord && obs->n_vis > 0) {
+            psc_status bs = build_time_order(ctx, obs);
+            if (bs != PSC_OK) return bs;
+        }
+        float2* vm = (float2*)vis_model_dev;
+        if (!vm && obs->n_vis > 0) {
+            if (!obs->ig_vm && dmalloc(&obs->ig_vm, (size_t)obs->n_row * obs->n_chan * obs->n_pol) != hipSuccess)
+                return fail(ctx, PSC_E_OOM, "image-gradient model visibilities");
+            vm = obs->ig_vm;
+        }
+        a.vis_out = vm;
+        PSC_HIP(ctx, launch_degrid(kPredict, ctx, obs, a, s));
+        a.vis_model = vm;
+        a.ig_ord = obs->ig_ord;
+        PSC_HIP(ctx, launch_grid(ctx->s, a, s));
+    } else {
+        // the table-form scatter: degrid and spread in one pass, a float64
+        // atomic per tap
+        PSC_HIP(ctx, launch_items(kGrid, ctx->s, a, s));
+    }
     PSC_HIP(ctx, launch_unpad_grid(ctx->rgrid, ctx->fa, n, ctx->s, s));
     PSC_HIP(ctx, launch_fft_rows(ctx->fa, n, log2n, s));
     PSC_HIP(ctx, launch_transpose(ctx->fa, ctx->fb, n, s));

@@ -1,0 +1,241 @@
+// psc_grid.hip -- the adjoint of the degrid with respect to the model grid.
+//
+// d chi^2 / d V^{M0}: every sample spreads w conj(R) over its S x S window
+// with the kernel coefficients that produced its V = sum_a V^{M0}[k_lo + a]
+// T_f[S-1-a] (table form, Eq. MEDD), R = V^Obs - V from a preceding predict.
+// The residual grid is then folded, transformed and divided by the taper
+// (psc_kernels.hip) to give the image gradient.
+//
+// A sample's window touches S^2 cells; added one by one with float64
+// atomics that is 2 S^2 global atomics per sample.  Here one block takes an
+// item (a baseline at one channel in one interval), builds the sub-tables of
+// every sub-lattice offset the item uses (f and its partner -f) in LDS, and
+// walks the item's samples in time order: consecutive samples move by a
+// fraction of a cell along the uv track, so a chunk of them covers a small
+// box of the grid.  The chunk's taps are summed into an LDS patch covering
+// that box (float32, sample by sample), and the patch is added to the
+// residual grid once (float64 atomics), cutting the global atomics by the
+// ratio of the chunk's taps to its box.  A chunk whose box does not fit the patch (a track
+// crossing the grid's edge) adds its taps directly.
+#include <climits>
+
+#include "psc_device.h"
+
+namespace psc {
+
+template <int S>
+__global__ void __launch_bounds__(kGridThreads) k_grid(ItemArgs a)
+{
+    constexpr int SP = S + 1, NT = S * S, W = kGridThreads / 64;
+    constexpr int PB = kGridPatch, CH = kGridChunk;
+    static_assert(NT == kGridThreads, "a thread per tap");
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ float2 twsh[S * 16];      // exp(+2 pi i t / (S O)), O <= 16
+    __shared__ float2 phsh[W][64];       // per-wave phases: l axis at [0, M), m axis at [32, 32 + M)
+    __shared__ int box[4];               // chunk's rows [0], [1] and columns [2], [3] (min, max)
+    __shared__ float4 rec[CH];           // chunk samples: k_lo, w conj(R), table slot
+
+    const int m = a.m, half_m = m >> 1;
+    const int m2p = (m * m + 3) & ~3;
+    const int O = a.oversample, so = S * O;
+    // dynamic LDS: sub-tables [2 groups][S][SP] | image-plane products | patch [PB][PB]
+    float2* tab = reinterpret_cast<float2*>(smem);
+    float* gsh = reinterpret_cast<float*>(tab + (size_t)2 * win_max_groups(O) * S * SP);
+    float2* patch = reinterpret_cast<float2*>(gsh + m2p);
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int per_xcd = gridDim.x >> 3;
+    const int li = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (li >= a.n_items) return;
+    const Item it = a.items[a.item_begin + li];
+
+    const int P = a.grid_n + S;  // pitch of the padded grid
+    const float inv_s = 1.0f / (float)S;
+    for (int t = tid; t < so; t += kGridThreads) twsh[t] = a.tw[t];
+
+    // the item's samples: one contiguous range of the sample array
+    const int n_grp = it.grp_end - it.grp_begin;
+    uint32_t s_lo = UINT_MAX, s_n = 0;
+    for (int gl = 0; gl < n_grp; ++gl) {
+        const Group g = a.groups[it.grp_begin + gl];
+        s_lo = min(s_lo, g.vis_begin);
+        s_n += (uint32_t)(g.n_vis + g.n_vis2);
+    }
+    // this thread's tap (a_l, a_m) and its sub-table index b = (S-1-a_l, S-1-a_m)
+    const int al = tid / S, am = tid - (tid / S) * S;
+    const int boff = (S - 1 - al) * SP + (S - 1 - am);
+
+    for (int pol = 0; pol < a.n_pol; ++pol) {
+        image_products<kPredict>(a, it, pol, gsh, m2p, tid, kGridThreads);
+        __syncthreads();
+
+        // ---- sub-tables: wavefront w builds the groups w, w + W, ... (f at
+        // slot 2 gl, its partner -f at slot 2 gl + 1)
+        for (int gl = wave; gl < n_grp; gl += W) {
+            const Group g = a.groups[it.grp_begin + gl];
+            const int fl = g.f / O, fm = g.f - (g.f / O) * O;
+            float2* ph = phsh[wave];
+            if (lane < m) {
+                const int n = lane - half_m;
+                const float2 p = twsh[(fl * n) & (so - 1)];
+                const float sg = (n & 1) ? -inv_s : inv_s;
+                ph[lane] = make_float2(p.x * sg, p.y * sg);
+            } else if (lane >= 32 && lane - 32 < m) {
+                const int n = lane - 32 - half_m;
+                const float2 p = twsh[(fm * n) & (so - 1)];
+                const float sg = (n & 1) ? -inv_s : inv_s;
+                ph[lane] = make_float2(p.x * sg, p.y * sg);
+            }
+            wave_sync();
+            // fold: U[r] = sum over n = r mod S of phi_l(n_l) phi_m(n_m) g[n]
+            float2* T = tab + (size_t)(2 * gl) * S * SP;
+            for (int r = lane; r < NT; r += 64) {
+                const int rl = r / S, rm = r - (r / S) * S;
+                float2 u = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int el = 0; el < 2; ++el) {
+                    const int nl = rl - el * S;
+                    if (nl < -half_m || nl >= half_m) continue;
+                    float2 x = make_float2(0.f, 0.f);
+#pragma unroll
+                    for (int em = 0; em < 2; ++em) {
+                        const int nmv = rm - em * S;
+                        if (nmv < -half_m || nmv >= half_m) continue;
+                        const float gv = gsh[(nl + half_m) * m + nmv + half_m];
+                        const float2 pm = ph[32 + nmv + half_m];
+                        x.x = fmaf(gv, pm.x, x.x);
+                        x.y = fmaf(gv, pm.y, x.y);
+                    }
+                    cmac(u, ph[nl + half_m], x);
+                }
+                T[rl * SP + rm] = u;
+            }
+            wave_sync();
+            // S x S DFT: rows, then columns
+            if (lane < S) {
+                float2 x[S];
+#pragma unroll
+                for (int i = 0; i < S; ++i) x[i] = T[lane * SP + i];
+                fft_reg<S>(x);
+#pragma unroll
+                for (int i = 0; i < S; ++i) T[lane * SP + i] = x[i];
+            }
+            wave_sync();
+            if (lane < S) {
+                float2 x[S];
+#pragma unroll
+                for (int i = 0; i < S; ++i) x[i] = T[i * SP + lane];
+                fft_reg<S>(x);
+#pragma unroll
+                for (int i = 0; i < S; ++i) T[i * SP + lane] = x[i];
+            }
+            wave_sync();
+            if (g.n_vis2 > 0) {
+                // partner -f: the conjugate, reflected (b -> S-1-b on an axis
+                // with f != 0, b -> -b mod S on an axis with f = 0)
+                float2* T2 = T + S * SP;
+                for (int e = lane; e < NT; e += 64) {
+                    const int bl = e / S, bm = e - (e / S) * S;
+                    const int sl = fl ? (S - 1 - bl) : ((S - bl) & (S - 1));
+                    const int sm = fm ? (S - 1 - bm) : ((S - bm) & (S - 1));
+                    const float2 v = T[sl * SP + sm];
+                    T2[bl * SP + bm] = make_float2(v.x, -v.y);
+                }
+            }
+            wave_sync();  // the phases are rewritten by the wavefront's next group
+        }
+        __syncthreads();
+
+        // ---- chunks of CH samples in time order
+        for (uint32_t base = 0; base < s_n; base += CH) {
+            const int nch = (int)min((uint32_t)CH, s_n - base);
+            if (tid == 0) {
+                box[0] = INT_MAX;
+                box[1] = INT_MIN;
+                box[2] = INT_MAX;
+                box[3] = INT_MIN;
+            }
+            __syncthreads();
+            if (tid < nch) {
+                const uint2 od = a.ig_ord[s_lo + base + tid];
+                const VisEnt e = a.vis[od.x];
+                const size_t o = (size_t)e.vidx * a.n_pol + pol;
+                const float2 vo = a.vis_in[o], vm = a.vis_model[o];
+                const float wgt = a.weight[o];
+                // w conj(R), R = V^Obs - V formed in float64
+                const float rr = (float)((double)vo.x - (double)vm.x);
+                const float ri = (float)((double)vo.y - (double)vm.y);
+                rec[tid] = make_float4(__builtin_bit_cast(float, e.klo), wgt * rr, -wgt * ri,
+                                       __builtin_bit_cast(float, od.y));
+                const int row = (int)(e.klo >> 16), col = (int)(e.klo & 0xffffu);
+                atomicMin(&box[0], row);
+                atomicMax(&box[1], row);
+                atomicMin(&box[2], col);
+                atomicMax(&box[3], col);
+            }
+            __syncthreads();
+            const int r0 = box[0], c0 = box[2];
+            const int hgt = box[1] - r0 + S, wid = box[3] - c0 + S;
+            const bool fits = hgt <= PB && wid <= PB;
+            if (fits)
+                for (int t = tid; t < hgt * PB; t += kGridThreads) patch[t] = make_float2(0.f, 0.f);
+            __syncthreads();
+            // the chunk's samples one after another: a sample's taps are
+            // distinct cells, so each adds without atomics, in sample order
+            // (float32 sums that do not depend on the schedule)
+            for (int k = 0; k < nch; ++k) {
+                const float4 rc = rec[k];
+                const uint32_t klo = __builtin_bit_cast(uint32_t, rc.x);
+                const int row = (int)(klo >> 16), col = (int)(klo & 0xffffu);
+                const float2 kv = tab[(size_t)__builtin_bit_cast(uint32_t, rc.w) * S * SP + boff];
+                const float vr = rc.y * kv.x - rc.z * kv.y, vi = rc.y * kv.y + rc.z * kv.x;
+                if (fits) {
+                    float2* pc = patch + (row - r0 + al) * PB + (col - c0 + am);
+                    const float2 p0 = *pc;
+                    *pc = make_float2(p0.x + vr, p0.y + vi);
+                    __syncthreads();
+                } else {
+                    double2* gd = a.grid_acc + (size_t)(row + al) * P + (col + am);
+                    unsafeAtomicAdd(&gd->x, (double)vr);
+                    unsafeAtomicAdd(&gd->y, (double)vi);
+                }
+            }
+            __syncthreads();
+            if (fits) {
+                for (int t = tid; t < hgt * wid; t += kGridThreads) {
+                    const int r = t / wid, cc = t - (t / wid) * wid;
+                    const float2 v = patch[r * PB + cc];
+                    double2* gd = a.grid_acc + (size_t)(r0 + r) * P + (c0 + cc);
+                    // cells no window of the chunk touched hold exact zeros
+                    if (v.x != 0.f) unsafeAtomicAdd(&gd->x, (double)v.x);
+                    if (v.y != 0.f) unsafeAtomicAdd(&gd->y, (double)v.y);
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+size_t grid_lds_bytes(int support, int m, int oversample)
+{
+    const size_t m2p = (size_t)((m * m + 3) & ~3);
+    return sizeof(float2) * 2 * win_max_groups(oversample) * support * (support + 1) + sizeof(float) * m2p +
+           sizeof(float2) * kGridPatch * kGridPatch;
+}
+
+hipError_t launch_grid(int support, const ItemArgs& a, hipStream_t s)
+{
+    if (a.n_items <= 0) return hipSuccess;
+    if (support != 16) return hipErrorInvalidValue;
+    const size_t sh = grid_lds_bytes(support, a.m, a.oversample);
+    if (sh > kGridLdsMax) return hipErrorInvalidValue;
+    static const hipError_t attr =
+        hipFuncSetAttribute((const void*)k_grid<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGridLdsMax);
+    if (attr != hipSuccess) return attr;
+    const int blocks = 8 * ((a.n_items + 7) / 8);
+    k_grid<16><<<blocks, kGridThreads, sh, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace psc

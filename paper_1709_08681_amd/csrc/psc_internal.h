@@ -78,6 +78,9 @@ struct ItemArgs {
     double2* grid_acc;          // grid mode: residual grid, (N+S) x (N+S), float64 sums
     const double* par_angle;    // nullable [n_row]: offsets in the mount frame (window form)
     int32_t use_mfma;           // degrid on the matrix cores (gradient and adjoint)
+    // image-gradient scatter (k_grid)
+    const uint2* ig_ord;        // per item, its samples in time order: (sample index, sub-table slot)
+    const float2* vis_model;    // V from the preceding predict
 };
 
 struct ReduceArgs {
@@ -133,6 +136,16 @@ hipError_t launch_win(int mode, int support, const ItemArgs& a, hipStream_t s);
 size_t win_lds_bytes(int support, int mode, int m, int oversample, int mount_frame_tab = -1);
 size_t winw_lds_bytes(int support, int waves, int mode, int m, int oversample, int mount_frame_tab = -1);
 size_t win_lds_budget(int support);
+// Image-gradient scatter with per-item LDS patches (psc_grid.hip), support
+// 16: one thread per tap, chunks of kGridChunk samples, patches of
+// kGridPatch^2 cells.  grid_lds_bytes is its dynamic LDS; launch_grid refuses
+// more than kGridLdsMax (the caller then uses the table-form scatter).
+constexpr int kGridThreads = 256;
+constexpr int kGridPatch = 48;
+constexpr int kGridChunk = 32;
+constexpr size_t kGridLdsMax = 150 * 1024;
+size_t grid_lds_bytes(int support, int m, int oversample);
+hipError_t launch_grid(int support, const ItemArgs& a, hipStream_t s);
 hipError_t launch_reduce(int ncontrib, const ReduceArgs& a, hipStream_t s);
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
 hipError_t launch_init_state(int32_t* done, int32_t* iters, int n, hipStream_t s);
