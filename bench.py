@@ -122,7 +122,8 @@ def batched_vs_plain(cfg, iters, device=0):
 
 def image_gradient_timing(s, obs, off, v_obs, w, reps, stream):
     """psc_image_gradient (d chi^2 / d I on the model grid) on the same data:
-    V-only degrid, residual scatter with float64 atomics, float64 N^2 FFT."""
+    predict, residual scatter through per-item LDS patches (float64 atomics
+    once per patch cell), float64 N^2 FFT."""
     import torch
     from paper_1709_08681_amd import psc as P
     n = obs.grid_n
@@ -138,7 +139,7 @@ def image_gradient_timing(s, obs, off, v_obs, w, reps, stream):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     return {"ms_per_call": ms, "vis_per_s": obs.n_vis / (ms * 1e-3), "calls": reps,
-            "grid": f"{n}^2", "note": "table form, support 16"}
+            "grid": f"{n}^2", "note": "table form, support 16, LDS-patch scatter"}
 
 
 def mount_frame_timing(obs, start, reps, device=0):
