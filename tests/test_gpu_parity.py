@@ -672,6 +672,26 @@ def test_image_gradient_cfg2_full_size(torch_dev):
         s.close()
 
 
+@pytest.mark.parametrize("over,dt", [(2, 30.0), (4, 600.0), (8, 30.0)])
+def test_image_gradient_scatter_paths(torch_dev, over, dt):
+    """The image gradient through each scatter: LDS patches at oversampling 2;
+    10-minute steps at oversampling 4, whose chunks span more than a patch and
+    add their taps directly; the one-pass table-form scatter at oversampling
+    8, where an item's sub-tables do not fit in LDS."""
+    torch = torch_dev
+    print(f"case: image gradient scatter, O {over}, dt {dt}", flush=True)
+    obs = small_ragged_obs(95, oversample=over, dt_s=dt)
+    prob = oracle.Problem.from_observation(obs)
+    s = session(obs)
+    try:
+        v = oracle.predict(prob, obs.offsets_true)
+        nz, w = synth.noise(v, 100.0, 31)
+        start = synth.perturbed_offsets(obs, 20.0, 32)
+        _check_image_gradient(torch, obs, prob, s, start, v + nz, w, 64, 33)
+    finally:
+        s.close()
+
+
 # ---------------------------------------------------------------------------
 # offsets in the antenna mount frame (per-row parallactic angle)
 # ---------------------------------------------------------------------------
