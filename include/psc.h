@@ -222,15 +222,17 @@ PSC_API psc_status psc_predict_vjp(psc_ctx* ctx, psc_obs* obs, const double* off
  *  vis_obs_dev, weight_dev  as for psc_gradient
  *  image_grad_out_dev [N][N] float64, indexed like the image of psc_set_model
  *  vis_model_dev      nullable; receives V^M
- * Table form at support 16 (PSC_E_UNSUPPORTED at 32).  The first call
- * allocates the context's scratch, (N+S)^2 + 2 N^2 complex float64, and, for
- * oversampling up to 4 (where every sub-table of an item fits in LDS), the
- * observation's time order of each item's samples (8 bytes per sample, built
- * on the host from a copy of the plan: a blocking call), and, when
- * vis_model_dev is null, room for V^M (complex64 per visibility).  The
- * samples of a 32-sample chunk are summed in float32 in a fixed order, and
- * chunks are added to the residual grid with float64 atomics, so results
- * agree between runs to float64 rounding, not bit for bit.
+ * Sky-frame offsets (PSC_E_UNSUPPORTED in the mount frame).  At support 16
+ * the scatter uses the item's sub-tables; at 32 it builds each sample's
+ * kernel.  The first call allocates the context's scratch, (N+S)^2 + 2 N^2
+ * complex float64; at support 16 with oversampling up to 4 (where every
+ * sub-table of an item fits in LDS) the observation's time order of each
+ * item's samples (8 bytes per sample, built on the host from a copy of the
+ * plan: a blocking call); and, when vis_model_dev is null, room for V^M
+ * (complex64 per visibility).  Taps are summed in float32 LDS patches in a
+ * fixed order and the patches added to the residual grid with float64
+ * atomics, so results agree between runs to float64 rounding, not bit for
+ * bit.
  */
 PSC_API psc_status psc_image_gradient(psc_ctx* ctx, psc_obs* obs, const double* offsets_dev,
                                       const void* vis_obs_dev, const float* weight_dev,

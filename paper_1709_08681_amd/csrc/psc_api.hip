@@ -760,7 +760,6 @@ PSC_API psc_status psc_image_gradient(psc_ctx* ctx, psc_obs* obs, const double* 
     if (st != PSC_OK) return st;
     if (!image_grad_out_dev || ((!vis_obs_dev || !weight_dev) && obs->n_vis > 0))
         return fail(ctx, PSC_E_ARG, "null data or output");
-    if (ctx->s != 16) return fail(ctx, PSC_E_UNSUPPORTED, "the image gradient is built for support 16");
     if (obs->par_angle)
         return fail(ctx, PSC_E_UNSUPPORTED, "the image gradient is built for sky-frame offsets");
     const int n = ctx->n;
@@ -787,9 +786,11 @@ PSC_API psc_status psc_image_gradient(psc_ctx* ctx, psc_obs* obs, const double* 
     a.grid_acc = ctx->rgrid;
     a.use_mfma = 0;
     PSC_HIP(ctx, launch_zero(ctx->rgrid, np, s));
-    if (grid_lds_bytes(ctx->s, ctx->m, ctx->o) <= kGridLdsMax) {
-        // predict, then the patch scatter over each item's samples in time order
-        if (!obs->ig_ord && obs->n_vis > 0) {
+    const bool table_patch = ctx->s == 16 && grid_lds_bytes(ctx->s, ctx->m, ctx->o) <= kGridLdsMax;
+    if (table_patch || ctx->s == 32) {
+        // predict, then a patch scatter: per item with its sub-tables and its
+        // samples in time order (support 16), or with a kernel per sample
+        if (table_patch && !obs->ig_ord && obs->n_vis > 0) {
             psc_status bs = build_time_order(ctx, obs);
             if (bs != PSC_OK) return bs;
         }
@@ -803,7 +804,10 @@ PSC_API psc_status psc_image_gradient(psc_ctx* ctx, psc_obs* obs, const double* 
         PSC_HIP(ctx, launch_degrid(kPredict, ctx, obs, a, s));
         a.vis_model = vm;
         a.ig_ord = obs->ig_ord;
-        PSC_HIP(ctx, launch_grid(ctx->s, a, s));
+        if (table_patch)
+            PSC_HIP(ctx, launch_grid(ctx->s, a, s));
+        else
+            PSC_HIP(ctx, launch_gridw(ctx->s, a, s));
     } else {
         // the table-form scatter: degrid and spread in one pass, a float64
         // atomic per tap

@@ -217,6 +217,271 @@ __global__ void __launch_bounds__(kGridThreads) k_grid(ItemArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Per-sample kernels: support 32, and offsets in the mount frame.
+//
+// Where an item's sub-tables do not fit in LDS (support 32), or every sample
+// has a kernel of its own (mount frame: each row's parallactic angle rotates
+// the beams), each wavefront builds the kernel of one sample at a time: the
+// fold of the image-plane products with the sample's own phases (its offset
+// f, or -f for a partner sample) and an S x S DFT through the wavefront's
+// tile, exactly the sub-table the degrid used for it.  The block then adds
+// the round's kernels, times w conj(R), to an LDS patch covering the item's
+// windows, one sample after another in a fixed order, and adds the patch to
+// the residual grid once at the end of the item; an item whose windows span
+// more than a patch adds every tap directly with float64 atomics.
+template <int S, bool MF>
+__global__ void __launch_bounds__(kGridThreads) k_gridw(ItemArgs a)
+{
+    constexpr int SP = S + 1, NT = S * S, W = kGridThreads / 64;
+    constexpr int PB = kGridPatch;
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ float2 twsh[S * 16];  // exp(+2 pi i t / (S O)), S O <= 16 S
+    __shared__ float2 phsh[W][128];  // per wavefront: l-axis phases at [0, M), m axis at [64, 64 + M)
+    __shared__ int box[4];           // item windows' first rows [0], [1] and columns [2], [3] (min, max)
+    __shared__ float4 crec[W];       // per wavefront: w conj(R), k_lo, whether it has a sample
+
+    const int m = a.m, half_m = m >> 1;
+    const int m2p = (m * m + 3) & ~3;
+    const int O = a.oversample, so = S * O;
+    // dynamic LDS: image-plane products (sky frame) | tiles [W][S][SP] | patch [PB][PB] | Airy table (MF)
+    float* gsh = reinterpret_cast<float*>(smem);
+    float2* tiles = reinterpret_cast<float2*>(gsh + (MF ? 0 : m2p));
+    float2* patch = tiles + (size_t)W * S * SP;
+    float4* airy_sh = reinterpret_cast<float4*>(patch + PB * PB);
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int per_xcd = gridDim.x >> 3;
+    const int li = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (li >= a.n_items) return;
+    const Item it = a.items[a.item_begin + li];
+
+    const int P = a.grid_n + S;  // pitch of the padded grid
+    const float inv_s = 1.0f / (float)S;
+    for (int t = tid; t < so; t += kGridThreads) twsh[t] = a.tw[t];
+    if constexpr (MF)
+        for (int t = tid; t < a.n_tab; t += kGridThreads) airy_sh[t] = a.airy[t];
+    if (tid == 0) {
+        box[0] = INT_MAX;
+        box[1] = INT_MIN;
+        box[2] = INT_MAX;
+        box[3] = INT_MIN;
+    }
+    // the item's samples: one contiguous range of the sample array
+    const int n_grp = it.grp_end - it.grp_begin;
+    uint32_t s_lo = UINT_MAX, s_n = 0;
+    for (int gl = 0; gl < n_grp; ++gl) {
+        const Group g = a.groups[it.grp_begin + gl];
+        s_lo = min(s_lo, g.vis_begin);
+        s_n += (uint32_t)(g.n_vis + g.n_vis2);
+    }
+    __syncthreads();
+    for (uint32_t k = tid; k < s_n; k += kGridThreads) {
+        const uint32_t klo = a.vis[s_lo + k].klo;
+        const int row = (int)(klo >> 16), col = (int)(klo & 0xffffu);
+        atomicMin(&box[0], row);
+        atomicMax(&box[1], row);
+        atomicMin(&box[2], col);
+        atomicMax(&box[3], col);
+    }
+    __syncthreads();
+    const int r0 = box[0], c0 = box[2];
+    const int hgt = box[1] - r0 + S, wid = box[3] - c0 + S;
+    const bool fits = s_n > 0 && hgt <= PB && wid <= PB;
+
+    // beam constants of the item's channel (mount frame)
+    const double lam = kCLight / a.freq[it.chan];
+    const float kk = (float)(kPi * a.dish / lam);
+    const double sigma = a.gauss_sigma_ld * lam / a.dish;
+    const float inv_s2 = (float)(1.0 / (sigma * sigma));
+    const float hstep = (float)a.h;
+    float2* wt = tiles + (size_t)wave * S * SP;
+    float2* ph = phsh[wave];
+
+    for (int pol = 0; pol < a.n_pol; ++pol) {
+        const double sq = (pol == 0 ? 1.0 : -1.0) * a.squint_frac * 1.02899 * lam / a.dish;
+        const double* oi = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.ai) * 2;
+        const double* oj = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.aj) * 2;
+        const double qil = oi[0] + sq, qim = oi[1], qjl = oj[0] + sq, qjm = oj[1];
+        if constexpr (!MF) image_products<kPredict>(a, it, pol, gsh, m2p, tid, kGridThreads);
+        if (fits)
+            for (int t = tid; t < hgt * PB; t += kGridThreads) patch[t] = make_float2(0.f, 0.f);
+        __syncthreads();
+
+        for (uint32_t base = 0; base < s_n; base += W) {
+            // ---- wavefront w builds the kernel of the item's sample base + w
+            const uint32_t k = base + wave;
+            if (k < s_n) {
+                const uint32_t idx = s_lo + k;
+                // its group and part
+                int fl = 0, fm = 0;
+                for (int gl = 0; gl < n_grp; ++gl) {
+                    const Group g = a.groups[it.grp_begin + gl];
+                    if (idx >= g.vis_begin && idx < g.vis_begin + (uint32_t)(g.n_vis + g.n_vis2)) {
+                        fl = g.f / O;
+                        fm = g.f - (g.f / O) * O;
+                        if (idx >= g.vis_begin + (uint32_t)g.n_vis) {
+                            fl = (O - fl) & (O - 1);
+                            fm = (O - fm) & (O - 1);
+                        }
+                    }
+                }
+                const VisEnt e = a.vis[idx];
+                const size_t o = (size_t)e.vidx * a.n_pol + pol;
+                // per-axis phases (-1)^n exp(2 pi i f n / (S O)) / S of the sample's offset
+                for (int j = lane; j < m; j += 64) {
+                    const int n = j - half_m;
+                    const float sg = (n & 1) ? -inv_s : inv_s;
+                    const float2 pl = twsh[(fl * n) & (so - 1)], pm = twsh[(fm * n) & (so - 1)];
+                    ph[j] = make_float2(pl.x * sg, pl.y * sg);
+                    ph[64 + j] = make_float2(pm.x * sg, pm.y * sg);
+                }
+                float pil = (float)qil, pim = (float)qim, pjl = (float)qjl, pjm = (float)qjm;
+                if constexpr (MF) {
+                    // this row's beam centres on the sky
+                    float sn, cs;
+                    sincosf((float)a.par_angle[e.vidx / (uint32_t)a.n_chan], &sn, &cs);
+                    pil = (float)(cs * qil - sn * qim);
+                    pim = (float)(sn * qil + cs * qim);
+                    pjl = (float)(cs * qjl - sn * qjm);
+                    pjm = (float)(sn * qjl + cs * qjm);
+                }
+                wave_sync();
+                // fold: U[r] = sum over n = r mod S of phi_l(n_l) phi_m(n_m) g[n]
+                for (int r = lane; r < NT; r += 64) {
+                    const int rl = r / S, rm = r - (r / S) * S;
+                    float2 u = make_float2(0.f, 0.f);
+#pragma unroll
+                    for (int el = 0; el < 2; ++el) {
+                        const int nl = rl - el * S;
+                        if (nl < -half_m || nl >= half_m) continue;
+                        float2 x = make_float2(0.f, 0.f);
+#pragma unroll
+                        for (int em = 0; em < 2; ++em) {
+                            const int nmv = rm - em * S;
+                            if (nmv < -half_m || nmv >= half_m) continue;
+                            float gv;
+                            if constexpr (MF) {
+                                const float l = (float)nl * hstep, mm = (float)nmv * hstep;
+                                float ei, qi, ej, qj;
+                                efq(a, airy_sh, kk, inv_s2, l - pil, mm - pim, ei, qi);
+                                efq(a, airy_sh, kk, inv_s2, l - pjl, mm - pjm, ej, qj);
+                                gv = ei * ej * (a.taper_img[nl + half_m] * a.taper_img[nmv + half_m]);
+                            } else {
+                                gv = gsh[(nl + half_m) * m + nmv + half_m];
+                            }
+                            const float2 pm = ph[64 + nmv + half_m];
+                            x.x = fmaf(gv, pm.x, x.x);
+                            x.y = fmaf(gv, pm.y, x.y);
+                        }
+                        cmac(u, ph[nl + half_m], x);
+                    }
+                    wt[rl * SP + rm] = u;
+                }
+                wave_sync();
+                // S x S DFT: rows, then columns
+                if (lane < S) {
+                    float2 x[S];
+#pragma unroll
+                    for (int i = 0; i < S; ++i) x[i] = wt[lane * SP + i];
+                    fft_reg<S>(x);
+#pragma unroll
+                    for (int i = 0; i < S; ++i) wt[lane * SP + i] = x[i];
+                }
+                wave_sync();
+                if (lane < S) {
+                    float2 x[S];
+#pragma unroll
+                    for (int i = 0; i < S; ++i) x[i] = wt[i * SP + lane];
+                    fft_reg<S>(x);
+#pragma unroll
+                    for (int i = 0; i < S; ++i) wt[i * SP + lane] = x[i];
+                }
+                if (lane == 0) {
+                    // w conj(R), R = V^Obs - V formed in float64
+                    const float2 vo = a.vis_in[o], vm = a.vis_model[o];
+                    const float wgt = a.weight[o];
+                    const float rr = (float)((double)vo.x - (double)vm.x);
+                    const float ri = (float)((double)vo.y - (double)vm.y);
+                    crec[wave] = make_float4(wgt * rr, -wgt * ri, __builtin_bit_cast(float, e.klo), 1.f);
+                }
+            } else if (lane == 0) {
+                crec[wave] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            __syncthreads();
+
+            // ---- the round's kernels times w conj(R), in wavefront order
+            for (int w2 = 0; w2 < W; ++w2) {
+                const float4 rc = crec[w2];
+                if (rc.w == 0.f) continue;
+                const uint32_t klo = __builtin_bit_cast(uint32_t, rc.z);
+                const int row = (int)(klo >> 16), col = (int)(klo & 0xffffu);
+                const float2* T = tiles + (size_t)w2 * S * SP;
+                for (int t = tid; t < NT; t += kGridThreads) {
+                    // tap (a_l, a_m) at sub-table index (S-1-a_l, S-1-a_m)
+                    const int al = t / S, am = t - (t / S) * S;
+                    const float2 kv = T[(S - 1 - al) * SP + (S - 1 - am)];
+                    const float vr = rc.x * kv.x - rc.y * kv.y, vi = rc.x * kv.y + rc.y * kv.x;
+                    if (fits) {
+                        float2* pc = patch + (row - r0 + al) * PB + (col - c0 + am);
+                        const float2 p0 = *pc;
+                        *pc = make_float2(p0.x + vr, p0.y + vi);
+                    } else {
+                        double2* gd = a.grid_acc + (size_t)(row + al) * P + (col + am);
+                        unsafeAtomicAdd(&gd->x, (double)vr);
+                        unsafeAtomicAdd(&gd->y, (double)vi);
+                    }
+                }
+                if (fits) __syncthreads();  // the next sample's taps may reach the same cells
+            }
+            __syncthreads();  // tiles and records are rewritten by the next round
+        }
+
+        if (fits) {
+            for (int t = tid; t < hgt * wid; t += kGridThreads) {
+                const int r = t / wid, cc = t - (t / wid) * wid;
+                const float2 v = patch[r * PB + cc];
+                double2* gd = a.grid_acc + (size_t)(r0 + r) * P + (c0 + cc);
+                // cells no window of the item touched hold exact zeros
+                if (v.x != 0.f) unsafeAtomicAdd(&gd->x, (double)v.x);
+                if (v.y != 0.f) unsafeAtomicAdd(&gd->y, (double)v.y);
+            }
+        }
+        __syncthreads();  // the patch and products are rewritten for the next polarisation
+    }
+}
+
+size_t gridw_lds_bytes(int support, int m, int mount_frame_tab)
+{
+    const bool mf = mount_frame_tab >= 0;
+    const size_t m2p = (size_t)((m * m + 3) & ~3);
+    return (mf ? 0 : sizeof(float) * m2p) + sizeof(float2) * (kGridThreads / 64) * support * (support + 1) +
+           sizeof(float2) * kGridPatch * kGridPatch + (mf ? sizeof(float4) * mount_frame_tab : 0);
+}
+
+template <int S, bool MF>
+static hipError_t launch_gridw_t(const ItemArgs& a, hipStream_t s)
+{
+    const size_t sh = gridw_lds_bytes(S, a.m, MF ? a.n_tab : -1);
+    if (sh > kGridLdsMax) return hipErrorInvalidValue;
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void*)k_gridw<S, MF>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGridLdsMax);
+    if (attr != hipSuccess) return attr;
+    const int blocks = 8 * ((a.n_items + 7) / 8);
+    k_gridw<S, MF><<<blocks, kGridThreads, sh, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gridw(int support, const ItemArgs& a, hipStream_t s)
+{
+    if (a.n_items <= 0) return hipSuccess;
+    const bool mf = a.par_angle != nullptr;
+    if (support == 16) return mf ? launch_gridw_t<16, true>(a, s) : launch_gridw_t<16, false>(a, s);
+    if (support == 32) return mf ? launch_gridw_t<32, true>(a, s) : launch_gridw_t<32, false>(a, s);
+    return hipErrorInvalidValue;
+}
+
 size_t grid_lds_bytes(int support, int m, int oversample)
 {
     const size_t m2p = (size_t)((m * m + 3) & ~3);

@@ -146,6 +146,10 @@ constexpr int kGridChunk = 32;
 constexpr size_t kGridLdsMax = 150 * 1024;
 size_t grid_lds_bytes(int support, int m, int oversample);
 hipError_t launch_grid(int support, const ItemArgs& a, hipStream_t s);
+// The same scatter with a kernel built per sample (support 32, mount frame):
+// gridw_lds_bytes is its dynamic LDS (mount_frame_tab as for win_lds_bytes).
+size_t gridw_lds_bytes(int support, int m, int mount_frame_tab = -1);
+hipError_t launch_gridw(int support, const ItemArgs& a, hipStream_t s);
 hipError_t launch_reduce(int ncontrib, const ReduceArgs& a, hipStream_t s);
 hipError_t launch_solve(const SolveArgs& a, hipStream_t s);
 hipError_t launch_init_state(int32_t* done, int32_t* iters, int n, hipStream_t s);

@@ -692,6 +692,36 @@ def test_image_gradient_scatter_paths(torch_dev, over, dt):
         s.close()
 
 
+@pytest.mark.parametrize("over,dt", [(8, 30.0), (4, 600.0)])
+def test_image_gradient_support32(torch_dev, over, dt):
+    """Support 32: a kernel built per sample and scattered through an item
+    patch (30 s steps) or tap by tap (10-minute steps, items wider than a
+    patch)."""
+    torch = torch_dev
+    print(f"case: image gradient support 32, O {over}, dt {dt}", flush=True)
+    obs = small_ragged_obs(97, support=32, oversample=over, dt_s=dt)
+    prob = oracle.Problem.from_observation(obs)
+    s = session(obs)
+    try:
+        v = oracle.predict(prob, obs.offsets_true)
+        nz, w = synth.noise(v, 100.0, 34)
+        start = synth.perturbed_offsets(obs, 20.0, 35)
+        G1 = _check_image_gradient(torch, obs, prob, s, start, v + nz, w, 64, 36)
+        G2 = s.image_gradient(s.offsets(start), c64(torch, s, v + nz), f32(torch, s, w, s.vis_shape))
+        assert rel(G2.cpu().numpy(), G1.cpu().numpy()) <= 1e-12
+    finally:
+        s.close()
+
+
+def test_image_gradient_cfg5_subset(torch_dev, cfg5_subset):
+    torch = torch_dev
+    obs, prob, s = cfg5_subset
+    print("case: image gradient cfg5 subset", flush=True)
+    v = oracle.predict(prob, obs.offsets_true)
+    start = synth.perturbed_offsets(obs, 30.0, 37)
+    _check_image_gradient(torch, obs, prob, s, start, v, 1.0, 48, 38)
+
+
 # ---------------------------------------------------------------------------
 # offsets in the antenna mount frame (per-row parallactic angle)
 # ---------------------------------------------------------------------------
