@@ -395,11 +395,28 @@ int oracle_gradient(const orc_problem* p, const double* offsets, const double* v
  * derivative of one visibility with respect to one pixel's flux, so out is
  * exact for pixels on or off the model's support.
  */
+/* The pattern of antenna a at sky position (l, m) in a row with parallactic
+ * angle chi, for offsets in the mount frame: the beam centre on the sky is
+ * R(chi) (q + squint), as in beam_row. */
+static double beam_at_row(const orc_problem* p, const double* offs_int, int pol, int a, int c, double chi,
+                          double l, double m)
+{
+    double lambda = ORC_C_LIGHT / p->freq_hz[c];
+    double sq = (pol == 0 ? 1.0 : -1.0) * p->squint_frac * hpbw_rad(lambda, p->dish_diam_m);
+    double ql = offs_int[(pol * p->n_ant + a) * 2 + 0] + sq;
+    double qm = offs_int[(pol * p->n_ant + a) * 2 + 1];
+    double cs = cos(chi), sn = sin(chi);
+    double e[3];
+    oracle_efp(p->illum, p->dish_diam_m, p->gauss_sigma_ld, p->freq_hz[c], l - (cs * ql - sn * qm),
+               m - (sn * ql + cs * qm), e);
+    return e[0];
+}
+
 int oracle_image_gradient(const orc_problem* p, const double* offsets, const double* vis_obs,
                           const double* weight, int n_pix, const double* pix_l, const double* pix_m,
                           double* out)
 {
-    if (check_problem(p) || n_pix < 0 || p->par_angle) return -1;
+    if (check_problem(p) || n_pix < 0) return -1;
     size_t n_vis = (size_t)p->n_row * p->n_chan * p->n_pol;
     double* vm = (double*)malloc((n_vis ? n_vis : 1) * 2 * sizeof(double));
     double* ones = (double*)malloc((n_pix ? n_pix : 1) * sizeof(double));
@@ -423,8 +440,9 @@ int oracle_image_gradient(const orc_problem* p, const double* offsets, const dou
         int64_t r0 = p->int_row_ptr[s], r1 = p->int_row_ptr[s + 1];
         if (r0 == r1) continue;
         const double* offs_int = offsets + (size_t)s * p->n_pol * p->n_ant * 2;
-        double* tab = beam_table(&q, offs_int);
-        if (!tab) {
+        /* sky frame: every row of the interval sees the same beams */
+        double* tab = p->par_angle ? NULL : beam_table(&q, offs_int);
+        if (!p->par_angle && !tab) {
             rc = -2;
             break;
         }
@@ -440,8 +458,14 @@ int oracle_image_gradient(const orc_problem* p, const double* offsets, const dou
                     double cr = cos(ph), ci = sin(ph);
                     for (int pol = 0; pol < p->n_pol; ++pol) {
                         size_t idx = ((size_t)r * p->n_chan + c) * p->n_pol + pol;
-                        double ei = tab[3 * ((((size_t)pol * p->n_ant + ai) * p->n_chan + c) * n_pix + k)];
-                        double ej = tab[3 * ((((size_t)pol * p->n_ant + aj) * p->n_chan + c) * n_pix + k)];
+                        double ei, ej;
+                        if (p->par_angle) {
+                            ei = beam_at_row(p, offs_int, pol, ai, c, p->par_angle[r], pix_l[k], pix_m[k]);
+                            ej = beam_at_row(p, offs_int, pol, aj, c, p->par_angle[r], pix_l[k], pix_m[k]);
+                        } else {
+                            ei = tab[3 * ((((size_t)pol * p->n_ant + ai) * p->n_chan + c) * n_pix + k)];
+                            ej = tab[3 * ((((size_t)pol * p->n_ant + aj) * p->n_chan + c) * n_pix + k)];
+                        }
                         double rr = vis_obs[2 * idx] - vm[2 * idx];
                         double ri = vis_obs[2 * idx + 1] - vm[2 * idx + 1];
                         acc += weight[idx] * ei * ej * (rr * cr + ri * ci);

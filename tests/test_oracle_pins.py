@@ -351,11 +351,13 @@ def test_solver_noisy_recovery_within_expected_scatter(oracle_lib):
 # Image gradient (the model-update direction of the self-calibration loop)
 # --------------------------------------------------------------------------
 
-def test_image_gradient_matches_chi2_differences(oracle_lib):
+@pytest.mark.parametrize("mount", [False, True])
+def test_image_gradient_matches_chi2_differences(oracle_lib, mount):
     """d chi^2 / d I_p against central differences of chi^2 in the flux of
     pixel p: for model pixels, and for empty pixels added to the sky with zero
     flux.  chi^2 is quadratic in the fluxes, so central differences are exact
-    up to rounding.  Two pols with squint, two intervals."""
+    up to rounding.  Two pols with squint, two intervals; with mount, offsets
+    in the antenna mount frame and a parallactic angle that differs per row."""
     o = oracle_lib
     rng = np.random.default_rng(21)
     n_ant, n_time = 4, 3
@@ -371,9 +373,11 @@ def test_image_gradient_matches_chi2_differences(oracle_lib):
     ptr = [0, 2 * 6, ant1.size]
     freqs = [1.2e9, 1.7e9]
 
+    pa = rng.uniform(-1.2, 1.2, ant1.size) if mount else None
+
     def prob_with(f):
         return o.Problem(src_l, src_m, f, n_ant, ant1, ant2, uv, ptr, freqs, n_pol=2,
-                         squint_frac=0.03, snap_scale=0.0)
+                         squint_frac=0.03, snap_scale=0.0, par_angle=pa)
 
     prob = prob_with(flux)
     offs = rng.normal(0.0, 30 * ARCSEC, size=prob.offsets_shape())
@@ -392,6 +396,23 @@ def test_image_gradient_matches_chi2_differences(oracle_lib):
         fm[k] -= h
         fd = (chi2(fp) - chi2(fm)) / (2 * h)
         assert abs(fd - g[k]) <= 1e-8 * max(abs(fd), 1e-6), (k, fd, g[k])
+
+
+def test_image_gradient_mount_frame_zero_angle(oracle_lib):
+    """Mount-frame offsets with every parallactic angle zero give the
+    sky-frame image gradient (the per-row beams reduce to the per-interval
+    ones)."""
+    o = oracle_lib
+    prob, offs = _tiny_problem(o, n_pol=2, squint=0.03)
+    pl = np.array([0.0, 0.003, -0.008, 0.006])
+    pm = np.array([0.0, -0.005, 0.002, 0.007])
+    vobs = o.predict(prob, offs) * 1.1 + 0.05
+    g_sky = o.image_gradient(prob, offs, vobs, 1.0, pl, pm)
+    mf = o.Problem(prob.src_l, prob.src_m, prob.src_flux, prob.n_ant, prob.ant1, prob.ant2, prob.uv_m,
+                   prob.int_row_ptr, prob.freq_hz, n_pol=2, squint_frac=0.03,
+                   par_angle=np.zeros(prob.ant1.size))
+    g_mf = o.image_gradient(mf, offs, vobs, 1.0, pl, pm)
+    np.testing.assert_allclose(g_mf, g_sky, rtol=1e-13, atol=0.0)
 
 
 def test_image_gradient_vanishes_at_truth_and_is_linear_in_weight(oracle_lib):
