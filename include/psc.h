@@ -222,9 +222,9 @@ PSC_API psc_status psc_predict_vjp(psc_ctx* ctx, psc_obs* obs, const double* off
  *  vis_obs_dev, weight_dev  as for psc_gradient
  *  image_grad_out_dev [N][N] float64, indexed like the image of psc_set_model
  *  vis_model_dev      nullable; receives V^M
- * Sky-frame offsets (PSC_E_UNSUPPORTED in the mount frame).  At support 16
- * the scatter uses the item's sub-tables; at 32 it builds each sample's
- * kernel.  The first call allocates the context's scratch, (N+S)^2 + 2 N^2
+ * At support 16 with sky-frame offsets the scatter uses the item's
+ * sub-tables; at 32, and with offsets in the mount frame (where each row's
+ * beams differ), it builds each sample's kernel.  The first call allocates the context's scratch, (N+S)^2 + 2 N^2
  * complex float64; at support 16 with oversampling up to 4 (where every
  * sub-table of an item fits in LDS) the observation's time order of each
  * item's samples (8 bytes per sample, built on the host from a copy of the

@@ -760,8 +760,6 @@ PSC_API psc_status psc_image_gradient(psc_ctx* ctx, psc_obs* obs, const double* 
     if (st != PSC_OK) return st;
     if (!image_grad_out_dev || ((!vis_obs_dev || !weight_dev) && obs->n_vis > 0))
         return fail(ctx, PSC_E_ARG, "null data or output");
-    if (obs->par_angle)
-        return fail(ctx, PSC_E_UNSUPPORTED, "the image gradient is built for sky-frame offsets");
     const int n = ctx->n;
     const size_t np = (size_t)(n + ctx->s) * (n + ctx->s);
     if (!ctx->rgrid) {
@@ -786,10 +784,12 @@ PSC_API psc_status psc_image_gradient(psc_ctx* ctx, psc_obs* obs, const double* 
     a.grid_acc = ctx->rgrid;
     a.use_mfma = 0;
     PSC_HIP(ctx, launch_zero(ctx->rgrid, np, s));
-    const bool table_patch = ctx->s == 16 && grid_lds_bytes(ctx->s, ctx->m, ctx->o) <= kGridLdsMax;
-    if (table_patch || ctx->s == 32) {
+    const bool table_patch =
+        ctx->s == 16 && !obs->par_angle && grid_lds_bytes(ctx->s, ctx->m, ctx->o) <= kGridLdsMax;
+    if (table_patch || ctx->s == 32 || obs->par_angle) {
         // predict, then a patch scatter: per item with its sub-tables and its
-        // samples in time order (support 16), or with a kernel per sample
+        // samples in time order (support 16, sky frame), or with a kernel per
+        // sample (support 32, mount frame)
         if (table_patch && !obs->ig_ord && obs->n_vis > 0) {
             psc_status bs = build_time_order(ctx, obs);
             if (bs != PSC_OK) return bs;

@@ -777,10 +777,6 @@ def test_mount_frame_predict_gradient_vjp(torch_dev, mount):
                     gref[it, p, j, ax] += (np.conj(g) * dv[r, c, p, 2 + ax]).real
     got = s.vjp(s.offsets(start), torch.as_tensor(G, device=s.dev)).cpu().numpy()
     assert rel(got, gref) <= 1e-4
-    out = torch.empty((obs.grid_n, obs.grid_n), dtype=torch.float64, device=s.dev)
-    with pytest.raises(psc.PscError) as ei:
-        psc.psc_image_gradient(s.ctx, s.handle, s.offsets(start), c64(torch, s, v), w1, out)
-    assert ei.value.status == psc.PSC_E_UNSUPPORTED
 
 
 def test_mount_frame_solve(torch_dev, mount):
@@ -808,6 +804,18 @@ def test_mount_frame_solve(torch_dev, mount):
     assert np.abs(off.cpu().numpy() - obs.offsets_true).max() / ARCSEC <= 0.05
 
 
+def test_mount_frame_image_gradient(torch_dev, mount):
+    """d chi^2 / d I with mount-frame offsets (every row's beams rotated by
+    its parallactic angle): a kernel built per sample."""
+    torch = torch_dev
+    obs, prob, s = mount
+    print("case: mount frame image gradient", flush=True)
+    v = oracle.predict(prob, obs.offsets_true)
+    nz, w = synth.noise(v, 100.0, 39)
+    start = synth.perturbed_offsets(obs, 20.0, 40)
+    _check_image_gradient(torch, obs, prob, s, start, v + nz, w, 48, 41)
+
+
 def test_mount_frame_support32(torch_dev, cfg5_subset):
     """Mount-frame offsets on the support-32 large-workload subset."""
     torch = torch_dev
@@ -825,5 +833,6 @@ def test_mount_frame_support32(torch_dev, cfg5_subset):
         live = obs.int_row_ptr[1:] > obs.int_row_ptr[:-1]
         for k in range(6):
             assert rel(acc[live][..., k], ref[live][..., k]) <= 1e-4, k
+        _check_image_gradient(torch, obs, prob, s, start, v, 1.0, 32, 42)
     finally:
         s.close()
