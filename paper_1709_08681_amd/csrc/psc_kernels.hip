@@ -400,9 +400,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
             const int t_xcol = t_xr ? 0 : (t_xl ? t_dl : t_dm);
             const int t_ycol = t_yr ? 0 : (t_yl ? t_dl : t_dm);
             // A pass degrids L * 64/S samples from v0 on (L per lane).  Full
-            // passes (L = SPL) run while more than 64/S samples remain; a
-            // remainder of at most 64/S samples takes one pass with L = 1, so
-            // the partly filled last pass of a part costs half as much.
+            // passes (L = SPL) run while more than (SPL - 1) 64/S samples
+            // remain; the remainder takes passes with L = 1 (one at SPL = 2),
+            // so the partly filled last pass of a part costs less.
             auto degrid = [&](uint32_t vb, int nv, VisEnt (&ent)[SPL]) {
             auto pass = [&](int v0, auto l_const) {
                 constexpr int L = decltype(l_const)::value;
@@ -502,7 +502,12 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
             };
             int v0 = 0;
             for (; nv - v0 > SPW * (SPL - 1); v0 += STEP) pass(v0, std::integral_constant<int, SPL>{});
-            if (v0 < nv) pass(v0, std::integral_constant<int, 1>{});
+            for (int q = 0; v0 < nv; v0 += SPW, ++q) {
+                // the first remainder pass has its entry from the last full
+                // pass; later ones (SPL > 2) fetch theirs
+                if (q > 0) ent[0] = a.vis[vb + (v0 + slot < nv ? v0 + slot : nv - 1)];
+                pass(v0, std::integral_constant<int, 1>{});
+            }
             };  // degrid
 
             if constexpr (MX) {
