@@ -57,6 +57,7 @@ class _Problem(C.Structure):
         ("squint_frac", C.c_double),
         ("snap_scale", C.c_double),
         ("par_angle", C.POINTER(C.c_double)),
+        ("w_m", C.POINTER(C.c_double)),
     ]
 
 
@@ -102,12 +103,13 @@ class Problem:
 
     ``src_l, src_m, src_flux``: non-zero sky pixels; ``uv_m``: [n_row, 2];
     ``int_row_ptr``: [n_int+1]; ``freq_hz``: [n_chan].  ``snap_scale`` > 0
-    rounds uv (in wavelengths) to the lattice 1/snap_scale.
+    rounds uv (in wavelengths) to the lattice 1/snap_scale.  ``w_m``: [n_row]
+    baseline w in metres for the w-term (None: w = 0).
     """
 
     def __init__(self, src_l, src_m, src_flux, n_ant, ant1, ant2, uv_m, int_row_ptr, freq_hz,
                  n_pol=1, dish_diam_m=25.0, illum=0, gauss_sigma_ld=1.0, squint_frac=0.0,
-                 snap_scale=0.0, par_angle=None):
+                 snap_scale=0.0, par_angle=None, w_m=None):
         self.src_l = np.ascontiguousarray(src_l, np.float64)
         self.src_m = np.ascontiguousarray(src_m, np.float64)
         self.src_flux = np.ascontiguousarray(src_flux, np.float64)
@@ -125,22 +127,27 @@ class Problem:
         self.par_angle = None if par_angle is None else np.ascontiguousarray(par_angle, np.float64)
         if self.par_angle is not None and self.par_angle.shape != (self.n_row,):
             raise ValueError("par_angle must have one value per row")
+        self.w_m = None if w_m is None else np.ascontiguousarray(w_m, np.float64)
+        if self.w_m is not None and self.w_m.shape != (self.n_row,):
+            raise ValueError("w_m must have one value per row")
         self._s = _Problem(
             int(self.src_flux.shape[0]), _dp(self.src_l), _dp(self.src_m), _dp(self.src_flux),
             self.n_ant, self.n_chan, self.n_pol, self.n_int, self.n_row,
             self.int_row_ptr.ctypes.data_as(C.POINTER(C.c_int64)), _ip(self.ant1), _ip(self.ant2),
             _dp(self.uv_m), _dp(self.freq_hz), float(dish_diam_m), int(illum), float(gauss_sigma_ld),
             float(squint_frac), float(snap_scale),
-            None if self.par_angle is None else _dp(self.par_angle))
+            None if self.par_angle is None else _dp(self.par_angle),
+            None if self.w_m is None else _dp(self.w_m))
 
     @classmethod
-    def from_observation(cls, obs, snap=True, mount_frame=False, **kw):
+    def from_observation(cls, obs, snap=True, mount_frame=False, w_term=False, **kw):
         """mount_frame: offsets in the antenna mount frame, carried onto the
-        sky by each row's parallactic angle."""
+        sky by each row's parallactic angle; w_term: with each row's w."""
         l, m, f = obs.sky_lm()
         args = dict(n_pol=obs.n_pol, dish_diam_m=obs.wl.dish_diam_m, squint_frac=obs.wl.squint_frac,
                     snap_scale=obs.snap_scale if snap else 0.0,
-                    par_angle=obs.par_angle if mount_frame else None)
+                    par_angle=obs.par_angle if mount_frame else None,
+                    w_m=obs.w_m if w_term else None)
         args.update(kw)
         return cls(l, m, f, obs.n_ant, obs.ant1, obs.ant2, obs.uv_m, obs.int_row_ptr, obs.freq_hz,
                    **args)

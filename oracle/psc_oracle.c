@@ -140,6 +140,23 @@ static void row_uv(const orc_problem* p, int64_t r, int c, double* u, double* v)
     *v = vv;
 }
 
+/* w of row r at channel c in wavelengths (not rounded: it enters only the
+ * phase), 0 without the w-term */
+static double row_w(const orc_problem* p, int64_t r, int c)
+{
+    return p->w_m ? p->w_m[r] * p->freq_hz[c] / ORC_C_LIGHT : 0.0;
+}
+
+/* Phase of the measurement equation for a source at (l, m): 2 pi (u l + v m
+ * + w (n - 1)), n = sqrt(1 - l^2 - m^2), with n - 1 = -x / (1 + sqrt(1 - x)),
+ * x = l^2 + m^2, free of the cancellation of sqrt(1 - x) - 1. */
+static double me_phase(double u, double v, double w, double l, double m)
+{
+    double x = l * l + m * m;
+    double nm1 = -x / (1.0 + sqrt(1.0 - x));
+    return 2.0 * ORC_PI * (u * l + v * m + w * nm1);
+}
+
 void oracle_snap_uv(const orc_problem* p, int64_t row, int chan, double* uv_out)
 {
     row_uv(p, row, chan, &uv_out[0], &uv_out[1]);
@@ -206,11 +223,11 @@ static void beam_row(const orc_problem* p, const double* offs_int, int pol, int 
  * out[0..1] = V, out[2..9] = dV/dl_i, dV/dm_i, dV/dl_j, dV/dm_j (re, im each).
  */
 static void vis_from_beams(const orc_problem* p, const double* ti, const double* tj, double u, double v,
-                           double* out, int want_grad)
+                           double w, double* out, int want_grad)
 {
     double acc[10] = {0};
     for (int s = 0; s < p->n_src; ++s) {
-        double ph = 2.0 * ORC_PI * (u * p->src_l[s] + v * p->src_m[s]);
+        double ph = me_phase(u, v, w, p->src_l[s], p->src_m[s]);
         double cr = cos(ph), ci = sin(ph);
         double fi = p->src_flux[s];
         double ei = ti[3 * s], ej = tj[3 * s];
@@ -231,11 +248,11 @@ static void vis_from_beams(const orc_problem* p, const double* ti, const double*
 
 /* The same from the interval's beam table (offsets in the sky frame). */
 static void vis_one(const orc_problem* p, const double* tab, int pol, int ai, int aj, int c,
-                    double u, double v, double* out, int want_grad)
+                    double u, double v, double w, double* out, int want_grad)
 {
     const double* ti = tab + 3 * ((((size_t)pol * p->n_ant + ai) * p->n_chan + c) * p->n_src);
     const double* tj = tab + 3 * ((((size_t)pol * p->n_ant + aj) * p->n_chan + c) * p->n_src);
-    vis_from_beams(p, ti, tj, u, v, out, want_grad);
+    vis_from_beams(p, ti, tj, u, v, w, out, want_grad);
 }
 
 /*
@@ -244,14 +261,14 @@ static void vis_one(const orc_problem* p, const double* tab, int pol, int ai, in
  * caller's scratch bi, bj ([n_src][3] each).
  */
 static void vis_row(const orc_problem* p, const double* tab, const double* offs_int, int64_t r, int pol,
-                    int c, double u, double v, double* bi, double* bj, double* out, int want_grad)
+                    int c, double u, double v, double w, double* bi, double* bj, double* out, int want_grad)
 {
     if (p->par_angle) {
         beam_row(p, offs_int, pol, p->ant1[r], c, p->par_angle[r], bi);
         beam_row(p, offs_int, pol, p->ant2[r], c, p->par_angle[r], bj);
-        vis_from_beams(p, bi, bj, u, v, out, want_grad);
+        vis_from_beams(p, bi, bj, u, v, w, out, want_grad);
     } else {
-        vis_one(p, tab, pol, p->ant1[r], p->ant2[r], c, u, v, out, want_grad);
+        vis_one(p, tab, pol, p->ant1[r], p->ant2[r], c, u, v, w, out, want_grad);
     }
 }
 
@@ -291,7 +308,7 @@ int oracle_predict(const orc_problem* p, const double* offsets, double* vis_out,
                     row_uv(p, r, c, &u, &v);
                     for (int pol = 0; pol < p->n_pol; ++pol) {
                         double out[10];
-                        vis_row(p, tab, offs_int, r, pol, c, u, v, bi, bj, out, dvis_out != NULL);
+                        vis_row(p, tab, offs_int, r, pol, c, u, v, row_w(p, r, c), bi, bj, out, dvis_out != NULL);
                         size_t idx = ((size_t)r * p->n_chan + c) * p->n_pol + pol;
                         vis_out[2 * idx] = out[0];
                         vis_out[2 * idx + 1] = out[1];
@@ -352,7 +369,7 @@ int oracle_gradient(const orc_problem* p, const double* offsets, const double* v
                     for (int pol = 0; pol < p->n_pol; ++pol) {
                         size_t idx = ((size_t)r * p->n_chan + c) * p->n_pol + pol;
                         double out[10];
-                        vis_row(p, tab, offs_int, r, pol, c, u, v, bi, bj, out, 1);
+                        vis_row(p, tab, offs_int, r, pol, c, u, v, row_w(p, r, c), bi, bj, out, 1);
                         if (vis_model_out) {
                             vis_model_out[2 * idx] = out[0];
                             vis_model_out[2 * idx + 1] = out[1];
@@ -454,7 +471,7 @@ int oracle_image_gradient(const orc_problem* p, const double* offsets, const dou
                 for (int c = 0; c < p->n_chan; ++c) {
                     double u, v;
                     row_uv(p, r, c, &u, &v);
-                    double ph = 2.0 * ORC_PI * (u * pix_l[k] + v * pix_m[k]);
+                    double ph = me_phase(u, v, row_w(p, r, c), pix_l[k], pix_m[k]);
                     double cr = cos(ph), ci = sin(ph);
                     for (int pol = 0; pol < p->n_pol; ++pol) {
                         size_t idx = ((size_t)r * p->n_chan + c) * p->n_pol + pol;

@@ -27,6 +27,7 @@ typedef struct {
     double squint_frac;     /* beam squint of pol 0 (+) and pol 1 (-), in HPBW */
     double snap_scale;      /* >0: uv (wavelengths) rounded to multiples of 1/snap_scale */
     const double* par_angle; /* nullable [n_row]: offsets in the mount frame, rotated by this angle */
+    const double* w_m;       /* nullable [n_row]: baseline w in metres (the w-term); null: w = 0 */
 } orc_problem;
 
 void oracle_efp(int illum, double dish_diam_m, double gauss_sigma_ld, double freq_hz,

@@ -70,6 +70,7 @@ class Workload:
     snr: float | None = None
     diffuse_fwhm_arcmin: float | None = None
     diffuse_peak_jy: float = 1e-3
+    fov_frac: float = 1.0
 
     @property
     def n_bl(self) -> int:
@@ -168,6 +169,20 @@ class Observation:
     @property
     def fov(self) -> float:
         return self.grid_n * self.cell_rad
+
+    @property
+    def w_m(self) -> np.ndarray:
+        """Baseline w (m) of every row: the component along the phase centre,
+        w = cos(dec) cos(H) X - cos(dec) sin(H) Y + sin(dec) Z for the
+        equatorial baseline (X, Y, Z) of the local east-north baseline
+        (the companion of u and v in the synthesis tracks)."""
+        wl = self.wl
+        east = self.ant_pos[self.ant2, 0] - self.ant_pos[self.ant1, 0]
+        north = self.ant_pos[self.ant2, 1] - self.ant_pos[self.ant1, 1]
+        lat, dec = np.radians(wl.lat_deg), np.radians(wl.dec_deg)
+        X, Y, Z = -north * np.sin(lat), east, north * np.cos(lat)
+        h = OMEGA_EARTH * (self.time_idx - 0.5 * (wl.n_time - 1)) * wl.dt_s
+        return np.cos(dec) * np.cos(h) * X - np.cos(dec) * np.sin(h) * Y + np.sin(dec) * Z
 
     @property
     def par_angle(self) -> np.ndarray:
@@ -276,8 +291,11 @@ def _uv_tracks(wl: Workload, ant_pos: np.ndarray):
 
 
 def fov_for(wl: Workload) -> float:
+    """Field of view: the widest whose aperture autocorrelation plus the
+    anti-aliasing taper fits the support, times fov_frac (below 1 leaves room
+    in the support for the w-term's kernel)."""
     lam_min = C_LIGHT / float(np.max(wl.freqs_hz))
-    return 0.98 * (wl.support - wl.es_width) * lam_min / (2.0 * wl.dish_diam_m)
+    return wl.fov_frac * 0.98 * (wl.support - wl.es_width) * lam_min / (2.0 * wl.dish_diam_m)
 
 
 def make_observation(wl: Workload, seed: int) -> Observation:

@@ -140,6 +140,96 @@ def test_hermitian_symmetry(oracle_lib):
     np.testing.assert_allclose(vf, np.conj(v), rtol=1e-13, atol=1e-13)
 
 
+# --------------------------------------------------------------------------
+# The w-term (the baseline's component along the phase centre)
+# --------------------------------------------------------------------------
+
+def _with_w(o, prob, w_m, **kw):
+    args = dict(n_pol=prob.n_pol, squint_frac=0.03, snap_scale=0.0, w_m=w_m)
+    args.update(kw)
+    return o.Problem(prob.src_l, prob.src_m, prob.src_flux, prob.n_ant, prob.ant1, prob.ant2, prob.uv_m,
+                     prob.int_row_ptr, prob.freq_hz, **args)
+
+
+def test_w_term_zero_w_changes_nothing(oracle_lib):
+    o = oracle_lib
+    prob, offs = _tiny_problem(o, n_pol=2, squint=0.03)
+    v, dv = o.predict(prob, offs, want_grad=True)
+    v0, dv0 = o.predict(_with_w(o, prob, np.zeros(prob.n_row)), offs, want_grad=True)
+    assert np.array_equal(v, v0) and np.array_equal(dv, dv0)
+
+
+def test_w_term_small_angle_series(oracle_lib):
+    """One source at small (l, m): V(w) / V(0) = exp(2 pi i w (n - 1)), whose
+    phase is the series -2 pi w (x/2 + x^2/8 + x^3/16 + ...) in x = l^2 + m^2
+    (n = sqrt(1 - x)); the fourth-order remainder is below 1e-9 rad here."""
+    o = oracle_lib
+    rng = np.random.default_rng(5)
+    n = 12
+    uv = rng.uniform(-3000.0, 3000.0, size=(n, 2))
+    w_m = rng.uniform(-900.0, 900.0, n)
+    l, m = 0.021, -0.013
+    base = o.Problem([l], [m], [1.7], 2, np.zeros(n), np.ones(n), uv, [0, n], [1.3e9, 1.8e9])
+    offs = np.zeros(base.offsets_shape())
+    ratio = o.predict(_with_w(o, base, w_m, n_pol=1, squint_frac=0.0), offs) / o.predict(base, offs)
+    x = l * l + m * m
+    for c, f in enumerate(base.freq_hz):
+        w = w_m * f / 299792458.0
+        want = -2 * np.pi * w * (x / 2 + x ** 2 / 8 + x ** 3 / 16)
+        np.testing.assert_allclose(np.abs(ratio[:, c, 0]), 1.0, rtol=1e-12)
+        assert np.abs(want).max() > 1.0  # a phase large enough to matter
+        np.testing.assert_allclose(ratio[:, c, 0], np.exp(1j * want), rtol=0, atol=1e-9)
+
+
+def test_w_term_hermitian_symmetry(oracle_lib):
+    """V_ji(-u, -v, -w) = conj V_ij(u, v, w) for a real sky."""
+    o = oracle_lib
+    prob, offs = _tiny_problem(o, n_pol=2, squint=0.03)
+    w_m = np.random.default_rng(6).uniform(-800.0, 800.0, prob.n_row)
+    v = o.predict(_with_w(o, prob, w_m), offs)
+    flip = o.Problem(prob.src_l, prob.src_m, prob.src_flux, prob.n_ant, prob.ant2, prob.ant1, -prob.uv_m,
+                     prob.int_row_ptr, prob.freq_hz, n_pol=2, squint_frac=0.03, w_m=-w_m)
+    np.testing.assert_allclose(o.predict(flip, offs), np.conj(v), rtol=1e-13, atol=1e-13)
+
+
+def test_w_term_gradient_matches_central_differences(oracle_lib):
+    """With the w-term, the analytic offset derivatives against central
+    differences (h = 0.01 arcsec) of the prediction, and the image gradient
+    against central differences of chi^2 in a pixel's flux."""
+    o = oracle_lib
+    prob, offs = _tiny_problem(o, n_pol=2, squint=0.03)
+    w_m = np.random.default_rng(7).uniform(-800.0, 800.0, prob.n_row)
+    pw = _with_w(o, prob, w_m)
+    _, dv = o.predict(pw, offs, want_grad=True)
+    h = 0.01 * ARCSEC
+    for ant in range(prob.n_ant):
+        for ax in range(2):
+            op = offs.copy(); om = offs.copy()
+            op[0, 1, ant, ax] += h
+            om[0, 1, ant, ax] -= h
+            fd = (o.predict(pw, op) - o.predict(pw, om))[:, :, 1] / (2 * h)
+            an = np.where((prob.ant1 == ant)[:, None], dv[:, :, 1, ax], 0) + \
+                np.where((prob.ant2 == ant)[:, None], dv[:, :, 1, 2 + ax], 0)
+            assert np.linalg.norm(fd - an) / np.linalg.norm(an) < 1e-6, (ant, ax)
+    vobs = o.predict(pw, offs) * 1.05 + 0.02
+    src_l, src_m = np.append(prob.src_l, 0.006), np.append(prob.src_m, -0.004)
+    flux = np.append(prob.src_flux, 0.0)
+
+    def with_flux(f):
+        return o.Problem(src_l, src_m, f, prob.n_ant, prob.ant1, prob.ant2, prob.uv_m, prob.int_row_ptr,
+                         prob.freq_hz, n_pol=2, squint_frac=0.03, w_m=w_m)
+
+    g = o.image_gradient(with_flux(flux), offs, vobs, 1.0, src_l, src_m)
+    hf = 1e-3
+    for k in range(flux.size):
+        fp, fm = flux.copy(), flux.copy()
+        fp[k] += hf
+        fm[k] -= hf
+        chi = [float((np.abs(vobs - o.predict(with_flux(f), offs)) ** 2).sum()) for f in (fp, fm)]
+        fd = (chi[0] - chi[1]) / (2 * hf)
+        assert abs(fd - g[k]) <= 1e-8 * max(abs(fd), 1e-6), (k, fd, g[k])
+
+
 def test_onaxis_source_zero_offsets_is_flux(oracle_lib):
     o = oracle_lib
     uv = np.random.default_rng(0).uniform(-4000, 4000, size=(10, 2))
