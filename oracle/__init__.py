@@ -58,6 +58,8 @@ class _Problem(C.Structure):
         ("snap_scale", C.c_double),
         ("par_angle", C.POINTER(C.c_double)),
         ("w_m", C.POINTER(C.c_double)),
+        ("aperture_n", C.c_int32),
+        ("aperture", C.POINTER(C.c_double)),
     ]
 
 
@@ -73,6 +75,8 @@ def _load():
             ip = C.POINTER(C.c_int32)
             lib.oracle_efp.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
                                        C.c_double, dp]
+            lib.oracle_efp_aperture.argtypes = [C.c_int, dp, C.c_double, C.c_double, C.c_double,
+                                                C.c_double, dp]
             lib.oracle_hpbw.argtypes = [C.c_double, C.c_double]
             lib.oracle_hpbw.restype = C.c_double
             lib.oracle_snap_uv.argtypes = [P, C.c_int64, C.c_int, dp]
@@ -104,12 +108,14 @@ class Problem:
     ``src_l, src_m, src_flux``: non-zero sky pixels; ``uv_m``: [n_row, 2];
     ``int_row_ptr``: [n_int+1]; ``freq_hz``: [n_chan].  ``snap_scale`` > 0
     rounds uv (in wavelengths) to the lattice 1/snap_scale.  ``w_m``: [n_row]
-    baseline w in metres for the w-term (None: w = 0).
+    baseline w in metres for the w-term (None: w = 0).  ``aperture``: a
+    square, real, even aperture illumination across the dish for the
+    measured-aperture mode (illum 2).
     """
 
     def __init__(self, src_l, src_m, src_flux, n_ant, ant1, ant2, uv_m, int_row_ptr, freq_hz,
                  n_pol=1, dish_diam_m=25.0, illum=0, gauss_sigma_ld=1.0, squint_frac=0.0,
-                 snap_scale=0.0, par_angle=None, w_m=None):
+                 snap_scale=0.0, par_angle=None, w_m=None, aperture=None):
         self.src_l = np.ascontiguousarray(src_l, np.float64)
         self.src_m = np.ascontiguousarray(src_m, np.float64)
         self.src_flux = np.ascontiguousarray(src_flux, np.float64)
@@ -130,6 +136,12 @@ class Problem:
         self.w_m = None if w_m is None else np.ascontiguousarray(w_m, np.float64)
         if self.w_m is not None and self.w_m.shape != (self.n_row,):
             raise ValueError("w_m must have one value per row")
+        self.aperture = None if aperture is None else np.ascontiguousarray(aperture, np.float64)
+        if (self.aperture is not None) != (int(illum) == 2):
+            raise ValueError("the measured-aperture mode (illum 2) takes an aperture, and only it")
+        if self.aperture is not None and (self.aperture.ndim != 2 or
+                                          self.aperture.shape[0] != self.aperture.shape[1]):
+            raise ValueError("aperture must be square")
         self._s = _Problem(
             int(self.src_flux.shape[0]), _dp(self.src_l), _dp(self.src_m), _dp(self.src_flux),
             self.n_ant, self.n_chan, self.n_pol, self.n_int, self.n_row,
@@ -137,7 +149,9 @@ class Problem:
             _dp(self.uv_m), _dp(self.freq_hz), float(dish_diam_m), int(illum), float(gauss_sigma_ld),
             float(squint_frac), float(snap_scale),
             None if self.par_angle is None else _dp(self.par_angle),
-            None if self.w_m is None else _dp(self.w_m))
+            None if self.w_m is None else _dp(self.w_m),
+            0 if self.aperture is None else int(self.aperture.shape[0]),
+            None if self.aperture is None else _dp(self.aperture))
 
     @classmethod
     def from_observation(cls, obs, snap=True, mount_frame=False, w_term=False, **kw):
@@ -174,6 +188,17 @@ def efp(illum, dish_diam_m, gauss_sigma_ld, freq_hz, dl, dm):
     out = np.zeros(3)
     lib.oracle_efp(int(illum), float(dish_diam_m), float(gauss_sigma_ld), float(freq_hz),
                    float(dl), float(dm), _dp(out))
+    return out
+
+
+def efp_aperture(aperture, dish_diam_m, freq_hz, dl, dm):
+    """(E, dE/dc_l, dE/dc_m) of a measured aperture's pattern at displacement
+    (dl, dm) from the beam centre c, in the mount frame."""
+    lib = _load()
+    ap = np.ascontiguousarray(aperture, np.float64)
+    out = np.zeros(3)
+    lib.oracle_efp_aperture(int(ap.shape[0]), _dp(ap), float(dish_diam_m), float(freq_hz), float(dl),
+                            float(dm), _dp(out))
     return out
 
 

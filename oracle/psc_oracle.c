@@ -18,7 +18,8 @@
  *        V_ij(u) = sum_p I_p E_i(l_p) E_j(l_p) exp(+2 pi i u.l_p)
  *    E is the voltage pattern of a uniformly illuminated circular dish,
  *    2 J1(x)/x with x = pi D |l| / lambda, or, in the Gaussian test mode, the
- *    main-lobe model of Sec. 3, exp(-|l|^2 alpha^2) with alpha^2 = 1/(2 s^2).
+ *    main-lobe model of Sec. 3, exp(-|l|^2 alpha^2) with alpha^2 = 1/(2 s^2),
+ *    or the transform of a measured aperture illumination (below).
  *  - gradient: the analytic derivative of V with respect to the two offsets
  *    of each end of the baseline (Eq. DA with a = (l_i, m_i)), and the
  *    per-antenna sums of Eq. DCHIDD together with chi^2 (Eq. Chisq) and the
@@ -49,6 +50,12 @@
  *    angle chi: p_sky = R(chi) (offset + squint), R = [[cos, -sin],
  *    [sin, cos]]; derivatives are taken with respect to the mount-frame
  *    offsets.  The paper solves in this frame for its VLA data (Sec. 4).
+ *  - A measured aperture (illum 2) is a real, even illumination on a square
+ *    grid of cells across the dish; its far-field pattern is the aperture's
+ *    Fourier transform (Sec. 1 and Sec. 3: the pattern of a dish follows
+ *    from its illumination, with blockage and taper), fixed to the mount:
+ *    towards sky position l a row sees E(R(chi)^T l - q), q the mount-frame
+ *    offset plus squint (chi = 0 without parallactic angles).
  */
 #include <math.h>
 #include <stdint.h>
@@ -104,6 +111,58 @@ static void efp_gauss(double s, double dl, double dm, double* e, double* de_dpl,
     *e = e0;
     *de_dpl = 2.0 * a2 * dl * e0;
     *de_dpm = 2.0 * a2 * dm * e0;
+}
+
+/*
+ * Far-field pattern of a measured aperture: the Fourier transform of the
+ * illumination A, summed directly over its cells and normalised to one on
+ * the beam axis,
+ *   E(d) = sum_k A_k cos(2 pi x_k . d / lambda) / sum_k A_k,
+ * x_k the cell centres in metres, x_a = (a - (n - 1)/2) D / n per axis, and d
+ * the displacement from the beam centre in the mount frame.  A is even, so
+ * the sine part of the transform cancels and E is real.  The derivatives
+ * with respect to the beam centre c (d = l - c) are
+ *   dE/dc = sum_k A_k (2 pi x_k / lambda) sin(2 pi x_k . d / lambda) / sum_k A_k.
+ */
+static void efp_aperture(int n, const double* ap, double dish, double lambda, double dl, double dm,
+                         double* e, double* de_dcl, double* de_dcm)
+{
+    double cell = dish / n, s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int a = 0; a < n; ++a) {
+        double x = (a - 0.5 * (n - 1)) * cell;
+        for (int b = 0; b < n; ++b) {
+            double amp = ap[(size_t)a * n + b];
+            if (amp == 0.0) continue;
+            double y = (b - 0.5 * (n - 1)) * cell;
+            double ph = 2.0 * ORC_PI * (x * dl + y * dm) / lambda;
+            double sn = sin(ph);
+            s0 += amp;
+            s1 += amp * cos(ph);
+            s2 += amp * (2.0 * ORC_PI * x / lambda) * sn;
+            s3 += amp * (2.0 * ORC_PI * y / lambda) * sn;
+        }
+    }
+    *e = s1 / s0;
+    *de_dcl = s2 / s0;
+    *de_dcm = s3 / s0;
+}
+
+void oracle_efp_aperture(int aperture_n, const double* aperture, double dish_diam_m, double freq_hz,
+                         double dl, double dm, double* out3)
+{
+    efp_aperture(aperture_n, aperture, dish_diam_m, ORC_C_LIGHT / freq_hz, dl, dm, &out3[0], &out3[1],
+                 &out3[2]);
+}
+
+/* The pattern of the problem's antennas at displacement (dl, dm) from the
+ * beam centre at channel c: (E, dE/dc_l, dE/dc_m). */
+static void efp_problem(const orc_problem* p, int c, double dl, double dm, double* out3)
+{
+    if (p->illum == 2)
+        efp_aperture(p->aperture_n, p->aperture, p->dish_diam_m, ORC_C_LIGHT / p->freq_hz[c], dl, dm,
+                     &out3[0], &out3[1], &out3[2]);
+    else
+        oracle_efp(p->illum, p->dish_diam_m, p->gauss_sigma_ld, p->freq_hz[c], dl, dm, out3);
 }
 
 static double hpbw_rad(double lambda, double dish)
@@ -182,8 +241,7 @@ static double* beam_table(const orc_problem* p, const double* offs_int /* [n_pol
                 double pm = offs_int[(pol * p->n_ant + a) * 2 + 1];
                 for (int s = 0; s < p->n_src; ++s) {
                     double* t = tab + 3 * ((((size_t)pol * p->n_ant + a) * p->n_chan + c) * p->n_src + s);
-                    oracle_efp(p->illum, p->dish_diam_m, p->gauss_sigma_ld, p->freq_hz[c],
-                               p->src_l[s] - pl, p->src_m[s] - pm, t);
+                    efp_problem(p, c, p->src_l[s] - pl, p->src_m[s] - pm, t);
                 }
             }
         }
@@ -206,6 +264,17 @@ static void beam_row(const orc_problem* p, const double* offs_int, int pol, int 
     double ql = offs_int[(pol * p->n_ant + a) * 2 + 0] + sq;
     double qm = offs_int[(pol * p->n_ant + a) * 2 + 1];
     double cs = cos(chi), sn = sin(chi);
+    if (p->illum == 2) {
+        /* the pattern is fixed to the mount: evaluate it at the source's
+         * mount-frame position R^T l minus q, where its derivatives are
+         * already those with respect to q */
+        for (int s = 0; s < p->n_src; ++s) {
+            double dl = cs * p->src_l[s] + sn * p->src_m[s] - ql;
+            double dm = -sn * p->src_l[s] + cs * p->src_m[s] - qm;
+            efp_problem(p, c, dl, dm, t + 3 * s);
+        }
+        return;
+    }
     double pl = cs * ql - sn * qm, pm = sn * ql + cs * qm;
     for (int s = 0; s < p->n_src; ++s) {
         double e[3];
@@ -284,6 +353,20 @@ static int check_problem(const orc_problem* p)
         if (p->ant1[r] < 0 || p->ant2[r] < 0 || p->ant1[r] >= p->n_ant || p->ant2[r] >= p->n_ant ||
             p->ant1[r] == p->ant2[r])
             return -1;
+    }
+    if (p->illum < 0 || p->illum > 2) return -1;
+    if (p->illum == 2) {
+        /* a real, even aperture with a non-zero on-axis response */
+        int n = p->aperture_n;
+        double s0 = 0.0;
+        if (n < 1 || !p->aperture) return -1;
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b) {
+                double v = p->aperture[(size_t)a * n + b];
+                if (!isfinite(v) || v != p->aperture[(size_t)(n - 1 - a) * n + (n - 1 - b)]) return -1;
+                s0 += v;
+            }
+        if (!(s0 > 0.0)) return -1;
     }
     return 0;
 }
@@ -424,8 +507,11 @@ static double beam_at_row(const orc_problem* p, const double* offs_int, int pol,
     double qm = offs_int[(pol * p->n_ant + a) * 2 + 1];
     double cs = cos(chi), sn = sin(chi);
     double e[3];
-    oracle_efp(p->illum, p->dish_diam_m, p->gauss_sigma_ld, p->freq_hz[c], l - (cs * ql - sn * qm),
-               m - (sn * ql + cs * qm), e);
+    if (p->illum == 2)
+        efp_problem(p, c, cs * l + sn * m - ql, -sn * l + cs * m - qm, e);
+    else
+        oracle_efp(p->illum, p->dish_diam_m, p->gauss_sigma_ld, p->freq_hz[c], l - (cs * ql - sn * qm),
+                   m - (sn * ql + cs * qm), e);
     return e[0];
 }
 

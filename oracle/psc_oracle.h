@@ -22,16 +22,24 @@ typedef struct {
     const double* freq_hz;      /* [n_chan] */
     /* antenna model */
     double dish_diam_m;
-    int32_t illum;          /* 0 = uniform circular (Airy), 1 = Gaussian main lobe */
+    int32_t illum;          /* 0 = uniform circular (Airy), 1 = Gaussian main lobe,
+                               2 = measured aperture (below) */
     double gauss_sigma_ld;  /* Gaussian mode: sigma of E in units of lambda/D */
     double squint_frac;     /* beam squint of pol 0 (+) and pol 1 (-), in HPBW */
     double snap_scale;      /* >0: uv (wavelengths) rounded to multiples of 1/snap_scale */
     const double* par_angle; /* nullable [n_row]: offsets in the mount frame, rotated by this angle */
     const double* w_m;       /* nullable [n_row]: baseline w in metres (the w-term); null: w = 0 */
+    /* illum 2: aperture illumination on aperture_n x aperture_n cells over the
+     * square of side D centred on the dish axis, [x][y] row-major (x along
+     * the mount frame's l axis), real and even: A[a][b] = A[n-1-a][n-1-b] */
+    int32_t aperture_n;
+    const double* aperture;
 } orc_problem;
 
 void oracle_efp(int illum, double dish_diam_m, double gauss_sigma_ld, double freq_hz,
                 double dl, double dm, double* out3);
+void oracle_efp_aperture(int aperture_n, const double* aperture, double dish_diam_m, double freq_hz,
+                         double dl, double dm, double* out3);
 double oracle_hpbw(double freq_hz, double dish_diam_m);
 void oracle_snap_uv(const orc_problem* p, int64_t row, int chan, double* uv_out);
 int oracle_predict(const orc_problem* p, const double* offsets, double* vis_out, double* dvis_out);

@@ -20,7 +20,8 @@ Conventions
   [ix, iy].
 * Baseline vector of row (i, j) is position_j - position_i, projected with the
   standard equatorial transform for hour angle H and declination dec at the
-  array latitude; w is dropped (co-planar data).
+  array latitude; w is returned separately (``Observation.w_m``) and used
+  only when the w-term is asked for.
 * The field of view FoV = N * cell is chosen from the kernel support:
   FoV = 0.98 (S - W_c) lambda_min / (2 D), so that the support of one
   baseline's uv kernel plus the anti-aliasing taper fits in S cells.
@@ -364,6 +365,39 @@ def noise(vis: np.ndarray, snr: float, seed: int):
     sigma = float(np.sqrt(np.mean(np.abs(vis) ** 2))) / snr
     nz = (rng.normal(size=vis.shape) + 1j * rng.normal(size=vis.shape)) * (sigma / math.sqrt(2.0))
     return nz, 1.0 / sigma ** 2
+
+
+def measured_aperture(n: int = 32, seed: int = 0, blockage_frac: float = 0.08, n_legs: int = 4,
+                      leg_width_frac: float = 0.03, leg_angle_deg: float = 45.0, edge_taper: float = 0.3,
+                      ripple: float = 0.05) -> np.ndarray:
+    """A stand-in for a measured aperture illumination (the paper's VLA beam
+    model comes from a simulation of the illumination with blockage and
+    taper, which is not available): n x n cells over the square of side D
+    centred on the dish axis, [x][y], x along the mount frame's l axis.
+
+    Inside the rim: a parabolic taper falling to ``edge_taper`` at the rim,
+    zero inside the central blockage (diameter ``blockage_frac`` D) and
+    under ``n_legs`` feed-leg shadows (radial strips of width
+    ``leg_width_frac`` D, the first at ``leg_angle_deg`` from +x), and a
+    seeded ripple of relative amplitude ``ripple`` standing in for
+    measurement noise.  The result is made even, A[a][b] =
+    A[n-1-a][n-1-b], so that the far-field pattern is real; the legs make it
+    non-circular.
+    """
+    rng = np.random.default_rng(seed)
+    x = (np.arange(n) - 0.5 * (n - 1)) / n  # cell centres in units of D
+    X, Y = np.meshgrid(x, x, indexing="ij")
+    r = np.hypot(X, Y)
+    amp = 1.0 - (1.0 - edge_taper) * (2.0 * r) ** 2
+    amp *= 1.0 + ripple * rng.standard_normal((n, n))
+    amp[r > 0.5] = 0.0
+    amp[r < 0.5 * blockage_frac] = 0.0
+    for k in range(n_legs):
+        ang = np.radians(leg_angle_deg) + 2.0 * np.pi * k / n_legs
+        along = X * np.cos(ang) + Y * np.sin(ang)
+        across = -X * np.sin(ang) + Y * np.cos(ang)
+        amp[(along > 0.0) & (np.abs(across) < 0.5 * leg_width_frac)] = 0.0
+    return 0.5 * (amp + amp[::-1, ::-1])
 
 
 def perturbed_offsets(obs: Observation, sigma_arcsec: float, seed: int) -> np.ndarray:
