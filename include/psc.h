@@ -62,12 +62,20 @@ typedef struct psc_obs psc_obs;
  *                visibility's uv is rounded to the nearest 1/O cell.
  *  image_samples M, image-plane samples per axis used to build kernels, at
  *                spacing FoV/S (0 = default 3S/2; even, S..2S).
- *  dish_diam_m   D of the uniformly illuminated circular dishes.
+ *  dish_diam_m   D of the dishes (uniformly illuminated circular ones for
+ *                illum 0).
  *  illum         0: far-field voltage pattern 2 J1(x)/x, x = pi D |l| / lambda;
  *                1: the Gaussian main-lobe model of Sec. 3,
  *                   exp(-|l|^2 / (2 s^2)), s = gauss_sigma_ld * lambda / D.
  *                   Its aperture is not compactly supported: the kernel fits
  *                   the S-cell window only for gauss_sigma_ld >~ 1.5.
+ *                2: a measured aperture (below): the far-field pattern is
+ *                   the Fourier transform of the aperture illumination (Sec. 1
+ *                   and Sec. 3: blockage, feed-support shadows and taper enter
+ *                   through it), fixed to the antenna mount.  Every
+ *                   observation is then handled in the mount frame (rows
+ *                   without a par_angle are at angle zero) and degrids in the
+ *                   window form; psc_set_degrid refuses the table forms.
  *  squint_frac   beam squint: polarisation 0 (1) is centred at
  *                +(-) squint_frac * HPBW(nu) along +l, HPBW = 1.02899 lambda/D
  *                (Sec. 4.2: the two parallel hands are solved separately).
@@ -75,6 +83,19 @@ typedef struct psc_obs psc_obs;
  *                in uv cells (0 = default 8); taper_beta its shape
  *                (0 = default 2.30 * W).
  *  device        HIP device ordinal.
+ *  aperture_n,   illum 2 only: the aperture illumination, a HOST array of
+ *  aperture      aperture_n x aperture_n float64 (1..256 per side) over the
+ *                square of side D centred on the dish axis, [x][y] row-major
+ *                with x along the mount frame's l axis; cell (i, j) is
+ *                centred at ((i - (n-1)/2) D/n, (j - (n-1)/2) D/n).  It must
+ *                be real, finite and even (A[i][j] = A[n-1-i][n-1-j], so the
+ *                pattern is real) with a positive sum; otherwise PSC_E_ARG.
+ *                Read by psc_create only (not retained).  The pattern is
+ *                normalised to one on axis, tabulated per observation on
+ *                32 nodes per lambda/D over the image samples plus a quarter
+ *                of the field of view, and interpolated bicubically (values
+ *                and slopes); displacements beyond the table take its edge
+ *                value.
  */
 typedef struct {
     int32_t grid_n;
@@ -89,6 +110,8 @@ typedef struct {
     int32_t taper_width;
     double taper_beta;
     int32_t device;
+    int32_t aperture_n;
+    const double* aperture;
 } psc_config;
 
 /*
@@ -99,7 +122,7 @@ typedef struct {
  *              [int_row_ptr[s], int_row_ptr[s+1]); intervals may be uneven
  *              or empty (Algorithm 1 solves each interval separately).
  *  ant1, ant2  [n_row] int32 antenna indices, 0 <= ant1 < ant2 < n_ant.
- *  uv_m        [n_row][2] float64 baseline (u, v) in metres, w ignored.
+ *  uv_m        [n_row][2] float64 baseline (u, v) in metres.
  *  freq_hz     [n_chan] float64 channel frequencies.
  *  n_pol       1 or 2 parallel-hand polarisations.
  *  par_angle   nullable [n_row] float64 parallactic angle chi of each row
@@ -110,8 +133,15 @@ typedef struct {
  *              update is with respect to the mount-frame offsets.  The
  *              kernels then differ from sample to sample: the observation
  *              degrids in the window form with per-sample image-plane
- *              products (psc_set_degrid refuses the table forms and
- *              psc_image_gradient returns PSC_E_UNSUPPORTED).
+ *              products (psc_set_degrid refuses the table forms).
+ *  w_m         nullable [n_row] float64 baseline w in metres (the component
+ *              along the phase centre).  When given, the measurement
+ *              equation carries the w-term, phase 2 pi w (n - 1) with
+ *              n = sqrt(1 - l^2 - m^2) beside u l + v m (w-projection: each
+ *              sample's kernel is the transform of the aperture products
+ *              times that phase, so it must still fit the support); the
+ *              observation degrids in the window form, and psc_set_degrid
+ *              refuses the table forms.  Null: w = 0.
  *
  * Visibility-shaped arrays used by the calls below are laid out
  * [n_row][n_chan][n_pol]; offsets are [n_int][n_pol][n_ant][2] float64 (l, m).
@@ -128,6 +158,7 @@ typedef struct {
     const double* uv_m;
     const double* freq_hz;
     const double* par_angle;
+    const double* w_m;
 } psc_obs_desc;
 
 /* Library version string. */

@@ -26,6 +26,9 @@ struct psc_ctx {
     double2* rgrid = nullptr;      // residual grid, (N+S) x (N+S)
     double2* fa = nullptr;         // [N][N] transform work
     double2* fb = nullptr;
+    // measured aperture (illum 2): its non-zero cells (xi, eta, weight), xi
+    // and eta in units of D, weights summing to one
+    std::vector<double> ap_cells;
     bool model_set = false;
     std::string err;
 };
@@ -43,9 +46,13 @@ struct psc_obs {
     uint32_t* ant_ent = nullptr;
     double* freq = nullptr;
     double* par_angle = nullptr;  // [n_row] or null (sky-frame offsets)
+    double* w_m = nullptr;        // [n_row] or null (no w-term)
     float4* airy = nullptr;
     int32_t n_tab = 0;
     double inv_dx = 0;
+    float4* ap_tab = nullptr;  // measured aperture: pattern table [ap_n][ap_n]
+    int32_t ap_n = 0;
+    double ap_c = 0, ap_step = 0;
     double* partials = nullptr;  // [n_items][n_pol][12]
     double* acc = nullptr;       // [n_int][n_pol][n_ant][6]
     double* max_step = nullptr;  // [n_int]
@@ -190,7 +197,30 @@ static psc_status create_impl(const psc_config* cfg, psc_ctx** out)
     if (tw < 2 || tw >= c.support) return fail(nullptr, PSC_E_ARG, "taper_width must be in [2, support)");
     if (!(c.cell_rad > 0) || !(c.dish_diam_m > 0) || !isfinite(c.cell_rad))
         return fail(nullptr, PSC_E_ARG, "cell_rad and dish_diam_m must be positive");
-    if (c.illum != 0 && c.illum != 1) return fail(nullptr, PSC_E_ARG, "illum must be 0 or 1");
+    if (c.illum < 0 || c.illum > 2) return fail(nullptr, PSC_E_ARG, "illum must be 0, 1 or 2");
+    std::vector<double> ap_cells;
+    if (c.illum == 2) {
+        const int an = c.aperture_n;
+        if (!c.aperture || an < 1 || an > 256)
+            return fail(nullptr, PSC_E_ARG, "illum 2 needs an aperture of aperture_n in [1, 256] cells per side");
+        double sum = 0.0;
+        for (int i = 0; i < an; ++i)
+            for (int j = 0; j < an; ++j) {
+                const double v = c.aperture[(size_t)i * an + j];
+                if (!isfinite(v) || v != c.aperture[(size_t)(an - 1 - i) * an + (an - 1 - j)])
+                    return fail(nullptr, PSC_E_ARG, "the aperture must be finite and even (A[i][j] = A[n-1-i][n-1-j])");
+                sum += v;
+            }
+        if (!(sum > 0.0)) return fail(nullptr, PSC_E_ARG, "the aperture's sum must be positive");
+        for (int i = 0; i < an; ++i)
+            for (int j = 0; j < an; ++j) {
+                const double v = c.aperture[(size_t)i * an + j];
+                if (v == 0.0) continue;
+                ap_cells.push_back((i - 0.5 * (an - 1)) / an);
+                ap_cells.push_back((j - 0.5 * (an - 1)) / an);
+                ap_cells.push_back(v / sum);
+            }
+    }
     if (c.illum == 1 && !(c.gauss_sigma_ld > 0))
         return fail(nullptr, PSC_E_ARG, "gauss_sigma_ld must be positive in Gaussian mode");
     if (!isfinite(c.squint_frac)) return fail(nullptr, PSC_E_ARG, "squint_frac must be finite");
@@ -200,6 +230,8 @@ static psc_status create_impl(const psc_config* cfg, psc_ctx** out)
 
     psc_ctx* ctx = new psc_ctx();
     ctx->cfg = c;
+    ctx->cfg.aperture = nullptr;  // read here only; the cells are kept instead
+    ctx->ap_cells = std::move(ap_cells);
     ctx->cfg.image_samples = m;
     ctx->cfg.taper_width = tw;
     ctx->cfg.taper_beta = tb;
@@ -301,7 +333,9 @@ PSC_API psc_status psc_obs_destroy(psc_obs* obs)
     dfree(obs->ant_ent);
     dfree(obs->freq);
     dfree(obs->par_angle);
+    dfree(obs->w_m);
     dfree(obs->airy);
+    dfree(obs->ap_tab);
     dfree(obs->partials);
     dfree(obs->acc);
     dfree(obs->max_step);
@@ -360,10 +394,17 @@ static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
         for (int64_t r = 0; r < n_row; ++r)
             if (!isfinite(pa[r])) return fail(ctx, PSC_E_ARG, "par_angle must be finite");
     }
+    std::vector<double> wv;
+    if (d->w_m && n_row > 0) {
+        wv.resize(n_row);
+        PSC_HIP(ctx, hipMemcpy(wv.data(), d->w_m, sizeof(double) * n_row, hipMemcpyDeviceToHost));
+        for (int64_t r = 0; r < n_row; ++r)
+            if (!isfinite(wv[r])) return fail(ctx, PSC_E_ARG, "w_m must be finite");
+    }
     // the kernel support must hold both apertures plus the taper
     const double lam_min = kCLight / fmax;
     const double need = 2.0 * ctx->cfg.dish_diam_m * ctx->fov / lam_min + ctx->cfg.taper_width;
-    if (ctx->cfg.illum == 0 && need > ctx->s)
+    if (ctx->cfg.illum != 1 && need > ctx->s)
         return fail(ctx, PSC_E_ARG, "support too small for the dish at the highest frequency "
                                     "(need 2 D FoV / lambda + taper_width <= support)");
 
@@ -496,10 +537,18 @@ static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
     // cubic Hermite with exact slopes: error below 5e-9 at this spacing
     const double dx = 1.0 / 16.0;
     const int n_tab = (int)ceil(x_max / dx) + 3;
+    // measured aperture: its pattern over the same range, in lambda/D units,
+    // at 32 nodes per lambda/D; the kernels evaluate it per sample in the
+    // mount frame, so every row needs an angle (zero without one)
+    const bool ap = ctx->cfg.illum == 2;
+    const double ap_step = 1.0 / 32.0;
+    const int ap_half = ap ? (int)ceil(rho_max * ctx->cfg.dish_diam_m / lam_min / ap_step) + 2 : 0;
+    const int ap_n = 2 * ap_half + 1;
+    if (ap && pa.empty()) pa.assign(n_row > 0 ? n_row : 1, 0.0);
 
     psc_obs* obs = new psc_obs();
     obs->ctx = ctx;
-    obs->degrid = (S == 16 && pa.empty()) ? PSC_DEGRID_VALU : PSC_DEGRID_WINDOW;
+    obs->degrid = (S == 16 && pa.empty() && wv.empty()) ? PSC_DEGRID_VALU : PSC_DEGRID_WINDOW;
     obs->n_ant = n_ant;
     obs->n_chan = n_chan;
     obs->n_pol = d->n_pol;
@@ -518,6 +567,7 @@ static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
     if (e == hipSuccess) e = dmalloc(&obs->ant_ent, ant_ent.size());
     if (e == hipSuccess) e = dmalloc(&obs->freq, n_chan);
     if (e == hipSuccess && !pa.empty()) e = dmalloc(&obs->par_angle, pa.size());
+    if (e == hipSuccess && !wv.empty()) e = dmalloc(&obs->w_m, wv.size());
     if (e == hipSuccess) e = dmalloc(&obs->airy, n_tab);
     if (e == hipSuccess) e = dmalloc(&obs->partials, items.size() * d->n_pol * 12);
     if (e == hipSuccess) e = dmalloc(&obs->acc, (size_t)n_int * d->n_pol * n_ant * 6);
@@ -537,9 +587,24 @@ static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
     if (e == hipSuccess) e = hipMemcpy(obs->freq, fr.data(), sizeof(double) * n_chan, hipMemcpyHostToDevice);
     if (e == hipSuccess && !pa.empty())
         e = hipMemcpy(obs->par_angle, pa.data(), sizeof(double) * pa.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !wv.empty())
+        e = hipMemcpy(obs->w_m, wv.data(), sizeof(double) * wv.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = launch_airy_table(obs->airy, n_tab, dx, nullptr);
+    double* cells = nullptr;
+    if (ap) {
+        obs->ap_n = ap_n;
+        obs->ap_c = ap_half;
+        obs->ap_step = ap_step;
+        const int n_cells = (int)(ctx->ap_cells.size() / 3);
+        if (e == hipSuccess) e = dmalloc(&obs->ap_tab, (size_t)ap_n * ap_n);
+        if (e == hipSuccess) e = dmalloc(&cells, ctx->ap_cells.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(cells, ctx->ap_cells.data(), sizeof(double) * ctx->ap_cells.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = launch_aperture_table(cells, n_cells, obs->ap_tab, ap_n, ap_half, ap_step, nullptr);
+    }
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&obs->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipDeviceSynchronize();
+    dfree(cells);
     if (e != hipSuccess) {
         psc_status st = e == hipErrorOutOfMemory ? PSC_E_OOM : PSC_E_HIP;
         std::string msg = std::string("psc_obs_create: ") + hipGetErrorString(e);
@@ -576,6 +641,7 @@ ItemArgs item_args(psc_ctx* ctx, psc_obs* obs, const double* offsets, int item_b
     a.n_pol = obs->n_pol;
     a.n_chan = obs->n_chan;
     a.par_angle = obs->par_angle;
+    a.w_m = obs->w_m;
     a.offsets = offsets;
     a.freq = obs->freq;
     a.grid = ctx->grid;
@@ -592,6 +658,10 @@ ItemArgs item_args(psc_ctx* ctx, psc_obs* obs, const double* offsets, int item_b
     a.airy = obs->airy;
     a.n_tab = obs->n_tab;
     a.inv_dx = (float)obs->inv_dx;
+    a.ap_tab = obs->ap_tab;
+    a.ap_n = obs->ap_n;
+    a.ap_c = (float)obs->ap_c;
+    a.ap_inv_step = obs->ap_step > 0 ? (float)(1.0 / obs->ap_step) : 0.f;
     a.partials = obs->partials;
     a.done = done;
     a.use_mfma = obs->degrid == PSC_DEGRID_MFMA ? 1 : 0;
@@ -785,11 +855,11 @@ PSC_API psc_status psc_image_gradient(psc_ctx* ctx, psc_obs* obs, const double* 
     a.use_mfma = 0;
     PSC_HIP(ctx, launch_zero(ctx->rgrid, np, s));
     const bool table_patch =
-        ctx->s == 16 && !obs->par_angle && grid_lds_bytes(ctx->s, ctx->m, ctx->o) <= kGridLdsMax;
-    if (table_patch || ctx->s == 32 || obs->par_angle) {
+        ctx->s == 16 && !obs->par_angle && !obs->w_m && grid_lds_bytes(ctx->s, ctx->m, ctx->o) <= kGridLdsMax;
+    if (table_patch || ctx->s == 32 || obs->par_angle || obs->w_m) {
         // predict, then a patch scatter: per item with its sub-tables and its
         // samples in time order (support 16, sky frame), or with a kernel per
-        // sample (support 32, mount frame)
+        // sample (support 32, mount frame, w-term)
         if (table_patch && !obs->ig_ord && obs->n_vis > 0) {
             psc_status bs = build_time_order(ctx, obs);
             if (bs != PSC_OK) return bs;
@@ -859,6 +929,8 @@ PSC_API psc_status psc_set_degrid(psc_obs* obs, int32_t variant)
     if (obs->par_angle && variant != PSC_DEGRID_WINDOW)
         return fail(obs->ctx, PSC_E_UNSUPPORTED,
                     "mount-frame offsets (parallactic angles) degrid in the window form only");
+    if (obs->w_m && variant != PSC_DEGRID_WINDOW)
+        return fail(obs->ctx, PSC_E_UNSUPPORTED, "the w-term degrids in the window form only");
     if (obs->graph) {  // a captured solve graph holds the old kernels
         (void)hipGraphExecDestroy(obs->graph);
         obs->graph = nullptr;
@@ -889,7 +961,7 @@ PSC_API psc_status psc_tune(psc_ctx* ctx, psc_obs* obs, const double* offsets_de
     int32_t best_v = obs->degrid;
     const int32_t keep = obs->degrid;
     for (int32_t v = PSC_DEGRID_VALU; v <= PSC_DEGRID_WINDOW && e == hipSuccess; ++v) {
-        if ((ctx->s != 16 || obs->par_angle) && v != PSC_DEGRID_WINDOW) {
+        if ((ctx->s != 16 || obs->par_angle || obs->w_m) && v != PSC_DEGRID_WINDOW) {
             if (times_us_out) times_us_out[v] = -1.0;  // not available at this support
             continue;
         }

@@ -235,6 +235,85 @@ __device__ __forceinline__ void image_products(const ItemArgs& a, const Item& it
     }
 }
 
+// A measured aperture's pattern and gradient at table coordinates (x, y)
+// (nodes, along the mount frame's l and m), by bicubic Hermite interpolation
+// of the node values and derivatives: E, and dE/dx, dE/dy per node step.
+// Coordinates beyond the table, or not finite, are clamped to its edge.
+template <bool DERIV>
+__device__ __forceinline__ void ap_eval(const ItemArgs& a, float x, float y, float& e, float& ex, float& ey)
+{
+    const float top = (float)(a.ap_n - 1);
+    x = fminf(fmaxf(x, 0.f), top);  // fmaxf(NaN, 0) = 0
+    y = fminf(fmaxf(y, 0.f), top);
+    const int i = min((int)x, a.ap_n - 2), j = min((int)y, a.ap_n - 2);
+    const float t = x - (float)i, u = y - (float)j;
+    const float4* p = a.ap_tab + (size_t)i * a.ap_n + j;
+    const float4 f00 = p[0], f01 = p[1], f10 = p[a.ap_n], f11 = p[a.ap_n + 1];
+    // cubic Hermite basis: value at 0 / 1 (h0, h1), slope at 0 / 1 (g0, g1)
+    const float t2 = t * t, t3 = t2 * t, u2 = u * u, u3 = u2 * u;
+    const float th0 = 2.f * t3 - 3.f * t2 + 1.f, th1 = 3.f * t2 - 2.f * t3;
+    const float tg0 = t3 - 2.f * t2 + t, tg1 = t3 - t2;
+    const float uh0 = 2.f * u3 - 3.f * u2 + 1.f, uh1 = 3.f * u2 - 2.f * u3;
+    const float ug0 = u3 - 2.f * u2 + u, ug1 = u3 - u2;
+    // along x at columns j and j + 1: the value (G) and the y slope (Q)
+    const float G0 = th0 * f00.x + tg0 * f00.y + th1 * f10.x + tg1 * f10.y;
+    const float G1 = th0 * f01.x + tg0 * f01.y + th1 * f11.x + tg1 * f11.y;
+    const float Q0 = th0 * f00.z + tg0 * f00.w + th1 * f10.z + tg1 * f10.w;
+    const float Q1 = th0 * f01.z + tg0 * f01.w + th1 * f11.z + tg1 * f11.w;
+    e = uh0 * G0 + ug0 * Q0 + uh1 * G1 + ug1 * Q1;
+    if constexpr (DERIV) {
+        const float dth0 = 6.f * (t2 - t), dtg0 = 3.f * t2 - 4.f * t + 1.f, dtg1 = 3.f * t2 - 2.f * t;
+        const float duh0 = 6.f * (u2 - u), dug0 = 3.f * u2 - 4.f * u + 1.f, dug1 = 3.f * u2 - 2.f * u;
+        const float Gx0 = dth0 * (f00.x - f10.x) + dtg0 * f00.y + dtg1 * f10.y;
+        const float Gx1 = dth0 * (f01.x - f11.x) + dtg0 * f01.y + dtg1 * f11.y;
+        const float Qx0 = dth0 * (f00.z - f10.z) + dtg0 * f00.w + dtg1 * f10.w;
+        const float Qx1 = dth0 * (f01.z - f11.z) + dtg0 * f01.w + dtg1 * f11.w;
+        ex = uh0 * Gx0 + ug0 * Qx0 + uh1 * Gx1 + ug1 * Qx1;
+        ey = duh0 * (G0 - G1) + dug0 * Q0 + dug1 * Q1;
+    }
+}
+
+// A measured aperture's pattern towards sky-frame displacement d = (dl, dm)
+// from a beam centre, for a row rotated by (cs, sn) = (cos, sin) of its
+// parallactic angle: E = T(R^T d D / lambda), the pattern fixed to the
+// mount; the derivatives are those with respect to the beam centre in the
+// mount frame, -grad T there.  s = D / (lambda * table step).
+template <bool DERIV>
+__device__ __forceinline__ void efp_ap(const ItemArgs& a, float s, float cs, float sn, float dl, float dm,
+                                       float& e, float& el, float& em)
+{
+    const float x = fmaf(cs * dl + sn * dm, s, a.ap_c), y = fmaf(cs * dm - sn * dl, s, a.ap_c);
+    float ex = 0.f, ey = 0.f;
+    ap_eval<DERIV>(a, x, y, e, ex, ey);
+    if constexpr (DERIV) {
+        el = -s * ex;
+        em = -s * ey;
+    }
+}
+
+// Image-plane products as mf_products, for a measured aperture, with the
+// derivative variants already with respect to the mount-frame offsets.
+template <int MODE>
+__device__ __forceinline__ void mf_products_ap(const ItemArgs& a, float s, float cs, float sn, float dli,
+                                               float dmi, float dlj, float dmj, float c,
+                                               float (&g)[mode_nv(MODE)])
+{
+    constexpr bool D = mode_nv(MODE) > 1;
+    float ei, eil = 0.f, eim = 0.f, ej, ejl = 0.f, ejm = 0.f;
+    efp_ap<D>(a, s, cs, sn, dli, dmi, ei, eil, eim);
+    efp_ap<D>(a, s, cs, sn, dlj, dmj, ej, ejl, ejm);
+    if constexpr (!D) {
+        g[0] = ei * ej * c;
+    } else {
+        constexpr int o = (MODE == kGrad) ? 1 : 0;
+        if constexpr (MODE == kGrad) g[0] = ei * ej * c;
+        g[o + 0] = eil * ej * c;
+        g[o + 1] = eim * ej * c;
+        g[o + 2] = ei * ejl * c;
+        g[o + 3] = ei * ejm * c;
+    }
+}
+
 // Image-plane products at one image sample for one visibility, from the two
 // antennas' offsets relative to the sample (dl_i, dm_i), (dl_j, dm_j) and the
 // taper value c there, in the variant order of image_products.

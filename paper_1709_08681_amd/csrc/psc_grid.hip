@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(kGridThreads) k_grid(ItemArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Per-sample kernels: support 32, and offsets in the mount frame.
+// Per-sample kernels: support 32, offsets in the mount frame, the w-term.
 //
 // Where an item's sub-tables do not fit in LDS (support 32), or every sample
 // has a kernel of its own (mount frame: each row's parallactic angle rotates
@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(kGridThreads) k_grid(ItemArgs a)
 // windows, one sample after another in a fixed order, and adds the patch to
 // the residual grid once at the end of the item; an item whose windows span
 // more than a patch adds every tap directly with float64 atomics.
-template <int S, bool MF>
+template <int S, int MF, bool WT>
 __global__ void __launch_bounds__(kGridThreads) k_gridw(ItemArgs a)
 {
     constexpr int SP = S + 1, NT = S * S, W = kGridThreads / 64;
@@ -245,9 +245,10 @@ __global__ void __launch_bounds__(kGridThreads) k_gridw(ItemArgs a)
     const int m = a.m, half_m = m >> 1;
     const int m2p = (m * m + 3) & ~3;
     const int O = a.oversample, so = S * O;
-    // dynamic LDS: image-plane products (sky frame) | tiles [W][S][SP] | patch [PB][PB] | Airy table (MF)
+    // dynamic LDS: image-plane products (sky frame) | tiles [W][S][SP] | patch [PB][PB] | Airy table
+    // (mount frame)
     float* gsh = reinterpret_cast<float*>(smem);
-    float2* tiles = reinterpret_cast<float2*>(gsh + (MF ? 0 : m2p));
+    float2* tiles = reinterpret_cast<float2*>(gsh + (MF != kFrameSky ? 0 : m2p));
     float2* patch = tiles + (size_t)W * S * SP;
     float4* airy_sh = reinterpret_cast<float4*>(patch + PB * PB);
 
@@ -260,7 +261,7 @@ __global__ void __launch_bounds__(kGridThreads) k_gridw(ItemArgs a)
     const int P = a.grid_n + S;  // pitch of the padded grid
     const float inv_s = 1.0f / (float)S;
     for (int t = tid; t < so; t += kGridThreads) twsh[t] = a.tw[t];
-    if constexpr (MF)
+    if constexpr (MF == kFrameMount)
         for (int t = tid; t < a.n_tab; t += kGridThreads) airy_sh[t] = a.airy[t];
     if (tid == 0) {
         box[0] = INT_MAX;
@@ -295,7 +296,9 @@ __global__ void __launch_bounds__(kGridThreads) k_gridw(ItemArgs a)
     const float kk = (float)(kPi * a.dish / lam);
     const double sigma = a.gauss_sigma_ld * lam / a.dish;
     const float inv_s2 = (float)(1.0 / (sigma * sigma));
+    const float aps = (float)(a.dish / lam * a.ap_inv_step);  // aperture table nodes per radian
     const float hstep = (float)a.h;
+    const double w_per_m = a.freq[it.chan] / kCLight;  // w-term: wavelengths per metre
     float2* wt = tiles + (size_t)wave * S * SP;
     float2* ph = phsh[wave];
 
@@ -304,7 +307,7 @@ __global__ void __launch_bounds__(kGridThreads) k_gridw(ItemArgs a)
         const double* oi = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.ai) * 2;
         const double* oj = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.aj) * 2;
         const double qil = oi[0] + sq, qim = oi[1], qjl = oj[0] + sq, qjm = oj[1];
-        if constexpr (!MF) image_products<kPredict>(a, it, pol, gsh, m2p, tid, kGridThreads);
+        if constexpr (MF == kFrameSky) image_products<kPredict>(a, it, pol, gsh, m2p, tid, kGridThreads);
         if (fits)
             for (int t = tid; t < hgt * PB; t += kGridThreads) patch[t] = make_float2(0.f, 0.f);
         __syncthreads();
@@ -338,9 +341,10 @@ __global__ void __launch_bounds__(kGridThreads) k_gridw(ItemArgs a)
                     ph[64 + j] = make_float2(pm.x * sg, pm.y * sg);
                 }
                 float pil = (float)qil, pim = (float)qim, pjl = (float)qjl, pjm = (float)qjm;
-                if constexpr (MF) {
+                const float wl = WT ? (float)(a.w_m[e.vidx / (uint32_t)a.n_chan] * w_per_m) : 0.f;
+                float sn = 0.f, cs = 1.f;
+                if constexpr (MF != kFrameSky) {
                     // this row's beam centres on the sky
-                    float sn, cs;
                     sincosf((float)a.par_angle[e.vidx / (uint32_t)a.n_chan], &sn, &cs);
                     pil = (float)(cs * qil - sn * qim);
                     pim = (float)(sn * qil + cs * qim);
@@ -362,8 +366,13 @@ __global__ void __launch_bounds__(kGridThreads) k_gridw(ItemArgs a)
                             const int nmv = rm - em * S;
                             if (nmv < -half_m || nmv >= half_m) continue;
                             float gv;
-                            if constexpr (MF) {
-                                const float l = (float)nl * hstep, mm = (float)nmv * hstep;
+                            const float l = (float)nl * hstep, mm = (float)nmv * hstep;
+                            if constexpr (MF == kFrameAperture) {
+                                float ei, ej, unused;
+                                efp_ap<false>(a, aps, cs, sn, l - pil, mm - pim, ei, unused, unused);
+                                efp_ap<false>(a, aps, cs, sn, l - pjl, mm - pjm, ej, unused, unused);
+                                gv = ei * ej * (a.taper_img[nl + half_m] * a.taper_img[nmv + half_m]);
+                            } else if constexpr (MF == kFrameMount) {
                                 float ei, qi, ej, qj;
                                 efq(a, airy_sh, kk, inv_s2, l - pil, mm - pim, ei, qi);
                                 efq(a, airy_sh, kk, inv_s2, l - pjl, mm - pjm, ej, qj);
@@ -372,8 +381,17 @@ __global__ void __launch_bounds__(kGridThreads) k_gridw(ItemArgs a)
                                 gv = gsh[(nl + half_m) * m + nmv + half_m];
                             }
                             const float2 pm = ph[64 + nmv + half_m];
-                            x.x = fmaf(gv, pm.x, x.x);
-                            x.y = fmaf(gv, pm.y, x.y);
+                            if constexpr (WT) {
+                                // times exp(2 pi i w (n - 1)), n - 1 = -x / (1 + sqrt(1 - x))
+                                const float xx = fmaf(l, l, mm * mm);
+                                const float nm1 = -xx / (1.f + sqrtf(1.f - xx));
+                                float sn, cs;
+                                sincospif(2.f * wl * nm1, &sn, &cs);
+                                cmac(x, make_float2(gv * cs, gv * sn), pm);
+                            } else {
+                                x.x = fmaf(gv, pm.x, x.x);
+                                x.y = fmaf(gv, pm.y, x.y);
+                            }
                         }
                         cmac(u, ph[nl + half_m], x);
                     }
@@ -460,25 +478,38 @@ size_t gridw_lds_bytes(int support, int m, int mount_frame_tab)
            sizeof(float2) * kGridPatch * kGridPatch + (mf ? sizeof(float4) * mount_frame_tab : 0);
 }
 
-template <int S, bool MF>
+template <int S, int MF, bool WT>
 static hipError_t launch_gridw_t(const ItemArgs& a, hipStream_t s)
 {
-    const size_t sh = gridw_lds_bytes(S, a.m, MF ? a.n_tab : -1);
+    const size_t sh = gridw_lds_bytes(S, a.m, MF == kFrameMount ? a.n_tab : MF == kFrameAperture ? 0 : -1);
     if (sh > kGridLdsMax) return hipErrorInvalidValue;
     static const hipError_t attr = hipFuncSetAttribute(
-        (const void*)k_gridw<S, MF>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGridLdsMax);
+        (const void*)k_gridw<S, MF, WT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGridLdsMax);
     if (attr != hipSuccess) return attr;
     const int blocks = 8 * ((a.n_items + 7) / 8);
-    k_gridw<S, MF><<<blocks, kGridThreads, sh, s>>>(a);
+    k_gridw<S, MF, WT><<<blocks, kGridThreads, sh, s>>>(a);
     return hipGetLastError();
+}
+
+template <int S>
+static hipError_t launch_gridw_f(int frame, bool wt, const ItemArgs& a, hipStream_t s)
+{
+    switch (frame) {
+    case kFrameSky: return wt ? launch_gridw_t<S, kFrameSky, true>(a, s) : launch_gridw_t<S, kFrameSky, false>(a, s);
+    case kFrameMount:
+        return wt ? launch_gridw_t<S, kFrameMount, true>(a, s) : launch_gridw_t<S, kFrameMount, false>(a, s);
+    default:
+        return wt ? launch_gridw_t<S, kFrameAperture, true>(a, s) : launch_gridw_t<S, kFrameAperture, false>(a, s);
+    }
 }
 
 hipError_t launch_gridw(int support, const ItemArgs& a, hipStream_t s)
 {
     if (a.n_items <= 0) return hipSuccess;
-    const bool mf = a.par_angle != nullptr;
-    if (support == 16) return mf ? launch_gridw_t<16, true>(a, s) : launch_gridw_t<16, false>(a, s);
-    if (support == 32) return mf ? launch_gridw_t<32, true>(a, s) : launch_gridw_t<32, false>(a, s);
+    const int fr = a.ap_tab != nullptr ? kFrameAperture : a.par_angle != nullptr ? kFrameMount : kFrameSky;
+    const bool wt = a.w_m != nullptr;
+    if (support == 16) return launch_gridw_f<16>(fr, wt, a, s);
+    if (support == 32) return launch_gridw_f<32>(fr, wt, a, s);
     return hipErrorInvalidValue;
 }
 

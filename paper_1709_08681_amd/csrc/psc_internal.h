@@ -41,6 +41,12 @@ struct VisEnt {
 
 enum Mode { kPredict = 0, kGrad = 1, kVjp = 2, kGrid = 3 };
 
+// Beam frame of the window-form kernels: radial beams on the sky (factored
+// image-plane products), radial beams in the mount frame (per-sample
+// products at each row's rotated centres), or a measured aperture's pattern
+// in the mount frame (per-sample products from its tabulated transform).
+enum Frame { kFrameSky = 0, kFrameMount = 1, kFrameAperture = 2 };
+
 // Kernel variants a mode degrids (V, or V and its four offset derivatives)
 // and the float64 sums it keeps per item.
 __host__ __device__ constexpr int mode_nv(int mode) { return mode == kGrad ? 5 : mode == kVjp ? 4 : 1; }
@@ -77,6 +83,14 @@ struct ItemArgs {
     const int32_t* done;        // nullable: per-interval skip flags
     double2* grid_acc;          // grid mode: residual grid, (N+S) x (N+S), float64 sums
     const double* par_angle;    // nullable [n_row]: offsets in the mount frame (window form)
+    const double* w_m;          // nullable [n_row]: baseline w in metres, the w-term (window form)
+    // measured aperture (illum 2): its transform on [ap_n][ap_n] nodes in
+    // lambda/D units, (T, s dT/du, s dT/dv, s^2 d2T/dudv) at u = (i - ap_c) s,
+    // s = 1 / ap_inv_step, i along the mount frame's l axis
+    const float4* ap_tab;
+    int32_t ap_n;
+    float ap_c;
+    float ap_inv_step;
     int32_t use_mfma;           // degrid on the matrix cores (gradient and adjoint)
     // image-gradient scatter (k_grid)
     const uint2* ig_ord;        // per item, its samples in time order: (sample index, sub-table slot)
@@ -115,6 +129,11 @@ hipError_t launch_fft_rows(double2* data, int n, int log2n, hipStream_t s);
 hipError_t launch_transpose(const double2* in, double2* out, int n, hipStream_t s);
 hipError_t launch_finish_grid(const double2* in, float2* out, int n, int pad, hipStream_t s);
 hipError_t launch_airy_table(float4* tab, int n_tab, double dx, hipStream_t s);
+// Measured-aperture pattern table (psc_aperture.hip): n x n nodes at
+// u = (i - c) step (lambda/D units) from the aperture's non-zero cells
+// [n_cells][3] = (xi, eta, weight), xi and eta in units of D.
+hipError_t launch_aperture_table(const double* cells, int n_cells, float4* tab, int n, double c, double step,
+                                 hipStream_t s);
 hipError_t launch_zero(double2* p, size_t n, hipStream_t s);
 hipError_t launch_unpad_grid(const double2* g, double2* out, int n, int pad, hipStream_t s);
 hipError_t launch_image_grad(const double2* f, const double* taper_pix, double* out, int n, hipStream_t s);

@@ -116,7 +116,7 @@ __device__ __forceinline__ void halves(float v, float& lo, float& hi)
 // the m-axis phase is the lane's own.  In the sum lane (h, c) takes the
 // image-sample m index n_m = c - S h (M/2 of the S lanes of each half have
 // one).
-template <int S, int MODE, bool MF, int W>
+template <int S, int MODE, int MF, int W, bool WT>
 __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
 {
     constexpr int H = S / 2, SP = S + 1;
@@ -137,11 +137,11 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
     const int m2p = (m * m + 3) & ~3;
     const int O = a.oversample, so = S * O;
     // dynamic LDS: per-worker float64 sums | the item's groups |
-    // image-plane factors [n][NG] | window tiles | Airy table (MF)
+    // image-plane factors [n][NG] (sky frame) | window tiles | Airy table (mount frame)
     double* gpart = reinterpret_cast<double*>(smem);  // [NW][NCP]
     Group* grp = reinterpret_cast<Group*>(gpart + NW * NCP);
     float* gsh = reinterpret_cast<float*>(grp + win_max_groups(O));
-    float2* wtile = reinterpret_cast<float2*>(gsh + (MF ? 0 : NG * m2p));
+    float2* wtile = reinterpret_cast<float2*>(gsh + (MF != kFrameSky ? 0 : NG * m2p));
     float4* airy_sh = reinterpret_cast<float4*>(wtile + (size_t)NW * S * SP);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
     const int n_grp = it.grp_end - it.grp_begin;
     for (int t = tid; t < so; t += kBlock) twsh[t] = a.tw[t];
     for (int t = tid; t < n_grp; t += kBlock) grp[t] = a.groups[it.grp_begin + t];
-    if constexpr (MF)
+    if constexpr (MF == kFrameMount)
         for (int t = tid; t < a.n_tab; t += kBlock) airy_sh[t] = a.airy[t];
     __syncthreads();
 
@@ -223,8 +223,21 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
     const float kk = (float)(kPi * a.dish / lam);
     const double sigma = a.gauss_sigma_ld * lam / a.dish;
     const float inv_s2 = (float)(1.0 / (sigma * sigma));
+    const float aps = (float)(a.dish / lam * a.ap_inv_step);  // aperture table nodes per radian
     const float hstep = (float)a.h;
     const float mmy = (float)nm * hstep;
+    // w-term: w in wavelengths per metre at the item's channel, and the
+    // lane's m^2
+    const double w_per_m = a.freq[it.chan] / kCLight;
+    const float mm2 = mmy * mmy;
+    // exp(2 pi i w (n - 1)) at (l, lane's m), n - 1 = -x / (1 + sqrt(1 - x))
+    auto wphase = [&](float wl, float l) {
+        const float x = fmaf(l, l, mm2);
+        const float nm1 = -x / (1.f + sqrtf(1.f - x));
+        float sn, cs;
+        sincospif(2.f * wl * nm1, &sn, &cs);
+        return make_float2(cs, sn);
+    };
     const float ctm = a.taper_img[jm];
 
     for (int pol = 0; pol < a.n_pol; ++pol) {
@@ -236,7 +249,7 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
         float2 x0[H];
         VisEnt e0 = {0u, 0u}, e1 = {0u, 0u};
         float2 vin0 = zero;
-        float wgt0 = 0.f;
+        float wgt0 = 0.f, w0 = 0.f;
         if (gi0 < n_grp) {
             e0 = entry(gi0, v0);
             e1 = entry(gi1, v1);
@@ -244,6 +257,7 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
             const size_t o0 = (size_t)e0.vidx * a.n_pol + pol;
             if (MODE != kPredict) vin0 = a.vis_in[o0];
             if (MODE == kGrad) wgt0 = a.weight[o0];
+            if constexpr (WT) w0 = (float)(a.w_m[e0.vidx / (uint32_t)a.n_chan] * w_per_m);
         }
 
         // offsets plus squint (along l, or along the mount's first axis)
@@ -251,7 +265,7 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
         const double* oi = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.ai) * 2;
         const double* oj = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.aj) * 2;
         const double qil = oi[0] + sq, qim = oi[1], qjl = oj[0] + sq, qjm = oj[1];
-        if constexpr (!MF)
+        if constexpr (MF == kFrameSky)
             image_factors<MODE>(a, gsh, kk, inv_s2, (float)qil, (float)qim, (float)qjl, (float)qjm, tid, kBlock);
         __syncthreads();
 
@@ -262,9 +276,10 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
             load_window(e1, x1);
             const size_t o1 = (size_t)e1.vidx * a.n_pol + pol;
             float2 vin1 = zero;
-            float wgt1 = 0.f;
+            float wgt1 = 0.f, w1 = 0.f;
             if (MODE != kPredict) vin1 = a.vis_in[o1];
             if (MODE == kGrad) wgt1 = a.weight[o1];
+            if constexpr (WT) w1 = (float)(a.w_m[e1.vidx / (uint32_t)a.n_chan] * w_per_m);
             int gi2 = gi1, v2 = v1;
             if (gi1 < n_grp) advance(gi2, v2, NW);
             const VisEnt e2 = entry(gi2, v2);
@@ -312,17 +327,22 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
 #pragma unroll
             for (int k = 0; k < NV; ++k) A[k] = B[k] = zero;
             float cs = 1.f, sn = 0.f;
-            if constexpr (MF) {
+            if constexpr (MF != kFrameSky) {
                 // this row's beam centres on the sky
                 sincosf((float)a.par_angle[e0.vidx / (uint32_t)a.n_chan], &sn, &cs);
                 const float pil = (float)(cs * qil - sn * qim), pim = (float)(sn * qil + cs * qim);
                 const float pjl = (float)(cs * qjl - sn * qjm), pjm = (float)(sn * qjl + cs * qjm);
                 auto term = [&](int jl, float2 (&acc)[NV]) {
-                    const float2 t = wt[((jl - half_m) & (S - 1)) * SP + c];
                     const float l = (float)(jl - half_m) * hstep;
+                    float2 t = wt[((jl - half_m) & (S - 1)) * SP + c];
+                    if constexpr (WT) t = cmul(t, wphase(w0, l));
                     float g[NV];
-                    mf_products<MODE>(a, airy_sh, kk, inv_s2, l - pil, mmy - pim, l - pjl, mmy - pjm,
-                                      a.taper_img[jl] * ctm, g);
+                    if constexpr (MF == kFrameAperture)
+                        mf_products_ap<MODE>(a, aps, cs, sn, l - pil, mmy - pim, l - pjl, mmy - pjm,
+                                             a.taper_img[jl] * ctm, g);
+                    else
+                        mf_products<MODE>(a, airy_sh, kk, inv_s2, l - pil, mmy - pim, l - pjl, mmy - pjm,
+                                          a.taper_img[jl] * ctm, g);
 #pragma unroll
                     for (int k = 0; k < NV; ++k) {
                         acc[k].x = fmaf(g[k], t.x, acc[k].x);
@@ -346,7 +366,8 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
                     const float* g = gp + j0 * m * NG;
 #pragma unroll 4
                     for (int jl = j0; jl < j1; ++jl, tp += SP, g += m * NG) {
-                        const float2 t = *tp;
+                        float2 t = *tp;
+                        if constexpr (WT) t = cmul(t, wphase(w0, (float)(jl - half_m) * hstep));
                         if constexpr (MODE != kVjp) {
                             acc[0].x = fmaf(g[0], t.x, acc[0].x);
                             acc[0].y = fmaf(g[0], t.y, acc[0].y);
@@ -384,7 +405,7 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
                 const float2 rb = cmul(rho, B[k]);
                 s[k] = cmul(pm, make_float2(A[k].x + rb.x, A[k].y + rb.y));
             }
-            if constexpr (!MF && MODE != kPredict) {
+            if constexpr (MF == kFrameSky && MODE != kPredict) {
                 // derivative variants from the factored sums (the lane's m coordinate is mmy)
                 constexpr int o = MODE == kGrad ? 1 : 0;
                 const float pl[2] = {(float)qil, (float)qjl}, pmm[2] = {(float)qim, (float)qjm};
@@ -407,7 +428,7 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
                     s[k].y = sum_xor32(s[k].y);
                 }
             }
-            if constexpr (MF && MODE != kPredict) {
+            if constexpr (MF == kFrameMount && MODE != kPredict) {
                 // derivatives with respect to the mount-frame offsets
                 constexpr int d0 = (MODE == kGrad) ? 1 : 0;
 #pragma unroll
@@ -432,6 +453,7 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
             for (int r = 0; r < H; ++r) x0[r] = x1[r];
             vin0 = vin1;
             wgt0 = wgt1;
+            w0 = w1;
             e0 = e1;
             e1 = e2;
             gi0 = gi1;
@@ -453,29 +475,45 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
     }
 }
 
-template <int S, int MODE, bool MF>
+template <int S, int MODE, int MF, bool WT>
 static hipError_t launch_win_t(const ItemArgs& a, hipStream_t s)
 {
-    const int tab = MF ? a.n_tab : -1;
+    const int tab = MF == kFrameMount ? a.n_tab : MF == kFrameAperture ? 0 : -1;
     const size_t budget = win_lds_budget(S);
     // raise the dynamic LDS limit once, to what one compute unit allows
-    static const hipError_t attr8 = hipFuncSetAttribute(
-        (const void*)k_winw<S, MODE, MF, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget);
     static const hipError_t attr4 = hipFuncSetAttribute(
-        (const void*)k_winw<S, MODE, MF, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget);
-    if (attr8 != hipSuccess) return attr8;
+        (const void*)k_winw<S, MODE, MF, 4, WT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget);
     if (attr4 != hipSuccess) return attr4;
     const int blocks = 8 * ((a.n_items + 7) / 8);
     // four wavefronts when two blocks fit a compute unit's LDS, else eight
+    // (support 32 with many image samples)
     const size_t sh4 = winw_lds_bytes(S, 4, MODE, a.m, a.oversample, tab);
-    const size_t sh8 = winw_lds_bytes(S, 8, MODE, a.m, a.oversample, tab);
     if (2 * (sh4 + (160 * 1024 - budget)) <= 160 * 1024) {
-        k_winw<S, MODE, MF, 4><<<blocks, 64 * 4, sh4, s>>>(a);
-    } else {
-        if (sh8 > budget) return hipErrorInvalidValue;
-        k_winw<S, MODE, MF, 8><<<blocks, 64 * 8, sh8, s>>>(a);
+        k_winw<S, MODE, MF, 4, WT><<<blocks, 64 * 4, sh4, s>>>(a);
+        return hipGetLastError();
     }
-    return hipGetLastError();
+    if constexpr (S == 32) {
+        static const hipError_t attr8 = hipFuncSetAttribute(
+            (const void*)k_winw<S, MODE, MF, 8, WT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget);
+        if (attr8 != hipSuccess) return attr8;
+        const size_t sh8 = winw_lds_bytes(S, 8, MODE, a.m, a.oversample, tab);
+        if (sh8 > budget) return hipErrorInvalidValue;
+        k_winw<S, MODE, MF, 8, WT><<<blocks, 64 * 8, sh8, s>>>(a);
+        return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int S, int MODE>
+static hipError_t launch_win_m(const ItemArgs& a, hipStream_t s)
+{
+    const bool wt = a.w_m != nullptr;
+    if (a.ap_tab != nullptr)
+        return wt ? launch_win_t<S, MODE, kFrameAperture, true>(a, s)
+                  : launch_win_t<S, MODE, kFrameAperture, false>(a, s);
+    if (a.par_angle != nullptr)
+        return wt ? launch_win_t<S, MODE, kFrameMount, true>(a, s) : launch_win_t<S, MODE, kFrameMount, false>(a, s);
+    return wt ? launch_win_t<S, MODE, kFrameSky, true>(a, s) : launch_win_t<S, MODE, kFrameSky, false>(a, s);
 }
 
 size_t win_lds_bytes(int support, int mode, int m, int oversample, int mount_frame_tab)
@@ -505,20 +543,19 @@ size_t win_lds_budget(int support)
 hipError_t launch_win(int mode, int support, const ItemArgs& a, hipStream_t s)
 {
     if (a.n_items <= 0) return hipSuccess;
-    const bool mf = a.par_angle != nullptr;
     if (support == 16) {
         switch (mode) {
-        case kPredict: return mf ? launch_win_t<16, kPredict, true>(a, s) : launch_win_t<16, kPredict, false>(a, s);
-        case kGrad: return mf ? launch_win_t<16, kGrad, true>(a, s) : launch_win_t<16, kGrad, false>(a, s);
-        case kVjp: return mf ? launch_win_t<16, kVjp, true>(a, s) : launch_win_t<16, kVjp, false>(a, s);
+        case kPredict: return launch_win_m<16, kPredict>(a, s);
+        case kGrad: return launch_win_m<16, kGrad>(a, s);
+        case kVjp: return launch_win_m<16, kVjp>(a, s);
         default: return hipErrorInvalidValue;
         }
     }
     if (support == 32) {
         switch (mode) {
-        case kPredict: return mf ? launch_win_t<32, kPredict, true>(a, s) : launch_win_t<32, kPredict, false>(a, s);
-        case kGrad: return mf ? launch_win_t<32, kGrad, true>(a, s) : launch_win_t<32, kGrad, false>(a, s);
-        case kVjp: return mf ? launch_win_t<32, kVjp, true>(a, s) : launch_win_t<32, kVjp, false>(a, s);
+        case kPredict: return launch_win_m<32, kPredict>(a, s);
+        case kGrad: return launch_win_m<32, kGrad>(a, s);
+        case kVjp: return launch_win_m<32, kVjp>(a, s);
         default: return hipErrorInvalidValue;
         }
     }

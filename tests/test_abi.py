@@ -5,6 +5,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -56,7 +57,7 @@ def _cfg(psc, **kw):
 @pytest.mark.parametrize("bad", [
     dict(grid_n=1000), dict(grid_n=32), dict(support=12), dict(oversample=0),
     dict(image_samples=15), dict(image_samples=40), dict(cell_rad=0.0), dict(dish_diam_m=-1.0),
-    dict(illum=2), dict(taper_width=16), dict(illum=1, gauss_sigma_ld=0.0),
+    dict(illum=2), dict(illum=3), dict(taper_width=16), dict(illum=1, gauss_sigma_ld=0.0),
 ])
 def test_create_rejects_invalid_config(psc, bad):
     with pytest.raises(psc.PscError) as ei:
@@ -74,6 +75,35 @@ def test_support32_fits_every_image_sample_count(psc, over):
     except psc.PscError as e:
         assert e.status != -4, str(e)
         assert "device" in str(e)
+    else:
+        psc.psc_destroy(ctx)
+
+
+def _aperture_cfg(psc, ap, **kw):
+    ap = np.ascontiguousarray(ap, dtype=np.float64)
+    return _cfg(psc, illum=2, aperture_n=ap.shape[0], aperture=ap.ctypes.data, **kw), ap
+
+
+def test_measured_aperture_validation(psc):
+    """illum 2 takes a real, even aperture with a positive sum and at most
+    256 cells per side; a valid one gets past the configuration checks
+    (here, without a GPU, to the device selection)."""
+    from paper_1709_08681_amd import synth
+    good = synth.measured_aperture(seed=1)
+    uneven = good.copy()
+    uneven[4, 9] += 0.25
+    nonfinite = good.copy()
+    nonfinite[0, 0] = nonfinite[-1, -1] = np.nan
+    for bad in (uneven, nonfinite, -good, np.zeros((8, 8)), np.ones((257, 257))):
+        cfg, keep = _aperture_cfg(psc, bad)
+        with pytest.raises(psc.PscError) as ei:
+            psc.psc_create(cfg)
+        assert ei.value.status == -1
+    cfg, keep = _aperture_cfg(psc, good)
+    try:
+        ctx = psc.psc_create(cfg)
+    except psc.PscError as e:
+        assert e.status != -1 or "device" in str(e), str(e)
     else:
         psc.psc_destroy(ctx)
 

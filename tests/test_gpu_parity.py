@@ -723,6 +723,75 @@ def test_image_gradient_cfg5_subset(torch_dev, cfg5_subset):
 
 
 # ---------------------------------------------------------------------------
+# the w-term (each row's w in the measurement equation, window form)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("S,over,mount", [(16, 4, False), (32, 8, False), (16, 4, True)])
+def test_w_term_predict_gradient_vjp_image(torch_dev, S, over, mount):
+    """Baselines to 3 km, so that leaving w out is a 2-3% error: prediction,
+    gradient sums, the adjoint and the image gradient against the oracle
+    with the w-term, at both supports and with mount-frame offsets."""
+    torch = torch_dev
+    from paper_1709_08681_amd import psc
+    print(f"case: w-term, S {S}, O {over}, mount {mount}", flush=True)
+    obs = small_ragged_obs(99, support=S, oversample=over, fov_frac=0.85, layout_radius_m=3000.0)
+    prob = oracle.Problem.from_observation(obs, w_term=True, mount_frame=mount)
+    s = session(obs, w_term=True, mount_frame=mount)
+    try:
+        assert psc.psc_get_degrid(s.handle) == psc.DEGRID_WINDOW
+        with pytest.raises(psc.PscError):
+            psc.psc_set_degrid(s.handle, psc.DEGRID_VALU)
+        v = oracle.predict(prob, obs.offsets_true)
+        v_no_w = oracle.predict(oracle.Problem.from_observation(obs, mount_frame=mount), obs.offsets_true)
+        assert rel(v_no_w, v) > 1e-3  # the w-term matters here
+        assert rel(s.predict(obs.offsets_true).cpu().numpy(), v) <= 1e-5
+        start = synth.perturbed_offsets(obs, 25.0, 43)
+        nz, w = synth.noise(v, 100.0, 44)
+        ref, vm_ref = oracle.gradient(prob, start, v + nz, w, want_model=True)
+        acc, vm = s.gradient(s.offsets(start), c64(torch, s, v + nz), f32(torch, s, w, s.vis_shape),
+                             want_model=True)
+        assert rel(vm.cpu().numpy(), vm_ref) <= 1e-5
+        acc = acc.cpu().numpy()
+        for k in range(6):
+            assert rel(acc[..., k], ref[..., k]) <= 1e-4, k
+        rng = np.random.default_rng(45)
+        G = (rng.normal(size=s.vis_shape) + 1j * rng.normal(size=s.vis_shape)).astype(np.complex64)
+        got = s.vjp(s.offsets(start), torch.as_tensor(G, device=s.dev)).cpu().numpy()
+        assert rel(got, vjp_reference(obs, prob, start, G, s.off_shape)) <= 1e-4
+        _check_image_gradient(torch, obs, prob, s, start, v + nz, w, 48, 46)
+    finally:
+        s.close()
+
+
+def test_w_term_solve(torch_dev):
+    """Algorithm 1 with the w-term: the same iterations and offsets as the
+    oracle's solve on noisy data, and recovery of the injected offsets from
+    noiseless data (without the w-term the model error would bias them)."""
+    torch = torch_dev
+    from paper_1709_08681_amd import psc
+    print("case: w-term solve", flush=True)
+    obs = small_ragged_obs(101, fov_frac=0.85, layout_radius_m=3000.0)
+    prob = oracle.Problem.from_observation(obs, w_term=True)
+    s = session(obs, w_term=True)
+    try:
+        v = oracle.predict(prob, obs.offsets_true)
+        start = synth.perturbed_offsets(obs, 20.0, 47)
+        nz, w = synth.noise(v, 100.0, 48)
+        ref, its_ref = oracle.solve(prob, v + nz, w, start, gain=0.5, n_max=8, tol_rad=1e-3 * ARCSEC)
+        off = s.offsets(start)
+        its = s.solve(c64(torch, s, v + nz), f32(torch, s, w, s.vis_shape), off, gain=0.5, n_max=8,
+                      tol_rad=1e-3 * ARCSEC, form=psc.SOLVE_GRAPH)
+        assert np.array_equal(its.cpu().numpy(), its_ref)
+        assert np.abs(off.cpu().numpy() - ref).max() / ARCSEC <= 0.1
+        w1 = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+        off = s.offsets(start)
+        s.solve(c64(torch, s, v), w1, off, gain=0.5, n_max=80, tol_rad=1e-5 * ARCSEC)
+        assert np.abs(off.cpu().numpy() - obs.offsets_true).max() / ARCSEC <= 0.05
+    finally:
+        s.close()
+
+
+# ---------------------------------------------------------------------------
 # offsets in the antenna mount frame (per-row parallactic angle)
 # ---------------------------------------------------------------------------
 
@@ -836,3 +905,101 @@ def test_mount_frame_support32(torch_dev, cfg5_subset):
         _check_image_gradient(torch, obs, prob, s, start, v, 1.0, 32, 42)
     finally:
         s.close()
+
+
+# ---------------------------------------------------------------------------
+# measured aperture (illum 2): a non-circular pattern fixed to the mount,
+# from a table of the aperture's transform
+# ---------------------------------------------------------------------------
+
+def _aperture_obs(support, oversample):
+    """Ten-minute timesteps over 2.3 hours, two polarisations with squint,
+    uneven intervals."""
+    lengths = [5, 3, 6]
+    wl = synth.workload(1, n_ant=7, n_time=sum(lengths), dt_s=600.0, interval_lengths=lengths, n_pol=2,
+                        squint_frac=0.03, freqs_hz=np.array([1.2e9, 1.6e9]), n_src=5, support=support,
+                        oversample=oversample)
+    return synth.make_observation(wl, 95)
+
+
+@pytest.mark.parametrize("S,over,mount", [(16, 4, True), (16, 4, False), (32, 8, True)])
+def test_measured_aperture_predict_gradient_vjp_image(torch_dev, S, over, mount):
+    """A blocked, tapered aperture with feed-leg shadows: prediction, model,
+    sums, the adjoint and the image gradient against the oracle's direct
+    Fourier sum over the aperture, in the mount frame (angle per row) and in
+    the sky frame, at both supports."""
+    torch = torch_dev
+    from paper_1709_08681_amd import psc
+    print(f"case: measured aperture, S {S}, O {over}, mount {mount}", flush=True)
+    obs = _aperture_obs(S, over)
+    A = synth.measured_aperture(seed=11)
+    prob = oracle.Problem.from_observation(obs, mount_frame=mount, illum=2, aperture=A)
+    s = session(obs, mount_frame=mount, aperture=A)
+    try:
+        assert psc.psc_get_degrid(s.handle) == psc.DEGRID_WINDOW
+        for variant in (psc.DEGRID_VALU, psc.DEGRID_MFMA):
+            with pytest.raises(psc.PscError) as ei:
+                psc.psc_set_degrid(s.handle, variant)
+            assert ei.value.status == psc.PSC_E_UNSUPPORTED
+        v = oracle.predict(prob, obs.offsets_true)
+        v_dish = oracle.predict(oracle.Problem.from_observation(obs, mount_frame=mount), obs.offsets_true)
+        assert rel(v_dish, v) > 1e-2  # not the uniform dish
+        start = synth.perturbed_offsets(obs, 25.0, 51)
+        assert rel(s.predict(start).cpu().numpy(), oracle.predict(prob, start)) <= 1e-5
+        nz, w = synth.noise(v, 100.0, 52)
+        ref, vm_ref = oracle.gradient(prob, start, v + nz, w, want_model=True)
+        acc, vm = s.gradient(s.offsets(start), c64(torch, s, v + nz), f32(torch, s, w, s.vis_shape),
+                             want_model=True)
+        assert rel(vm.cpu().numpy(), vm_ref) <= 1e-5
+        acc = acc.cpu().numpy()
+        for k in range(6):
+            assert rel(acc[..., k], ref[..., k]) <= 1e-4, k
+        rng = np.random.default_rng(53)
+        G = (rng.normal(size=s.vis_shape) + 1j * rng.normal(size=s.vis_shape)).astype(np.complex64)
+        got = s.vjp(s.offsets(start), torch.as_tensor(G, device=s.dev)).cpu().numpy()
+        assert rel(got, vjp_reference(obs, prob, start, G, s.off_shape)) <= 1e-4
+        _check_image_gradient(torch, obs, prob, s, start, v + nz, w, 48, 54)
+    finally:
+        s.close()
+
+
+def test_measured_aperture_solve(torch_dev):
+    """Algorithm 1 with the measured aperture in the mount frame: the same
+    iterations and offsets as the oracle's solve, plain and graph forms
+    equal, and noiseless recovery of the injected offsets."""
+    torch = torch_dev
+    from paper_1709_08681_amd import psc
+    print("case: measured aperture solve", flush=True)
+    obs = _aperture_obs(16, 4)
+    A = synth.measured_aperture(seed=12)
+    prob = oracle.Problem.from_observation(obs, mount_frame=True, illum=2, aperture=A)
+    s = session(obs, mount_frame=True, aperture=A)
+    try:
+        v = oracle.predict(prob, obs.offsets_true)
+        start = synth.perturbed_offsets(obs, 25.0, 55)
+        ref_off, its_ref = oracle.solve(prob, v, 1.0, start, gain=0.5, n_max=8, tol_rad=1e-3 * ARCSEC)
+        w1 = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+        outs = []
+        for form in (psc.SOLVE_PLAIN, psc.SOLVE_GRAPH):
+            off = s.offsets(start)
+            its = s.solve(c64(torch, s, v), w1, off, gain=0.5, n_max=8, tol_rad=1e-3 * ARCSEC, form=form)
+            assert np.array_equal(its.cpu().numpy(), its_ref)
+            outs.append(off.cpu().numpy())
+            assert np.abs(outs[-1] - ref_off).max() / ARCSEC <= 0.1
+        assert np.array_equal(outs[0], outs[1])
+        off = s.offsets(start)
+        s.solve(c64(torch, s, v), w1, off, gain=0.5, n_max=80, tol_rad=1e-5 * ARCSEC)
+        assert np.abs(off.cpu().numpy() - obs.offsets_true).max() / ARCSEC <= 0.05
+    finally:
+        s.close()
+
+
+def test_measured_aperture_must_be_even(torch_dev):
+    from paper_1709_08681_amd import psc
+    print("case: measured aperture validation", flush=True)
+    obs = _aperture_obs(16, 4)
+    A = synth.measured_aperture(seed=13)
+    A[2, 7] += 0.5
+    with pytest.raises(psc.PscError) as ei:
+        session(obs, aperture=A)
+    assert ei.value.status == psc.PSC_E_ARG
