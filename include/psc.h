@@ -141,7 +141,10 @@ typedef struct {
  *              sample's kernel is the transform of the aperture products
  *              times that phase, so it must still fit the support); the
  *              observation degrids in the window form, and psc_set_degrid
- *              refuses the table forms.  Null: w = 0.
+ *              refuses the table forms.  The phase widens each kernel by
+ *              about |w| FoV / D uv cells over the beam; psc_obs_create
+ *              returns PSC_E_UNSUPPORTED when max |w| FoV / D exceeds 1.5
+ *              (w-projection beyond that needs a wider support).  Null: w = 0.
  *
  * Visibility-shaped arrays used by the calls below are laid out
  * [n_row][n_chan][n_pol]; offsets are [n_int][n_pol][n_ant][2] float64 (l, m).

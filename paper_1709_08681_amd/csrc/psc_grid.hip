@@ -382,11 +382,12 @@ __global__ void __launch_bounds__(kGridThreads) k_gridw(ItemArgs a)
                             }
                             const float2 pm = ph[64 + nmv + half_m];
                             if constexpr (WT) {
-                                // times exp(2 pi i w (n - 1)), n - 1 = -x / (1 + sqrt(1 - x))
+                                // times exp(2 pi i w (n - 1)), n - 1 = -x / (1 + sqrt(1 - x)),
+                                // the phase in turns reduced to [0, 1) for the hardware sine
                                 const float xx = fmaf(l, l, mm * mm);
-                                const float nm1 = -xx / (1.f + sqrtf(1.f - xx));
-                                float sn, cs;
-                                sincospif(2.f * wl * nm1, &sn, &cs);
+                                const float nm1 = -xx * __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_sqrtf(1.f - xx));
+                                const float rv = __builtin_amdgcn_fractf(wl * nm1);
+                                const float sn = __builtin_amdgcn_sinf(rv), cs = __builtin_amdgcn_cosf(rv);
                                 cmac(x, make_float2(gv * cs, gv * sn), pm);
                             } else {
                                 x.x = fmaf(gv, pm.x, x.x);

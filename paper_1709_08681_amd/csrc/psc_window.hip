@@ -230,13 +230,15 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
     // lane's m^2
     const double w_per_m = a.freq[it.chan] / kCLight;
     const float mm2 = mmy * mmy;
-    // exp(2 pi i w (n - 1)) at (l, lane's m), n - 1 = -x / (1 + sqrt(1 - x))
+    // exp(2 pi i w (n - 1)) at (l, lane's m), n - 1 = -x / (1 + sqrt(1 - x)),
+    // from the hardware sine and cosine of the phase in turns reduced to
+    // [0, 1) (the phase itself is a float32 product; the parity tests bound
+    // the result)
     auto wphase = [&](float wl, float l) {
         const float x = fmaf(l, l, mm2);
-        const float nm1 = -x / (1.f + sqrtf(1.f - x));
-        float sn, cs;
-        sincospif(2.f * wl * nm1, &sn, &cs);
-        return make_float2(cs, sn);
+        const float nm1 = -x * __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_sqrtf(1.f - x));
+        const float r = __builtin_amdgcn_fractf(wl * nm1);
+        return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
     };
     const float ctm = a.taper_img[jm];
 

@@ -763,6 +763,19 @@ def test_w_term_predict_gradient_vjp_image(torch_dev, S, over, mount):
         s.close()
 
 
+def test_w_term_beyond_the_support_is_refused(torch_dev):
+    """Baselines to 24 km at support 16: |w| FoV / D near 3 uv cells, more
+    than the support leaves (the window form's error would pass 1e-4)."""
+    from paper_1709_08681_amd import psc
+    print("case: w-term refused", flush=True)
+    obs = small_ragged_obs(99, layout_radius_m=24000.0)
+    assert np.abs(obs.w_m).max() * obs.fov / obs.wl.dish_diam_m > 1.5
+    with pytest.raises(psc.PscError) as ei:
+        session(obs, w_term=True)
+    assert ei.value.status == psc.PSC_E_UNSUPPORTED
+    session(obs).close()  # the same observation without the w-term
+
+
 def test_w_term_solve(torch_dev):
     """Algorithm 1 with the w-term: the same iterations and offsets as the
     oracle's solve on noisy data, and recovery of the injected offsets from
