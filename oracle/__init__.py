@@ -60,6 +60,7 @@ class _Problem(C.Structure):
         ("w_m", C.POINTER(C.c_double)),
         ("aperture_n", C.c_int32),
         ("aperture", C.POINTER(C.c_double)),
+        ("beam_scale", C.POINTER(C.c_double)),
     ]
 
 
@@ -81,12 +82,16 @@ def _load():
             lib.oracle_hpbw.restype = C.c_double
             lib.oracle_snap_uv.argtypes = [P, C.c_int64, C.c_int, dp]
             lib.oracle_predict.argtypes = [P, dp, dp, dp]
+            lib.oracle_predict_scale.argtypes = [P, dp, dp, dp]
+            lib.oracle_scale_gradient.argtypes = [P, dp, dp, dp, dp]
+            lib.oracle_scale_step.argtypes = [C.c_int, C.c_int, C.c_int, dp, C.c_double, dp, ip, dp]
             lib.oracle_gradient.argtypes = [P, dp, dp, dp, dp, dp]
             lib.oracle_image_gradient.argtypes = [P, dp, dp, dp, C.c_int, dp, dp, dp]
             lib.oracle_solve_step.argtypes = [C.c_int, C.c_int, C.c_int, dp, C.c_double, C.c_double, dp, ip,
                                               dp, ip]
             lib.oracle_solve.argtypes = [P, dp, dp, dp, C.c_double, C.c_int, C.c_double, ip]
-            for name in ("oracle_predict", "oracle_gradient", "oracle_image_gradient",
+            for name in ("oracle_predict", "oracle_predict_scale", "oracle_scale_gradient", "oracle_scale_step",
+                         "oracle_gradient", "oracle_image_gradient",
                          "oracle_solve_step", "oracle_solve",
                          "oracle_num_threads"):
                 getattr(lib, name).restype = C.c_int
@@ -110,12 +115,13 @@ class Problem:
     rounds uv (in wavelengths) to the lattice 1/snap_scale.  ``w_m``: [n_row]
     baseline w in metres for the w-term (None: w = 0).  ``aperture``: a
     square, real, even aperture illumination across the dish for the
-    measured-aperture mode (illum 2).
+    measured-aperture mode (illum 2).  ``beam_scale``: [n_int, n_pol, n_ant]
+    beam-width scale sigma of each antenna, E = E0(d / sigma) (None: 1).
     """
 
     def __init__(self, src_l, src_m, src_flux, n_ant, ant1, ant2, uv_m, int_row_ptr, freq_hz,
                  n_pol=1, dish_diam_m=25.0, illum=0, gauss_sigma_ld=1.0, squint_frac=0.0,
-                 snap_scale=0.0, par_angle=None, w_m=None, aperture=None):
+                 snap_scale=0.0, par_angle=None, w_m=None, aperture=None, beam_scale=None):
         self.src_l = np.ascontiguousarray(src_l, np.float64)
         self.src_m = np.ascontiguousarray(src_m, np.float64)
         self.src_flux = np.ascontiguousarray(src_flux, np.float64)
@@ -142,6 +148,9 @@ class Problem:
         if self.aperture is not None and (self.aperture.ndim != 2 or
                                           self.aperture.shape[0] != self.aperture.shape[1]):
             raise ValueError("aperture must be square")
+        self.beam_scale = None if beam_scale is None else np.ascontiguousarray(beam_scale, np.float64)
+        if self.beam_scale is not None and self.beam_scale.shape != (self.n_int, self.n_pol, self.n_ant):
+            raise ValueError("beam_scale must be [n_int, n_pol, n_ant]")
         self._s = _Problem(
             int(self.src_flux.shape[0]), _dp(self.src_l), _dp(self.src_m), _dp(self.src_flux),
             self.n_ant, self.n_chan, self.n_pol, self.n_int, self.n_row,
@@ -151,7 +160,8 @@ class Problem:
             None if self.par_angle is None else _dp(self.par_angle),
             None if self.w_m is None else _dp(self.w_m),
             0 if self.aperture is None else int(self.aperture.shape[0]),
-            None if self.aperture is None else _dp(self.aperture))
+            None if self.aperture is None else _dp(self.aperture),
+            None if self.beam_scale is None else _dp(self.beam_scale))
 
     @classmethod
     def from_observation(cls, obs, snap=True, mount_frame=False, w_term=False, **kw):
@@ -278,6 +288,44 @@ def solve_step(acc, gain, offsets, done=None, mu=0.0):
     _check(lib.oracle_solve_step(n_int, n_pol, n_ant, _dp(acc), float(gain), float(mu), _dp(o), _ip(nu),
                                  _dp(mx), _ip(d)), "solve_step")
     return o, nu, mx
+
+
+def predict_scale(prob: Problem, offsets):
+    """Model visibilities and their derivatives with respect to the two
+    antennas' beam-width scales, [n_row, n_chan, n_pol, 2] (d/dsigma_i,
+    d/dsigma_j)."""
+    lib = _load()
+    o = _offs(prob, offsets)
+    vis = np.zeros(prob.vis_shape() + (2,))
+    ds = np.zeros(prob.vis_shape() + (2, 2))
+    _check(lib.oracle_predict_scale(prob.ref, _dp(o), _dp(vis), _dp(ds)), "predict_scale")
+    return vis[..., 0] + 1j * vis[..., 1], ds[..., 0] + 1j * ds[..., 1]
+
+
+def scale_gradient(prob: Problem, offsets, vis_obs, weight):
+    """Per-antenna sums [n_int, n_pol, n_ant, 3] = chi, g_sigma, H_sigma for the
+    beam-width scales the problem carries."""
+    lib = _load()
+    o = _offs(prob, offsets)
+    vo = np.ascontiguousarray(np.broadcast_to(vis_obs, prob.vis_shape()), np.complex128)
+    vo2 = np.ascontiguousarray(vo.view(np.float64))
+    w = np.ascontiguousarray(np.broadcast_to(weight, prob.vis_shape()), np.float64)
+    acc = np.zeros(prob.offsets_shape()[:3] + (3,))
+    _check(lib.oracle_scale_gradient(prob.ref, _dp(o), _dp(vo2), _dp(w), _dp(acc)), "scale_gradient")
+    return acc
+
+
+def scale_step(acc3, gain, scale):
+    """Returns (new scales, not_updated, max_step [n_int])."""
+    lib = _load()
+    acc3 = np.ascontiguousarray(acc3, np.float64)
+    n_int, n_pol, n_ant = acc3.shape[:3]
+    s = np.array(scale, dtype=np.float64, copy=True, order="C")
+    nu = np.zeros((n_int, n_pol, n_ant), np.int32)
+    mx = np.zeros(n_int)
+    _check(lib.oracle_scale_step(n_int, n_pol, n_ant, _dp(acc3), float(gain), _dp(s), _ip(nu), _dp(mx)),
+           "scale_step")
+    return s, nu, mx
 
 
 def solve(prob: Problem, vis_obs, weight, offsets0, gain=0.5, n_max=10, tol_rad=None):

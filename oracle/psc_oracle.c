@@ -50,6 +50,11 @@
  *    angle chi: p_sky = R(chi) (offset + squint), R = [[cos, -sin],
  *    [sin, cos]]; derivatives are taken with respect to the mount-frame
  *    offsets.  The paper solves in this frame for its VLA data (Sec. 4).
+ *  - An optional beam-width scale sigma per (interval, pol, antenna), a
+ *    generalised antenna parameter besides the offsets (Eq. DA with a_i =
+ *    sigma_i; Sec. 5.3 treats the shape of the beam as parameters solved by
+ *    the same machinery): the antenna's pattern is E0(d / sigma), d the
+ *    displacement from its beam centre; sigma = 1 is the nominal beam.
  *  - A measured aperture (illum 2) is a real, even illumination on a square
  *    grid of cells across the dish; its far-field pattern is the aperture's
  *    Fourier transform (Sec. 1 and Sec. 3: the pattern of a dish follows
@@ -165,6 +170,26 @@ static void efp_problem(const orc_problem* p, int c, double dl, double dm, doubl
         oracle_efp(p->illum, p->dish_diam_m, p->gauss_sigma_ld, p->freq_hz[c], dl, dm, out3);
 }
 
+/* The pattern widened by sigma, E(d) = E0(d / sigma), at displacement d
+ * from the beam centre: out4 = (E, dE/dc_l, dE/dc_m, dE/dsigma).  The centre
+ * derivatives are E0's at d / sigma divided by sigma, and
+ * dE/dsigma = -(d / sigma^2) . grad E0 = (d . dE/dc) / sigma. */
+static void efp_scaled(const orc_problem* p, int c, double sigma, double dl, double dm, double* out4)
+{
+    double e[3];
+    efp_problem(p, c, dl / sigma, dm / sigma, e);
+    out4[0] = e[0];
+    out4[1] = e[1] / sigma;
+    out4[2] = e[2] / sigma;
+    out4[3] = (dl * out4[1] + dm * out4[2]) / sigma;
+}
+
+/* sigma of antenna a, pol pol in one interval's scales (null: 1) */
+static double sigma_of(const orc_problem* p, const double* scl_int, int pol, int a)
+{
+    return scl_int ? scl_int[pol * p->n_ant + a] : 1.0;
+}
+
 static double hpbw_rad(double lambda, double dish)
 {
     return 1.02899 * lambda / dish;
@@ -223,12 +248,14 @@ void oracle_snap_uv(const orc_problem* p, int64_t row, int chan, double* uv_out)
 
 /*
  * Beam values of every antenna towards every source, for one interval:
- * tab[((pol*n_ant + a)*n_chan + c)*n_src + s][3] = (E, dE/dl_a, dE/dm_a).
+ * tab[((pol*n_ant + a)*n_chan + c)*n_src + s][4] = (E, dE/dl_a, dE/dm_a,
+ * dE/dsigma_a).
  */
-static double* beam_table(const orc_problem* p, const double* offs_int /* [n_pol][n_ant][2] */)
+static double* beam_table(const orc_problem* p, const double* offs_int /* [n_pol][n_ant][2] */,
+                          const double* scl_int /* nullable [n_pol][n_ant] */)
 {
     size_t n = (size_t)p->n_pol * p->n_ant * p->n_chan * p->n_src;
-    double* tab = (double*)malloc(n * 3 * sizeof(double));
+    double* tab = (double*)malloc(n * 4 * sizeof(double));
     if (!tab) return NULL;
     for (int pol = 0; pol < p->n_pol; ++pol) {
         double sgn = (pol == 0) ? 1.0 : -1.0;
@@ -239,9 +266,10 @@ static double* beam_table(const orc_problem* p, const double* offs_int /* [n_pol
                 double sq = sgn * p->squint_frac * hpbw_rad(lambda, p->dish_diam_m);
                 double pl = offs_int[(pol * p->n_ant + a) * 2 + 0] + sq;
                 double pm = offs_int[(pol * p->n_ant + a) * 2 + 1];
+                double sig = sigma_of(p, scl_int, pol, a);
                 for (int s = 0; s < p->n_src; ++s) {
-                    double* t = tab + 3 * ((((size_t)pol * p->n_ant + a) * p->n_chan + c) * p->n_src + s);
-                    efp_problem(p, c, p->src_l[s] - pl, p->src_m[s] - pm, t);
+                    double* t = tab + 4 * ((((size_t)pol * p->n_ant + a) * p->n_chan + c) * p->n_src + s);
+                    efp_scaled(p, c, sig, p->src_l[s] - pl, p->src_m[s] - pm, t);
                 }
             }
         }
@@ -254,11 +282,13 @@ static double* beam_table(const orc_problem* p, const double* offs_int /* [n_pol
  * given in the antenna frame: the offset plus squint q is carried onto the
  * sky by the row's parallactic angle chi, p = R(chi) q with
  * R = [[cos, -sin], [sin, cos]], and the derivatives are taken with respect
- * to q, dE/dq = R^T dE/dp.  t[3 s .. 3 s + 2] = (E, dE/dq_l, dE/dq_m).
+ * to q, dE/dq = R^T dE/dp.  t[4 s .. 4 s + 3] = (E, dE/dq_l, dE/dq_m,
+ * dE/dsigma).
  */
-static void beam_row(const orc_problem* p, const double* offs_int, int pol, int a, int c, double chi,
-                     double* t)
+static void beam_row(const orc_problem* p, const double* offs_int, const double* scl_int, int pol, int a,
+                     int c, double chi, double* t)
 {
+    double sig = sigma_of(p, scl_int, pol, a);
     double lambda = ORC_C_LIGHT / p->freq_hz[c];
     double sq = (pol == 0 ? 1.0 : -1.0) * p->squint_frac * hpbw_rad(lambda, p->dish_diam_m);
     double ql = offs_int[(pol * p->n_ant + a) * 2 + 0] + sq;
@@ -271,42 +301,44 @@ static void beam_row(const orc_problem* p, const double* offs_int, int pol, int 
         for (int s = 0; s < p->n_src; ++s) {
             double dl = cs * p->src_l[s] + sn * p->src_m[s] - ql;
             double dm = -sn * p->src_l[s] + cs * p->src_m[s] - qm;
-            efp_problem(p, c, dl, dm, t + 3 * s);
+            efp_scaled(p, c, sig, dl, dm, t + 4 * s);
         }
         return;
     }
     double pl = cs * ql - sn * qm, pm = sn * ql + cs * qm;
     for (int s = 0; s < p->n_src; ++s) {
-        double e[3];
-        oracle_efp(p->illum, p->dish_diam_m, p->gauss_sigma_ld, p->freq_hz[c], p->src_l[s] - pl,
-                   p->src_m[s] - pm, e);
-        t[3 * s] = e[0];
-        t[3 * s + 1] = cs * e[1] + sn * e[2];
-        t[3 * s + 2] = -sn * e[1] + cs * e[2];
+        double e[4];
+        efp_scaled(p, c, sig, p->src_l[s] - pl, p->src_m[s] - pm, e);
+        t[4 * s] = e[0];
+        t[4 * s + 1] = cs * e[1] + sn * e[2];
+        t[4 * s + 2] = -sn * e[1] + cs * e[2];
+        t[4 * s + 3] = e[3];
     }
 }
 
 /*
- * Model visibility and its four offset derivatives for one (row, chan, pol)
- * from the two antennas' beam values ti, tj ([n_src][3] each):
- * out[0..1] = V, out[2..9] = dV/dl_i, dV/dm_i, dV/dl_j, dV/dm_j (re, im each).
+ * Model visibility and its derivatives for one (row, chan, pol) from the two
+ * antennas' beam values ti, tj ([n_src][4] each): out[0..1] = V,
+ * out[2..9] = dV/dl_i, dV/dm_i, dV/dl_j, dV/dm_j, out[10..13] =
+ * dV/dsigma_i, dV/dsigma_j (re, im each).
  */
 static void vis_from_beams(const orc_problem* p, const double* ti, const double* tj, double u, double v,
                            double w, double* out, int want_grad)
 {
-    double acc[10] = {0};
+    double acc[14] = {0};
     for (int s = 0; s < p->n_src; ++s) {
         double ph = me_phase(u, v, w, p->src_l[s], p->src_m[s]);
         double cr = cos(ph), ci = sin(ph);
         double fi = p->src_flux[s];
-        double ei = ti[3 * s], ej = tj[3 * s];
+        double ei = ti[4 * s], ej = tj[4 * s];
         double a0 = fi * ei * ej;
         acc[0] += a0 * cr;
         acc[1] += a0 * ci;
         if (want_grad) {
-            double d[4] = {fi * ti[3 * s + 1] * ej, fi * ti[3 * s + 2] * ej,
-                           fi * ei * tj[3 * s + 1], fi * ei * tj[3 * s + 2]};
-            for (int k = 0; k < 4; ++k) {
+            double d[6] = {fi * ti[4 * s + 1] * ej, fi * ti[4 * s + 2] * ej,
+                           fi * ei * tj[4 * s + 1], fi * ei * tj[4 * s + 2],
+                           fi * ti[4 * s + 3] * ej, fi * ei * tj[4 * s + 3]};
+            for (int k = 0; k < 6; ++k) {
                 acc[2 + 2 * k] += d[k] * cr;
                 acc[3 + 2 * k] += d[k] * ci;
             }
@@ -319,22 +351,23 @@ static void vis_from_beams(const orc_problem* p, const double* ti, const double*
 static void vis_one(const orc_problem* p, const double* tab, int pol, int ai, int aj, int c,
                     double u, double v, double w, double* out, int want_grad)
 {
-    const double* ti = tab + 3 * ((((size_t)pol * p->n_ant + ai) * p->n_chan + c) * p->n_src);
-    const double* tj = tab + 3 * ((((size_t)pol * p->n_ant + aj) * p->n_chan + c) * p->n_src);
+    const double* ti = tab + 4 * ((((size_t)pol * p->n_ant + ai) * p->n_chan + c) * p->n_src);
+    const double* tj = tab + 4 * ((((size_t)pol * p->n_ant + aj) * p->n_chan + c) * p->n_src);
     vis_from_beams(p, ti, tj, u, v, w, out, want_grad);
 }
 
 /*
  * One (row, chan, pol): from the interval's beam table, or, when the problem
  * carries parallactic angles, from beams evaluated for this row into the
- * caller's scratch bi, bj ([n_src][3] each).
+ * caller's scratch bi, bj ([n_src][4] each).  out has 14 entries.
  */
-static void vis_row(const orc_problem* p, const double* tab, const double* offs_int, int64_t r, int pol,
-                    int c, double u, double v, double w, double* bi, double* bj, double* out, int want_grad)
+static void vis_row(const orc_problem* p, const double* tab, const double* offs_int, const double* scl_int,
+                    int64_t r, int pol, int c, double u, double v, double w, double* bi, double* bj, double* out,
+                    int want_grad)
 {
     if (p->par_angle) {
-        beam_row(p, offs_int, pol, p->ant1[r], c, p->par_angle[r], bi);
-        beam_row(p, offs_int, pol, p->ant2[r], c, p->par_angle[r], bj);
+        beam_row(p, offs_int, scl_int, pol, p->ant1[r], c, p->par_angle[r], bi);
+        beam_row(p, offs_int, scl_int, pol, p->ant2[r], c, p->par_angle[r], bj);
         vis_from_beams(p, bi, bj, u, v, w, out, want_grad);
     } else {
         vis_one(p, tab, pol, p->ant1[r], p->ant2[r], c, u, v, w, out, want_grad);
@@ -355,6 +388,9 @@ static int check_problem(const orc_problem* p)
             return -1;
     }
     if (p->illum < 0 || p->illum > 2) return -1;
+    if (p->beam_scale)
+        for (size_t k = 0; k < (size_t)p->n_int * p->n_pol * p->n_ant; ++k)
+            if (!(p->beam_scale[k] > 0.0) || !isfinite(p->beam_scale[k])) return -1;
     if (p->illum == 2) {
         /* a real, even aperture with a non-zero on-axis response */
         int n = p->aperture_n;
@@ -371,37 +407,129 @@ static int check_problem(const orc_problem* p)
     return 0;
 }
 
-int oracle_predict(const orc_problem* p, const double* offsets, double* vis_out, double* dvis_out)
+/* Predict, with the offset derivatives [n_vis][4][re, im] in dvis_out and the
+ * beam-scale derivatives [n_vis][2][re, im] (antenna i, then j) in dscale_out
+ * when they are not NULL. */
+static int predict_impl(const orc_problem* p, const double* offsets, double* vis_out, double* dvis_out,
+                        double* dscale_out)
 {
     if (check_problem(p)) return -1;
     for (int s = 0; s < p->n_int; ++s) {
         int64_t r0 = p->int_row_ptr[s], r1 = p->int_row_ptr[s + 1];
         if (r0 == r1) continue; /* an empty interval predicts nothing */
         const double* offs_int = offsets + (size_t)s * p->n_pol * p->n_ant * 2;
-        double* tab = p->par_angle ? NULL : beam_table(p, offs_int);
+        const double* scl_int = p->beam_scale ? p->beam_scale + (size_t)s * p->n_pol * p->n_ant : NULL;
+        double* tab = p->par_angle ? NULL : beam_table(p, offs_int, scl_int);
         if (!p->par_angle && !tab) return -2;
 #pragma omp parallel
         {
-            double* bi = (double*)malloc(sizeof(double) * 6 * (p->n_src + 1));
-            double* bj = bi + 3 * (p->n_src + 1);
+            double* bi = (double*)malloc(sizeof(double) * 8 * (p->n_src + 1));
+            double* bj = bi + 4 * (p->n_src + 1);
 #pragma omp for schedule(dynamic, 16)
             for (int64_t r = r0; r < r1; ++r) {
                 for (int c = 0; c < p->n_chan; ++c) {
                     double u, v;
                     row_uv(p, r, c, &u, &v);
                     for (int pol = 0; pol < p->n_pol; ++pol) {
-                        double out[10];
-                        vis_row(p, tab, offs_int, r, pol, c, u, v, row_w(p, r, c), bi, bj, out, dvis_out != NULL);
+                        double out[14];
+                        vis_row(p, tab, offs_int, scl_int, r, pol, c, u, v, row_w(p, r, c), bi, bj, out,
+                                dvis_out != NULL || dscale_out != NULL);
                         size_t idx = ((size_t)r * p->n_chan + c) * p->n_pol + pol;
                         vis_out[2 * idx] = out[0];
                         vis_out[2 * idx + 1] = out[1];
                         if (dvis_out) memcpy(dvis_out + 8 * idx, out + 2, 8 * sizeof(double));
+                        if (dscale_out) memcpy(dscale_out + 4 * idx, out + 10, 4 * sizeof(double));
                     }
                 }
             }
             free(bi);
         }
         free(tab);
+    }
+    return 0;
+}
+
+int oracle_predict(const orc_problem* p, const double* offsets, double* vis_out, double* dvis_out)
+{
+    return predict_impl(p, offsets, vis_out, dvis_out, NULL);
+}
+
+int oracle_predict_scale(const orc_problem* p, const double* offsets, double* vis_out, double* dscale_out)
+{
+    return predict_impl(p, offsets, vis_out, NULL, dscale_out);
+}
+
+/*
+ * The sums of Eq. DCHIDD for the beam-width scale, a generalised antenna
+ * parameter (Eq. DA with a_i = sigma_i): per (interval, pol, antenna)
+ * acc3[k], k = chi, g_sigma = sum Re(conj(R) w dV/dsigma_a),
+ * H_sigma = sum w |dV/dsigma_a|^2, over both ends of every baseline.
+ */
+int oracle_scale_gradient(const orc_problem* p, const double* offsets, const double* vis_obs,
+                          const double* weight, double* acc3)
+{
+    if (check_problem(p)) return -1;
+    size_t n_vis = (size_t)p->n_row * p->n_chan * p->n_pol;
+    double* vm = (double*)malloc((n_vis ? n_vis : 1) * 2 * sizeof(double));
+    double* ds = (double*)malloc((n_vis ? n_vis : 1) * 4 * sizeof(double));
+    if (!vm || !ds) {
+        free(vm);
+        free(ds);
+        return -2;
+    }
+    int rc = predict_impl(p, offsets, vm, NULL, ds);
+    memset(acc3, 0, (size_t)p->n_int * p->n_pol * p->n_ant * 3 * sizeof(double));
+    for (int s = 0; s < p->n_int && rc == 0; ++s) {
+        for (int64_t r = p->int_row_ptr[s]; r < p->int_row_ptr[s + 1]; ++r) {
+            for (int c = 0; c < p->n_chan; ++c) {
+                for (int pol = 0; pol < p->n_pol; ++pol) {
+                    size_t idx = ((size_t)r * p->n_chan + c) * p->n_pol + pol;
+                    double w = weight[idx];
+                    double rr = vis_obs[2 * idx] - vm[2 * idx];
+                    double ri = vis_obs[2 * idx + 1] - vm[2 * idx + 1];
+                    for (int end = 0; end < 2; ++end) {
+                        int a = end ? p->ant2[r] : p->ant1[r];
+                        const double* d = ds + 4 * idx + 2 * end;
+                        double* t = acc3 + (((size_t)s * p->n_pol + pol) * p->n_ant + a) * 3;
+                        t[0] += w * (rr * rr + ri * ri);
+                        t[1] += w * (rr * d[0] + ri * d[1]);
+                        t[2] += w * (d[0] * d[0] + d[1] * d[1]);
+                    }
+                }
+            }
+        }
+    }
+    free(vm);
+    free(ds);
+    return rc;
+}
+
+/*
+ * Damped Gauss-Newton step of the beam-width scale per (interval, pol,
+ * antenna): sigma += gamma g_sigma / H_sigma, as the offsets' update with
+ * one parameter.  An antenna with H_sigma <= 0, non-finite sums, or a step
+ * that would leave sigma non-positive is left as is and marked in
+ * not_updated (nullable).  max_step_out[s] (nullable) receives the largest
+ * |delta sigma| of interval s.
+ */
+int oracle_scale_step(int n_int, int n_pol, int n_ant, const double* acc3, double gain, double* scale_io,
+                      int32_t* not_updated, double* max_step_out)
+{
+    if (n_int < 0 || n_pol < 1 || n_ant < 1 || !(gain > 0.0)) return -1;
+    for (int s = 0; s < n_int; ++s) {
+        double mx = 0.0;
+        for (int k = 0; k < n_pol * n_ant; ++k) {
+            size_t i = (size_t)s * n_pol * n_ant + k;
+            double g = acc3[3 * i + 1], h = acc3[3 * i + 2];
+            double nxt = scale_io[i] + gain * g / h;
+            int ok = h > 0.0 && isfinite(g) && isfinite(h) && isfinite(nxt) && nxt > 0.0;
+            if (ok) {
+                mx = fmax(mx, fabs(nxt - scale_io[i]));
+                scale_io[i] = nxt;
+            }
+            if (not_updated) not_updated[i] = !ok;
+        }
+        if (max_step_out) max_step_out[s] = mx;
     }
     return 0;
 }
@@ -428,7 +556,8 @@ int oracle_gradient(const orc_problem* p, const double* offsets, const double* v
         int64_t r0 = p->int_row_ptr[s], r1 = p->int_row_ptr[s + 1];
         if (r0 == r1) continue; /* no samples: every sum of the interval stays 0 */
         const double* offs_int = offsets + (size_t)s * p->n_pol * p->n_ant * 2;
-        double* tab = p->par_angle ? NULL : beam_table(p, offs_int);
+        const double* scl_int = p->beam_scale ? p->beam_scale + (size_t)s * p->n_pol * p->n_ant : NULL;
+        double* tab = p->par_angle ? NULL : beam_table(p, offs_int, scl_int);
         if (!p->par_angle && !tab) {
             free(part);
             return -2;
@@ -441,8 +570,8 @@ int oracle_gradient(const orc_problem* p, const double* offsets, const double* v
             tid = omp_get_thread_num();
 #endif
             double* mine = part + (size_t)tid * per;
-            double* bi = (double*)malloc(sizeof(double) * 6 * (p->n_src + 1));
-            double* bj = bi + 3 * (p->n_src + 1);
+            double* bi = (double*)malloc(sizeof(double) * 8 * (p->n_src + 1));
+            double* bj = bi + 4 * (p->n_src + 1);
 #pragma omp for schedule(static)
             for (int64_t r = r0; r < r1; ++r) {
                 int ai = p->ant1[r], aj = p->ant2[r];
@@ -451,8 +580,8 @@ int oracle_gradient(const orc_problem* p, const double* offsets, const double* v
                     row_uv(p, r, c, &u, &v);
                     for (int pol = 0; pol < p->n_pol; ++pol) {
                         size_t idx = ((size_t)r * p->n_chan + c) * p->n_pol + pol;
-                        double out[10];
-                        vis_row(p, tab, offs_int, r, pol, c, u, v, row_w(p, r, c), bi, bj, out, 1);
+                        double out[14];
+                        vis_row(p, tab, offs_int, scl_int, r, pol, c, u, v, row_w(p, r, c), bi, bj, out, 1);
                         if (vis_model_out) {
                             vis_model_out[2 * idx] = out[0];
                             vis_model_out[2 * idx + 1] = out[1];
@@ -498,20 +627,20 @@ int oracle_gradient(const orc_problem* p, const double* offsets, const double* v
 /* The pattern of antenna a at sky position (l, m) in a row with parallactic
  * angle chi, for offsets in the mount frame: the beam centre on the sky is
  * R(chi) (q + squint), as in beam_row. */
-static double beam_at_row(const orc_problem* p, const double* offs_int, int pol, int a, int c, double chi,
-                          double l, double m)
+static double beam_at_row(const orc_problem* p, const double* offs_int, const double* scl_int, int pol, int a,
+                          int c, double chi, double l, double m)
 {
+    double sig = sigma_of(p, scl_int, pol, a);
     double lambda = ORC_C_LIGHT / p->freq_hz[c];
     double sq = (pol == 0 ? 1.0 : -1.0) * p->squint_frac * hpbw_rad(lambda, p->dish_diam_m);
     double ql = offs_int[(pol * p->n_ant + a) * 2 + 0] + sq;
     double qm = offs_int[(pol * p->n_ant + a) * 2 + 1];
     double cs = cos(chi), sn = sin(chi);
-    double e[3];
+    double e[4];
     if (p->illum == 2)
-        efp_problem(p, c, cs * l + sn * m - ql, -sn * l + cs * m - qm, e);
+        efp_scaled(p, c, sig, cs * l + sn * m - ql, -sn * l + cs * m - qm, e);
     else
-        oracle_efp(p->illum, p->dish_diam_m, p->gauss_sigma_ld, p->freq_hz[c], l - (cs * ql - sn * qm),
-                   m - (sn * ql + cs * qm), e);
+        efp_scaled(p, c, sig, l - (cs * ql - sn * qm), m - (sn * ql + cs * qm), e);
     return e[0];
 }
 
@@ -543,8 +672,9 @@ int oracle_image_gradient(const orc_problem* p, const double* offsets, const dou
         int64_t r0 = p->int_row_ptr[s], r1 = p->int_row_ptr[s + 1];
         if (r0 == r1) continue;
         const double* offs_int = offsets + (size_t)s * p->n_pol * p->n_ant * 2;
+        const double* scl_int = p->beam_scale ? p->beam_scale + (size_t)s * p->n_pol * p->n_ant : NULL;
         /* sky frame: every row of the interval sees the same beams */
-        double* tab = p->par_angle ? NULL : beam_table(&q, offs_int);
+        double* tab = p->par_angle ? NULL : beam_table(&q, offs_int, scl_int);
         if (!p->par_angle && !tab) {
             rc = -2;
             break;
@@ -563,11 +693,13 @@ int oracle_image_gradient(const orc_problem* p, const double* offsets, const dou
                         size_t idx = ((size_t)r * p->n_chan + c) * p->n_pol + pol;
                         double ei, ej;
                         if (p->par_angle) {
-                            ei = beam_at_row(p, offs_int, pol, ai, c, p->par_angle[r], pix_l[k], pix_m[k]);
-                            ej = beam_at_row(p, offs_int, pol, aj, c, p->par_angle[r], pix_l[k], pix_m[k]);
+                            ei = beam_at_row(p, offs_int, scl_int, pol, ai, c, p->par_angle[r], pix_l[k],
+                                             pix_m[k]);
+                            ej = beam_at_row(p, offs_int, scl_int, pol, aj, c, p->par_angle[r], pix_l[k],
+                                             pix_m[k]);
                         } else {
-                            ei = tab[3 * ((((size_t)pol * p->n_ant + ai) * p->n_chan + c) * n_pix + k)];
-                            ej = tab[3 * ((((size_t)pol * p->n_ant + aj) * p->n_chan + c) * n_pix + k)];
+                            ei = tab[4 * ((((size_t)pol * p->n_ant + ai) * p->n_chan + c) * n_pix + k)];
+                            ej = tab[4 * ((((size_t)pol * p->n_ant + aj) * p->n_chan + c) * n_pix + k)];
                         }
                         double rr = vis_obs[2 * idx] - vm[2 * idx];
                         double ri = vis_obs[2 * idx + 1] - vm[2 * idx + 1];

@@ -34,6 +34,9 @@ typedef struct {
      * the mount frame's l axis), real and even: A[a][b] = A[n-1-a][n-1-b] */
     int32_t aperture_n;
     const double* aperture;
+    /* nullable [n_int][n_pol][n_ant]: beam-width scale sigma > 0 of each
+     * antenna, E = E0(d / sigma) (null: 1) */
+    const double* beam_scale;
 } orc_problem;
 
 void oracle_efp(int illum, double dish_diam_m, double gauss_sigma_ld, double freq_hz,
@@ -43,6 +46,11 @@ void oracle_efp_aperture(int aperture_n, const double* aperture, double dish_dia
 double oracle_hpbw(double freq_hz, double dish_diam_m);
 void oracle_snap_uv(const orc_problem* p, int64_t row, int chan, double* uv_out);
 int oracle_predict(const orc_problem* p, const double* offsets, double* vis_out, double* dvis_out);
+int oracle_predict_scale(const orc_problem* p, const double* offsets, double* vis_out, double* dscale_out);
+int oracle_scale_gradient(const orc_problem* p, const double* offsets, const double* vis_obs,
+                          const double* weight, double* acc3);
+int oracle_scale_step(int n_int, int n_pol, int n_ant, const double* acc3, double gain, double* scale_io,
+                      int32_t* not_updated, double* max_step_out);
 int oracle_gradient(const orc_problem* p, const double* offsets, const double* vis_obs,
                     const double* weight, double* acc, double* vis_model_out);
 int oracle_image_gradient(const orc_problem* p, const double* offsets, const double* vis_obs,
