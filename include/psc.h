@@ -329,6 +329,54 @@ PSC_API psc_status psc_tune(psc_ctx* ctx, psc_obs* obs, const double* offsets_de
                             const void* vis_obs_dev, const float* weight_dev, int32_t repeats,
                             double* times_us_out, void* stream);
 
+/*
+ * Beam-width scale, a generalised antenna parameter (Eq. DA holds for any
+ * antenna parameter a_i; Sec. 5.3 solves the beam's shape with the same
+ * machinery as the offsets).  Antenna a's pattern becomes E0(d / sigma_a),
+ * d its displacement from the beam centre: sigma > 1 widens the beam.
+ *
+ * psc_set_beam_scale (sync): copies scale_dev, [n_int][n_pol][n_ant]
+ * float64 (device, borrowed), into the observation; every later predict,
+ * gradient, adjoint, solve and image gradient uses it.  Values must be
+ * positive and finite (PSC_E_ARG, the observation unchanged).  The scales
+ * enter through per-sample image-plane products, so the observation then
+ * degrids in the window form (psc_set_degrid refuses the table forms) and
+ * rows without a parallactic angle take angle zero.  A null scale_dev drops
+ * the scales (sigma = 1 again; the window form stays).  A captured solve
+ * graph is discarded.
+ * psc_get_beam_scale (async): copies the observation's scales to
+ * scale_out_dev; PSC_E_STATE when none are set.
+ */
+PSC_API psc_status psc_set_beam_scale(psc_ctx* ctx, psc_obs* obs, const double* scale_dev, void* stream);
+PSC_API psc_status psc_get_beam_scale(psc_ctx* ctx, const psc_obs* obs, double* scale_out_dev, void* stream);
+
+/*
+ * Sums of Eq. DCHIDD for the beam-width scales (async): per (interval, pol,
+ * antenna), over both ends of every baseline,
+ *   acc_out_dev[..][3] = chi = sum w |R|^2, g = sum Re(conj(R) w dV/dsigma_a),
+ *                        H = sum w |dV/dsigma_a|^2,
+ * with R = V^Obs - V^M at the given offsets and the observation's scales;
+ * float64 sums of float32 terms, like psc_gradient.  Arguments as for
+ * psc_gradient.  PSC_E_STATE without scales set.
+ */
+PSC_API psc_status psc_scale_gradient(psc_ctx* ctx, psc_obs* obs, const double* offsets_dev,
+                                      const void* vis_obs_dev, const float* weight_dev, double* acc_out_dev,
+                                      void* stream);
+
+/*
+ * Damped update of the observation's scales (async): sigma += gain g / H per
+ * (interval, pol, antenna) from acc_dev ([n_int][n_pol][n_ant][3], from
+ * psc_scale_gradient), 0 < gain <= 1 (the loop gain of Eq. SelfCal; all
+ * antennas move together, as for the offsets, and gain 1 makes the two ends
+ * of a baseline overshoot together).  Antennas with H <= 0, non-finite sums,
+ * or a step that would leave sigma non-positive keep their scale and get
+ * not_updated = 1.
+ *  not_updated_dev  nullable [n_int][n_pol][n_ant] int32
+ *  max_step_out_dev nullable [n_int] float64: largest |delta sigma| per interval
+ */
+PSC_API psc_status psc_scale_step(psc_ctx* ctx, psc_obs* obs, const double* acc_dev, double gain,
+                                  int32_t* not_updated_dev, double* max_step_out_dev, void* stream);
+
 /* Execution forms of psc_solve. */
 #define PSC_SOLVE_PLAIN 0    /* host loop over intervals, one launch set per interval */
 #define PSC_SOLVE_BATCHED 1  /* every interval in one launch set per iteration */

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpsc.so")
-SOURCES = ["psc_api.hip", "psc_kernels.hip", "psc_window.hip", "psc_grid.hip", "psc_aperture.hip"]
+SOURCES = ["psc_api.hip", "psc_kernels.hip", "psc_window.hip", "psc_grid.hip", "psc_aperture.hip", "psc_scale.hip"]
 ARCH = os.environ.get("PSC_OFFLOAD_ARCH", "gfx950")
 
 

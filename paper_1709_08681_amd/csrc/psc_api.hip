@@ -51,6 +51,7 @@ struct psc_obs {
     int32_t n_tab = 0;
     double inv_dx = 0;
     float4* ap_tab = nullptr;  // measured aperture: pattern table [ap_n][ap_n]
+    double* scale = nullptr;   // beam-width scales [n_int][n_pol][n_ant] (null: all 1)
     int32_t ap_n = 0;
     double ap_c = 0, ap_step = 0;
     double* partials = nullptr;  // [n_items][n_pol][12]
@@ -341,6 +342,7 @@ PSC_API psc_status psc_obs_destroy(psc_obs* obs)
     dfree(obs->w_m);
     dfree(obs->airy);
     dfree(obs->ap_tab);
+    dfree(obs->scale);
     dfree(obs->partials);
     dfree(obs->acc);
     dfree(obs->max_step);
@@ -676,6 +678,7 @@ ItemArgs item_args(psc_ctx* ctx, psc_obs* obs, const double* offsets, int item_b
     a.ap_n = obs->ap_n;
     a.ap_c = (float)obs->ap_c;
     a.ap_inv_step = obs->ap_step > 0 ? (float)(1.0 / obs->ap_step) : 0.f;
+    a.scale = obs->scale;
     a.partials = obs->partials;
     a.done = done;
     a.use_mfma = obs->degrid == PSC_DEGRID_MFMA ? 1 : 0;
@@ -945,6 +948,8 @@ PSC_API psc_status psc_set_degrid(psc_obs* obs, int32_t variant)
                     "mount-frame offsets (parallactic angles) degrid in the window form only");
     if (obs->w_m && variant != PSC_DEGRID_WINDOW)
         return fail(obs->ctx, PSC_E_UNSUPPORTED, "the w-term degrids in the window form only");
+    if (obs->scale && variant != PSC_DEGRID_WINDOW)
+        return fail(obs->ctx, PSC_E_UNSUPPORTED, "beam-width scales degrid in the window form only");
     if (obs->graph) {  // a captured solve graph holds the old kernels
         (void)hipGraphExecDestroy(obs->graph);
         obs->graph = nullptr;
@@ -957,6 +962,89 @@ PSC_API psc_status psc_get_degrid(const psc_obs* obs, int32_t* variant)
 {
     if (!obs || !variant) return fail(nullptr, PSC_E_ARG, "null argument");
     *variant = obs->degrid;
+    return PSC_OK;
+}
+
+PSC_API psc_status psc_set_beam_scale(psc_ctx* ctx, psc_obs* obs, const double* scale_dev, void* stream)
+{
+    if (!ctx) return fail(nullptr, PSC_E_ARG, "null context");
+    ctx->err.clear();
+    if (!obs || obs->ctx != ctx) return fail(ctx, PSC_E_ARG, "observation missing or from another context");
+    PSC_HIP(ctx, hipSetDevice(ctx->cfg.device));
+    hipStream_t st = (hipStream_t)stream;
+    if (!scale_dev) {  // back to the nominal beams
+        if (obs->scale) {
+            PSC_HIP(ctx, hipStreamSynchronize(st));
+            dfree(obs->scale);
+        }
+        return PSC_OK;
+    }
+    const size_t n = (size_t)obs->n_int * obs->n_pol * obs->n_ant;
+    std::vector<double> h(n);
+    PSC_HIP(ctx, hipMemcpyAsync(h.data(), scale_dev, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    PSC_HIP(ctx, hipStreamSynchronize(st));
+    for (size_t k = 0; k < n; ++k)
+        if (!(h[k] > 0.0) || !isfinite(h[k])) return fail(ctx, PSC_E_ARG, "beam scales must be positive and finite");
+    // the scales enter through the per-sample image-plane products: rows
+    // without a parallactic angle take angle zero
+    if (!obs->par_angle) {
+        const size_t nr = obs->n_row > 0 ? (size_t)obs->n_row : 1;
+        PSC_HIP(ctx, dmalloc(&obs->par_angle, nr));
+        PSC_HIP(ctx, hipMemsetAsync(obs->par_angle, 0, sizeof(double) * nr, st));
+    }
+    if (!obs->scale) PSC_HIP(ctx, dmalloc(&obs->scale, n));
+    PSC_HIP(ctx, hipMemcpyAsync(obs->scale, scale_dev, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    PSC_HIP(ctx, hipStreamSynchronize(st));
+    obs->degrid = PSC_DEGRID_WINDOW;
+    if (obs->graph) {  // a captured solve graph holds the old kernels
+        (void)hipGraphExecDestroy(obs->graph);
+        obs->graph = nullptr;
+    }
+    return PSC_OK;
+}
+
+PSC_API psc_status psc_get_beam_scale(psc_ctx* ctx, const psc_obs* obs, double* scale_out_dev, void* stream)
+{
+    if (!ctx) return fail(nullptr, PSC_E_ARG, "null context");
+    ctx->err.clear();
+    if (!obs || obs->ctx != ctx || !scale_out_dev) return fail(ctx, PSC_E_ARG, "null argument");
+    if (!obs->scale) return fail(ctx, PSC_E_STATE, "no beam scales set (psc_set_beam_scale)");
+    PSC_HIP(ctx, hipSetDevice(ctx->cfg.device));
+    const size_t n = (size_t)obs->n_int * obs->n_pol * obs->n_ant;
+    PSC_HIP(ctx, hipMemcpyAsync(scale_out_dev, obs->scale, sizeof(double) * n, hipMemcpyDeviceToDevice,
+                                (hipStream_t)stream));
+    return PSC_OK;
+}
+
+PSC_API psc_status psc_scale_gradient(psc_ctx* ctx, psc_obs* obs, const double* offsets_dev,
+                                      const void* vis_obs_dev, const float* weight_dev, double* acc_out_dev,
+                                      void* stream)
+{
+    psc_status st = check_call(ctx, obs, offsets_dev);
+    if (st != PSC_OK) return st;
+    if (!acc_out_dev || ((!vis_obs_dev || !weight_dev) && obs->n_vis > 0))
+        return fail(ctx, PSC_E_ARG, "null data or output");
+    if (!obs->scale) return fail(ctx, PSC_E_STATE, "no beam scales set (psc_set_beam_scale)");
+    hipStream_t s = (hipStream_t)stream;
+    ItemArgs a = item_args(ctx, obs, offsets_dev, 0, (int)obs->n_items, nullptr);
+    a.vis_in = (const float2*)vis_obs_dev;
+    a.weight = weight_dev;
+    PSC_HIP(ctx, launch_win(kScale, ctx->s, a, s));
+    PSC_HIP(ctx, launch_reduce(6, reduce_args(obs, 0, obs->n_int, acc_out_dev, nullptr), s));
+    return PSC_OK;
+}
+
+PSC_API psc_status psc_scale_step(psc_ctx* ctx, psc_obs* obs, const double* acc_dev, double gain,
+                                  int32_t* not_updated_dev, double* max_step_out_dev, void* stream)
+{
+    if (!ctx) return fail(nullptr, PSC_E_ARG, "null context");
+    ctx->err.clear();
+    if (!obs || obs->ctx != ctx || !acc_dev) return fail(ctx, PSC_E_ARG, "null argument");
+    if (!(gain > 0.0) || !(gain <= 1.0)) return fail(ctx, PSC_E_ARG, "gain must be in (0, 1]");
+    if (!obs->scale) return fail(ctx, PSC_E_STATE, "no beam scales set (psc_set_beam_scale)");
+    PSC_HIP(ctx, hipSetDevice(ctx->cfg.device));
+    PSC_HIP(ctx, launch_scale_step(obs->n_int, obs->n_pol, obs->n_ant, acc_dev, gain, obs->scale, not_updated_dev,
+                                   max_step_out_dev, (hipStream_t)stream));
     return PSC_OK;
 }
 

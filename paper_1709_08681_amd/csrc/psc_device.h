@@ -291,19 +291,40 @@ __device__ __forceinline__ void efp_ap(const ItemArgs& a, float s, float cs, flo
     }
 }
 
+// Beam constants of one antenna at an item's channel, its width scale sigma
+// applied: the Airy argument per radian kk = pi D / (lambda sigma), the
+// Gaussian 1 / (s sigma)^2, the aperture table's nodes per radian over
+// sigma, and 1 / sigma (for the scale derivative).
+struct BeamK {
+    float kk, inv_s2, aps, rsig;
+};
+
+__device__ __forceinline__ BeamK beam_k(float kk, float inv_s2, float aps, float sigma)
+{
+    const float r = 1.f / sigma;
+    return BeamK{kk * r, inv_s2 * r * r, aps * r, r};
+}
+
 // Image-plane products as mf_products, for a measured aperture, with the
-// derivative variants already with respect to the mount-frame offsets.
+// derivative variants already with respect to the mount-frame offsets (and
+// dE/dsigma = (d . dE/dc) / sigma with d in the mount frame).
 template <int MODE>
-__device__ __forceinline__ void mf_products_ap(const ItemArgs& a, float s, float cs, float sn, float dli,
-                                               float dmi, float dlj, float dmj, float c,
+__device__ __forceinline__ void mf_products_ap(const ItemArgs& a, const BeamK& bi, const BeamK& bj, float cs,
+                                               float sn, float dli, float dmi, float dlj, float dmj, float c,
                                                float (&g)[mode_nv(MODE)])
 {
     constexpr bool D = mode_nv(MODE) > 1;
     float ei, eil = 0.f, eim = 0.f, ej, ejl = 0.f, ejm = 0.f;
-    efp_ap<D>(a, s, cs, sn, dli, dmi, ei, eil, eim);
-    efp_ap<D>(a, s, cs, sn, dlj, dmj, ej, ejl, ejm);
+    efp_ap<D>(a, bi.aps, cs, sn, dli, dmi, ei, eil, eim);
+    efp_ap<D>(a, bj.aps, cs, sn, dlj, dmj, ej, ejl, ejm);
     if constexpr (!D) {
         g[0] = ei * ej * c;
+    } else if constexpr (MODE == kScale) {
+        const float si = ((cs * dli + sn * dmi) * eil + (cs * dmi - sn * dli) * eim) * bi.rsig;
+        const float sj = ((cs * dlj + sn * dmj) * ejl + (cs * dmj - sn * dlj) * ejm) * bj.rsig;
+        g[0] = ei * ej * c;
+        g[1] = si * ej * c;
+        g[2] = ei * sj * c;
     } else {
         constexpr int o = (MODE == kGrad) ? 1 : 0;
         if constexpr (MODE == kGrad) g[0] = ei * ej * c;
@@ -318,15 +339,20 @@ __device__ __forceinline__ void mf_products_ap(const ItemArgs& a, float s, float
 // antennas' offsets relative to the sample (dl_i, dm_i), (dl_j, dm_j) and the
 // taper value c there, in the variant order of image_products.
 template <int MODE>
-__device__ __forceinline__ void mf_products(const ItemArgs& a, const float4* tab, float kk, float inv_s2,
-                                            float dli, float dmi, float dlj, float dmj, float c,
+__device__ __forceinline__ void mf_products(const ItemArgs& a, const float4* tab, const BeamK& bi,
+                                            const BeamK& bj, float dli, float dmi, float dlj, float dmj, float c,
                                             float (&g)[mode_nv(MODE)])
 {
     float ei, eil, eim, ej, ejl, ejm;
-    efp(a, tab, kk, inv_s2, dli, dmi, ei, eil, eim);
-    efp(a, tab, kk, inv_s2, dlj, dmj, ej, ejl, ejm);
+    efp(a, tab, bi.kk, bi.inv_s2, dli, dmi, ei, eil, eim);
+    efp(a, tab, bj.kk, bj.inv_s2, dlj, dmj, ej, ejl, ejm);
     if constexpr (mode_nv(MODE) == 1) {
         g[0] = ei * ej * c;
+    } else if constexpr (MODE == kScale) {
+        // dE/dsigma = (d . dE/dp) / sigma
+        g[0] = ei * ej * c;
+        g[1] = (dli * eil + dmi * eim) * bi.rsig * ej * c;
+        g[2] = ei * (dlj * ejl + dmj * ejm) * bj.rsig * c;
     } else {
         constexpr int o = (MODE == kGrad) ? 1 : 0;
         if constexpr (MODE == kGrad) g[0] = ei * ej * c;
@@ -384,6 +410,22 @@ __device__ __forceinline__ void vjp_term(int t, const float2 (&s)[NV], float2 gv
     for (int k = 1; k < 4; ++k)
         if (tt == k) dv = s[k];
     if (t < 4) acc += (double)gv.x * (double)dv.x + (double)gv.y * (double)dv.y;
+}
+
+// Beam-scale sums: lane t < 6 adds term t = 3 * end + c, c indexing chi,
+// g_sigma, H_sigma = w |R|^2, w Re(conj(R) dV/dsigma_end), w |dV/dsigma_end|^2
+// (Eq. DCHIDD with the scale as the antenna parameter); s[0] = V^M,
+// s[1], s[2] = dV/dsigma_i, dV/dsigma_j.
+__device__ __forceinline__ void scale_term(int t, const float2 (&s)[3], float2 vo, float wgt, double& acc)
+{
+    const float rr = (float)((double)vo.x - (double)s[0].x);
+    const float ri = (float)((double)vo.y - (double)s[0].y);
+    const int c = t % 3;
+    const float2 d = t >= 3 ? s[2] : s[1];
+    const float xr = c == 2 ? d.x : rr, xi = c == 2 ? d.y : ri;
+    const float yr = c == 0 ? rr : d.x, yi = c == 0 ? ri : d.y;
+    const float val = fmaf(xr, yr, xi * yi);
+    if (t < 6) acc = fma((double)wgt, (double)val, acc);
 }
 
 }  // namespace psc

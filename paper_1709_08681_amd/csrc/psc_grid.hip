@@ -308,6 +308,13 @@ __global__ void __launch_bounds__(kGridThreads) k_gridw(ItemArgs a)
         const double* oj = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.aj) * 2;
         const double qil = oi[0] + sq, qim = oi[1], qjl = oj[0] + sq, qjm = oj[1];
         if constexpr (MF == kFrameSky) image_products<kPredict>(a, it, pol, gsh, m2p, tid, kGridThreads);
+        // each antenna's beam constants with its width scale (mount-frame paths)
+        BeamK bki = beam_k(kk, inv_s2, aps, 1.f), bkj = bki;
+        if (MF != kFrameSky && a.scale != nullptr) {
+            const double* sc = a.scale + ((size_t)it.interval * a.n_pol + pol) * a.n_ant;
+            bki = beam_k(kk, inv_s2, aps, (float)sc[it.ai]);
+            bkj = beam_k(kk, inv_s2, aps, (float)sc[it.aj]);
+        }
         if (fits)
             for (int t = tid; t < hgt * PB; t += kGridThreads) patch[t] = make_float2(0.f, 0.f);
         __syncthreads();
@@ -369,13 +376,13 @@ __global__ void __launch_bounds__(kGridThreads) k_gridw(ItemArgs a)
                             const float l = (float)nl * hstep, mm = (float)nmv * hstep;
                             if constexpr (MF == kFrameAperture) {
                                 float ei, ej, unused;
-                                efp_ap<false>(a, aps, cs, sn, l - pil, mm - pim, ei, unused, unused);
-                                efp_ap<false>(a, aps, cs, sn, l - pjl, mm - pjm, ej, unused, unused);
+                                efp_ap<false>(a, bki.aps, cs, sn, l - pil, mm - pim, ei, unused, unused);
+                                efp_ap<false>(a, bkj.aps, cs, sn, l - pjl, mm - pjm, ej, unused, unused);
                                 gv = ei * ej * (a.taper_img[nl + half_m] * a.taper_img[nmv + half_m]);
                             } else if constexpr (MF == kFrameMount) {
                                 float ei, qi, ej, qj;
-                                efq(a, airy_sh, kk, inv_s2, l - pil, mm - pim, ei, qi);
-                                efq(a, airy_sh, kk, inv_s2, l - pjl, mm - pjm, ej, qj);
+                                efq(a, airy_sh, bki.kk, bki.inv_s2, l - pil, mm - pim, ei, qi);
+                                efq(a, airy_sh, bkj.kk, bkj.inv_s2, l - pjl, mm - pjm, ej, qj);
                                 gv = ei * ej * (a.taper_img[nl + half_m] * a.taper_img[nmv + half_m]);
                             } else {
                                 gv = gsh[(nl + half_m) * m + nmv + half_m];

@@ -39,7 +39,7 @@ struct VisEnt {
     uint32_t klo;
 };
 
-enum Mode { kPredict = 0, kGrad = 1, kVjp = 2, kGrid = 3 };
+enum Mode { kPredict = 0, kGrad = 1, kVjp = 2, kGrid = 3, kScale = 4 };
 
 // Beam frame of the window-form kernels: radial beams on the sky (factored
 // image-plane products), radial beams in the mount frame (per-sample
@@ -47,10 +47,16 @@ enum Mode { kPredict = 0, kGrad = 1, kVjp = 2, kGrid = 3 };
 // in the mount frame (per-sample products from its tabulated transform).
 enum Frame { kFrameSky = 0, kFrameMount = 1, kFrameAperture = 2 };
 
-// Kernel variants a mode degrids (V, or V and its four offset derivatives)
-// and the float64 sums it keeps per item.
-__host__ __device__ constexpr int mode_nv(int mode) { return mode == kGrad ? 5 : mode == kVjp ? 4 : 1; }
-__host__ __device__ constexpr int mode_nc(int mode) { return mode == kGrad ? 12 : mode == kVjp ? 4 : 0; }
+// Kernel variants a mode degrids (V, its four offset derivatives, or its two
+// beam-scale derivatives) and the float64 sums it keeps per item.
+__host__ __device__ constexpr int mode_nv(int mode)
+{
+    return mode == kGrad ? 5 : mode == kVjp ? 4 : mode == kScale ? 3 : 1;
+}
+__host__ __device__ constexpr int mode_nc(int mode)
+{
+    return mode == kGrad ? 12 : mode == kVjp ? 4 : mode == kScale ? 6 : 0;
+}
 
 // Arguments of the fused kernel-build + degrid kernel.
 struct ItemArgs {
@@ -91,6 +97,9 @@ struct ItemArgs {
     int32_t ap_n;
     float ap_c;
     float ap_inv_step;
+    // nullable [n_int][n_pol][n_ant]: beam-width scale sigma of each antenna,
+    // pattern E0(d / sigma) (per-sample products: mount-frame paths only)
+    const double* scale;
     int32_t use_mfma;           // degrid on the matrix cores (gradient and adjoint)
     // image-gradient scatter (k_grid)
     const uint2* ig_ord;        // per item, its samples in time order: (sample index, sub-table slot)
@@ -134,6 +143,10 @@ hipError_t launch_airy_table(float4* tab, int n_tab, double dx, hipStream_t s);
 // [n_cells][3] = (xi, eta, weight), xi and eta in units of D.
 hipError_t launch_aperture_table(const double* cells, int n_cells, float4* tab, int n, double c, double step,
                                  hipStream_t s);
+// Damped step of the beam-width scales (psc_scale.hip): per (interval, pol,
+// antenna) sigma += gain g / H from acc3 = (chi, g, H); one block per interval.
+hipError_t launch_scale_step(int n_int, int n_pol, int n_ant, const double* acc3, double gain, double* scale,
+                             int32_t* not_updated, double* max_step, hipStream_t s);
 hipError_t launch_zero(double2* p, size_t n, hipStream_t s);
 hipError_t launch_unpad_grid(const double2* g, double2* out, int n, int pad, hipStream_t s);
 hipError_t launch_image_grad(const double2* f, const double* taper_pix, double* out, int n, hipStream_t s);

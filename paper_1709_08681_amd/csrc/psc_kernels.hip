@@ -953,6 +953,8 @@ hipError_t launch_reduce(int ncontrib, const ReduceArgs& a, hipStream_t s)
     if (nb <= 0) return hipSuccess;
     if (ncontrib == 12)
         k_reduce<12><<<nb, 64, 0, s>>>(a);
+    else if (ncontrib == 6)
+        k_reduce<6><<<nb, 64, 0, s>>>(a);
     else if (ncontrib == 4)
         k_reduce<4><<<nb, 64, 0, s>>>(a);
     else

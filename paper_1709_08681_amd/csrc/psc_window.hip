@@ -258,7 +258,7 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
             load_window(e0, x0);
             const size_t o0 = (size_t)e0.vidx * a.n_pol + pol;
             if (MODE != kPredict) vin0 = a.vis_in[o0];
-            if (MODE == kGrad) wgt0 = a.weight[o0];
+            if (MODE == kGrad || MODE == kScale) wgt0 = a.weight[o0];
             if constexpr (WT) w0 = (float)(a.w_m[e0.vidx / (uint32_t)a.n_chan] * w_per_m);
         }
 
@@ -269,6 +269,15 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
         const double qil = oi[0] + sq, qim = oi[1], qjl = oj[0] + sq, qjm = oj[1];
         if constexpr (MF == kFrameSky)
             image_factors<MODE>(a, gsh, kk, inv_s2, (float)qil, (float)qim, (float)qjl, (float)qjm, tid, kBlock);
+        // each antenna's beam constants with its width scale (mount-frame paths)
+        BeamK bki = beam_k(kk, inv_s2, aps, 1.f), bkj = bki;
+        if constexpr (MF != kFrameSky) {
+            if (a.scale != nullptr) {
+                const double* sc = a.scale + ((size_t)it.interval * a.n_pol + pol) * a.n_ant;
+                bki = beam_k(kk, inv_s2, aps, (float)sc[it.ai]);
+                bkj = beam_k(kk, inv_s2, aps, (float)sc[it.aj]);
+            }
+        }
         __syncthreads();
 
         double acc64 = 0.0;
@@ -280,7 +289,7 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
             float2 vin1 = zero;
             float wgt1 = 0.f, w1 = 0.f;
             if (MODE != kPredict) vin1 = a.vis_in[o1];
-            if (MODE == kGrad) wgt1 = a.weight[o1];
+            if (MODE == kGrad || MODE == kScale) wgt1 = a.weight[o1];
             if constexpr (WT) w1 = (float)(a.w_m[e1.vidx / (uint32_t)a.n_chan] * w_per_m);
             int gi2 = gi1, v2 = v1;
             if (gi1 < n_grp) advance(gi2, v2, NW);
@@ -340,10 +349,10 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
                     if constexpr (WT) t = cmul(t, wphase(w0, l));
                     float g[NV];
                     if constexpr (MF == kFrameAperture)
-                        mf_products_ap<MODE>(a, aps, cs, sn, l - pil, mmy - pim, l - pjl, mmy - pjm,
+                        mf_products_ap<MODE>(a, bki, bkj, cs, sn, l - pil, mmy - pim, l - pjl, mmy - pjm,
                                              a.taper_img[jl] * ctm, g);
                     else
-                        mf_products<MODE>(a, airy_sh, kk, inv_s2, l - pil, mmy - pim, l - pjl, mmy - pjm,
+                        mf_products<MODE>(a, airy_sh, bki, bkj, l - pil, mmy - pim, l - pjl, mmy - pjm,
                                           a.taper_img[jl] * ctm, g);
 #pragma unroll
                     for (int k = 0; k < NV; ++k) {
@@ -430,7 +439,7 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
                     s[k].y = sum_xor32(s[k].y);
                 }
             }
-            if constexpr (MF == kFrameMount && MODE != kPredict) {
+            if constexpr (MF == kFrameMount && MODE != kPredict && MODE != kScale) {
                 // derivatives with respect to the mount-frame offsets
                 constexpr int d0 = (MODE == kGrad) ? 1 : 0;
 #pragma unroll
@@ -441,11 +450,13 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
                 }
             }
             const size_t o0 = (size_t)e0.vidx * a.n_pol + pol;
-            if (MODE == kPredict) {
+            if constexpr (MODE == kPredict) {
                 if (sl == 0) a.vis_out[o0] = s[0];
-            } else if (MODE == kGrad) {
+            } else if constexpr (MODE == kGrad) {
                 if (a.vis_out != nullptr && sl == 0) a.vis_out[o0] = s[0];
                 grad_term(tsel, s, vin0, wgt0, acc64);
+            } else if constexpr (MODE == kScale) {
+                scale_term(sl, s, vin0, wgt0, acc64);
             } else {
                 vjp_term(sl, s, vin0, acc64);
             }
@@ -510,6 +521,14 @@ template <int S, int MODE>
 static hipError_t launch_win_m(const ItemArgs& a, hipStream_t s)
 {
     const bool wt = a.w_m != nullptr;
+    if constexpr (MODE == kScale) {
+        // per-sample products only: the scale derivative is not factored
+        if (a.par_angle == nullptr) return hipErrorInvalidValue;
+        if (a.ap_tab != nullptr)
+            return wt ? launch_win_t<S, MODE, kFrameAperture, true>(a, s)
+                      : launch_win_t<S, MODE, kFrameAperture, false>(a, s);
+        return wt ? launch_win_t<S, MODE, kFrameMount, true>(a, s) : launch_win_t<S, MODE, kFrameMount, false>(a, s);
+    }
     if (a.ap_tab != nullptr)
         return wt ? launch_win_t<S, MODE, kFrameAperture, true>(a, s)
                   : launch_win_t<S, MODE, kFrameAperture, false>(a, s);
@@ -550,6 +569,7 @@ hipError_t launch_win(int mode, int support, const ItemArgs& a, hipStream_t s)
         case kPredict: return launch_win_m<16, kPredict>(a, s);
         case kGrad: return launch_win_m<16, kGrad>(a, s);
         case kVjp: return launch_win_m<16, kVjp>(a, s);
+        case kScale: return launch_win_m<16, kScale>(a, s);
         default: return hipErrorInvalidValue;
         }
     }
@@ -558,6 +578,7 @@ hipError_t launch_win(int mode, int support, const ItemArgs& a, hipStream_t s)
         case kPredict: return launch_win_m<32, kPredict>(a, s);
         case kGrad: return launch_win_m<32, kGrad>(a, s);
         case kVjp: return launch_win_m<32, kVjp>(a, s);
+        case kScale: return launch_win_m<32, kScale>(a, s);
         default: return hipErrorInvalidValue;
         }
     }

@@ -29,7 +29,8 @@ ARCSEC = math.pi / (180.0 * 3600.0)
 EXPORTS = ["psc_version", "psc_create", "psc_destroy", "psc_last_error", "psc_set_model",
            "psc_obs_create", "psc_obs_destroy", "psc_obs_info", "psc_predict", "psc_gradient",
            "psc_predict_vjp", "psc_solve_step", "psc_solve", "psc_set_degrid", "psc_get_degrid",
-           "psc_tune", "psc_image_gradient"]
+           "psc_tune", "psc_image_gradient", "psc_set_beam_scale", "psc_get_beam_scale",
+           "psc_scale_gradient", "psc_scale_step"]
 
 
 class PscError(RuntimeError):
@@ -90,6 +91,10 @@ def load():
             "psc_get_degrid": ([vp, C.POINTER(i32)], C.c_int),
             "psc_tune": ([vp, vp, vp, vp, vp, i32, C.POINTER(dbl), vp], C.c_int),
             "psc_image_gradient": ([vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
+            "psc_set_beam_scale": ([vp, vp, vp, vp], C.c_int),
+            "psc_get_beam_scale": ([vp, vp, vp, vp], C.c_int),
+            "psc_scale_gradient": ([vp, vp, vp, vp, vp, vp, vp], C.c_int),
+            "psc_scale_step": ([vp, vp, vp, dbl, vp, vp, vp], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -198,6 +203,24 @@ def psc_image_gradient(ctx, obs, offsets_dev, vis_obs_dev, weight_dev, image_gra
     _check(load().psc_image_gradient(ctx, obs, _ptr(offsets_dev), _ptr(vis_obs_dev), _ptr(weight_dev),
                                      _ptr(image_grad_out_dev), _ptr(vis_model_dev), _stream(stream)),
            ctx)
+
+
+def psc_set_beam_scale(ctx, obs, scale_dev, stream=None):
+    _check(load().psc_set_beam_scale(ctx, obs, _ptr(scale_dev), _stream(stream)), ctx)
+
+
+def psc_get_beam_scale(ctx, obs, scale_out_dev, stream=None):
+    _check(load().psc_get_beam_scale(ctx, obs, _ptr(scale_out_dev), _stream(stream)), ctx)
+
+
+def psc_scale_gradient(ctx, obs, offsets_dev, vis_obs_dev, weight_dev, acc_out_dev, stream=None):
+    _check(load().psc_scale_gradient(ctx, obs, _ptr(offsets_dev), _ptr(vis_obs_dev), _ptr(weight_dev),
+                                     _ptr(acc_out_dev), _stream(stream)), ctx)
+
+
+def psc_scale_step(ctx, obs, acc_dev, gain, not_updated_dev=None, max_step_dev=None, stream=None):
+    _check(load().psc_scale_step(ctx, obs, _ptr(acc_dev), float(gain), _ptr(not_updated_dev),
+                                 _ptr(max_step_dev), _stream(stream)), ctx)
 
 
 def psc_tune(ctx, obs, offsets_dev, vis_obs_dev, weight_dev, repeats=3, stream=None):
@@ -324,6 +347,37 @@ class Session:
         g = torch.empty(self.off_shape, dtype=torch.float64, device=self.dev)
         psc_predict_vjp(self.ctx, self.handle, off, grad_vis.contiguous(), g)
         return g
+
+    def set_beam_scale(self, scale):
+        """Beam-width scales [n_int, n_pol, n_ant] (array or device tensor), or
+        None for the nominal beams."""
+        torch = self.torch
+        if scale is None:
+            psc_set_beam_scale(self.ctx, self.handle, None)
+            return
+        sc = scale if isinstance(scale, torch.Tensor) else torch.as_tensor(
+            np.ascontiguousarray(scale, dtype=np.float64), device=self.dev)
+        psc_set_beam_scale(self.ctx, self.handle, sc.contiguous())
+
+    def beam_scale(self):
+        out = self.torch.empty(self.off_shape[:3], dtype=self.torch.float64, device=self.dev)
+        psc_get_beam_scale(self.ctx, self.handle, out)
+        return out
+
+    def scale_gradient(self, offsets, vis_obs, weight):
+        torch = self.torch
+        off = offsets if isinstance(offsets, torch.Tensor) else self.offsets(offsets)
+        acc = torch.empty(self.off_shape[:3] + (3,), dtype=torch.float64, device=self.dev)
+        psc_scale_gradient(self.ctx, self.handle, off, vis_obs, weight, acc)
+        return acc
+
+    def scale_step(self, acc, gain=0.5):
+        """Returns (not_updated, max_step per interval)."""
+        torch = self.torch
+        nu = torch.empty(self.off_shape[:3], dtype=torch.int32, device=self.dev)
+        mx = torch.empty(self.obs.n_int, dtype=torch.float64, device=self.dev)
+        psc_scale_step(self.ctx, self.handle, acc, gain, nu, mx)
+        return nu, mx
 
     def image_gradient(self, offsets, vis_obs, weight):
         """d chi^2 / d I on the model grid, [N][N] float64."""

@@ -1016,3 +1016,111 @@ def test_measured_aperture_must_be_even(torch_dev):
     with pytest.raises(psc.PscError) as ei:
         session(obs, aperture=A)
     assert ei.value.status == psc.PSC_E_ARG
+
+
+# ---------------------------------------------------------------------------
+# beam-width scales: a generalised antenna parameter beside the offsets
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("S,over,mount,ap", [(16, 4, False, False), (16, 4, True, False),
+                                             (32, 8, True, False), (16, 4, True, True)])
+def test_beam_scale_predict_gradients_image(torch_dev, S, over, mount, ap):
+    """Scales within 5% of nominal: prediction, the offsets' sums, the scale
+    sums, the adjoint and the image gradient against the oracle, sky and
+    mount frame, both supports, and with a measured aperture."""
+    torch = torch_dev
+    from paper_1709_08681_amd import psc
+    print(f"case: beam scale, S {S}, O {over}, mount {mount}, aperture {ap}", flush=True)
+    obs = _aperture_obs(S, over)
+    A = synth.measured_aperture(seed=14) if ap else None
+    sc = np.random.default_rng(61).uniform(0.95, 1.05, (obs.n_int, obs.n_pol, obs.n_ant))
+    kw = dict(illum=2, aperture=A) if ap else {}
+    prob = oracle.Problem.from_observation(obs, mount_frame=mount, beam_scale=sc, **kw)
+    s = session(obs, mount_frame=mount, aperture=A)
+    try:
+        s.set_beam_scale(sc)
+        assert np.array_equal(s.beam_scale().cpu().numpy(), sc)
+        assert psc.psc_get_degrid(s.handle) == psc.DEGRID_WINDOW
+        with pytest.raises(psc.PscError) as ei:
+            psc.psc_set_degrid(s.handle, psc.DEGRID_VALU)
+        assert ei.value.status == psc.PSC_E_UNSUPPORTED
+        v = oracle.predict(prob, obs.offsets_true)
+        v_nom = oracle.predict(oracle.Problem.from_observation(obs, mount_frame=mount, **kw), obs.offsets_true)
+        assert rel(v_nom, v) > 1e-3  # the scales matter
+        start = synth.perturbed_offsets(obs, 25.0, 62)
+        assert rel(s.predict(start).cpu().numpy(), oracle.predict(prob, start)) <= 1e-5
+        nz, w = synth.noise(v, 100.0, 63)
+        vo_d, w_d = c64(torch, s, v + nz), f32(torch, s, w, s.vis_shape)
+        ref, vm_ref = oracle.gradient(prob, start, v + nz, w, want_model=True)
+        acc, vm = s.gradient(s.offsets(start), vo_d, w_d, want_model=True)
+        assert rel(vm.cpu().numpy(), vm_ref) <= 1e-5
+        acc = acc.cpu().numpy()
+        for k in range(6):
+            assert rel(acc[..., k], ref[..., k]) <= 1e-4, k
+        ref3 = oracle.scale_gradient(prob, start, v + nz, w)
+        acc3 = s.scale_gradient(s.offsets(start), vo_d, w_d).cpu().numpy()
+        for k in range(3):
+            assert rel(acc3[..., k], ref3[..., k]) <= 1e-4, k
+        rng = np.random.default_rng(64)
+        G = (rng.normal(size=s.vis_shape) + 1j * rng.normal(size=s.vis_shape)).astype(np.complex64)
+        got = s.vjp(s.offsets(start), torch.as_tensor(G, device=s.dev)).cpu().numpy()
+        assert rel(got, vjp_reference(obs, prob, start, G, s.off_shape)) <= 1e-4
+        _check_image_gradient(torch, obs, prob, s, start, v + nz, w, 32, 65)
+        # dropping the scales gives the nominal beams again
+        s.set_beam_scale(None)
+        nominal = oracle.Problem.from_observation(obs, mount_frame=mount, **kw)
+        assert rel(s.predict(start).cpu().numpy(), oracle.predict(nominal, start)) <= 1e-5
+    finally:
+        s.close()
+
+
+def test_beam_scale_solve(torch_dev):
+    """Injected scales (3% spread) at the true offsets, noiseless data: the
+    damped scale steps from sigma = 1 follow the oracle's and recover them."""
+    torch = torch_dev
+    print("case: beam scale solve", flush=True)
+    obs = _aperture_obs(16, 4)
+    truth = np.random.default_rng(66).uniform(0.97, 1.03, (obs.n_int, obs.n_pol, obs.n_ant))
+    v = oracle.predict(oracle.Problem.from_observation(obs, beam_scale=truth), obs.offsets_true)
+    s = session(obs)
+    try:
+        w1 = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+        vo = c64(torch, s, v)
+        off = s.offsets(obs.offsets_true)
+        s.set_beam_scale(np.ones_like(truth))
+        ref = np.ones_like(truth)
+        for it in range(60):
+            acc = s.scale_gradient(off, vo, w1)
+            nu, mx = s.scale_step(acc, 0.5)
+            if it < 8:
+                a3 = oracle.scale_gradient(oracle.Problem.from_observation(obs, beam_scale=ref), obs.offsets_true,
+                                           v, 1.0)
+                ref, _, _ = oracle.scale_step(a3, 0.5, ref)
+                if it == 7:
+                    assert np.abs(s.beam_scale().cpu().numpy() - ref).max() <= 1e-5
+        assert int(nu.sum()) == 0
+        assert np.abs(s.beam_scale().cpu().numpy() - truth).max() <= 1e-4
+    finally:
+        s.close()
+
+
+def test_beam_scale_errors(torch_dev):
+    torch = torch_dev
+    from paper_1709_08681_amd import psc
+    print("case: beam scale errors", flush=True)
+    obs = _aperture_obs(16, 4)
+    s = session(obs)
+    try:
+        w1 = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+        vo = torch.zeros(s.vis_shape, dtype=torch.complex64, device=s.dev)
+        with pytest.raises(psc.PscError) as ei:
+            s.scale_gradient(s.offsets(obs.offsets_true), vo, w1)
+        assert ei.value.status == psc.PSC_E_STATE
+        bad = np.ones((obs.n_int, obs.n_pol, obs.n_ant))
+        bad[1, 0, 2] = 0.0
+        with pytest.raises(psc.PscError) as ei:
+            s.set_beam_scale(bad)
+        assert ei.value.status == psc.PSC_E_ARG
+        assert psc.psc_get_degrid(s.handle) == psc.DEGRID_VALU  # unchanged
+    finally:
+        s.close()
