@@ -142,32 +142,65 @@ def image_gradient_timing(s, obs, off, v_obs, w, reps, stream):
             "grid": f"{n}^2", "note": "table form, support 16, LDS-patch scatter"}
 
 
-def mount_frame_timing(obs, start, reps, device=0):
-    """psc_gradient with offsets in the antenna mount frame (every row's
-    parallactic angle): window form with per-sample image-plane products."""
+def extension_timing(obs, start, reps, what, device=0):
+    """Gradient launches of one extension on the workload's data, on a session
+    of its own:
+      mount_frame        offsets in the antenna mount frame (every row's
+                         parallactic angle), per-sample image-plane products;
+      measured_aperture  the same with a measured, non-circular aperture
+                         (bicubic lookups of its transform);
+      beam_scale         psc_scale_gradient: the sums for a beam-width scale
+                         per antenna (scales set within 3% of nominal);
+      w_term             the workload's array shrunk to arms of 1 km (the
+                         w-term's support limit; see the header), window form
+                         with e^{2 pi i w (n-1)} per image sample."""
     import torch
     from paper_1709_08681_amd import psc as P
-    s = P.Session(obs, device=device, mount_frame=True)
+    from paper_1709_08681_amd import synth
+    kw, note = {}, ""
+    if what == "mount_frame":
+        kw, note = dict(mount_frame=True), "window form, per-sample image-plane products"
+    elif what == "measured_aperture":
+        kw = dict(mount_frame=True, aperture=synth.measured_aperture())
+        note = "window form, per-sample bicubic lookups of the aperture's transform, mount frame"
+    elif what == "beam_scale":
+        kw, note = dict(mount_frame=True), "psc_scale_gradient, window form, mount frame"
+    elif what == "w_term":
+        if obs.wl.name != "single_interval":
+            return {"skipped": "timed on the single-interval array only"}
+        obs = synth.make_config(2, layout_radius_m=1000.0)
+        start = synth.perturbed_offsets(obs, 30.0, 1)
+        kw, note = dict(w_term=True), "window form with the w phase, arms shrunk to 1 km"
+    s = P.Session(obs, device=device, **kw)
     try:
         stream = torch.cuda.current_stream()
         v = s.predict(s.offsets(obs.offsets_true))
         w = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
         off = s.offsets(start)
-        acc = torch.empty(s.off_shape[:3] + (6,), dtype=torch.float64, device=s.dev)
-        P.psc_gradient(s.ctx, s.handle, off, v, w, acc, None, stream)
+        if what == "beam_scale":
+            s.set_beam_scale(np.random.default_rng(0).uniform(0.97, 1.03, s.off_shape[:3]))
+            acc = torch.empty(s.off_shape[:3] + (3,), dtype=torch.float64, device=s.dev)
+            call = lambda: P.psc_scale_gradient(s.ctx, s.handle, off, v, w, acc, stream)
+        else:
+            if what == "w_term":
+                P.psc_set_degrid(s.handle, P.DEGRID_WINDOW)
+            acc = torch.empty(s.off_shape[:3] + (6,), dtype=torch.float64, device=s.dev)
+            call = lambda: P.psc_gradient(s.ctx, s.handle, off, v, w, acc, None, stream)
+        call()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record(stream)
         for _ in range(reps):
-            P.psc_gradient(s.ctx, s.handle, off, v, w, acc, None, stream)
+            call()
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        pa = obs.par_angle
-        return {"ms_per_gradient": ms, "vis_per_s": obs.n_vis / (ms * 1e-3), "calls": reps,
-                "par_angle_range_deg": [float(np.degrees(pa.min())), float(np.degrees(pa.max()))],
-                "note": "window form, per-sample image-plane products"}
+        res = {"ms_per_gradient": ms, "vis_per_s": obs.n_vis / (ms * 1e-3), "calls": reps, "note": note}
+        if what == "mount_frame":
+            pa = obs.par_angle
+            res["par_angle_range_deg"] = [float(np.degrees(pa.min())), float(np.degrees(pa.max()))]
+        return res
     finally:
         s.close()
 
@@ -221,6 +254,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-image-gradient", action="store_true")
     ap.add_argument("--no-mount-frame", action="store_true")
+    ap.add_argument("--no-extensions", action="store_true",
+                    help="skip the measured-aperture, beam-scale and w-term timings")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only; the hot path is sharded by solution "
@@ -317,7 +352,12 @@ def main():
     s.close()
     if not args.no_mount_frame:
         print("bench: mount-frame offsets", file=sys.stderr, flush=True)
-        out["mount_frame"] = mount_frame_timing(obs, start, 3)
+        out["mount_frame"] = extension_timing(obs, start, 3, "mount_frame")
+    if not args.no_extensions:
+        out["extensions"] = {}
+        for what in ("measured_aperture", "beam_scale", "w_term"):
+            print(f"bench: {what}", file=sys.stderr, flush=True)
+            out["extensions"][what] = extension_timing(obs, start, 3, what)
     if not args.no_batched:
         print(f"bench: batched vs plain on workload {args.batched_config}", file=sys.stderr,
               flush=True)
