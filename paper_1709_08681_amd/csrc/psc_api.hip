@@ -974,8 +974,12 @@ PSC_API psc_status psc_set_beam_scale(psc_ctx* ctx, psc_obs* obs, const double* 
     hipStream_t st = (hipStream_t)stream;
     if (!scale_dev) {  // back to the nominal beams
         if (obs->scale) {
-            PSC_HIP(ctx, hipStreamSynchronize(st));
+            PSC_HIP(ctx, hipDeviceSynchronize());  // no launch may still read them
             dfree(obs->scale);
+            if (obs->graph) {  // a captured solve graph holds the freed scales
+                (void)hipGraphExecDestroy(obs->graph);
+                obs->graph = nullptr;
+            }
         }
         return PSC_OK;
     }

@@ -1124,3 +1124,41 @@ def test_beam_scale_errors(torch_dev):
         assert psc.psc_get_degrid(s.handle) == psc.DEGRID_VALU  # unchanged
     finally:
         s.close()
+
+
+def test_offsets_solve_with_beam_scales(torch_dev):
+    """Algorithm 1 for the offsets with the beams widened or narrowed: the
+    same iterations and offsets as the oracle's solve, in the plain and the
+    graph forms; a graph captured before the scales were set, or before they
+    were dropped, is rebuilt."""
+    torch = torch_dev
+    from paper_1709_08681_amd import psc
+    print("case: offsets solve with beam scales", flush=True)
+    obs = _aperture_obs(16, 4)
+    sc = np.random.default_rng(67).uniform(0.95, 1.05, (obs.n_int, obs.n_pol, obs.n_ant))
+    prob = oracle.Problem.from_observation(obs, beam_scale=sc)
+    nominal = oracle.Problem.from_observation(obs)
+    v = oracle.predict(prob, obs.offsets_true)
+    start = synth.perturbed_offsets(obs, 25.0, 68)
+    kw = dict(gain=0.5, n_max=8, tol_rad=1e-3 * ARCSEC)
+    ref, its_ref = oracle.solve(prob, v, 1.0, start, **kw)
+    ref0, its0 = oracle.solve(nominal, v, 1.0, start, **kw)
+    s = session(obs)
+    try:
+        w1 = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+        vo = c64(torch, s, v)
+        off = s.offsets(start)
+        s.solve(vo, w1, off, form=psc.SOLVE_GRAPH, **kw)  # captured on the nominal beams
+        s.set_beam_scale(sc)
+        for form in (psc.SOLVE_PLAIN, psc.SOLVE_GRAPH):
+            off = s.offsets(start)
+            its = s.solve(vo, w1, off, form=form, **kw)
+            assert np.array_equal(its.cpu().numpy(), its_ref)
+            assert np.abs(off.cpu().numpy() - ref).max() / ARCSEC <= 0.1
+        s.set_beam_scale(None)
+        off = s.offsets(start)
+        its = s.solve(vo, w1, off, form=psc.SOLVE_GRAPH, **kw)
+        assert np.array_equal(its.cpu().numpy(), its0)
+        assert np.abs(off.cpu().numpy() - ref0).max() / ARCSEC <= 0.1
+    finally:
+        s.close()
