@@ -339,11 +339,12 @@ PSC_API psc_status psc_tune(psc_ctx* ctx, psc_obs* obs, const double* offsets_de
  * float64 (device, borrowed), into the observation; every later predict,
  * gradient, adjoint, solve and image gradient uses it.  Values must be
  * positive and finite (PSC_E_ARG, the observation unchanged).  The scales
- * enter through per-sample image-plane products, so the observation then
- * degrids in the window form (psc_set_degrid refuses the table forms) and
- * rows without a parallactic angle take angle zero.  A null scale_dev drops
- * the scales (sigma = 1 again; the window form stays).  A captured solve
- * graph is discarded.
+ * enter through the window form's image-plane products (per antenna), so
+ * the observation then degrids in the window form (psc_set_degrid refuses
+ * the table forms); the image gradient then builds each sample's kernel
+ * (in the sky frame at angle zero, from [n_row] zeros the first call
+ * allocates).  A null scale_dev drops the scales (sigma = 1 again; the
+ * window form stays).  A captured solve graph is discarded.
  * psc_get_beam_scale (async): copies the observation's scales to
  * scale_out_dev; PSC_E_STATE when none are set.
  */

@@ -52,6 +52,7 @@ struct psc_obs {
     double inv_dx = 0;
     float4* ap_tab = nullptr;  // measured aperture: pattern table [ap_n][ap_n]
     double* scale = nullptr;   // beam-width scales [n_int][n_pol][n_ant] (null: all 1)
+    double* zero_pa = nullptr; // [n_row] zeros: the per-sample scatter's angles with scales, sky frame
     int32_t ap_n = 0;
     double ap_c = 0, ap_step = 0;
     double* partials = nullptr;  // [n_items][n_pol][12]
@@ -343,6 +344,7 @@ PSC_API psc_status psc_obs_destroy(psc_obs* obs)
     dfree(obs->airy);
     dfree(obs->ap_tab);
     dfree(obs->scale);
+    dfree(obs->zero_pa);
     dfree(obs->partials);
     dfree(obs->acc);
     dfree(obs->max_step);
@@ -871,9 +873,9 @@ PSC_API psc_status psc_image_gradient(psc_ctx* ctx, psc_obs* obs, const double* 
     a.grid_acc = ctx->rgrid;
     a.use_mfma = 0;
     PSC_HIP(ctx, launch_zero(ctx->rgrid, np, s));
-    const bool table_patch =
-        ctx->s == 16 && !obs->par_angle && !obs->w_m && grid_lds_bytes(ctx->s, ctx->m, ctx->o) <= kGridLdsMax;
-    if (table_patch || ctx->s == 32 || obs->par_angle || obs->w_m) {
+    const bool table_patch = ctx->s == 16 && !obs->par_angle && !obs->w_m && !obs->scale &&
+                             grid_lds_bytes(ctx->s, ctx->m, ctx->o) <= kGridLdsMax;
+    if (table_patch || ctx->s == 32 || obs->par_angle || obs->w_m || obs->scale) {
         // predict, then a patch scatter: per item with its sub-tables and its
         // samples in time order (support 16, sky frame), or with a kernel per
         // sample (support 32, mount frame, w-term)
@@ -891,10 +893,13 @@ PSC_API psc_status psc_image_gradient(psc_ctx* ctx, psc_obs* obs, const double* 
         PSC_HIP(ctx, launch_degrid(kPredict, ctx, obs, a, s));
         a.vis_model = vm;
         a.ig_ord = obs->ig_ord;
-        if (table_patch)
+        if (table_patch) {
             PSC_HIP(ctx, launch_grid(ctx->s, a, s));
-        else
+        } else {
+            // scaled beams in the sky frame: the per-sample kernels at angle zero
+            if (obs->scale && !a.par_angle) a.par_angle = obs->zero_pa;
             PSC_HIP(ctx, launch_gridw(ctx->s, a, s));
+        }
     } else {
         // the table-form scatter: degrid and spread in one pass, a float64
         // atomic per tap
@@ -989,12 +994,12 @@ PSC_API psc_status psc_set_beam_scale(psc_ctx* ctx, psc_obs* obs, const double* 
     PSC_HIP(ctx, hipStreamSynchronize(st));
     for (size_t k = 0; k < n; ++k)
         if (!(h[k] > 0.0) || !isfinite(h[k])) return fail(ctx, PSC_E_ARG, "beam scales must be positive and finite");
-    // the scales enter through the per-sample image-plane products: rows
-    // without a parallactic angle take angle zero
-    if (!obs->par_angle) {
+    // the image gradient's scatter builds each sample's kernel when the
+    // beams are scaled: in the sky frame it runs at angle zero
+    if (!obs->par_angle && !obs->zero_pa) {
         const size_t nr = obs->n_row > 0 ? (size_t)obs->n_row : 1;
-        PSC_HIP(ctx, dmalloc(&obs->par_angle, nr));
-        PSC_HIP(ctx, hipMemsetAsync(obs->par_angle, 0, sizeof(double) * nr, st));
+        PSC_HIP(ctx, dmalloc(&obs->zero_pa, nr));
+        PSC_HIP(ctx, hipMemsetAsync(obs->zero_pa, 0, sizeof(double) * nr, st));
     }
     if (!obs->scale) PSC_HIP(ctx, dmalloc(&obs->scale, n));
     PSC_HIP(ctx, hipMemcpyAsync(obs->scale, scale_dev, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
@@ -1067,7 +1072,7 @@ PSC_API psc_status psc_tune(psc_ctx* ctx, psc_obs* obs, const double* offsets_de
     int32_t best_v = obs->degrid;
     const int32_t keep = obs->degrid;
     for (int32_t v = PSC_DEGRID_VALU; v <= PSC_DEGRID_WINDOW && e == hipSuccess; ++v) {
-        if ((ctx->s != 16 || obs->par_angle || obs->w_m) && v != PSC_DEGRID_WINDOW) {
+        if ((ctx->s != 16 || obs->par_angle || obs->w_m || obs->scale) && v != PSC_DEGRID_WINDOW) {
             if (times_us_out) times_us_out[v] = -1.0;  // not available at this support
             continue;
         }

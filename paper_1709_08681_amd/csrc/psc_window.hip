@@ -22,27 +22,40 @@
 
 namespace psc {
 
-// Image-plane factors of an item at the M x M samples, [n][NG] with NG = 1, 2, 3
-// for predict, adjoint, gradient: g = E_i E_j c and, for the derivatives,
-// the gradient factors q_i E_j c and E_i q_j c (dE/dp = q (l - p)), from
-// which the sum forms the four derivative variants of Eq. DA.
-template <int MODE>
-__device__ __forceinline__ void image_factors(const ItemArgs& a, float* gsh, float kk, float inv_s2, float pil,
-                                              float pim, float pjl, float pjm, int tid, int nthr)
+// Image-plane factors per sample of the window form (sky frame): for predict,
+// adjoint, gradient and beam scale.
+__host__ __device__ constexpr int win_ng(int mode)
 {
-    constexpr int NG = MODE == kGrad ? 3 : MODE == kVjp ? 2 : 1;
+    return mode == kGrad || mode == kScale ? 3 : mode == kVjp ? 2 : 1;
+}
+
+// Image-plane factors of an item at the M x M samples, [n][NG]: g = E_i E_j c
+// and, for the offsets' derivatives, the gradient factors q_i E_j c and
+// E_i q_j c (dE/dp = q (l - p)), from which the sum forms the four derivative
+// variants of Eq. DA; for the beam scales, dE/dsigma = q |l - p|^2 / sigma in
+// place of q.  bi, bj: each antenna's beam constants (its width scale applied).
+template <int MODE>
+__device__ __forceinline__ void image_factors(const ItemArgs& a, float* gsh, const BeamK& bi, const BeamK& bj,
+                                              float pil, float pim, float pjl, float pjm, int tid, int nthr)
+{
+    constexpr int NG = win_ng(MODE);
     const int m = a.m, half_m = m >> 1, m2 = m * m;
     const float hstep = (float)a.h;
     for (int idx = tid; idx < m2; idx += nthr) {
         const int il = idx / m, im = idx - il * m;
         const float l = (float)(il - half_m) * hstep, mm = (float)(im - half_m) * hstep;
         float ei, qi, ej, qj;
-        efq(a, a.airy, kk, inv_s2, l - pil, mm - pim, ei, qi);
-        efq(a, a.airy, kk, inv_s2, l - pjl, mm - pjm, ej, qj);
+        const float dli = l - pil, dmi = mm - pim, dlj = l - pjl, dmj = mm - pjm;
+        efq(a, a.airy, bi.kk, bi.inv_s2, dli, dmi, ei, qi);
+        efq(a, a.airy, bj.kk, bj.inv_s2, dlj, dmj, ej, qj);
         const float c = a.taper_img[il] * a.taper_img[im];
         float* gn = gsh + idx * NG;
         if constexpr (MODE == kPredict) {
             gn[0] = ei * ej * c;
+        } else if constexpr (MODE == kScale) {
+            gn[0] = ei * ej * c;
+            gn[1] = qi * fmaf(dli, dli, dmi * dmi) * bi.rsig * ej * c;
+            gn[2] = ei * qj * fmaf(dlj, dlj, dmj * dmj) * bj.rsig * c;
         } else {
             constexpr int o = MODE == kGrad ? 1 : 0;
             if constexpr (MODE == kGrad) gn[0] = ei * ej * c;
@@ -126,7 +139,7 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
     constexpr int NV = mode_nv(MODE);
     constexpr int NC = mode_nc(MODE);
     constexpr int NCP = NC > 0 ? NC : 1;
-    constexpr int NG = MODE == kGrad ? 3 : MODE == kVjp ? 2 : 1;  // image-plane factors per sample
+    constexpr int NG = win_ng(MODE);  // image-plane factors per sample (sky frame)
     constexpr int kBlock = 64 * W;
     static_assert(NC <= SL, "one term per lane");
 
@@ -267,17 +280,15 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
         const double* oi = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.ai) * 2;
         const double* oj = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.aj) * 2;
         const double qil = oi[0] + sq, qim = oi[1], qjl = oj[0] + sq, qjm = oj[1];
-        if constexpr (MF == kFrameSky)
-            image_factors<MODE>(a, gsh, kk, inv_s2, (float)qil, (float)qim, (float)qjl, (float)qjm, tid, kBlock);
-        // each antenna's beam constants with its width scale (mount-frame paths)
+        // each antenna's beam constants with its width scale
         BeamK bki = beam_k(kk, inv_s2, aps, 1.f), bkj = bki;
-        if constexpr (MF != kFrameSky) {
-            if (a.scale != nullptr) {
-                const double* sc = a.scale + ((size_t)it.interval * a.n_pol + pol) * a.n_ant;
-                bki = beam_k(kk, inv_s2, aps, (float)sc[it.ai]);
-                bkj = beam_k(kk, inv_s2, aps, (float)sc[it.aj]);
-            }
+        if (a.scale != nullptr) {
+            const double* sc = a.scale + ((size_t)it.interval * a.n_pol + pol) * a.n_ant;
+            bki = beam_k(kk, inv_s2, aps, (float)sc[it.ai]);
+            bkj = beam_k(kk, inv_s2, aps, (float)sc[it.aj]);
         }
+        if constexpr (MF == kFrameSky)
+            image_factors<MODE>(a, gsh, bki, bkj, (float)qil, (float)qim, (float)qjl, (float)qjm, tid, kBlock);
         __syncthreads();
 
         double acc64 = 0.0;
@@ -379,11 +390,19 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
                     for (int jl = j0; jl < j1; ++jl, tp += SP, g += m * NG) {
                         float2 t = *tp;
                         if constexpr (WT) t = cmul(t, wphase(w0, (float)(jl - half_m) * hstep));
-                        if constexpr (MODE != kVjp) {
+                        if constexpr (MODE == kScale) {
+                            // three plain sums: V and the two scale derivatives
+#pragma unroll
+                            for (int k = 0; k < 3; ++k) {
+                                acc[k].x = fmaf(g[k], t.x, acc[k].x);
+                                acc[k].y = fmaf(g[k], t.y, acc[k].y);
+                            }
+                        }
+                        if constexpr (MODE != kVjp && MODE != kScale) {
                             acc[0].x = fmaf(g[0], t.x, acc[0].x);
                             acc[0].y = fmaf(g[0], t.y, acc[0].y);
                         }
-                        if constexpr (MODE != kPredict) {
+                        if constexpr (MODE != kPredict && MODE != kScale) {
                             constexpr int o = MODE == kGrad ? 1 : 0;
                             const float l = (float)(jl - half_m) * hstep;
                             const float2 tl = make_float2(t.x * l, t.y * l);
@@ -416,7 +435,7 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
                 const float2 rb = cmul(rho, B[k]);
                 s[k] = cmul(pm, make_float2(A[k].x + rb.x, A[k].y + rb.y));
             }
-            if constexpr (MF == kFrameSky && MODE != kPredict) {
+            if constexpr (MF == kFrameSky && MODE != kPredict && MODE != kScale) {
                 // derivative variants from the factored sums (the lane's m coordinate is mmy)
                 constexpr int o = MODE == kGrad ? 1 : 0;
                 const float pl[2] = {(float)qil, (float)qjl}, pmm[2] = {(float)qim, (float)qjm};
@@ -521,14 +540,6 @@ template <int S, int MODE>
 static hipError_t launch_win_m(const ItemArgs& a, hipStream_t s)
 {
     const bool wt = a.w_m != nullptr;
-    if constexpr (MODE == kScale) {
-        // per-sample products only: the scale derivative is not factored
-        if (a.par_angle == nullptr) return hipErrorInvalidValue;
-        if (a.ap_tab != nullptr)
-            return wt ? launch_win_t<S, MODE, kFrameAperture, true>(a, s)
-                      : launch_win_t<S, MODE, kFrameAperture, false>(a, s);
-        return wt ? launch_win_t<S, MODE, kFrameMount, true>(a, s) : launch_win_t<S, MODE, kFrameMount, false>(a, s);
-    }
     if (a.ap_tab != nullptr)
         return wt ? launch_win_t<S, MODE, kFrameAperture, true>(a, s)
                   : launch_win_t<S, MODE, kFrameAperture, false>(a, s);
@@ -549,7 +560,7 @@ size_t winw_lds_bytes(int support, int waves, int mode, int m, int oversample, i
     const int nc = mode_nc(mode) > 0 ? mode_nc(mode) : 1;
     const size_t m2p = (size_t)((m * m + 3) & ~3);
     const bool mf = mount_frame_tab >= 0;
-    const int ng = mode == kGrad ? 3 : mode == kVjp ? 2 : 1;  // image-plane factors per sample
+    const int ng = win_ng(mode);  // image-plane factors per sample (sky frame)
     return sizeof(double) * nc * workers + sizeof(Group) * win_max_groups(oversample) +
            (mf ? 0 : sizeof(float) * ng * m2p) + sizeof(float2) * (size_t)workers * support * (support + 1) +
            (mf ? sizeof(float4) * mount_frame_tab : 0);
