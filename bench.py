@@ -228,7 +228,7 @@ def cpu_baseline(obs, start, seconds):
         if time.perf_counter() - t0 >= seconds:
             break
     dt = time.perf_counter() - t0
-    return {
+    out = {
         "value": obs.n_vis * iters / dt,
         "unit": "vis/s",
         "cores": int(oracle.num_threads()),
@@ -236,7 +236,59 @@ def cpu_baseline(obs, start, seconds):
         "sample": f"{obs.n_vis} visibilities x {len(prob.src_flux)} sky pixels "
                   f"({'whole workload' if obs.n_vis * n_src <= budget else 'first timesteps'}), "
                   f"{iters} gradient+update iteration(s) in {dt:.1f} s, FP64 direct summation",
+        "cpu_model": cpu_model(),
     }
+    out.update(single_thread_rate(prob, off, v_obs_np))
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def single_thread_rate(prob, off, v_obs):
+    """One gradient + update of the oracle on one thread, over the first
+    rows of the same problem (a child process with OMP_NUM_THREADS=1; it
+    does not touch the GPU)."""
+    import subprocess
+    import tempfile
+    rows = int(min(prob.n_row, max(1, 2e7 // max(1, len(prob.src_flux) * prob.n_chan * prob.n_pol))))
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "sample.npz")
+        np.savez(path, src_l=prob.src_l, src_m=prob.src_m, src_flux=prob.src_flux, ant1=prob.ant1[:rows],
+                 ant2=prob.ant2[:rows], uv_m=prob.uv_m[:rows], freq_hz=prob.freq_hz,
+                 offsets=np.ascontiguousarray(off[:1]), vis=np.ascontiguousarray(v_obs[:rows]),
+                 scalars=np.array([prob.n_ant, prob.n_pol, prob._s.dish_diam_m, prob._s.squint_frac,
+                                   prob._s.snap_scale]))
+        code = (
+            "import sys, time, numpy as np\n"
+            f"sys.path.insert(0, {ROOT!r})\n"
+            "import oracle\n"
+            f"z = np.load({path!r})\n"
+            "n_ant, n_pol, dish, squint, snap = z['scalars']\n"
+            "p = oracle.Problem(z['src_l'], z['src_m'], z['src_flux'], int(n_ant), z['ant1'], z['ant2'], z['uv_m'],\n"
+            "                   [0, len(z['ant1'])], z['freq_hz'], n_pol=int(n_pol), dish_diam_m=dish,\n"
+            "                   squint_frac=squint, snap_scale=snap)\n"
+            "t0 = time.perf_counter()\n"
+            "acc = oracle.gradient(p, z['offsets'], z['vis'], 1.0)\n"
+            "oracle.solve_step(acc, 0.5, z['offsets'])\n"
+            "print(time.perf_counter() - t0, oracle.num_threads())\n")
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    if r.returncode != 0:
+        return {"single_thread": f"failed: {r.stderr.strip()[-200:]}"}
+    dt, nthr = r.stdout.split()[-2:]
+    n = rows * prob.n_chan * prob.n_pol
+    return {"single_thread_vis_per_s": n / float(dt),
+            "single_thread_sample": f"{n} visibilities (first {rows} rows, one interval), "
+                                    f"{int(nthr)} thread, one gradient+update in {float(dt):.2f} s"}
 
 
 def main():

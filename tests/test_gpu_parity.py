@@ -1162,3 +1162,32 @@ def test_offsets_solve_with_beam_scales(torch_dev):
         assert np.abs(off.cpu().numpy() - ref0).max() / ARCSEC <= 0.1
     finally:
         s.close()
+
+
+def test_scale_step_matches_oracle(torch_dev):
+    """The damped scale step on random sums against the oracle's, with an
+    antenna without data, one whose step would turn sigma negative, and a
+    non-finite sum; the scales live on the observation."""
+    torch = torch_dev
+    print("case: scale step", flush=True)
+    obs = _aperture_obs(16, 4)
+    shape = (obs.n_int, obs.n_pol, obs.n_ant)
+    rng = np.random.default_rng(69)
+    sc0 = rng.uniform(0.9, 1.1, shape)
+    acc = np.zeros(shape + (3,))
+    acc[..., 0] = rng.uniform(1.0, 2.0, shape)
+    acc[..., 1] = rng.normal(0.0, 0.05, shape)
+    acc[..., 2] = rng.uniform(0.5, 2.0, shape)
+    acc[0, 0, 1, 2] = 0.0          # no data
+    acc[1, 1, 3, 1:] = [-40.0, 1.0]  # sigma would turn negative
+    acc[2, 0, 5, 1] = np.nan        # non-finite
+    ref, nu_ref, mx_ref = oracle.scale_step(acc, 0.5, sc0)
+    s = session(obs)
+    try:
+        s.set_beam_scale(sc0)
+        nu, mx = s.scale_step(torch.as_tensor(acc, device=s.dev), 0.5)
+        np.testing.assert_allclose(s.beam_scale().cpu().numpy(), ref, rtol=1e-15, atol=0.0)
+        assert np.array_equal(nu.cpu().numpy(), nu_ref)
+        np.testing.assert_allclose(mx.cpu().numpy(), mx_ref, rtol=1e-12)
+    finally:
+        s.close()
