@@ -139,7 +139,10 @@ __device__ __forceinline__ void efp(const ItemArgs& a, const float4* tab, float 
         em = e * dm * inv_s2;
         return;
     }
-    const float x = kk * sqrtf(dl * dl + dm * dm);
+    // the hardware square root (about 1 ulp; the correctly rounded sqrtf adds
+    // some fifteen instructions, which the per-sample mount-frame products
+    // pay at every image sample)
+    const float x = kk * __builtin_amdgcn_sqrtf(fmaf(dl, dl, dm * dm));
     float u = x * a.inv_dx;
     int i;
     if (!(u < (float)(a.n_tab - 2))) {  // beyond the table, or not finite: clamp
