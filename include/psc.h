@@ -72,9 +72,8 @@ typedef struct psc_obs psc_obs;
  *                2: a measured aperture (below): the far-field pattern is
  *                   the Fourier transform of the aperture illumination (Sec. 1
  *                   and Sec. 3: blockage, feed-support shadows and taper enter
- *                   through it), fixed to the antenna mount.  Every
- *                   observation is then handled in the mount frame (rows
- *                   without a par_angle are at angle zero) and degrids in the
+ *                   through it), fixed to the antenna mount (turned by each
+ *                   row's par_angle when given).  Observations degrid in the
  *                   window form; psc_set_degrid refuses the table forms.
  *  squint_frac   beam squint: polarisation 0 (1) is centred at
  *                +(-) squint_frac * HPBW(nu) along +l, HPBW = 1.02899 lambda/D

@@ -556,17 +556,16 @@ static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
     const double dx = 1.0 / 16.0;
     const int n_tab = (int)ceil(x_max / dx) + 3;
     // measured aperture: its pattern over the same range, in lambda/D units,
-    // at 32 nodes per lambda/D; the kernels evaluate it per sample in the
-    // mount frame, so every row needs an angle (zero without one)
+    // at 32 nodes per lambda/D (the window form stores its products per item
+    // in the sky frame and evaluates them per sample in the mount frame)
     const bool ap = ctx->cfg.illum == 2;
     const double ap_step = 1.0 / 32.0;
     const int ap_half = ap ? (int)ceil(rho_max * ctx->cfg.dish_diam_m / lam_min / ap_step) + 2 : 0;
     const int ap_n = 2 * ap_half + 1;
-    if (ap && pa.empty()) pa.assign(n_row > 0 ? n_row : 1, 0.0);
 
     psc_obs* obs = new psc_obs();
     obs->ctx = ctx;
-    obs->degrid = (S == 16 && pa.empty() && wv.empty()) ? PSC_DEGRID_VALU : PSC_DEGRID_WINDOW;
+    obs->degrid = (S == 16 && pa.empty() && wv.empty() && !ap) ? PSC_DEGRID_VALU : PSC_DEGRID_WINDOW;
     obs->n_ant = n_ant;
     obs->n_chan = n_chan;
     obs->n_pol = d->n_pol;
@@ -619,6 +618,13 @@ static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
         if (e == hipSuccess)
             e = hipMemcpy(cells, ctx->ap_cells.data(), sizeof(double) * ctx->ap_cells.size(), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = launch_aperture_table(cells, n_cells, obs->ap_tab, ap_n, ap_half, ap_step, nullptr);
+        // the image gradient's scatter builds each sample's kernel: in the
+        // sky frame at angle zero
+        if (e == hipSuccess && pa.empty()) {
+            const size_t nr = n_row > 0 ? (size_t)n_row : 1;
+            e = dmalloc(&obs->zero_pa, nr);
+            if (e == hipSuccess) e = hipMemset(obs->zero_pa, 0, sizeof(double) * nr);
+        }
     }
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&obs->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -873,9 +879,9 @@ PSC_API psc_status psc_image_gradient(psc_ctx* ctx, psc_obs* obs, const double* 
     a.grid_acc = ctx->rgrid;
     a.use_mfma = 0;
     PSC_HIP(ctx, launch_zero(ctx->rgrid, np, s));
-    const bool table_patch = ctx->s == 16 && !obs->par_angle && !obs->w_m && !obs->scale &&
+    const bool table_patch = ctx->s == 16 && !obs->par_angle && !obs->w_m && !obs->scale && !obs->ap_tab &&
                              grid_lds_bytes(ctx->s, ctx->m, ctx->o) <= kGridLdsMax;
-    if (table_patch || ctx->s == 32 || obs->par_angle || obs->w_m || obs->scale) {
+    if (table_patch || ctx->s == 32 || obs->par_angle || obs->w_m || obs->scale || obs->ap_tab) {
         // predict, then a patch scatter: per item with its sub-tables and its
         // samples in time order (support 16, sky frame), or with a kernel per
         // sample (support 32, mount frame, w-term)
@@ -896,8 +902,9 @@ PSC_API psc_status psc_image_gradient(psc_ctx* ctx, psc_obs* obs, const double* 
         if (table_patch) {
             PSC_HIP(ctx, launch_grid(ctx->s, a, s));
         } else {
-            // scaled beams in the sky frame: the per-sample kernels at angle zero
-            if (obs->scale && !a.par_angle) a.par_angle = obs->zero_pa;
+            // scaled beams or a measured aperture in the sky frame: the
+            // per-sample kernels at angle zero
+            if ((obs->scale || obs->ap_tab) && !a.par_angle) a.par_angle = obs->zero_pa;
             PSC_HIP(ctx, launch_gridw(ctx->s, a, s));
         }
     } else {
@@ -955,6 +962,8 @@ PSC_API psc_status psc_set_degrid(psc_obs* obs, int32_t variant)
         return fail(obs->ctx, PSC_E_UNSUPPORTED, "the w-term degrids in the window form only");
     if (obs->scale && variant != PSC_DEGRID_WINDOW)
         return fail(obs->ctx, PSC_E_UNSUPPORTED, "beam-width scales degrid in the window form only");
+    if (obs->ap_tab && variant != PSC_DEGRID_WINDOW)
+        return fail(obs->ctx, PSC_E_UNSUPPORTED, "a measured aperture degrids in the window form only");
     if (obs->graph) {  // a captured solve graph holds the old kernels
         (void)hipGraphExecDestroy(obs->graph);
         obs->graph = nullptr;
@@ -1072,7 +1081,7 @@ PSC_API psc_status psc_tune(psc_ctx* ctx, psc_obs* obs, const double* offsets_de
     int32_t best_v = obs->degrid;
     const int32_t keep = obs->degrid;
     for (int32_t v = PSC_DEGRID_VALU; v <= PSC_DEGRID_WINDOW && e == hipSuccess; ++v) {
-        if ((ctx->s != 16 || obs->par_angle || obs->w_m || obs->scale) && v != PSC_DEGRID_WINDOW) {
+        if ((ctx->s != 16 || obs->par_angle || obs->w_m || obs->scale || obs->ap_tab) && v != PSC_DEGRID_WINDOW) {
             if (times_us_out) times_us_out[v] = -1.0;  // not available at this support
             continue;
         }

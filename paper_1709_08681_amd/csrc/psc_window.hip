@@ -29,38 +29,61 @@ __host__ __device__ constexpr int win_ng(int mode)
     return mode == kGrad || mode == kScale ? 3 : mode == kVjp ? 2 : 1;
 }
 
+// A measured aperture in the sky frame (no parallactic angles): the pattern
+// is fixed for the item, so its image-plane products are stored per image
+// sample like the radial factors, but one per variant (the pattern is not
+// radial, so the derivative sums do not factor).
+constexpr int kFrameSkyAperture = 3;
+
+// Factors stored per image sample by a window kernel of the given frame and
+// mode (0: none, the mount frames evaluate them per sample).
+__host__ __device__ constexpr int win_factors(int frame, int mode)
+{
+    return frame == kFrameSky ? win_ng(mode) : frame == kFrameSkyAperture ? mode_nv(mode) : 0;
+}
+
 // Image-plane factors of an item at the M x M samples, [n][NG]: g = E_i E_j c
 // and, for the offsets' derivatives, the gradient factors q_i E_j c and
 // E_i q_j c (dE/dp = q (l - p)), from which the sum forms the four derivative
 // variants of Eq. DA; for the beam scales, dE/dsigma = q |l - p|^2 / sigma in
-// place of q.  bi, bj: each antenna's beam constants (its width scale applied).
-template <int MODE>
+// place of q.  AP: a measured aperture, one stored product per variant (as
+// mf_products_ap at angle zero).  bi, bj: each antenna's beam constants (its
+// width scale applied).
+template <int MODE, bool AP>
 __device__ __forceinline__ void image_factors(const ItemArgs& a, float* gsh, const BeamK& bi, const BeamK& bj,
                                               float pil, float pim, float pjl, float pjm, int tid, int nthr)
 {
-    constexpr int NG = win_ng(MODE);
+    constexpr int NG = AP ? mode_nv(MODE) : win_ng(MODE);
     const int m = a.m, half_m = m >> 1, m2 = m * m;
     const float hstep = (float)a.h;
     for (int idx = tid; idx < m2; idx += nthr) {
         const int il = idx / m, im = idx - il * m;
         const float l = (float)(il - half_m) * hstep, mm = (float)(im - half_m) * hstep;
-        float ei, qi, ej, qj;
         const float dli = l - pil, dmi = mm - pim, dlj = l - pjl, dmj = mm - pjm;
-        efq(a, a.airy, bi.kk, bi.inv_s2, dli, dmi, ei, qi);
-        efq(a, a.airy, bj.kk, bj.inv_s2, dlj, dmj, ej, qj);
         const float c = a.taper_img[il] * a.taper_img[im];
         float* gn = gsh + idx * NG;
-        if constexpr (MODE == kPredict) {
-            gn[0] = ei * ej * c;
-        } else if constexpr (MODE == kScale) {
-            gn[0] = ei * ej * c;
-            gn[1] = qi * fmaf(dli, dli, dmi * dmi) * bi.rsig * ej * c;
-            gn[2] = ei * qj * fmaf(dlj, dlj, dmj * dmj) * bj.rsig * c;
+        if constexpr (AP) {
+            // the sky frame is the mount frame at angle zero
+            float g[mode_nv(MODE)];
+            mf_products_ap<MODE>(a, bi, bj, 1.f, 0.f, dli, dmi, dlj, dmj, c, g);
+#pragma unroll
+            for (int k = 0; k < NG; ++k) gn[k] = g[k];
         } else {
-            constexpr int o = MODE == kGrad ? 1 : 0;
-            if constexpr (MODE == kGrad) gn[0] = ei * ej * c;
-            gn[o] = qi * ej * c;
-            gn[o + 1] = ei * qj * c;
+            float ei, qi, ej, qj;
+            efq(a, a.airy, bi.kk, bi.inv_s2, dli, dmi, ei, qi);
+            efq(a, a.airy, bj.kk, bj.inv_s2, dlj, dmj, ej, qj);
+            if constexpr (MODE == kPredict) {
+                gn[0] = ei * ej * c;
+            } else if constexpr (MODE == kScale) {
+                gn[0] = ei * ej * c;
+                gn[1] = qi * fmaf(dli, dli, dmi * dmi) * bi.rsig * ej * c;
+                gn[2] = ei * qj * fmaf(dlj, dlj, dmj * dmj) * bj.rsig * c;
+            } else {
+                constexpr int o = MODE == kGrad ? 1 : 0;
+                if constexpr (MODE == kGrad) gn[0] = ei * ej * c;
+                gn[o] = qi * ej * c;
+                gn[o + 1] = ei * qj * c;
+            }
         }
     }
 }
@@ -139,7 +162,10 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
     constexpr int NV = mode_nv(MODE);
     constexpr int NC = mode_nc(MODE);
     constexpr int NCP = NC > 0 ? NC : 1;
-    constexpr int NG = win_ng(MODE);  // image-plane factors per sample (sky frame)
+    constexpr bool SKY = MF == kFrameSky || MF == kFrameSkyAperture;  // factors stored per image sample
+    // one stored factor per variant, summed plainly (no factored derivatives)
+    constexpr bool PLAIN = MODE == kScale || MF == kFrameSkyAperture;
+    constexpr int NG = SKY ? win_factors(MF, MODE) : 1;  // image-plane factors per image sample
     constexpr int kBlock = 64 * W;
     static_assert(NC <= SL, "one term per lane");
 
@@ -154,7 +180,7 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
     double* gpart = reinterpret_cast<double*>(smem);  // [NW][NCP]
     Group* grp = reinterpret_cast<Group*>(gpart + NW * NCP);
     float* gsh = reinterpret_cast<float*>(grp + win_max_groups(O));
-    float2* wtile = reinterpret_cast<float2*>(gsh + (MF != kFrameSky ? 0 : NG * m2p));
+    float2* wtile = reinterpret_cast<float2*>(gsh + (SKY ? NG * m2p : 0));
     float4* airy_sh = reinterpret_cast<float4*>(wtile + (size_t)NW * S * SP);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -287,8 +313,9 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
             bki = beam_k(kk, inv_s2, aps, (float)sc[it.ai]);
             bkj = beam_k(kk, inv_s2, aps, (float)sc[it.aj]);
         }
-        if constexpr (MF == kFrameSky)
-            image_factors<MODE>(a, gsh, bki, bkj, (float)qil, (float)qim, (float)qjl, (float)qjm, tid, kBlock);
+        if constexpr (SKY)
+            image_factors<MODE, MF == kFrameSkyAperture>(a, gsh, bki, bkj, (float)qil, (float)qim, (float)qjl,
+                                                         (float)qjm, tid, kBlock);
         __syncthreads();
 
         double acc64 = 0.0;
@@ -349,7 +376,7 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
 #pragma unroll
             for (int k = 0; k < NV; ++k) A[k] = B[k] = zero;
             float cs = 1.f, sn = 0.f;
-            if constexpr (MF != kFrameSky) {
+            if constexpr (!SKY) {
                 // this row's beam centres on the sky
                 sincosf((float)a.par_angle[e0.vidx / (uint32_t)a.n_chan], &sn, &cs);
                 const float pil = (float)(cs * qil - sn * qim), pim = (float)(sn * qil + cs * qim);
@@ -390,19 +417,19 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
                     for (int jl = j0; jl < j1; ++jl, tp += SP, g += m * NG) {
                         float2 t = *tp;
                         if constexpr (WT) t = cmul(t, wphase(w0, (float)(jl - half_m) * hstep));
-                        if constexpr (MODE == kScale) {
-                            // three plain sums: V and the two scale derivatives
+                        if constexpr (PLAIN) {
+                            // one plain sum per variant
 #pragma unroll
-                            for (int k = 0; k < 3; ++k) {
+                            for (int k = 0; k < NV; ++k) {
                                 acc[k].x = fmaf(g[k], t.x, acc[k].x);
                                 acc[k].y = fmaf(g[k], t.y, acc[k].y);
                             }
                         }
-                        if constexpr (MODE != kVjp && MODE != kScale) {
+                        if constexpr (MODE != kVjp && !PLAIN) {
                             acc[0].x = fmaf(g[0], t.x, acc[0].x);
                             acc[0].y = fmaf(g[0], t.y, acc[0].y);
                         }
-                        if constexpr (MODE != kPredict && MODE != kScale) {
+                        if constexpr (MODE != kPredict && !PLAIN) {
                             constexpr int o = MODE == kGrad ? 1 : 0;
                             const float l = (float)(jl - half_m) * hstep;
                             const float2 tl = make_float2(t.x * l, t.y * l);
@@ -435,7 +462,7 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
                 const float2 rb = cmul(rho, B[k]);
                 s[k] = cmul(pm, make_float2(A[k].x + rb.x, A[k].y + rb.y));
             }
-            if constexpr (MF == kFrameSky && MODE != kPredict && MODE != kScale) {
+            if constexpr (SKY && !PLAIN && MODE != kPredict) {
                 // derivative variants from the factored sums (the lane's m coordinate is mmy)
                 constexpr int o = MODE == kGrad ? 1 : 0;
                 const float pl[2] = {(float)qil, (float)qjl}, pmm[2] = {(float)qim, (float)qjm};
@@ -507,10 +534,20 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
     }
 }
 
+// Dynamic LDS of a k_winw block of the given frame: winw_lds_bytes, with the
+// stored factors counted per frame.
+static size_t winw_frame_lds(int support, int waves, int mode, int frame, int m, int oversample, int n_tab)
+{
+    const size_t m2p = (size_t)((m * m + 3) & ~3);
+    const int tab = frame == kFrameMount ? n_tab : frame == kFrameSky ? -1 : 0;
+    size_t b = winw_lds_bytes(support, waves, mode, m, oversample, tab);
+    if (frame == kFrameSkyAperture) b += sizeof(float) * (size_t)win_factors(frame, mode) * m2p;
+    return b;
+}
+
 template <int S, int MODE, int MF, bool WT>
 static hipError_t launch_win_t(const ItemArgs& a, hipStream_t s)
 {
-    const int tab = MF == kFrameMount ? a.n_tab : MF == kFrameAperture ? 0 : -1;
     const size_t budget = win_lds_budget(S);
     // raise the dynamic LDS limit once, to what one compute unit allows
     static const hipError_t attr4 = hipFuncSetAttribute(
@@ -519,7 +556,7 @@ static hipError_t launch_win_t(const ItemArgs& a, hipStream_t s)
     const int blocks = 8 * ((a.n_items + 7) / 8);
     // four wavefronts when two blocks fit a compute unit's LDS, else eight
     // (support 32 with many image samples)
-    const size_t sh4 = winw_lds_bytes(S, 4, MODE, a.m, a.oversample, tab);
+    const size_t sh4 = winw_frame_lds(S, 4, MODE, MF, a.m, a.oversample, a.n_tab);
     if (2 * (sh4 + (160 * 1024 - budget)) <= 160 * 1024) {
         k_winw<S, MODE, MF, 4, WT><<<blocks, 64 * 4, sh4, s>>>(a);
         return hipGetLastError();
@@ -528,7 +565,7 @@ static hipError_t launch_win_t(const ItemArgs& a, hipStream_t s)
         static const hipError_t attr8 = hipFuncSetAttribute(
             (const void*)k_winw<S, MODE, MF, 8, WT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget);
         if (attr8 != hipSuccess) return attr8;
-        const size_t sh8 = winw_lds_bytes(S, 8, MODE, a.m, a.oversample, tab);
+        const size_t sh8 = winw_frame_lds(S, 8, MODE, MF, a.m, a.oversample, a.n_tab);
         if (sh8 > budget) return hipErrorInvalidValue;
         k_winw<S, MODE, MF, 8, WT><<<blocks, 64 * 8, sh8, s>>>(a);
         return hipGetLastError();
@@ -540,9 +577,12 @@ template <int S, int MODE>
 static hipError_t launch_win_m(const ItemArgs& a, hipStream_t s)
 {
     const bool wt = a.w_m != nullptr;
-    if (a.ap_tab != nullptr)
+    if (a.ap_tab != nullptr && a.par_angle != nullptr)
         return wt ? launch_win_t<S, MODE, kFrameAperture, true>(a, s)
                   : launch_win_t<S, MODE, kFrameAperture, false>(a, s);
+    if (a.ap_tab != nullptr)
+        return wt ? launch_win_t<S, MODE, kFrameSkyAperture, true>(a, s)
+                  : launch_win_t<S, MODE, kFrameSkyAperture, false>(a, s);
     if (a.par_angle != nullptr)
         return wt ? launch_win_t<S, MODE, kFrameMount, true>(a, s) : launch_win_t<S, MODE, kFrameMount, false>(a, s);
     return wt ? launch_win_t<S, MODE, kFrameSky, true>(a, s) : launch_win_t<S, MODE, kFrameSky, false>(a, s);
