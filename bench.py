@@ -149,6 +149,8 @@ def extension_timing(obs, start, reps, what, device=0):
                          parallactic angle), per-sample image-plane products;
       measured_aperture  the same with a measured, non-circular aperture
                          (bicubic lookups of its transform);
+      measured_aperture_sky  the aperture without parallactic angles (its
+                         products stored per item, five plain sums);
       beam_scale         psc_scale_gradient: the sums for a beam-width scale
                          per antenna (scales set within 3% of nominal);
       w_term             the workload's array shrunk to arms of 1 km (the
@@ -163,6 +165,9 @@ def extension_timing(obs, start, reps, what, device=0):
     elif what == "measured_aperture":
         kw = dict(mount_frame=True, aperture=synth.measured_aperture())
         note = "window form, per-sample bicubic lookups of the aperture's transform, mount frame"
+    elif what == "measured_aperture_sky":
+        kw = dict(aperture=synth.measured_aperture())
+        note = "window form, the aperture's products stored per item, sky frame"
     elif what == "beam_scale":
         kw, note = dict(mount_frame=True), "psc_scale_gradient, window form, mount frame"
     elif what == "w_term":
@@ -407,7 +412,7 @@ def main():
         out["mount_frame"] = extension_timing(obs, start, 3, "mount_frame")
     if not args.no_extensions:
         out["extensions"] = {}
-        for what in ("measured_aperture", "beam_scale", "w_term"):
+        for what in ("measured_aperture", "measured_aperture_sky", "beam_scale", "w_term"):
             print(f"bench: {what}", file=sys.stderr, flush=True)
             out["extensions"][what] = extension_timing(obs, start, 3, what)
     if not args.no_batched:
