@@ -1191,3 +1191,40 @@ def test_scale_step_matches_oracle(torch_dev):
         np.testing.assert_allclose(mx.cpu().numpy(), mx_ref, rtol=1e-12)
     finally:
         s.close()
+
+
+@pytest.mark.parametrize("mount", [False, True])
+def test_extensions_together(torch_dev, mount):
+    """The measured aperture, beam scales and the w-term at once (baselines
+    to 3 km, field at 0.85 of the support's limit): prediction, the offsets'
+    sums, the scale sums and the image gradient against the oracle."""
+    torch = torch_dev
+    print(f"case: aperture + scales + w-term, mount {mount}", flush=True)
+    lengths = [5, 3, 6]
+    wl = synth.workload(1, n_ant=7, n_time=sum(lengths), dt_s=600.0, interval_lengths=lengths, n_pol=2,
+                        squint_frac=0.03, freqs_hz=np.array([1.2e9, 1.6e9]), n_src=5, fov_frac=0.85,
+                        layout_radius_m=3000.0)
+    obs = synth.make_observation(wl, 97)
+    A = synth.measured_aperture(seed=15)
+    sc = np.random.default_rng(70).uniform(0.96, 1.04, (obs.n_int, obs.n_pol, obs.n_ant))
+    prob = oracle.Problem.from_observation(obs, mount_frame=mount, w_term=True, illum=2, aperture=A,
+                                           beam_scale=sc)
+    s = session(obs, mount_frame=mount, w_term=True, aperture=A)
+    try:
+        s.set_beam_scale(sc)
+        start = synth.perturbed_offsets(obs, 25.0, 71)
+        assert rel(s.predict(start).cpu().numpy(), oracle.predict(prob, start)) <= 1e-5
+        v = oracle.predict(prob, obs.offsets_true)
+        nz, w = synth.noise(v, 100.0, 72)
+        vo_d, w_d = c64(torch, s, v + nz), f32(torch, s, w, s.vis_shape)
+        ref = oracle.gradient(prob, start, v + nz, w)
+        acc = s.gradient(s.offsets(start), vo_d, w_d).cpu().numpy()
+        for k in range(6):
+            assert rel(acc[..., k], ref[..., k]) <= 1e-4, k
+        ref3 = oracle.scale_gradient(prob, start, v + nz, w)
+        acc3 = s.scale_gradient(s.offsets(start), vo_d, w_d).cpu().numpy()
+        for k in range(3):
+            assert rel(acc3[..., k], ref3[..., k]) <= 1e-4, k
+        _check_image_gradient(torch, obs, prob, s, start, v + nz, w, 32, 73)
+    finally:
+        s.close()
