@@ -116,3 +116,8 @@ def test_null_arguments(psc):
     assert lib.psc_set_model(None, None, None) == -1
     assert lib.psc_predict(None, None, None, None, None) == -1
     assert lib.psc_last_error(None) is not None
+    assert lib.psc_set_beam_scale(None, None, None, None) == -1
+    assert lib.psc_get_beam_scale(None, None, None, None) == -1
+    assert lib.psc_scale_gradient(None, None, None, None, None, None, None) == -1
+    assert lib.psc_scale_step(None, None, None, 0.5, None, None, None) == -1
+    assert lib.psc_image_gradient(None, None, None, None, None, None, None, None) == -1
