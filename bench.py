@@ -71,16 +71,17 @@ def describe(obs):
     }
 
 
-def batched_vs_plain(cfg, iters, device=0):
+def batched_vs_plain(cfg, iters, device=0, **overrides):
     """Algorithm 1 over every solution interval of workload `cfg` for a fixed
     number of iterations (tol = 0), in the three execution forms: PLAIN (host
     loop over intervals, launches per interval, host check per iteration),
     BATCHED (every interval in one launch set per iteration) and GRAPH
-    (BATCHED, all iterations captured in one HIP graph and replayed)."""
+    (BATCHED, all iterations captured in one HIP graph and replayed).
+    `overrides` change the workload (e.g. its interval lengths)."""
     import torch
     from paper_1709_08681_amd import synth
     from paper_1709_08681_amd import psc as P
-    obs = synth.make_config(cfg)
+    obs = synth.make_config(cfg, **overrides)
     s = P.Session(obs, device=device)
     try:
         v_obs = s.predict(s.offsets(obs.offsets_true))
@@ -419,6 +420,12 @@ def main():
         print(f"bench: batched vs plain on workload {args.batched_config}", file=sys.stderr,
               flush=True)
         out["batched_vs_plain"] = batched_vs_plain(args.batched_config, args.batched_iters)
+        # the same array with 1024 short intervals (1 to 8 timesteps): per-interval
+        # launches then carry little work each
+        short = [int(x) for x in np.random.default_rng(7).integers(1, 9, size=1024)]
+        print("bench: batched vs plain, short intervals", file=sys.stderr, flush=True)
+        out["batched_vs_plain_short"] = batched_vs_plain(args.batched_config, args.batched_iters,
+                                                         interval_lengths=short)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(obs, start, args.cpu_seconds)
