@@ -53,6 +53,7 @@ struct psc_obs {
     float4* ap_tab = nullptr;  // measured aperture: pattern table [ap_n][ap_n]
     double* scale = nullptr;   // beam-width scales [n_int][n_pol][n_ant] (null: all 1)
     double* zero_pa = nullptr; // [n_row] zeros: the per-sample scatter's angles with scales, sky frame
+    int32_t win_waves = 0;     // window-form block size at support 16 (see ItemArgs)
     int32_t ap_n = 0;
     double ap_c = 0, ap_step = 0;
     double* partials = nullptr;  // [n_items][n_pol][12]
@@ -577,6 +578,10 @@ static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
     obs->n_vis = (int64_t)vis.size();
     obs->n_tab = n_tab;
     obs->inv_dx = 1.0 / dx;
+    // items of fewer than 128 samples on average: window-form blocks of two
+    // wavefronts (measured on the batched array: 42.8 vs 60.0 ms per gradient
+    // at 4.6 samples per item, 68.5 vs 72.3 ms at 65; 6% slower at 360)
+    obs->win_waves = (S == 16 && !items.empty() && (double)vis.size() < 128.0 * (double)items.size()) ? 2 : 0;
     hipError_t e = dmalloc(&obs->items, items.size());
     if (e == hipSuccess) e = dmalloc(&obs->groups, groups.size());
     if (e == hipSuccess) e = dmalloc(&obs->vis, vis.size());
@@ -687,6 +692,7 @@ ItemArgs item_args(psc_ctx* ctx, psc_obs* obs, const double* offsets, int item_b
     a.ap_c = (float)obs->ap_c;
     a.ap_inv_step = obs->ap_step > 0 ? (float)(1.0 / obs->ap_step) : 0.f;
     a.scale = obs->scale;
+    a.win_waves = obs->win_waves;
     a.partials = obs->partials;
     a.done = done;
     a.use_mfma = obs->degrid == PSC_DEGRID_MFMA ? 1 : 0;

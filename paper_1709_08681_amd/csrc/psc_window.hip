@@ -554,6 +554,17 @@ static hipError_t launch_win_t(const ItemArgs& a, hipStream_t s)
         (const void*)k_winw<S, MODE, MF, 4, WT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget);
     if (attr4 != hipSuccess) return attr4;
     const int blocks = 8 * ((a.n_items + 7) / 8);
+    if constexpr (S == 16) {
+        // items of few samples: two wavefronts (four workers) per block
+        if (a.win_waves == 2) {
+            static const hipError_t attr2 = hipFuncSetAttribute(
+                (const void*)k_winw<S, MODE, MF, 2, WT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget);
+            if (attr2 != hipSuccess) return attr2;
+            const size_t sh2 = winw_frame_lds(S, 2, MODE, MF, a.m, a.oversample, a.n_tab);
+            k_winw<S, MODE, MF, 2, WT><<<blocks, 64 * 2, sh2, s>>>(a);
+            return hipGetLastError();
+        }
+    }
     // four wavefronts when two blocks fit a compute unit's LDS, else eight
     // (support 32 with many image samples)
     const size_t sh4 = winw_frame_lds(S, 4, MODE, MF, a.m, a.oversample, a.n_tab);
