@@ -578,10 +578,13 @@ static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
     obs->n_vis = (int64_t)vis.size();
     obs->n_tab = n_tab;
     obs->inv_dx = 1.0 / dx;
-    // items of fewer than 128 samples on average: window-form blocks of two
-    // wavefronts (measured on the batched array: 42.8 vs 60.0 ms per gradient
-    // at 4.6 samples per item, 68.5 vs 72.3 ms at 65; 6% slower at 360)
-    obs->win_waves = (S == 16 && !items.empty() && (double)vis.size() < 128.0 * (double)items.size()) ? 2 : 0;
+    // items of few samples on average: window-form blocks of one wavefront
+    // below 16 samples per item, of two below 128 (measured on the batched
+    // array: at 4.6 samples per item 36.3 ms per gradient with one, 42.8
+    // with two, 60.0 with four wavefronts; at 65, 68.5 with two against 69
+    // with one and 72.3 with four; at 360 two were 6% slower than four)
+    const double per_item = items.empty() ? 0.0 : (double)vis.size() / (double)items.size();
+    obs->win_waves = S != 16 || items.empty() ? 0 : per_item < 16.0 ? 1 : per_item < 128.0 ? 2 : 0;
     hipError_t e = dmalloc(&obs->items, items.size());
     if (e == hipSuccess) e = dmalloc(&obs->groups, groups.size());
     if (e == hipSuccess) e = dmalloc(&obs->vis, vis.size());

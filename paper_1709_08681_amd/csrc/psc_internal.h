@@ -100,9 +100,9 @@ struct ItemArgs {
     // nullable [n_int][n_pol][n_ant]: beam-width scale sigma of each antenna,
     // pattern E0(d / sigma) (per-sample products: mount-frame paths only)
     const double* scale;
-    // window form at support 16: 2 for blocks of two wavefronts (items of
-    // few samples, where four would leave workers idle), 0 to size blocks by
-    // LDS alone
+    // window form at support 16: 1 or 2 for blocks of one or two wavefronts
+    // (items of few samples, where four would leave workers idle), 0 to size
+    // blocks by LDS alone
     int32_t win_waves;
     int32_t use_mfma;           // degrid on the matrix cores (gradient and adjoint)
     // image-gradient scatter (k_grid)

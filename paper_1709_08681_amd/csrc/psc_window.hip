@@ -555,7 +555,16 @@ static hipError_t launch_win_t(const ItemArgs& a, hipStream_t s)
     if (attr4 != hipSuccess) return attr4;
     const int blocks = 8 * ((a.n_items + 7) / 8);
     if constexpr (S == 16) {
-        // items of few samples: two wavefronts (four workers) per block
+        // items of few samples: one or two wavefronts (two or four workers)
+        // per block
+        if (a.win_waves == 1) {
+            static const hipError_t attr1 = hipFuncSetAttribute(
+                (const void*)k_winw<S, MODE, MF, 1, WT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget);
+            if (attr1 != hipSuccess) return attr1;
+            const size_t sh1 = winw_frame_lds(S, 1, MODE, MF, a.m, a.oversample, a.n_tab);
+            k_winw<S, MODE, MF, 1, WT><<<blocks, 64, sh1, s>>>(a);
+            return hipGetLastError();
+        }
         if (a.win_waves == 2) {
             static const hipError_t attr2 = hipFuncSetAttribute(
                 (const void*)k_winw<S, MODE, MF, 2, WT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget);
