@@ -166,7 +166,10 @@ __device__ __forceinline__ void efp(const ItemArgs& a, const float4* tab, float 
 
 // The same pattern in factored form: E and the factor q of its gradient with
 // respect to the pointing offset, dE/dp = q (dl, dm) (the pattern depends on
-// |l - p| alone, so the gradient points along l - p).
+// |l - p| alone, so the gradient points along l - p).  HW: the hardware square
+// root instead of the correctly rounded one (faster in some kernels, slower
+// in others through register allocation: chosen by measurement).
+template <bool HW = false>
 __device__ __forceinline__ void efq(const ItemArgs& a, const float4* tab, float kk, float inv_s2, float dl,
                                     float dm, float& e, float& q)
 {
@@ -175,7 +178,7 @@ __device__ __forceinline__ void efq(const ItemArgs& a, const float4* tab, float 
         q = e * inv_s2;
         return;
     }
-    const float x = kk * sqrtf(dl * dl + dm * dm);
+    const float x = HW ? kk * __builtin_amdgcn_sqrtf(fmaf(dl, dl, dm * dm)) : kk * sqrtf(dl * dl + dm * dm);
     float u = x * a.inv_dx;
     int i;
     if (!(u < (float)(a.n_tab - 2))) {  // beyond the table, or not finite: clamp

@@ -48,8 +48,9 @@ __host__ __device__ constexpr int win_factors(int frame, int mode)
 // variants of Eq. DA; for the beam scales, dE/dsigma = q |l - p|^2 / sigma in
 // place of q.  AP: a measured aperture, one stored product per variant (as
 // mf_products_ap at angle zero).  bi, bj: each antenna's beam constants (its
-// width scale applied).
-template <int MODE, bool AP>
+// width scale applied).  HW: the hardware square root in the beam lookups
+// (2.6% faster at support 32, 16% slower at 16).
+template <int MODE, bool AP, bool HW>
 __device__ __forceinline__ void image_factors(const ItemArgs& a, float* gsh, const BeamK& bi, const BeamK& bj,
                                               float pil, float pim, float pjl, float pjm, int tid, int nthr)
 {
@@ -70,8 +71,8 @@ __device__ __forceinline__ void image_factors(const ItemArgs& a, float* gsh, con
             for (int k = 0; k < NG; ++k) gn[k] = g[k];
         } else {
             float ei, qi, ej, qj;
-            efq(a, a.airy, bi.kk, bi.inv_s2, dli, dmi, ei, qi);
-            efq(a, a.airy, bj.kk, bj.inv_s2, dlj, dmj, ej, qj);
+            efq<HW>(a, a.airy, bi.kk, bi.inv_s2, dli, dmi, ei, qi);
+            efq<HW>(a, a.airy, bj.kk, bj.inv_s2, dlj, dmj, ej, qj);
             if constexpr (MODE == kPredict) {
                 gn[0] = ei * ej * c;
             } else if constexpr (MODE == kScale) {
@@ -314,8 +315,8 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
             bkj = beam_k(kk, inv_s2, aps, (float)sc[it.aj]);
         }
         if constexpr (SKY)
-            image_factors<MODE, MF == kFrameSkyAperture>(a, gsh, bki, bkj, (float)qil, (float)qim, (float)qjl,
-                                                         (float)qjm, tid, kBlock);
+            image_factors<MODE, MF == kFrameSkyAperture, S == 32>(a, gsh, bki, bkj, (float)qil, (float)qim,
+                                                                   (float)qjl, (float)qjm, tid, kBlock);
         __syncthreads();
 
         double acc64 = 0.0;
