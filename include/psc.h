@@ -377,6 +377,22 @@ PSC_API psc_status psc_scale_gradient(psc_ctx* ctx, psc_obs* obs, const double* 
 PSC_API psc_status psc_scale_step(psc_ctx* ctx, psc_obs* obs, const double* acc_dev, double gain,
                                   int32_t* not_updated_dev, double* max_step_out_dev, void* stream);
 
+/*
+ * Solve for the observation's beam scales at fixed offsets (async), as
+ * Algorithm 1 solves for the offsets, with every interval in one launch set
+ * per iteration: up to n_max rounds of psc_scale_gradient and psc_scale_step
+ * on the device; an interval stops once its largest |delta sigma| is below
+ * tol (finished intervals are skipped by every kernel).  The scales are
+ * updated in place on the observation (psc_get_beam_scale reads them).
+ *  offsets_dev      [n_int][n_pol][n_ant][2] float64, not changed
+ *  vis_obs_dev, weight_dev  as for psc_gradient
+ *  iters_out_dev    nullable [n_int] int32: steps taken per interval
+ * PSC_E_STATE without scales set.
+ */
+PSC_API psc_status psc_solve_scale(psc_ctx* ctx, psc_obs* obs, const double* offsets_dev, const void* vis_obs_dev,
+                                   const float* weight_dev, double gain, int32_t n_max, double tol,
+                                   int32_t* iters_out_dev, void* stream);
+
 /* Execution forms of psc_solve. */
 #define PSC_SOLVE_PLAIN 0    /* host loop over intervals, one launch set per interval */
 #define PSC_SOLVE_BATCHED 1  /* every interval in one launch set per iteration */

@@ -1071,7 +1071,35 @@ PSC_API psc_status psc_scale_step(psc_ctx* ctx, psc_obs* obs, const double* acc_
     if (!obs->scale) return fail(ctx, PSC_E_STATE, "no beam scales set (psc_set_beam_scale)");
     PSC_HIP(ctx, hipSetDevice(ctx->cfg.device));
     PSC_HIP(ctx, launch_scale_step(obs->n_int, obs->n_pol, obs->n_ant, acc_dev, gain, obs->scale, not_updated_dev,
-                                   max_step_out_dev, (hipStream_t)stream));
+                                   max_step_out_dev, nullptr, nullptr, 0.0, (hipStream_t)stream));
+    return PSC_OK;
+}
+
+PSC_API psc_status psc_solve_scale(psc_ctx* ctx, psc_obs* obs, const double* offsets_dev, const void* vis_obs_dev,
+                                   const float* weight_dev, double gain, int32_t n_max, double tol,
+                                   int32_t* iters_out_dev, void* stream)
+{
+    psc_status st = check_call(ctx, obs, offsets_dev);
+    if (st != PSC_OK) return st;
+    if ((!vis_obs_dev || !weight_dev) && obs->n_vis > 0) return fail(ctx, PSC_E_ARG, "null data");
+    if (!(gain > 0.0) || !(gain <= 1.0)) return fail(ctx, PSC_E_ARG, "gain must be in (0, 1]");
+    if (n_max < 0 || !(tol >= 0.0)) return fail(ctx, PSC_E_ARG, "n_max must be >= 0 and tol >= 0");
+    if (!obs->scale) return fail(ctx, PSC_E_STATE, "no beam scales set (psc_set_beam_scale)");
+    hipStream_t s = (hipStream_t)stream;
+    PSC_HIP(ctx, launch_init_state(obs->done, obs->iters, obs->n_int, s));
+    ItemArgs a = item_args(ctx, obs, offsets_dev, 0, (int)obs->n_items, obs->done);
+    a.vis_in = (const float2*)vis_obs_dev;
+    a.weight = weight_dev;
+    // every interval in one launch set per iteration; finished intervals are
+    // skipped by every kernel (their items, sums and steps)
+    for (int it = 0; it < n_max; ++it) {
+        PSC_HIP(ctx, launch_win(kScale, ctx->s, a, s));
+        PSC_HIP(ctx, launch_reduce(6, reduce_args(obs, 0, obs->n_int, obs->acc, obs->done), s));
+        PSC_HIP(ctx, launch_scale_step(obs->n_int, obs->n_pol, obs->n_ant, obs->acc, gain, obs->scale, nullptr,
+                                       obs->max_step, obs->done, obs->iters, tol, s));
+    }
+    if (iters_out_dev)
+        PSC_HIP(ctx, hipMemcpyAsync(iters_out_dev, obs->iters, sizeof(int32_t) * obs->n_int, hipMemcpyDeviceToDevice, s));
     return PSC_OK;
 }
 

@@ -149,8 +149,10 @@ hipError_t launch_aperture_table(const double* cells, int n_cells, float4* tab, 
                                  hipStream_t s);
 // Damped step of the beam-width scales (psc_scale.hip): per (interval, pol,
 // antenna) sigma += gain g / H from acc3 = (chi, g, H); one block per interval.
+// done, iters (nullable): solve state, as for the offsets' step.
 hipError_t launch_scale_step(int n_int, int n_pol, int n_ant, const double* acc3, double gain, double* scale,
-                             int32_t* not_updated, double* max_step, hipStream_t s);
+                             int32_t* not_updated, double* max_step, int32_t* done, int32_t* iters, double tol,
+                             hipStream_t s);
 hipError_t launch_zero(double2* p, size_t n, hipStream_t s);
 hipError_t launch_unpad_grid(const double2* g, double2* out, int n, int pad, hipStream_t s);
 hipError_t launch_image_grad(const double2* f, const double* taper_pix, double* out, int n, hipStream_t s);

@@ -8,13 +8,20 @@ namespace psc {
 
 // One block per interval: sigma += gain g / H for every (pol, antenna) with
 // H > 0, finite sums and a positive result; others are left as they are and
-// flagged.  The block's largest |delta sigma| goes to max_step[s].
+// flagged.  The block's largest |delta sigma| goes to max_step[s].  With
+// solve state (done, iters non-null): a finished interval is skipped, and an
+// interval whose step falls below tol is marked finished.
 __global__ void __launch_bounds__(256)
 k_scale_step(int n_pol, int n_ant, const double* __restrict__ acc3, double gain, double* __restrict__ scale,
-             int32_t* __restrict__ not_updated, double* __restrict__ max_step)
+             int32_t* __restrict__ not_updated, double* __restrict__ max_step, int32_t* __restrict__ done,
+             int32_t* __restrict__ iters, double tol)
 {
     __shared__ double smax[256];
     const int s = blockIdx.x, tid = threadIdx.x;
+    if (done != nullptr && done[s]) {
+        if (tid == 0 && max_step != nullptr) max_step[s] = 0.0;
+        return;
+    }
     const int npa = n_pol * n_ant;
     double mx = 0.0;
     for (int k = tid; k < npa; k += 256) {
@@ -35,14 +42,19 @@ k_scale_step(int n_pol, int n_ant, const double* __restrict__ acc3, double gain,
         if (tid < w) smax[tid] = fmax(smax[tid], smax[tid + w]);
         __syncthreads();
     }
-    if (tid == 0 && max_step != nullptr) max_step[s] = smax[0];
+    if (tid == 0) {
+        if (max_step != nullptr) max_step[s] = smax[0];
+        if (iters != nullptr) iters[s] += 1;
+        if (done != nullptr) done[s] = smax[0] < tol ? 1 : 0;
+    }
 }
 
 hipError_t launch_scale_step(int n_int, int n_pol, int n_ant, const double* acc3, double gain, double* scale,
-                             int32_t* not_updated, double* max_step, hipStream_t s)
+                             int32_t* not_updated, double* max_step, int32_t* done, int32_t* iters, double tol,
+                             hipStream_t s)
 {
     if (n_int <= 0) return hipSuccess;
-    k_scale_step<<<n_int, 256, 0, s>>>(n_pol, n_ant, acc3, gain, scale, not_updated, max_step);
+    k_scale_step<<<n_int, 256, 0, s>>>(n_pol, n_ant, acc3, gain, scale, not_updated, max_step, done, iters, tol);
     return hipGetLastError();
 }
 

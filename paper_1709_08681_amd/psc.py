@@ -30,7 +30,7 @@ EXPORTS = ["psc_version", "psc_create", "psc_destroy", "psc_last_error", "psc_se
            "psc_obs_create", "psc_obs_destroy", "psc_obs_info", "psc_predict", "psc_gradient",
            "psc_predict_vjp", "psc_solve_step", "psc_solve", "psc_set_degrid", "psc_get_degrid",
            "psc_tune", "psc_image_gradient", "psc_set_beam_scale", "psc_get_beam_scale",
-           "psc_scale_gradient", "psc_scale_step"]
+           "psc_scale_gradient", "psc_scale_step", "psc_solve_scale"]
 
 
 class PscError(RuntimeError):
@@ -95,6 +95,7 @@ def load():
             "psc_get_beam_scale": ([vp, vp, vp, vp], C.c_int),
             "psc_scale_gradient": ([vp, vp, vp, vp, vp, vp, vp], C.c_int),
             "psc_scale_step": ([vp, vp, vp, dbl, vp, vp, vp], C.c_int),
+            "psc_solve_scale": ([vp, vp, vp, vp, vp, dbl, i32, dbl, vp, vp], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -221,6 +222,12 @@ def psc_scale_gradient(ctx, obs, offsets_dev, vis_obs_dev, weight_dev, acc_out_d
 def psc_scale_step(ctx, obs, acc_dev, gain, not_updated_dev=None, max_step_dev=None, stream=None):
     _check(load().psc_scale_step(ctx, obs, _ptr(acc_dev), float(gain), _ptr(not_updated_dev),
                                  _ptr(max_step_dev), _stream(stream)), ctx)
+
+
+def psc_solve_scale(ctx, obs, offsets_dev, vis_obs_dev, weight_dev, gain, n_max, tol, iters_dev=None,
+                    stream=None):
+    _check(load().psc_solve_scale(ctx, obs, _ptr(offsets_dev), _ptr(vis_obs_dev), _ptr(weight_dev), float(gain),
+                                  int(n_max), float(tol), _ptr(iters_dev), _stream(stream)), ctx)
 
 
 def psc_tune(ctx, obs, offsets_dev, vis_obs_dev, weight_dev, repeats=3, stream=None):
@@ -378,6 +385,15 @@ class Session:
         mx = torch.empty(self.obs.n_int, dtype=torch.float64, device=self.dev)
         psc_scale_step(self.ctx, self.handle, acc, gain, nu, mx)
         return nu, mx
+
+    def solve_beam_scale(self, offsets, vis_obs, weight, gain=0.5, n_max=30, tol=1e-6):
+        """Solve for the beam scales at fixed offsets; returns the steps taken
+        per interval (the scales stay on the observation)."""
+        torch = self.torch
+        off = offsets if isinstance(offsets, torch.Tensor) else self.offsets(offsets)
+        its = torch.zeros(self.obs.n_int, dtype=torch.int32, device=self.dev)
+        psc_solve_scale(self.ctx, self.handle, off, vis_obs, weight, gain, n_max, tol, its)
+        return its
 
     def image_gradient(self, offsets, vis_obs, weight):
         """d chi^2 / d I on the model grid, [N][N] float64."""

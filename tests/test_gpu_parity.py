@@ -1228,3 +1228,50 @@ def test_extensions_together(torch_dev, mount):
         _check_image_gradient(torch, obs, prob, s, start, v + nz, w, 32, 73)
     finally:
         s.close()
+
+
+def test_solve_beam_scale(torch_dev):
+    """psc_solve_scale: with tol 0 it equals as many separate scale-gradient
+    and step calls, bit for bit; with a tolerance, the steps per interval and
+    the scales follow the oracle's loop under the same stopping rule, and the
+    injected scales are recovered."""
+    torch = torch_dev
+    print("case: beam scale solve on the device", flush=True)
+    obs = _aperture_obs(16, 4)
+    shape = (obs.n_int, obs.n_pol, obs.n_ant)
+    truth = np.random.default_rng(74).uniform(0.97, 1.03, shape)
+    v = oracle.predict(oracle.Problem.from_observation(obs, beam_scale=truth), obs.offsets_true)
+    s = session(obs)
+    try:
+        off = s.offsets(obs.offsets_true)
+        vo = c64(torch, s, v)
+        w1 = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+        s.set_beam_scale(np.ones(shape))
+        s.solve_beam_scale(off, vo, w1, gain=0.5, n_max=6, tol=0.0)
+        solved = s.beam_scale().clone()
+        s.set_beam_scale(np.ones(shape))
+        for _ in range(6):
+            s.scale_step(s.scale_gradient(off, vo, w1), 0.5)
+        assert torch.equal(solved, s.beam_scale())
+        tol = 1e-4
+        s.set_beam_scale(np.ones(shape))
+        its = s.solve_beam_scale(off, vo, w1, gain=0.5, n_max=60, tol=tol).cpu().numpy()
+        ref = np.ones(shape)
+        done = np.zeros(obs.n_int, bool)
+        its_ref = np.zeros(obs.n_int, np.int32)
+        for _ in range(60):
+            if done.all():
+                break
+            a3 = oracle.scale_gradient(oracle.Problem.from_observation(obs, beam_scale=ref), obs.offsets_true, v,
+                                       1.0)
+            new, _, mx = oracle.scale_step(a3, 0.5, ref)
+            new[done] = ref[done]
+            its_ref[~done] += 1
+            ref = new
+            done |= mx < tol
+        assert np.abs(its - its_ref).max() <= 1, (its, its_ref)
+        got = s.beam_scale().cpu().numpy()
+        assert np.abs(got - ref).max() <= 2e-4
+        assert np.abs(got - truth).max() <= 5e-4
+    finally:
+        s.close()
