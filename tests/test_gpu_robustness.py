@@ -162,5 +162,31 @@ def test_all_flagged_interval_and_empty_observation(torch_dev):
                       gain=0.5, n_max=3, tol_rad=1e-3 * ARCSEC, form=psc.SOLVE_GRAPH)
         assert torch.count_nonzero(off) == 0
         assert its.shape[0] == empty.n_int
+        vz = torch.zeros(s.vis_shape, dtype=torch.complex64, device=s.dev)
+        wz = torch.zeros(s.vis_shape, dtype=torch.float32, device=s.dev)
+        img = s.image_gradient(off, vz, wz)
+        assert torch.count_nonzero(img) == 0
+        # beam scales on no rows: zero sums, no step, scales unchanged
+        s.set_beam_scale(np.full(s.off_shape[:3], 1.02))
+        sacc = s.scale_gradient(off, vz, wz)
+        assert torch.count_nonzero(sacc) == 0
+        nu, mx = s.scale_step(sacc, 0.5)
+        assert torch.all(nu == 1) and torch.count_nonzero(mx) == 0
+        sits = s.solve_beam_scale(off, vz, wz, n_max=3)
+        assert sits.shape[0] == empty.n_int
+        assert torch.all(s.beam_scale() == 1.02)
+        assert torch.count_nonzero(s.image_gradient(off, vz, wz)) == 0
+        s.set_beam_scale(None)
+    finally:
+        s.close()
+    # a measured aperture on no rows
+    s = Session(empty, device=0, aperture=synth.measured_aperture(n=16, seed=1), mount_frame=True)
+    try:
+        off = s.offsets(np.zeros(s.off_shape))
+        vz = torch.zeros(s.vis_shape, dtype=torch.complex64, device=s.dev)
+        wz = torch.zeros(s.vis_shape, dtype=torch.float32, device=s.dev)
+        assert s.predict(off).numel() == 0
+        assert torch.count_nonzero(s.gradient(off, vz, wz)) == 0
+        assert torch.count_nonzero(s.image_gradient(off, vz, wz)) == 0
     finally:
         s.close()
