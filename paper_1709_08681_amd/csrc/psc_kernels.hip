@@ -471,12 +471,12 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
                     const int v = v0 + slot + SPW * j;
                     if (v >= nv) continue;
                     const size_t o = (size_t)ent[j].vidx * a.n_pol + pol;
-                    if (MODE == kPredict) {
+                    if constexpr (MODE == kPredict) {
                         if (t == 0) a.vis_out[o] = s[j][0];
-                    } else if (MODE == kGrad) {
+                    } else if constexpr (MODE == kGrad) {
                         if (a.vis_out != nullptr && t == 0) a.vis_out[o] = s[j][0];
                         grad_term(tsel, s[j], vin[j], wgt[j], acc64);
-                    } else if (MODE == kVjp) {
+                    } else if constexpr (MODE == kVjp) {
                         vjp_term(t, s[j], vin[j], acc64);
                     } else {
                         // adjoint of the degrid: w conj(R) spread back over the
