@@ -559,6 +559,62 @@ def test_cfg2_full_size_window_form(torch_dev):
         s.close()
 
 
+@pytest.mark.parametrize("what", ["mount_frame", "measured_aperture", "beam_scale", "w_term"])
+def test_cfg2_full_size_extensions_sampled_rows(torch_dev, what):
+    """The extension kernels on the full single-interval array, in the launch
+    configuration the bench times them in (360 samples per item, blocks of
+    four wavefronts), in the mount frame (the w-term, like the bench, in the
+    sky frame on the array shrunk to arms of 1 km): the model visibilities of every
+    36th timestep (every 180th for the measured aperture, whose oracle sums
+    the aperture's cells for every pixel and row), and the per-antenna sums
+    with the weights zero outside those timesteps, against the oracle on
+    those rows alone."""
+    torch = torch_dev
+    every = 180 if what == "measured_aperture" else 36
+    print(f"case: cfg2 full size, {what}, every {every}th timestep", flush=True)
+    obs = synth.make_config(2, layout_radius_m=1000.0) if what == "w_term" else synth.make_config(2)
+    times = np.unique(obs.time_idx)[::every]
+    rows = np.nonzero(np.isin(obs.time_idx, times))[0]
+    sub = obs.subset(times=times)
+    kw, okw = dict(mount_frame=True), dict(mount_frame=True)
+    if what == "w_term":
+        kw, okw = dict(w_term=True), dict(w_term=True)
+    if what == "measured_aperture":
+        A = synth.measured_aperture()
+        kw["aperture"] = A
+        okw.update(illum=2, aperture=A)
+    scale = None
+    if what == "beam_scale":
+        scale = np.random.default_rng(0).uniform(0.97, 1.03, (obs.n_int, obs.n_pol, obs.n_ant))
+        okw["beam_scale"] = scale
+    prob = oracle.Problem.from_observation(sub, **okw)
+    s = session(obs, **kw)
+    try:
+        if scale is not None:
+            s.set_beam_scale(scale)
+        start = synth.perturbed_offsets(obs, 30.0, 14)
+        v_sub = oracle.predict(prob, obs.offsets_true)
+        vobs = np.zeros(s.vis_shape, np.complex128)
+        vobs[rows] = v_sub
+        w = np.zeros(s.vis_shape)
+        w[rows] = 1.0
+        e_v = rel(s.predict(start).cpu().numpy()[rows], oracle.predict(prob, start))
+        if what == "beam_scale":
+            acc = s.scale_gradient(s.offsets(start), c64(torch, s, vobs), f32(torch, s, w, s.vis_shape))
+            ref = oracle.scale_gradient(prob, start, v_sub, 1.0)
+        else:
+            acc = s.gradient(s.offsets(start), c64(torch, s, vobs), f32(torch, s, w, s.vis_shape))
+            ref = oracle.gradient(prob, start, v_sub, 1.0)
+        acc = acc.cpu().numpy()
+        e_a = [rel(acc[..., k], ref[..., k]) for k in range(ref.shape[-1])]
+        print(f"cfg2 {what}: vis rel {e_v:.2e}, acc rel {max(e_a):.2e} ({len(rows)} of {obs.n_row} rows)",
+              flush=True)
+        assert e_v <= 1e-5
+        assert max(e_a) <= 1e-4
+    finally:
+        s.close()
+
+
 @pytest.fixture(scope="module")
 def cfg5_subset(torch_dev):
     """Large workload (4096^2 grid, support 32, oversampling 8, two
