@@ -316,8 +316,8 @@ def main():
                     help="skip the measured-aperture, beam-scale and w-term timings")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only; the hot path is sharded by solution "
-              "interval or channel block across GPUs (see DESIGN.md), which is not built here.",
+        print("bench.py: runs on one GPU only; sharding the path across GPUs (by solution "
+              "interval or by channel block) is designed but not implemented.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -40,7 +40,7 @@ typedef enum {
     PSC_E_ARG = -1,          /* invalid argument (shape, range, null pointer) */
     PSC_E_HIP = -2,          /* a HIP runtime call failed */
     PSC_E_OOM = -3,          /* device or host allocation failed */
-    PSC_E_UNSUPPORTED = -4,  /* valid request outside what this build implements */
+    PSC_E_UNSUPPORTED = -4,  /* valid request outside what the library implements */
     PSC_E_STATE = -5         /* call out of order (e.g. predict before set_model) */
 } psc_status;
 
