@@ -1063,6 +1063,36 @@ def test_measured_aperture_solve(torch_dev):
         s.close()
 
 
+@pytest.mark.parametrize("n,mount", [(256, False), (256, True), (2, True), (1, False), (1, True)])
+def test_measured_aperture_size_limits(torch_dev, n, mount):
+    """The largest illumination the library takes (256 cells per side), the
+    smallest that is not flat (2 x 2 cells) and a single cell, whose pattern
+    is 1 everywhere: prediction and the sums against the oracle; with one
+    cell the offsets' sums and curvatures are exactly zero on both sides."""
+    torch = torch_dev
+    print(f"case: measured aperture of {n} x {n} cells, mount {mount}", flush=True)
+    obs = _aperture_obs(16, 4)
+    A = synth.measured_aperture(n=n, seed=3) if n > 2 else np.ones((n, n))
+    prob = oracle.Problem.from_observation(obs, mount_frame=mount, illum=2, aperture=A)
+    s = session(obs, mount_frame=mount, aperture=A)
+    try:
+        start = synth.perturbed_offsets(obs, 25.0, 51)
+        v = oracle.predict(prob, obs.offsets_true)
+        assert rel(s.predict(start).cpu().numpy(), oracle.predict(prob, start)) <= 1e-5
+        # noisy data, so that chi is not zero where the beam is flat
+        nz, w = synth.noise(v, 100.0, 52)
+        ref = oracle.gradient(prob, start, v + nz, w)
+        acc = s.gradient(s.offsets(start), c64(torch, s, v + nz), f32(torch, s, w, s.vis_shape)).cpu().numpy()
+        if n == 1:
+            assert rel(acc[..., 0], ref[..., 0]) <= 1e-4
+            assert np.all(ref[..., 1:] == 0) and np.all(acc[..., 1:] == 0)
+        else:
+            for k in range(6):
+                assert rel(acc[..., k], ref[..., k]) <= 1e-4, k
+    finally:
+        s.close()
+
+
 def test_measured_aperture_must_be_even(torch_dev):
     from paper_1709_08681_amd import psc
     print("case: measured aperture validation", flush=True)
