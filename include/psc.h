@@ -337,7 +337,12 @@ PSC_API psc_status psc_tune(psc_ctx* ctx, psc_obs* obs, const double* offsets_de
  * psc_set_beam_scale (sync): copies scale_dev, [n_int][n_pol][n_ant]
  * float64 (device, borrowed), into the observation; every later predict,
  * gradient, adjoint, solve and image gradient uses it.  Values must be
- * positive and finite (PSC_E_ARG, the observation unchanged).  The scales
+ * positive and finite (PSC_E_ARG, the observation unchanged).  A scale
+ * below 1 widens the aperture to D / sigma and the baseline kernel with it;
+ * unless illum = 1, the smallest scale must keep 2 D FoV / (sigma lambda_min)
+ * <= support - taper_width / 2 - 1/2 cells (PSC_E_UNSUPPORTED otherwise, the
+ * observation unchanged; about sigma >= 0.68 when the field of view is
+ * chosen so that the aperture term is half of a 16-cell support).  The scales
  * enter through the window form's image-plane products (per antenna), so
  * the observation then degrids in the window form (psc_set_degrid refuses
  * the table forms); the image gradient then builds each sample's kernel

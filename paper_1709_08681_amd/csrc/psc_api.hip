@@ -50,6 +50,7 @@ struct psc_obs {
     float4* airy = nullptr;
     int32_t n_tab = 0;
     double inv_dx = 0;
+    double fmax = 0;           // highest channel frequency (Hz)
     float4* ap_tab = nullptr;  // measured aperture: pattern table [ap_n][ap_n]
     double* scale = nullptr;   // beam-width scales [n_int][n_pol][n_ant] (null: all 1)
     double* zero_pa = nullptr; // [n_row] zeros: the per-sample scatter's angles with scales, sky frame
@@ -566,6 +567,7 @@ static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
 
     psc_obs* obs = new psc_obs();
     obs->ctx = ctx;
+    obs->fmax = fmax;
     obs->degrid = (S == 16 && pa.empty() && wv.empty() && !ap) ? PSC_DEGRID_VALU : PSC_DEGRID_WINDOW;
     obs->n_ant = n_ant;
     obs->n_chan = n_chan;
@@ -1010,8 +1012,24 @@ PSC_API psc_status psc_set_beam_scale(psc_ctx* ctx, psc_obs* obs, const double* 
     std::vector<double> h(n);
     PSC_HIP(ctx, hipMemcpyAsync(h.data(), scale_dev, sizeof(double) * n, hipMemcpyDeviceToHost, st));
     PSC_HIP(ctx, hipStreamSynchronize(st));
-    for (size_t k = 0; k < n; ++k)
+    double smin = 1.0;
+    for (size_t k = 0; k < n; ++k) {
         if (!(h[k] > 0.0) || !isfinite(h[k])) return fail(ctx, PSC_E_ARG, "beam scales must be positive and finite");
+        smin = std::min(smin, h[k]);
+    }
+    // a scale below 1 widens the aperture to D / sigma, and each baseline
+    // kernel with it: 2 (D / sigma) FoV / lambda cells at the highest
+    // frequency.  The window form stays within the parity tolerance while
+    // that leaves about half the taper's width of the support free (on a
+    // 1.4 GHz array whose aperture term is 8 cells of 16 at sigma = 1:
+    // float32 rounding down to sigma = 0.8, 7e-6 on the visibilities and
+    // 6e-5 on the sums at 0.7); narrower beams are refused.
+    if (ctx->cfg.illum != 1) {
+        const double ap_cells = 2.0 * ctx->cfg.dish_diam_m * ctx->fov * obs->fmax / kCLight / smin;
+        if (ap_cells > ctx->s - 0.5 * ctx->cfg.taper_width - 0.5)
+            return fail(ctx, PSC_E_UNSUPPORTED, "beam scale too small: the widened aperture's kernel "
+                                                "(2 D FoV / (sigma lambda) cells) outgrows the support");
+    }
     // the image gradient's scatter builds each sample's kernel when the
     // beams are scaled: in the sky frame it runs at angle zero
     if (!obs->par_angle && !obs->zero_pa) {

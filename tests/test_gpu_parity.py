@@ -1208,6 +1208,19 @@ def test_beam_scale_errors(torch_dev):
             s.set_beam_scale(bad)
         assert ei.value.status == psc.PSC_E_ARG
         assert psc.psc_get_degrid(s.handle) == psc.DEGRID_VALU  # unchanged
+        # a beam narrowed to 0.6 widens the aperture past what the support
+        # holds (8 of 16 cells at sigma = 1 here); 0.75 still fits
+        narrow = np.ones((obs.n_int, obs.n_pol, obs.n_ant))
+        narrow[2, 1, 4] = 0.6
+        with pytest.raises(psc.PscError) as ei:
+            s.set_beam_scale(narrow)
+        assert ei.value.status == psc.PSC_E_UNSUPPORTED
+        assert psc.psc_get_degrid(s.handle) == psc.DEGRID_VALU
+        narrow[2, 1, 4] = 0.75
+        s.set_beam_scale(narrow)
+        prob = oracle.Problem.from_observation(obs, beam_scale=narrow)
+        start = synth.perturbed_offsets(obs, 25.0, 57)
+        assert rel(s.predict(start).cpu().numpy(), oracle.predict(prob, start)) <= 1e-5
     finally:
         s.close()
 
