@@ -374,8 +374,9 @@ PSC_API psc_status psc_scale_gradient(psc_ctx* ctx, psc_obs* obs, const double* 
  * psc_scale_gradient), 0 < gain <= 1 (the loop gain of Eq. SelfCal; all
  * antennas move together, as for the offsets, and gain 1 makes the two ends
  * of a baseline overshoot together).  Antennas with H <= 0, non-finite sums,
- * or a step that would leave sigma non-positive keep their scale and get
- * not_updated = 1.
+ * or a step that would leave sigma non-positive or below the narrowest beam
+ * the support holds (the bound of psc_set_beam_scale) keep their scale and
+ * get not_updated = 1.
  *  not_updated_dev  nullable [n_int][n_pol][n_ant] int32
  *  max_step_out_dev nullable [n_int] float64: largest |delta sigma| per interval
  */

@@ -990,6 +990,20 @@ PSC_API psc_status psc_get_degrid(const psc_obs* obs, int32_t* variant)
     return PSC_OK;
 }
 
+// The narrowest beam the support holds: a scale below 1 widens the aperture
+// to D / sigma, and each baseline kernel with it, to 2 (D / sigma) FoV /
+// lambda cells at the highest frequency.  The window form stays within the
+// parity tolerance while that leaves about half the taper's width of the
+// support free (on a 1.4 GHz array whose aperture term is 8 cells of 16 at
+// sigma = 1: float32 rounding down to sigma = 0.8, 7e-6 on the visibilities
+// and 6e-5 on the sums at 0.7).  No bound for the Gaussian test mode.
+static double scale_floor(const psc_ctx* ctx, const psc_obs* obs)
+{
+    if (ctx->cfg.illum == 1) return 0.0;
+    const double ap_cells = 2.0 * ctx->cfg.dish_diam_m * ctx->fov * obs->fmax / kCLight;
+    return ap_cells / (ctx->s - 0.5 * ctx->cfg.taper_width - 0.5);
+}
+
 PSC_API psc_status psc_set_beam_scale(psc_ctx* ctx, psc_obs* obs, const double* scale_dev, void* stream)
 {
     if (!ctx) return fail(nullptr, PSC_E_ARG, "null context");
@@ -1017,19 +1031,9 @@ PSC_API psc_status psc_set_beam_scale(psc_ctx* ctx, psc_obs* obs, const double* 
         if (!(h[k] > 0.0) || !isfinite(h[k])) return fail(ctx, PSC_E_ARG, "beam scales must be positive and finite");
         smin = std::min(smin, h[k]);
     }
-    // a scale below 1 widens the aperture to D / sigma, and each baseline
-    // kernel with it: 2 (D / sigma) FoV / lambda cells at the highest
-    // frequency.  The window form stays within the parity tolerance while
-    // that leaves about half the taper's width of the support free (on a
-    // 1.4 GHz array whose aperture term is 8 cells of 16 at sigma = 1:
-    // float32 rounding down to sigma = 0.8, 7e-6 on the visibilities and
-    // 6e-5 on the sums at 0.7); narrower beams are refused.
-    if (ctx->cfg.illum != 1) {
-        const double ap_cells = 2.0 * ctx->cfg.dish_diam_m * ctx->fov * obs->fmax / kCLight / smin;
-        if (ap_cells > ctx->s - 0.5 * ctx->cfg.taper_width - 0.5)
-            return fail(ctx, PSC_E_UNSUPPORTED, "beam scale too small: the widened aperture's kernel "
-                                                "(2 D FoV / (sigma lambda) cells) outgrows the support");
-    }
+    if (smin < scale_floor(ctx, obs))
+        return fail(ctx, PSC_E_UNSUPPORTED, "beam scale too small: the widened aperture's kernel "
+                                            "(2 D FoV / (sigma lambda) cells) outgrows the support");
     // the image gradient's scatter builds each sample's kernel when the
     // beams are scaled: in the sky frame it runs at angle zero
     if (!obs->par_angle && !obs->zero_pa) {
@@ -1089,7 +1093,8 @@ PSC_API psc_status psc_scale_step(psc_ctx* ctx, psc_obs* obs, const double* acc_
     if (!obs->scale) return fail(ctx, PSC_E_STATE, "no beam scales set (psc_set_beam_scale)");
     PSC_HIP(ctx, hipSetDevice(ctx->cfg.device));
     PSC_HIP(ctx, launch_scale_step(obs->n_int, obs->n_pol, obs->n_ant, acc_dev, gain, obs->scale, not_updated_dev,
-                                   max_step_out_dev, nullptr, nullptr, 0.0, (hipStream_t)stream));
+                                   max_step_out_dev, nullptr, nullptr, 0.0, scale_floor(ctx, obs),
+                                   (hipStream_t)stream));
     return PSC_OK;
 }
 
@@ -1108,13 +1113,14 @@ PSC_API psc_status psc_solve_scale(psc_ctx* ctx, psc_obs* obs, const double* off
     ItemArgs a = item_args(ctx, obs, offsets_dev, 0, (int)obs->n_items, obs->done);
     a.vis_in = (const float2*)vis_obs_dev;
     a.weight = weight_dev;
+    const double sfloor = scale_floor(ctx, obs);
     // every interval in one launch set per iteration; finished intervals are
     // skipped by every kernel (their items, sums and steps)
     for (int it = 0; it < n_max; ++it) {
         PSC_HIP(ctx, launch_win(kScale, ctx->s, a, s));
         PSC_HIP(ctx, launch_reduce(6, reduce_args(obs, 0, obs->n_int, obs->acc, obs->done), s));
         PSC_HIP(ctx, launch_scale_step(obs->n_int, obs->n_pol, obs->n_ant, obs->acc, gain, obs->scale, nullptr,
-                                       obs->max_step, obs->done, obs->iters, tol, s));
+                                       obs->max_step, obs->done, obs->iters, tol, sfloor, s));
     }
     if (iters_out_dev)
         PSC_HIP(ctx, hipMemcpyAsync(iters_out_dev, obs->iters, sizeof(int32_t) * obs->n_int, hipMemcpyDeviceToDevice, s));

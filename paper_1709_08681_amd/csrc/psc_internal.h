@@ -152,7 +152,7 @@ hipError_t launch_aperture_table(const double* cells, int n_cells, float4* tab, 
 // done, iters (nullable): solve state, as for the offsets' step.
 hipError_t launch_scale_step(int n_int, int n_pol, int n_ant, const double* acc3, double gain, double* scale,
                              int32_t* not_updated, double* max_step, int32_t* done, int32_t* iters, double tol,
-                             hipStream_t s);
+                             double min_scale, hipStream_t s);
 hipError_t launch_zero(double2* p, size_t n, hipStream_t s);
 hipError_t launch_unpad_grid(const double2* g, double2* out, int n, int pad, hipStream_t s);
 hipError_t launch_image_grad(const double2* f, const double* taper_pix, double* out, int n, hipStream_t s);

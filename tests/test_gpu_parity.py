@@ -1221,6 +1221,15 @@ def test_beam_scale_errors(torch_dev):
         prob = oracle.Problem.from_observation(obs, beam_scale=narrow)
         start = synth.perturbed_offsets(obs, 25.0, 57)
         assert rel(s.predict(start).cpu().numpy(), oracle.predict(prob, start)) <= 1e-5
+        # the step does not narrow a beam past the same bound: 0.75 - 0.15
+        # is refused and flagged, 1 - 0.15 taken
+        acc = np.zeros((obs.n_int, obs.n_pol, obs.n_ant, 3))
+        acc[..., 2] = 1.0
+        acc[2, 1, 4, 1] = acc[2, 1, 3, 1] = -0.15
+        nu, _ = s.scale_step(torch.as_tensor(acc, device=s.dev), 1.0)
+        got, nu = s.beam_scale().cpu().numpy(), nu.cpu().numpy()
+        assert nu[2, 1, 4] == 1 and got[2, 1, 4] == 0.75
+        assert nu[2, 1, 3] == 0 and got[2, 1, 3] == pytest.approx(0.85, abs=1e-15)
     finally:
         s.close()
 
