@@ -404,6 +404,138 @@ def test_solve_step_edge_cases(oracle_lib):
     assert abs(mx[0] - max(np.hypot(*new[0, 0, 0]), np.hypot(*new[0, 0, 2]))) < 1e-15
 
 
+def _two_interval_problem(oracle, n_ant=4, n_time=4, seed=31, empty_second=False):
+    """Two solution intervals over the same baselines (a third, empty one when
+    asked for): rows [0, n/2) and [n/2, n)."""
+    rng = np.random.default_rng(seed)
+    i, j = np.triu_indices(n_ant, 1)
+    ant1, ant2 = np.tile(i, n_time), np.tile(j, n_time)
+    uv = rng.uniform(-2000.0, 2000.0, size=(ant1.size, 2))
+    src_l, src_m = rng.uniform(-0.008, 0.008, 4), rng.uniform(-0.008, 0.008, 4)
+    flux = rng.uniform(0.5, 1.5, 4)
+    half = ant1.size // 2
+    ptr = [0, half, half, ant1.size] if empty_second else [0, half, ant1.size]
+    prob = oracle.Problem(src_l, src_m, flux, n_ant, ant1, ant2, uv, ptr, [1.3e9, 1.6e9])
+    truth = rng.normal(0.0, 30 * ARCSEC, size=prob.offsets_shape())
+    return prob, truth, rng
+
+
+def _manual_rounds(o, prob, v, start, n, gain=0.5):
+    """n rounds of Algorithm 1's body written out from the oracle's two steps:
+    sums at the current offsets, then one damped update of every interval.
+    Returns the offsets after each round and each round's largest step per
+    interval (|p_new - p_old| over pols and antennas, taken here from the
+    offsets themselves, not from the step's own report)."""
+    offs, steps = [np.array(start, dtype=np.float64, copy=True)], []
+    for _ in range(n):
+        acc = o.gradient(prob, offs[-1], v, 1.0)
+        new, _, _ = o.solve_step(acc, gain, offs[-1])
+        d = np.hypot(*np.moveaxis(new - offs[-1], -1, 0))  # [n_int, n_pol, n_ant]
+        steps.append(d.reshape(d.shape[0], -1).max(axis=1))
+        offs.append(new)
+    return offs, np.array(steps)
+
+
+def test_terminate_zero_iterations_leaves_offsets(oracle_lib):
+    """Algorithm 1 with n_max = 0 runs no iteration: offsets untouched, zero
+    iterations for every interval."""
+    o = oracle_lib
+    prob, truth, rng = _two_interval_problem(o)
+    v = o.predict(prob, truth)
+    start = truth + rng.normal(0.0, 20 * ARCSEC, size=truth.shape)
+    sol, its = o.solve(prob, v, 1.0, start, gain=0.5, n_max=0, tol_rad=1e-3 * ARCSEC)
+    assert np.array_equal(sol, start)
+    assert its.tolist() == [0, 0]
+
+
+def test_terminate_infinite_tolerance_stops_after_one_step(oracle_lib):
+    """With tol above any step, each interval takes exactly one update (the
+    step is applied before the stop test, Terminate after Update), and the
+    result is one round of sums + step done by hand."""
+    o = oracle_lib
+    prob, truth, rng = _two_interval_problem(o)
+    v = o.predict(prob, truth)
+    start = truth + rng.normal(0.0, 20 * ARCSEC, size=truth.shape)
+    sol, its = o.solve(prob, v, 1.0, start, gain=0.5, n_max=10, tol_rad=np.inf)
+    offs, _ = _manual_rounds(o, prob, v, start, 1)
+    assert its.tolist() == [1, 1]
+    np.testing.assert_allclose(sol, offs[1], rtol=0, atol=1e-15)
+    assert not np.array_equal(sol, start)
+
+
+def test_terminate_zero_tolerance_runs_n_max(oracle_lib):
+    """With tol = 0 no step is below it, so every interval runs n_max
+    iterations, each equal to one round done by hand."""
+    o = oracle_lib
+    prob, truth, rng = _two_interval_problem(o)
+    v = o.predict(prob, truth)
+    start = truth + rng.normal(0.0, 20 * ARCSEC, size=truth.shape)
+    n_max = 5
+    sol, its = o.solve(prob, v, 1.0, start, gain=0.5, n_max=n_max, tol_rad=0.0)
+    offs, _ = _manual_rounds(o, prob, v, start, n_max)
+    assert its.tolist() == [n_max, n_max]
+    np.testing.assert_allclose(sol, offs[n_max], rtol=0, atol=1e-15)
+
+
+def test_terminate_first_step_below_tol_sets_iteration_count(oracle_lib):
+    """An interval stops at the first iteration k whose largest step is below
+    tol: with tol placed between the hand-computed steps k-1 and k the
+    oracle reports exactly k iterations and the offsets after k rounds; the
+    other interval, given a tol that falls elsewhere in its own sequence,
+    stops at its own k.  Checked for several k."""
+    o = oracle_lib
+    prob, truth, rng = _two_interval_problem(o)
+    v = o.predict(prob, truth)
+    start = truth + rng.normal(0.0, 20 * ARCSEC, size=truth.shape)
+    offs, steps = _manual_rounds(o, prob, v, start, 9)
+    # noiseless Gauss-Newton with gain 1/2 contracts: strictly falling steps
+    assert np.all(np.diff(steps, axis=0) < 0), steps
+    for k in (1, 2, 4, 7):
+        tol = np.sqrt(steps[k - 1, 0] * (steps[k - 2, 0] if k > 1 else 10 * steps[0, 0]))
+        sol, its = o.solve(prob, v, 1.0, start, gain=0.5, n_max=20, tol_rad=tol)
+        # both intervals see the same tol; each stops where its own steps cross it
+        k_each = [int(np.argmax(steps[:, s] < tol)) + 1 for s in range(2)]
+        assert k_each[0] == k
+        assert its.tolist() == k_each, (its, k_each, steps)
+        for s in range(2):
+            np.testing.assert_allclose(sol[s], offs[k_each[s]][s], rtol=0, atol=1e-15)
+
+
+def test_terminate_converged_interval_stops_while_other_continues(oracle_lib):
+    """One interval starts at the truth on noiseless data: its residuals and
+    gradient are exactly zero, so its one step is zero and it stops after the
+    first iteration unchanged.  The other starts perturbed, keeps iterating,
+    and ends where solving it alone ends (intervals are independent)."""
+    o = oracle_lib
+    prob, truth, rng = _two_interval_problem(o)
+    v = o.predict(prob, truth)
+    start = truth.copy()
+    start[1] += rng.normal(0.0, 20 * ARCSEC, size=truth[1].shape)
+    tol, n_max = 0.05 * ARCSEC, 200
+    sol, its = o.solve(prob, v, 1.0, start, gain=0.5, n_max=n_max, tol_rad=tol)
+    # the second interval stops on its tol, before n_max
+    assert its[0] == 1 and 3 < its[1] < n_max, its
+    assert np.array_equal(sol[0], truth[0])
+    offs, steps = _manual_rounds(o, prob, v, start, int(its[1]))
+    assert np.all(steps[:, 0] == 0.0)
+    assert steps[-1, 1] < tol and np.all(steps[:-1, 1] >= tol)
+    np.testing.assert_allclose(sol[1], offs[-1][1], rtol=0, atol=1e-15)
+
+
+def test_terminate_empty_interval(oracle_lib):
+    """An interval with no rows has no sums: its antennas are not updated and
+    its largest step is 0, which is below any positive tol (one iteration,
+    offsets unchanged) and never below tol = 0 (n_max iterations)."""
+    o = oracle_lib
+    prob, truth, rng = _two_interval_problem(o, empty_second=True)
+    v = o.predict(prob, truth)
+    start = truth + rng.normal(0.0, 20 * ARCSEC, size=truth.shape)
+    sol, its = o.solve(prob, v, 1.0, start, gain=0.5, n_max=6, tol_rad=1e-3 * ARCSEC)
+    assert its[1] == 1 and np.array_equal(sol[1], start[1])
+    sol, its = o.solve(prob, v, 1.0, start, gain=0.5, n_max=6, tol_rad=0.0)
+    assert its.tolist() == [6, 6, 6] and np.array_equal(sol[1], start[1])
+
+
 def test_solver_recovers_injected_offsets_noiseless(oracle_lib):
     o = oracle_lib
     obs = synth.make_config(1)
