@@ -1,18 +1,25 @@
 """Benchmark: predict+gradient visibilities per second on one MI355X.
 
-One step is one pass of the hot path over the whole workload: kernel
-construction, degridding of V^M and its four offset derivatives, residual,
-float64 per-antenna chi^2 / gradient / normal-matrix sums (psc_gradient), and
-the damped per-antenna update (psc_solve_step).  The default workload is the
-single-interval configuration: 27 antennas in a Y (351 baselines, arms to
-21 km), 360 x 10 s, 16 channels over 1-2 GHz, one polarisation, a 1024^2
-model grid with 200 point sources, support 16, oversampling 4.
+One step is one pass of the hot path over the whole workload: Algorithm 1's
+body for every solution interval at once -- kernel construction, degridding
+of V^M and its four offset derivatives, residual, float64 per-antenna chi^2 /
+gradient / normal-matrix sums, and the damped per-antenna update with its
+termination flags.
+
+The headline workload is the batched configuration: 27 antennas in a Y (351
+baselines, arms to 21 km), 256 solution intervals of 10 to 120 timesteps of
+10 s (16,565 timesteps), 16 channels over 1-2 GHz, one polarisation, a 2048^2
+model grid with 200 point sources, support 16, oversampling 4: 93,029,040
+visibilities per step.  Steps run in the graph form (psc_solve, every
+interval in one launch set per iteration, the K timed iterations captured
+in one HIP graph and replayed); the plain form (a host loop over intervals
+with per-interval launches) and the batched form without the graph are timed
+beside it on the same data, and their offsets must agree bit for bit.
 
 Prints one JSON line (see the repository's benchmark contract).
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -26,29 +33,32 @@ if ROOT not in sys.path:
 FP32_VECTOR_PEAK = 157.3e12  # MI355X published FP32 vector rate (FLOP/s)
 HBM_PEAK = 8.0e12
 
+# committed rocprofv3 summaries: (file, sources the profiled kernel is built from)
+PROFILES = {
+    "window": ("k_winw_grad_batched.md", ("psc_window.hip", "psc_device.h", "psc_internal.h")),
+    "table": ("k_item_grad_single_interval.md", ("psc_kernels.hip", "psc_device.h", "psc_internal.h")),
+    "window_large": ("k_winw_grad_large_share.md", ("psc_window.hip", "psc_device.h", "psc_internal.h")),
+}
 
-KERNEL_SOURCES = ("psc_kernels.hip", "psc_device.h", "psc_internal.h")
 
-
-def kernel_source_hash():
-    """sha256 (first 16 hex digits) over the sources the table-form kernel is
-    built from."""
+def source_hash(sources):
+    """sha256 (first 16 hex digits) over the kernel sources."""
     import hashlib
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in sources:
         with open(os.path.join(ROOT, "paper_1709_08681_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the gradient kernel from the committed rocprofv3
-    summary, or None when the kernel sources have changed since it was taken."""
+def measured_traffic(which):
+    """HBM bytes per launch of a kernel from its committed rocprofv3 summary,
+    or None when the kernel's sources have changed since it was taken."""
     import re
-    prof = os.path.join(ROOT, "profiles", "k_item_grad_single_interval.md")
+    name, sources = PROFILES[which]
     try:
-        h = kernel_source_hash()
-        txt = open(prof).read()
+        txt = open(os.path.join(ROOT, "profiles", name)).read()
+        h = source_hash(sources)
     except OSError:
         return None
     m = re.search(r"traffic_bytes=(\d+) kernel_source_sha256_16=([0-9a-f]+)", txt)
@@ -57,95 +67,214 @@ def measured_traffic():
 
 def describe(obs):
     wl = obs.wl
-    return {
-        "workload": f"{wl.name}: {obs.n_ant} antennas ({wl.layout}), {wl.n_bl} baselines, "
-                    f"{wl.n_time} x {wl.dt_s:g} s, {obs.n_chan} channels, {obs.n_pol} pol, "
-                    f"{obs.n_int} interval(s), {obs.grid_n}^2 grid, support {wl.support}, "
-                    f"oversampling {wl.oversample}",
-        "n_vis": int(obs.n_vis),
-        "n_intervals": int(obs.n_int),
-        "grid_n": int(obs.grid_n),
-        "support": int(wl.support),
-        "oversample": int(wl.oversample),
-        "step": "psc_gradient + psc_solve_step",
-    }
+    return (f"{wl.name}: {obs.n_ant} antennas ({wl.layout}), {wl.n_bl} baselines, "
+            f"{len(np.unique(obs.time_idx))} x {wl.dt_s:g} s, {obs.n_chan} channels, {obs.n_pol} pol, "
+            f"{obs.n_int} interval(s), {obs.grid_n}^2 grid, support {wl.support}, "
+            f"oversampling {wl.oversample}")
 
 
-def batched_vs_plain(cfg, iters, device=0, **overrides):
-    """Algorithm 1 over every solution interval of workload `cfg` for a fixed
-    number of iterations (tol = 0), in the three execution forms: PLAIN (host
-    loop over intervals, launches per interval, host check per iteration),
-    BATCHED (every interval in one launch set per iteration) and GRAPH
-    (BATCHED, all iterations captured in one HIP graph and replayed).
-    `overrides` change the workload (e.g. its interval lengths)."""
-    import torch
-    from paper_1709_08681_amd import synth
-    from paper_1709_08681_amd import psc as P
-    obs = synth.make_config(cfg, **overrides)
-    s = P.Session(obs, device=device)
-    try:
-        v_obs = s.predict(s.offsets(obs.offsets_true))
-        w = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
-        start = s.offsets(synth.perturbed_offsets(obs, 30.0, 98))
-        # the autotuner keeps the fastest degrid variant for all three forms
-        tune_us = P.psc_tune(s.ctx, s.handle, start, v_obs, w, 2, None)
-        variant = P.psc_get_degrid(s.handle)
-        res = {}
-        for name, form in (("plain", P.SOLVE_PLAIN), ("batched", P.SOLVE_BATCHED),
-                           ("graph", P.SOLVE_GRAPH)):
-            off = start.clone()
-            s.solve(v_obs, w, off, gain=0.5, n_max=1, tol_rad=0.0, form=form)  # warm-up
-            off = start.clone()
+def kernel_name(P, variant, S, waves):
+    return {P.DEGRID_VALU: f"k_item<{S},grad> (table form, vector FP32)",
+            P.DEGRID_MFMA: f"k_item<{S},grad> (table form, FP32 matrix cores)",
+            P.DEGRID_WINDOW: f"k_winw<{S},grad,{waves} waves> (window form, {2 * S}-lane workers)"}[variant]
+
+
+def roofline(flops, kernel_ms, traffic, kernel):
+    achieved = flops / (kernel_ms * 1e-3)
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK, "traffic": traffic,
+            "traffic_unit": "bytes per launch (FETCH_SIZE x2 + WRITE_SIZE, copy-calibrated)",
+            "kernel": kernel + " + k_reduce", "launch_ms": kernel_ms}
+
+
+class Workload:
+    """A planned workload on the GPU: observed data made by psc_predict at the
+    injected offsets, unit weights, a start 30 arcsec off per axis, the
+    autotuner's degrid variant."""
+
+    def __init__(self, cfg, channels=0, tune=True, **overrides):
+        import torch
+        from paper_1709_08681_amd import synth
+        from paper_1709_08681_amd import psc as P
+        self.torch, self.P = torch, P
+        obs = synth.make_config(cfg, **overrides)
+        if channels:
+            obs = obs.subset(chans=range(channels))
+        self.obs = obs
+        self.s = P.Session(obs, device=0)
+        s = self.s
+        self.stream = torch.cuda.current_stream()
+        self.v_obs = s.predict(s.offsets(obs.offsets_true))
+        self.w = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+        self.start_np = synth.perturbed_offsets(obs, 30.0, 99)
+        self.start = s.offsets(self.start_np)
+        self.off = self.start.clone()  # one offsets buffer for every timed run
+        self.acc = torch.empty(s.off_shape[:3] + (6,), dtype=torch.float64, device=s.dev)
+        self.mx = torch.empty(obs.n_int, dtype=torch.float64, device=s.dev)
+        self.tune_us = None
+        if tune:
+            self.tune_us = P.psc_tune(s.ctx, s.handle, self.start, self.v_obs, self.w, 3, self.stream)
+        self.info = P.psc_obs_launch_info(s.handle)
+        S = obs.wl.support
+        self.kernel = kernel_name(P, self.info["degrid"], S, self.info["window_waves"])
+        self.flops = obs.n_vis * 40.0 * S * S  # five complex multiply-adds per tap
+
+    def solve_form(self, form, iters, warmup):
+        """Algorithm 1 for `iters` iterations (tol = 0, so every interval runs
+        them all) from the same start in the given form; returns (ms per
+        iteration, offsets, ms of the first call).  The warm-up call has the
+        same arguments, so the graph form captures its graph there and the
+        timed call only replays it."""
+        torch, s = self.torch, self.s
+        first_ms = None
+        for k in range(max(1, warmup)):
+            self.off.copy_(self.start)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            s.solve(v_obs, w, off, gain=0.5, n_max=iters, tol_rad=0.0, form=form)
+            s.solve(self.v_obs, self.w, self.off, gain=0.5, n_max=iters, tol_rad=0.0, form=form)
             torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            res[name] = {"vis_per_s": obs.n_vis * iters / dt, "ms_per_iteration": dt * 1e3 / iters}
-            res[name + "_offsets"] = off
-        same = bool(torch.equal(res["plain_offsets"], res["graph_offsets"]) and
-                    torch.equal(res["batched_offsets"], res["graph_offsets"]))
-        out = {k: v for k, v in res.items() if not k.endswith("_offsets")}
-        out.update({
-            "workload": describe(obs)["workload"],
-            "n_vis": int(obs.n_vis),
-            "iterations": iters,
-            "graph_over_plain": out["graph"]["vis_per_s"] / out["plain"]["vis_per_s"],
-            "bit_identical_offsets": same,
-            "degrid": {P.DEGRID_VALU: "table, vector", P.DEGRID_MFMA: "table, matrix cores",
-                       P.DEGRID_WINDOW: "window"}[variant],
-            "tune_us": {"vector": tune_us[0], "matrix_core": tune_us[1], "window": tune_us[2]},
-        })
+            if k == 0:
+                first_ms = (time.perf_counter() - t0) * 1e3
+        self.off.copy_(self.start)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.solve(self.v_obs, self.w, self.off, gain=0.5, n_max=iters, tol_rad=0.0, form=form)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return dt * 1e3 / iters, self.off.clone(), first_ms
+
+    def eager_steps(self, steps, warmup):
+        """The same iteration written out with the C-ABI calls on the bench's
+        stream (psc_gradient, then psc_solve_step), HIP events around every
+        gradient launch: returns (ms per step, ms per gradient launch)."""
+        torch, P, s, obs = self.torch, self.P, self.s, self.obs
+
+        def step(ev=None):
+            if ev is not None:
+                ev[0].record(self.stream)
+            P.psc_gradient(s.ctx, s.handle, self.off, self.v_obs, self.w, self.acc, None, self.stream)
+            if ev is not None:
+                ev[1].record(self.stream)
+            P.psc_solve_step(s.ctx, obs.n_int, obs.n_pol, obs.n_ant, self.acc, 0.5, 0.0, self.off, None,
+                             self.mx, self.stream)
+
+        self.off.copy_(self.start)
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(self.stream)
+        for k in range(steps):
+            step(evs[k])
+        t1.record(self.stream)
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / steps, sum(a.elapsed_time(b) for a, b in evs) / steps
+
+    def close(self):
+        self.s.close()
+
+
+def forms_report(wl, iters, warmup, forms=("graph", "batched", "plain")):
+    """The three execution forms of Algorithm 1 on one workload."""
+    P = wl.P
+    code = {"plain": P.SOLVE_PLAIN, "batched": P.SOLVE_BATCHED, "graph": P.SOLVE_GRAPH}
+    res, offs = {}, {}
+    for name in forms:
+        ms, offs[name], first = wl.solve_form(code[name], iters, warmup)
+        res[name] = {"vis_per_s": wl.obs.n_vis / (ms * 1e-3), "ms_per_iteration": ms}
+        if name == "graph":
+            # the first call captured and instantiated the graph, then ran it
+            res[name]["capture_and_instantiate_ms"] = first - ms * iters
+    ref = offs[forms[0]]
+    res["bit_identical_offsets"] = bool(all(wl.torch.equal(ref, o) for o in offs.values()))
+    if "plain" in res and "graph" in res:
+        res["graph_over_plain"] = res["graph"]["vis_per_s"] / res["plain"]["vis_per_s"]
+    if "plain" in res and "batched" in res:
+        res["batched_over_plain"] = res["batched"]["vis_per_s"] / res["plain"]["vis_per_s"]
+    res["iterations"] = iters
+    return res
+
+
+def single_interval_extra(steps, warmup):
+    """The single-interval workload (2,021,760 visibilities, 1024^2 grid): the
+    eager step with its own roofline."""
+    wl = Workload(2)
+    try:
+        ms_step, kern_ms = wl.eager_steps(steps, warmup)
+        table = wl.info["degrid"] == wl.P.DEGRID_VALU
+        return {"workload": describe(wl.obs), "n_vis": int(wl.obs.n_vis), "ms_per_step": ms_step,
+                "vis_per_s": wl.obs.n_vis / (ms_step * 1e-3), "degrid": wl.kernel,
+                "plan_ms": wl.info["plan_ms"],
+                "tune_us": dict(zip(("vector", "matrix_core", "window"), wl.tune_us)),
+                "roofline": roofline(wl.flops, kern_ms, measured_traffic("table") if table else None,
+                                     wl.kernel)}
+    finally:
+        wl.close()
+
+
+def large_share_extra(channels, iters):
+    """One GPU's channel share of the large workload (128 antennas, 8128
+    baselines, 600 x 10 s, 2 pols with opposite squint, 64 uneven intervals,
+    4096^2 grid, support 32, oversampling 8): the three solve forms, the eager
+    step's roofline, and the autograd forward + backward (psc_predict, then
+    psc_predict_vjp through torch.autograd)."""
+    torch = __import__("torch")
+    from paper_1709_08681_amd.autograd import predict as diff_predict
+    t0 = time.perf_counter()
+    wl = Workload(5, channels=channels, tune=False)
+    setup_s = time.perf_counter() - t0
+    try:
+        out = {"workload": describe(wl.obs), "n_vis": int(wl.obs.n_vis), "degrid": wl.kernel,
+               "plan_ms": wl.info["plan_ms"], "setup_s": setup_s}
+        out.update(forms_report(wl, iters, 1))
+        ms_step, kern_ms = wl.eager_steps(iters, 1)
+        out["eager"] = {"ms_per_step": ms_step, "vis_per_s": wl.obs.n_vis / (ms_step * 1e-3)}
+        out["roofline"] = roofline(wl.flops, kern_ms, measured_traffic("window_large"), wl.kernel)
+        # autograd: chi^2 = sum w |V_obs - V(p)|^2, backward through the adjoint
+        p = wl.start.clone().requires_grad_(True)
+        for k in range(2):
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            v = diff_predict(p, wl.s)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            loss = ((wl.v_obs - v).abs() ** 2).sum()
+            loss.backward()
+            torch.cuda.synchronize()
+            tc = time.perf_counter()
+            p.grad = None
+            del v, loss
+        out["autograd"] = {"forward_ms": (tb - ta) * 1e3, "backward_ms": (tc - tb) * 1e3,
+                           "note": "psc_predict forward; chi^2 in torch; backward = psc_predict_vjp "
+                                   "(kernels rebuilt, not stored) + torch's elementwise grad"}
         return out
     finally:
-        s.close()
+        wl.close()
 
 
-def image_gradient_timing(s, obs, off, v_obs, w, reps, stream):
-    """psc_image_gradient (d chi^2 / d I on the model grid) on the same data:
-    predict, residual scatter through per-item LDS patches (float64 atomics
-    once per patch cell), float64 N^2 FFT."""
-    import torch
-    from paper_1709_08681_amd import psc as P
-    n = obs.grid_n
+def image_gradient_timing(wl, reps):
+    """psc_image_gradient (d chi^2 / d I on the model grid) on the same data."""
+    torch, P, s = wl.torch, wl.P, wl.s
+    n = wl.obs.grid_n
     out = torch.empty((n, n), dtype=torch.float64, device=s.dev)
-    P.psc_image_gradient(s.ctx, s.handle, off, v_obs, w, out, None, stream)  # warm-up, scratch
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    P.psc_image_gradient(s.ctx, s.handle, wl.start, wl.v_obs, wl.w, out, None, wl.stream)  # warm-up
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    e0.record(stream)
+    e0.record(wl.stream)
     for _ in range(reps):
-        P.psc_image_gradient(s.ctx, s.handle, off, v_obs, w, out, None, stream)
-    e1.record(stream)
+        P.psc_image_gradient(s.ctx, s.handle, wl.start, wl.v_obs, wl.w, out, None, wl.stream)
+    e1.record(wl.stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    return {"ms_per_call": ms, "vis_per_s": obs.n_vis / (ms * 1e-3), "calls": reps,
-            "grid": f"{n}^2", "note": "table form, support 16, LDS-patch scatter"}
+    return {"ms_per_call": ms, "vis_per_s": wl.obs.n_vis / (ms * 1e-3), "calls": reps,
+            "grid": f"{n}^2"}
 
 
-def extension_timing(obs, start, reps, what, device=0):
-    """Gradient launches of one extension on the workload's data, on a session
-    of its own:
+def extension_timing(cfg, reps, what):
+    """Gradient launches of one extension on a workload's data, on a session of
+    its own:
       mount_frame        offsets in the antenna mount frame (every row's
                          parallactic angle), per-sample image-plane products;
       measured_aperture  the same with a measured, non-circular aperture
@@ -154,30 +283,20 @@ def extension_timing(obs, start, reps, what, device=0):
                          products stored per item, five plain sums);
       beam_scale         psc_scale_gradient: the sums for a beam-width scale
                          per antenna (scales set within 3% of nominal);
-      w_term             the workload's array shrunk to arms of 1 km (the
-                         w-term's support limit; see the header), window form
-                         with e^{2 pi i w (n-1)} per image sample."""
+      w_term             the array's arms shrunk to 1 km (the w-term's
+                         support limit), window form with e^{2 pi i w (n-1)}
+                         per image sample."""
     import torch
     from paper_1709_08681_amd import psc as P
     from paper_1709_08681_amd import synth
-    kw, note = {}, ""
-    if what == "mount_frame":
-        kw, note = dict(mount_frame=True), "window form, per-sample image-plane products"
-    elif what == "measured_aperture":
-        kw = dict(mount_frame=True, aperture=synth.measured_aperture())
-        note = "window form, per-sample bicubic lookups of the aperture's transform, mount frame"
-    elif what == "measured_aperture_sky":
-        kw = dict(aperture=synth.measured_aperture())
-        note = "window form, the aperture's products stored per item, sky frame"
-    elif what == "beam_scale":
-        kw, note = dict(mount_frame=True), "psc_scale_gradient, window form, mount frame"
-    elif what == "w_term":
-        if obs.wl.name != "single_interval":
-            return {"skipped": "timed on the single-interval array only"}
-        obs = synth.make_config(2, layout_radius_m=1000.0)
-        start = synth.perturbed_offsets(obs, 30.0, 1)
-        kw, note = dict(w_term=True), "window form with the w phase, arms shrunk to 1 km"
-    s = P.Session(obs, device=device, **kw)
+    obs = synth.make_config(cfg, layout_radius_m=1000.0) if what == "w_term" else synth.make_config(cfg)
+    start = synth.perturbed_offsets(obs, 30.0, 99)
+    kw = {"mount_frame": dict(mount_frame=True),
+          "measured_aperture": dict(mount_frame=True, aperture=synth.measured_aperture()),
+          "measured_aperture_sky": dict(aperture=synth.measured_aperture()),
+          "beam_scale": dict(mount_frame=True),
+          "w_term": dict(w_term=True)}[what]
+    s = P.Session(obs, device=0, **kw)
     try:
         stream = torch.cuda.current_stream()
         v = s.predict(s.offsets(obs.offsets_true))
@@ -193,8 +312,7 @@ def extension_timing(obs, start, reps, what, device=0):
             acc = torch.empty(s.off_shape[:3] + (6,), dtype=torch.float64, device=s.dev)
             call = lambda: P.psc_gradient(s.ctx, s.handle, off, v, w, acc, None, stream)
         call()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record(stream)
         for _ in range(reps):
@@ -202,29 +320,36 @@ def extension_timing(obs, start, reps, what, device=0):
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        res = {"ms_per_gradient": ms, "vis_per_s": obs.n_vis / (ms * 1e-3), "calls": reps, "note": note}
-        if what == "mount_frame":
-            pa = obs.par_angle
-            res["par_angle_range_deg"] = [float(np.degrees(pa.min())), float(np.degrees(pa.max()))]
-        return res
+        return {"workload": describe(obs), "ms_per_gradient": ms, "vis_per_s": obs.n_vis / (ms * 1e-3),
+                "calls": reps}
     finally:
         s.close()
 
 
-def cpu_baseline(obs, start, seconds):
-    """The oracle (FP64 direct sum) on the host cores: gradient + update
-    iterations for about `seconds`, over the whole workload or, when one
-    iteration would take far longer, over its first timesteps."""
+def cpu_baseline(cfg, start, seconds):
+    """The oracle (FP64 direct sum, OpenMP on every host core) on a bounded
+    sample of the workload: the first solution intervals whose visibilities
+    times sky pixels stay within a budget of about ten seconds of oracle work
+    per iteration, gradient + update iterations for about `seconds`.  The
+    oracle's cost per visibility is proportional to the number of non-zero sky
+    pixels, which the sample shares with the whole workload, so its vis/s
+    stands for the whole workload's."""
     import oracle
+    from paper_1709_08681_amd import synth
+    obs = synth.make_config(cfg)
     n_src = len(obs.src_flux) + (0 if obs.extra_flux is None else len(obs.extra_flux))
-    budget = 5e8  # visibility x pixel terms, about 10 s of the oracle on 16 cores
-    if obs.n_vis * n_src > budget:
-        per_t = obs.n_vis / max(1, len(np.unique(obs.time_idx)))
-        n_t = max(1, int(budget / (per_t * n_src)))
-        obs = obs.subset(times=range(n_t))  # offsets keep their shape
+    budget = 5e8  # visibility x pixel terms per iteration
+    whole = obs.n_vis * n_src <= budget
+    if not whole:
+        per_row = obs.n_chan * obs.n_pol
+        rows_ok = int(budget / (per_row * n_src))
+        n_keep = int(np.searchsorted(obs.int_row_ptr, rows_ok, side="right")) - 1
+        n_keep = max(1, n_keep)
+        keep_t = np.unique(obs.time_idx[:obs.int_row_ptr[n_keep]])
+        obs = obs.subset(times=keep_t)
     prob = oracle.Problem.from_observation(obs)
     v_obs_np = oracle.predict(prob, obs.offsets_true)  # untimed: the oracle's own data
-    off = start.copy()
+    off = np.array(start, dtype=np.float64, copy=True)
     t0 = time.perf_counter()
     iters = 0
     while True:
@@ -234,14 +359,15 @@ def cpu_baseline(obs, start, seconds):
         if time.perf_counter() - t0 >= seconds:
             break
     dt = time.perf_counter() - t0
+    live = int(np.count_nonzero(np.diff(obs.int_row_ptr)))
     out = {
         "value": obs.n_vis * iters / dt,
         "unit": "vis/s",
         "cores": int(oracle.num_threads()),
         "kind": "oracle",
-        "sample": f"{obs.n_vis} visibilities x {len(prob.src_flux)} sky pixels "
-                  f"({'whole workload' if obs.n_vis * n_src <= budget else 'first timesteps'}), "
-                  f"{iters} gradient+update iteration(s) in {dt:.1f} s, FP64 direct summation",
+        "sample": (f"{obs.n_vis} visibilities x {len(prob.src_flux)} sky pixels "
+                   f"({'whole workload' if whole else f'the first {live} of {obs.n_int} solution intervals'}), "
+                   f"{iters} gradient+update iteration(s) in {dt:.1f} s, FP64 direct summation"),
         "cpu_model": cpu_model(),
     }
     out.update(single_thread_rate(prob, off, v_obs_np))
@@ -260,9 +386,9 @@ def cpu_model():
 
 
 def single_thread_rate(prob, off, v_obs):
-    """One gradient + update of the oracle on one thread, over the first
-    rows of the same problem (a child process with OMP_NUM_THREADS=1; it
-    does not touch the GPU)."""
+    """One gradient + update of the oracle on one thread, over the first rows
+    of the same problem (a child process with OMP_NUM_THREADS=1; it does not
+    touch the GPU)."""
     import subprocess
     import tempfile
     rows = int(min(prob.n_row, max(1, 2e7 // max(1, len(prob.src_flux) * prob.n_chan * prob.n_pol))))
@@ -302,18 +428,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--channels", type=int, default=0,
-                    help="keep the first N channels: one GPU's channel share of a larger workload")
+    ap.add_argument("--config", type=int, default=3, help="headline workload (3: batched)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batched-config", type=int, default=3)
-    ap.add_argument("--batched-iters", type=int, default=3)
-    ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--no-image-gradient", action="store_true")
-    ap.add_argument("--no-mount-frame", action="store_true")
-    ap.add_argument("--no-extensions", action="store_true",
-                    help="skip the measured-aperture, beam-scale and w-term timings")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the single-interval, large-share, short-interval and extension timings")
+    ap.add_argument("--large-channels", type=int, default=32,
+                    help="channels of the large workload's share (one GPU of eight: 32)")
+    ap.add_argument("--large-iters", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: runs on one GPU only; sharding the path across GPUs (by solution "
@@ -321,74 +443,19 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import torch
-    from paper_1709_08681_amd import synth
-    from paper_1709_08681_amd import psc as P
-    from paper_1709_08681_amd.psc import Session, psc_gradient, psc_solve_step
-
-    obs = synth.make_config(args.config)
-    if args.channels:
-        obs = obs.subset(chans=range(args.channels))
-    print(f"bench: workload {obs.wl.name}, {obs.n_vis} visibilities", file=sys.stderr, flush=True)
-    s = Session(obs, device=0)
-    stream = torch.cuda.current_stream()
-    off_true = s.offsets(obs.offsets_true)
-    v_obs = s.predict(off_true)
-    w = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
-    start = synth.perturbed_offsets(obs, 30.0, 99)
-    off = s.offsets(start)
-    acc = torch.empty(s.off_shape[:3] + (6,), dtype=torch.float64, device=s.dev)
-    mx = torch.empty(obs.n_int, dtype=torch.float64, device=s.dev)
-    # the autotuner times every degrid variant on this data and keeps the fastest
-    tune_us = P.psc_tune(s.ctx, s.handle, off, v_obs, w, 3, stream)
-    variant = P.psc_get_degrid(s.handle)
-    S = obs.wl.support
-    kernel = {P.DEGRID_VALU: f"k_item<{S},grad> (table form, vector FP32)",
-              P.DEGRID_MFMA: f"k_item<{S},grad> (table form, FP32 matrix cores)",
-              P.DEGRID_WINDOW: f"k_winw<{S},grad> (window form, {2 * S}-lane workers)"}[variant]
-
-    def step(ev=None):
-        if ev is not None:
-            ev[0].record(stream)
-        psc_gradient(s.ctx, s.handle, off, v_obs, w, acc, None, stream)
-        if ev is not None:
-            ev[1].record(stream)
-        psc_solve_step(s.ctx, obs.n_int, obs.n_pol, obs.n_ant, acc, 0.5, 0.0, off, None, mx, stream)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_start.record(stream)
-    for k in range(args.steps):
-        step(evs[k])
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    ms_total = t_start.elapsed_time(t_end)
-    ms_step = ms_total / args.steps
-    grad_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
-    value = obs.n_vis / (ms_step * 1e-3)
-
-    flops = obs.n_vis * 40.0 * S * S  # five complex multiply-adds per tap
-    achieved = flops / (grad_ms * 1e-3)
-    roof = {
-        "bound": "alu",
-        "achieved": achieved / 1e12,
-        "peak": FP32_VECTOR_PEAK / 1e12,
-        "unit": "TFLOP/s",
-        "frac": achieved / FP32_VECTOR_PEAK,
-        "traffic": measured_traffic() if (args.config == 2 and variant == P.DEGRID_VALU) else None,
-        "traffic_unit": "bytes per launch (FETCH_SIZE x2 + WRITE_SIZE, copy-calibrated)",
-        "kernel": kernel + " + k_reduce",
-        "launch_ms": grad_ms,
-    }
+    print(f"bench: headline workload {args.config}", file=sys.stderr, flush=True)
+    wl = Workload(args.config)
+    obs = wl.obs
+    rep = forms_report(wl, args.steps, args.warmup)
+    ms_step = rep["graph"]["ms_per_iteration"]
+    print("bench: eager steps with per-launch events", file=sys.stderr, flush=True)
+    eager_ms, kern_ms = wl.eager_steps(args.steps, args.warmup)
+    which = "window" if wl.info["degrid"] == wl.P.DEGRID_WINDOW else "table"
+    traffic = measured_traffic(which) if args.config in (3, 2) and \
+        PROFILES[which][0].endswith({3: "batched.md", 2: "single_interval.md"}[args.config]) else None
     out = {
         "metric": "predict+gradient visibilities/s",
-        "value": value,
+        "value": obs.n_vis / (ms_step * 1e-3),
         "unit": "vis/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -400,35 +467,51 @@ def main():
         "dtype": "f32",
         "accumulate_dtype": "f64",
         "data": "synthetic",
-        "config": dict(describe(obs), degrid=kernel,
-                       tune_us={name: t for name, t in zip(("vector", "matrix_core", "window"), tune_us)}),
-        "roofline": roof,
+        "config": {
+            "workload": describe(obs),
+            "n_vis": int(obs.n_vis),
+            "n_intervals": int(obs.n_int),
+            "grid_n": int(obs.grid_n),
+            "support": int(obs.wl.support),
+            "oversample": int(obs.wl.oversample),
+            "step": "one Algorithm-1 iteration over every interval: psc_solve, graph form",
+            "degrid": wl.kernel,
+            "samples_per_item": wl.info["samples_per_item"],
+            "plan_ms": wl.info["plan_ms"],
+            "tune_us": dict(zip(("vector", "matrix_core", "window"), wl.tune_us)),
+        },
+        "roofline": roofline(wl.flops, kern_ms, traffic, wl.kernel),
+        "batched_vs_plain": rep,
+        "eager_step": {"ms_per_step": eager_ms, "ms_per_gradient_launch": kern_ms,
+                       "note": "psc_gradient + psc_solve_step on the bench's stream, HIP events "
+                               "around each gradient launch; the roofline's launch time"},
     }
-    if not args.no_image_gradient and S == 16:
+    if not args.no_extras and obs.wl.support == 16:
         print("bench: image gradient", file=sys.stderr, flush=True)
-        out["image_gradient"] = image_gradient_timing(s, obs, off, v_obs, w, 5, stream)
-    s.close()
-    if not args.no_mount_frame:
-        print("bench: mount-frame offsets", file=sys.stderr, flush=True)
-        out["mount_frame"] = extension_timing(obs, start, 3, "mount_frame")
-    if not args.no_extensions:
-        out["extensions"] = {}
-        for what in ("measured_aperture", "measured_aperture_sky", "beam_scale", "w_term"):
-            print(f"bench: {what}", file=sys.stderr, flush=True)
-            out["extensions"][what] = extension_timing(obs, start, 3, what)
-    if not args.no_batched:
-        print(f"bench: batched vs plain on workload {args.batched_config}", file=sys.stderr,
-              flush=True)
-        out["batched_vs_plain"] = batched_vs_plain(args.batched_config, args.batched_iters)
-        # the same array with 1024 short intervals (1 to 8 timesteps): per-interval
+        out["image_gradient"] = image_gradient_timing(wl, 3)
+    wl.close()
+    if not args.no_extras:
+        print("bench: single interval", file=sys.stderr, flush=True)
+        out["single_interval"] = single_interval_extra(args.steps, args.warmup)
+        print("bench: short intervals", file=sys.stderr, flush=True)
+        # the batched array with 1024 intervals of 1 to 8 timesteps: per-interval
         # launches then carry little work each
         short = [int(x) for x in np.random.default_rng(7).integers(1, 9, size=1024)]
-        print("bench: batched vs plain, short intervals", file=sys.stderr, flush=True)
-        out["batched_vs_plain_short"] = batched_vs_plain(args.batched_config, args.batched_iters,
-                                                         interval_lengths=short)
+        wls = Workload(3, interval_lengths=short)
+        try:
+            out["batched_vs_plain_short"] = dict(forms_report(wls, 3, 1), workload=describe(wls.obs),
+                                                 n_vis=int(wls.obs.n_vis), degrid=wls.kernel)
+        finally:
+            wls.close()
+        print(f"bench: large workload, {args.large_channels}-channel share", file=sys.stderr, flush=True)
+        out["large_share"] = large_share_extra(args.large_channels, args.large_iters)
+        out["extensions"] = {}
+        for what in ("mount_frame", "measured_aperture", "measured_aperture_sky", "beam_scale", "w_term"):
+            print(f"bench: {what}", file=sys.stderr, flush=True)
+            out["extensions"][what] = extension_timing(2, 3, what)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(obs, start, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(args.config, wl.start_np, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

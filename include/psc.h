@@ -200,6 +200,30 @@ PSC_API psc_status psc_obs_info(const psc_obs* obs, int64_t* n_items, int64_t* n
                                 int64_t* n_vis);
 
 /*
+ * How the observation's gradient launches (host struct, filled by
+ * psc_obs_launch_info; sync, no device work).  Describes the launch shape
+ * of the A-Projection degrid of Algorithm 1 as planned for this data, so a
+ * caller can see which kernel the autotuner kept and how the plan split it.
+ *   degrid            PSC_DEGRID_* the gradient and adjoint run in
+ *   window_waves      wavefronts per block of the window-form gradient
+ *                     kernel (1 or 2 for items of few samples at support
+ *                     16, else 4, or 8 at support 32 when two blocks of four
+ *                     do not fit a compute unit's LDS)
+ *   samples_per_item  mean samples per work item (interval, baseline,
+ *                     channel): what the block shape is chosen from
+ *   plan_ms           host wall time psc_obs_create took (planning, uploads
+ *                     and setup kernels)
+ * PSC_E_ARG for a null observation or output.
+ */
+typedef struct {
+    int32_t degrid;
+    int32_t window_waves;
+    double samples_per_item;
+    double plan_ms;
+} psc_launch_info;
+PSC_API psc_status psc_obs_launch_info(const psc_obs* obs, psc_launch_info* out);
+
+/*
  * Predict (async): V^M_ij = [A_i (x) A_j*] * V^{M0} (Eq. MEDD, Eq. ME with the
  * direction-independent term equal to one), where A_i carries antenna i's
  * pointing offset as an aperture phase gradient (Sec. 3, Eq. AIJPOINTING

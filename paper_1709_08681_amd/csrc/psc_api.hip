@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <new>
 #include <string>
 #include <vector>
@@ -55,6 +56,7 @@ struct psc_obs {
     double* scale = nullptr;   // beam-width scales [n_int][n_pol][n_ant] (null: all 1)
     double* zero_pa = nullptr; // [n_row] zeros: the per-sample scatter's angles with scales, sky frame
     int32_t win_waves = 0;     // window-form block size at support 16 (see ItemArgs)
+    double plan_ms = 0;        // wall time psc_obs_create took
     int32_t ap_n = 0;
     double ap_c = 0, ap_step = 0;
     double* partials = nullptr;  // [n_items][n_pol][12]
@@ -646,6 +648,20 @@ static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
         return fail(ctx, st, msg);
     }
     *out = obs;
+    return PSC_OK;
+}
+
+PSC_API psc_status psc_obs_launch_info(const psc_obs* obs, psc_launch_info* out)
+{
+    if (!obs) return fail(nullptr, PSC_E_ARG, "null observation");
+    if (!out) return fail(obs->ctx, PSC_E_ARG, "null output");
+    const psc_ctx* ctx = obs->ctx;
+    const int frame = obs->ap_tab ? (obs->par_angle ? kFrameAperture : kFrameSkyAperture)
+                                  : (obs->par_angle ? kFrameMount : kFrameSky);
+    out->degrid = obs->degrid;
+    out->window_waves = win_block_waves(ctx->s, kGrad, frame, ctx->m, ctx->o, obs->n_tab, obs->win_waves);
+    out->samples_per_item = obs->n_items > 0 ? (double)obs->n_vis / (double)obs->n_items : 0.0;
+    out->plan_ms = obs->plan_ms;
     return PSC_OK;
 }
 
@@ -1268,7 +1284,11 @@ PSC_API psc_status psc_create(const psc_config* cfg, psc_ctx** out)
 PSC_API psc_status psc_obs_create(psc_ctx* ctx, const psc_obs_desc* d, psc_obs** out)
 {
     try {
-        return obs_create_impl(ctx, d, out);
+        const auto t0 = std::chrono::steady_clock::now();
+        const psc_status st = obs_create_impl(ctx, d, out);
+        if (st == PSC_OK)
+            (*out)->plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return st;
     } catch (...) {
         return host_oom(ctx);
     }

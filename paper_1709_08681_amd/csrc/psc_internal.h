@@ -174,6 +174,12 @@ hipError_t launch_win(int mode, int support, const ItemArgs& a, hipStream_t s);
 size_t win_lds_bytes(int support, int mode, int m, int oversample, int mount_frame_tab = -1);
 size_t winw_lds_bytes(int support, int waves, int mode, int m, int oversample, int mount_frame_tab = -1);
 size_t win_lds_budget(int support);
+// Wavefronts per block of a window-form launch (frame: a kFrame* value, or
+// kFrameSkyAperture for a measured aperture without parallactic angles),
+// given the plan's choice for items of few samples (ItemArgs::win_waves); 0
+// when no block fits.
+constexpr int kFrameSkyAperture = 3;
+int win_block_waves(int support, int mode, int frame, int m, int oversample, int n_tab, int plan_waves);
 // Image-gradient scatter with per-item LDS patches (psc_grid.hip), support
 // 16: one thread per tap, chunks of kGridChunk samples, patches of
 // kGridPatch^2 cells.  grid_lds_bytes is its dynamic LDS; launch_grid refuses

@@ -29,11 +29,11 @@ __host__ __device__ constexpr int win_ng(int mode)
     return mode == kGrad || mode == kScale ? 3 : mode == kVjp ? 2 : 1;
 }
 
-// A measured aperture in the sky frame (no parallactic angles): the pattern
-// is fixed for the item, so its image-plane products are stored per image
-// sample like the radial factors, but one per variant (the pattern is not
-// radial, so the derivative sums do not factor).
-constexpr int kFrameSkyAperture = 3;
+// kFrameSkyAperture (psc_internal.h): a measured aperture in the sky frame
+// (no parallactic angles); the pattern is fixed for the item, so its
+// image-plane products are stored per image sample like the radial factors,
+// but one per variant (the pattern is not radial, so the derivative sums do
+// not factor).
 
 // Factors stored per image sample by a window kernel of the given frame and
 // mode (0: none, the mount frames evaluate them per sample).
@@ -546,50 +546,49 @@ static size_t winw_frame_lds(int support, int waves, int mode, int frame, int m,
     return b;
 }
 
+int win_block_waves(int support, int mode, int frame, int m, int oversample, int n_tab, int plan_waves)
+{
+    // items of few samples at support 16: one or two wavefronts (two or four
+    // workers) per block, as the plan chose
+    if (support == 16 && (plan_waves == 1 || plan_waves == 2)) return plan_waves;
+    // four wavefronts when two blocks fit a compute unit's LDS, else eight
+    // (support 32 with many image samples)
+    const size_t budget = win_lds_budget(support);
+    const size_t sh4 = winw_frame_lds(support, 4, mode, frame, m, oversample, n_tab);
+    if (2 * (sh4 + (160 * 1024 - budget)) <= 160 * 1024) return 4;
+    if (support == 32 && winw_frame_lds(support, 8, mode, frame, m, oversample, n_tab) <= budget) return 8;
+    return 0;
+}
+
+template <int S, int MODE, int MF, int W, bool WT>
+static hipError_t launch_win_w(const ItemArgs& a, hipStream_t s)
+{
+    // raise the dynamic LDS limit once, to what one compute unit allows
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void*)k_winw<S, MODE, MF, W, WT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (int)win_lds_budget(S));
+    if (attr != hipSuccess) return attr;
+    const int blocks = 8 * ((a.n_items + 7) / 8);
+    const size_t sh = winw_frame_lds(S, W, MODE, MF, a.m, a.oversample, a.n_tab);
+    k_winw<S, MODE, MF, W, WT><<<blocks, 64 * W, sh, s>>>(a);
+    return hipGetLastError();
+}
+
 template <int S, int MODE, int MF, bool WT>
 static hipError_t launch_win_t(const ItemArgs& a, hipStream_t s)
 {
-    const size_t budget = win_lds_budget(S);
-    // raise the dynamic LDS limit once, to what one compute unit allows
-    static const hipError_t attr4 = hipFuncSetAttribute(
-        (const void*)k_winw<S, MODE, MF, 4, WT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget);
-    if (attr4 != hipSuccess) return attr4;
-    const int blocks = 8 * ((a.n_items + 7) / 8);
-    if constexpr (S == 16) {
-        // items of few samples: one or two wavefronts (two or four workers)
-        // per block
-        if (a.win_waves == 1) {
-            static const hipError_t attr1 = hipFuncSetAttribute(
-                (const void*)k_winw<S, MODE, MF, 1, WT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget);
-            if (attr1 != hipSuccess) return attr1;
-            const size_t sh1 = winw_frame_lds(S, 1, MODE, MF, a.m, a.oversample, a.n_tab);
-            k_winw<S, MODE, MF, 1, WT><<<blocks, 64, sh1, s>>>(a);
-            return hipGetLastError();
-        }
-        if (a.win_waves == 2) {
-            static const hipError_t attr2 = hipFuncSetAttribute(
-                (const void*)k_winw<S, MODE, MF, 2, WT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget);
-            if (attr2 != hipSuccess) return attr2;
-            const size_t sh2 = winw_frame_lds(S, 2, MODE, MF, a.m, a.oversample, a.n_tab);
-            k_winw<S, MODE, MF, 2, WT><<<blocks, 64 * 2, sh2, s>>>(a);
-            return hipGetLastError();
-        }
-    }
-    // four wavefronts when two blocks fit a compute unit's LDS, else eight
-    // (support 32 with many image samples)
-    const size_t sh4 = winw_frame_lds(S, 4, MODE, MF, a.m, a.oversample, a.n_tab);
-    if (2 * (sh4 + (160 * 1024 - budget)) <= 160 * 1024) {
-        k_winw<S, MODE, MF, 4, WT><<<blocks, 64 * 4, sh4, s>>>(a);
-        return hipGetLastError();
-    }
-    if constexpr (S == 32) {
-        static const hipError_t attr8 = hipFuncSetAttribute(
-            (const void*)k_winw<S, MODE, MF, 8, WT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget);
-        if (attr8 != hipSuccess) return attr8;
-        const size_t sh8 = winw_frame_lds(S, 8, MODE, MF, a.m, a.oversample, a.n_tab);
-        if (sh8 > budget) return hipErrorInvalidValue;
-        k_winw<S, MODE, MF, 8, WT><<<blocks, 64 * 8, sh8, s>>>(a);
-        return hipGetLastError();
+    switch (win_block_waves(S, MODE, MF, a.m, a.oversample, a.n_tab, a.win_waves)) {
+    case 4: return launch_win_w<S, MODE, MF, 4, WT>(a, s);
+    case 1:
+        if constexpr (S == 16) return launch_win_w<S, MODE, MF, 1, WT>(a, s);
+        break;
+    case 2:
+        if constexpr (S == 16) return launch_win_w<S, MODE, MF, 2, WT>(a, s);
+        break;
+    case 8:
+        if constexpr (S == 32) return launch_win_w<S, MODE, MF, 8, WT>(a, s);
+        break;
+    default: break;
     }
     return hipErrorInvalidValue;
 }

@@ -27,7 +27,7 @@ DEGRID_VALU, DEGRID_MFMA, DEGRID_WINDOW = 0, 1, 2
 ARCSEC = math.pi / (180.0 * 3600.0)
 
 EXPORTS = ["psc_version", "psc_create", "psc_destroy", "psc_last_error", "psc_set_model",
-           "psc_obs_create", "psc_obs_destroy", "psc_obs_info", "psc_predict", "psc_gradient",
+           "psc_obs_create", "psc_obs_destroy", "psc_obs_info", "psc_obs_launch_info", "psc_predict", "psc_gradient",
            "psc_predict_vjp", "psc_solve_step", "psc_solve", "psc_set_degrid", "psc_get_degrid",
            "psc_tune", "psc_image_gradient", "psc_set_beam_scale", "psc_get_beam_scale",
            "psc_scale_gradient", "psc_scale_step", "psc_solve_scale"]
@@ -47,6 +47,11 @@ class Config(C.Structure):
         ("taper_width", C.c_int32), ("taper_beta", C.c_double), ("device", C.c_int32),
         ("aperture_n", C.c_int32), ("aperture", C.c_void_p),
     ]
+
+
+class LaunchInfo(C.Structure):
+    _fields_ = [("degrid", C.c_int32), ("window_waves", C.c_int32), ("samples_per_item", C.c_double),
+                ("plan_ms", C.c_double)]
 
 
 class ObsDesc(C.Structure):
@@ -82,6 +87,7 @@ def load():
             "psc_obs_create": ([vp, C.POINTER(ObsDesc), C.POINTER(vp)], C.c_int),
             "psc_obs_destroy": ([vp], C.c_int),
             "psc_obs_info": ([vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)], C.c_int),
+            "psc_obs_launch_info": ([vp, C.POINTER(LaunchInfo)], C.c_int),
             "psc_predict": ([vp, vp, vp, vp, vp], C.c_int),
             "psc_gradient": ([vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
             "psc_predict_vjp": ([vp, vp, vp, vp, vp, vp], C.c_int),
@@ -158,6 +164,14 @@ def psc_obs_info(obs):
     a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
     _check(load().psc_obs_info(obs, C.byref(a), C.byref(b), C.byref(c)))
     return a.value, b.value, c.value
+
+
+def psc_obs_launch_info(obs):
+    """dict(degrid, window_waves, samples_per_item, plan_ms)."""
+    li = LaunchInfo()
+    _check(load().psc_obs_launch_info(obs, C.byref(li)))
+    return {"degrid": li.degrid, "window_waves": li.window_waves,
+            "samples_per_item": li.samples_per_item, "plan_ms": li.plan_ms}
 
 
 def psc_predict(ctx, obs, offsets_dev, vis_out_dev, stream=None):

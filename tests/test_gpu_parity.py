@@ -32,6 +32,42 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
+def elem_err(a, b):
+    """Largest single-visibility error relative to the rms visibility of the
+    set: max_k |a_k - b_k| / rms |b|."""
+    a, b = np.asarray(a).ravel(), np.asarray(b).ravel()
+    return float(np.abs(a - b).max() / np.sqrt(np.mean(np.abs(b) ** 2)))
+
+
+def per_antenna_err(acc, ref):
+    """Worst per-antenna relative error of each kind of sum: chi, the
+    gradient (g_l, g_m) and the normal matrix (H_ll, H_lm, H_mm), each
+    ||d||/||ref|| over one (interval, pol, antenna) entry; entries whose sums
+    are zero on the oracle side (no data) must be zero on the GPU side too."""
+    acc, ref = np.asarray(acc).reshape(-1, 6), np.asarray(ref).reshape(-1, 6)
+    out = []
+    for cols in ((0,), (1, 2), (3, 4, 5)):
+        d = np.linalg.norm(acc[:, cols] - ref[:, cols], axis=1)
+        n = np.linalg.norm(ref[:, cols], axis=1)
+        live = n > 0
+        assert np.all(d[~live] == 0.0)
+        out.append(float((d[live] / n[live]).max()) if live.any() else 0.0)
+    return out
+
+
+# Per-element bounds.  Each visibility is a float32 sum of S^2 taps (or, in
+# the window form, an S-point transform pair and an M^2 image-sample sum),
+# whose rounding error is of order sqrt(terms) * 2^-24 of the sum of the
+# terms' magnitudes; with the taper's kernel that sum stays within a few
+# times rms |V|, so one visibility's error stays near 1e-6 of rms |V|.  The
+# bound below is ten times the set-wide tolerance: a single visibility wrong
+# at 1e-4 of rms |V| fails it, which the norm over millions would hide.
+ELEM_VIS_TOL = 1e-4
+# per (interval, pol, antenna) entry: the set-wide sum tolerance, applied to
+# every antenna alone
+ANT_SUM_TOL = 1e-4
+
+
 def session(obs, **kw):
     from paper_1709_08681_amd.psc import Session
     return Session(obs, device=0, **kw)
@@ -268,23 +304,35 @@ def test_ragged_intervals_two_pols(torch_dev):
 # single interval at full size (config 2: 2,021,760 visibilities)
 # ---------------------------------------------------------------------------
 
-def test_cfg2_full_size_parity(torch_dev):
+@pytest.mark.parametrize("variant", ["vector", "matrix_core"])
+def test_cfg2_full_size_parity(torch_dev, variant):
+    """Single-interval workload at full size (2,021,760 visibilities), table
+    form on the vector units and on the matrix cores: every visibility and
+    every per-antenna sum against the oracle, set-wide and element by
+    element."""
     torch = torch_dev
-    print("case: cfg2 full size", flush=True)
+    from paper_1709_08681_amd import psc
+    print(f"case: cfg2 full size, table form, {variant}", flush=True)
     obs = synth.make_config(2)
     prob = oracle.Problem.from_observation(obs)
     s = session(obs)
     try:
+        psc.psc_set_degrid(s.handle, psc.DEGRID_VALU if variant == "vector" else psc.DEGRID_MFMA)
         start = synth.perturbed_offsets(obs, 30.0, 14)
         v_true = oracle.predict(prob, obs.offsets_true)
         ref_acc, ref_vm = oracle.gradient(prob, start, v_true, 1.0, want_model=True)
         w = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
         acc, vm = s.gradient(s.offsets(start), c64(torch, s, v_true), w, want_model=True)
-        e_v = rel(vm.cpu().numpy(), ref_vm)
-        e_a = [rel(acc.cpu().numpy()[..., k], ref_acc[..., k]) for k in range(6)]
-        print(f"cfg2: vis rel {e_v:.2e}, acc rel {max(e_a):.2e}", flush=True)
+        vm, acc = vm.cpu().numpy(), acc.cpu().numpy()
+        e_v = rel(vm, ref_vm)
+        e_a = [rel(acc[..., k], ref_acc[..., k]) for k in range(6)]
+        e_el, e_ant = elem_err(vm, ref_vm), per_antenna_err(acc, ref_acc)
+        print(f"cfg2 {variant}: vis rel {e_v:.2e}, acc rel {max(e_a):.2e}, max element {e_el:.2e}, "
+              f"per antenna {max(e_ant):.2e}", flush=True)
         assert e_v <= 1e-5
         assert max(e_a) <= 1e-4
+        assert e_el <= ELEM_VIS_TOL
+        assert max(e_ant) <= ANT_SUM_TOL
     finally:
         s.close()
 
@@ -293,26 +341,48 @@ def test_cfg2_full_size_parity(torch_dev):
 # subsets of the batched and differentiation workloads
 # ---------------------------------------------------------------------------
 
-def test_cfg3_subset_ragged_intervals(torch_dev):
+@pytest.mark.parametrize("variant", ["vector", "window"])
+def test_cfg3_subset_ragged_intervals(torch_dev, variant):
     """Batched workload (2048^2 grid, uneven intervals): 6 antennas, the first
-    five intervals, all 16 channels; gradient sums and Algorithm 1."""
+    five intervals (45 timesteps, so 45 samples per item on average: the
+    window form's two-wavefront blocks, as on the whole workload), all 16
+    channels.  Prediction, gradient sums, the adjoint, and Algorithm 1 in the
+    plain, batched and graph forms, in the table form and the window form."""
     torch = torch_dev
     from paper_1709_08681_amd import psc
-    print("case: cfg3 subset", flush=True)
+    print(f"case: cfg3 subset, {variant}", flush=True)
     full = synth.make_config(3)
     nt = sum(full.wl.interval_lengths[:5])
     obs = full.subset(ants=range(6), times=range(nt))
     prob = oracle.Problem.from_observation(obs)
     s = session(obs)
     try:
+        if variant == "window":
+            psc.psc_set_degrid(s.handle, psc.DEGRID_WINDOW)
+            info = psc.psc_obs_launch_info(s.handle)
+            assert info["degrid"] == psc.DEGRID_WINDOW
+            assert 16 <= info["samples_per_item"] < 128
+            assert info["window_waves"] == 2, info
         start = synth.perturbed_offsets(obs, 30.0, 15)
         v = oracle.predict(prob, obs.offsets_true)
-        ref = oracle.gradient(prob, start, v, 1.0)
+        vp = s.predict(start).cpu().numpy()
+        vp_ref = oracle.predict(prob, start)
+        assert rel(vp, vp_ref) <= 1e-5 and elem_err(vp, vp_ref) <= ELEM_VIS_TOL
+        ref, ref_vm = oracle.gradient(prob, start, v, 1.0, want_model=True)
         w1 = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
-        acc = s.gradient(s.offsets(start), c64(torch, s, v), w1).cpu().numpy()
+        acc, vm = s.gradient(s.offsets(start), c64(torch, s, v), w1, want_model=True)
+        acc, vm = acc.cpu().numpy(), vm.cpu().numpy()
+        assert rel(vm, ref_vm) <= 1e-5 and elem_err(vm, ref_vm) <= ELEM_VIS_TOL
         live = obs.int_row_ptr[1:] > obs.int_row_ptr[:-1]
         for k in range(6):
             assert rel(acc[live][..., k], ref[live][..., k]) <= 1e-4, k
+        assert max(per_antenna_err(acc, ref)) <= ANT_SUM_TOL
+        # adjoint: sum Re(conj(G) dV/dp) for a seeded cotangent
+        G = np.random.default_rng(16).normal(size=s.vis_shape) + 1j * np.random.default_rng(17).normal(
+            size=s.vis_shape)
+        gv = s.vjp(s.offsets(start), c64(torch, s, G)).cpu().numpy()
+        gv_ref = vjp_reference(obs, prob, start, G, s.off_shape)
+        assert rel(gv[live], gv_ref[live]) <= 1e-4
         ref_off, its_ref = oracle.solve(prob, v, 1.0, start, gain=0.5, n_max=6, tol_rad=1e-3 * ARCSEC)
         outs = []
         for form in (psc.SOLVE_PLAIN, psc.SOLVE_BATCHED, psc.SOLVE_GRAPH):
@@ -323,6 +393,57 @@ def test_cfg3_subset_ragged_intervals(torch_dev):
             outs.append(off.cpu().numpy())
             assert np.abs(outs[-1] - ref_off).max() / ARCSEC <= 0.1
         assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    finally:
+        s.close()
+
+
+def test_cfg3_full_size_tuned_sampled_rows(torch_dev):
+    """The whole batched workload (256 uneven intervals, 93 M visibilities)
+    after the autotuner, in the launch configuration the bench times: the
+    model of every 83rd timestep and the per-antenna sums with the weights
+    zero elsewhere, against the oracle on those rows; then Algorithm 1 in the
+    graph form over all intervals against the oracle's solve of the same
+    rows (iteration counts equal, offsets within 0.1 arcsec)."""
+    torch = torch_dev
+    from paper_1709_08681_amd import psc
+    every = 83
+    print(f"case: cfg3 full size after psc_tune, every {every}th timestep", flush=True)
+    obs = synth.make_config(3)
+    times = np.unique(obs.time_idx)[::every]
+    rows = np.nonzero(np.isin(obs.time_idx, times))[0]
+    sub = obs.subset(times=times)
+    prob = oracle.Problem.from_observation(sub)
+    s = session(obs)
+    try:
+        start = synth.perturbed_offsets(obs, 30.0, 19)
+        v_sub = oracle.predict(prob, obs.offsets_true)
+        vobs = np.zeros(s.vis_shape, np.complex64)
+        vobs[rows] = v_sub
+        w = np.zeros(s.vis_shape, np.float32)
+        w[rows] = 1.0
+        g_vobs, g_w = c64(torch, s, vobs), f32(torch, s, w, s.vis_shape)
+        del vobs, w
+        off = s.offsets(start)
+        psc.psc_tune(s.ctx, s.handle, off, g_vobs, g_w, 1, None)
+        info = psc.psc_obs_launch_info(s.handle)
+        print(f"cfg3 full: tuned degrid {info}", flush=True)
+        vp = s.predict(start)[torch.as_tensor(rows, device=s.dev)].cpu().numpy()
+        vp_ref = oracle.predict(prob, start)
+        acc = s.gradient(off, g_vobs, g_w).cpu().numpy()
+        ref = oracle.gradient(prob, start, v_sub, 1.0)
+        e_v, e_el = rel(vp, vp_ref), elem_err(vp, vp_ref)
+        e_a = [rel(acc[..., k], ref[..., k]) for k in range(6)]
+        e_ant = per_antenna_err(acc, ref)
+        print(f"cfg3 full: vis rel {e_v:.2e}, max element {e_el:.2e}, acc rel {max(e_a):.2e}, "
+              f"per antenna {max(e_ant):.2e} ({len(rows)} of {obs.n_row} rows)", flush=True)
+        assert e_v <= 1e-5 and e_el <= ELEM_VIS_TOL
+        assert max(e_a) <= 1e-4 and max(e_ant) <= ANT_SUM_TOL
+        ref_off, its_ref = oracle.solve(prob, v_sub, 1.0, start, gain=0.5, n_max=3, tol_rad=1e-3 * ARCSEC)
+        its = s.solve(g_vobs, g_w, off, gain=0.5, n_max=3, tol_rad=1e-3 * ARCSEC, form=psc.SOLVE_GRAPH)
+        assert np.array_equal(its.cpu().numpy(), its_ref)
+        d = np.abs(off.cpu().numpy() - ref_off).max() / ARCSEC
+        print(f"cfg3 full: graph solve offsets within {d:.2e} arcsec of the oracle", flush=True)
+        assert d <= 0.1
     finally:
         s.close()
 
@@ -550,11 +671,16 @@ def test_cfg2_full_size_window_form(torch_dev):
         ref_acc, ref_vm = oracle.gradient(prob, start, v_true, 1.0, want_model=True)
         w = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
         acc, vm = s.gradient(s.offsets(start), c64(torch, s, v_true), w, want_model=True)
-        e_v = rel(vm.cpu().numpy(), ref_vm)
-        e_a = [rel(acc.cpu().numpy()[..., k], ref_acc[..., k]) for k in range(6)]
-        print(f"cfg2 window: vis rel {e_v:.2e}, acc rel {max(e_a):.2e}", flush=True)
+        vm, acc = vm.cpu().numpy(), acc.cpu().numpy()
+        e_v = rel(vm, ref_vm)
+        e_a = [rel(acc[..., k], ref_acc[..., k]) for k in range(6)]
+        e_el, e_ant = elem_err(vm, ref_vm), per_antenna_err(acc, ref_acc)
+        print(f"cfg2 window: vis rel {e_v:.2e}, acc rel {max(e_a):.2e}, max element {e_el:.2e}, "
+              f"per antenna {max(e_ant):.2e}", flush=True)
         assert e_v <= 1e-5
         assert max(e_a) <= 1e-4
+        assert e_el <= ELEM_VIS_TOL
+        assert max(e_ant) <= ANT_SUM_TOL
     finally:
         s.close()
 
@@ -598,7 +724,9 @@ def test_cfg2_full_size_extensions_sampled_rows(torch_dev, what):
         vobs[rows] = v_sub
         w = np.zeros(s.vis_shape)
         w[rows] = 1.0
-        e_v = rel(s.predict(start).cpu().numpy()[rows], oracle.predict(prob, start))
+        vp = s.predict(start).cpu().numpy()[rows]
+        vp_ref = oracle.predict(prob, start)
+        e_v, e_el = rel(vp, vp_ref), elem_err(vp, vp_ref)
         if what == "beam_scale":
             acc = s.scale_gradient(s.offsets(start), c64(torch, s, vobs), f32(torch, s, w, s.vis_shape))
             ref = oracle.scale_gradient(prob, start, v_sub, 1.0)
@@ -607,10 +735,13 @@ def test_cfg2_full_size_extensions_sampled_rows(torch_dev, what):
             ref = oracle.gradient(prob, start, v_sub, 1.0)
         acc = acc.cpu().numpy()
         e_a = [rel(acc[..., k], ref[..., k]) for k in range(ref.shape[-1])]
-        print(f"cfg2 {what}: vis rel {e_v:.2e}, acc rel {max(e_a):.2e} ({len(rows)} of {obs.n_row} rows)",
-              flush=True)
+        e_ant = per_antenna_err(acc, ref) if ref.shape[-1] == 6 else [0.0]
+        print(f"cfg2 {what}: vis rel {e_v:.2e}, acc rel {max(e_a):.2e}, max element {e_el:.2e}, "
+              f"per antenna {max(e_ant):.2e} ({len(rows)} of {obs.n_row} rows)", flush=True)
         assert e_v <= 1e-5
         assert max(e_a) <= 1e-4
+        assert e_el <= ELEM_VIS_TOL
+        assert max(e_ant) <= ANT_SUM_TOL
     finally:
         s.close()
 
