@@ -253,6 +253,24 @@ PSC_API psc_status psc_gradient(psc_ctx* ctx, psc_obs* obs, const double* offset
                                 double* acc_out_dev, void* vis_model_dev, void* stream);
 
 /*
+ * psc_gradient for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation, arguments, results and errors as psc_gradient, but
+ * the per-item float64 partial sums go to a fixed scratch array inside the
+ * library instead of the observation's own buffer, and the call makes no
+ * allocation of any kind.  The scratch is 64 MiB per GPU, held from the
+ * library's load until the process ends: observations with n_items * n_pol
+ * * 12 float64 sums beyond it are refused with PSC_E_UNSUPPORTED (about
+ * 699,000 work items per polarisation; n_items from psc_obs_info).  Every
+ * call on one GPU shares that GPU's scratch: calls that overlap on one GPU
+ * (different streams, or threads without ordering) race and give wrong sums.
+ * Every work item rewrites all of its sums, so nothing needs clearing.
+ */
+PSC_API psc_status psc_gradient_noalloc(psc_ctx* ctx, psc_obs* obs, const double* offsets_dev,
+                                        const void* vis_obs_dev, const float* weight_dev,
+                                        double* acc_out_dev, void* vis_model_dev, void* stream);
+
+/*
  * Vector-Jacobian product of psc_predict (async), the adjoint used by
  * automatic differentiation: for every (interval, pol, antenna a)
  *   grad[a] = sum over visibilities touching a of Re(conj(G) dV/dp_a)

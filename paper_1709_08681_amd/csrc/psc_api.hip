@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -179,6 +180,41 @@ int floor_div(long long a, int b)
 
 }  // namespace
 
+// Scratch of the allocation-free gradient (psc_gradient_noalloc): the
+// per-item float64 partial sums, kept in a file-scope device array so that
+// the call allocates nothing.  Every GPU the library runs on holds its own
+// copy until the process ends.  In host code `scratch` names a host-side
+// stand-in, not a device address: host code uses only the per-device address
+// that hipGetSymbolAddress returns (scratch_address).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr size_t kScratchDoubles = kScratchBytes / sizeof(double);
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of the current device's scratch, looked up once per
+// device (the device `dev` must be current).
+hipError_t scratch_address(int dev, double** out)
+{
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
 extern "C" {
 
 PSC_API const char* psc_version(void) { return "psc 0.1 (gfx950)"; }
@@ -238,6 +274,10 @@ static psc_status create_impl(const psc_config* cfg, psc_ctx** out)
     if (c.support == 32 && win_lds_bytes(32, kGrad, m, c.oversample) > win_lds_budget(32))
         return fail(nullptr, PSC_E_UNSUPPORTED, "support 32: the window form exceeds the LDS of one compute unit");
     if (hipSetDevice(c.device) != hipSuccess) return fail(nullptr, PSC_E_ARG, "invalid device");
+
+    double* scratch_dev = nullptr;
+    if (scratch_address(c.device, &scratch_dev) != hipSuccess)
+        return fail(nullptr, PSC_E_HIP, "hipGetSymbolAddress of the allocation-free scratch failed");
 
     psc_ctx* ctx = new psc_ctx();
     ctx->cfg = c;
@@ -815,6 +855,33 @@ PSC_API psc_status psc_gradient(psc_ctx* ctx, psc_obs* obs, const double* offset
     a.vis_out = (float2*)vis_model_dev;
     PSC_HIP(ctx, launch_degrid(kGrad, ctx, obs, a, s));
     PSC_HIP(ctx, launch_reduce(12, reduce_args(obs, 0, obs->n_int, acc_out_dev, nullptr), s));
+    return PSC_OK;
+}
+
+PSC_API psc_status psc_gradient_noalloc(psc_ctx* ctx, psc_obs* obs, const double* offsets_dev,
+                                        const void* vis_obs_dev, const float* weight_dev, double* acc_out_dev,
+                                        void* vis_model_dev, void* stream)
+{
+    psc_status st = check_call(ctx, obs, offsets_dev);
+    if (st != PSC_OK) return st;
+    if (!acc_out_dev || ((!vis_obs_dev || !weight_dev) && obs->n_vis > 0))
+        return fail(ctx, PSC_E_ARG, "null data or output");
+    if ((size_t)obs->n_items * (size_t)obs->n_pol * 12 > kScratchDoubles)
+        return fail(ctx, PSC_E_UNSUPPORTED,
+                    "psc_gradient_noalloc: the observation's partial sums (12 float64 per work item and "
+                    "polarisation) exceed its 64 MiB scratch; use psc_gradient");
+    double* part = nullptr;
+    PSC_HIP(ctx, scratch_address(ctx->cfg.device, &part));
+    hipStream_t s = (hipStream_t)stream;
+    ItemArgs a = item_args(ctx, obs, offsets_dev, 0, (int)obs->n_items, nullptr);
+    a.vis_in = (const float2*)vis_obs_dev;
+    a.weight = weight_dev;
+    a.vis_out = (float2*)vis_model_dev;
+    a.partials = part;  // every item writes all of its sums: nothing to clear
+    PSC_HIP(ctx, launch_degrid(kGrad, ctx, obs, a, s));
+    ReduceArgs r = reduce_args(obs, 0, obs->n_int, acc_out_dev, nullptr);
+    r.partials = part;
+    PSC_HIP(ctx, launch_reduce(12, r, s));
     return PSC_OK;
 }
 

@@ -27,8 +27,8 @@ DEGRID_VALU, DEGRID_MFMA, DEGRID_WINDOW = 0, 1, 2
 ARCSEC = math.pi / (180.0 * 3600.0)
 
 EXPORTS = ["psc_version", "psc_create", "psc_destroy", "psc_last_error", "psc_set_model",
-           "psc_obs_create", "psc_obs_destroy", "psc_obs_info", "psc_obs_launch_info", "psc_predict", "psc_gradient",
-           "psc_predict_vjp", "psc_solve_step", "psc_solve", "psc_set_degrid", "psc_get_degrid",
+           "psc_obs_create", "psc_obs_destroy", "psc_obs_info", "psc_obs_launch_info", "psc_predict",
+           "psc_gradient", "psc_gradient_noalloc", "psc_predict_vjp", "psc_solve_step", "psc_solve", "psc_set_degrid", "psc_get_degrid",
            "psc_tune", "psc_image_gradient", "psc_set_beam_scale", "psc_get_beam_scale",
            "psc_scale_gradient", "psc_scale_step", "psc_solve_scale"]
 
@@ -90,6 +90,7 @@ def load():
             "psc_obs_launch_info": ([vp, C.POINTER(LaunchInfo)], C.c_int),
             "psc_predict": ([vp, vp, vp, vp, vp], C.c_int),
             "psc_gradient": ([vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
+            "psc_gradient_noalloc": ([vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
             "psc_predict_vjp": ([vp, vp, vp, vp, vp, vp], C.c_int),
             "psc_solve_step": ([vp, i32, i32, i32, vp, dbl, dbl, vp, vp, vp, vp], C.c_int),
             "psc_solve": ([vp, vp, vp, vp, vp, dbl, i32, dbl, i32, vp, vp], C.c_int),
@@ -182,6 +183,12 @@ def psc_gradient(ctx, obs, offsets_dev, vis_obs_dev, weight_dev, acc_out_dev, vi
                  stream=None):
     _check(load().psc_gradient(ctx, obs, _ptr(offsets_dev), _ptr(vis_obs_dev), _ptr(weight_dev),
                                _ptr(acc_out_dev), _ptr(vis_model_dev), _stream(stream)), ctx)
+
+
+def psc_gradient_noalloc(ctx, obs, offsets_dev, vis_obs_dev, weight_dev, acc_out_dev, vis_model_dev=None,
+                         stream=None):
+    _check(load().psc_gradient_noalloc(ctx, obs, _ptr(offsets_dev), _ptr(vis_obs_dev), _ptr(weight_dev),
+                                       _ptr(acc_out_dev), _ptr(vis_model_dev), _stream(stream)), ctx)
 
 
 def psc_predict_vjp(ctx, obs, offsets_dev, grad_vis_dev, grad_offsets_dev, stream=None):
