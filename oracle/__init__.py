@@ -90,9 +90,15 @@ def _load():
             lib.oracle_solve_step.argtypes = [C.c_int, C.c_int, C.c_int, dp, C.c_double, C.c_double, dp, ip,
                                               dp, ip]
             lib.oracle_solve.argtypes = [P, dp, dp, dp, C.c_double, C.c_int, C.c_double, ip]
+            lib.oracle_efp_defocus.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
+                                               C.c_double, C.c_double, dp]
+            lib.oracle_predict_defocus.argtypes = [P, dp, dp, dp, dp]
+            lib.oracle_defocus_gradient.argtypes = [P, dp, dp, dp, dp, dp]
+            lib.oracle_defocus_step.argtypes = [C.c_int, C.c_int, C.c_int, dp, C.c_double, dp, ip, dp]
             for name in ("oracle_predict", "oracle_predict_scale", "oracle_scale_gradient", "oracle_scale_step",
                          "oracle_gradient", "oracle_image_gradient",
-                         "oracle_solve_step", "oracle_solve",
+                         "oracle_solve_step", "oracle_solve", "oracle_predict_defocus",
+                         "oracle_defocus_gradient", "oracle_defocus_step",
                          "oracle_num_threads"):
                 getattr(lib, name).restype = C.c_int
             _lib = lib
@@ -342,6 +348,58 @@ def solve(prob: Problem, vis_obs, weight, offsets0, gain=0.5, n_max=10, tol_rad=
     _check(lib.oracle_solve(prob.ref, _dp(vo2), _dp(w), _dp(o), float(gain), int(n_max),
                             float(tol_rad), _ip(its)), "solve")
     return o, its
+
+
+def efp_defocus(illum, dish_diam_m, gauss_sigma_ld, freq_hz, delta, dl, dm):
+    """(E, dE/ddelta) of the pattern with an aperture defocus delta (radians
+    at the rim), complex, at displacement (dl, dm) from the beam centre."""
+    out = np.zeros(4)
+    _load().oracle_efp_defocus(int(illum), float(dish_diam_m), float(gauss_sigma_ld), float(freq_hz),
+                               float(delta), float(dl), float(dm), _dp(out))
+    return out[0] + 1j * out[1], out[2] + 1j * out[3]
+
+
+def _defocus(prob, defocus):
+    return np.ascontiguousarray(np.broadcast_to(defocus, prob.offsets_shape()[:3]), np.float64)
+
+
+def predict_defocus(prob: Problem, offsets, defocus):
+    """Model visibilities with every antenna's defocus [n_int, n_pol, n_ant]
+    and their derivatives [n_row, n_chan, n_pol, 2] (d/ddelta_i, d/ddelta_j)."""
+    lib = _load()
+    o = _offs(prob, offsets)
+    d = _defocus(prob, defocus)
+    vis = np.zeros(prob.vis_shape() + (2,))
+    dd = np.zeros(prob.vis_shape() + (2, 2))
+    _check(lib.oracle_predict_defocus(prob.ref, _dp(o), _dp(d), _dp(vis), _dp(dd)), "predict_defocus")
+    return vis[..., 0] + 1j * vis[..., 1], dd[..., 0] + 1j * dd[..., 1]
+
+
+def defocus_gradient(prob: Problem, offsets, defocus, vis_obs, weight):
+    """Per-antenna sums [n_int, n_pol, n_ant, 3] = chi, g_delta, H_delta."""
+    lib = _load()
+    o = _offs(prob, offsets)
+    d = _defocus(prob, defocus)
+    vo = np.ascontiguousarray(np.broadcast_to(vis_obs, prob.vis_shape()), np.complex128)
+    vo2 = np.ascontiguousarray(vo.view(np.float64))
+    w = np.ascontiguousarray(np.broadcast_to(weight, prob.vis_shape()), np.float64)
+    acc = np.zeros(prob.offsets_shape()[:3] + (3,))
+    _check(lib.oracle_defocus_gradient(prob.ref, _dp(o), _dp(d), _dp(vo2), _dp(w), _dp(acc)),
+           "defocus_gradient")
+    return acc
+
+
+def defocus_step(acc3, gain, defocus):
+    """Returns (new defocus, not_updated, max_step [n_int])."""
+    lib = _load()
+    acc3 = np.ascontiguousarray(acc3, np.float64)
+    n_int, n_pol, n_ant = acc3.shape[:3]
+    d = np.array(defocus, dtype=np.float64, copy=True, order="C")
+    nu = np.zeros((n_int, n_pol, n_ant), np.int32)
+    mx = np.zeros(n_int)
+    _check(lib.oracle_defocus_step(n_int, n_pol, n_ant, _dp(acc3), float(gain), _dp(d), _ip(nu), _dp(mx)),
+           "defocus_step")
+    return d, nu, mx
 
 
 def num_threads():

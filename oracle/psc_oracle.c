@@ -816,3 +816,257 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/* Aperture phase term: defocus, a complex generalised antenna parameter.   */
+/* ------------------------------------------------------------------------ */
+/*
+ * Eq. DA holds for any antenna parameter a_i, complex patterns included, and
+ * Sec. 5.3 names phase terms of the aperture illumination (defocus,
+ * astigmatism) as the first shape parameters to solve for with the same
+ * machinery.  A defocus delta (radians of aperture phase at the rim)
+ * multiplies the illumination by exp(i delta (r/R)^2), R = D/2, and the
+ * far-field pattern becomes complex:
+ *   uniform disc:  E(rho; delta) = 2 int_0^1 J0(k rho t) exp(i delta t^2) t dt,
+ *                  k = pi D / lambda, so that E = 2 J1(x)/x, x = k rho, at
+ *                  delta = 0 (a Hankel transform of order zero);
+ *   Gaussian mode: the illumination exp(-2 pi^2 s^2 |x|^2 / lambda^2) of the
+ *                  pattern exp(-rho^2/(2 s^2)), s = gauss_sigma_ld lambda/D,
+ *                  times the phase, transforms in closed form:
+ *                  E = z exp(-z rho^2 / (2 s^2)), z = 1 / (1 - i kappa),
+ *                  kappa = 2 delta / (pi^2 gauss_sigma_ld^2)
+ *                  (frequency-independent, since s and R both scale with D).
+ * The visibility carries the first antenna's pattern and the conjugate of the
+ * second's (Eq. ME: E_i E_j^*), which real patterns do not show:
+ *   V_ij = sum_p I_p E_i(l_p - p_i) conj(E_j(l_p - p_j)) exp(+2 pi i u.l_p).
+ * dV/ddelta_i takes dE_i/ddelta in place of E_i; dV/ddelta_j takes
+ * conj(dE_j/ddelta) in place of conj(E_j).
+ */
+
+/* Gauss-Legendre nodes and weights on [0, 1]: Newton's method on P_n from
+ * the Chebyshev-like first guesses cos(pi (i + 3/4) / (n + 1/2)). */
+#define ORC_NGL 128
+static double g_gl_t[ORC_NGL], g_gl_w[ORC_NGL];
+static int g_gl_ready = 0;
+static void gl_nodes(void)
+{
+    if (g_gl_ready) return;
+    const int n = ORC_NGL;
+    for (int i = 0; i < n; ++i) {
+        double x = cos(ORC_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = x;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (x * p1 - p0) / (x * x - 1.0);
+            double dx = p1 / dp;
+            x -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        g_gl_t[i] = 0.5 * (1.0 - x);
+        g_gl_w[i] = 1.0 / ((1.0 - x * x) * dp * dp);  /* 2/((1-x^2) P'^2), halved for [0, 1] */
+    }
+    g_gl_ready = 1;
+}
+
+/* Pattern with defocus delta at displacement (dl, dm) from the beam centre:
+ * out4 = (Re E, Im E, Re dE/ddelta, Im dE/ddelta). */
+static void efp_defocus(int illum, double dish, double sigma_ld, double lambda, double delta, double dl,
+                        double dm, double* out4)
+{
+    double rho2 = dl * dl + dm * dm;
+    if (illum == 1) {
+        double s = sigma_ld * lambda / dish;
+        double kap = 2.0 * delta / (ORC_PI * ORC_PI * sigma_ld * sigma_ld);
+        /* z = 1/(1 - i kappa) = (1 + i kappa)/(1 + kappa^2) */
+        double den = 1.0 + kap * kap, zr = 1.0 / den, zi = kap / den;
+        double a = rho2 / (2.0 * s * s);
+        /* E = z exp(-a z) */
+        double mag = exp(-a * zr), ph = -a * zi;
+        double er = mag * cos(ph), ei = mag * sin(ph);
+        double Er = zr * er - zi * ei, Ei = zr * ei + zi * er;
+        /* dE/dkappa = i z E (1 - a z) */
+        double tr = 1.0 - a * zr, ti = -a * zi;           /* 1 - a z */
+        double ur = zr * Er - zi * Ei, ui = zr * Ei + zi * Er; /* z E */
+        double vr = ur * tr - ui * ti, vi = ur * ti + ui * tr; /* z E (1 - a z) */
+        double dk = 2.0 / (ORC_PI * ORC_PI * sigma_ld * sigma_ld);
+        out4[0] = Er;
+        out4[1] = Ei;
+        out4[2] = -vi * dk; /* i (vr + i vi) = -vi + i vr */
+        out4[3] = vr * dk;
+        return;
+    }
+    gl_nodes();
+    double x = ORC_PI * dish / lambda * sqrt(rho2);
+    double er = 0.0, ei = 0.0, dr = 0.0, di = 0.0;
+    for (int q = 0; q < ORC_NGL; ++q) {
+        double t = g_gl_t[q], w = 2.0 * g_gl_w[q] * t * j0(x * t);
+        double c = cos(delta * t * t), sn = sin(delta * t * t);
+        er += w * c;
+        ei += w * sn;
+        /* d/ddelta of exp(i delta t^2) = i t^2 exp(i delta t^2) */
+        dr -= w * t * t * sn;
+        di += w * t * t * c;
+    }
+    out4[0] = er;
+    out4[1] = ei;
+    out4[2] = dr;
+    out4[3] = di;
+}
+
+void oracle_efp_defocus(int illum, double dish_diam_m, double gauss_sigma_ld, double freq_hz, double delta,
+                        double dl, double dm, double* out4)
+{
+    efp_defocus(illum, dish_diam_m, gauss_sigma_ld, ORC_C_LIGHT / freq_hz, delta, dl, dm, out4);
+}
+
+static int check_defocus(const orc_problem* p, const double* defocus)
+{
+    gl_nodes(); /* before any parallel region reads them */
+    if (check_problem(p) || p->illum == 2 || p->par_angle || p->beam_scale || !defocus) return -1;
+    for (size_t k = 0; k < (size_t)p->n_int * p->n_pol * p->n_ant; ++k)
+        if (!isfinite(defocus[k])) return -1;
+    return 0;
+}
+
+/* V [n_vis][re, im] and, when ddef_out is not NULL, dV/ddelta_i and
+ * dV/ddelta_j [n_vis][2][re, im] with every antenna's defocus
+ * [n_int][n_pol][n_ant] (sky-frame offsets). */
+int oracle_predict_defocus(const orc_problem* p, const double* offsets, const double* defocus, double* vis_out,
+                           double* ddef_out)
+{
+    if (check_defocus(p, defocus)) return -1;
+    for (int s = 0; s < p->n_int; ++s) {
+        int64_t r0 = p->int_row_ptr[s], r1 = p->int_row_ptr[s + 1];
+        if (r0 == r1) continue;
+        const double* offs_int = offsets + (size_t)s * p->n_pol * p->n_ant * 2;
+        const double* def_int = defocus + (size_t)s * p->n_pol * p->n_ant;
+        /* beams: tab[((pol * n_ant + a) * n_chan + c) * n_src + src][4] */
+        size_t nt = (size_t)p->n_pol * p->n_ant * p->n_chan * p->n_src;
+        double* tab = (double*)malloc((nt ? nt : 1) * 4 * sizeof(double));
+        if (!tab) return -2;
+        for (int pol = 0; pol < p->n_pol; ++pol) {
+#pragma omp parallel for schedule(dynamic, 1)
+            for (int a = 0; a < p->n_ant; ++a) {
+                for (int c = 0; c < p->n_chan; ++c) {
+                    double lambda = ORC_C_LIGHT / p->freq_hz[c];
+                    double sq = (pol == 0 ? 1.0 : -1.0) * p->squint_frac * hpbw_rad(lambda, p->dish_diam_m);
+                    double pl = offs_int[(pol * p->n_ant + a) * 2 + 0] + sq;
+                    double pm = offs_int[(pol * p->n_ant + a) * 2 + 1];
+                    for (int k = 0; k < p->n_src; ++k)
+                        efp_defocus(p->illum, p->dish_diam_m, p->gauss_sigma_ld, lambda,
+                                    def_int[pol * p->n_ant + a], p->src_l[k] - pl, p->src_m[k] - pm,
+                                    tab + 4 * ((((size_t)pol * p->n_ant + a) * p->n_chan + c) * p->n_src + k));
+                }
+            }
+        }
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t r = r0; r < r1; ++r) {
+            for (int c = 0; c < p->n_chan; ++c) {
+                double u, v;
+                row_uv(p, r, c, &u, &v);
+                double w = row_w(p, r, c);
+                for (int pol = 0; pol < p->n_pol; ++pol) {
+                    const double* ti = tab + 4 * ((((size_t)pol * p->n_ant + p->ant1[r]) * p->n_chan + c) * p->n_src);
+                    const double* tj = tab + 4 * ((((size_t)pol * p->n_ant + p->ant2[r]) * p->n_chan + c) * p->n_src);
+                    double acc[6] = {0};
+                    for (int k = 0; k < p->n_src; ++k) {
+                        double ph = me_phase(u, v, w, p->src_l[k], p->src_m[k]);
+                        double fr = p->src_flux[k] * cos(ph), fi = p->src_flux[k] * sin(ph);
+                        const double* a = ti + 4 * k;
+                        const double* b = tj + 4 * k;
+                        /* E_i conj(E_j), dE_i conj(E_j), E_i conj(dE_j) */
+                        double pr[3], pi_[3];
+                        pr[0] = a[0] * b[0] + a[1] * b[1];
+                        pi_[0] = a[1] * b[0] - a[0] * b[1];
+                        pr[1] = a[2] * b[0] + a[3] * b[1];
+                        pi_[1] = a[3] * b[0] - a[2] * b[1];
+                        pr[2] = a[0] * b[2] + a[1] * b[3];
+                        pi_[2] = a[1] * b[2] - a[0] * b[3];
+                        for (int q = 0; q < 3; ++q) {
+                            acc[2 * q] += fr * pr[q] - fi * pi_[q];
+                            acc[2 * q + 1] += fr * pi_[q] + fi * pr[q];
+                        }
+                    }
+                    size_t idx = ((size_t)r * p->n_chan + c) * p->n_pol + pol;
+                    vis_out[2 * idx] = acc[0];
+                    vis_out[2 * idx + 1] = acc[1];
+                    if (ddef_out) memcpy(ddef_out + 4 * idx, acc + 2, 4 * sizeof(double));
+                }
+            }
+        }
+        free(tab);
+    }
+    return 0;
+}
+
+/* The sums of Eq. DCHIDD for the defocus: per (interval, pol, antenna)
+ * acc3 = (chi, g = sum Re(conj(R) w dV/ddelta_a), H = sum w |dV/ddelta_a|^2)
+ * over both ends of every baseline. */
+int oracle_defocus_gradient(const orc_problem* p, const double* offsets, const double* defocus,
+                            const double* vis_obs, const double* weight, double* acc3)
+{
+    if (check_defocus(p, defocus)) return -1;
+    size_t n_vis = (size_t)p->n_row * p->n_chan * p->n_pol;
+    double* vm = (double*)malloc((n_vis ? n_vis : 1) * 2 * sizeof(double));
+    double* dd = (double*)malloc((n_vis ? n_vis : 1) * 4 * sizeof(double));
+    if (!vm || !dd) {
+        free(vm);
+        free(dd);
+        return -2;
+    }
+    int rc = oracle_predict_defocus(p, offsets, defocus, vm, dd);
+    memset(acc3, 0, (size_t)p->n_int * p->n_pol * p->n_ant * 3 * sizeof(double));
+    for (int s = 0; s < p->n_int && rc == 0; ++s) {
+        for (int64_t r = p->int_row_ptr[s]; r < p->int_row_ptr[s + 1]; ++r) {
+            for (int c = 0; c < p->n_chan; ++c) {
+                for (int pol = 0; pol < p->n_pol; ++pol) {
+                    size_t idx = ((size_t)r * p->n_chan + c) * p->n_pol + pol;
+                    double w = weight[idx];
+                    double rr = vis_obs[2 * idx] - vm[2 * idx];
+                    double ri = vis_obs[2 * idx + 1] - vm[2 * idx + 1];
+                    for (int end = 0; end < 2; ++end) {
+                        int a = end ? p->ant2[r] : p->ant1[r];
+                        const double* d = dd + 4 * idx + 2 * end;
+                        double* t = acc3 + (((size_t)s * p->n_pol + pol) * p->n_ant + a) * 3;
+                        t[0] += w * (rr * rr + ri * ri);
+                        t[1] += w * (rr * d[0] + ri * d[1]);
+                        t[2] += w * (d[0] * d[0] + d[1] * d[1]);
+                    }
+                }
+            }
+        }
+    }
+    free(vm);
+    free(dd);
+    return rc;
+}
+
+/* Damped Gauss-Newton step of the defocus per (interval, pol, antenna):
+ * delta += gamma g / H; an antenna with H <= 0 or non-finite sums is left
+ * as is and marked in not_updated (nullable); max_step_out[s] (nullable) is
+ * the largest |delta step| of interval s. */
+int oracle_defocus_step(int n_int, int n_pol, int n_ant, const double* acc3, double gain, double* defocus_io,
+                        int32_t* not_updated, double* max_step_out)
+{
+    if (n_int < 0 || n_pol < 1 || n_ant < 1 || !(gain > 0.0)) return -1;
+    for (int s = 0; s < n_int; ++s) {
+        double mx = 0.0;
+        for (int k = 0; k < n_pol * n_ant; ++k) {
+            size_t i = (size_t)s * n_pol * n_ant + k;
+            double g = acc3[3 * i + 1], h = acc3[3 * i + 2];
+            double step = gain * g / h;
+            int ok = h > 0.0 && isfinite(g) && isfinite(h) && isfinite(step);
+            if (ok) {
+                mx = fmax(mx, fabs(step));
+                defocus_io[i] += step;
+            }
+            if (not_updated) not_updated[i] = !ok;
+        }
+        if (max_step_out) max_step_out[s] = mx;
+    }
+    return 0;
+}

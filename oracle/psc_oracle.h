@@ -61,6 +61,18 @@ int oracle_solve_step(int n_int, int n_pol, int n_ant, const double* acc, double
                       const int32_t* done);
 int oracle_solve(const orc_problem* p, const double* vis_obs, const double* weight,
                  double* offsets_io, double gain, int n_max, double tol_rad, int32_t* iters_out);
+/* Aperture phase term (defocus delta per [n_int][n_pol][n_ant], radians of
+ * phase at the dish rim): complex patterns; illum 0 or 1, sky-frame
+ * offsets, no beam scales.  out4 = (Re E, Im E, Re dE/ddelta, Im dE/ddelta);
+ * ddef_out [n_vis][2][re, im] = dV/ddelta_i, dV/ddelta_j; acc3 = (chi, g, H). */
+void oracle_efp_defocus(int illum, double dish_diam_m, double gauss_sigma_ld, double freq_hz, double delta,
+                        double dl, double dm, double* out4);
+int oracle_predict_defocus(const orc_problem* p, const double* offsets, const double* defocus, double* vis_out,
+                           double* ddef_out);
+int oracle_defocus_gradient(const orc_problem* p, const double* offsets, const double* defocus,
+                            const double* vis_obs, const double* weight, double* acc3);
+int oracle_defocus_step(int n_int, int n_pol, int n_ant, const double* acc3, double gain, double* defocus_io,
+                        int32_t* not_updated, double* max_step_out);
 int oracle_num_threads(void);
 
 #endif
