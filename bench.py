@@ -141,7 +141,8 @@ class Workload:
         s.solve(self.v_obs, self.w, self.off, gain=0.5, n_max=iters, tol_rad=0.0, form=form)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        return dt * 1e3 / iters, self.off.clone(), first_ms
+        # the first call's excess over a timed call: graph capture and instantiation
+        return dt * 1e3 / iters, self.off.clone(), first_ms - dt * 1e3
 
     def eager_steps(self, steps, warmup):
         """The same iteration written out with the C-ABI calls on the bench's
@@ -186,7 +187,7 @@ def forms_report(wl, iters, warmup, forms=("graph", "batched", "plain")):
         res[name] = {"vis_per_s": wl.obs.n_vis / (ms * 1e-3), "ms_per_iteration": ms}
         if name == "graph":
             # the first call captured and instantiated the graph, then ran it
-            res[name]["capture_and_instantiate_ms"] = first - ms * iters
+            res[name]["capture_and_instantiate_ms"] = first
     ref = offs[forms[0]]
     res["bit_identical_offsets"] = bool(all(wl.torch.equal(ref, o) for o in offs.values()))
     if "plain" in res and "graph" in res:
@@ -283,9 +284,12 @@ def extension_timing(cfg, reps, what):
                          products stored per item, five plain sums);
       beam_scale         psc_scale_gradient: the sums for a beam-width scale
                          per antenna (scales set within 3% of nominal);
-      w_term             the array's arms shrunk to 1 km (the w-term's
-                         support limit), window form with e^{2 pi i w (n-1)}
-                         per image sample."""
+      w_term             the array's arms shrunk to 1 km (one kernel holds
+                         the w-term), window form with e^{2 pi i w (n-1)}
+                         per image sample;
+      w_stack            the array as configured (arms to 21 km) with its w:
+                         w-stacked model grids, each sample's residual w in
+                         its kernel."""
     import torch
     from paper_1709_08681_amd import psc as P
     from paper_1709_08681_amd import synth
@@ -295,7 +299,8 @@ def extension_timing(cfg, reps, what):
           "measured_aperture": dict(mount_frame=True, aperture=synth.measured_aperture()),
           "measured_aperture_sky": dict(aperture=synth.measured_aperture()),
           "beam_scale": dict(mount_frame=True),
-          "w_term": dict(w_term=True)}[what]
+          "w_term": dict(w_term=True),
+          "w_stack": dict(w_term=True)}[what]
     s = P.Session(obs, device=0, **kw)
     try:
         stream = torch.cuda.current_stream()
@@ -307,7 +312,7 @@ def extension_timing(cfg, reps, what):
             acc = torch.empty(s.off_shape[:3] + (3,), dtype=torch.float64, device=s.dev)
             call = lambda: P.psc_scale_gradient(s.ctx, s.handle, off, v, w, acc, stream)
         else:
-            if what == "w_term":
+            if what in ("w_term", "w_stack"):
                 P.psc_set_degrid(s.handle, P.DEGRID_WINDOW)
             acc = torch.empty(s.off_shape[:3] + (6,), dtype=torch.float64, device=s.dev)
             call = lambda: P.psc_gradient(s.ctx, s.handle, off, v, w, acc, None, stream)
@@ -320,8 +325,11 @@ def extension_timing(cfg, reps, what):
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        return {"workload": describe(obs), "ms_per_gradient": ms, "vis_per_s": obs.n_vis / (ms * 1e-3),
-                "calls": reps}
+        out = {"workload": describe(obs), "ms_per_gradient": ms, "vis_per_s": obs.n_vis / (ms * 1e-3),
+               "calls": reps}
+        if what == "w_stack":
+            out["w_planes"] = P.psc_obs_launch_info(s.handle)["w_planes"]
+        return out
     finally:
         s.close()
 
@@ -429,6 +437,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=3, help="headline workload (3: batched)")
+    ap.add_argument("--channels", type=int, default=0,
+                    help="keep the headline workload's first N channels (one GPU's channel share)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
@@ -444,15 +454,16 @@ def main():
         sys.exit(2)
 
     print(f"bench: headline workload {args.config}", file=sys.stderr, flush=True)
-    wl = Workload(args.config)
+    wl = Workload(args.config, channels=args.channels, tune=True)
     obs = wl.obs
     rep = forms_report(wl, args.steps, args.warmup)
     ms_step = rep["graph"]["ms_per_iteration"]
     print("bench: eager steps with per-launch events", file=sys.stderr, flush=True)
     eager_ms, kern_ms = wl.eager_steps(args.steps, args.warmup)
-    which = "window" if wl.info["degrid"] == wl.P.DEGRID_WINDOW else "table"
-    traffic = measured_traffic(which) if args.config in (3, 2) and \
-        PROFILES[which][0].endswith({3: "batched.md", 2: "single_interval.md"}[args.config]) else None
+    # the committed counters of this workload's kernel, when they are for it
+    which = {(3, wl.P.DEGRID_WINDOW): "window", (2, wl.P.DEGRID_VALU): "table",
+             (5, wl.P.DEGRID_WINDOW): "window_large"}.get((args.config, wl.info["degrid"]))
+    traffic = measured_traffic(which) if which and (args.config != 5 or args.channels == 32) else None
     out = {
         "metric": "predict+gradient visibilities/s",
         "value": obs.n_vis / (ms_step * 1e-3),
@@ -506,7 +517,8 @@ def main():
         print(f"bench: large workload, {args.large_channels}-channel share", file=sys.stderr, flush=True)
         out["large_share"] = large_share_extra(args.large_channels, args.large_iters)
         out["extensions"] = {}
-        for what in ("mount_frame", "measured_aperture", "measured_aperture_sky", "beam_scale", "w_term"):
+        for what in ("mount_frame", "measured_aperture", "measured_aperture_sky", "beam_scale", "w_term",
+                     "w_stack"):
             print(f"bench: {what}", file=sys.stderr, flush=True)
             out["extensions"][what] = extension_timing(2, 3, what)
     if not args.no_cpu_baseline:

@@ -213,6 +213,8 @@ PSC_API psc_status psc_obs_info(const psc_obs* obs, int64_t* n_items, int64_t* n
  *                     channel): what the block shape is chosen from
  *   plan_ms           host wall time psc_obs_create took (planning, uploads
  *                     and setup kernels)
+ *   w_planes          model grids of a w-stacked observation (0 when the
+ *                     w-term, if any, fits one kernel)
  * PSC_E_ARG for a null observation or output.
  */
 typedef struct {
@@ -220,6 +222,8 @@ typedef struct {
     int32_t window_waves;
     double samples_per_item;
     double plan_ms;
+    int32_t w_planes;
+    int32_t reserved;
 } psc_launch_info;
 PSC_API psc_status psc_obs_launch_info(const psc_obs* obs, psc_launch_info* out);
 

@@ -9,6 +9,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/psc.h"
@@ -31,6 +32,8 @@ struct psc_ctx {
     // measured aperture (illum 2): its non-zero cells (xi, eta, weight), xi
     // and eta in units of D, weights summing to one
     std::vector<double> ap_cells;
+    double* image = nullptr;            // the model image [N][N] float64, kept for w-planes
+    std::vector<psc_obs*> stacked;      // observations with w-planes, rebuilt with the model
     bool model_set = false;
     std::string err;
 };
@@ -44,6 +47,13 @@ struct psc_obs {
     Item* items = nullptr;
     Group* groups = nullptr;
     VisEnt* vis = nullptr;
+    VisEnt* wvis = nullptr;    // the same samples, per item in row order (window form)
+    uint8_t* wf = nullptr;     // their offsets (fl << 4) | fm
+    // w-stacking: the model grid for w_k = k w_dw wavelengths, k = w_k0 ..
+    // w_k0 + w_nk - 1, [w_nk][(N+S)^2] complex64 (w_nk = 0: none)
+    float2* wplanes = nullptr;
+    int32_t w_k0 = 0, w_nk = 0;
+    double w_dw = 0;
     uint32_t* ant_ptr = nullptr;
     uint32_t* ant_ent = nullptr;
     double* freq = nullptr;
@@ -170,6 +180,9 @@ bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 // spread of the w phase over a beam width, in uv cells (measured against the
 // direct sum: relative error below 1e-5 up to about 1.8 at both supports).
 constexpr double kMaxWCells = 1.5;
+// w-stacking: the residual w - w_k a sample's kernel carries widens it by at
+// most this many cells.
+constexpr double kWStackCells = 1.0;
 
 int floor_div(long long a, int b)
 {
@@ -334,6 +347,7 @@ PSC_API psc_status psc_destroy(psc_ctx* ctx)
     if (!ctx) return PSC_OK;
     (void)hipSetDevice(ctx->cfg.device);
     dfree(ctx->grid);
+    dfree(ctx->image);
     dfree(ctx->taper_pix);
     dfree(ctx->taper_img);
     dfree(ctx->tw);
@@ -344,6 +358,40 @@ PSC_API psc_status psc_destroy(psc_ctx* ctx)
     return PSC_OK;
 }
 
+// V^{M0} = F[I/c] (w = 0: the model grid) or, for a w-plane, F[I e^{2 pi i
+// w (n-1)} / c], float64 FFT, stored padded as complex64 (N+S)^2 at `out`.
+static hipError_t model_transform(psc_ctx* ctx, const double* image, bool wplane, double w, float2* out,
+                                  double2* a, double2* b, hipStream_t st)
+{
+    const int n = ctx->n;
+    int log2n = 0;
+    while ((1 << log2n) < n) ++log2n;
+    hipError_t e = wplane ? launch_wplane_image(image, ctx->taper_pix, a, n, ctx->cfg.cell_rad, w, st)
+                          : launch_taper_image(image, ctx->taper_pix, a, n, st);
+    if (e == hipSuccess) e = launch_fft_rows(a, n, log2n, st);
+    if (e == hipSuccess) e = launch_transpose(a, b, n, st);
+    if (e == hipSuccess) e = launch_fft_rows(b, n, log2n, st);
+    if (e == hipSuccess) e = launch_transpose(b, a, n, st);
+    if (e == hipSuccess) e = launch_finish_grid(a, out, n, ctx->s, st);
+    return e;
+}
+
+// The w-planes of one observation from the kept model image.
+static hipError_t build_wplanes(psc_ctx* ctx, psc_obs* obs, hipStream_t st)
+{
+    const size_t n2 = (size_t)ctx->n * ctx->n, p2 = (size_t)(ctx->n + ctx->s) * (ctx->n + ctx->s);
+    double2 *a = nullptr, *b = nullptr;
+    hipError_t e = dmalloc(&a, n2);
+    if (e == hipSuccess) e = dmalloc(&b, n2);
+    for (int k = 0; k < obs->w_nk && e == hipSuccess; ++k)
+        e = model_transform(ctx, ctx->image, true, (double)(obs->w_k0 + k) * obs->w_dw, obs->wplanes + k * p2, a,
+                            b, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    dfree(a);
+    dfree(b);
+    return e;
+}
+
 PSC_API psc_status psc_set_model(psc_ctx* ctx, const double* image_dev, void* stream)
 {
     if (!ctx) return fail(nullptr, PSC_E_ARG, "null context");
@@ -351,21 +399,19 @@ PSC_API psc_status psc_set_model(psc_ctx* ctx, const double* image_dev, void* st
     ctx->err.clear();
     PSC_HIP(ctx, hipSetDevice(ctx->cfg.device));
     hipStream_t st = (hipStream_t)stream;
-    const int n = ctx->n;
-    int log2n = 0;
-    while ((1 << log2n) < n) ++log2n;
+    const size_t n2 = (size_t)ctx->n * ctx->n;
     double2 *a = nullptr, *b = nullptr;
-    hipError_t e = dmalloc(&a, (size_t)n * n);
-    if (e == hipSuccess) e = dmalloc(&b, (size_t)n * n);
-    if (e == hipSuccess) e = launch_taper_image(image_dev, ctx->taper_pix, a, n, st);
-    if (e == hipSuccess) e = launch_fft_rows(a, n, log2n, st);
-    if (e == hipSuccess) e = launch_transpose(a, b, n, st);
-    if (e == hipSuccess) e = launch_fft_rows(b, n, log2n, st);
-    if (e == hipSuccess) e = launch_transpose(b, a, n, st);
-    if (e == hipSuccess) e = launch_finish_grid(a, ctx->grid, n, ctx->s, st);
+    hipError_t e = ctx->image ? hipSuccess : dmalloc(&ctx->image, n2);
+    if (e == hipSuccess) e = hipMemcpyAsync(ctx->image, image_dev, sizeof(double) * n2, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = dmalloc(&a, n2);
+    if (e == hipSuccess) e = dmalloc(&b, n2);
+    if (e == hipSuccess) e = model_transform(ctx, ctx->image, false, 0.0, ctx->grid, a, b, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     dfree(a);
     dfree(b);
+    // observations with w-stacking follow the model
+    for (psc_obs* obs : ctx->stacked)
+        if (e == hipSuccess) e = build_wplanes(ctx, obs, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "psc_set_model");
     ctx->model_set = true;
     return PSC_OK;
@@ -379,7 +425,14 @@ PSC_API psc_status psc_obs_destroy(psc_obs* obs)
     if (obs->cap_stream) (void)hipStreamDestroy(obs->cap_stream);
     dfree(obs->items);
     dfree(obs->groups);
+    if (obs->ctx) {
+        auto& v = obs->ctx->stacked;
+        v.erase(std::remove(v.begin(), v.end(), obs), v.end());
+    }
+    dfree(obs->wplanes);
     dfree(obs->vis);
+    dfree(obs->wvis);
+    dfree(obs->wf);
     dfree(obs->ant_ptr);
     dfree(obs->ant_ent);
     dfree(obs->freq);
@@ -448,6 +501,7 @@ static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
             if (!isfinite(pa[r])) return fail(ctx, PSC_E_ARG, "par_angle must be finite");
     }
     std::vector<double> wv;
+    bool w_stack = false;
     if (d->w_m && n_row > 0) {
         wv.resize(n_row);
         PSC_HIP(ctx, hipMemcpy(wv.data(), d->w_m, sizeof(double) * n_row, hipMemcpyDeviceToHost));
@@ -458,10 +512,9 @@ static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
         }
         // the w phase widens each kernel by about |w| l / lambda wavelengths
         // at sky offset l; over the beam (l ~ lambda / D) that is |w| FoV / D
-        // uv cells, which must stay within what the support leaves
-        if (w_max * ctx->fov / ctx->cfg.dish_diam_m > kMaxWCells)
-            return fail(ctx, PSC_E_UNSUPPORTED, "w-term: |w| FoV / D exceeds the support's room "
-                                                "(the w phase would outgrow the kernel support)");
+        // uv cells, which must stay within what the support leaves.  Beyond
+        // that the observation is w-stacked (see below).
+        w_stack = w_max * ctx->fov / ctx->cfg.dish_diam_m > kMaxWCells;
     }
     // the kernel support must hold both apertures plus the taper
     const double lam_min = kCLight / fmax;
@@ -474,107 +527,202 @@ static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
     const int n_bl = n_ant * (n_ant - 1) / 2;
     auto bl_of = [n_ant](int i, int j) { return i * (2 * n_ant - i - 1) / 2 + (j - i - 1); };
 
+    // The plan of a run of intervals [s0, s1): its items, groups and samples,
+    // with indices local to the run (made global when the runs are joined).
+    struct PlanPart {
+        std::vector<Item> items;
+        std::vector<Group> groups;
+        std::vector<VisEnt> vis, wvis;
+        std::vector<uint8_t> wf;
+        std::vector<int32_t> n_items;  // per interval of the run
+        bool failed = false;
+    };
+    auto plan_run = [&](int s0, int s1, PlanPart& pp) {
+        std::vector<Item>& items = pp.items;
+        std::vector<Group>& groups = pp.groups;
+        std::vector<VisEnt>& vis = pp.vis;
+        std::vector<VisEnt>& wvis = pp.wvis;
+        std::vector<uint8_t>& wf = pp.wf;
+        const size_t n_samp = (size_t)(rp[s1] - rp[s0]) * n_chan;
+        vis.reserve(n_samp);
+        wvis.reserve(n_samp);
+        wf.reserve(n_samp);
+        pp.n_items.assign(s1 - s0, 0);
+        std::vector<int64_t> bl_count(n_bl + 1), bl_start(n_bl + 1);
+        std::vector<int64_t> bl_rows;
+        std::vector<int32_t> fcount(O * O), fpos(O * O);
+        std::vector<int32_t> fq(0);
+        std::vector<uint32_t> kq(0);
+        for (int s = s0; s < s1; ++s) {
+            const int64_t r0 = rp[s], r1 = rp[s + 1];
+            const size_t items_before = items.size();
+            std::fill(bl_count.begin(), bl_count.end(), 0);
+            for (int64_t r = r0; r < r1; ++r) bl_count[bl_of(a1[r], a2[r]) + 1]++;
+            bl_start[0] = 0;
+            for (int b = 0; b < n_bl; ++b) bl_start[b + 1] = bl_start[b] + bl_count[b + 1];
+            bl_rows.assign(r1 - r0, 0);
+            {
+                std::vector<int64_t> pos(bl_start.begin(), bl_start.end());
+                for (int64_t r = r0; r < r1; ++r) bl_rows[pos[bl_of(a1[r], a2[r])]++] = r;
+            }
+            for (int b = 0; b < n_bl; ++b) {
+                const int64_t nb = bl_start[b + 1] - bl_start[b];
+                if (nb == 0) continue;
+                const int64_t* rows = bl_rows.data() + bl_start[b];
+                fq.resize(nb);
+                kq.resize(nb);
+                for (int c = 0; c < n_chan; ++c) {
+                    Item it;
+                    it.interval = s;
+                    it.ai = a1[rows[0]];
+                    it.aj = a2[rows[0]];
+                    it.chan = c;
+                    it.grp_begin = (int32_t)groups.size();
+                    std::fill(fcount.begin(), fcount.end(), 0);
+                    for (int64_t k = 0; k < nb; ++k) {
+                        const int64_t r = rows[k];
+                        // uv in wavelengths, rounded to the 1/O lattice
+                        const double uu = uv[2 * r] * fr[c] / kCLight;
+                        const double vv = uv[2 * r + 1] * fr[c] / kCLight;
+                        const long long ql = llround(uu * ctx->snap);
+                        const long long qm = llround(vv * ctx->snap);
+                        const int bl_l = floor_div(ql, O), bl_m = floor_div(qm, O);
+                        const int f = (int)(ql - (long long)bl_l * O) * O + (int)(qm - (long long)bl_m * O);
+                        int kl = (bl_l - S / 2 + 1) % N;
+                        int km = (bl_m - S / 2 + 1) % N;
+                        kl += kl < 0 ? N : 0;
+                        km += km < 0 ? N : 0;
+                        fq[k] = f;
+                        kq[k] = ((uint32_t)kl << 16) | (uint32_t)km;
+                        fcount[f]++;
+                    }
+                    // one group per pair of opposite offsets {f, -f}
+                    const size_t base = vis.size();
+                    int32_t acc = 0;
+                    for (int f = 0; f < O * O; ++f) {
+                        const int fl = f / O, fm = f % O;
+                        const int pf = ((O - fl) % O) * O + (O - fm) % O;
+                        if (pf < f) continue;  // handled with its partner
+                        int prim = f, sec = (pf != f) ? pf : -1;
+                        if (fcount[prim] == 0) {
+                            if (sec < 0 || fcount[sec] == 0) continue;
+                            prim = sec;
+                            sec = -1;
+                        }
+                        Group g;
+                        g.f = prim;
+                        g.vis_begin = (uint32_t)(base + acc);
+                        g.n_vis = fcount[prim];
+                        g.n_vis2 = (sec >= 0) ? fcount[sec] : 0;
+                        fpos[prim] = acc;
+                        acc += g.n_vis;
+                        if (g.n_vis2 > 0) {
+                            fpos[sec] = acc;
+                            acc += g.n_vis2;
+                        }
+                        groups.push_back(g);
+                    }
+                    vis.resize(base + nb);
+                    for (int64_t k = 0; k < nb; ++k) {
+                        VisEnt ve;
+                        ve.vidx = (uint32_t)(rows[k] * n_chan + c);
+                        ve.klo = kq[k];
+                        vis[base + fpos[fq[k]]++] = ve;
+                        wvis.push_back(ve);
+                        wf.push_back((uint8_t)(((fq[k] / O) << 4) | (fq[k] % O)));
+                    }
+                    it.vis_begin = (uint32_t)base;
+                    it.n_vis = (int32_t)nb;
+                    it.grp_end = (int32_t)groups.size();
+                    // largest groups first: the block's wavefronts claim groups in
+                    // this order, so the long ones start early and the item's
+                    // wavefronts finish together
+                    std::stable_sort(groups.begin() + it.grp_begin, groups.end(),
+                                     [](const Group& x, const Group& y) {
+                                         const int cx = (x.n_vis + 7) / 8 + (x.n_vis2 + 7) / 8;
+                                         const int cy = (y.n_vis + 7) / 8 + (y.n_vis2 + 7) / 8;
+                                         return cx > cy;
+                                     });
+                    items.push_back(it);
+                }
+            }
+            pp.n_items[s - s0] = (int32_t)(items.size() - items_before);
+        }
+    };
+
+    // Intervals are planned independently: runs of them on host threads,
+    // split by row count, then joined in interval order (the result does not
+    // depend on the split).
+    const int n_thr = (int)std::max<int64_t>(1, std::min<int64_t>(
+        {(int64_t)std::max(1u, std::thread::hardware_concurrency()), 16, (int64_t)n_int,
+         1 + n_row * n_chan / 200000}));
+    std::vector<int> cut(n_thr + 1, n_int);
+    cut[0] = 0;
+    for (int t = 1; t < n_thr; ++t) {
+        const int64_t target = n_row * t / n_thr;
+        cut[t] = std::max(cut[t - 1], (int)(std::upper_bound(rp.begin(), rp.end(), target) - rp.begin()) - 1);
+        cut[t] = std::min(cut[t], n_int);
+    }
+    std::vector<PlanPart> parts(n_thr);
+    {
+        std::vector<std::thread> pool;
+        for (int t = 1; t < n_thr; ++t)
+            pool.emplace_back([&, t] {
+                try {
+                    plan_run(cut[t], cut[t + 1], parts[t]);
+                } catch (...) {
+                    parts[t].failed = true;
+                }
+            });
+        try {
+            plan_run(cut[0], cut[1], parts[0]);
+        } catch (...) {
+            parts[0].failed = true;
+        }
+        for (auto& th : pool) th.join();
+    }
+    size_t tot_items = 0, tot_groups = 0, tot_vis = 0;
+    for (const PlanPart& pp : parts) {
+        if (pp.failed) return fail(ctx, PSC_E_OOM, "host memory allocation failed while planning");
+        tot_items += pp.items.size();
+        tot_groups += pp.groups.size();
+        tot_vis += pp.vis.size();
+    }
+    if (tot_groups > 2147483647u || tot_vis > 4294967295u || tot_items > 2000000000u)
+        return fail(ctx, PSC_E_UNSUPPORTED, "too many samples for one observation");
     std::vector<Item> items;
     std::vector<Group> groups;
-    std::vector<VisEnt> vis;
-    vis.reserve((size_t)n_row * n_chan);
+    std::vector<VisEnt> vis, wvis;
+    std::vector<uint8_t> wf;
+    items.reserve(tot_items);
+    groups.reserve(tot_groups);
+    vis.reserve(tot_vis);
+    wvis.reserve(tot_vis);
+    wf.reserve(tot_vis);
     std::vector<int32_t> item_ptr(n_int + 1, 0);
-    std::vector<int64_t> bl_count(n_bl + 1), bl_start(n_bl + 1);
-    std::vector<int64_t> bl_rows;
-    std::vector<int32_t> fcount(O * O), fpos(O * O);
-    std::vector<int32_t> fq(0);
-    std::vector<uint32_t> kq(0);
-    for (int s = 0; s < n_int; ++s) {
-        const int64_t r0 = rp[s], r1 = rp[s + 1];
-        std::fill(bl_count.begin(), bl_count.end(), 0);
-        for (int64_t r = r0; r < r1; ++r) bl_count[bl_of(a1[r], a2[r]) + 1]++;
-        bl_start[0] = 0;
-        for (int b = 0; b < n_bl; ++b) bl_start[b + 1] = bl_start[b] + bl_count[b + 1];
-        bl_rows.assign(r1 - r0, 0);
-        {
-            std::vector<int64_t> pos(bl_start.begin(), bl_start.end());
-            for (int64_t r = r0; r < r1; ++r) bl_rows[pos[bl_of(a1[r], a2[r])]++] = r;
+    for (int t = 0; t < n_thr; ++t) {
+        PlanPart& pp = parts[t];
+        const uint32_t g_off = (uint32_t)groups.size(), v_off = (uint32_t)vis.size();
+        for (Item it : pp.items) {
+            it.grp_begin += (int32_t)g_off;
+            it.grp_end += (int32_t)g_off;
+            it.vis_begin += v_off;
+            items.push_back(it);
         }
-        for (int b = 0; b < n_bl; ++b) {
-            const int64_t nb = bl_start[b + 1] - bl_start[b];
-            if (nb == 0) continue;
-            const int64_t* rows = bl_rows.data() + bl_start[b];
-            fq.resize(nb);
-            kq.resize(nb);
-            for (int c = 0; c < n_chan; ++c) {
-                Item it;
-                it.interval = s;
-                it.ai = a1[rows[0]];
-                it.aj = a2[rows[0]];
-                it.chan = c;
-                it.grp_begin = (int32_t)groups.size();
-                std::fill(fcount.begin(), fcount.end(), 0);
-                for (int64_t k = 0; k < nb; ++k) {
-                    const int64_t r = rows[k];
-                    // uv in wavelengths, rounded to the 1/O lattice
-                    const double uu = uv[2 * r] * fr[c] / kCLight;
-                    const double vv = uv[2 * r + 1] * fr[c] / kCLight;
-                    const long long ql = llround(uu * ctx->snap);
-                    const long long qm = llround(vv * ctx->snap);
-                    const int bl_l = floor_div(ql, O), bl_m = floor_div(qm, O);
-                    const int f = (int)(ql - (long long)bl_l * O) * O + (int)(qm - (long long)bl_m * O);
-                    int kl = (bl_l - S / 2 + 1) % N;
-                    int km = (bl_m - S / 2 + 1) % N;
-                    kl += kl < 0 ? N : 0;
-                    km += km < 0 ? N : 0;
-                    fq[k] = f;
-                    kq[k] = ((uint32_t)kl << 16) | (uint32_t)km;
-                    fcount[f]++;
-                }
-                // one group per pair of opposite offsets {f, -f}
-                const size_t base = vis.size();
-                int32_t acc = 0;
-                for (int f = 0; f < O * O; ++f) {
-                    const int fl = f / O, fm = f % O;
-                    const int pf = ((O - fl) % O) * O + (O - fm) % O;
-                    if (pf < f) continue;  // handled with its partner
-                    int prim = f, sec = (pf != f) ? pf : -1;
-                    if (fcount[prim] == 0) {
-                        if (sec < 0 || fcount[sec] == 0) continue;
-                        prim = sec;
-                        sec = -1;
-                    }
-                    Group g;
-                    g.f = prim;
-                    g.vis_begin = (uint32_t)(base + acc);
-                    g.n_vis = fcount[prim];
-                    g.n_vis2 = (sec >= 0) ? fcount[sec] : 0;
-                    fpos[prim] = acc;
-                    acc += g.n_vis;
-                    if (g.n_vis2 > 0) {
-                        fpos[sec] = acc;
-                        acc += g.n_vis2;
-                    }
-                    groups.push_back(g);
-                }
-                vis.resize(base + nb);
-                for (int64_t k = 0; k < nb; ++k) {
-                    VisEnt ve;
-                    ve.vidx = (uint32_t)(rows[k] * n_chan + c);
-                    ve.klo = kq[k];
-                    vis[base + fpos[fq[k]]++] = ve;
-                }
-                it.grp_end = (int32_t)groups.size();
-                // largest groups first: the block's wavefronts claim groups in
-                // this order, so the long ones start early and the item's
-                // wavefronts finish together
-                std::stable_sort(groups.begin() + it.grp_begin, groups.end(), [](const Group& x, const Group& y) {
-                    const int cx = (x.n_vis + 7) / 8 + (x.n_vis2 + 7) / 8;
-                    const int cy = (y.n_vis + 7) / 8 + (y.n_vis2 + 7) / 8;
-                    return cx > cy;
-                });
-                items.push_back(it);
-            }
+        for (Group g : pp.groups) {
+            g.vis_begin += v_off;
+            groups.push_back(g);
         }
-        item_ptr[s + 1] = (int32_t)items.size();
+        vis.insert(vis.end(), pp.vis.begin(), pp.vis.end());
+        wvis.insert(wvis.end(), pp.wvis.begin(), pp.wvis.end());
+        wf.insert(wf.end(), pp.wf.begin(), pp.wf.end());
+        for (int s = cut[t]; s < cut[t + 1]; ++s) item_ptr[s + 1] = item_ptr[s] + pp.n_items[s - cut[t]];
+        std::vector<Item>().swap(pp.items);  // release the run's memory as it is joined
+        std::vector<Group>().swap(pp.groups);
+        std::vector<VisEnt>().swap(pp.vis);
+        std::vector<VisEnt>().swap(pp.wvis);
+        std::vector<uint8_t>().swap(pp.wf);
     }
-    if (groups.size() > 2147483647u || vis.size() > 4294967295u)
-        return fail(ctx, PSC_E_UNSUPPORTED, "too many samples for one observation");
 
     // per (interval, antenna) list of (item, end) in item order
     std::vector<uint32_t> ant_ptr((size_t)n_int * n_ant + 1, 0), ant_ent(2 * items.size());
@@ -632,6 +780,8 @@ static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
     hipError_t e = dmalloc(&obs->items, items.size());
     if (e == hipSuccess) e = dmalloc(&obs->groups, groups.size());
     if (e == hipSuccess) e = dmalloc(&obs->vis, vis.size());
+    if (e == hipSuccess) e = dmalloc(&obs->wvis, wvis.size());
+    if (e == hipSuccess) e = dmalloc(&obs->wf, wf.size());
     if (e == hipSuccess) e = dmalloc(&obs->ant_ptr, ant_ptr.size());
     if (e == hipSuccess) e = dmalloc(&obs->ant_ent, ant_ent.size());
     if (e == hipSuccess) e = dmalloc(&obs->freq, n_chan);
@@ -649,6 +799,10 @@ static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
         e = hipMemcpy(obs->groups, groups.data(), sizeof(Group) * groups.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !vis.empty())
         e = hipMemcpy(obs->vis, vis.data(), sizeof(VisEnt) * vis.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !wvis.empty())
+        e = hipMemcpy(obs->wvis, wvis.data(), sizeof(VisEnt) * wvis.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !wf.empty())
+        e = hipMemcpy(obs->wf, wf.data(), wf.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(obs->ant_ptr, ant_ptr.data(), sizeof(uint32_t) * ant_ptr.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !ant_ent.empty())
@@ -678,6 +832,41 @@ static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
             if (e == hipSuccess) e = hipMemset(obs->zero_pa, 0, sizeof(double) * nr);
         }
     }
+    if (w_stack) {
+        // w-stacking (Sec. 5.1: non-coplanar arrays, beyond what one kernel
+        // holds): the model transformed again for planes w_k = k dw
+        // wavelengths; each sample reads the plane nearest its w and carries
+        // the residual w - w_k in its kernel.  dw keeps that residual's
+        // widening at most kWStackCells cells at the lowest frequency.
+        double fmin = fr[0];
+        for (int c = 1; c < n_chan; ++c) fmin = std::min(fmin, fr[c]);
+        const double dw = 2.0 * kWStackCells * ctx->cfg.dish_diam_m / (ctx->fov * (kCLight / fmin));
+        const double w_lo = *std::min_element(wv.begin(), wv.end());
+        const double w_hi = *std::max_element(wv.begin(), wv.end());
+        int k_lo = 0, k_hi = 0;
+        bool first = true;
+        for (int c = 0; c < n_chan; ++c) {
+            const double w_per_m = fr[c] / kCLight;  // as the kernels form it
+            for (double w : {w_lo, w_hi}) {
+                const int k = (int)rint((w * w_per_m) / dw);
+                k_lo = first ? k : std::min(k_lo, k);
+                k_hi = first ? k : std::max(k_hi, k);
+                first = false;
+            }
+        }
+        const size_t p2 = (size_t)(N + S) * (N + S);
+        const size_t bytes = (size_t)(k_hi - k_lo + 1) * p2 * sizeof(float2);
+        if (bytes > (size_t)2147483647) {
+            psc_obs_destroy(obs);
+            return fail(ctx, PSC_E_UNSUPPORTED,
+                        "w-term: the w-stacked model grids would exceed 2 GiB (w range too wide for the grid)");
+        }
+        obs->w_k0 = k_lo;
+        obs->w_nk = k_hi - k_lo + 1;
+        obs->w_dw = dw;
+        if (e == hipSuccess) e = dmalloc(&obs->wplanes, (size_t)obs->w_nk * p2);
+        if (e == hipSuccess && ctx->model_set) e = build_wplanes(ctx, obs, nullptr);
+    }
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&obs->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     dfree(cells);
@@ -687,6 +876,7 @@ static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
         psc_obs_destroy(obs);
         return fail(ctx, st, msg);
     }
+    if (obs->w_nk > 0) ctx->stacked.push_back(obs);
     *out = obs;
     return PSC_OK;
 }
@@ -702,6 +892,8 @@ PSC_API psc_status psc_obs_launch_info(const psc_obs* obs, psc_launch_info* out)
     out->window_waves = win_block_waves(ctx->s, kGrad, frame, ctx->m, ctx->o, obs->n_tab, obs->win_waves);
     out->samples_per_item = obs->n_items > 0 ? (double)obs->n_vis / (double)obs->n_items : 0.0;
     out->plan_ms = obs->plan_ms;
+    out->w_planes = obs->w_nk;
+    out->reserved = 0;
     return PSC_OK;
 }
 
@@ -725,6 +917,8 @@ ItemArgs item_args(psc_ctx* ctx, psc_obs* obs, const double* offsets, int item_b
     a.items = obs->items;
     a.groups = obs->groups;
     a.vis = obs->vis;
+    a.wvis = obs->wvis;
+    a.wf = obs->wf;
     a.item_begin = item_begin;
     a.n_items = n_items;
     a.n_ant = obs->n_ant;
@@ -732,6 +926,10 @@ ItemArgs item_args(psc_ctx* ctx, psc_obs* obs, const double* offsets, int item_b
     a.n_chan = obs->n_chan;
     a.par_angle = obs->par_angle;
     a.w_m = obs->w_m;
+    a.wgrid = obs->wplanes;
+    a.w_dw = obs->w_dw;
+    a.w_k0 = obs->w_k0;
+    a.w_nk = obs->w_nk;
     a.offsets = offsets;
     a.freq = obs->freq;
     a.grid = ctx->grid;
@@ -949,6 +1147,8 @@ PSC_API psc_status psc_image_gradient(psc_ctx* ctx, psc_obs* obs, const double* 
     if (st != PSC_OK) return st;
     if (!image_grad_out_dev || ((!vis_obs_dev || !weight_dev) && obs->n_vis > 0))
         return fail(ctx, PSC_E_ARG, "null data or output");
+    if (obs->w_nk > 0)
+        return fail(ctx, PSC_E_UNSUPPORTED, "psc_image_gradient: not available for a w-stacked observation");
     const int n = ctx->n;
     const size_t np = (size_t)(n + ctx->s) * (n + ctx->s);
     if (!ctx->rgrid) {

@@ -45,8 +45,7 @@ __global__ void __launch_bounds__(kGridThreads) k_grid(ItemArgs a)
     float2* patch = reinterpret_cast<float2*>(gsh + m2p);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int per_xcd = gridDim.x >> 3;
-    const int li = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    const int li = item_of_block();
     if (li >= a.n_items) return;
     const Item it = a.items[a.item_begin + li];
 
@@ -253,8 +252,7 @@ __global__ void __launch_bounds__(kGridThreads) k_gridw(ItemArgs a)
     float4* airy_sh = reinterpret_cast<float4*>(patch + PB * PB);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int per_xcd = gridDim.x >> 3;
-    const int li = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    const int li = item_of_block();
     if (li >= a.n_items) return;
     const Item it = a.items[a.item_begin + li];
 
@@ -494,7 +492,7 @@ static hipError_t launch_gridw_t(const ItemArgs& a, hipStream_t s)
     static const hipError_t attr = hipFuncSetAttribute(
         (const void*)k_gridw<S, MF, WT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGridLdsMax);
     if (attr != hipSuccess) return attr;
-    const int blocks = 8 * ((a.n_items + 7) / 8);
+    const int blocks = (int)item_blocks(a.n_items);
     k_gridw<S, MF, WT><<<blocks, kGridThreads, sh, s>>>(a);
     return hipGetLastError();
 }
@@ -537,7 +535,7 @@ hipError_t launch_grid(int support, const ItemArgs& a, hipStream_t s)
     static const hipError_t attr =
         hipFuncSetAttribute((const void*)k_grid<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGridLdsMax);
     if (attr != hipSuccess) return attr;
-    const int blocks = 8 * ((a.n_items + 7) / 8);
+    const int blocks = (int)item_blocks(a.n_items);
     k_grid<16><<<blocks, kGridThreads, sh, s>>>(a);
     return hipGetLastError();
 }

@@ -18,6 +18,8 @@ struct Item {
     int32_t ai, aj;  // antennas, ai < aj
     int32_t chan;
     int32_t grp_begin, grp_end;  // [begin, end) into the group array
+    uint32_t vis_begin;          // the item's samples: [vis_begin, vis_begin + n_vis) of the
+    int32_t n_vis;               // sample arrays (grouped by offset, or in row order)
 };
 
 // Samples of an item sharing the sub-lattice offset f = fl * O + fm, which
@@ -33,7 +35,10 @@ struct Group {
 
 // One visibility sample: vidx = row * n_chan + chan (vis arrays are
 // [vidx][pol]), klo = first grid row/column of its S x S window, packed as
-// (row << 16) | column, both already reduced modulo N.
+// (row << 16) | column, both already reduced modulo N.  The table form reads
+// an item's samples grouped by sub-lattice offset (Group); the window form
+// reads them in row order (time order within a baseline), each with its own
+// offset (fl << 4) | fm in a byte array beside.
 struct VisEnt {
     uint32_t vidx;
     uint32_t klo;
@@ -58,11 +63,32 @@ __host__ __device__ constexpr int mode_nc(int mode)
     return mode == kGrad ? 12 : mode == kVjp ? 4 : mode == kScale ? 6 : 0;
 }
 
+// Work items per launch are spread over the eight XCDs (each with its own
+// L2) in chunks of kXcdChunk consecutive items dealt round-robin: the
+// hardware hands block b to XCD b mod 8, so the k-th block an XCD runs takes
+// item ((k / C) 8 + b mod 8) C + k mod C.  Consecutive items (the channels of
+// one baseline, which read the same rows of the visibility arrays) stay on
+// one XCD, while every XCD sees every part of the item list, so a launch
+// whose items differ in cost along the list (uneven solution intervals)
+// stays balanced.  Launch item_blocks(n) blocks and skip li >= n.
+constexpr int kXcdChunk = 32;
+__host__ __device__ inline long long item_blocks(long long n_items)
+{
+    return 8LL * kXcdChunk * ((n_items + 8LL * kXcdChunk - 1) / (8LL * kXcdChunk));
+}
+__device__ __forceinline__ int item_of_block()
+{
+    const int b = (int)blockIdx.x, k = b >> 3;
+    return (((k / kXcdChunk) << 3) + (b & 7)) * kXcdChunk + (k % kXcdChunk);
+}
+
 // Arguments of the fused kernel-build + degrid kernel.
 struct ItemArgs {
     const Item* items;
     const Group* groups;
     const VisEnt* vis;
+    const VisEnt* wvis;         // window form: each item's samples in row order
+    const uint8_t* wf;          // window form: each sample's offset (fl << 4) | fm
     int32_t item_begin, n_items;
     int32_t n_ant, n_pol, n_chan;
     const double* offsets;      // [n_int][n_pol][n_ant][2]
@@ -90,6 +116,12 @@ struct ItemArgs {
     double2* grid_acc;          // grid mode: residual grid, (N+S) x (N+S), float64 sums
     const double* par_angle;    // nullable [n_row]: offsets in the mount frame (window form)
     const double* w_m;          // nullable [n_row]: baseline w in metres, the w-term (window form)
+    // w-stacking (w_nk > 0): the model grid again for w = w_k, k = w_k0 ..
+    // w_k0 + w_nk - 1, w_k = k w_dw wavelengths, each (N+S)^2 and padded like
+    // the grid: the transform of I exp(2 pi i w_k (n - 1)) / c
+    const float2* wgrid;
+    double w_dw;
+    int32_t w_k0, w_nk;
     // measured aperture (illum 2): its transform on [ap_n][ap_n] nodes in
     // lambda/D units, (T, s dT/du, s dT/dv, s^2 d2T/dudv) at u = (i - ap_c) s,
     // s = 1 / ap_inv_step, i along the mount frame's l axis
@@ -138,6 +170,8 @@ struct SolveArgs {
 // Kernel launchers (psc_kernels.hip).  Each returns the launch's hipError_t.
 hipError_t launch_taper_image(const double* img, const double* taper_pix, double2* out, int n,
                               hipStream_t s);
+hipError_t launch_wplane_image(const double* img, const double* taper_pix, double2* out, int n, double cell,
+                               double w, hipStream_t s);
 hipError_t launch_fft_rows(double2* data, int n, int log2n, hipStream_t s);
 hipError_t launch_transpose(const double2* in, double2* out, int n, hipStream_t s);
 hipError_t launch_finish_grid(const double2* in, float2* out, int n, int pad, hipStream_t s);

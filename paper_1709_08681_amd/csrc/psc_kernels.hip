@@ -79,6 +79,29 @@ __global__ void k_transpose(const double2* __restrict__ in, double2* __restrict_
 // Writes V^{M0} into a (N+pad) x (N+pad) array whose last `pad` rows and
 // columns repeat the first ones (V^{M0} is N-periodic because the sky lies on
 // the pixel lattice), so an S x S window starting anywhere in [0, N) never wraps.
+// The tapered image of one w-plane: (I / c) exp(2 pi i w (n - 1)) with the
+// pixel's direction cosines l = (ix - N/2) cell, m = (iy - N/2) cell and
+// n - 1 = -x / (1 + sqrt(1 - x)), x = l^2 + m^2 (Eq. ME with the baseline's w),
+// in float64.
+__global__ void k_wplane_image(const double* __restrict__ img, const double* __restrict__ tp,
+                               double2* __restrict__ out, int n, double cell, double w)
+{
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)n * n) return;
+    const int ix = (int)(idx / n), iy = (int)(idx % n);
+    const double v = img[idx] / (tp[ix] * tp[iy]);
+    if (v == 0.0) {
+        out[idx] = make_double2(0.0, 0.0);
+        return;
+    }
+    const double l = (ix - n / 2) * cell, m = (iy - n / 2) * cell;
+    const double x = l * l + m * m;
+    const double nm1 = -x / (1.0 + sqrt(1.0 - x));
+    double sn, cs;
+    sincospi(2.0 * w * nm1, &sn, &cs);
+    out[idx] = make_double2(v * cs, v * sn);
+}
+
 __global__ void k_finish_grid(const double2* __restrict__ in, float2* __restrict__ out, int n, int pad)
 {
     const int p = n + pad;
@@ -197,8 +220,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 
     float2* ush = reinterpret_cast<float2*>(reinterpret_cast<unsigned char*>(gsh) + sizeof(float) * NV * m2p);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int per_xcd = gridDim.x >> 3;
-    const int li = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    const int li = item_of_block();
     if (li >= a.n_items) return;
     const int item_idx = a.item_begin + li;
     const Item it = a.items[item_idx];
@@ -858,6 +880,14 @@ hipError_t launch_taper_image(const double* img, const double* taper_pix, double
     return hipGetLastError();
 }
 
+hipError_t launch_wplane_image(const double* img, const double* taper_pix, double2* out, int n, double cell,
+                               double w, hipStream_t s)
+{
+    const size_t tot = (size_t)n * n;
+    k_wplane_image<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(img, taper_pix, out, n, cell, w);
+    return hipGetLastError();
+}
+
 hipError_t launch_fft_rows(double2* data, int n, int log2n, hipStream_t s)
 {
     const size_t sh = sizeof(double2) * (size_t)n;
@@ -926,7 +956,7 @@ static hipError_t launch_items_t(const ItemArgs& a, hipStream_t s)
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmax);
     }();
     if (attr != hipSuccess) return attr;
-    const int blocks = 8 * ((a.n_items + 7) / 8);
+    const int blocks = (int)item_blocks(a.n_items);
     k_item<S, MODE, SPL, MX><<<blocks, kBlock, sh, s>>>(a);
     return hipGetLastError();
 }

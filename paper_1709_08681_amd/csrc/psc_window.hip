@@ -153,8 +153,14 @@ __device__ __forceinline__ void halves(float v, float& lo, float& hi)
 // the m-axis phase is the lane's own.  In the sum lane (h, c) takes the
 // image-sample m index n_m = c - S h (M/2 of the S lanes of each half have
 // one).
-template <int S, int MODE, int MF, int W, bool WT>
-__global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
+//
+// MT: the image-sample count per axis when fixed at compile time (the
+// default 3S/2, sky frame), 0 to read it from the arguments; fixed, the
+// image-sample sums run with constant trip counts.  The mount frame at
+// support 16 asks for three wavefronts per SIMD (a few registers spill;
+// 13% faster on the single-interval workload than two).
+template <int S, int MODE, int MF, int W, bool WT, int MT = 0>
+__global__ void __launch_bounds__(64 * W, S == 16 && MF == kFrameMount ? 3 : 1) k_winw(ItemArgs a)
 {
     constexpr int H = S / 2, SP = S + 1;
     constexpr int SL = 2 * S;    // lanes per worker
@@ -173,20 +179,25 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ float2 twsh[S * 16];  // exp(+2 pi i t / (S O)), S O <= 16 S
 
-    const int m = a.m, half_m = m >> 1;
+    const int m = MT > 0 ? MT : a.m, half_m = m >> 1;
     const int m2p = (m * m + 3) & ~3;
+    constexpr int kUnroll = 4;
     const int O = a.oversample, so = S * O;
-    // dynamic LDS: per-worker float64 sums | the item's groups |
-    // image-plane factors [n][NG] (sky frame) | window tiles | Airy table (mount frame)
+    // dynamic LDS: per-worker float64 sums | image-plane factors [n][NG]
+    // (sky frame) | window tiles | Airy table (mount frame)
     double* gpart = reinterpret_cast<double*>(smem);  // [NW][NCP]
-    Group* grp = reinterpret_cast<Group*>(gpart + NW * NCP);
-    float* gsh = reinterpret_cast<float*>(grp + win_max_groups(O));
+    float* gsh = reinterpret_cast<float*>(gpart + NW * NCP);
     float2* wtile = reinterpret_cast<float2*>(gsh + (SKY ? NG * m2p : 0));
-    float4* airy_sh = reinterpret_cast<float4*>(wtile + (size_t)NW * S * SP);
+    // each lane's share of its worker's current window transform, before the
+    // sample's phases, kept while samples share the window: in LDS at
+    // support 16 ([H][block lanes]; in registers it would cost a wavefront
+    // per SIMD), in registers at 32 (whose blocks are bound by LDS)
+    constexpr bool YLDS = S == 16;
+    float2* ybuf = wtile + (size_t)NW * S * SP;
+    float4* airy_sh = reinterpret_cast<float4*>(ybuf + (YLDS ? (size_t)H * kBlock : 0));
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int per_xcd = gridDim.x >> 3;
-    const int li = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    const int li = item_of_block();
     if (li >= a.n_items) return;
     const int item_idx = a.item_begin + li;
     const Item it = a.items[item_idx];
@@ -196,12 +207,14 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
     const float inv_s = 1.0f / (float)S;
     const int P = N + S;  // pitch of the padded grid
     const int rowbytes = P * (int)sizeof(float2);
+    // the model grid, or with w-stacking the stack of its w-planes (each
+    // (N+S)^2, at most 2 GiB together)
+    const bool stacked = WT && a.w_nk > 0;
+    const int plane_bytes = P * P * (int)sizeof(float2);
     const __amdgpu_buffer_rsrc_t grsrc = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)a.grid, (short)0, P * P * (int)sizeof(float2), 0x00020000);
+        (void*)(stacked ? a.wgrid : a.grid), (short)0, (stacked ? a.w_nk : 1) * plane_bytes, 0x00020000);
 
-    const int n_grp = it.grp_end - it.grp_begin;
     for (int t = tid; t < so; t += kBlock) twsh[t] = a.tw[t];
-    for (int t = tid; t < n_grp; t += kBlock) grp[t] = a.groups[it.grp_begin + t];
     if constexpr (MF == kFrameMount)
         for (int t = tid; t < a.n_tab; t += kBlock) airy_sh[t] = a.airy[t];
     __syncthreads();
@@ -232,25 +245,21 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
         const float sg = (n & 1) ? -inv_s : inv_s;
         return make_float2(t.x * sg, t.y * sg);
     };
-    // the sample v positions on from (gi, v) in the item's numbering
-    auto advance = [&](int& gi, int& v, int step) {
-        v += step;
-        while (gi < n_grp) {
-            const int tot = grp[gi].n_vis + grp[gi].n_vis2;
-            if (v < tot) break;
-            v -= tot;
-            ++gi;
-        }
-    };
-    // a sample's entry; past the end, the item's first (loads stay in bounds)
-    auto entry = [&](int gi, int v) {
-        return gi < n_grp ? a.vis[grp[gi].vis_begin + v] : a.vis[grp[0].vis_begin];
-    };
-    // rows H hh + r of the reversed column c: grid row k_lo_l + S-1-(H hh + r)
-    auto load_window = [&](const VisEnt& e, float2 (&x)[H]) {
+    // The item's samples in row order (time order along the baseline's uv
+    // track), each worker a contiguous share [k_lo, k_hi): consecutive
+    // samples of one worker often fall in the same window (a track moves a
+    // fraction of a cell per integration), whose transform is then reused.
+    const int n_s = it.n_vis;
+    const int k_lo = (int)(((long long)worker * n_s) / NW), k_hi = (int)(((long long)(worker + 1) * n_s) / NW);
+    const VisEnt* went = a.wvis + it.vis_begin;
+    const uint8_t* wfp = a.wf + it.vis_begin;
+    // rows H hh + r of the reversed column c: grid row k_lo_l + S-1-(H hh + r),
+    // of w-plane `plane` when stacked
+    auto load_window = [&](const VisEnt& e, int plane, float2 (&x)[H]) {
         const int row0 = (int)(e.klo >> 16);
         const int col0 = (int)(e.klo & 0xffffu);
-        const int voff = (row0 * P + col0 + (S - 1 - c)) * (int)sizeof(float2) + (1 - hh) * H * rowbytes;
+        const int voff = plane * plane_bytes + (row0 * P + col0 + (S - 1 - c)) * (int)sizeof(float2) +
+                         (1 - hh) * H * rowbytes;
 #pragma unroll
         for (int r = 0; r < H; ++r)
             x[r] = __builtin_bit_cast(
@@ -274,6 +283,19 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
     // from the hardware sine and cosine of the phase in turns reduced to
     // [0, 1) (the phase itself is a float32 product; the parity tests bound
     // the result)
+    // a sample's w in wavelengths, and with w-stacking its plane k (the one
+    // nearest, w_k = k dw) and the residual w - w_k that the kernel carries
+    auto wsel = [&](const VisEnt& e, float& wr, int& plane) {
+        const double wl = a.w_m[e.vidx / (uint32_t)a.n_chan] * w_per_m;
+        if (stacked) {
+            const int k = min(max((int)rint(wl / a.w_dw), a.w_k0), a.w_k0 + a.w_nk - 1);
+            wr = (float)(wl - (double)k * a.w_dw);
+            plane = k - a.w_k0;
+        } else {
+            wr = (float)wl;
+            plane = 0;
+        }
+    };
     auto wphase = [&](float wl, float l) {
         const float x = fmaf(l, l, mm2);
         const float nm1 = -x * __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_sqrtf(1.f - x));
@@ -283,23 +305,25 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
     const float ctm = a.taper_img[jm];
 
     for (int pol = 0; pol < a.n_pol; ++pol) {
-        // this worker's first two samples, their entries, the first window
-        int gi0 = 0, v0 = worker;
-        advance(gi0, v0, 0);
-        int gi1 = gi0, v1 = v0;
-        if (gi0 < n_grp) advance(gi1, v1, NW);
-        float2 x0[H];
+        // this worker's first sample and the entry after it, the first window
+        int k0 = k_lo;
         VisEnt e0 = {0u, 0u}, e1 = {0u, 0u};
+        int f0 = 0, f1 = 0;
+        float2 x0[H];
         float2 vin0 = zero;
         float wgt0 = 0.f, w0 = 0.f;
-        if (gi0 < n_grp) {
-            e0 = entry(gi0, v0);
-            e1 = entry(gi1, v1);
-            load_window(e0, x0);
+        int pl0 = 0;
+        if (k0 < k_hi) {
+            e0 = went[k0];
+            f0 = wfp[k0];
+            const int k1 = k0 + 1 < k_hi ? k0 + 1 : k0;  // past the end: the last (loads stay in bounds)
+            e1 = went[k1];
+            f1 = wfp[k1];
+            if constexpr (WT) wsel(e0, w0, pl0);
+            load_window(e0, pl0, x0);
             const size_t o0 = (size_t)e0.vidx * a.n_pol + pol;
             if (MODE != kPredict) vin0 = a.vis_in[o0];
             if (MODE == kGrad || MODE == kScale) wgt0 = a.weight[o0];
-            if constexpr (WT) w0 = (float)(a.w_m[e0.vidx / (uint32_t)a.n_chan] * w_per_m);
         }
 
         // offsets plus squint (along l, or along the mount's first axis)
@@ -320,57 +344,68 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
         __syncthreads();
 
         double acc64 = 0.0;
-        while (gi0 < n_grp) {
-            // ---- fetch ahead: the next sample's window and inputs, the entry after it
+        bool need0 = true;
+        float2 y[H];
+        while (k0 < k_hi) {
+            // ---- fetch ahead: the next sample's window (when it differs), its
+            // inputs, the entry after it
+            const bool more = k0 + 1 < k_hi;
+            float w1 = 0.f;
+            int pl1 = 0;
+            if constexpr (WT) wsel(e1, w1, pl1);
+            const bool need1 = more && (e1.klo != e0.klo || pl1 != pl0);
             float2 x1[H];
-            load_window(e1, x1);
+            if (need1) load_window(e1, pl1, x1);
             const size_t o1 = (size_t)e1.vidx * a.n_pol + pol;
             float2 vin1 = zero;
-            float wgt1 = 0.f, w1 = 0.f;
+            float wgt1 = 0.f;
             if (MODE != kPredict) vin1 = a.vis_in[o1];
             if (MODE == kGrad || MODE == kScale) wgt1 = a.weight[o1];
-            if constexpr (WT) w1 = (float)(a.w_m[e1.vidx / (uint32_t)a.n_chan] * w_per_m);
-            int gi2 = gi1, v2 = v1;
-            if (gi1 < n_grp) advance(gi2, v2, NW);
-            const VisEnt e2 = entry(gi2, v2);
+            const int k2 = k0 + 2 < k_hi ? k0 + 2 : k_hi - 1;
+            const VisEnt e2 = went[k2];
+            const int f2 = wfp[k2];
 
-            // ---- the current sample's offset per axis: f, or -f after the group's first part
-            const Group g0 = grp[gi0];
-            int fl = g0.f / O, fm = g0.f - (g0.f / O) * O;
-            if (v0 >= g0.n_vis) {
-                fl = (O - fl) & (O - 1);
-                fm = (O - fm) & (O - 1);
-            }
+            // ---- the current sample's sub-lattice offset per axis
+            const int fl = f0 >> 4, fm = f0 & 15;
 
-            // ---- along l: first radix-2 step across the halves, then 16 points
-            float2 y[H];
+            if (need0) {
+                // ---- along l: first radix-2 step across the halves, then H points
 #pragma unroll
-            for (int r = 0; r < H; ++r) {
-                // the column's rows r (half 0) and H + r (half 1), in every lane
-                float tx, bx, ty, by;
-                halves<S>(x0[r].x, tx, bx);
-                halves<S>(x0[r].y, ty, by);
-                y[r] = make_float2(fmaf(sgn, bx, tx), fmaf(sgn, by, ty));
-                if (r > 0) y[r] = cmul(y[r], tw1[r]);
+                for (int r = 0; r < H; ++r) {
+                    // the column's rows r (half 0) and H + r (half 1), in every lane
+                    float tx, bx, ty, by;
+                    halves<S>(x0[r].x, tx, bx);
+                    halves<S>(x0[r].y, ty, by);
+                    y[r] = make_float2(fmaf(sgn, bx, tx), fmaf(sgn, by, ty));
+                    if (r > 0) y[r] = cmul(y[r], tw1[r]);
+                }
+                fft_reg<H>(y);
+                wave_sync();  // the previous sample's tile has been read
+#pragma unroll
+                for (int b = 0; b < H; ++b) wt[(2 * b + hh) * SP + c] = y[b];
+                wave_sync();
+                // ---- along m: row c, the same split
+#pragma unroll
+                for (int r = 0; r < H; ++r) {
+                    const float2 t0 = wt[c * SP + r], t1 = wt[c * SP + H + r];
+                    y[r] = make_float2(fmaf(sgn, t1.x, t0.x), fmaf(sgn, t1.y, t0.y));
+                    if (r > 0) y[r] = cmul(y[r], tw1[r]);
+                }
+                fft_reg<H>(y);
+                if constexpr (YLDS) {
+#pragma unroll
+                    for (int b = 0; b < H; ++b) ybuf[b * kBlock + tid] = y[b];
+                }
+            } else if constexpr (YLDS) {
+#pragma unroll
+                for (int b = 0; b < H; ++b) y[b] = ybuf[b * kBlock + tid];
             }
-            fft_reg<H>(y);
-            wave_sync();  // the previous sample's tile has been read
-#pragma unroll
-            for (int b = 0; b < H; ++b) wt[(2 * b + hh) * SP + c] = y[b];
-            wave_sync();
-            // ---- along m: row c, the same split; times the row's l-axis phase
-#pragma unroll
-            for (int r = 0; r < H; ++r) {
-                const float2 t0 = wt[c * SP + r], t1 = wt[c * SP + H + r];
-                y[r] = make_float2(fmaf(sgn, t1.x, t0.x), fmaf(sgn, t1.y, t0.y));
-                if (r > 0) y[r] = cmul(y[r], tw1[r]);
-            }
-            fft_reg<H>(y);
+            // ---- row c times the sample's l-axis phase of the row's index
             const float2 prow = phase(fl, nl_row);
+            wave_sync();  // the tile (the previous sample's, or the transpose) has been read
 #pragma unroll
             for (int b = 0; b < H; ++b) wt[c * SP + 2 * b + hh] = cmul(y[b], prow);
             wave_sync();
-
             // ---- A_k, B_k: sums over l of g_k[n_l][n_m] T[n_l mod 32][c] for
             // n_l below and above 32 - M/2
             float2 A[NV], B[NV];
@@ -414,7 +449,7 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
                 auto seg = [&](int j0, int j1, int b0, float2 (&acc)[NV]) {
                     const float2* tp = wt + b0 * SP + c;
                     const float* g = gp + j0 * m * NG;
-#pragma unroll 4
+#pragma unroll kUnroll
                     for (int jl = j0; jl < j1; ++jl, tp += SP, g += m * NG) {
                         float2 t = *tp;
                         if constexpr (WT) t = cmul(t, wphase(w0, (float)(jl - half_m) * hstep));
@@ -509,17 +544,20 @@ __global__ void __launch_bounds__(64 * W) k_winw(ItemArgs a)
             }
 
             // ---- move on
+            if (need1) {
 #pragma unroll
-            for (int r = 0; r < H; ++r) x0[r] = x1[r];
+                for (int r = 0; r < H; ++r) x0[r] = x1[r];
+            }
+            need0 = need1;
             vin0 = vin1;
             wgt0 = wgt1;
             w0 = w1;
+            pl0 = pl1;
             e0 = e1;
+            f0 = f1;
             e1 = e2;
-            gi0 = gi1;
-            v0 = v1;
-            gi1 = gi2;
-            v1 = v2;
+            f1 = f2;
+            ++k0;
         }
 
         // ---- per-item partial sums: workers added in order
@@ -560,18 +598,28 @@ int win_block_waves(int support, int mode, int frame, int m, int oversample, int
     return 0;
 }
 
-template <int S, int MODE, int MF, int W, bool WT>
-static hipError_t launch_win_w(const ItemArgs& a, hipStream_t s)
+template <int S, int MODE, int MF, int W, bool WT, int MT>
+static hipError_t launch_win_wm(const ItemArgs& a, hipStream_t s)
 {
     // raise the dynamic LDS limit once, to what one compute unit allows
     static const hipError_t attr = hipFuncSetAttribute(
-        (const void*)k_winw<S, MODE, MF, W, WT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (const void*)k_winw<S, MODE, MF, W, WT, MT>, hipFuncAttributeMaxDynamicSharedMemorySize,
         (int)win_lds_budget(S));
     if (attr != hipSuccess) return attr;
-    const int blocks = 8 * ((a.n_items + 7) / 8);
+    const int blocks = (int)item_blocks(a.n_items);
     const size_t sh = winw_frame_lds(S, W, MODE, MF, a.m, a.oversample, a.n_tab);
-    k_winw<S, MODE, MF, W, WT><<<blocks, 64 * W, sh, s>>>(a);
+    k_winw<S, MODE, MF, W, WT, MT><<<blocks, 64 * W, sh, s>>>(a);
     return hipGetLastError();
+}
+
+template <int S, int MODE, int MF, int W, bool WT>
+static hipError_t launch_win_w(const ItemArgs& a, hipStream_t s)
+{
+    // the default image-sample count fixed at compile time: at support 32,
+    // sky frame (1% on the large workload; at 16 it costs registers and 2%)
+    if constexpr (MF == kFrameSky && S == 32)
+        if (a.m == 3 * S / 2) return launch_win_wm<S, MODE, MF, W, WT, 3 * S / 2>(a, s);
+    return launch_win_wm<S, MODE, MF, W, WT, 0>(a, s);
 }
 
 template <int S, int MODE, int MF, bool WT>
@@ -621,8 +669,10 @@ size_t winw_lds_bytes(int support, int waves, int mode, int m, int oversample, i
     const size_t m2p = (size_t)((m * m + 3) & ~3);
     const bool mf = mount_frame_tab >= 0;
     const int ng = win_ng(mode);  // image-plane factors per sample (sky frame)
-    return sizeof(double) * nc * workers + sizeof(Group) * win_max_groups(oversample) +
-           (mf ? 0 : sizeof(float) * ng * m2p) + sizeof(float2) * (size_t)workers * support * (support + 1) +
+    (void)oversample;
+    return sizeof(double) * nc * workers + (mf ? 0 : sizeof(float) * ng * m2p) +
+           sizeof(float2) * (size_t)workers * support * (support + 1) +
+           (support == 16 ? sizeof(float2) * (size_t)(support / 2) * 64 * waves : 0) +
            (mf ? sizeof(float4) * mount_frame_tab : 0);
 }
 

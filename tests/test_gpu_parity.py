@@ -685,7 +685,7 @@ def test_cfg2_full_size_window_form(torch_dev):
         s.close()
 
 
-@pytest.mark.parametrize("what", ["mount_frame", "measured_aperture", "beam_scale", "w_term"])
+@pytest.mark.parametrize("what", ["mount_frame", "measured_aperture", "beam_scale", "w_term", "w_stack"])
 def test_cfg2_full_size_extensions_sampled_rows(torch_dev, what):
     """The extension kernels on the full single-interval array, in the launch
     configuration the bench times them in (360 samples per item, blocks of
@@ -698,12 +698,14 @@ def test_cfg2_full_size_extensions_sampled_rows(torch_dev, what):
     torch = torch_dev
     every = 180 if what == "measured_aperture" else 36
     print(f"case: cfg2 full size, {what}, every {every}th timestep", flush=True)
+    # w_term: the array shrunk to arms of 1 km (one kernel holds the w-term);
+    # w_stack: the array as configured, arms to 21 km (w-stacked)
     obs = synth.make_config(2, layout_radius_m=1000.0) if what == "w_term" else synth.make_config(2)
     times = np.unique(obs.time_idx)[::every]
     rows = np.nonzero(np.isin(obs.time_idx, times))[0]
     sub = obs.subset(times=times)
     kw, okw = dict(mount_frame=True), dict(mount_frame=True)
-    if what == "w_term":
+    if what in ("w_term", "w_stack"):
         kw, okw = dict(w_term=True), dict(w_term=True)
     if what == "measured_aperture":
         A = synth.measured_aperture()
@@ -950,17 +952,93 @@ def test_w_term_predict_gradient_vjp_image(torch_dev, S, over, mount):
         s.close()
 
 
-def test_w_term_beyond_the_support_is_refused(torch_dev):
-    """Baselines to 24 km at support 16: |w| FoV / D near 3 uv cells, more
-    than the support leaves (the window form's error would pass 1e-4)."""
+@pytest.mark.parametrize("S,over,mount", [(16, 4, False), (32, 8, False), (16, 4, True)])
+def test_w_stacking_predict_gradient_vjp_solve(torch_dev, S, over, mount):
+    """Baselines to 24 km: |w| FoV / D up to several uv cells, more than one
+    kernel holds, so the observation is w-stacked (each sample reads the
+    model grid of the w-plane nearest its w and carries the rest in its
+    kernel).  Prediction, gradient sums, the adjoint and Algorithm 1 against
+    the oracle's exact w phase; the image gradient is refused."""
+    torch = torch_dev
     from paper_1709_08681_amd import psc
-    print("case: w-term refused", flush=True)
-    obs = small_ragged_obs(99, layout_radius_m=24000.0)
+    print(f"case: w-stacking, S {S}, O {over}, mount {mount}", flush=True)
+    obs = small_ragged_obs(99, support=S, oversample=over, layout_radius_m=24000.0)
     assert np.abs(obs.w_m).max() * obs.fov / obs.wl.dish_diam_m > 1.5
+    prob = oracle.Problem.from_observation(obs, w_term=True, mount_frame=mount)
+    s = session(obs, w_term=True, mount_frame=mount)
+    try:
+        info = psc.psc_obs_launch_info(s.handle)
+        print(f"w-stacking: {info['w_planes']} planes", flush=True)
+        assert info["w_planes"] > 1
+        v = oracle.predict(prob, obs.offsets_true)
+        vp = s.predict(obs.offsets_true).cpu().numpy()
+        assert rel(vp, v) <= 1e-5 and elem_err(vp, v) <= ELEM_VIS_TOL
+        start = synth.perturbed_offsets(obs, 25.0, 43)
+        nz, w = synth.noise(v, 100.0, 44)
+        ref, vm_ref = oracle.gradient(prob, start, v + nz, w, want_model=True)
+        acc, vm = s.gradient(s.offsets(start), c64(torch, s, v + nz), f32(torch, s, w, s.vis_shape),
+                             want_model=True)
+        vm, acc = vm.cpu().numpy(), acc.cpu().numpy()
+        assert rel(vm, vm_ref) <= 1e-5 and elem_err(vm, vm_ref) <= ELEM_VIS_TOL
+        for k in range(6):
+            assert rel(acc[..., k], ref[..., k]) <= 1e-4, k
+        assert max(per_antenna_err(acc, ref)) <= ANT_SUM_TOL
+        rng = np.random.default_rng(45)
+        G = (rng.normal(size=s.vis_shape) + 1j * rng.normal(size=s.vis_shape)).astype(np.complex64)
+        got = s.vjp(s.offsets(start), torch.as_tensor(G, device=s.dev)).cpu().numpy()
+        assert rel(got, vjp_reference(obs, prob, start, G, s.off_shape)) <= 1e-4
+        ref_off, its_ref = oracle.solve(prob, v + nz, w, start, gain=0.5, n_max=5, tol_rad=1e-3 * ARCSEC)
+        off = s.offsets(start)
+        its = s.solve(c64(torch, s, v + nz), f32(torch, s, w, s.vis_shape), off, gain=0.5, n_max=5,
+                      tol_rad=1e-3 * ARCSEC, form=psc.SOLVE_GRAPH)
+        assert np.array_equal(its.cpu().numpy(), its_ref)
+        assert np.abs(off.cpu().numpy() - ref_off).max() / ARCSEC <= 0.1
+        with pytest.raises(psc.PscError) as ei:
+            s.image_gradient(s.offsets(start), c64(torch, s, v), f32(torch, s, w, s.vis_shape))
+        assert ei.value.status == psc.PSC_E_UNSUPPORTED
+    finally:
+        s.close()
+
+
+def test_w_stacking_follows_the_model(torch_dev):
+    """A w-stacked observation planned before the model is set, then given
+    two different models in turn: its w-planes follow each one."""
+    torch = torch_dev
+    from paper_1709_08681_amd import psc
+    print("case: w-stacking follows psc_set_model", flush=True)
+    obs = small_ragged_obs(98, layout_radius_m=24000.0)
+    s = session(obs, w_term=True)
+    try:
+        assert psc.psc_obs_launch_info(s.handle)["w_planes"] > 1
+        for scale, seed in ((2.0, 0), (0.5, 1)):
+            img = obs.image() * scale
+            # move one source by a pixel, so the models differ in more than scale
+            ix, iy = np.nonzero(img)
+            img[ix[seed] + 1, iy[seed]] = img[ix[seed], iy[seed]]
+            img[ix[seed], iy[seed]] = 0.0
+            psc.psc_set_model(s.ctx, torch.as_tensor(img, device=s.dev))
+            n = obs.grid_n
+            l, m = (np.nonzero(img)[0] - n // 2) * obs.cell_rad, (np.nonzero(img)[1] - n // 2) * obs.cell_rad
+            prob = oracle.Problem(l, m, img[np.nonzero(img)], obs.n_ant, obs.ant1, obs.ant2, obs.uv_m,
+                                  obs.int_row_ptr, obs.freq_hz, n_pol=obs.n_pol,
+                                  dish_diam_m=obs.wl.dish_diam_m, squint_frac=obs.wl.squint_frac,
+                                  snap_scale=obs.snap_scale, w_m=obs.w_m)
+            v = oracle.predict(prob, obs.offsets_true)
+            assert rel(s.predict(obs.offsets_true).cpu().numpy(), v) <= 1e-5
+    finally:
+        s.close()
+
+
+def test_w_stacking_beyond_its_limit_is_refused(torch_dev):
+    """Baselines of 10,000 km: the w-planes would need far more than 2 GiB of
+    model grids; refused, while the same observation without w plans."""
+    from paper_1709_08681_amd import psc
+    print("case: w-stacking refused", flush=True)
+    obs = small_ragged_obs(97, layout_radius_m=1.0e7)
     with pytest.raises(psc.PscError) as ei:
         session(obs, w_term=True)
     assert ei.value.status == psc.PSC_E_UNSUPPORTED
-    session(obs).close()  # the same observation without the w-term
+    session(obs).close()
 
 
 def test_w_term_solve(torch_dev):
