@@ -445,6 +445,47 @@ PSC_API psc_status psc_solve_scale(psc_ctx* ctx, psc_obs* obs, const double* off
                                    const float* weight_dev, double gain, int32_t n_max, double tol,
                                    int32_t* iters_out_dev, void* stream);
 
+/*
+ * Aperture defocus, a complex generalised antenna parameter (Eq. DA with a
+ * complex a_i; Sec. 5.3 names aperture phase terms such as defocus as the
+ * first shape parameters to solve for).  A defocus delta (radians of
+ * aperture phase at the dish rim) multiplies antenna a's illumination by
+ * exp(i delta (r/R)^2), R = D/2, so its pattern is complex:
+ *   uniform disc (illum 0): E = 2 int_0^1 J0(pi D rho t / lambda)
+ *                            exp(i delta t^2) t dt, rho the distance from
+ *                            the beam centre (2 J1(x)/x at delta = 0);
+ *   Gaussian mode (illum 1): E = z exp(-z rho^2 / (2 s^2)), z = 1 / (1 - i
+ *                            kappa), kappa = 2 delta / (pi^2 gauss_sigma_ld^2).
+ * Visibilities carry E_i conj(E_j) (Eq. ME).  Available for illum 0 and 1,
+ * sky-frame offsets, without beam scales; the window form predicts with it.
+ *
+ * psc_set_defocus (sync): defocus_dev [n_int][n_pol][n_ant] float64 device
+ *   array, copied; each value finite with |delta| <= pi (PSC_E_ARG
+ *   otherwise).  NULL removes it (real patterns again).  PSC_E_UNSUPPORTED
+ *   with a measured aperture, parallactic angles or beam scales.  While set,
+ *   psc_predict uses the complex patterns; psc_gradient, psc_gradient_noalloc,
+ *   psc_predict_vjp, psc_image_gradient, psc_solve, psc_tune and the
+ *   beam-scale calls return PSC_E_UNSUPPORTED.
+ * psc_get_defocus (async): copies the current values to defocus_out_dev.
+ * psc_defocus_gradient (async): the Eq. DCHIDD sums for the defocus, per
+ *   (interval, pol, antenna) acc_out_dev[3] = (chi, g = sum Re(conj(R) w
+ *   dV/ddelta_a), H = sum w |dV/ddelta_a|^2) over both ends of every
+ *   baseline, R = V^Obs - V^M, at the given offsets.
+ * psc_defocus_step (async): delta += gain g / H on the device for every
+ *   (interval, pol, antenna) with H > 0 and finite sums whose result stays
+ *   within |delta| <= pi; the others are kept and flagged in
+ *   not_updated_dev (nullable, int32 [n_int][n_pol][n_ant]); max_step_out_dev
+ *   (nullable, [n_int]) gets each interval's largest |step|.  gain in (0, 1].
+ * The three calls after psc_set_defocus return PSC_E_STATE without it.
+ */
+PSC_API psc_status psc_set_defocus(psc_ctx* ctx, psc_obs* obs, const double* defocus_dev, void* stream);
+PSC_API psc_status psc_get_defocus(psc_ctx* ctx, const psc_obs* obs, double* defocus_out_dev, void* stream);
+PSC_API psc_status psc_defocus_gradient(psc_ctx* ctx, psc_obs* obs, const double* offsets_dev,
+                                        const void* vis_obs_dev, const float* weight_dev, double* acc_out_dev,
+                                        void* stream);
+PSC_API psc_status psc_defocus_step(psc_ctx* ctx, psc_obs* obs, const double* acc_dev, double gain,
+                                    int32_t* not_updated_dev, double* max_step_out_dev, void* stream);
+
 /* Execution forms of psc_solve. */
 #define PSC_SOLVE_PLAIN 0    /* host loop over intervals, one launch set per interval */
 #define PSC_SOLVE_BATCHED 1  /* every interval in one launch set per iteration */

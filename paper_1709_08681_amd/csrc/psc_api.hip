@@ -65,6 +65,8 @@ struct psc_obs {
     double fmax = 0;           // highest channel frequency (Hz)
     float4* ap_tab = nullptr;  // measured aperture: pattern table [ap_n][ap_n]
     double* scale = nullptr;   // beam-width scales [n_int][n_pol][n_ant] (null: all 1)
+    double* defocus = nullptr; // aperture defocus [n_int][n_pol][n_ant] (null: none; complex patterns)
+    float2* mtab = nullptr;    // the uniform disc's moment table [n_tab][kMoments] (defocus, illum 0)
     double* zero_pa = nullptr; // [n_row] zeros: the per-sample scatter's angles with scales, sky frame
     int32_t win_waves = 0;     // window-form block size at support 16 (see ItemArgs)
     double plan_ms = 0;        // wall time psc_obs_create took
@@ -430,6 +432,8 @@ PSC_API psc_status psc_obs_destroy(psc_obs* obs)
         v.erase(std::remove(v.begin(), v.end(), obs), v.end());
     }
     dfree(obs->wplanes);
+    dfree(obs->defocus);
+    dfree(obs->mtab);
     dfree(obs->vis);
     dfree(obs->wvis);
     dfree(obs->wf);
@@ -951,6 +955,9 @@ ItemArgs item_args(psc_ctx* ctx, psc_obs* obs, const double* offsets, int item_b
     a.ap_c = (float)obs->ap_c;
     a.ap_inv_step = obs->ap_step > 0 ? (float)(1.0 / obs->ap_step) : 0.f;
     a.scale = obs->scale;
+    a.defocus = obs->defocus;
+    a.mtab = obs->mtab;
+    a.n_mom = kMoments;
     a.win_waves = obs->win_waves;
     a.partials = obs->partials;
     a.done = done;
@@ -983,6 +990,16 @@ psc_status check_call(psc_ctx* ctx, psc_obs* obs, const double* offsets)
     if (!offsets) return fail(ctx, PSC_E_ARG, "null offsets");
     if (!ctx->model_set) return fail(ctx, PSC_E_STATE, "psc_set_model has not been called");
     if (hipSetDevice(ctx->cfg.device) != hipSuccess) return fail(ctx, PSC_E_HIP, "hipSetDevice");
+    return PSC_OK;
+}
+
+// Calls whose kernels take real patterns only: refused while an aperture
+// defocus is set.
+psc_status no_defocus(psc_ctx* ctx, const psc_obs* obs, const char* what)
+{
+    if (obs->defocus)
+        return fail(ctx, PSC_E_UNSUPPORTED,
+                    std::string(what) + ": not available with an aperture defocus set (psc_set_defocus)");
     return PSC_OK;
 }
 
@@ -1046,6 +1063,7 @@ PSC_API psc_status psc_gradient(psc_ctx* ctx, psc_obs* obs, const double* offset
     if (st != PSC_OK) return st;
     if (!acc_out_dev || ((!vis_obs_dev || !weight_dev) && obs->n_vis > 0))
         return fail(ctx, PSC_E_ARG, "null data or output");
+    if ((st = no_defocus(ctx, obs, "psc_gradient")) != PSC_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     ItemArgs a = item_args(ctx, obs, offsets_dev, 0, (int)obs->n_items, nullptr);
     a.vis_in = (const float2*)vis_obs_dev;
@@ -1062,6 +1080,7 @@ PSC_API psc_status psc_gradient_noalloc(psc_ctx* ctx, psc_obs* obs, const double
 {
     psc_status st = check_call(ctx, obs, offsets_dev);
     if (st != PSC_OK) return st;
+    if ((st = no_defocus(ctx, obs, "psc_gradient_noalloc")) != PSC_OK) return st;
     if (!acc_out_dev || ((!vis_obs_dev || !weight_dev) && obs->n_vis > 0))
         return fail(ctx, PSC_E_ARG, "null data or output");
     if ((size_t)obs->n_items * (size_t)obs->n_pol * 12 > kScratchDoubles)
@@ -1088,6 +1107,7 @@ PSC_API psc_status psc_predict_vjp(psc_ctx* ctx, psc_obs* obs, const double* off
 {
     psc_status st = check_call(ctx, obs, offsets_dev);
     if (st != PSC_OK) return st;
+    if ((st = no_defocus(ctx, obs, "psc_predict_vjp")) != PSC_OK) return st;
     if (!grad_offsets_out_dev || (!grad_vis_dev && obs->n_vis > 0))
         return fail(ctx, PSC_E_ARG, "null data or output");
     hipStream_t s = (hipStream_t)stream;
@@ -1145,6 +1165,7 @@ PSC_API psc_status psc_image_gradient(psc_ctx* ctx, psc_obs* obs, const double* 
 {
     psc_status st = check_call(ctx, obs, offsets_dev);
     if (st != PSC_OK) return st;
+    if ((st = no_defocus(ctx, obs, "psc_image_gradient")) != PSC_OK) return st;
     if (!image_grad_out_dev || ((!vis_obs_dev || !weight_dev) && obs->n_vis > 0))
         return fail(ctx, PSC_E_ARG, "null data or output");
     if (obs->w_nk > 0)
@@ -1258,6 +1279,8 @@ PSC_API psc_status psc_set_degrid(psc_obs* obs, int32_t variant)
         return fail(obs->ctx, PSC_E_UNSUPPORTED, "beam-width scales degrid in the window form only");
     if (obs->ap_tab && variant != PSC_DEGRID_WINDOW)
         return fail(obs->ctx, PSC_E_UNSUPPORTED, "a measured aperture degrids in the window form only");
+    if (obs->defocus && variant != PSC_DEGRID_WINDOW)
+        return fail(obs->ctx, PSC_E_UNSUPPORTED, "an aperture defocus degrids in the window form only");
     if (obs->graph) {  // a captured solve graph holds the old kernels
         (void)hipGraphExecDestroy(obs->graph);
         obs->graph = nullptr;
@@ -1305,6 +1328,8 @@ PSC_API psc_status psc_set_beam_scale(psc_ctx* ctx, psc_obs* obs, const double* 
         }
         return PSC_OK;
     }
+    if (obs->defocus)
+        return fail(ctx, PSC_E_UNSUPPORTED, "beam scales and an aperture defocus cannot be set together");
     const size_t n = (size_t)obs->n_int * obs->n_pol * obs->n_ant;
     std::vector<double> h(n);
     PSC_HIP(ctx, hipMemcpyAsync(h.data(), scale_dev, sizeof(double) * n, hipMemcpyDeviceToHost, st));
@@ -1354,6 +1379,7 @@ PSC_API psc_status psc_scale_gradient(psc_ctx* ctx, psc_obs* obs, const double* 
 {
     psc_status st = check_call(ctx, obs, offsets_dev);
     if (st != PSC_OK) return st;
+    if ((st = no_defocus(ctx, obs, "psc_scale_gradient")) != PSC_OK) return st;
     if (!acc_out_dev || ((!vis_obs_dev || !weight_dev) && obs->n_vis > 0))
         return fail(ctx, PSC_E_ARG, "null data or output");
     if (!obs->scale) return fail(ctx, PSC_E_STATE, "no beam scales set (psc_set_beam_scale)");
@@ -1387,6 +1413,7 @@ PSC_API psc_status psc_solve_scale(psc_ctx* ctx, psc_obs* obs, const double* off
 {
     psc_status st = check_call(ctx, obs, offsets_dev);
     if (st != PSC_OK) return st;
+    if ((st = no_defocus(ctx, obs, "psc_solve_scale")) != PSC_OK) return st;
     if ((!vis_obs_dev || !weight_dev) && obs->n_vis > 0) return fail(ctx, PSC_E_ARG, "null data");
     if (!(gain > 0.0) || !(gain <= 1.0)) return fail(ctx, PSC_E_ARG, "gain must be in (0, 1]");
     if (n_max < 0 || !(tol >= 0.0)) return fail(ctx, PSC_E_ARG, "n_max must be >= 0 and tol >= 0");
@@ -1410,11 +1437,118 @@ PSC_API psc_status psc_solve_scale(psc_ctx* ctx, psc_obs* obs, const double* off
     return PSC_OK;
 }
 
+PSC_API psc_status psc_set_defocus(psc_ctx* ctx, psc_obs* obs, const double* defocus_dev, void* stream)
+{
+    if (!ctx) return fail(nullptr, PSC_E_ARG, "null context");
+    ctx->err.clear();
+    if (!obs || obs->ctx != ctx) return fail(ctx, PSC_E_ARG, "observation missing or from another context");
+    PSC_HIP(ctx, hipSetDevice(ctx->cfg.device));
+    hipStream_t st = (hipStream_t)stream;
+    if (!defocus_dev) {  // back to real patterns
+        if (obs->defocus) {
+            PSC_HIP(ctx, hipDeviceSynchronize());  // no launch may still read them
+            dfree(obs->defocus);
+        }
+        return PSC_OK;
+    }
+    if (ctx->cfg.illum == 2 || obs->par_angle || obs->scale)
+        return fail(ctx, PSC_E_UNSUPPORTED, "aperture defocus: uniform disc or Gaussian patterns, sky-frame "
+                                            "offsets and no beam scales only");
+    const size_t n = (size_t)obs->n_int * obs->n_pol * obs->n_ant;
+    std::vector<double> h(n);
+    PSC_HIP(ctx, hipMemcpyAsync(h.data(), defocus_dev, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    PSC_HIP(ctx, hipStreamSynchronize(st));
+    for (size_t k = 0; k < n; ++k)
+        if (!isfinite(h[k]) || fabs(h[k]) > kMaxDefocus)
+            return fail(ctx, PSC_E_ARG, "defocus must be finite and within [-pi, pi] radians");
+    if (ctx->cfg.illum == 0 && !obs->mtab) {
+        // the uniform disc's moments on the Airy table's nodes
+        std::vector<double> gx, gw;
+        gauss_legendre(96, gx, gw);
+        for (size_t q = 0; q < gx.size(); ++q) {
+            gx[q] = 0.5 * (gx[q] + 1.0);
+            gw[q] *= 0.5;
+        }
+        double *dt = nullptr, *dw = nullptr;
+        hipError_t e = dmalloc(&obs->mtab, (size_t)obs->n_tab * kMoments);
+        if (e == hipSuccess) e = dmalloc(&dt, gx.size());
+        if (e == hipSuccess) e = dmalloc(&dw, gw.size());
+        if (e == hipSuccess) e = hipMemcpy(dt, gx.data(), sizeof(double) * gx.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(dw, gw.data(), sizeof(double) * gw.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = launch_moment_table(obs->mtab, obs->n_tab, kMoments, 1.0 / obs->inv_dx, dt, dw, (int)gx.size(), st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        dfree(dt);
+        dfree(dw);
+        if (e != hipSuccess) {
+            dfree(obs->mtab);
+            return hip_fail(ctx, e, "psc_set_defocus: moment table");
+        }
+    }
+    if (!obs->defocus) PSC_HIP(ctx, dmalloc(&obs->defocus, n));
+    PSC_HIP(ctx, hipMemcpyAsync(obs->defocus, defocus_dev, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    PSC_HIP(ctx, hipStreamSynchronize(st));
+    obs->degrid = PSC_DEGRID_WINDOW;
+    if (obs->graph) {  // a captured solve graph holds the old kernels
+        (void)hipGraphExecDestroy(obs->graph);
+        obs->graph = nullptr;
+    }
+    return PSC_OK;
+}
+
+PSC_API psc_status psc_get_defocus(psc_ctx* ctx, const psc_obs* obs, double* defocus_out_dev, void* stream)
+{
+    if (!ctx) return fail(nullptr, PSC_E_ARG, "null context");
+    ctx->err.clear();
+    if (!obs || obs->ctx != ctx || !defocus_out_dev) return fail(ctx, PSC_E_ARG, "null argument");
+    if (!obs->defocus) return fail(ctx, PSC_E_STATE, "no aperture defocus set (psc_set_defocus)");
+    PSC_HIP(ctx, hipSetDevice(ctx->cfg.device));
+    const size_t n = (size_t)obs->n_int * obs->n_pol * obs->n_ant;
+    PSC_HIP(ctx, hipMemcpyAsync(defocus_out_dev, obs->defocus, sizeof(double) * n, hipMemcpyDeviceToDevice,
+                                (hipStream_t)stream));
+    return PSC_OK;
+}
+
+PSC_API psc_status psc_defocus_gradient(psc_ctx* ctx, psc_obs* obs, const double* offsets_dev,
+                                        const void* vis_obs_dev, const float* weight_dev, double* acc_out_dev,
+                                        void* stream)
+{
+    psc_status st = check_call(ctx, obs, offsets_dev);
+    if (st != PSC_OK) return st;
+    if (!acc_out_dev || ((!vis_obs_dev || !weight_dev) && obs->n_vis > 0))
+        return fail(ctx, PSC_E_ARG, "null data or output");
+    if (!obs->defocus) return fail(ctx, PSC_E_STATE, "no aperture defocus set (psc_set_defocus)");
+    hipStream_t s = (hipStream_t)stream;
+    ItemArgs a = item_args(ctx, obs, offsets_dev, 0, (int)obs->n_items, nullptr);
+    a.vis_in = (const float2*)vis_obs_dev;
+    a.weight = weight_dev;
+    // the scale mode's sums (chi, Re(conj(R) w dV/da), w |dV/da|^2 per end)
+    // with the defocus derivatives in place of the scale's
+    PSC_HIP(ctx, launch_win(kScale, ctx->s, a, s));
+    PSC_HIP(ctx, launch_reduce(6, reduce_args(obs, 0, obs->n_int, acc_out_dev, nullptr), s));
+    return PSC_OK;
+}
+
+PSC_API psc_status psc_defocus_step(psc_ctx* ctx, psc_obs* obs, const double* acc_dev, double gain,
+                                    int32_t* not_updated_dev, double* max_step_out_dev, void* stream)
+{
+    if (!ctx) return fail(nullptr, PSC_E_ARG, "null context");
+    ctx->err.clear();
+    if (!obs || obs->ctx != ctx || !acc_dev) return fail(ctx, PSC_E_ARG, "null argument");
+    if (!(gain > 0.0) || !(gain <= 1.0)) return fail(ctx, PSC_E_ARG, "gain must be in (0, 1]");
+    if (!obs->defocus) return fail(ctx, PSC_E_STATE, "no aperture defocus set (psc_set_defocus)");
+    PSC_HIP(ctx, hipSetDevice(ctx->cfg.device));
+    PSC_HIP(ctx, launch_defocus_step(obs->n_int, obs->n_pol, obs->n_ant, acc_dev, gain, obs->defocus,
+                                     not_updated_dev, max_step_out_dev, (hipStream_t)stream));
+    return PSC_OK;
+}
+
 PSC_API psc_status psc_tune(psc_ctx* ctx, psc_obs* obs, const double* offsets_dev, const void* vis_obs_dev,
                             const float* weight_dev, int32_t repeats, double* times_us_out, void* stream)
 {
     psc_status st = check_call(ctx, obs, offsets_dev);
     if (st != PSC_OK) return st;
+    if ((st = no_defocus(ctx, obs, "psc_tune")) != PSC_OK) return st;
     if ((!vis_obs_dev || !weight_dev) && obs->n_vis > 0) return fail(ctx, PSC_E_ARG, "null data");
     if (repeats < 1 || repeats > 1000) return fail(ctx, PSC_E_ARG, "repeats must be in [1, 1000]");
     hipStream_t s = (hipStream_t)stream;
@@ -1460,6 +1594,7 @@ static psc_status solve_impl(psc_ctx* ctx, psc_obs* obs, const void* vis_obs_dev
 {
     psc_status st = check_call(ctx, obs, offsets_io_dev);
     if (st != PSC_OK) return st;
+    if ((st = no_defocus(ctx, obs, "psc_solve")) != PSC_OK) return st;
     if ((!vis_obs_dev || !weight_dev) && obs->n_vis > 0) return fail(ctx, PSC_E_ARG, "null data");
     if (!(gain > 0.0) || !(gain <= 1.0)) return fail(ctx, PSC_E_ARG, "gain must be in (0, 1]");
     if (n_max < 0 || !(tol_rad >= 0.0)) return fail(ctx, PSC_E_ARG, "n_max must be >= 0 and tol_rad >= 0");

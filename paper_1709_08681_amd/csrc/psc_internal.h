@@ -132,6 +132,14 @@ struct ItemArgs {
     // nullable [n_int][n_pol][n_ant]: beam-width scale sigma of each antenna,
     // pattern E0(d / sigma) (per-sample products: mount-frame paths only)
     const double* scale;
+    // nullable [n_int][n_pol][n_ant]: aperture defocus delta of each antenna
+    // (radians of phase at the rim; complex patterns, sky frame): with
+    // illum 0 the pattern is sum_n (i delta)^n / n! M_n(x) from the moment
+    // table mtab [x node][n_mom] (M_n(x) = 2 int_0^1 J0(x t) t^(2n+1) dt,
+    // (value, dx slope) at x = node / 16), with illum 1 a closed form
+    const double* defocus;
+    const float2* mtab;
+    int32_t n_mom;
     // window form at support 16: 1 or 2 for blocks of one or two wavefronts
     // (items of few samples, where four would leave workers idle), 0 to size
     // blocks by LDS alone
@@ -188,6 +196,13 @@ hipError_t launch_scale_step(int n_int, int n_pol, int n_ant, const double* acc3
                              int32_t* not_updated, double* max_step, int32_t* done, int32_t* iters, double tol,
                              double min_scale, hipStream_t s);
 hipError_t launch_zero(double2* p, size_t n, hipStream_t s);
+// Aperture defocus (psc_scale.hip): the uniform disc's moment table, and the
+// damped step delta += gain g / H per (interval, pol, antenna), kept within
+// |delta| <= kMaxDefocus (steps beyond are not taken and flagged).
+hipError_t launch_moment_table(float2* tab, int n_tab, int n_mom, double dx, const double* gl_t, const double* gl_w,
+                               int n_gl, hipStream_t s);
+hipError_t launch_defocus_step(int n_int, int n_pol, int n_ant, const double* acc3, double gain, double* defocus,
+                               int32_t* not_updated, double* max_step, hipStream_t s);
 hipError_t launch_unpad_grid(const double2* g, double2* out, int n, int pad, hipStream_t s);
 hipError_t launch_image_grad(const double2* f, const double* taper_pix, double* out, int n, hipStream_t s);
 hipError_t launch_items(int mode, int support, const ItemArgs& a, hipStream_t s);
@@ -213,6 +228,13 @@ size_t win_lds_budget(int support);
 // given the plan's choice for items of few samples (ItemArgs::win_waves); 0
 // when no block fits.
 constexpr int kFrameSkyAperture = 3;
+// Complex patterns in the sky frame (an aperture phase term): complex
+// image-plane products per image sample, summed plainly.
+constexpr int kFrameSkyComplex = 4;
+// Aperture defocus: moments M_0 .. M_{kMoments-1} of the uniform disc, enough
+// for the pattern's series to 1e-13 at |delta| <= kMaxDefocus.
+constexpr int kMoments = 27;
+constexpr double kMaxDefocus = 3.14159265358979323846;
 int win_block_waves(int support, int mode, int frame, int m, int oversample, int n_tab, int plan_waves);
 // Image-gradient scatter with per-item LDS patches (psc_grid.hip), support
 // 16: one thread per tap, chunks of kGridChunk samples, patches of

@@ -39,7 +39,106 @@ __host__ __device__ constexpr int win_ng(int mode)
 // mode (0: none, the mount frames evaluate them per sample).
 __host__ __device__ constexpr int win_factors(int frame, int mode)
 {
-    return frame == kFrameSky ? win_ng(mode) : frame == kFrameSkyAperture ? mode_nv(mode) : 0;
+    return frame == kFrameSky           ? win_ng(mode)
+           : frame == kFrameSkyAperture ? mode_nv(mode)
+           : frame == kFrameSkyComplex  ? 2 * mode_nv(mode)
+                                        : 0;
+}
+
+// A pattern with aperture defocus delta at displacement (dl, dm) from its
+// beam centre, e = E and, with DERIV, de = dE/ddelta (complex).  Uniform disc:
+// E = sum_n (i delta)^n / n! M_n(x), dE/ddelta = sum_n i^(n+1) delta^n / n!
+// M_{n+1}(x), x = kk rho, M_n from the moment table (cubic Hermite).
+// Gaussian mode: E = z exp(-z rho^2 / (2 s^2)), z = 1 / (1 - i kappa), kappa =
+// kgd delta, dE/ddelta = kgd i z E (1 - z rho^2 / (2 s^2)).
+template <bool DERIV>
+__device__ __forceinline__ void efd(const ItemArgs& a, float kk, float inv_s2, float kgd, float delta, float dl,
+                                    float dm, float2& e, float2& de)
+{
+    const float rho2 = fmaf(dl, dl, dm * dm);
+    if (a.illum == 1) {
+        const float kap = kgd * delta;
+        const float den = __builtin_amdgcn_rcpf(fmaf(kap, kap, 1.f));
+        const float zr = den, zi = kap * den;
+        const float ah = 0.5f * rho2 * inv_s2;
+        const float mag = __expf(-ah * zr);
+        float sn, cs;
+        __sincosf(-ah * zi, &sn, &cs);
+        const float er = mag * cs, ei = mag * sn;
+        e = make_float2(zr * er - zi * ei, zr * ei + zi * er);
+        if (DERIV) {
+            const float tr = fmaf(-ah, zr, 1.f), ti = -ah * zi;
+            const float ur = zr * e.x - zi * e.y, ui = zr * e.y + zi * e.x;
+            const float vr = ur * tr - ui * ti, vi = ur * ti + ui * tr;
+            de = make_float2(-vi * kgd, vr * kgd);
+        }
+        return;
+    }
+    const float x = kk * __builtin_amdgcn_sqrtf(rho2);
+    const float xs = x * a.inv_dx;
+    int i0 = (int)xs;
+    i0 = i0 < a.n_tab - 2 ? i0 : a.n_tab - 2;
+    const float u = fminf(xs - (float)i0, 1.f);
+    const float u1 = 1.f - u;
+    const float h00 = (1.f + 2.f * u) * u1 * u1, h10 = u * u1 * u1, h01 = u * u * (3.f - 2.f * u),
+                h11 = u * u * (u - 1.f);
+    const float2* r0 = a.mtab + (size_t)i0 * kMoments;
+    const float2* r1 = r0 + kMoments;
+    float er = 0.f, ei = 0.f, dr = 0.f, di = 0.f, coef = 1.f;
+    float mn;
+    {
+        const float2 p0 = r0[0], p1 = r1[0];
+        mn = fmaf(h00, p0.x, fmaf(h10, p0.y, fmaf(h01, p1.x, h11 * p1.y)));
+    }
+#pragma unroll
+    for (int n = 0; n < kMoments - 1; ++n) {
+        const float2 p0 = r0[n + 1], p1 = r1[n + 1];
+        const float mn1 = fmaf(h00, p0.x, fmaf(h10, p0.y, fmaf(h01, p1.x, h11 * p1.y)));
+        // (i delta)^n / n! = i^n coef: the powers of i cycle 1, i, -1, -i
+        switch (n & 3) {
+        case 0: er = fmaf(coef, mn, er); if (DERIV) di = fmaf(coef, mn1, di); break;
+        case 1: ei = fmaf(coef, mn, ei); if (DERIV) dr = fmaf(-coef, mn1, dr); break;
+        case 2: er = fmaf(-coef, mn, er); if (DERIV) di = fmaf(-coef, mn1, di); break;
+        default: ei = fmaf(-coef, mn, ei); if (DERIV) dr = fmaf(coef, mn1, dr); break;
+        }
+        coef *= delta * (1.f / (float)(n + 1));
+        mn = mn1;
+    }
+    e = make_float2(er, ei);
+    if (DERIV) de = make_float2(dr, di);
+}
+
+// Image-plane products of an item with complex patterns (aperture defocus,
+// sky frame), [n][2 NV] (re, im): g = E_i conj(E_j) c, and for the defocus
+// sums dE_i/ddelta_i conj(E_j) c and E_i conj(dE_j/ddelta_j) c.
+template <int MODE>
+__device__ __forceinline__ void image_factors_cx(const ItemArgs& a, float* gsh, float kk, float inv_s2, float kgd,
+                                                 float di, float dj, float pil, float pim, float pjl, float pjm,
+                                                 int tid, int nthr)
+{
+    constexpr bool D = MODE == kScale;
+    constexpr int NG = 2 * mode_nv(MODE);
+    const int m = a.m, half_m = m >> 1, m2 = m * m;
+    const float hstep = (float)a.h;
+    for (int idx = tid; idx < m2; idx += nthr) {
+        const int il = idx / m, im = idx - il * m;
+        const float l = (float)(il - half_m) * hstep, mm = (float)(im - half_m) * hstep;
+        const float c = a.taper_img[il] * a.taper_img[im];
+        float2 ei, dei, ej, dej;
+        efd<D>(a, kk, inv_s2, kgd, di, l - pil, mm - pim, ei, dei);
+        efd<D>(a, kk, inv_s2, kgd, dj, l - pjl, mm - pjm, ej, dej);
+        float* gn = gsh + idx * NG;
+        // x conj(y) c
+        auto xcy = [&](float2 x, float2 y, float* o) {
+            o[0] = c * fmaf(x.x, y.x, x.y * y.y);
+            o[1] = c * fmaf(x.y, y.x, -x.x * y.y);
+        };
+        xcy(ei, ej, gn);
+        if constexpr (D) {
+            xcy(dei, ej, gn + 2);
+            xcy(ei, dej, gn + 4);
+        }
+    }
 }
 
 // Image-plane factors of an item at the M x M samples, [n][NG]: g = E_i E_j c
@@ -169,9 +268,10 @@ __global__ void __launch_bounds__(64 * W, S == 16 && MF == kFrameMount ? 3 : 1) 
     constexpr int NV = mode_nv(MODE);
     constexpr int NC = mode_nc(MODE);
     constexpr int NCP = NC > 0 ? NC : 1;
-    constexpr bool SKY = MF == kFrameSky || MF == kFrameSkyAperture;  // factors stored per image sample
+    constexpr bool CPLX = MF == kFrameSkyComplex;  // complex patterns: complex products
+    constexpr bool SKY = MF == kFrameSky || MF == kFrameSkyAperture || CPLX;  // factors stored per image sample
     // one stored factor per variant, summed plainly (no factored derivatives)
-    constexpr bool PLAIN = MODE == kScale || MF == kFrameSkyAperture;
+    constexpr bool PLAIN = MODE == kScale || MF == kFrameSkyAperture || CPLX;
     constexpr int NG = SKY ? win_factors(MF, MODE) : 1;  // image-plane factors per image sample
     constexpr int kBlock = 64 * W;
     static_assert(NC <= SL, "one term per lane");
@@ -338,9 +438,15 @@ __global__ void __launch_bounds__(64 * W, S == 16 && MF == kFrameMount ? 3 : 1) 
             bki = beam_k(kk, inv_s2, aps, (float)sc[it.ai]);
             bkj = beam_k(kk, inv_s2, aps, (float)sc[it.aj]);
         }
-        if constexpr (SKY)
+        if constexpr (CPLX) {
+            const double* dfp = a.defocus + ((size_t)it.interval * a.n_pol + pol) * a.n_ant;
+            const float kgd = (float)(2.0 / (kPi * kPi * a.gauss_sigma_ld * a.gauss_sigma_ld));
+            image_factors_cx<MODE>(a, gsh, kk, inv_s2, kgd, (float)dfp[it.ai], (float)dfp[it.aj], (float)qil,
+                                   (float)qim, (float)qjl, (float)qjm, tid, kBlock);
+        } else if constexpr (SKY) {
             image_factors<MODE, MF == kFrameSkyAperture, S == 32>(a, gsh, bki, bkj, (float)qil, (float)qim,
                                                                    (float)qjl, (float)qjm, tid, kBlock);
+        }
         __syncthreads();
 
         double acc64 = 0.0;
@@ -453,7 +559,15 @@ __global__ void __launch_bounds__(64 * W, S == 16 && MF == kFrameMount ? 3 : 1) 
                     for (int jl = j0; jl < j1; ++jl, tp += SP, g += m * NG) {
                         float2 t = *tp;
                         if constexpr (WT) t = cmul(t, wphase(w0, (float)(jl - half_m) * hstep));
-                        if constexpr (PLAIN) {
+                        if constexpr (CPLX) {
+                            // one plain sum per variant, complex products
+#pragma unroll
+                            for (int k = 0; k < NV; ++k) {
+                                const float gr = g[2 * k], gi = g[2 * k + 1];
+                                acc[k].x = fmaf(gr, t.x, fmaf(-gi, t.y, acc[k].x));
+                                acc[k].y = fmaf(gr, t.y, fmaf(gi, t.x, acc[k].y));
+                            }
+                        } else if constexpr (PLAIN) {
                             // one plain sum per variant
 #pragma unroll
                             for (int k = 0; k < NV; ++k) {
@@ -580,7 +694,10 @@ static size_t winw_frame_lds(int support, int waves, int mode, int frame, int m,
     const size_t m2p = (size_t)((m * m + 3) & ~3);
     const int tab = frame == kFrameMount ? n_tab : frame == kFrameSky ? -1 : 0;
     size_t b = winw_lds_bytes(support, waves, mode, m, oversample, tab);
-    if (frame == kFrameSkyAperture) b += sizeof(float) * (size_t)win_factors(frame, mode) * m2p;
+    // frames with stored products other than the radial factors: the base
+    // size counts none (tab = 0), so all of them are added here
+    if (frame == kFrameSkyAperture || frame == kFrameSkyComplex)
+        b += sizeof(float) * (size_t)win_factors(frame, mode) * m2p;
     return b;
 }
 
@@ -598,6 +715,24 @@ int win_block_waves(int support, int mode, int frame, int m, int oversample, int
     return 0;
 }
 
+// The dynamic LDS a k_winw<S, MODE, MF, W> block lays out (the kernel's own
+// arithmetic): float64 sums, stored products, tiles, the transform kept for
+// reuse, the Airy table.  A launch whose allocation is smaller is refused.
+template <int S, int MODE, int MF, int W>
+static size_t winw_layout_bytes(int m, int n_tab)
+{
+    constexpr int NW = W * (64 / (2 * S));
+    constexpr int NC = mode_nc(MODE);
+    constexpr bool SKY = MF == kFrameSky || MF == kFrameSkyAperture || MF == kFrameSkyComplex;
+    const size_t m2p = (size_t)((m * m + 3) & ~3);
+    size_t b = sizeof(double) * NW * (NC > 0 ? NC : 1);
+    b += SKY ? sizeof(float) * (size_t)win_factors(MF, MODE) * m2p : 0;
+    b += sizeof(float2) * (size_t)NW * S * (S + 1);
+    b += S == 16 ? sizeof(float2) * (size_t)(S / 2) * 64 * W : 0;
+    b += MF == kFrameMount ? sizeof(float4) * (size_t)n_tab : 0;
+    return b;
+}
+
 template <int S, int MODE, int MF, int W, bool WT, int MT>
 static hipError_t launch_win_wm(const ItemArgs& a, hipStream_t s)
 {
@@ -608,6 +743,7 @@ static hipError_t launch_win_wm(const ItemArgs& a, hipStream_t s)
     if (attr != hipSuccess) return attr;
     const int blocks = (int)item_blocks(a.n_items);
     const size_t sh = winw_frame_lds(S, W, MODE, MF, a.m, a.oversample, a.n_tab);
+    if (sh < winw_layout_bytes<S, MODE, MF, W>(a.m, a.n_tab)) return hipErrorInvalidValue;
     k_winw<S, MODE, MF, W, WT, MT><<<blocks, 64 * W, sh, s>>>(a);
     return hipGetLastError();
 }
@@ -645,6 +781,13 @@ template <int S, int MODE>
 static hipError_t launch_win_m(const ItemArgs& a, hipStream_t s)
 {
     const bool wt = a.w_m != nullptr;
+    if (a.defocus != nullptr) {
+        // complex patterns: prediction, and the defocus sums (the scale mode's terms)
+        if constexpr (MODE == kPredict || MODE == kScale)
+            return wt ? launch_win_t<S, MODE, kFrameSkyComplex, true>(a, s)
+                      : launch_win_t<S, MODE, kFrameSkyComplex, false>(a, s);
+        return hipErrorInvalidValue;
+    }
     if (a.ap_tab != nullptr && a.par_angle != nullptr)
         return wt ? launch_win_t<S, MODE, kFrameAperture, true>(a, s)
                   : launch_win_t<S, MODE, kFrameAperture, false>(a, s);

@@ -30,7 +30,8 @@ EXPORTS = ["psc_version", "psc_create", "psc_destroy", "psc_last_error", "psc_se
            "psc_obs_create", "psc_obs_destroy", "psc_obs_info", "psc_obs_launch_info", "psc_predict",
            "psc_gradient", "psc_gradient_noalloc", "psc_predict_vjp", "psc_solve_step", "psc_solve", "psc_set_degrid", "psc_get_degrid",
            "psc_tune", "psc_image_gradient", "psc_set_beam_scale", "psc_get_beam_scale",
-           "psc_scale_gradient", "psc_scale_step", "psc_solve_scale"]
+           "psc_scale_gradient", "psc_scale_step", "psc_solve_scale", "psc_set_defocus", "psc_get_defocus",
+           "psc_defocus_gradient", "psc_defocus_step"]
 
 
 class PscError(RuntimeError):
@@ -103,6 +104,10 @@ def load():
             "psc_scale_gradient": ([vp, vp, vp, vp, vp, vp, vp], C.c_int),
             "psc_scale_step": ([vp, vp, vp, dbl, vp, vp, vp], C.c_int),
             "psc_solve_scale": ([vp, vp, vp, vp, vp, dbl, i32, dbl, vp, vp], C.c_int),
+            "psc_set_defocus": ([vp, vp, vp, vp], C.c_int),
+            "psc_get_defocus": ([vp, vp, vp, vp], C.c_int),
+            "psc_defocus_gradient": ([vp, vp, vp, vp, vp, vp, vp], C.c_int),
+            "psc_defocus_step": ([vp, vp, vp, dbl, vp, vp, vp], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -249,6 +254,24 @@ def psc_solve_scale(ctx, obs, offsets_dev, vis_obs_dev, weight_dev, gain, n_max,
                     stream=None):
     _check(load().psc_solve_scale(ctx, obs, _ptr(offsets_dev), _ptr(vis_obs_dev), _ptr(weight_dev), float(gain),
                                   int(n_max), float(tol), _ptr(iters_dev), _stream(stream)), ctx)
+
+
+def psc_set_defocus(ctx, obs, defocus_dev, stream=None):
+    _check(load().psc_set_defocus(ctx, obs, _ptr(defocus_dev), _stream(stream)), ctx)
+
+
+def psc_get_defocus(ctx, obs, defocus_out_dev, stream=None):
+    _check(load().psc_get_defocus(ctx, obs, _ptr(defocus_out_dev), _stream(stream)), ctx)
+
+
+def psc_defocus_gradient(ctx, obs, offsets_dev, vis_obs_dev, weight_dev, acc_out_dev, stream=None):
+    _check(load().psc_defocus_gradient(ctx, obs, _ptr(offsets_dev), _ptr(vis_obs_dev), _ptr(weight_dev),
+                                       _ptr(acc_out_dev), _stream(stream)), ctx)
+
+
+def psc_defocus_step(ctx, obs, acc_dev, gain, not_updated_dev=None, max_step_dev=None, stream=None):
+    _check(load().psc_defocus_step(ctx, obs, _ptr(acc_dev), float(gain), _ptr(not_updated_dev),
+                                   _ptr(max_step_dev), _stream(stream)), ctx)
 
 
 def psc_tune(ctx, obs, offsets_dev, vis_obs_dev, weight_dev, repeats=3, stream=None):
@@ -415,6 +438,34 @@ class Session:
         its = torch.zeros(self.obs.n_int, dtype=torch.int32, device=self.dev)
         psc_solve_scale(self.ctx, self.handle, off, vis_obs, weight, gain, n_max, tol, its)
         return its
+
+    def set_defocus(self, defocus):
+        """Every antenna's aperture defocus [n_int, n_pol, n_ant] (radians at
+        the rim), or None for real patterns again."""
+        if defocus is None:
+            psc_set_defocus(self.ctx, self.handle, None)
+            return
+        d = self.tensor(np.array(np.broadcast_to(defocus, self.off_shape[:3])), self.torch.float64)
+        psc_set_defocus(self.ctx, self.handle, d)
+
+    def defocus(self):
+        out = self.torch.empty(self.off_shape[:3], dtype=self.torch.float64, device=self.dev)
+        psc_get_defocus(self.ctx, self.handle, out)
+        return out
+
+    def defocus_gradient(self, offsets, vis_obs, weight):
+        torch = self.torch
+        off = offsets if isinstance(offsets, torch.Tensor) else self.offsets(offsets)
+        acc = torch.empty(self.off_shape[:3] + (3,), dtype=torch.float64, device=self.dev)
+        psc_defocus_gradient(self.ctx, self.handle, off, vis_obs, weight, acc)
+        return acc
+
+    def defocus_step(self, acc, gain=0.5):
+        torch = self.torch
+        nu = torch.empty(self.off_shape[:3], dtype=torch.int32, device=self.dev)
+        mx = torch.empty(self.obs.n_int, dtype=torch.float64, device=self.dev)
+        psc_defocus_step(self.ctx, self.handle, acc, gain, nu, mx)
+        return nu, mx
 
     def image_gradient(self, offsets, vis_obs, weight):
         """d chi^2 / d I on the model grid, [N][N] float64."""

@@ -1592,3 +1592,118 @@ def test_solve_beam_scale(torch_dev):
         assert np.abs(got - truth).max() <= 5e-4
     finally:
         s.close()
+
+
+# ---------------------------------------------------------------------------
+# aperture defocus: a complex generalised antenna parameter
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("S,over,illum", [(16, 4, 0), (16, 4, 1), (32, 8, 0)])
+def test_defocus_predict_sums_step(torch_dev, S, over, illum):
+    """Aperture defocus per (interval, pol, antenna) (Eq. DA with complex
+    a_i; Sec. 5.3): complex patterns E_i conj(E_j) in the window form against
+    the oracle (uniform disc by its Hankel quadrature, Gaussian aperture in
+    closed form): prediction, the defocus sums, the damped step, five rounds of
+    sums + step, back to real patterns, and the calls refused meanwhile."""
+    torch = torch_dev
+    from paper_1709_08681_amd import psc
+    print(f"case: defocus, S {S}, O {over}, illum {illum}", flush=True)
+    obs = small_ragged_obs(77, support=S, oversample=over)
+    kw = dict(illum=1, gauss_sigma_ld=1.5) if illum == 1 else {}
+    prob = oracle.Problem.from_observation(obs, **kw)
+    s = session(obs, **kw)
+    rng = np.random.default_rng(78)
+    truth = rng.uniform(-0.8, 0.8, s.off_shape[:3])
+    start = truth + rng.normal(0.0, 0.1, truth.shape)
+    try:
+        with pytest.raises(psc.PscError) as ei:
+            s.defocus()
+        assert ei.value.status == psc.PSC_E_STATE
+        psc.psc_set_degrid(s.handle, psc.DEGRID_WINDOW)  # as with the defocus set
+        v_real = s.predict(obs.offsets_true).cpu().numpy()
+        s.set_defocus(truth)
+        assert np.array_equal(s.defocus().cpu().numpy(), truth)
+        v_ref, _ = oracle.predict_defocus(prob, obs.offsets_true, truth)
+        vp = s.predict(obs.offsets_true).cpu().numpy()
+        e_v = rel(vp, v_ref)
+        print(f"defocus predict rel {e_v:.2e}, effect {rel(v_real, v_ref):.2e}", flush=True)
+        assert e_v <= 1e-5 and elem_err(vp, v_ref) <= ELEM_VIS_TOL
+        assert rel(v_real, v_ref) > 1e-3  # the defocus matters here
+        # sums at a perturbed defocus, data from the truth with noise
+        nz, w = synth.noise(v_ref, 100.0, 79)
+        s.set_defocus(start)
+        off = s.offsets(obs.offsets_true)
+        acc = s.defocus_gradient(off, c64(torch, s, v_ref + nz), f32(torch, s, w, s.vis_shape)).cpu().numpy()
+        ref = oracle.defocus_gradient(prob, obs.offsets_true, start, v_ref + nz, w)
+        e_a = [rel(acc[..., k], ref[..., k]) for k in range(3)]
+        print(f"defocus sums rel {max(e_a):.2e}", flush=True)
+        assert max(e_a) <= 1e-4
+        # the step on the oracle's own sums
+        nu, mx = s.defocus_step(torch.as_tensor(ref, device=s.dev), 0.5)
+        d_ref, nu_ref, mx_ref = oracle.defocus_step(ref, 0.5, start)
+        np.testing.assert_allclose(s.defocus().cpu().numpy(), d_ref, rtol=0, atol=1e-12)
+        assert np.array_equal(nu.cpu().numpy(), nu_ref)
+        np.testing.assert_allclose(mx.cpu().numpy(), mx_ref, rtol=1e-12)
+        # five rounds of sums + step on each side
+        s.set_defocus(start)
+        d_o = start.copy()
+        vo = c64(torch, s, v_ref + nz)
+        wt = f32(torch, s, w, s.vis_shape)
+        for _ in range(5):
+            s.defocus_step(s.defocus_gradient(off, vo, wt), 0.5)
+            d_o, _, _ = oracle.defocus_step(oracle.defocus_gradient(prob, obs.offsets_true, d_o, v_ref + nz, w),
+                                            0.5, d_o)
+        d_g = s.defocus().cpu().numpy()
+        print(f"defocus after 5 rounds: {np.abs(d_g - d_o).max():.2e} rad from the oracle's", flush=True)
+        assert np.abs(d_g - d_o).max() <= 1e-5
+        # the calls that take real patterns only are refused meanwhile
+        for call in (lambda: s.gradient(off, vo, wt), lambda: s.vjp(off, vo),
+                     lambda: s.solve(vo, wt, s.offsets(obs.offsets_true), n_max=1)):
+            with pytest.raises(psc.PscError) as ei:
+                call()
+            assert ei.value.status == psc.PSC_E_UNSUPPORTED
+        with pytest.raises(psc.PscError) as ei:
+            s.set_defocus(np.full(s.off_shape[:3], 3.2))
+        assert ei.value.status == psc.PSC_E_ARG
+        s.set_defocus(None)
+        assert np.array_equal(s.predict(obs.offsets_true).cpu().numpy(), v_real)
+    finally:
+        s.close()
+
+
+def test_defocus_full_size_sampled_rows(torch_dev):
+    """Aperture defocus on the full single-interval array (360 samples per
+    item, four-wavefront blocks): the model of every 36th timestep and the
+    defocus sums with the weights zero elsewhere, against the oracle on those
+    rows."""
+    torch = torch_dev
+    every = 36
+    print(f"case: cfg2 full size, defocus, every {every}th timestep", flush=True)
+    obs = synth.make_config(2)
+    times = np.unique(obs.time_idx)[::every]
+    rows = np.nonzero(np.isin(obs.time_idx, times))[0]
+    sub = obs.subset(times=times)
+    prob = oracle.Problem.from_observation(sub)
+    s = session(obs)
+    try:
+        rng = np.random.default_rng(80)
+        truth = rng.uniform(-1.0, 1.0, s.off_shape[:3])
+        start = truth + rng.normal(0.0, 0.1, truth.shape)
+        v_sub, _ = oracle.predict_defocus(prob, obs.offsets_true, truth)
+        s.set_defocus(start)
+        vp = s.predict(obs.offsets_true).cpu().numpy()[rows]
+        vp_ref, _ = oracle.predict_defocus(prob, obs.offsets_true, start)
+        vobs = np.zeros(s.vis_shape, np.complex128)
+        vobs[rows] = v_sub
+        w = np.zeros(s.vis_shape)
+        w[rows] = 1.0
+        acc = s.defocus_gradient(s.offsets(obs.offsets_true), c64(torch, s, vobs),
+                                 f32(torch, s, w, s.vis_shape)).cpu().numpy()
+        ref = oracle.defocus_gradient(prob, obs.offsets_true, start, v_sub, 1.0)
+        e_v, e_el = rel(vp, vp_ref), elem_err(vp, vp_ref)
+        e_a = [rel(acc[..., k], ref[..., k]) for k in range(3)]
+        print(f"cfg2 defocus: vis rel {e_v:.2e}, max element {e_el:.2e}, sums rel {max(e_a):.2e}", flush=True)
+        assert e_v <= 1e-5 and e_el <= ELEM_VIS_TOL
+        assert max(e_a) <= 1e-4
+    finally:
+        s.close()
