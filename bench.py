@@ -289,7 +289,10 @@ def extension_timing(cfg, reps, what):
                          per image sample;
       w_stack            the array as configured (arms to 21 km) with its w:
                          w-stacked model grids, each sample's residual w in
-                         its kernel."""
+                         its kernel;
+      defocus            psc_defocus_gradient: the sums for an aperture
+                         defocus per antenna (within 0.5 rad), complex
+                         patterns of the uniform disc."""
     import torch
     from paper_1709_08681_amd import psc as P
     from paper_1709_08681_amd import synth
@@ -300,7 +303,8 @@ def extension_timing(cfg, reps, what):
           "measured_aperture_sky": dict(aperture=synth.measured_aperture()),
           "beam_scale": dict(mount_frame=True),
           "w_term": dict(w_term=True),
-          "w_stack": dict(w_term=True)}[what]
+          "w_stack": dict(w_term=True),
+          "defocus": {}}[what]
     s = P.Session(obs, device=0, **kw)
     try:
         stream = torch.cuda.current_stream()
@@ -311,6 +315,10 @@ def extension_timing(cfg, reps, what):
             s.set_beam_scale(np.random.default_rng(0).uniform(0.97, 1.03, s.off_shape[:3]))
             acc = torch.empty(s.off_shape[:3] + (3,), dtype=torch.float64, device=s.dev)
             call = lambda: P.psc_scale_gradient(s.ctx, s.handle, off, v, w, acc, stream)
+        elif what == "defocus":
+            s.set_defocus(np.random.default_rng(0).uniform(-0.5, 0.5, s.off_shape[:3]))
+            acc = torch.empty(s.off_shape[:3] + (3,), dtype=torch.float64, device=s.dev)
+            call = lambda: P.psc_defocus_gradient(s.ctx, s.handle, off, v, w, acc, stream)
         else:
             if what in ("w_term", "w_stack"):
                 P.psc_set_degrid(s.handle, P.DEGRID_WINDOW)
@@ -518,7 +526,7 @@ def main():
         out["large_share"] = large_share_extra(args.large_channels, args.large_iters)
         out["extensions"] = {}
         for what in ("mount_frame", "measured_aperture", "measured_aperture_sky", "beam_scale", "w_term",
-                     "w_stack"):
+                     "w_stack", "defocus"):
             print(f"bench: {what}", file=sys.stderr, flush=True)
             out["extensions"][what] = extension_timing(2, 3, what)
     if not args.no_cpu_baseline:

@@ -190,8 +190,9 @@ __device__ __forceinline__ void image_factors(const ItemArgs& a, float* gsh, con
 
 // Cross-half exchanges without the LDS crossbar.  v_permlane32_swap(v, v)
 // returns (lanes 0-31 of v in both halves, lanes 32-63 of v in both halves);
-// v_permlane16_swap(v, v) returns (rows 0 and 2 of v, each in its own and the
-// next row; rows 1 and 3 likewise), so the sum of its two results is the sum
+// v_permlane16_swap(a, b) swaps the odd 16-lane rows of a with the even rows
+// of b: it returns (a's rows 0 and 2 each followed by b's, a's rows 1 and 3
+// each followed by b's), so with a = b the sum of its two results is the sum
 // of lane l and lane l ^ 16.
 __device__ __forceinline__ void halves32(float v, float& lo, float& hi)
 {
@@ -200,18 +201,31 @@ __device__ __forceinline__ void halves32(float v, float& lo, float& hi)
     lo = __builtin_bit_cast(float, (unsigned)r[0]);
     hi = __builtin_bit_cast(float, (unsigned)r[1]);
 }
-__device__ __forceinline__ float sum_xor16(float v)
+// Sums over the 2S lanes of a worker of two values at once, each total in
+// every lane of the worker.  One row swap pairs a's and b's partial sums of
+// the two (at support 32: four) 16-lane rows so that the rows hold a and b
+// alternately; one 16-lane reduction then serves both values, and a last
+// swap hands each row the other's total.  Seven instructions for two values
+// at support 16 against six for each one alone.
+template <int S>
+__device__ __forceinline__ void worker_sum2(float& a, float& b)
 {
-    const unsigned u = __builtin_bit_cast(unsigned, v);
-    const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
-    return __builtin_bit_cast(float, (unsigned)r[0]) + __builtin_bit_cast(float, (unsigned)r[1]);
+    const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, a),
+                                                    __builtin_bit_cast(unsigned, b), false, false);
+    // rows (a0 + a1, b0 + b1, a2 + a3, b2 + b3)
+    float p = __builtin_bit_cast(float, (unsigned)r[0]) + __builtin_bit_cast(float, (unsigned)r[1]);
+    if constexpr (S == 32) {
+        float lo, hi;
+        halves32(p, lo, hi);
+        p = lo + hi;
+    }
+    p = row16_sum(p);
+    const auto q = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, p),
+                                                    __builtin_bit_cast(unsigned, p), false, false);
+    a = __builtin_bit_cast(float, (unsigned)q[0]);
+    b = __builtin_bit_cast(float, (unsigned)q[1]);
 }
-__device__ __forceinline__ float sum_xor32(float v)
-{
-    float lo, hi;
-    halves32(v, lo, hi);
-    return lo + hi;
-}
+
 // The two halves of a worker of 2S lanes: (value of lane (0, c), value of
 // lane (1, c)) in every lane (h, c).
 template <int S>
@@ -625,16 +639,7 @@ __global__ void __launch_bounds__(64 * W, S == 16 && MF == kFrameMount ? 3 : 1) 
                 }
             }
 #pragma unroll
-            for (int k = 0; k < NV; ++k) {
-                s[k].x = row16_sum(s[k].x);
-                s[k].y = row16_sum(s[k].y);
-                s[k].x = sum_xor16(s[k].x);
-                s[k].y = sum_xor16(s[k].y);
-                if constexpr (SL == 64) {
-                    s[k].x = sum_xor32(s[k].x);
-                    s[k].y = sum_xor32(s[k].y);
-                }
-            }
+            for (int k = 0; k < NV; ++k) worker_sum2<S>(s[k].x, s[k].y);
             if constexpr (MF == kFrameMount && MODE != kPredict && MODE != kScale) {
                 // derivatives with respect to the mount-frame offsets
                 constexpr int d0 = (MODE == kGrad) ? 1 : 0;
