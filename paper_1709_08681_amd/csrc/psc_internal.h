@@ -144,6 +144,7 @@ struct ItemArgs {
     // (items of few samples, where four would leave workers idle), 0 to size
     // blocks by LDS alone
     int32_t win_waves;
+    int32_t tab_lds;            // window form: the Airy table is staged in LDS (set by the launcher)
     int32_t use_mfma;           // degrid on the matrix cores (gradient and adjoint)
     // image-gradient scatter (k_grid)
     const uint2* ig_ord;        // per item, its samples in time order: (sample index, sub-table slot)

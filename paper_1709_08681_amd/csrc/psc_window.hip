@@ -150,14 +150,18 @@ __device__ __forceinline__ void image_factors_cx(const ItemArgs& a, float* gsh, 
 // width scale applied).  HW: the hardware square root in the beam lookups
 // (2.6% faster at support 32, 16% slower at 16).
 template <int MODE, bool AP, bool HW>
-__device__ __forceinline__ void image_factors(const ItemArgs& a, float* gsh, const BeamK& bi, const BeamK& bj,
-                                              float pil, float pim, float pjl, float pjm, int tid, int nthr)
+__device__ __forceinline__ void image_factors(const ItemArgs& a, const float4* tab, float* gsh, const BeamK& bi,
+                                              const BeamK& bj, float pil, float pim, float pjl, float pjm, int tid,
+                                              int nthr)
 {
     constexpr int NG = AP ? mode_nv(MODE) : win_ng(MODE);
     const int m = a.m, half_m = m >> 1, m2 = m * m;
     const float hstep = (float)a.h;
+    const float inv_m = 1.f / (float)m;
     for (int idx = tid; idx < m2; idx += nthr) {
-        const int il = idx / m, im = idx - il * m;
+        // idx / m without an integer division: (idx + 1/2) / m lies at least
+        // 1/(2m) from an integer, far beyond the float product's error
+        const int il = (int)(((float)idx + 0.5f) * inv_m), im = idx - il * m;
         const float l = (float)(il - half_m) * hstep, mm = (float)(im - half_m) * hstep;
         const float dli = l - pil, dmi = mm - pim, dlj = l - pjl, dmj = mm - pjm;
         const float c = a.taper_img[il] * a.taper_img[im];
@@ -170,8 +174,8 @@ __device__ __forceinline__ void image_factors(const ItemArgs& a, float* gsh, con
             for (int k = 0; k < NG; ++k) gn[k] = g[k];
         } else {
             float ei, qi, ej, qj;
-            efq<HW>(a, a.airy, bi.kk, bi.inv_s2, dli, dmi, ei, qi);
-            efq<HW>(a, a.airy, bj.kk, bj.inv_s2, dlj, dmj, ej, qj);
+            efq<HW>(a, tab, bi.kk, bi.inv_s2, dli, dmi, ei, qi);
+            efq<HW>(a, tab, bj.kk, bj.inv_s2, dlj, dmj, ej, qj);
             if constexpr (MODE == kPredict) {
                 gn[0] = ei * ej * c;
             } else if constexpr (MODE == kScale) {
@@ -329,7 +333,11 @@ __global__ void __launch_bounds__(64 * W, S == 16 && MF == kFrameMount ? 3 : 1) 
         (void*)(stacked ? a.wgrid : a.grid), (short)0, (stacked ? a.w_nk : 1) * plane_bytes, 0x00020000);
 
     for (int t = tid; t < so; t += kBlock) twsh[t] = a.tw[t];
-    if constexpr (MF == kFrameMount)
+    // the Airy table: in LDS for the mount frame's per-sample lookups, and
+    // for the sky frame's image-plane factors when it fits beside two blocks
+    // (support 32)
+    const bool tlds = MF == kFrameMount || (MF == kFrameSky && S == 32 && a.tab_lds);
+    if (tlds)
         for (int t = tid; t < a.n_tab; t += kBlock) airy_sh[t] = a.airy[t];
     __syncthreads();
 
@@ -458,7 +466,7 @@ __global__ void __launch_bounds__(64 * W, S == 16 && MF == kFrameMount ? 3 : 1) 
             image_factors_cx<MODE>(a, gsh, kk, inv_s2, kgd, (float)dfp[it.ai], (float)dfp[it.aj], (float)qil,
                                    (float)qim, (float)qjl, (float)qjm, tid, kBlock);
         } else if constexpr (SKY) {
-            image_factors<MODE, MF == kFrameSkyAperture, S == 32>(a, gsh, bki, bkj, (float)qil, (float)qim,
+            image_factors<MODE, MF == kFrameSkyAperture, S == 32>(a, tlds ? airy_sh : a.airy, gsh, bki, bkj, (float)qil, (float)qim,
                                                                    (float)qjl, (float)qjm, tid, kBlock);
         }
         __syncthreads();
@@ -692,6 +700,16 @@ __global__ void __launch_bounds__(64 * W, S == 16 && MF == kFrameMount ? 3 : 1) 
     }
 }
 
+// Whether a sky-frame block at support 32 stages the Airy table in LDS: when
+// a four-wavefront block with it still leaves room for a second block on the
+// compute unit (the lookups of the image-plane factors then stay on chip).
+static bool sky_tab_lds(int support, int mode, int frame, int m, int oversample, int n_tab)
+{
+    if (frame != kFrameSky || support != 32) return false;
+    const size_t b4 = winw_lds_bytes(support, 4, mode, m, oversample, -1) + sizeof(float4) * (size_t)n_tab;
+    return 2 * (b4 + (160 * 1024 - win_lds_budget(support))) <= 160 * 1024;
+}
+
 // Dynamic LDS of a k_winw block of the given frame: winw_lds_bytes, with the
 // stored factors counted per frame.
 static size_t winw_frame_lds(int support, int waves, int mode, int frame, int m, int oversample, int n_tab)
@@ -699,6 +717,7 @@ static size_t winw_frame_lds(int support, int waves, int mode, int frame, int m,
     const size_t m2p = (size_t)((m * m + 3) & ~3);
     const int tab = frame == kFrameMount ? n_tab : frame == kFrameSky ? -1 : 0;
     size_t b = winw_lds_bytes(support, waves, mode, m, oversample, tab);
+    if (sky_tab_lds(support, mode, frame, m, oversample, n_tab)) b += sizeof(float4) * (size_t)n_tab;
     // frames with stored products other than the radial factors: the base
     // size counts none (tab = 0), so all of them are added here
     if (frame == kFrameSkyAperture || frame == kFrameSkyComplex)
@@ -724,7 +743,7 @@ int win_block_waves(int support, int mode, int frame, int m, int oversample, int
 // arithmetic): float64 sums, stored products, tiles, the transform kept for
 // reuse, the Airy table.  A launch whose allocation is smaller is refused.
 template <int S, int MODE, int MF, int W>
-static size_t winw_layout_bytes(int m, int n_tab)
+static size_t winw_layout_bytes(int m, int n_tab, bool tab_lds)
 {
     constexpr int NW = W * (64 / (2 * S));
     constexpr int NC = mode_nc(MODE);
@@ -734,7 +753,7 @@ static size_t winw_layout_bytes(int m, int n_tab)
     b += SKY ? sizeof(float) * (size_t)win_factors(MF, MODE) * m2p : 0;
     b += sizeof(float2) * (size_t)NW * S * (S + 1);
     b += S == 16 ? sizeof(float2) * (size_t)(S / 2) * 64 * W : 0;
-    b += MF == kFrameMount ? sizeof(float4) * (size_t)n_tab : 0;
+    b += MF == kFrameMount || (MF == kFrameSky && S == 32 && tab_lds) ? sizeof(float4) * (size_t)n_tab : 0;
     return b;
 }
 
@@ -747,9 +766,11 @@ static hipError_t launch_win_wm(const ItemArgs& a, hipStream_t s)
         (int)win_lds_budget(S));
     if (attr != hipSuccess) return attr;
     const int blocks = (int)item_blocks(a.n_items);
+    ItemArgs b = a;
+    b.tab_lds = sky_tab_lds(S, MODE, MF, a.m, a.oversample, a.n_tab);
     const size_t sh = winw_frame_lds(S, W, MODE, MF, a.m, a.oversample, a.n_tab);
-    if (sh < winw_layout_bytes<S, MODE, MF, W>(a.m, a.n_tab)) return hipErrorInvalidValue;
-    k_winw<S, MODE, MF, W, WT, MT><<<blocks, 64 * W, sh, s>>>(a);
+    if (sh < winw_layout_bytes<S, MODE, MF, W>(a.m, a.n_tab, b.tab_lds)) return hipErrorInvalidValue;
+    k_winw<S, MODE, MF, W, WT, MT><<<blocks, 64 * W, sh, s>>>(b);
     return hipGetLastError();
 }
 
