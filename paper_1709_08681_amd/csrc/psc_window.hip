@@ -569,7 +569,12 @@ __global__ void __launch_bounds__(64 * W, S == 16 && MF == kFrameMount ? 3 : 1) 
             } else {
                 // factored sums: the value sum g T, and per antenna Q = sum q T
                 // and L = sum q l T, l the image-sample l coordinate (the
-                // variant dV/dp_l = L - p_l Q, dV/dp_m = (m - p_m) Q)
+                // variant dV/dp_l = L - p_l Q, dV/dp_m = (m - p_m) Q).  L comes
+                // from running sums: over the part's rows n < j1 in order,
+                // Q += q T and then P += Q leave P = sum (j1 - n) q T, so with
+                // l = (n - M/2) h, L = h ((j1 - M/2) Q - P): no product by l
+                // per row (the float32 error stays within twice that of the
+                // direct sum, coherent rows included).
                 const float* gp = gsh + jm * NG;
                 // the halves read factors S samples apart, S NG words: an odd
                 // multiple of 32 for NG odd, so they use disjoint banks
@@ -603,17 +608,15 @@ __global__ void __launch_bounds__(64 * W, S == 16 && MF == kFrameMount ? 3 : 1) 
                         }
                         if constexpr (MODE != kPredict && !PLAIN) {
                             constexpr int o = MODE == kGrad ? 1 : 0;
-                            const float l = (float)(jl - half_m) * hstep;
-                            const float2 tl = make_float2(t.x * l, t.y * l);
 #pragma unroll
                             for (int end = 0; end < 2; ++end) {
                                 const float q = g[o + end];
-                                float2& L = acc[o + 2 * end];
+                                float2& P = acc[o + 2 * end];
                                 float2& Q = acc[o + 2 * end + 1];
-                                L.x = fmaf(q, tl.x, L.x);
-                                L.y = fmaf(q, tl.y, L.y);
                                 Q.x = fmaf(q, t.x, Q.x);
                                 Q.y = fmaf(q, t.y, Q.y);
+                                P.x += Q.x;
+                                P.y += Q.y;
                             }
                         }
                     }
@@ -624,6 +627,19 @@ __global__ void __launch_bounds__(64 * W, S == 16 && MF == kFrameMount ? 3 : 1) 
                 seg(0, half_m, S - half_m, A);
                 seg(half_m, S, 0, A);
                 seg(S, m, S - half_m, B);
+                if constexpr (MODE != kPredict && !PLAIN) {
+                    // L from P and Q: the A part ends at row S, the B part at M
+                    constexpr int o = MODE == kGrad ? 1 : 0;
+                    const float ca = (float)(S - half_m), cb = (float)(m - half_m);
+#pragma unroll
+                    for (int end = 0; end < 2; ++end) {
+                        float2& pa = A[o + 2 * end];
+                        float2& pb = B[o + 2 * end];
+                        const float2 qa = A[o + 2 * end + 1], qb = B[o + 2 * end + 1];
+                        pa = make_float2(hstep * fmaf(ca, qa.x, -pa.x), hstep * fmaf(ca, qa.y, -pa.y));
+                        pb = make_float2(hstep * fmaf(cb, qb.x, -pb.x), hstep * fmaf(cb, qb.y, -pb.y));
+                    }
+                }
             }
             // ---- s_k = phi_m(n_m) (A_k + exp(2 pi i f_l / O) B_k), summed over the worker
             const float2 rho = twsh[(fl * S) & (so - 1)];
