@@ -122,27 +122,20 @@ class Workload:
     def solve_form(self, form, iters, warmup):
         """Algorithm 1 for `iters` iterations (tol = 0, so every interval runs
         them all) from the same start in the given form; returns (ms per
-        iteration, offsets, ms of the first call).  The warm-up call has the
-        same arguments, so the graph form captures its graph there and the
-        timed call only replays it."""
+        iteration, offsets).  The warm-up call has the same arguments, so the
+        graph form captures its graph there and the timed call only replays
+        it."""
         torch, s = self.torch, self.s
-        first_ms = None
         for k in range(max(1, warmup)):
             self.off.copy_(self.start)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
             s.solve(self.v_obs, self.w, self.off, gain=0.5, n_max=iters, tol_rad=0.0, form=form)
-            torch.cuda.synchronize()
-            if k == 0:
-                first_ms = (time.perf_counter() - t0) * 1e3
         self.off.copy_(self.start)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.solve(self.v_obs, self.w, self.off, gain=0.5, n_max=iters, tol_rad=0.0, form=form)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        # the first call's excess over a timed call: graph capture and instantiation
-        return dt * 1e3 / iters, self.off.clone(), first_ms - dt * 1e3
+        return dt * 1e3 / iters, self.off.clone()
 
     def eager_steps(self, steps, warmup):
         """The same iteration written out with the C-ABI calls on the bench's
@@ -183,11 +176,12 @@ def forms_report(wl, iters, warmup, forms=("graph", "batched", "plain")):
     code = {"plain": P.SOLVE_PLAIN, "batched": P.SOLVE_BATCHED, "graph": P.SOLVE_GRAPH}
     res, offs = {}, {}
     for name in forms:
-        ms, offs[name], first = wl.solve_form(code[name], iters, warmup)
+        ms, offs[name] = wl.solve_form(code[name], iters, warmup)
         res[name] = {"vis_per_s": wl.obs.n_vis / (ms * 1e-3), "ms_per_iteration": ms}
         if name == "graph":
-            # the first call captured and instantiated the graph, then ran it
-            res[name]["capture_and_instantiate_ms"] = first
+            # host time the library spent capturing and instantiating the
+            # graph in the warm-up call (outside the timed call)
+            res[name]["capture_and_instantiate_ms"] = P.psc_obs_launch_info(wl.s.handle)["capture_ms"]
     ref = offs[forms[0]]
     res["bit_identical_offsets"] = bool(all(wl.torch.equal(ref, o) for o in offs.values()))
     if "plain" in res and "graph" in res:

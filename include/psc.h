@@ -215,6 +215,10 @@ PSC_API psc_status psc_obs_info(const psc_obs* obs, int64_t* n_items, int64_t* n
  *                     and setup kernels)
  *   w_planes          model grids of a w-stacked observation (0 when the
  *                     w-term, if any, fits one kernel)
+ *   tab_nodes         nodes of the Airy table (grown by psc_set_beam_scale
+ *                     for scales below 1)
+ *   capture_ms        host wall time the last graph-form psc_solve spent
+ *                     capturing and instantiating its graph (0 before any)
  * PSC_E_ARG for a null observation or output.
  */
 typedef struct {
@@ -223,7 +227,8 @@ typedef struct {
     double samples_per_item;
     double plan_ms;
     int32_t w_planes;
-    int32_t reserved;
+    int32_t tab_nodes;
+    double capture_ms;
 } psc_launch_info;
 PSC_API psc_status psc_obs_launch_info(const psc_obs* obs, psc_launch_info* out);
 
@@ -393,8 +398,13 @@ PSC_API psc_status psc_tune(psc_ctx* ctx, psc_obs* obs, const double* offsets_de
  * the observation then degrids in the window form (psc_set_degrid refuses
  * the table forms); the image gradient then builds each sample's kernel
  * (in the sky frame at angle zero, from [n_row] zeros the first call
- * allocates).  A null scale_dev drops the scales (sigma = 1 again; the
- * window form stays).  A captured solve graph is discarded.
+ * allocates).  A scale below 1 stretches every pattern lookup to
+ * |l - p| / sigma, so the first call rebuilds the beam tables (Airy, and a
+ * measured aperture's pattern) over the range at the smallest scale allowed,
+ * which the scale step cannot pass either (device memory reallocated; the
+ * defocus moment table is dropped with them).  A null scale_dev drops the
+ * scales (sigma = 1 again; the window form and the tables stay).  A
+ * captured solve graph is discarded.
  * psc_get_beam_scale (async): copies the observation's scales to
  * scale_out_dev; PSC_E_STATE when none are set.
  */

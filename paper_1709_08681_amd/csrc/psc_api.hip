@@ -70,8 +70,12 @@ struct psc_obs {
     double* zero_pa = nullptr; // [n_row] zeros: the per-sample scatter's angles with scales, sky frame
     int32_t win_waves = 0;     // window-form block size at support 16 (see ItemArgs)
     double plan_ms = 0;        // wall time psc_obs_create took
+    double capture_ms = 0;     // wall time of the last solve graph's capture + instantiation
     int32_t ap_n = 0;
     double ap_c = 0, ap_step = 0;
+    // the tables' ranges at beam scale 1 (Airy argument x, aperture radius in
+    // lambda/D), and the smallest scale they cover
+    double tab_x1 = 0, ap_r1 = 0, tab_scale = 1.0;
     double* partials = nullptr;  // [n_items][n_pol][12]
     double* acc = nullptr;       // [n_int][n_pol][n_ant][6]
     double* max_step = nullptr;  // [n_int]
@@ -774,6 +778,8 @@ static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
     obs->n_vis = (int64_t)vis.size();
     obs->n_tab = n_tab;
     obs->inv_dx = 1.0 / dx;
+    obs->tab_x1 = x_max;
+    obs->ap_r1 = rho_max * ctx->cfg.dish_diam_m / lam_min;
     // items of few samples on average: window-form blocks of one wavefront
     // below 16 samples per item, of two below 128 (measured on the batched
     // array: at 4.6 samples per item 36.3 ms per gradient with one, 42.8
@@ -897,7 +903,8 @@ PSC_API psc_status psc_obs_launch_info(const psc_obs* obs, psc_launch_info* out)
     out->samples_per_item = obs->n_items > 0 ? (double)obs->n_vis / (double)obs->n_items : 0.0;
     out->plan_ms = obs->plan_ms;
     out->w_planes = obs->w_nk;
-    out->reserved = 0;
+    out->tab_nodes = obs->n_tab;
+    out->capture_ms = obs->capture_ms;
     return PSC_OK;
 }
 
@@ -1310,6 +1317,54 @@ static double scale_floor(const psc_ctx* ctx, const psc_obs* obs)
     return ap_cells / (ctx->s - 0.5 * ctx->cfg.taper_width - 0.5);
 }
 
+// A beam scale sigma < 1 stretches every pattern lookup to |l - p| / sigma:
+// the Airy table (and a measured aperture's pattern table) built at
+// psc_obs_create for sigma = 1 is rebuilt to cover the range over smin.
+// The moment table of the defocus mode follows the Airy table's nodes, so it
+// is dropped (scales and a defocus are not set together; psc_set_defocus
+// builds it again).  The caller has synchronised the device.
+static hipError_t grow_tables(const psc_ctx* ctx, psc_obs* obs, double smin)
+{
+    const double dx = 1.0 / obs->inv_dx;
+    const int n_tab = (int)ceil(obs->tab_x1 / smin / dx) + 3;
+    float4* airy = nullptr;
+    hipError_t e = dmalloc(&airy, n_tab);
+    if (e == hipSuccess) e = launch_airy_table(airy, n_tab, dx, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        dfree(airy);
+        return e;
+    }
+    dfree(obs->airy);
+    dfree(obs->mtab);
+    obs->airy = airy;
+    obs->n_tab = n_tab;
+    if (obs->ap_tab) {
+        const int ap_half = (int)ceil(obs->ap_r1 / smin / obs->ap_step) + 2;
+        const int ap_n = 2 * ap_half + 1;
+        const int n_cells = (int)(ctx->ap_cells.size() / 3);
+        float4* tab = nullptr;
+        double* cells = nullptr;
+        e = dmalloc(&tab, (size_t)ap_n * ap_n);
+        if (e == hipSuccess) e = dmalloc(&cells, ctx->ap_cells.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(cells, ctx->ap_cells.data(), sizeof(double) * ctx->ap_cells.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = launch_aperture_table(cells, n_cells, tab, ap_n, ap_half, obs->ap_step, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        dfree(cells);
+        if (e != hipSuccess) {
+            dfree(tab);
+            return e;
+        }
+        dfree(obs->ap_tab);
+        obs->ap_tab = tab;
+        obs->ap_n = ap_n;
+        obs->ap_c = ap_half;
+    }
+    obs->tab_scale = smin;
+    return hipSuccess;
+}
+
 PSC_API psc_status psc_set_beam_scale(psc_ctx* ctx, psc_obs* obs, const double* scale_dev, void* stream)
 {
     if (!ctx) return fail(nullptr, PSC_E_ARG, "null context");
@@ -1342,6 +1397,14 @@ PSC_API psc_status psc_set_beam_scale(psc_ctx* ctx, psc_obs* obs, const double* 
     if (smin < scale_floor(ctx, obs))
         return fail(ctx, PSC_E_UNSUPPORTED, "beam scale too small: the widened aperture's kernel "
                                             "(2 D FoV / (sigma lambda) cells) outgrows the support");
+    // the pattern tables cover every scale the observation can reach: the
+    // scale step narrows beams on the device, down to the same floor
+    const double cover = std::min(1.0, scale_floor(ctx, obs));
+    if (ctx->cfg.illum != 1 && cover < obs->tab_scale) {
+        PSC_HIP(ctx, hipDeviceSynchronize());  // no launch may still read the tables
+        const hipError_t e = grow_tables(ctx, obs, cover);
+        if (e != hipSuccess) return hip_fail(ctx, e, "psc_set_beam_scale: pattern tables");
+    }
     // the image gradient's scatter builds each sample's kernel when the
     // beams are scaled: in the sky frame it runs at angle zero
     if (!obs->par_angle && !obs->zero_pa) {
@@ -1622,6 +1685,7 @@ static psc_status solve_impl(psc_ctx* ctx, psc_obs* obs, const void* vis_obs_dev
                           obs->g_off == offsets_io_dev && obs->g_gain == gain && obs->g_tol == tol_rad &&
                           obs->g_nmax == n_max;
         if (!same) {
+            const auto t0 = std::chrono::steady_clock::now();
             if (obs->graph) {
                 (void)hipGraphExecDestroy(obs->graph);
                 obs->graph = nullptr;
@@ -1650,6 +1714,7 @@ static psc_status solve_impl(psc_ctx* ctx, psc_obs* obs, const void* vis_obs_dev
             obs->g_gain = gain;
             obs->g_tol = tol_rad;
             obs->g_nmax = n_max;
+            obs->capture_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         }
         // the graph runs on the capture stream after the caller's queued work
         PSC_HIP(ctx, hipStreamSynchronize(s));
