@@ -64,6 +64,7 @@ struct psc_obs {
     double inv_dx = 0;
     double fmax = 0;           // highest channel frequency (Hz)
     float4* ap_tab = nullptr;  // measured aperture: pattern table [ap_n][ap_n]
+    float2* beams = nullptr;   // sky frame, radial beams: per-antenna (E, q) tables (ItemArgs::beams)
     double* scale = nullptr;   // beam-width scales [n_int][n_pol][n_ant] (null: all 1)
     double* defocus = nullptr; // aperture defocus [n_int][n_pol][n_ant] (null: none; complex patterns)
     float2* mtab = nullptr;    // the uniform disc's moment table [n_tab][kMoments] (defocus, illum 0)
@@ -198,6 +199,10 @@ int floor_div(long long a, int b)
 }
 
 }  // namespace
+
+// largest per-antenna pattern table an observation allocates (16 GiB: one
+// GPU's 32-channel share of the large workload needs 9.7 GB)
+constexpr size_t kBeamTabBytes = size_t(16) << 30;
 
 // Scratch of the allocation-free gradient (psc_gradient_noalloc): the
 // per-item float64 partial sums, kept in a file-scope device array so that
@@ -448,6 +453,7 @@ PSC_API psc_status psc_obs_destroy(psc_obs* obs)
     dfree(obs->w_m);
     dfree(obs->airy);
     dfree(obs->ap_tab);
+    dfree(obs->beams);
     dfree(obs->scale);
     dfree(obs->zero_pa);
     dfree(obs->partials);
@@ -798,6 +804,15 @@ static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
     if (e == hipSuccess && !pa.empty()) e = dmalloc(&obs->par_angle, pa.size());
     if (e == hipSuccess && !wv.empty()) e = dmalloc(&obs->w_m, wv.size());
     if (e == hipSuccess) e = dmalloc(&obs->airy, n_tab);
+    // sky-frame radial beams: room for every antenna's pattern at the image
+    // samples per interval, polarisation and channel, which the window form
+    // fills before each degrid (at most kBeamTabBytes; beyond that each item
+    // evaluates its antennas' patterns itself)
+    {
+        const size_t nb = (size_t)n_int * d->n_pol * n_chan * n_ant * (size_t)ctx->m * ctx->m;
+        if (e == hipSuccess && pa.empty() && !ap && nb > 0 && nb * sizeof(float2) <= kBeamTabBytes)
+            e = dmalloc(&obs->beams, nb);
+    }
     if (e == hipSuccess) e = dmalloc(&obs->partials, items.size() * d->n_pol * 12);
     if (e == hipSuccess) e = dmalloc(&obs->acc, (size_t)n_int * d->n_pol * n_ant * 6);
     if (e == hipSuccess) e = dmalloc(&obs->max_step, n_int);
@@ -968,6 +983,15 @@ ItemArgs item_args(psc_ctx* ctx, psc_obs* obs, const double* offsets, int item_b
     a.win_waves = obs->win_waves;
     a.partials = obs->partials;
     a.done = done;
+    // the intervals the items span: the pattern tables filled for them
+    a.beams = obs->beams;
+    {
+        const int32_t* p = obs->int_item_ptr.data();
+        a.beam_int0 = (int)(std::upper_bound(p, p + obs->n_int + 1, item_begin) - p) - 1;
+        a.beam_int1 = (int)(std::lower_bound(p, p + obs->n_int + 1, item_begin + n_items) - p);
+        a.beam_int0 = std::max(0, std::min(a.beam_int0, obs->n_int));
+        a.beam_int1 = std::max(a.beam_int0, std::min(a.beam_int1, obs->n_int));
+    }
     a.use_mfma = obs->degrid == PSC_DEGRID_MFMA ? 1 : 0;
     return a;
 }

@@ -145,6 +145,12 @@ struct ItemArgs {
     // blocks by LDS alone
     int32_t win_waves;
     int32_t tab_lds;            // window form: the Airy table is staged in LDS (set by the launcher)
+    // window form, sky frame, radial beams: every antenna's pattern and
+    // gradient factor (E, q) at the image samples, [n_int][n_pol][n_chan]
+    // [n_ant][m^2], filled for intervals [beam_int0, beam_int1) before the
+    // degrid (null: each item evaluates its two antennas' patterns itself)
+    float2* beams;
+    int32_t beam_int0, beam_int1;
     int32_t use_mfma;           // degrid on the matrix cores (gradient and adjoint)
     // image-gradient scatter (k_grid)
     const uint2* ig_ord;        // per item, its samples in time order: (sample index, sub-table slot)

@@ -148,11 +148,13 @@ __device__ __forceinline__ void image_factors_cx(const ItemArgs& a, float* gsh, 
 // place of q.  AP: a measured aperture, one stored product per variant (as
 // mf_products_ap at angle zero).  bi, bj: each antenna's beam constants (its
 // width scale applied).  HW: the hardware square root in the beam lookups
-// (2.6% faster at support 32, 16% slower at 16).
+// (2.6% faster at support 32, 16% slower at 16).  pi, pj: the two antennas'
+// tabulated (E, q) at the image samples (k_ant_beams), or null to evaluate
+// them here from the Airy table tab.
 template <int MODE, bool AP, bool HW>
-__device__ __forceinline__ void image_factors(const ItemArgs& a, const float4* tab, float* gsh, const BeamK& bi,
-                                              const BeamK& bj, float pil, float pim, float pjl, float pjm, int tid,
-                                              int nthr)
+__device__ __forceinline__ void image_factors(const ItemArgs& a, const float4* tab, const float2* pi,
+                                              const float2* pj, float* gsh, const BeamK& bi, const BeamK& bj,
+                                              float pil, float pim, float pjl, float pjm, int tid, int nthr)
 {
     constexpr int NG = AP ? mode_nv(MODE) : win_ng(MODE);
     const int m = a.m, half_m = m >> 1, m2 = m * m;
@@ -174,8 +176,16 @@ __device__ __forceinline__ void image_factors(const ItemArgs& a, const float4* t
             for (int k = 0; k < NG; ++k) gn[k] = g[k];
         } else {
             float ei, qi, ej, qj;
-            efq<HW>(a, tab, bi.kk, bi.inv_s2, dli, dmi, ei, qi);
-            efq<HW>(a, tab, bj.kk, bj.inv_s2, dlj, dmj, ej, qj);
+            if (pi != nullptr) {
+                const float2 ti = pi[idx], tj = pj[idx];
+                ei = ti.x;
+                qi = ti.y;
+                ej = tj.x;
+                qj = tj.y;
+            } else {
+                efq<HW>(a, tab, bi.kk, bi.inv_s2, dli, dmi, ei, qi);
+                efq<HW>(a, tab, bj.kk, bj.inv_s2, dlj, dmj, ej, qj);
+            }
             if constexpr (MODE == kPredict) {
                 gn[0] = ei * ej * c;
             } else if constexpr (MODE == kScale) {
@@ -335,8 +345,9 @@ __global__ void __launch_bounds__(64 * W, S == 16 && MF == kFrameMount ? 3 : 1) 
     for (int t = tid; t < so; t += kBlock) twsh[t] = a.tw[t];
     // the Airy table: in LDS for the mount frame's per-sample lookups, and
     // for the sky frame's image-plane factors when it fits beside two blocks
-    // (support 32)
-    const bool tlds = MF == kFrameMount || (MF == kFrameSky && S == 32 && a.tab_lds);
+    // (support 32) and the antennas' patterns are not tabulated
+    const bool btab = MF == kFrameSky && a.beams != nullptr;
+    const bool tlds = MF == kFrameMount || (MF == kFrameSky && S == 32 && a.tab_lds && !btab);
     if (tlds)
         for (int t = tid; t < a.n_tab; t += kBlock) airy_sh[t] = a.airy[t];
     __syncthreads();
@@ -466,8 +477,15 @@ __global__ void __launch_bounds__(64 * W, S == 16 && MF == kFrameMount ? 3 : 1) 
             image_factors_cx<MODE>(a, gsh, kk, inv_s2, kgd, (float)dfp[it.ai], (float)dfp[it.aj], (float)qil,
                                    (float)qim, (float)qjl, (float)qjm, tid, kBlock);
         } else if constexpr (SKY) {
-            image_factors<MODE, MF == kFrameSkyAperture, S == 32>(a, tlds ? airy_sh : a.airy, gsh, bki, bkj, (float)qil, (float)qim,
-                                                                   (float)qjl, (float)qjm, tid, kBlock);
+            const float2 *pi = nullptr, *pj = nullptr;
+            if (btab) {
+                const size_t t0 = (((size_t)it.interval * a.n_pol + pol) * a.n_chan + it.chan) * a.n_ant;
+                pi = a.beams + (t0 + it.ai) * (size_t)(a.m * a.m);
+                pj = a.beams + (t0 + it.aj) * (size_t)(a.m * a.m);
+            }
+            image_factors<MODE, MF == kFrameSkyAperture, S == 32>(a, tlds ? airy_sh : a.airy, pi, pj, gsh, bki, bkj,
+                                                                   (float)qil, (float)qim, (float)qjl, (float)qjm,
+                                                                   tid, kBlock);
         }
         __syncthreads();
 
@@ -867,9 +885,64 @@ size_t win_lds_budget(int support)
     return 160 * 1024 - sizeof(float2) * support * 16;
 }
 
+// Every antenna's pattern E and gradient factor q (dE/dp = q (l - p)) at the
+// image samples, per interval, polarisation and channel (Eq. DA): what each
+// item of the sky frame otherwise evaluates for its two antennas, once per
+// antenna instead of once per baseline.  One block per table; the same
+// offsets, squint and width scale as the degrid kernel's items, evaluated
+// by the same efq.  Intervals already converged (done) are skipped.
+template <bool HW>
+__global__ void __launch_bounds__(256) k_ant_beams(ItemArgs a)
+{
+    const int t = (int)blockIdx.x;
+    const int ant = t % a.n_ant;
+    const int chan = (t / a.n_ant) % a.n_chan;
+    const int pol = (t / (a.n_ant * a.n_chan)) % a.n_pol;
+    const int k = a.beam_int0 + t / (a.n_ant * a.n_chan * a.n_pol);
+    if (a.done != nullptr && a.done[k]) return;
+    const double lam = kCLight / a.freq[chan];
+    const float kk = (float)(kPi * a.dish / lam);
+    const double sigma = a.gauss_sigma_ld * lam / a.dish;
+    const float inv_s2 = (float)(1.0 / (sigma * sigma));
+    const float aps = (float)(a.dish / lam * a.ap_inv_step);
+    const double sq = (pol == 0 ? 1.0 : -1.0) * a.squint_frac * 1.02899 * lam / a.dish;
+    const double* o = a.offsets + (((size_t)k * a.n_pol + pol) * a.n_ant + ant) * 2;
+    const float pl = (float)(o[0] + sq), pm = (float)o[1];
+    BeamK b = beam_k(kk, inv_s2, aps, 1.f);
+    if (a.scale != nullptr) b = beam_k(kk, inv_s2, aps, (float)a.scale[((size_t)k * a.n_pol + pol) * a.n_ant + ant]);
+    const int m = a.m, half_m = m >> 1, m2 = m * m;
+    const float hstep = (float)a.h;
+    const float inv_m = 1.f / (float)m;
+    float2* out = a.beams + (((size_t)k * a.n_pol + pol) * a.n_chan + chan) * a.n_ant * (size_t)m2 + (size_t)ant * m2;
+    for (int idx = threadIdx.x; idx < m2; idx += 256) {
+        const int il = (int)(((float)idx + 0.5f) * inv_m), im = idx - il * m;
+        const float l = (float)(il - half_m) * hstep, mm = (float)(im - half_m) * hstep;
+        float e, q;
+        efq<HW>(a, a.airy, b.kk, b.inv_s2, l - pl, mm - pm, e, q);
+        out[idx] = make_float2(e, q);
+    }
+}
+
+hipError_t launch_ant_beams(int support, const ItemArgs& a, hipStream_t s)
+{
+    const long long n = (long long)(a.beam_int1 - a.beam_int0) * a.n_pol * a.n_chan * a.n_ant;
+    if (n <= 0) return hipSuccess;
+    if (n > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (support == 32)
+        k_ant_beams<true><<<(unsigned)n, 256, 0, s>>>(a);
+    else
+        k_ant_beams<false><<<(unsigned)n, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
 hipError_t launch_win(int mode, int support, const ItemArgs& a, hipStream_t s)
 {
     if (a.n_items <= 0) return hipSuccess;
+    // the sky frame with radial beams: tabulate each antenna's pattern first
+    if (a.beams != nullptr && a.par_angle == nullptr && a.ap_tab == nullptr && a.defocus == nullptr) {
+        const hipError_t e = launch_ant_beams(support, a, s);
+        if (e != hipSuccess) return e;
+    }
     if (support == 16) {
         switch (mode) {
         case kPredict: return launch_win_m<16, kPredict>(a, s);
