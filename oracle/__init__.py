@@ -60,6 +60,8 @@ class _Problem(C.Structure):
         ("w_m", C.POINTER(C.c_double)),
         ("aperture_n", C.c_int32),
         ("aperture", C.POINTER(C.c_double)),
+        ("n_apertures", C.c_int32),
+        ("ant_aperture", C.POINTER(C.c_int32)),
         ("beam_scale", C.POINTER(C.c_double)),
     ]
 
@@ -121,13 +123,16 @@ class Problem:
     rounds uv (in wavelengths) to the lattice 1/snap_scale.  ``w_m``: [n_row]
     baseline w in metres for the w-term (None: w = 0).  ``aperture``: a
     square, real, even aperture illumination across the dish for the
-    measured-aperture mode (illum 2).  ``beam_scale``: [n_int, n_pol, n_ant]
+    measured-aperture mode (illum 2), or a stack [n_ap, n, n] of them for a
+    heterogeneous array with ``ant_aperture`` [n_ant] naming each antenna's
+    (None: the first for all).  ``beam_scale``: [n_int, n_pol, n_ant]
     beam-width scale sigma of each antenna, E = E0(d / sigma) (None: 1).
     """
 
     def __init__(self, src_l, src_m, src_flux, n_ant, ant1, ant2, uv_m, int_row_ptr, freq_hz,
                  n_pol=1, dish_diam_m=25.0, illum=0, gauss_sigma_ld=1.0, squint_frac=0.0,
-                 snap_scale=0.0, par_angle=None, w_m=None, aperture=None, beam_scale=None):
+                 snap_scale=0.0, par_angle=None, w_m=None, aperture=None, beam_scale=None,
+                 ant_aperture=None):
         self.src_l = np.ascontiguousarray(src_l, np.float64)
         self.src_m = np.ascontiguousarray(src_m, np.float64)
         self.src_flux = np.ascontiguousarray(src_flux, np.float64)
@@ -151,9 +156,14 @@ class Problem:
         self.aperture = None if aperture is None else np.ascontiguousarray(aperture, np.float64)
         if (self.aperture is not None) != (int(illum) == 2):
             raise ValueError("the measured-aperture mode (illum 2) takes an aperture, and only it")
-        if self.aperture is not None and (self.aperture.ndim != 2 or
-                                          self.aperture.shape[0] != self.aperture.shape[1]):
-            raise ValueError("aperture must be square")
+        if self.aperture is not None and self.aperture.ndim == 2:
+            self.aperture = self.aperture[None]
+        if self.aperture is not None and (self.aperture.ndim != 3 or
+                                          self.aperture.shape[1] != self.aperture.shape[2]):
+            raise ValueError("aperture must be square, or a stack of square apertures")
+        self.ant_aperture = None if ant_aperture is None else np.ascontiguousarray(ant_aperture, np.int32)
+        if self.ant_aperture is not None and (self.aperture is None or self.ant_aperture.shape != (self.n_ant,)):
+            raise ValueError("ant_aperture takes one index per antenna, with an aperture stack")
         self.beam_scale = None if beam_scale is None else np.ascontiguousarray(beam_scale, np.float64)
         if self.beam_scale is not None and self.beam_scale.shape != (self.n_int, self.n_pol, self.n_ant):
             raise ValueError("beam_scale must be [n_int, n_pol, n_ant]")
@@ -165,8 +175,10 @@ class Problem:
             float(squint_frac), float(snap_scale),
             None if self.par_angle is None else _dp(self.par_angle),
             None if self.w_m is None else _dp(self.w_m),
-            0 if self.aperture is None else int(self.aperture.shape[0]),
+            0 if self.aperture is None else int(self.aperture.shape[1]),
             None if self.aperture is None else _dp(self.aperture),
+            0 if self.aperture is None else int(self.aperture.shape[0]),
+            None if self.ant_aperture is None else _ip(self.ant_aperture),
             None if self.beam_scale is None else _dp(self.beam_scale))
 
     @classmethod

@@ -60,7 +60,10 @@
  *    Fourier transform (Sec. 1 and Sec. 3: the pattern of a dish follows
  *    from its illumination, with blockage and taper), fixed to the mount:
  *    towards sky position l a row sees E(R(chi)^T l - q), q the mount-frame
- *    offset plus squint (chi = 0 without parallactic angles).
+ *    offset plus squint (chi = 0 without parallactic angles).  A
+ *    heterogeneous array (Sec. 3) gives each antenna one of several
+ *    apertures: a baseline's visibility then carries E_i of antenna i's
+ *    illumination and E_j of antenna j's.
  */
 #include <math.h>
 #include <stdint.h>
@@ -159,12 +162,21 @@ void oracle_efp_aperture(int aperture_n, const double* aperture, double dish_dia
                  &out3[2]);
 }
 
-/* The pattern of the problem's antennas at displacement (dl, dm) from the
- * beam centre at channel c: (E, dE/dc_l, dE/dc_m). */
-static void efp_problem(const orc_problem* p, int c, double dl, double dm, double* out3)
+/* The measured aperture of antenna a (illum 2): the first of the stack
+ * unless the problem names one per antenna (Sec. 3: the heterogeneous
+ * array, each antenna with its own illumination). */
+static const double* aperture_of(const orc_problem* p, int a)
+{
+    const size_t n2 = (size_t)p->aperture_n * p->aperture_n;
+    return p->aperture + (p->ant_aperture ? (size_t)p->ant_aperture[a] * n2 : 0);
+}
+
+/* The pattern of antenna a at displacement (dl, dm) from its beam centre at
+ * channel c: (E, dE/dc_l, dE/dc_m). */
+static void efp_problem(const orc_problem* p, int c, int a, double dl, double dm, double* out3)
 {
     if (p->illum == 2)
-        efp_aperture(p->aperture_n, p->aperture, p->dish_diam_m, ORC_C_LIGHT / p->freq_hz[c], dl, dm,
+        efp_aperture(p->aperture_n, aperture_of(p, a), p->dish_diam_m, ORC_C_LIGHT / p->freq_hz[c], dl, dm,
                      &out3[0], &out3[1], &out3[2]);
     else
         oracle_efp(p->illum, p->dish_diam_m, p->gauss_sigma_ld, p->freq_hz[c], dl, dm, out3);
@@ -174,10 +186,10 @@ static void efp_problem(const orc_problem* p, int c, double dl, double dm, doubl
  * from the beam centre: out4 = (E, dE/dc_l, dE/dc_m, dE/dsigma).  The centre
  * derivatives are E0's at d / sigma divided by sigma, and
  * dE/dsigma = -(d / sigma^2) . grad E0 = (d . dE/dc) / sigma. */
-static void efp_scaled(const orc_problem* p, int c, double sigma, double dl, double dm, double* out4)
+static void efp_scaled(const orc_problem* p, int c, int a, double sigma, double dl, double dm, double* out4)
 {
     double e[3];
-    efp_problem(p, c, dl / sigma, dm / sigma, e);
+    efp_problem(p, c, a, dl / sigma, dm / sigma, e);
     out4[0] = e[0];
     out4[1] = e[1] / sigma;
     out4[2] = e[2] / sigma;
@@ -269,7 +281,7 @@ static double* beam_table(const orc_problem* p, const double* offs_int /* [n_pol
                 double sig = sigma_of(p, scl_int, pol, a);
                 for (int s = 0; s < p->n_src; ++s) {
                     double* t = tab + 4 * ((((size_t)pol * p->n_ant + a) * p->n_chan + c) * p->n_src + s);
-                    efp_scaled(p, c, sig, p->src_l[s] - pl, p->src_m[s] - pm, t);
+                    efp_scaled(p, c, a, sig, p->src_l[s] - pl, p->src_m[s] - pm, t);
                 }
             }
         }
@@ -301,14 +313,14 @@ static void beam_row(const orc_problem* p, const double* offs_int, const double*
         for (int s = 0; s < p->n_src; ++s) {
             double dl = cs * p->src_l[s] + sn * p->src_m[s] - ql;
             double dm = -sn * p->src_l[s] + cs * p->src_m[s] - qm;
-            efp_scaled(p, c, sig, dl, dm, t + 4 * s);
+            efp_scaled(p, c, a, sig, dl, dm, t + 4 * s);
         }
         return;
     }
     double pl = cs * ql - sn * qm, pm = sn * ql + cs * qm;
     for (int s = 0; s < p->n_src; ++s) {
         double e[4];
-        efp_scaled(p, c, sig, p->src_l[s] - pl, p->src_m[s] - pm, e);
+        efp_scaled(p, c, a, sig, p->src_l[s] - pl, p->src_m[s] - pm, e);
         t[4 * s] = e[0];
         t[4 * s + 1] = cs * e[1] + sn * e[2];
         t[4 * s + 2] = -sn * e[1] + cs * e[2];
@@ -392,17 +404,24 @@ static int check_problem(const orc_problem* p)
         for (size_t k = 0; k < (size_t)p->n_int * p->n_pol * p->n_ant; ++k)
             if (!(p->beam_scale[k] > 0.0) || !isfinite(p->beam_scale[k])) return -1;
     if (p->illum == 2) {
-        /* a real, even aperture with a non-zero on-axis response */
-        int n = p->aperture_n;
-        double s0 = 0.0;
+        /* real, even apertures with a non-zero on-axis response, and every
+         * antenna's index among them */
+        int n = p->aperture_n, n_ap = p->n_apertures > 0 ? p->n_apertures : 1;
         if (n < 1 || !p->aperture) return -1;
-        for (int a = 0; a < n; ++a)
-            for (int b = 0; b < n; ++b) {
-                double v = p->aperture[(size_t)a * n + b];
-                if (!isfinite(v) || v != p->aperture[(size_t)(n - 1 - a) * n + (n - 1 - b)]) return -1;
-                s0 += v;
-            }
-        if (!(s0 > 0.0)) return -1;
+        if (p->ant_aperture)
+            for (int a = 0; a < p->n_ant; ++a)
+                if (p->ant_aperture[a] < 0 || p->ant_aperture[a] >= n_ap) return -1;
+        for (int k = 0; k < n_ap; ++k) {
+            const double* ap = p->aperture + (size_t)k * n * n;
+            double s0 = 0.0;
+            for (int a = 0; a < n; ++a)
+                for (int b = 0; b < n; ++b) {
+                    double v = ap[(size_t)a * n + b];
+                    if (!isfinite(v) || v != ap[(size_t)(n - 1 - a) * n + (n - 1 - b)]) return -1;
+                    s0 += v;
+                }
+            if (!(s0 > 0.0)) return -1;
+        }
     }
     return 0;
 }
@@ -638,9 +657,9 @@ static double beam_at_row(const orc_problem* p, const double* offs_int, const do
     double cs = cos(chi), sn = sin(chi);
     double e[4];
     if (p->illum == 2)
-        efp_scaled(p, c, sig, cs * l + sn * m - ql, -sn * l + cs * m - qm, e);
+        efp_scaled(p, c, a, sig, cs * l + sn * m - ql, -sn * l + cs * m - qm, e);
     else
-        efp_scaled(p, c, sig, l - (cs * ql - sn * qm), m - (sn * ql + cs * qm), e);
+        efp_scaled(p, c, a, sig, l - (cs * ql - sn * qm), m - (sn * ql + cs * qm), e);
     return e[0];
 }
 

@@ -31,9 +31,14 @@ typedef struct {
     const double* w_m;       /* nullable [n_row]: baseline w in metres (the w-term); null: w = 0 */
     /* illum 2: aperture illumination on aperture_n x aperture_n cells over the
      * square of side D centred on the dish axis, [x][y] row-major (x along
-     * the mount frame's l axis), real and even: A[a][b] = A[n-1-a][n-1-b] */
+     * the mount frame's l axis), real and even: A[a][b] = A[n-1-a][n-1-b].
+     * A heterogeneous array stacks n_apertures of them, [n_apertures][n][n],
+     * and ant_aperture (nullable [n_ant]) names each antenna's (null: all
+     * antennas take the first; n_apertures 0 counts as 1) */
     int32_t aperture_n;
     const double* aperture;
+    int32_t n_apertures;
+    const int32_t* ant_aperture;
     /* nullable [n_int][n_pol][n_ant]: beam-width scale sigma > 0 of each
      * antenna, E = E0(d / sigma) (null: 1) */
     const double* beam_scale;
