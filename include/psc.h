@@ -95,6 +95,10 @@ typedef struct psc_obs psc_obs;
  *                of the field of view, and interpolated bicubically (values
  *                and slopes); displacements beyond the table take its edge
  *                value.
+ *  aperture_count  apertures stacked in `aperture`, [count][n][n], each
+ *                under the same rules (0 counts as 1); an observation's
+ *                ant_aperture gives each antenna one of them (Sec. 3: a
+ *                heterogeneous array).  Each is tabulated per observation.
  */
 typedef struct {
     int32_t grid_n;
@@ -111,6 +115,7 @@ typedef struct {
     int32_t device;
     int32_t aperture_n;
     const double* aperture;
+    int32_t aperture_count;
 } psc_config;
 
 /*
@@ -141,9 +146,17 @@ typedef struct {
  *              times that phase, so it must still fit the support); the
  *              observation degrids in the window form, and psc_set_degrid
  *              refuses the table forms.  The phase widens each kernel by
- *              about |w| FoV / D uv cells over the beam; psc_obs_create
- *              returns PSC_E_UNSUPPORTED when max |w| FoV / D exceeds 1.5
- *              (w-projection beyond that needs a wider support).  Null: w = 0.
+ *              about |w| FoV / D uv cells over the beam; when max |w| FoV / D
+ *              exceeds 1.5 the observation w-stacks (Sec. 5.1): the model is
+ *              transformed again for planes w_k = k dw, each sample reads the
+ *              plane nearest its w and carries the residual in its kernel
+ *              (PSC_E_UNSUPPORTED when the planes would exceed 2 GiB).
+ *              Null: w = 0.
+ *  ant_aperture nullable [n_ant] int32: with illum 2 and several apertures
+ *              (psc_config::aperture_count), the aperture of each antenna,
+ *              0 <= index < aperture_count (Sec. 3: the heterogeneous
+ *              array); null: every antenna takes aperture 0.  PSC_E_ARG for
+ *              an index out of range, or for a map without illum 2.
  *
  * Visibility-shaped arrays used by the calls below are laid out
  * [n_row][n_chan][n_pol]; offsets are [n_int][n_pol][n_ant][2] float64 (l, m).
@@ -161,6 +174,7 @@ typedef struct {
     const double* freq_hz;
     const double* par_angle;
     const double* w_m;
+    const int32_t* ant_aperture;
 } psc_obs_desc;
 
 /* Library version string. */

@@ -29,9 +29,9 @@ struct psc_ctx {
     double2* rgrid = nullptr;      // residual grid, (N+S) x (N+S)
     double2* fa = nullptr;         // [N][N] transform work
     double2* fb = nullptr;
-    // measured aperture (illum 2): its non-zero cells (xi, eta, weight), xi
-    // and eta in units of D, weights summing to one
-    std::vector<double> ap_cells;
+    // measured apertures (illum 2), each as its non-zero cells (xi, eta,
+    // weight), xi and eta in units of D, weights summing to one
+    std::vector<std::vector<double>> ap_cells;
     double* image = nullptr;            // the model image [N][N] float64, kept for w-planes
     std::vector<psc_obs*> stacked;      // observations with w-planes, rebuilt with the model
     bool model_set = false;
@@ -63,7 +63,8 @@ struct psc_obs {
     int32_t n_tab = 0;
     double inv_dx = 0;
     double fmax = 0;           // highest channel frequency (Hz)
-    float4* ap_tab = nullptr;  // measured aperture: pattern table [ap_n][ap_n]
+    float4* ap_tab = nullptr;  // measured apertures: pattern tables [n_apertures][ap_n][ap_n]
+    int32_t* ap_ant = nullptr; // [n_ant] each antenna's aperture (null: all the first)
     float2* beams = nullptr;   // sky frame, radial beams: per-antenna (E, q) tables (ItemArgs::beams)
     double* scale = nullptr;   // beam-width scales [n_int][n_pol][n_ant] (null: all 1)
     double* defocus = nullptr; // aperture defocus [n_int][n_pol][n_ant] (null: none; complex patterns)
@@ -269,28 +270,38 @@ static psc_status create_impl(const psc_config* cfg, psc_ctx** out)
     if (!(c.cell_rad > 0) || !(c.dish_diam_m > 0) || !isfinite(c.cell_rad))
         return fail(nullptr, PSC_E_ARG, "cell_rad and dish_diam_m must be positive");
     if (c.illum < 0 || c.illum > 2) return fail(nullptr, PSC_E_ARG, "illum must be 0, 1 or 2");
-    std::vector<double> ap_cells;
+    // each aperture as its non-zero cells (x, y in units of D, weight over
+    // the aperture's sum)
+    std::vector<std::vector<double>> ap_cells;
     if (c.illum == 2) {
         const int an = c.aperture_n;
+        const int n_ap = c.aperture_count > 0 ? c.aperture_count : 1;
         if (!c.aperture || an < 1 || an > 256)
             return fail(nullptr, PSC_E_ARG, "illum 2 needs an aperture of aperture_n in [1, 256] cells per side");
-        double sum = 0.0;
-        for (int i = 0; i < an; ++i)
-            for (int j = 0; j < an; ++j) {
-                const double v = c.aperture[(size_t)i * an + j];
-                if (!isfinite(v) || v != c.aperture[(size_t)(an - 1 - i) * an + (an - 1 - j)])
-                    return fail(nullptr, PSC_E_ARG, "the aperture must be finite and even (A[i][j] = A[n-1-i][n-1-j])");
-                sum += v;
-            }
-        if (!(sum > 0.0)) return fail(nullptr, PSC_E_ARG, "the aperture's sum must be positive");
-        for (int i = 0; i < an; ++i)
-            for (int j = 0; j < an; ++j) {
-                const double v = c.aperture[(size_t)i * an + j];
-                if (v == 0.0) continue;
-                ap_cells.push_back((i - 0.5 * (an - 1)) / an);
-                ap_cells.push_back((j - 0.5 * (an - 1)) / an);
-                ap_cells.push_back(v / sum);
-            }
+        if (n_ap > 256) return fail(nullptr, PSC_E_ARG, "aperture_count above 256");
+        for (int k = 0; k < n_ap; ++k) {
+            const double* A = c.aperture + (size_t)k * an * an;
+            double sum = 0.0;
+            for (int i = 0; i < an; ++i)
+                for (int j = 0; j < an; ++j) {
+                    const double v = A[(size_t)i * an + j];
+                    if (!isfinite(v) || v != A[(size_t)(an - 1 - i) * an + (an - 1 - j)])
+                        return fail(nullptr, PSC_E_ARG,
+                                    "every aperture must be finite and even (A[i][j] = A[n-1-i][n-1-j])");
+                    sum += v;
+                }
+            if (!(sum > 0.0)) return fail(nullptr, PSC_E_ARG, "every aperture's sum must be positive");
+            std::vector<double> cells;
+            for (int i = 0; i < an; ++i)
+                for (int j = 0; j < an; ++j) {
+                    const double v = A[(size_t)i * an + j];
+                    if (v == 0.0) continue;
+                    cells.push_back((i - 0.5 * (an - 1)) / an);
+                    cells.push_back((j - 0.5 * (an - 1)) / an);
+                    cells.push_back(v / sum);
+                }
+            ap_cells.push_back(std::move(cells));
+        }
     }
     if (c.illum == 1 && !(c.gauss_sigma_ld > 0))
         return fail(nullptr, PSC_E_ARG, "gauss_sigma_ld must be positive in Gaussian mode");
@@ -453,6 +464,7 @@ PSC_API psc_status psc_obs_destroy(psc_obs* obs)
     dfree(obs->w_m);
     dfree(obs->airy);
     dfree(obs->ap_tab);
+    dfree(obs->ap_ant);
     dfree(obs->beams);
     dfree(obs->scale);
     dfree(obs->zero_pa);
@@ -465,6 +477,31 @@ PSC_API psc_status psc_obs_destroy(psc_obs* obs)
     dfree(obs->ig_vm);
     delete obs;
     return PSC_OK;
+}
+
+// Pattern tables of the context's measured apertures, [n][ap_n][ap_n]
+// (launch_aperture_table per aperture; synchronous).
+static hipError_t aperture_tables(const psc_ctx* ctx, int ap_n, int ap_half, double ap_step, float4** out)
+{
+    const size_t n2 = (size_t)ap_n * ap_n;
+    float4* tab = nullptr;
+    hipError_t e = dmalloc(&tab, n2 * ctx->ap_cells.size());
+    for (size_t k = 0; k < ctx->ap_cells.size() && e == hipSuccess; ++k) {
+        const std::vector<double>& c = ctx->ap_cells[k];
+        double* cells = nullptr;
+        e = dmalloc(&cells, c.size());
+        if (e == hipSuccess) e = hipMemcpy(cells, c.data(), sizeof(double) * c.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = launch_aperture_table(cells, (int)(c.size() / 3), tab + k * n2, ap_n, ap_half, ap_step, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        dfree(cells);
+    }
+    if (e != hipSuccess) {
+        dfree(tab);
+        return e;
+    }
+    *out = tab;
+    return hipSuccess;
 }
 
 static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs** out)
@@ -507,6 +544,15 @@ static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
     }
     for (int64_t i = 0; i < 2 * n_row; ++i)
         if (!isfinite(uv[i])) return fail(ctx, PSC_E_ARG, "uv_m must be finite");
+    std::vector<int32_t> apa;
+    if (d->ant_aperture) {
+        if (ctx->cfg.illum != 2) return fail(ctx, PSC_E_ARG, "ant_aperture needs the measured-aperture mode (illum 2)");
+        apa.resize(n_ant);
+        PSC_HIP(ctx, hipMemcpy(apa.data(), d->ant_aperture, sizeof(int32_t) * n_ant, hipMemcpyDeviceToHost));
+        for (int a = 0; a < n_ant; ++a)
+            if (apa[a] < 0 || apa[a] >= (int)ctx->ap_cells.size())
+                return fail(ctx, PSC_E_ARG, "ant_aperture: every index must be in [0, aperture_count)");
+    }
     std::vector<double> pa;
     if (d->par_angle && n_row > 0) {
         pa.resize(n_row);
@@ -838,17 +884,14 @@ static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
     if (e == hipSuccess && !wv.empty())
         e = hipMemcpy(obs->w_m, wv.data(), sizeof(double) * wv.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = launch_airy_table(obs->airy, n_tab, dx, nullptr);
-    double* cells = nullptr;
     if (ap) {
         obs->ap_n = ap_n;
         obs->ap_c = ap_half;
         obs->ap_step = ap_step;
-        const int n_cells = (int)(ctx->ap_cells.size() / 3);
-        if (e == hipSuccess) e = dmalloc(&obs->ap_tab, (size_t)ap_n * ap_n);
-        if (e == hipSuccess) e = dmalloc(&cells, ctx->ap_cells.size());
-        if (e == hipSuccess)
-            e = hipMemcpy(cells, ctx->ap_cells.data(), sizeof(double) * ctx->ap_cells.size(), hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = launch_aperture_table(cells, n_cells, obs->ap_tab, ap_n, ap_half, ap_step, nullptr);
+        if (e == hipSuccess) e = aperture_tables(ctx, ap_n, ap_half, ap_step, &obs->ap_tab);
+        if (e == hipSuccess && !apa.empty()) e = dmalloc(&obs->ap_ant, apa.size());
+        if (e == hipSuccess && !apa.empty())
+            e = hipMemcpy(obs->ap_ant, apa.data(), sizeof(int32_t) * apa.size(), hipMemcpyHostToDevice);
         // the image gradient's scatter builds each sample's kernel: in the
         // sky frame at angle zero
         if (e == hipSuccess && pa.empty()) {
@@ -894,7 +937,6 @@ static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
     }
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&obs->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipDeviceSynchronize();
-    dfree(cells);
     if (e != hipSuccess) {
         psc_status st = e == hipErrorOutOfMemory ? PSC_E_OOM : PSC_E_HIP;
         std::string msg = std::string("psc_obs_create: ") + hipGetErrorString(e);
@@ -973,6 +1015,7 @@ ItemArgs item_args(psc_ctx* ctx, psc_obs* obs, const double* offsets, int item_b
     a.n_tab = obs->n_tab;
     a.inv_dx = (float)obs->inv_dx;
     a.ap_tab = obs->ap_tab;
+    a.ap_ant = obs->ap_ant;
     a.ap_n = obs->ap_n;
     a.ap_c = (float)obs->ap_c;
     a.ap_inv_step = obs->ap_step > 0 ? (float)(1.0 / obs->ap_step) : 0.f;
@@ -1366,20 +1409,9 @@ static hipError_t grow_tables(const psc_ctx* ctx, psc_obs* obs, double smin)
     if (obs->ap_tab) {
         const int ap_half = (int)ceil(obs->ap_r1 / smin / obs->ap_step) + 2;
         const int ap_n = 2 * ap_half + 1;
-        const int n_cells = (int)(ctx->ap_cells.size() / 3);
         float4* tab = nullptr;
-        double* cells = nullptr;
-        e = dmalloc(&tab, (size_t)ap_n * ap_n);
-        if (e == hipSuccess) e = dmalloc(&cells, ctx->ap_cells.size());
-        if (e == hipSuccess)
-            e = hipMemcpy(cells, ctx->ap_cells.data(), sizeof(double) * ctx->ap_cells.size(), hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = launch_aperture_table(cells, n_cells, tab, ap_n, ap_half, obs->ap_step, nullptr);
-        if (e == hipSuccess) e = hipDeviceSynchronize();
-        dfree(cells);
-        if (e != hipSuccess) {
-            dfree(tab);
-            return e;
-        }
+        e = aperture_tables(ctx, ap_n, ap_half, obs->ap_step, &tab);
+        if (e != hipSuccess) return e;
         dfree(obs->ap_tab);
         obs->ap_tab = tab;
         obs->ap_n = ap_n;

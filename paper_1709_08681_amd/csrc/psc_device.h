@@ -241,19 +241,28 @@ __device__ __forceinline__ void image_products(const ItemArgs& a, const Item& it
     }
 }
 
+// The pattern table of antenna ant's measured aperture (a heterogeneous
+// array gives each antenna one of several).
+__device__ __forceinline__ const float4* ap_table(const ItemArgs& a, int ant)
+{
+    return a.ap_ant == nullptr ? a.ap_tab : a.ap_tab + (size_t)a.ap_ant[ant] * a.ap_n * a.ap_n;
+}
+
 // A measured aperture's pattern and gradient at table coordinates (x, y)
 // (nodes, along the mount frame's l and m), by bicubic Hermite interpolation
-// of the node values and derivatives: E, and dE/dx, dE/dy per node step.
-// Coordinates beyond the table, or not finite, are clamped to its edge.
+// of the node values and derivatives of table tab: E, and dE/dx, dE/dy per
+// node step.  Coordinates beyond the table, or not finite, are clamped to
+// its edge.
 template <bool DERIV>
-__device__ __forceinline__ void ap_eval(const ItemArgs& a, float x, float y, float& e, float& ex, float& ey)
+__device__ __forceinline__ void ap_eval(const ItemArgs& a, const float4* tab, float x, float y, float& e,
+                                        float& ex, float& ey)
 {
     const float top = (float)(a.ap_n - 1);
     x = fminf(fmaxf(x, 0.f), top);  // fmaxf(NaN, 0) = 0
     y = fminf(fmaxf(y, 0.f), top);
     const int i = min((int)x, a.ap_n - 2), j = min((int)y, a.ap_n - 2);
     const float t = x - (float)i, u = y - (float)j;
-    const float4* p = a.ap_tab + (size_t)i * a.ap_n + j;
+    const float4* p = tab + (size_t)i * a.ap_n + j;
     const float4 f00 = p[0], f01 = p[1], f10 = p[a.ap_n], f11 = p[a.ap_n + 1];
     // cubic Hermite basis: value at 0 / 1 (h0, h1), slope at 0 / 1 (g0, g1)
     const float t2 = t * t, t3 = t2 * t, u2 = u * u, u3 = u2 * u;
@@ -285,12 +294,12 @@ __device__ __forceinline__ void ap_eval(const ItemArgs& a, float x, float y, flo
 // mount; the derivatives are those with respect to the beam centre in the
 // mount frame, -grad T there.  s = D / (lambda * table step).
 template <bool DERIV>
-__device__ __forceinline__ void efp_ap(const ItemArgs& a, float s, float cs, float sn, float dl, float dm,
-                                       float& e, float& el, float& em)
+__device__ __forceinline__ void efp_ap(const ItemArgs& a, const float4* tab, float s, float cs, float sn, float dl,
+                                       float dm, float& e, float& el, float& em)
 {
     const float x = fmaf(cs * dl + sn * dm, s, a.ap_c), y = fmaf(cs * dm - sn * dl, s, a.ap_c);
     float ex = 0.f, ey = 0.f;
-    ap_eval<DERIV>(a, x, y, e, ex, ey);
+    ap_eval<DERIV>(a, tab, x, y, e, ex, ey);
     if constexpr (DERIV) {
         el = -s * ex;
         em = -s * ey;
@@ -311,18 +320,19 @@ __device__ __forceinline__ BeamK beam_k(float kk, float inv_s2, float aps, float
     return BeamK{kk * r, inv_s2 * r * r, aps * r, r};
 }
 
-// Image-plane products as mf_products, for a measured aperture, with the
-// derivative variants already with respect to the mount-frame offsets (and
-// dE/dsigma = (d . dE/dc) / sigma with d in the mount frame).
+// Image-plane products as mf_products, for measured apertures (antenna i's
+// table ti, antenna j's tj), with the derivative variants already with
+// respect to the mount-frame offsets (and dE/dsigma = (d . dE/dc) / sigma
+// with d in the mount frame).
 template <int MODE>
-__device__ __forceinline__ void mf_products_ap(const ItemArgs& a, const BeamK& bi, const BeamK& bj, float cs,
-                                               float sn, float dli, float dmi, float dlj, float dmj, float c,
-                                               float (&g)[mode_nv(MODE)])
+__device__ __forceinline__ void mf_products_ap(const ItemArgs& a, const float4* ti, const float4* tj,
+                                               const BeamK& bi, const BeamK& bj, float cs, float sn, float dli,
+                                               float dmi, float dlj, float dmj, float c, float (&g)[mode_nv(MODE)])
 {
     constexpr bool D = mode_nv(MODE) > 1;
     float ei, eil = 0.f, eim = 0.f, ej, ejl = 0.f, ejm = 0.f;
-    efp_ap<D>(a, bi.aps, cs, sn, dli, dmi, ei, eil, eim);
-    efp_ap<D>(a, bj.aps, cs, sn, dlj, dmj, ej, ejl, ejm);
+    efp_ap<D>(a, ti, bi.aps, cs, sn, dli, dmi, ei, eil, eim);
+    efp_ap<D>(a, tj, bj.aps, cs, sn, dlj, dmj, ej, ejl, ejm);
     if constexpr (!D) {
         g[0] = ei * ej * c;
     } else if constexpr (MODE == kScale) {

@@ -374,8 +374,10 @@ __global__ void __launch_bounds__(kGridThreads) k_gridw(ItemArgs a)
                             const float l = (float)nl * hstep, mm = (float)nmv * hstep;
                             if constexpr (MF == kFrameAperture) {
                                 float ei, ej, unused;
-                                efp_ap<false>(a, bki.aps, cs, sn, l - pil, mm - pim, ei, unused, unused);
-                                efp_ap<false>(a, bkj.aps, cs, sn, l - pjl, mm - pjm, ej, unused, unused);
+                                efp_ap<false>(a, ap_table(a, it.ai), bki.aps, cs, sn, l - pil, mm - pim, ei,
+                                              unused, unused);
+                                efp_ap<false>(a, ap_table(a, it.aj), bkj.aps, cs, sn, l - pjl, mm - pjm, ej,
+                                              unused, unused);
                                 gv = ei * ej * (a.taper_img[nl + half_m] * a.taper_img[nmv + half_m]);
                             } else if constexpr (MF == kFrameMount) {
                                 float ei, qi, ej, qj;

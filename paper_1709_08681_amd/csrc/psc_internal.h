@@ -122,10 +122,13 @@ struct ItemArgs {
     const float2* wgrid;
     double w_dw;
     int32_t w_k0, w_nk;
-    // measured aperture (illum 2): its transform on [ap_n][ap_n] nodes in
-    // lambda/D units, (T, s dT/du, s dT/dv, s^2 d2T/dudv) at u = (i - ap_c) s,
-    // s = 1 / ap_inv_step, i along the mount frame's l axis
+    // measured apertures (illum 2): each one's transform on [ap_n][ap_n]
+    // nodes in lambda/D units, (T, s dT/du, s dT/dv, s^2 d2T/dudv) at
+    // u = (i - ap_c) s, s = 1 / ap_inv_step, i along the mount frame's l
+    // axis, stacked [n_apertures][ap_n][ap_n]; ap_ant (nullable [n_ant])
+    // names each antenna's (null: the first)
     const float4* ap_tab;
+    const int32_t* ap_ant;
     int32_t ap_n;
     float ap_c;
     float ap_inv_step;

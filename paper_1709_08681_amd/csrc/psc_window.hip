@@ -153,8 +153,9 @@ __device__ __forceinline__ void image_factors_cx(const ItemArgs& a, float* gsh, 
 // them here from the Airy table tab.
 template <int MODE, bool AP, bool HW>
 __device__ __forceinline__ void image_factors(const ItemArgs& a, const float4* tab, const float2* pi,
-                                              const float2* pj, float* gsh, const BeamK& bi, const BeamK& bj,
-                                              float pil, float pim, float pjl, float pjm, int tid, int nthr)
+                                              const float2* pj, int ai, int aj, float* gsh, const BeamK& bi,
+                                              const BeamK& bj, float pil, float pim, float pjl, float pjm, int tid,
+                                              int nthr)
 {
     constexpr int NG = AP ? mode_nv(MODE) : win_ng(MODE);
     const int m = a.m, half_m = m >> 1, m2 = m * m;
@@ -171,7 +172,7 @@ __device__ __forceinline__ void image_factors(const ItemArgs& a, const float4* t
         if constexpr (AP) {
             // the sky frame is the mount frame at angle zero
             float g[mode_nv(MODE)];
-            mf_products_ap<MODE>(a, bi, bj, 1.f, 0.f, dli, dmi, dlj, dmj, c, g);
+            mf_products_ap<MODE>(a, ap_table(a, ai), ap_table(a, aj), bi, bj, 1.f, 0.f, dli, dmi, dlj, dmj, c, g);
 #pragma unroll
             for (int k = 0; k < NG; ++k) gn[k] = g[k];
         } else {
@@ -483,9 +484,9 @@ __global__ void __launch_bounds__(64 * W, S == 16 && MF == kFrameMount ? 3 : 1) 
                 pi = a.beams + (t0 + it.ai) * (size_t)(a.m * a.m);
                 pj = a.beams + (t0 + it.aj) * (size_t)(a.m * a.m);
             }
-            image_factors<MODE, MF == kFrameSkyAperture, S == 32>(a, tlds ? airy_sh : a.airy, pi, pj, gsh, bki, bkj,
-                                                                   (float)qil, (float)qim, (float)qjl, (float)qjm,
-                                                                   tid, kBlock);
+            image_factors<MODE, MF == kFrameSkyAperture, S == 32>(a, tlds ? airy_sh : a.airy, pi, pj, it.ai, it.aj,
+                                                                   gsh, bki, bkj, (float)qil, (float)qim,
+                                                                   (float)qjl, (float)qjm, tid, kBlock);
         }
         __syncthreads();
 
@@ -563,14 +564,19 @@ __global__ void __launch_bounds__(64 * W, S == 16 && MF == kFrameMount ? 3 : 1) 
                 sincosf((float)a.par_angle[e0.vidx / (uint32_t)a.n_chan], &sn, &cs);
                 const float pil = (float)(cs * qil - sn * qim), pim = (float)(sn * qil + cs * qim);
                 const float pjl = (float)(cs * qjl - sn * qjm), pjm = (float)(sn * qjl + cs * qjm);
+                const float4 *api = nullptr, *apj = nullptr;  // the two antennas' aperture tables
+                if constexpr (MF == kFrameAperture) {
+                    api = ap_table(a, it.ai);
+                    apj = ap_table(a, it.aj);
+                }
                 auto term = [&](int jl, float2 (&acc)[NV]) {
                     const float l = (float)(jl - half_m) * hstep;
                     float2 t = wt[((jl - half_m) & (S - 1)) * SP + c];
                     if constexpr (WT) t = cmul(t, wphase(w0, l));
                     float g[NV];
                     if constexpr (MF == kFrameAperture)
-                        mf_products_ap<MODE>(a, bki, bkj, cs, sn, l - pil, mmy - pim, l - pjl, mmy - pjm,
-                                             a.taper_img[jl] * ctm, g);
+                        mf_products_ap<MODE>(a, api, apj, bki, bkj, cs, sn, l - pil, mmy - pim, l - pjl,
+                                             mmy - pjm, a.taper_img[jl] * ctm, g);
                     else
                         mf_products<MODE>(a, airy_sh, bki, bkj, l - pil, mmy - pim, l - pjl, mmy - pjm,
                                           a.taper_img[jl] * ctm, g);

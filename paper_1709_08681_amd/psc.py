@@ -46,7 +46,7 @@ class Config(C.Structure):
         ("image_samples", C.c_int32), ("cell_rad", C.c_double), ("dish_diam_m", C.c_double),
         ("illum", C.c_int32), ("gauss_sigma_ld", C.c_double), ("squint_frac", C.c_double),
         ("taper_width", C.c_int32), ("taper_beta", C.c_double), ("device", C.c_int32),
-        ("aperture_n", C.c_int32), ("aperture", C.c_void_p),
+        ("aperture_n", C.c_int32), ("aperture", C.c_void_p), ("aperture_count", C.c_int32),
     ]
 
 
@@ -60,7 +60,7 @@ class ObsDesc(C.Structure):
         ("n_ant", C.c_int32), ("n_chan", C.c_int32), ("n_pol", C.c_int32), ("n_int", C.c_int32),
         ("n_row", C.c_int64), ("int_row_ptr", C.c_void_p), ("ant1", C.c_void_p),
         ("ant2", C.c_void_p), ("uv_m", C.c_void_p), ("freq_hz", C.c_void_p),
-        ("par_angle", C.c_void_p), ("w_m", C.c_void_p),
+        ("par_angle", C.c_void_p), ("w_m", C.c_void_p), ("ant_aperture", C.c_void_p),
     ]
 
 
@@ -290,17 +290,18 @@ def psc_tune(ctx, obs, offsets_dev, vis_obs_dev, weight_dev, repeats=3, stream=N
 
 def config_for(obs, device=0, aperture=None, **kw) -> Config:
     """Config of a synthetic observation; ``aperture`` (a square float64
-    array, kept alive by the caller until psc_create returns) selects the
-    measured-aperture mode (illum 2)."""
+    array, or a stack [count, n, n] of them, kept alive by the caller until
+    psc_create returns) selects the measured-aperture mode (illum 2)."""
     wl = obs.wl
     cfg = Config(grid_n=obs.grid_n, support=wl.support, oversample=wl.oversample, image_samples=0,
                  cell_rad=obs.cell_rad, dish_diam_m=wl.dish_diam_m, illum=0, gauss_sigma_ld=1.0,
                  squint_frac=wl.squint_frac, taper_width=wl.es_width, taper_beta=0.0, device=device,
-                 aperture_n=0, aperture=None)
+                 aperture_n=0, aperture=None, aperture_count=0)
     if aperture is not None:
         cfg.illum = 2
-        cfg.aperture_n = int(aperture.shape[0])
+        cfg.aperture_n = int(aperture.shape[-1])
         cfg.aperture = aperture.ctypes.data
+        cfg.aperture_count = int(aperture.shape[0]) if aperture.ndim == 3 else 1
     for k, v in kw.items():
         setattr(cfg, k, v)
     return cfg
@@ -315,11 +316,13 @@ class Session:
     parallactic angle (``obs.par_angle``) carries them onto the sky; with
     ``w_term`` every row's w (``obs.w_m``) enters the measurement equation;
     ``aperture`` (square, real, even) gives every antenna that measured
-    aperture illumination, whose pattern turns with the mount.
+    aperture illumination, whose pattern turns with the mount; a stack
+    [count, n, n] with ``ant_aperture`` [n_ant] gives each antenna its own
+    (a heterogeneous array).
     """
 
     def __init__(self, obs, device=0, image=None, mount_frame=False, w_term=False, aperture=None,
-                 **cfg_overrides):
+                 ant_aperture=None, **cfg_overrides):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libpsc needs a ROCm GPU; none is visible")
@@ -327,8 +330,8 @@ class Session:
         self.dev = torch.device("cuda", device)
         self.obs = obs
         ap = None if aperture is None else np.ascontiguousarray(aperture, dtype=np.float64)
-        if ap is not None and (ap.ndim != 2 or ap.shape[0] != ap.shape[1]):
-            raise ValueError("aperture must be a square array")
+        if ap is not None and (ap.ndim not in (2, 3) or ap.shape[-2] != ap.shape[-1]):
+            raise ValueError("aperture must be a square array or a stack of them")
         self.cfg = config_for(obs, device=device, aperture=ap, **cfg_overrides)
         self.ctx = psc_create(self.cfg)
         self.cfg.aperture = None  # read by psc_create only
@@ -346,11 +349,13 @@ class Session:
             # mount-frame offsets: every row's parallactic angle
             self.g_pa = t(obs.par_angle, torch.float64) if mount_frame else None
             self.g_w = t(obs.w_m, torch.float64) if w_term else None
+            self.g_apa = None if ant_aperture is None else t(ant_aperture, torch.int32)
             desc = ObsDesc(obs.n_ant, obs.n_chan, obs.n_pol, obs.n_int, obs.n_row,
                            self.g_ptr.data_ptr(), self.g_a1.data_ptr(), self.g_a2.data_ptr(),
                            self.g_uv.data_ptr(), self.g_fr.data_ptr(),
                            self.g_pa.data_ptr() if mount_frame else None,
-                           self.g_w.data_ptr() if w_term else None)
+                           self.g_w.data_ptr() if w_term else None,
+                           None if self.g_apa is None else self.g_apa.data_ptr())
             self.handle = psc_obs_create(self.ctx, desc)
         except Exception:
             self.close()

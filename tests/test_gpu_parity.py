@@ -1243,6 +1243,80 @@ def test_measured_aperture_predict_gradient_vjp_image(torch_dev, S, over, mount)
         s.close()
 
 
+def _aperture_stack():
+    """Three different illuminations for a heterogeneous array."""
+    return np.stack([synth.measured_aperture(seed=31),
+                     synth.measured_aperture(seed=32, blockage_frac=0.15, n_legs=3, leg_angle_deg=10.0),
+                     synth.measured_aperture(seed=33, blockage_frac=0.0, n_legs=0, edge_taper=0.1)])
+
+
+@pytest.mark.parametrize("S,over,mount", [(16, 4, True), (16, 4, False), (32, 8, True)])
+def test_heterogeneous_apertures_predict_gradient_vjp_image(torch_dev, S, over, mount):
+    """Each antenna with one of three measured apertures (Sec. 3, the
+    heterogeneous array): prediction, model, sums, the adjoint and the image
+    gradient against the oracle, mount and sky frame, both supports."""
+    torch = torch_dev
+    from paper_1709_08681_amd import psc
+    print(f"case: heterogeneous apertures, S {S}, O {over}, mount {mount}", flush=True)
+    obs = _aperture_obs(S, over)
+    stack = _aperture_stack()
+    ant_ap = np.array([2, 0, 1, 1, 0, 2, 1], np.int32)[:obs.n_ant]
+    prob = oracle.Problem.from_observation(obs, mount_frame=mount, illum=2, aperture=stack, ant_aperture=ant_ap)
+    s = session(obs, mount_frame=mount, aperture=stack, ant_aperture=ant_ap)
+    try:
+        assert psc.psc_get_degrid(s.handle) == psc.DEGRID_WINDOW
+        v = oracle.predict(prob, obs.offsets_true)
+        v_one = oracle.predict(oracle.Problem.from_observation(obs, mount_frame=mount, illum=2, aperture=stack[0]),
+                               obs.offsets_true)
+        assert rel(v_one, v) > 1e-3  # the assignment matters
+        start = synth.perturbed_offsets(obs, 25.0, 71)
+        assert rel(s.predict(start).cpu().numpy(), oracle.predict(prob, start)) <= 1e-5
+        nz, w = synth.noise(v, 100.0, 72)
+        ref, vm_ref = oracle.gradient(prob, start, v + nz, w, want_model=True)
+        acc, vm = s.gradient(s.offsets(start), c64(torch, s, v + nz), f32(torch, s, w, s.vis_shape),
+                             want_model=True)
+        assert rel(vm.cpu().numpy(), vm_ref) <= 1e-5
+        vm = vm.cpu().numpy()
+        assert elem_err(vm, vm_ref) <= ELEM_VIS_TOL
+        acc = acc.cpu().numpy()
+        for k in range(6):
+            assert rel(acc[..., k], ref[..., k]) <= 1e-4, k
+        rng = np.random.default_rng(73)
+        G = (rng.normal(size=s.vis_shape) + 1j * rng.normal(size=s.vis_shape)).astype(np.complex64)
+        got = s.vjp(s.offsets(start), torch.as_tensor(G, device=s.dev)).cpu().numpy()
+        assert rel(got, vjp_reference(obs, prob, start, G, s.off_shape)) <= 1e-4
+        _check_image_gradient(torch, obs, prob, s, start, v + nz, w, 32, 74)
+        # beam scales below 1 rebuild every aperture's table (0.9: above the
+        # floor of both supports, about 0.68 at 16 and 0.86 at 32 here)
+        sc = np.random.default_rng(75).uniform(0.9, 1.05, (obs.n_int, obs.n_pol, obs.n_ant))
+        s.set_beam_scale(sc)
+        prob_s = oracle.Problem.from_observation(obs, mount_frame=mount, illum=2, aperture=stack,
+                                                 ant_aperture=ant_ap, beam_scale=sc)
+        assert rel(s.predict(start).cpu().numpy(), oracle.predict(prob_s, start)) <= 1e-5
+    finally:
+        s.close()
+
+
+def test_heterogeneous_aperture_map_errors(torch_dev):
+    from paper_1709_08681_amd import psc
+    print("case: heterogeneous aperture map validation", flush=True)
+    obs = _aperture_obs(16, 4)
+    stack = _aperture_stack()
+    bad = np.zeros(obs.n_ant, np.int32)
+    bad[3] = 3  # three apertures: 0..2
+    with pytest.raises(psc.PscError) as ei:
+        session(obs, aperture=stack, ant_aperture=bad)
+    assert ei.value.status == psc.PSC_E_ARG
+    with pytest.raises(psc.PscError) as ei:
+        session(obs, ant_aperture=np.zeros(obs.n_ant, np.int32))  # no measured aperture
+    assert ei.value.status == psc.PSC_E_ARG
+    odd = stack.copy()
+    odd[1, 2, 5] += 0.5  # the second aperture is not even
+    with pytest.raises(psc.PscError) as ei:
+        session(obs, aperture=odd, ant_aperture=np.zeros(obs.n_ant, np.int32))
+    assert ei.value.status == psc.PSC_E_ARG
+
+
 def test_measured_aperture_solve(torch_dev):
     """Algorithm 1 with the measured aperture in the mount frame: the same
     iterations and offsets as the oracle's solve, plain and graph forms
