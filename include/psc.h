@@ -207,8 +207,10 @@ PSC_API psc_status psc_set_model(psc_ctx* ctx, const double* image_dev, void* st
  * radial beams) the scratch includes every antenna's pattern and gradient
  * factor at the M x M image samples per interval, polarisation and channel,
  * n_int n_pol n_chan n_ant M^2 x 8 bytes, which the window form fills before
- * each degrid (Eq. DA per antenna, shared by its baselines); above 16 GiB
- * it is left out and each work item evaluates its two antennas' patterns.
+ * each degrid (Eq. DA per antenna, shared by its baselines) while one
+ * interval's share stays within 8 MiB (its tables then stay in L2) and the
+ * whole within 16 GiB; otherwise it is left out and each work item
+ * evaluates its two antennas' patterns.
  * Calls on one observation share this scratch and must not overlap.
  * Returns PSC_E_ARG for inconsistent indices (ant1 >= ant2, out of range,
  * non-monotone int_row_ptr).

@@ -201,8 +201,15 @@ int floor_div(long long a, int b)
 
 }  // namespace
 
-// largest per-antenna pattern table an observation allocates (16 GiB: one
-// GPU's 32-channel share of the large workload needs 9.7 GB)
+// Per-antenna pattern tables are used while one interval's tables (all
+// polarisations, channels and antennas) stay within 8 MiB, about two XCDs'
+// L2: items run interval by interval, and an item reads its second
+// antenna's tables cold.  The batched workload needs 2 MB per interval
+// (2.4% faster per gradient); one GPU's share of the large workload would
+// need 75 MB per interval and fetched 734 GB per launch from HBM for no
+// gain, so its items evaluate their own patterns.  The whole allocation is
+// capped at 16 GiB.
+constexpr size_t kBeamTabIntervalBytes = size_t(8) << 20;
 constexpr size_t kBeamTabBytes = size_t(16) << 30;
 
 // Scratch of the allocation-free gradient (psc_gradient_noalloc): the
@@ -852,11 +859,14 @@ static psc_status obs_create_impl(psc_ctx* ctx, const psc_obs_desc* d, psc_obs**
     if (e == hipSuccess) e = dmalloc(&obs->airy, n_tab);
     // sky-frame radial beams: room for every antenna's pattern at the image
     // samples per interval, polarisation and channel, which the window form
-    // fills before each degrid (at most kBeamTabBytes; beyond that each item
-    // evaluates its antennas' patterns itself)
+    // fills before each degrid (within kBeamTabIntervalBytes per interval
+    // and kBeamTabBytes in all; beyond that each item evaluates its
+    // antennas' patterns itself)
     {
-        const size_t nb = (size_t)n_int * d->n_pol * n_chan * n_ant * (size_t)ctx->m * ctx->m;
-        if (e == hipSuccess && pa.empty() && !ap && nb > 0 && nb * sizeof(float2) <= kBeamTabBytes)
+        const size_t per_int = (size_t)d->n_pol * n_chan * n_ant * (size_t)ctx->m * ctx->m;
+        const size_t nb = (size_t)n_int * per_int;
+        if (e == hipSuccess && pa.empty() && !ap && nb > 0 && per_int * sizeof(float2) <= kBeamTabIntervalBytes &&
+            nb * sizeof(float2) <= kBeamTabBytes)
             e = dmalloc(&obs->beams, nb);
     }
     if (e == hipSuccess) e = dmalloc(&obs->partials, items.size() * d->n_pol * 12);

@@ -347,7 +347,7 @@ __global__ void __launch_bounds__(64 * W, S == 16 && MF == kFrameMount ? 3 : 1) 
     // the Airy table: in LDS for the mount frame's per-sample lookups, and
     // for the sky frame's image-plane factors when it fits beside two blocks
     // (support 32) and the antennas' patterns are not tabulated
-    const bool btab = MF == kFrameSky && a.beams != nullptr;
+    const bool btab = MF == kFrameSky && S == 16 && a.beams != nullptr;
     const bool tlds = MF == kFrameMount || (MF == kFrameSky && S == 32 && a.tab_lds && !btab);
     if (tlds)
         for (int t = tid; t < a.n_tab; t += kBlock) airy_sh[t] = a.airy[t];
@@ -479,10 +479,12 @@ __global__ void __launch_bounds__(64 * W, S == 16 && MF == kFrameMount ? 3 : 1) 
                                    (float)qim, (float)qjl, (float)qjm, tid, kBlock);
         } else if constexpr (SKY) {
             const float2 *pi = nullptr, *pj = nullptr;
-            if (btab) {
-                const size_t t0 = (((size_t)it.interval * a.n_pol + pol) * a.n_chan + it.chan) * a.n_ant;
-                pi = a.beams + (t0 + it.ai) * (size_t)(a.m * a.m);
-                pj = a.beams + (t0 + it.aj) * (size_t)(a.m * a.m);
+            if constexpr (S == 16) {  // tables only at support 16 (none compiled at 32)
+                if (btab) {
+                    const size_t t0 = (((size_t)it.interval * a.n_pol + pol) * a.n_chan + it.chan) * a.n_ant;
+                    pi = a.beams + (t0 + it.ai) * (size_t)(a.m * a.m);
+                    pj = a.beams + (t0 + it.aj) * (size_t)(a.m * a.m);
+                }
             }
             image_factors<MODE, MF == kFrameSkyAperture, S == 32>(a, tlds ? airy_sh : a.airy, pi, pj, it.ai, it.aj,
                                                                    gsh, bki, bkj, (float)qil, (float)qim,
@@ -944,8 +946,10 @@ hipError_t launch_ant_beams(int support, const ItemArgs& a, hipStream_t s)
 hipError_t launch_win(int mode, int support, const ItemArgs& a, hipStream_t s)
 {
     if (a.n_items <= 0) return hipSuccess;
-    // the sky frame with radial beams: tabulate each antenna's pattern first
-    if (a.beams != nullptr && a.par_angle == nullptr && a.ap_tab == nullptr && a.defocus == nullptr) {
+    // the sky frame with radial beams at support 16: tabulate each
+    // antenna's pattern first
+    if (support == 16 && a.beams != nullptr && a.par_angle == nullptr && a.ap_tab == nullptr &&
+        a.defocus == nullptr) {
         const hipError_t e = launch_ant_beams(support, a, s);
         if (e != hipSuccess) return e;
     }
