@@ -242,6 +242,10 @@ PSC_API psc_status psc_obs_info(const psc_obs* obs, int64_t* n_items, int64_t* n
  *                     for scales below 1)
  *   capture_ms        host wall time the last graph-form psc_solve spent
  *                     capturing and instantiating its graph (0 before any)
+ *   pattern_tables    1 when the window form reads every antenna's pattern
+ *                     from per-antenna tables filled before each degrid
+ *                     (sky frame, radial beams, support 16, one interval's
+ *                     tables within 8 MiB; see psc_obs_create), else 0
  * PSC_E_ARG for a null observation or output.
  */
 typedef struct {
@@ -252,6 +256,8 @@ typedef struct {
     int32_t w_planes;
     int32_t tab_nodes;
     double capture_ms;
+    int32_t pattern_tables;
+    int32_t reserved;
 } psc_launch_info;
 PSC_API psc_status psc_obs_launch_info(const psc_obs* obs, psc_launch_info* out);
 

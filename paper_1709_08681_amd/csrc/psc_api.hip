@@ -972,6 +972,8 @@ PSC_API psc_status psc_obs_launch_info(const psc_obs* obs, psc_launch_info* out)
     out->w_planes = obs->w_nk;
     out->tab_nodes = obs->n_tab;
     out->capture_ms = obs->capture_ms;
+    out->pattern_tables = (obs->beams != nullptr && ctx->s == 16 && !obs->par_angle && !obs->ap_tab) ? 1 : 0;
+    out->reserved = 0;
     return PSC_OK;
 }
 

@@ -1031,6 +1031,34 @@ def test_w_stacking_follows_the_model(torch_dev):
         s.close()
 
 
+def test_pattern_tables_only_where_an_interval_fits(torch_dev):
+    """Per-antenna pattern tables: used by the sky frame at support 16 while
+    one interval's tables (pols x channels x antennas x M^2 x 8 bytes) fit
+    8 MiB; the mount frame, support 32 and larger arrays evaluate patterns
+    per item.  Both paths agree with the oracle (the parity tests above run
+    each); here the rule itself."""
+    from paper_1709_08681_amd import psc
+    print("case: pattern-table rule", flush=True)
+    small = synth.make_config(3).subset(ants=range(6), times=range(20))  # 1 x 16 x 6 x 576 x 8 B
+    s = session(small)
+    try:
+        assert psc.psc_obs_launch_info(s.handle)["pattern_tables"] == 1
+    finally:
+        s.close()
+    s = session(small, mount_frame=True)
+    try:
+        assert psc.psc_obs_launch_info(s.handle)["pattern_tables"] == 0
+    finally:
+        s.close()
+    # 64 antennas x 64 channels: 18.9 MB per interval
+    big = synth.make_config(4).subset(times=range(2))
+    s = session(big)
+    try:
+        assert psc.psc_obs_launch_info(s.handle)["pattern_tables"] == 0
+    finally:
+        s.close()
+
+
 def test_w_stacking_beyond_its_limit_is_refused(torch_dev):
     """Baselines of 10,000 km: the w-planes would need far more than 2 GiB of
     model grids; refused, while the same observation without w plans."""
