@@ -898,8 +898,8 @@ size_t win_lds_budget(int support)
 // item of the sky frame otherwise evaluates for its two antennas, once per
 // antenna instead of once per baseline.  One block per table; the same
 // offsets, squint and width scale as the degrid kernel's items, evaluated
-// by the same efq.  Intervals already converged (done) are skipped.
-template <bool HW>
+// by the same efq (support 16: the correctly rounded square root).
+// Intervals already converged (done) are skipped.
 __global__ void __launch_bounds__(256) k_ant_beams(ItemArgs a)
 {
     const int t = (int)blockIdx.x;
@@ -926,20 +926,17 @@ __global__ void __launch_bounds__(256) k_ant_beams(ItemArgs a)
         const int il = (int)(((float)idx + 0.5f) * inv_m), im = idx - il * m;
         const float l = (float)(il - half_m) * hstep, mm = (float)(im - half_m) * hstep;
         float e, q;
-        efq<HW>(a, a.airy, b.kk, b.inv_s2, l - pl, mm - pm, e, q);
+        efq<false>(a, a.airy, b.kk, b.inv_s2, l - pl, mm - pm, e, q);
         out[idx] = make_float2(e, q);
     }
 }
 
-hipError_t launch_ant_beams(int support, const ItemArgs& a, hipStream_t s)
+hipError_t launch_ant_beams(const ItemArgs& a, hipStream_t s)
 {
     const long long n = (long long)(a.beam_int1 - a.beam_int0) * a.n_pol * a.n_chan * a.n_ant;
     if (n <= 0) return hipSuccess;
     if (n > 0x7fffffffLL) return hipErrorInvalidValue;
-    if (support == 32)
-        k_ant_beams<true><<<(unsigned)n, 256, 0, s>>>(a);
-    else
-        k_ant_beams<false><<<(unsigned)n, 256, 0, s>>>(a);
+    k_ant_beams<<<(unsigned)n, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -950,7 +947,7 @@ hipError_t launch_win(int mode, int support, const ItemArgs& a, hipStream_t s)
     // antenna's pattern first
     if (support == 16 && a.beams != nullptr && a.par_angle == nullptr && a.ap_tab == nullptr &&
         a.defocus == nullptr) {
-        const hipError_t e = launch_ant_beams(support, a, s);
+        const hipError_t e = launch_ant_beams(a, s);
         if (e != hipSuccess) return e;
     }
     if (support == 16) {
