@@ -148,6 +148,7 @@ struct ItemArgs {
     // blocks by LDS alone
     int32_t win_waves;
     int32_t tab_lds;            // window form: the Airy table is staged in LDS (set by the launcher)
+    int32_t unit_items;         // window form: consecutive items per block (set by the launcher)
     // window form, sky frame, radial beams: every antenna's pattern and
     // gradient factor (E, q) at the image samples, [n_int][n_pol][n_chan]
     // [n_ant][m^2], filled for intervals [beam_int0, beam_int1) before the

@@ -257,6 +257,21 @@ __device__ __forceinline__ void halves(float v, float& lo, float& hi)
     }
 }
 
+// Whether a launch may give each block several consecutive items: the
+// sky-frame variants at support 32, whose set-up (twiddles, Airy table) is
+// largest against an item's work.
+__host__ __device__ constexpr bool win_multi_item(int S, int MF)
+{
+    return S == 32 && MF == kFrameSky;
+}
+
+// Wavefronts per SIMD the window kernel asks the compiler to fit.
+__host__ __device__ constexpr int win_min_waves(int S, int MF, bool WT)
+{
+    return S == 16 && (MF == kFrameMount || (WT && MF == kFrameSky)) ? 3
+         : S == 32 && MF == kFrameMount && !WT ? 2 : 1;
+}
+
 // ---------------------------------------------------------------------------
 // Workers of 2S lanes: a wavefront per sample at support 32, half a wavefront
 // at support 16.
@@ -286,9 +301,12 @@ __device__ __forceinline__ void halves(float v, float& lo, float& hi)
 // default 3S/2, sky frame), 0 to read it from the arguments; fixed, the
 // image-sample sums run with constant trip counts.  The mount frame at
 // support 16 asks for three wavefronts per SIMD (a few registers spill;
-// 13% faster on the single-interval workload than two).
+// 13% faster on the single-interval workload than two), and so does the
+// sky frame's w-term, which needs a register or two more than three allow;
+// the mount frame at support 32 asks for two (without the bound its
+// gradient spills into accumulation registers and runs at one).
 template <int S, int MODE, int MF, int W, bool WT, int MT = 0>
-__global__ void __launch_bounds__(64 * W, S == 16 && MF == kFrameMount ? 3 : 1) k_winw(ItemArgs a)
+__global__ void __launch_bounds__(64 * W, win_min_waves(S, MF, WT)) k_winw(ItemArgs a)
 {
     constexpr int H = S / 2, SP = S + 1;
     constexpr int SL = 2 * S;    // lanes per worker
@@ -326,11 +344,15 @@ __global__ void __launch_bounds__(64 * W, S == 16 && MF == kFrameMount ? 3 : 1) 
     float4* airy_sh = reinterpret_cast<float4*>(ybuf + (YLDS ? (size_t)H * kBlock : 0));
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int li = item_of_block();
-    if (li >= a.n_items) return;
-    const int item_idx = a.item_begin + li;
-    const Item it = a.items[item_idx];
-    if (a.done != nullptr && a.done[it.interval]) return;
+    // the block's items: in the sky frame at support 32, unit_items
+    // consecutive ones, which share the block's set-up below (the twiddles
+    // and the Airy table in LDS); otherwise one (a loop over items costs the
+    // other variants registers, and some of them a wavefront per SIMD)
+    constexpr bool MULTI = win_multi_item(S, MF);
+    const int R = MULTI && a.unit_items > 1 ? a.unit_items : 1;
+    const long long li0_wide = (long long)item_of_block() * R;
+    if (li0_wide >= a.n_items) return;
+    const int li0 = (int)li0_wide;
 
     const int N = a.grid_n;
     const float inv_s = 1.0f / (float)S;
@@ -352,393 +374,404 @@ __global__ void __launch_bounds__(64 * W, S == 16 && MF == kFrameMount ? 3 : 1) 
     if (tlds)
         for (int t = tid; t < a.n_tab; t += kBlock) airy_sh[t] = a.airy[t];
     __syncthreads();
+    auto one_item = [&](const int li) {
+        if (li >= a.n_items) return;
+        const int item_idx = a.item_begin + li;
+        const Item it = a.items[item_idx];
+        if (a.done != nullptr && a.done[it.interval]) return;
 
-    const int sl = lane & (SL - 1);  // lane within the worker
-    const int worker = wave * SPW + lane / SL;
-    const int c = sl & (S - 1), hh = sl / S;
-    float2* wt = wtile + (size_t)worker * S * SP;  // this worker's tile
-    const TermSel tsel(sl);
-    const float2 zero = make_float2(0.f, 0.f);
-    // the lane's image-sample m index, and the l index its transform row c
-    // stands for
-    const int nm = c - hh * S;
-    const bool m_ok = nm >= -half_m && nm < half_m;
-    const int jm = m_ok ? nm + half_m : 0;
-    const int nl_row = ((c + half_m) & (S - 1)) - half_m;
-    // first radix-2 step of an S-point transform: half h keeps
-    // (x_r + (-1)^h x_{H+r}) exp(+2 pi i h r / S)
-    const float sgn = hh ? -1.f : 1.f;
-    float2 tw1[H];
-#pragma unroll
-    for (int r = 0; r < H; ++r)
-        tw1[r] = hh ? make_float2(kTw.re[(64 / S) * r], kTw.im[(64 / S) * r]) : make_float2(1.f, 0.f);
-
-    // (-1)^n exp(2 pi i f n / (S O)) / S
-    auto phase = [&](int f, int n) {
-        const float2 t = twsh[(f * n) & (so - 1)];
-        const float sg = (n & 1) ? -inv_s : inv_s;
-        return make_float2(t.x * sg, t.y * sg);
-    };
-    // The item's samples in row order (time order along the baseline's uv
-    // track), each worker a contiguous share [k_lo, k_hi): consecutive
-    // samples of one worker often fall in the same window (a track moves a
-    // fraction of a cell per integration), whose transform is then reused.
-    const int n_s = it.n_vis;
-    const int k_lo = (int)(((long long)worker * n_s) / NW), k_hi = (int)(((long long)(worker + 1) * n_s) / NW);
-    const VisEnt* went = a.wvis + it.vis_begin;
-    const uint8_t* wfp = a.wf + it.vis_begin;
-    // rows H hh + r of the reversed column c: grid row k_lo_l + S-1-(H hh + r),
-    // of w-plane `plane` when stacked
-    auto load_window = [&](const VisEnt& e, int plane, float2 (&x)[H]) {
-        const int row0 = (int)(e.klo >> 16);
-        const int col0 = (int)(e.klo & 0xffffu);
-        const int voff = plane * plane_bytes + (row0 * P + col0 + (S - 1 - c)) * (int)sizeof(float2) +
-                         (1 - hh) * H * rowbytes;
-#pragma unroll
+        const int sl = lane & (SL - 1);  // lane within the worker
+        const int worker = wave * SPW + lane / SL;
+        const int c = sl & (S - 1), hh = sl / S;
+        float2* wt = wtile + (size_t)worker * S * SP;  // this worker's tile
+        const TermSel tsel(sl);
+        const float2 zero = make_float2(0.f, 0.f);
+        // the lane's image-sample m index, and the l index its transform row c
+        // stands for
+        const int nm = c - hh * S;
+        const bool m_ok = nm >= -half_m && nm < half_m;
+        const int jm = m_ok ? nm + half_m : 0;
+        const int nl_row = ((c + half_m) & (S - 1)) - half_m;
+        // first radix-2 step of an S-point transform: half h keeps
+        // (x_r + (-1)^h x_{H+r}) exp(+2 pi i h r / S)
+        const float sgn = hh ? -1.f : 1.f;
+        float2 tw1[H];
+    #pragma unroll
         for (int r = 0; r < H; ++r)
-            x[r] = __builtin_bit_cast(
-                float2, __builtin_amdgcn_raw_buffer_load_b64(grsrc, voff, (H - 1 - r) * rowbytes, 0));
-    };
+            tw1[r] = hh ? make_float2(kTw.re[(64 / S) * r], kTw.im[(64 / S) * r]) : make_float2(1.f, 0.f);
 
-    // mount frame: beam constants of the item's channel, the lane's
-    // image-sample m coordinate and taper value
-    const double lam = kCLight / a.freq[it.chan];
-    const float kk = (float)(kPi * a.dish / lam);
-    const double sigma = a.gauss_sigma_ld * lam / a.dish;
-    const float inv_s2 = (float)(1.0 / (sigma * sigma));
-    const float aps = (float)(a.dish / lam * a.ap_inv_step);  // aperture table nodes per radian
-    const float hstep = (float)a.h;
-    const float mmy = (float)nm * hstep;
-    // w-term: w in wavelengths per metre at the item's channel, and the
-    // lane's m^2
-    const double w_per_m = a.freq[it.chan] / kCLight;
-    const float mm2 = mmy * mmy;
-    // exp(2 pi i w (n - 1)) at (l, lane's m), n - 1 = -x / (1 + sqrt(1 - x)),
-    // from the hardware sine and cosine of the phase in turns reduced to
-    // [0, 1) (the phase itself is a float32 product; the parity tests bound
-    // the result)
-    // a sample's w in wavelengths, and with w-stacking its plane k (the one
-    // nearest, w_k = k dw) and the residual w - w_k that the kernel carries
-    auto wsel = [&](const VisEnt& e, float& wr, int& plane) {
-        const double wl = a.w_m[e.vidx / (uint32_t)a.n_chan] * w_per_m;
-        if (stacked) {
-            const int k = min(max((int)rint(wl / a.w_dw), a.w_k0), a.w_k0 + a.w_nk - 1);
-            wr = (float)(wl - (double)k * a.w_dw);
-            plane = k - a.w_k0;
-        } else {
-            wr = (float)wl;
-            plane = 0;
-        }
-    };
-    auto wphase = [&](float wl, float l) {
-        const float x = fmaf(l, l, mm2);
-        const float nm1 = -x * __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_sqrtf(1.f - x));
-        const float r = __builtin_amdgcn_fractf(wl * nm1);
-        return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
-    };
-    const float ctm = a.taper_img[jm];
+        // (-1)^n exp(2 pi i f n / (S O)) / S
+        auto phase = [&](int f, int n) {
+            const float2 t = twsh[(f * n) & (so - 1)];
+            const float sg = (n & 1) ? -inv_s : inv_s;
+            return make_float2(t.x * sg, t.y * sg);
+        };
+        // The item's samples in row order (time order along the baseline's uv
+        // track), each worker a contiguous share [k_lo, k_hi): consecutive
+        // samples of one worker often fall in the same window (a track moves a
+        // fraction of a cell per integration), whose transform is then reused.
+        const int n_s = it.n_vis;
+        const int k_lo = (int)(((long long)worker * n_s) / NW), k_hi = (int)(((long long)(worker + 1) * n_s) / NW);
+        const VisEnt* went = a.wvis + it.vis_begin;
+        const uint8_t* wfp = a.wf + it.vis_begin;
+        // rows H hh + r of the reversed column c: grid row k_lo_l + S-1-(H hh + r),
+        // of w-plane `plane` when stacked
+        auto load_window = [&](const VisEnt& e, int plane, float2 (&x)[H]) {
+            const int row0 = (int)(e.klo >> 16);
+            const int col0 = (int)(e.klo & 0xffffu);
+            const int voff = plane * plane_bytes + (row0 * P + col0 + (S - 1 - c)) * (int)sizeof(float2) +
+                             (1 - hh) * H * rowbytes;
+    #pragma unroll
+            for (int r = 0; r < H; ++r)
+                x[r] = __builtin_bit_cast(
+                    float2, __builtin_amdgcn_raw_buffer_load_b64(grsrc, voff, (H - 1 - r) * rowbytes, 0));
+        };
 
-    for (int pol = 0; pol < a.n_pol; ++pol) {
-        // this worker's first sample and the entry after it, the first window
-        int k0 = k_lo;
-        VisEnt e0 = {0u, 0u}, e1 = {0u, 0u};
-        int f0 = 0, f1 = 0;
-        float2 x0[H];
-        float2 vin0 = zero;
-        float wgt0 = 0.f, w0 = 0.f;
-        int pl0 = 0;
-        if (k0 < k_hi) {
-            e0 = went[k0];
-            f0 = wfp[k0];
-            const int k1 = k0 + 1 < k_hi ? k0 + 1 : k0;  // past the end: the last (loads stay in bounds)
-            e1 = went[k1];
-            f1 = wfp[k1];
-            if constexpr (WT) wsel(e0, w0, pl0);
-            load_window(e0, pl0, x0);
-            const size_t o0 = (size_t)e0.vidx * a.n_pol + pol;
-            if (MODE != kPredict) vin0 = a.vis_in[o0];
-            if (MODE == kGrad || MODE == kScale) wgt0 = a.weight[o0];
-        }
-
-        // offsets plus squint (along l, or along the mount's first axis)
-        const double sq = (pol == 0 ? 1.0 : -1.0) * a.squint_frac * 1.02899 * lam / a.dish;
-        const double* oi = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.ai) * 2;
-        const double* oj = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.aj) * 2;
-        const double qil = oi[0] + sq, qim = oi[1], qjl = oj[0] + sq, qjm = oj[1];
-        // each antenna's beam constants with its width scale
-        BeamK bki = beam_k(kk, inv_s2, aps, 1.f), bkj = bki;
-        if (a.scale != nullptr) {
-            const double* sc = a.scale + ((size_t)it.interval * a.n_pol + pol) * a.n_ant;
-            bki = beam_k(kk, inv_s2, aps, (float)sc[it.ai]);
-            bkj = beam_k(kk, inv_s2, aps, (float)sc[it.aj]);
-        }
-        if constexpr (CPLX) {
-            const double* dfp = a.defocus + ((size_t)it.interval * a.n_pol + pol) * a.n_ant;
-            const float kgd = (float)(2.0 / (kPi * kPi * a.gauss_sigma_ld * a.gauss_sigma_ld));
-            image_factors_cx<MODE>(a, gsh, kk, inv_s2, kgd, (float)dfp[it.ai], (float)dfp[it.aj], (float)qil,
-                                   (float)qim, (float)qjl, (float)qjm, tid, kBlock);
-        } else if constexpr (SKY) {
-            const float2 *pi = nullptr, *pj = nullptr;
-            if constexpr (S == 16) {  // tables only at support 16 (none compiled at 32)
-                if (btab) {
-                    const size_t t0 = (((size_t)it.interval * a.n_pol + pol) * a.n_chan + it.chan) * a.n_ant;
-                    pi = a.beams + (t0 + it.ai) * (size_t)(a.m * a.m);
-                    pj = a.beams + (t0 + it.aj) * (size_t)(a.m * a.m);
-                }
+        // mount frame: beam constants of the item's channel, the lane's
+        // image-sample m coordinate and taper value
+        const double lam = kCLight / a.freq[it.chan];
+        const float kk = (float)(kPi * a.dish / lam);
+        const double sigma = a.gauss_sigma_ld * lam / a.dish;
+        const float inv_s2 = (float)(1.0 / (sigma * sigma));
+        const float aps = (float)(a.dish / lam * a.ap_inv_step);  // aperture table nodes per radian
+        const float hstep = (float)a.h;
+        const float mmy = (float)nm * hstep;
+        // w-term: w in wavelengths per metre at the item's channel, and the
+        // lane's m^2
+        const double w_per_m = a.freq[it.chan] / kCLight;
+        const float mm2 = mmy * mmy;
+        // exp(2 pi i w (n - 1)) at (l, lane's m), n - 1 = -x / (1 + sqrt(1 - x)),
+        // from the hardware sine and cosine of the phase in turns reduced to
+        // [0, 1) (the phase itself is a float32 product; the parity tests bound
+        // the result)
+        // a sample's w in wavelengths, and with w-stacking its plane k (the one
+        // nearest, w_k = k dw) and the residual w - w_k that the kernel carries
+        auto wsel = [&](const VisEnt& e, float& wr, int& plane) {
+            const double wl = a.w_m[e.vidx / (uint32_t)a.n_chan] * w_per_m;
+            if (stacked) {
+                const int k = min(max((int)rint(wl / a.w_dw), a.w_k0), a.w_k0 + a.w_nk - 1);
+                wr = (float)(wl - (double)k * a.w_dw);
+                plane = k - a.w_k0;
+            } else {
+                wr = (float)wl;
+                plane = 0;
             }
-            image_factors<MODE, MF == kFrameSkyAperture, S == 32>(a, tlds ? airy_sh : a.airy, pi, pj, it.ai, it.aj,
-                                                                   gsh, bki, bkj, (float)qil, (float)qim,
-                                                                   (float)qjl, (float)qjm, tid, kBlock);
-        }
-        __syncthreads();
+        };
+        auto wphase = [&](float wl, float l) {
+            const float x = fmaf(l, l, mm2);
+            const float nm1 = -x * __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_sqrtf(1.f - x));
+            const float r = __builtin_amdgcn_fractf(wl * nm1);
+            return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
+        };
+        const float ctm = a.taper_img[jm];
 
-        double acc64 = 0.0;
-        bool need0 = true;
-        float2 y[H];
-        while (k0 < k_hi) {
-            // ---- fetch ahead: the next sample's window (when it differs), its
-            // inputs, the entry after it
-            const bool more = k0 + 1 < k_hi;
-            float w1 = 0.f;
-            int pl1 = 0;
-            if constexpr (WT) wsel(e1, w1, pl1);
-            const bool need1 = more && (e1.klo != e0.klo || pl1 != pl0);
-            float2 x1[H];
-            if (need1) load_window(e1, pl1, x1);
-            const size_t o1 = (size_t)e1.vidx * a.n_pol + pol;
-            float2 vin1 = zero;
-            float wgt1 = 0.f;
-            if (MODE != kPredict) vin1 = a.vis_in[o1];
-            if (MODE == kGrad || MODE == kScale) wgt1 = a.weight[o1];
-            const int k2 = k0 + 2 < k_hi ? k0 + 2 : k_hi - 1;
-            const VisEnt e2 = went[k2];
-            const int f2 = wfp[k2];
+        for (int pol = 0; pol < a.n_pol; ++pol) {
+            // this worker's first sample and the entry after it, the first window
+            int k0 = k_lo;
+            VisEnt e0 = {0u, 0u}, e1 = {0u, 0u};
+            int f0 = 0, f1 = 0;
+            float2 x0[H];
+            float2 vin0 = zero;
+            float wgt0 = 0.f, w0 = 0.f;
+            int pl0 = 0;
+            if (k0 < k_hi) {
+                e0 = went[k0];
+                f0 = wfp[k0];
+                const int k1 = k0 + 1 < k_hi ? k0 + 1 : k0;  // past the end: the last (loads stay in bounds)
+                e1 = went[k1];
+                f1 = wfp[k1];
+                if constexpr (WT) wsel(e0, w0, pl0);
+                load_window(e0, pl0, x0);
+                const size_t o0 = (size_t)e0.vidx * a.n_pol + pol;
+                if (MODE != kPredict) vin0 = a.vis_in[o0];
+                if (MODE == kGrad || MODE == kScale) wgt0 = a.weight[o0];
+            }
 
-            // ---- the current sample's sub-lattice offset per axis
-            const int fl = f0 >> 4, fm = f0 & 15;
-
-            if (need0) {
-                // ---- along l: first radix-2 step across the halves, then H points
-#pragma unroll
-                for (int r = 0; r < H; ++r) {
-                    // the column's rows r (half 0) and H + r (half 1), in every lane
-                    float tx, bx, ty, by;
-                    halves<S>(x0[r].x, tx, bx);
-                    halves<S>(x0[r].y, ty, by);
-                    y[r] = make_float2(fmaf(sgn, bx, tx), fmaf(sgn, by, ty));
-                    if (r > 0) y[r] = cmul(y[r], tw1[r]);
+            // offsets plus squint (along l, or along the mount's first axis)
+            const double sq = (pol == 0 ? 1.0 : -1.0) * a.squint_frac * 1.02899 * lam / a.dish;
+            const double* oi = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.ai) * 2;
+            const double* oj = a.offsets + (((size_t)it.interval * a.n_pol + pol) * a.n_ant + it.aj) * 2;
+            const double qil = oi[0] + sq, qim = oi[1], qjl = oj[0] + sq, qjm = oj[1];
+            // each antenna's beam constants with its width scale
+            BeamK bki = beam_k(kk, inv_s2, aps, 1.f), bkj = bki;
+            if (a.scale != nullptr) {
+                const double* sc = a.scale + ((size_t)it.interval * a.n_pol + pol) * a.n_ant;
+                bki = beam_k(kk, inv_s2, aps, (float)sc[it.ai]);
+                bkj = beam_k(kk, inv_s2, aps, (float)sc[it.aj]);
+            }
+            if constexpr (CPLX) {
+                const double* dfp = a.defocus + ((size_t)it.interval * a.n_pol + pol) * a.n_ant;
+                const float kgd = (float)(2.0 / (kPi * kPi * a.gauss_sigma_ld * a.gauss_sigma_ld));
+                image_factors_cx<MODE>(a, gsh, kk, inv_s2, kgd, (float)dfp[it.ai], (float)dfp[it.aj], (float)qil,
+                                       (float)qim, (float)qjl, (float)qjm, tid, kBlock);
+            } else if constexpr (SKY) {
+                const float2 *pi = nullptr, *pj = nullptr;
+                if constexpr (S == 16) {  // tables only at support 16 (none compiled at 32)
+                    if (btab) {
+                        const size_t t0 = (((size_t)it.interval * a.n_pol + pol) * a.n_chan + it.chan) * a.n_ant;
+                        pi = a.beams + (t0 + it.ai) * (size_t)(a.m * a.m);
+                        pj = a.beams + (t0 + it.aj) * (size_t)(a.m * a.m);
+                    }
                 }
-                fft_reg<H>(y);
-                wave_sync();  // the previous sample's tile has been read
-#pragma unroll
-                for (int b = 0; b < H; ++b) wt[(2 * b + hh) * SP + c] = y[b];
+                image_factors<MODE, MF == kFrameSkyAperture, S == 32>(a, tlds ? airy_sh : a.airy, pi, pj, it.ai, it.aj,
+                                                                       gsh, bki, bkj, (float)qil, (float)qim,
+                                                                       (float)qjl, (float)qjm, tid, kBlock);
+            }
+            __syncthreads();
+
+            double acc64 = 0.0;
+            bool need0 = true;
+            float2 y[H];
+            while (k0 < k_hi) {
+                // ---- fetch ahead: the next sample's window (when it differs), its
+                // inputs, the entry after it
+                const bool more = k0 + 1 < k_hi;
+                float w1 = 0.f;
+                int pl1 = 0;
+                if constexpr (WT) wsel(e1, w1, pl1);
+                const bool need1 = more && (e1.klo != e0.klo || pl1 != pl0);
+                float2 x1[H];
+                if (need1) load_window(e1, pl1, x1);
+                const size_t o1 = (size_t)e1.vidx * a.n_pol + pol;
+                float2 vin1 = zero;
+                float wgt1 = 0.f;
+                if (MODE != kPredict) vin1 = a.vis_in[o1];
+                if (MODE == kGrad || MODE == kScale) wgt1 = a.weight[o1];
+                const int k2 = k0 + 2 < k_hi ? k0 + 2 : k_hi - 1;
+                const VisEnt e2 = went[k2];
+                const int f2 = wfp[k2];
+
+                // ---- the current sample's sub-lattice offset per axis
+                const int fl = f0 >> 4, fm = f0 & 15;
+
+                if (need0) {
+                    // ---- along l: first radix-2 step across the halves, then H points
+    #pragma unroll
+                    for (int r = 0; r < H; ++r) {
+                        // the column's rows r (half 0) and H + r (half 1), in every lane
+                        float tx, bx, ty, by;
+                        halves<S>(x0[r].x, tx, bx);
+                        halves<S>(x0[r].y, ty, by);
+                        y[r] = make_float2(fmaf(sgn, bx, tx), fmaf(sgn, by, ty));
+                        if (r > 0) y[r] = cmul(y[r], tw1[r]);
+                    }
+                    fft_reg<H>(y);
+                    wave_sync();  // the previous sample's tile has been read
+    #pragma unroll
+                    for (int b = 0; b < H; ++b) wt[(2 * b + hh) * SP + c] = y[b];
+                    wave_sync();
+                    // ---- along m: row c, the same split
+    #pragma unroll
+                    for (int r = 0; r < H; ++r) {
+                        const float2 t0 = wt[c * SP + r], t1 = wt[c * SP + H + r];
+                        y[r] = make_float2(fmaf(sgn, t1.x, t0.x), fmaf(sgn, t1.y, t0.y));
+                        if (r > 0) y[r] = cmul(y[r], tw1[r]);
+                    }
+                    fft_reg<H>(y);
+                    if constexpr (YLDS) {
+    #pragma unroll
+                        for (int b = 0; b < H; ++b) ybuf[b * kBlock + tid] = y[b];
+                    }
+                } else if constexpr (YLDS) {
+    #pragma unroll
+                    for (int b = 0; b < H; ++b) y[b] = ybuf[b * kBlock + tid];
+                }
+                // ---- row c times the sample's l-axis phase of the row's index
+                const float2 prow = phase(fl, nl_row);
+                wave_sync();  // the tile (the previous sample's, or the transpose) has been read
+    #pragma unroll
+                for (int b = 0; b < H; ++b) wt[c * SP + 2 * b + hh] = cmul(y[b], prow);
                 wave_sync();
-                // ---- along m: row c, the same split
-#pragma unroll
-                for (int r = 0; r < H; ++r) {
-                    const float2 t0 = wt[c * SP + r], t1 = wt[c * SP + H + r];
-                    y[r] = make_float2(fmaf(sgn, t1.x, t0.x), fmaf(sgn, t1.y, t0.y));
-                    if (r > 0) y[r] = cmul(y[r], tw1[r]);
-                }
-                fft_reg<H>(y);
-                if constexpr (YLDS) {
-#pragma unroll
-                    for (int b = 0; b < H; ++b) ybuf[b * kBlock + tid] = y[b];
-                }
-            } else if constexpr (YLDS) {
-#pragma unroll
-                for (int b = 0; b < H; ++b) y[b] = ybuf[b * kBlock + tid];
-            }
-            // ---- row c times the sample's l-axis phase of the row's index
-            const float2 prow = phase(fl, nl_row);
-            wave_sync();  // the tile (the previous sample's, or the transpose) has been read
-#pragma unroll
-            for (int b = 0; b < H; ++b) wt[c * SP + 2 * b + hh] = cmul(y[b], prow);
-            wave_sync();
-            // ---- A_k, B_k: sums over l of g_k[n_l][n_m] T[n_l mod 32][c] for
-            // n_l below and above 32 - M/2
-            float2 A[NV], B[NV];
-#pragma unroll
-            for (int k = 0; k < NV; ++k) A[k] = B[k] = zero;
-            float cs = 1.f, sn = 0.f;
-            if constexpr (!SKY) {
-                // this row's beam centres on the sky
-                sincosf((float)a.par_angle[e0.vidx / (uint32_t)a.n_chan], &sn, &cs);
-                const float pil = (float)(cs * qil - sn * qim), pim = (float)(sn * qil + cs * qim);
-                const float pjl = (float)(cs * qjl - sn * qjm), pjm = (float)(sn * qjl + cs * qjm);
-                const float4 *api = nullptr, *apj = nullptr;  // the two antennas' aperture tables
-                if constexpr (MF == kFrameAperture) {
-                    api = ap_table(a, it.ai);
-                    apj = ap_table(a, it.aj);
-                }
-                auto term = [&](int jl, float2 (&acc)[NV]) {
-                    const float l = (float)(jl - half_m) * hstep;
-                    float2 t = wt[((jl - half_m) & (S - 1)) * SP + c];
-                    if constexpr (WT) t = cmul(t, wphase(w0, l));
-                    float g[NV];
-                    if constexpr (MF == kFrameAperture)
-                        mf_products_ap<MODE>(a, api, apj, bki, bkj, cs, sn, l - pil, mmy - pim, l - pjl,
-                                             mmy - pjm, a.taper_img[jl] * ctm, g);
-                    else
-                        mf_products<MODE>(a, airy_sh, bki, bkj, l - pil, mmy - pim, l - pjl, mmy - pjm,
-                                          a.taper_img[jl] * ctm, g);
-#pragma unroll
-                    for (int k = 0; k < NV; ++k) {
-                        acc[k].x = fmaf(g[k], t.x, acc[k].x);
-                        acc[k].y = fmaf(g[k], t.y, acc[k].y);
+                // ---- A_k, B_k: sums over l of g_k[n_l][n_m] T[n_l mod 32][c] for
+                // n_l below and above 32 - M/2
+                float2 A[NV], B[NV];
+    #pragma unroll
+                for (int k = 0; k < NV; ++k) A[k] = B[k] = zero;
+                float cs = 1.f, sn = 0.f;
+                if constexpr (!SKY) {
+                    // this row's beam centres on the sky
+                    sincosf((float)a.par_angle[e0.vidx / (uint32_t)a.n_chan], &sn, &cs);
+                    const float pil = (float)(cs * qil - sn * qim), pim = (float)(sn * qil + cs * qim);
+                    const float pjl = (float)(cs * qjl - sn * qjm), pjm = (float)(sn * qjl + cs * qjm);
+                    const float4 *api = nullptr, *apj = nullptr;  // the two antennas' aperture tables
+                    if constexpr (MF == kFrameAperture) {
+                        api = ap_table(a, it.ai);
+                        apj = ap_table(a, it.aj);
                     }
-                };
-#pragma unroll 2
-                for (int jl = 0; jl < S; ++jl) term(jl, A);
-#pragma unroll 2
-                for (int jl = S; jl < m; ++jl) term(jl, B);
-            } else {
-                // factored sums: the value sum g T, and per antenna Q = sum q T
-                // and L = sum q l T, l the image-sample l coordinate (the
-                // variant dV/dp_l = L - p_l Q, dV/dp_m = (m - p_m) Q).  L comes
-                // from running sums: over the part's rows n < j1 in order,
-                // Q += q T and then P += Q leave P = sum (j1 - n) q T, so with
-                // l = (n - M/2) h, L = h ((j1 - M/2) Q - P): no product by l
-                // per row (the float32 error stays within twice that of the
-                // direct sum, coherent rows included).
-                const float* gp = gsh + jm * NG;
-                // the halves read factors S samples apart, S NG words: an odd
-                // multiple of 32 for NG odd, so they use disjoint banks
-                // image-sample rows [j0, j1) at tile rows b0, b0 + 1, ... (no wrap)
-                auto seg = [&](int j0, int j1, int b0, float2 (&acc)[NV]) {
-                    const float2* tp = wt + b0 * SP + c;
-                    const float* g = gp + j0 * m * NG;
-#pragma unroll kUnroll
-                    for (int jl = j0; jl < j1; ++jl, tp += SP, g += m * NG) {
-                        float2 t = *tp;
-                        if constexpr (WT) t = cmul(t, wphase(w0, (float)(jl - half_m) * hstep));
-                        if constexpr (CPLX) {
-                            // one plain sum per variant, complex products
-#pragma unroll
-                            for (int k = 0; k < NV; ++k) {
-                                const float gr = g[2 * k], gi = g[2 * k + 1];
-                                acc[k].x = fmaf(gr, t.x, fmaf(-gi, t.y, acc[k].x));
-                                acc[k].y = fmaf(gr, t.y, fmaf(gi, t.x, acc[k].y));
+                    auto term = [&](int jl, float2 (&acc)[NV]) {
+                        const float l = (float)(jl - half_m) * hstep;
+                        float2 t = wt[((jl - half_m) & (S - 1)) * SP + c];
+                        if constexpr (WT) t = cmul(t, wphase(w0, l));
+                        float g[NV];
+                        if constexpr (MF == kFrameAperture)
+                            mf_products_ap<MODE>(a, api, apj, bki, bkj, cs, sn, l - pil, mmy - pim, l - pjl,
+                                                 mmy - pjm, a.taper_img[jl] * ctm, g);
+                        else
+                            mf_products<MODE>(a, airy_sh, bki, bkj, l - pil, mmy - pim, l - pjl, mmy - pjm,
+                                              a.taper_img[jl] * ctm, g);
+    #pragma unroll
+                        for (int k = 0; k < NV; ++k) {
+                            acc[k].x = fmaf(g[k], t.x, acc[k].x);
+                            acc[k].y = fmaf(g[k], t.y, acc[k].y);
+                        }
+                    };
+    #pragma unroll 2
+                    for (int jl = 0; jl < S; ++jl) term(jl, A);
+    #pragma unroll 2
+                    for (int jl = S; jl < m; ++jl) term(jl, B);
+                } else {
+                    // factored sums: the value sum g T, and per antenna Q = sum q T
+                    // and L = sum q l T, l the image-sample l coordinate (the
+                    // variant dV/dp_l = L - p_l Q, dV/dp_m = (m - p_m) Q).  L comes
+                    // from running sums: over the part's rows n < j1 in order,
+                    // Q += q T and then P += Q leave P = sum (j1 - n) q T, so with
+                    // l = (n - M/2) h, L = h ((j1 - M/2) Q - P): no product by l
+                    // per row (the float32 error stays within twice that of the
+                    // direct sum, coherent rows included).
+                    const float* gp = gsh + jm * NG;
+                    // the halves read factors S samples apart, S NG words: an odd
+                    // multiple of 32 for NG odd, so they use disjoint banks
+                    // image-sample rows [j0, j1) at tile rows b0, b0 + 1, ... (no wrap)
+                    auto seg = [&](int j0, int j1, int b0, float2 (&acc)[NV]) {
+                        const float2* tp = wt + b0 * SP + c;
+                        const float* g = gp + j0 * m * NG;
+    #pragma unroll kUnroll
+                        for (int jl = j0; jl < j1; ++jl, tp += SP, g += m * NG) {
+                            float2 t = *tp;
+                            if constexpr (WT) t = cmul(t, wphase(w0, (float)(jl - half_m) * hstep));
+                            if constexpr (CPLX) {
+                                // one plain sum per variant, complex products
+    #pragma unroll
+                                for (int k = 0; k < NV; ++k) {
+                                    const float gr = g[2 * k], gi = g[2 * k + 1];
+                                    acc[k].x = fmaf(gr, t.x, fmaf(-gi, t.y, acc[k].x));
+                                    acc[k].y = fmaf(gr, t.y, fmaf(gi, t.x, acc[k].y));
+                                }
+                            } else if constexpr (PLAIN) {
+                                // one plain sum per variant
+    #pragma unroll
+                                for (int k = 0; k < NV; ++k) {
+                                    acc[k].x = fmaf(g[k], t.x, acc[k].x);
+                                    acc[k].y = fmaf(g[k], t.y, acc[k].y);
+                                }
                             }
-                        } else if constexpr (PLAIN) {
-                            // one plain sum per variant
-#pragma unroll
-                            for (int k = 0; k < NV; ++k) {
-                                acc[k].x = fmaf(g[k], t.x, acc[k].x);
-                                acc[k].y = fmaf(g[k], t.y, acc[k].y);
+                            if constexpr (MODE != kVjp && !PLAIN) {
+                                acc[0].x = fmaf(g[0], t.x, acc[0].x);
+                                acc[0].y = fmaf(g[0], t.y, acc[0].y);
+                            }
+                            if constexpr (MODE != kPredict && !PLAIN) {
+                                constexpr int o = MODE == kGrad ? 1 : 0;
+    #pragma unroll
+                                for (int end = 0; end < 2; ++end) {
+                                    const float q = g[o + end];
+                                    float2& P = acc[o + 2 * end];
+                                    float2& Q = acc[o + 2 * end + 1];
+                                    Q.x = fmaf(q, t.x, Q.x);
+                                    Q.y = fmaf(q, t.y, Q.y);
+                                    P.x += Q.x;
+                                    P.y += Q.y;
+                                }
                             }
                         }
-                        if constexpr (MODE != kVjp && !PLAIN) {
-                            acc[0].x = fmaf(g[0], t.x, acc[0].x);
-                            acc[0].y = fmaf(g[0], t.y, acc[0].y);
-                        }
-                        if constexpr (MODE != kPredict && !PLAIN) {
-                            constexpr int o = MODE == kGrad ? 1 : 0;
-#pragma unroll
-                            for (int end = 0; end < 2; ++end) {
-                                const float q = g[o + end];
-                                float2& P = acc[o + 2 * end];
-                                float2& Q = acc[o + 2 * end + 1];
-                                Q.x = fmaf(q, t.x, Q.x);
-                                Q.y = fmaf(q, t.y, Q.y);
-                                P.x += Q.x;
-                                P.y += Q.y;
-                            }
+                    };
+                    // n_l in [-M/2, 0) is tile row n_l + 32 and [0, 32 - M/2) row
+                    // n_l (the A part); [32 - M/2, M/2) is row n_l, the row of
+                    // n_l - 32 (the B part)
+                    seg(0, half_m, S - half_m, A);
+                    seg(half_m, S, 0, A);
+                    seg(S, m, S - half_m, B);
+                    if constexpr (MODE != kPredict && !PLAIN) {
+                        // L from P and Q: the A part ends at row S, the B part at M
+                        constexpr int o = MODE == kGrad ? 1 : 0;
+                        const float ca = (float)(S - half_m), cb = (float)(m - half_m);
+    #pragma unroll
+                        for (int end = 0; end < 2; ++end) {
+                            float2& pa = A[o + 2 * end];
+                            float2& pb = B[o + 2 * end];
+                            const float2 qa = A[o + 2 * end + 1], qb = B[o + 2 * end + 1];
+                            pa = make_float2(hstep * fmaf(ca, qa.x, -pa.x), hstep * fmaf(ca, qa.y, -pa.y));
+                            pb = make_float2(hstep * fmaf(cb, qb.x, -pb.x), hstep * fmaf(cb, qb.y, -pb.y));
                         }
                     }
-                };
-                // n_l in [-M/2, 0) is tile row n_l + 32 and [0, 32 - M/2) row
-                // n_l (the A part); [32 - M/2, M/2) is row n_l, the row of
-                // n_l - 32 (the B part)
-                seg(0, half_m, S - half_m, A);
-                seg(half_m, S, 0, A);
-                seg(S, m, S - half_m, B);
-                if constexpr (MODE != kPredict && !PLAIN) {
-                    // L from P and Q: the A part ends at row S, the B part at M
+                }
+                // ---- s_k = phi_m(n_m) (A_k + exp(2 pi i f_l / O) B_k), summed over the worker
+                const float2 rho = twsh[(fl * S) & (so - 1)];
+                const float2 pm = m_ok ? phase(fm, nm) : zero;
+                float2 s[NV];
+    #pragma unroll
+                for (int k = 0; k < NV; ++k) {
+                    const float2 rb = cmul(rho, B[k]);
+                    s[k] = cmul(pm, make_float2(A[k].x + rb.x, A[k].y + rb.y));
+                }
+                if constexpr (SKY && !PLAIN && MODE != kPredict) {
+                    // derivative variants from the factored sums (the lane's m coordinate is mmy)
                     constexpr int o = MODE == kGrad ? 1 : 0;
-                    const float ca = (float)(S - half_m), cb = (float)(m - half_m);
-#pragma unroll
+                    const float pl[2] = {(float)qil, (float)qjl}, pmm[2] = {(float)qim, (float)qjm};
+    #pragma unroll
                     for (int end = 0; end < 2; ++end) {
-                        float2& pa = A[o + 2 * end];
-                        float2& pb = B[o + 2 * end];
-                        const float2 qa = A[o + 2 * end + 1], qb = B[o + 2 * end + 1];
-                        pa = make_float2(hstep * fmaf(ca, qa.x, -pa.x), hstep * fmaf(ca, qa.y, -pa.y));
-                        pb = make_float2(hstep * fmaf(cb, qb.x, -pb.x), hstep * fmaf(cb, qb.y, -pb.y));
+                        const float2 L = s[o + 2 * end], Q = s[o + 2 * end + 1];
+                        const float dm = mmy - pmm[end];
+                        s[o + 2 * end] = make_float2(fmaf(-pl[end], Q.x, L.x), fmaf(-pl[end], Q.y, L.y));
+                        s[o + 2 * end + 1] = make_float2(dm * Q.x, dm * Q.y);
                     }
                 }
-            }
-            // ---- s_k = phi_m(n_m) (A_k + exp(2 pi i f_l / O) B_k), summed over the worker
-            const float2 rho = twsh[(fl * S) & (so - 1)];
-            const float2 pm = m_ok ? phase(fm, nm) : zero;
-            float2 s[NV];
-#pragma unroll
-            for (int k = 0; k < NV; ++k) {
-                const float2 rb = cmul(rho, B[k]);
-                s[k] = cmul(pm, make_float2(A[k].x + rb.x, A[k].y + rb.y));
-            }
-            if constexpr (SKY && !PLAIN && MODE != kPredict) {
-                // derivative variants from the factored sums (the lane's m coordinate is mmy)
-                constexpr int o = MODE == kGrad ? 1 : 0;
-                const float pl[2] = {(float)qil, (float)qjl}, pmm[2] = {(float)qim, (float)qjm};
-#pragma unroll
-                for (int end = 0; end < 2; ++end) {
-                    const float2 L = s[o + 2 * end], Q = s[o + 2 * end + 1];
-                    const float dm = mmy - pmm[end];
-                    s[o + 2 * end] = make_float2(fmaf(-pl[end], Q.x, L.x), fmaf(-pl[end], Q.y, L.y));
-                    s[o + 2 * end + 1] = make_float2(dm * Q.x, dm * Q.y);
+    #pragma unroll
+                for (int k = 0; k < NV; ++k) worker_sum2<S>(s[k].x, s[k].y);
+                if constexpr (MF == kFrameMount && MODE != kPredict && MODE != kScale) {
+                    // derivatives with respect to the mount-frame offsets
+                    constexpr int d0 = (MODE == kGrad) ? 1 : 0;
+    #pragma unroll
+                    for (int end = 0; end < 2; ++end) {
+                        const float2 dl = s[d0 + 2 * end], dm = s[d0 + 2 * end + 1];
+                        s[d0 + 2 * end] = make_float2(cs * dl.x + sn * dm.x, cs * dl.y + sn * dm.y);
+                        s[d0 + 2 * end + 1] = make_float2(cs * dm.x - sn * dl.x, cs * dm.y - sn * dl.y);
+                    }
                 }
-            }
-#pragma unroll
-            for (int k = 0; k < NV; ++k) worker_sum2<S>(s[k].x, s[k].y);
-            if constexpr (MF == kFrameMount && MODE != kPredict && MODE != kScale) {
-                // derivatives with respect to the mount-frame offsets
-                constexpr int d0 = (MODE == kGrad) ? 1 : 0;
-#pragma unroll
-                for (int end = 0; end < 2; ++end) {
-                    const float2 dl = s[d0 + 2 * end], dm = s[d0 + 2 * end + 1];
-                    s[d0 + 2 * end] = make_float2(cs * dl.x + sn * dm.x, cs * dl.y + sn * dm.y);
-                    s[d0 + 2 * end + 1] = make_float2(cs * dm.x - sn * dl.x, cs * dm.y - sn * dl.y);
+                const size_t o0 = (size_t)e0.vidx * a.n_pol + pol;
+                if constexpr (MODE == kPredict) {
+                    if (sl == 0) a.vis_out[o0] = s[0];
+                } else if constexpr (MODE == kGrad) {
+                    if (a.vis_out != nullptr && sl == 0) a.vis_out[o0] = s[0];
+                    grad_term(tsel, s, vin0, wgt0, acc64);
+                } else if constexpr (MODE == kScale) {
+                    scale_term(sl, s, vin0, wgt0, acc64);
+                } else {
+                    vjp_term(sl, s, vin0, acc64);
                 }
-            }
-            const size_t o0 = (size_t)e0.vidx * a.n_pol + pol;
-            if constexpr (MODE == kPredict) {
-                if (sl == 0) a.vis_out[o0] = s[0];
-            } else if constexpr (MODE == kGrad) {
-                if (a.vis_out != nullptr && sl == 0) a.vis_out[o0] = s[0];
-                grad_term(tsel, s, vin0, wgt0, acc64);
-            } else if constexpr (MODE == kScale) {
-                scale_term(sl, s, vin0, wgt0, acc64);
-            } else {
-                vjp_term(sl, s, vin0, acc64);
+
+                // ---- move on
+                if (need1) {
+    #pragma unroll
+                    for (int r = 0; r < H; ++r) x0[r] = x1[r];
+                }
+                need0 = need1;
+                vin0 = vin1;
+                wgt0 = wgt1;
+                w0 = w1;
+                pl0 = pl1;
+                e0 = e1;
+                f0 = f1;
+                e1 = e2;
+                f1 = f2;
+                ++k0;
             }
 
-            // ---- move on
-            if (need1) {
-#pragma unroll
-                for (int r = 0; r < H; ++r) x0[r] = x1[r];
+            // ---- per-item partial sums: workers added in order
+            if (NC > 0 && sl < NC) gpart[worker * NCP + sl] = acc64;
+            __syncthreads();
+            if (NC > 0 && tid < NC) {
+                double sum = 0.0;
+    #pragma unroll
+                for (int w = 0; w < NW; ++w) sum += gpart[w * NCP + tid];
+                a.partials[((size_t)item_idx * a.n_pol + pol) * NC + tid] = sum;
             }
-            need0 = need1;
-            vin0 = vin1;
-            wgt0 = wgt1;
-            w0 = w1;
-            pl0 = pl1;
-            e0 = e1;
-            f0 = f1;
-            e1 = e2;
-            f1 = f2;
-            ++k0;
+            __syncthreads();
         }
-
-        // ---- per-item partial sums: workers added in order
-        if (NC > 0 && sl < NC) gpart[worker * NCP + sl] = acc64;
-        __syncthreads();
-        if (NC > 0 && tid < NC) {
-            double sum = 0.0;
-#pragma unroll
-            for (int w = 0; w < NW; ++w) sum += gpart[w * NCP + tid];
-            a.partials[((size_t)item_idx * a.n_pol + pol) * NC + tid] = sum;
-        }
-        __syncthreads();
+    };
+    if constexpr (MULTI) {
+        for (int r = 0; r < R && r < a.n_items - li0; ++r) one_item(li0 + r);
+    } else {
+        one_item(li0);
     }
 }
 
@@ -807,9 +840,13 @@ static hipError_t launch_win_wm(const ItemArgs& a, hipStream_t s)
         (const void*)k_winw<S, MODE, MF, W, WT, MT>, hipFuncAttributeMaxDynamicSharedMemorySize,
         (int)win_lds_budget(S));
     if (attr != hipSuccess) return attr;
-    const int blocks = (int)item_blocks(a.n_items);
     ItemArgs b = a;
     b.tab_lds = sky_tab_lds(S, MODE, MF, a.m, a.oversample, a.n_tab);
+    // many items, sky frame at support 32: 32 consecutive ones per block, sharing its
+    // set-up (a launch of one interval of the large workload, 260k items,
+    // keeps one per block)
+    b.unit_items = win_multi_item(S, MF) && a.n_items >= (1 << 19) ? 32 : 1;
+    const int blocks = (int)item_blocks((a.n_items + b.unit_items - 1) / b.unit_items);
     const size_t sh = winw_frame_lds(S, W, MODE, MF, a.m, a.oversample, a.n_tab);
     if (sh < winw_layout_bytes<S, MODE, MF, W>(a.m, a.n_tab, b.tab_lds)) return hipErrorInvalidValue;
     k_winw<S, MODE, MF, W, WT, MT><<<blocks, 64 * W, sh, s>>>(b);

@@ -810,6 +810,59 @@ def test_cfg5_subset_solve(torch_dev, cfg5_subset):
     assert np.array_equal(outs[0], outs[1])
 
 
+def test_cfg5_share_full_size_sampled_rows(torch_dev):
+    """One GPU's share of the large workload at full size (its first 32 of
+    256 channels: 312 M visibilities in 64 uneven intervals, support 32), in
+    the launch configuration the bench times, where a whole-batch launch
+    gives each block 32 consecutive items and one interval's launch one: the
+    model of every 200th timestep and the per-antenna sums with the weights
+    zero elsewhere against the oracle on those rows; then two iterations of
+    Algorithm 1 in the plain form (a launch per interval) and the batched
+    form (one launch), iteration counts and offsets bit-identical."""
+    torch = torch_dev
+    from paper_1709_08681_amd import psc
+    every = 200
+    print(f"case: cfg5 32-channel share at full size, every {every}th timestep", flush=True)
+    obs = synth.make_config(5).subset(chans=range(32))
+    times = np.unique(obs.time_idx)[::every]
+    rows = np.nonzero(np.isin(obs.time_idx, times))[0]
+    sub = obs.subset(times=times)
+    prob = oracle.Problem.from_observation(sub)
+    s = session(obs)
+    try:
+        assert psc.psc_get_degrid(s.handle) == psc.DEGRID_WINDOW
+        start = synth.perturbed_offsets(obs, 30.0, 24)
+        v_sub = oracle.predict(prob, obs.offsets_true)
+        vobs = np.zeros(s.vis_shape, np.complex64)
+        vobs[rows] = v_sub
+        w = np.zeros(s.vis_shape, np.float32)
+        w[rows] = 1.0
+        g_vobs, g_w = c64(torch, s, vobs), f32(torch, s, w, s.vis_shape)
+        del vobs, w
+        off = s.offsets(start)
+        vp = s.predict(start)[torch.as_tensor(rows, device=s.dev)].cpu().numpy()
+        vp_ref = oracle.predict(prob, start)
+        acc = s.gradient(off, g_vobs, g_w).cpu().numpy()
+        ref = oracle.gradient(prob, start, v_sub, 1.0)
+        e_v, e_el = rel(vp, vp_ref), elem_err(vp, vp_ref)
+        e_a = [rel(acc[..., k], ref[..., k]) for k in range(6)]
+        e_ant = per_antenna_err(acc, ref)
+        print(f"cfg5 share: vis rel {e_v:.2e}, max element {e_el:.2e}, acc rel {max(e_a):.2e}, "
+              f"per antenna {max(e_ant):.2e} ({len(rows)} of {obs.n_row} rows)", flush=True)
+        assert e_v <= 1e-5 and e_el <= ELEM_VIS_TOL
+        assert max(e_a) <= 1e-4 and max(e_ant) <= ANT_SUM_TOL
+        outs = []
+        for form in (psc.SOLVE_PLAIN, psc.SOLVE_BATCHED):
+            o = s.offsets(start)
+            its = s.solve(g_vobs, g_w, o, gain=0.5, n_max=2, tol_rad=1e-3 * ARCSEC, form=form)
+            outs.append((its.cpu().numpy(), o.cpu().numpy()))
+        assert np.array_equal(outs[0][0], outs[1][0])
+        assert np.array_equal(outs[0][1], outs[1][1])
+        assert not np.array_equal(outs[0][1], start)
+    finally:
+        s.close()
+
+
 # ---------------------------------------------------------------------------
 # image gradient: the adjoint of predict with respect to the model image
 # ---------------------------------------------------------------------------
