@@ -246,6 +246,13 @@ PSC_API psc_status psc_obs_info(const psc_obs* obs, int64_t* n_items, int64_t* n
  *                     from per-antenna tables filled before each degrid
  *                     (sky frame, radial beams, support 16, one interval's
  *                     tables within 8 MiB; see psc_obs_create), else 0
+ *   items_per_block   consecutive work items each block of a gradient
+ *                     launch over all intervals takes: 32 for the window
+ *                     form in the sky frame at support 32 with at least
+ *                     2^19 items (the block's set-up, twiddles and Airy
+ *                     table into LDS, is then paid once per 32 items),
+ *                     else 1; a launch of fewer items (one interval of the
+ *                     plain solve form) takes one each
  * PSC_E_ARG for a null observation or output.
  */
 typedef struct {
@@ -257,7 +264,7 @@ typedef struct {
     int32_t tab_nodes;
     double capture_ms;
     int32_t pattern_tables;
-    int32_t reserved;
+    int32_t items_per_block;
 } psc_launch_info;
 PSC_API psc_status psc_obs_launch_info(const psc_obs* obs, psc_launch_info* out);
 

@@ -973,7 +973,12 @@ PSC_API psc_status psc_obs_launch_info(const psc_obs* obs, psc_launch_info* out)
     out->tab_nodes = obs->n_tab;
     out->capture_ms = obs->capture_ms;
     out->pattern_tables = (obs->beams != nullptr && ctx->s == 16 && !obs->par_angle && !obs->ap_tab) ? 1 : 0;
-    out->reserved = 0;
+    // the whole-batch launch's blocks (the window form's rule on every item,
+    // complex patterns while a defocus is set; the table form takes one item
+    // per block)
+    out->items_per_block = obs->degrid == PSC_DEGRID_WINDOW
+                               ? win_items_per_block(ctx->s, obs->defocus ? kFrameSkyComplex : frame, obs->n_items)
+                               : 1;
     return PSC_OK;
 }
 

@@ -247,6 +247,20 @@ constexpr int kFrameSkyComplex = 4;
 constexpr int kMoments = 27;
 constexpr double kMaxDefocus = 3.14159265358979323846;
 int win_block_waves(int support, int mode, int frame, int m, int oversample, int n_tab, int plan_waves);
+// Items per block of a window-form launch over n_items items: the sky-frame
+// variants at support 32, whose set-up (twiddles, Airy table in LDS) is
+// largest against an item's work, take kWinItemsPerBlock consecutive items
+// when a launch has at least kWinMultiItemMin; every other launch one.
+constexpr int kWinItemsPerBlock = 32;
+constexpr long long kWinMultiItemMin = 1LL << 19;
+__host__ __device__ constexpr bool win_multi_item(int support, int frame)
+{
+    return support == 32 && frame == kFrameSky;
+}
+__host__ __device__ constexpr int win_items_per_block(int support, int frame, long long n_items)
+{
+    return win_multi_item(support, frame) && n_items >= kWinMultiItemMin ? kWinItemsPerBlock : 1;
+}
 // Image-gradient scatter with per-item LDS patches (psc_grid.hip), support
 // 16: one thread per tap, chunks of kGridChunk samples, patches of
 // kGridPatch^2 cells.  grid_lds_bytes is its dynamic LDS; launch_grid refuses

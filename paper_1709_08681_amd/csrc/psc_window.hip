@@ -257,14 +257,6 @@ __device__ __forceinline__ void halves(float v, float& lo, float& hi)
     }
 }
 
-// Whether a launch may give each block several consecutive items: the
-// sky-frame variants at support 32, whose set-up (twiddles, Airy table) is
-// largest against an item's work.
-__host__ __device__ constexpr bool win_multi_item(int S, int MF)
-{
-    return S == 32 && MF == kFrameSky;
-}
-
 // Wavefronts per SIMD the window kernel asks the compiler to fit.
 __host__ __device__ constexpr int win_min_waves(int S, int MF, bool WT)
 {
@@ -842,10 +834,10 @@ static hipError_t launch_win_wm(const ItemArgs& a, hipStream_t s)
     if (attr != hipSuccess) return attr;
     ItemArgs b = a;
     b.tab_lds = sky_tab_lds(S, MODE, MF, a.m, a.oversample, a.n_tab);
-    // many items, sky frame at support 32: 32 consecutive ones per block, sharing its
-    // set-up (a launch of one interval of the large workload, 260k items,
-    // keeps one per block)
-    b.unit_items = win_multi_item(S, MF) && a.n_items >= (1 << 19) ? 32 : 1;
+    // many items, sky frame at support 32: 32 consecutive ones per block,
+    // sharing its set-up (a launch of one interval of the large workload,
+    // 260k items, keeps one per block)
+    b.unit_items = win_items_per_block(S, MF, a.n_items);
     const int blocks = (int)item_blocks((a.n_items + b.unit_items - 1) / b.unit_items);
     const size_t sh = winw_frame_lds(S, W, MODE, MF, a.m, a.oversample, a.n_tab);
     if (sh < winw_layout_bytes<S, MODE, MF, W>(a.m, a.n_tab, b.tab_lds)) return hipErrorInvalidValue;

@@ -53,7 +53,7 @@ class Config(C.Structure):
 class LaunchInfo(C.Structure):
     _fields_ = [("degrid", C.c_int32), ("window_waves", C.c_int32), ("samples_per_item", C.c_double),
                 ("plan_ms", C.c_double), ("w_planes", C.c_int32), ("tab_nodes", C.c_int32), ("capture_ms", C.c_double),
-                ("pattern_tables", C.c_int32), ("reserved", C.c_int32)]
+                ("pattern_tables", C.c_int32), ("items_per_block", C.c_int32)]
 
 
 class ObsDesc(C.Structure):
@@ -175,12 +175,13 @@ def psc_obs_info(obs):
 
 def psc_obs_launch_info(obs):
     """dict(degrid, window_waves, samples_per_item, plan_ms, w_planes, tab_nodes, capture_ms,
-    pattern_tables)."""
+    pattern_tables, items_per_block)."""
     li = LaunchInfo()
     _check(load().psc_obs_launch_info(obs, C.byref(li)))
     return {"degrid": li.degrid, "window_waves": li.window_waves,
             "samples_per_item": li.samples_per_item, "plan_ms": li.plan_ms, "w_planes": li.w_planes,
-            "tab_nodes": li.tab_nodes, "capture_ms": li.capture_ms, "pattern_tables": li.pattern_tables}
+            "tab_nodes": li.tab_nodes, "capture_ms": li.capture_ms, "pattern_tables": li.pattern_tables,
+            "items_per_block": li.items_per_block}
 
 
 def psc_predict(ctx, obs, offsets_dev, vis_out_dev, stream=None):

@@ -863,6 +863,64 @@ def test_cfg5_share_full_size_sampled_rows(torch_dev):
         s.close()
 
 
+def test_support32_multi_item_blocks_ragged(torch_dev):
+    """Blocks of 32 items (sky frame, support 32, a launch of at least 2^19
+    items) on a ragged item count: 127 antennas of the large workload (8001
+    baselines), 31 channels, one timestep in each of its first three
+    intervals: 744,093 items, so the whole-batch launch ends on a block of
+    29 and has blocks that straddle two intervals.  Every visibility and
+    every per-antenna sum against the oracle at perturbed offsets; then
+    Algorithm 1 with the first interval starting at the true offsets (done
+    after one step, so the later whole-batch launches skip its items inside
+    blocks shared with the second interval): plain (one item per block),
+    batched and graph forms bit-identical."""
+    torch = torch_dev
+    from paper_1709_08681_amd import psc
+    print("case: support-32 blocks of 32 items, ragged count", flush=True)
+    full = synth.make_config(5)
+    starts = np.concatenate([[0], np.cumsum(full.wl.interval_lengths)])[:3]
+    obs = full.subset(ants=range(127), times=starts, chans=range(31))
+    live = np.nonzero(obs.int_row_ptr[1:] > obs.int_row_ptr[:-1])[0]
+    assert list(live) == [0, 1, 2]
+    prob = oracle.Problem.from_observation(obs)
+    s = session(obs)
+    try:
+        n_items = psc.psc_obs_info(s.handle)[0]
+        info = psc.psc_obs_launch_info(s.handle)
+        assert n_items == 3 * 8001 * 31 and n_items % 32 == 29
+        assert info["degrid"] == psc.DEGRID_WINDOW and info["items_per_block"] == 32
+        start = synth.perturbed_offsets(obs, 30.0, 25)
+        v = oracle.predict(prob, obs.offsets_true)
+        vp = s.predict(start).cpu().numpy()
+        vp_ref = oracle.predict(prob, start)
+        w1 = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
+        g_v = c64(torch, s, v)
+        acc = s.gradient(s.offsets(start), g_v, w1).cpu().numpy()
+        ref = oracle.gradient(prob, start, v, 1.0)
+        e_v, e_el = rel(vp, vp_ref), elem_err(vp, vp_ref)
+        e_a = [rel(acc[live][..., k], ref[live][..., k]) for k in range(6)]
+        e_ant = per_antenna_err(acc[live], ref[live])
+        print(f"multi-item blocks: vis rel {e_v:.2e}, max element {e_el:.2e}, acc rel {max(e_a):.2e}, "
+              f"per antenna {max(e_ant):.2e}", flush=True)
+        assert e_v <= 1e-5 and e_el <= ELEM_VIS_TOL
+        assert max(e_a) <= 1e-4 and max(e_ant) <= ANT_SUM_TOL
+        # the first interval from the true offsets: its step is the model's
+        # error alone, far below the tolerance
+        start[0] = obs.offsets_true[0]
+        outs = []
+        for form in (psc.SOLVE_PLAIN, psc.SOLVE_BATCHED, psc.SOLVE_GRAPH):
+            o = s.offsets(start)
+            its = s.solve(g_v, w1, o, gain=0.5, n_max=4, tol_rad=1e-2 * ARCSEC, form=form)
+            outs.append((its.cpu().numpy(), o.cpu().numpy()))
+        its = outs[0][0]
+        print(f"multi-item blocks: iterations per live interval {its[live]}", flush=True)
+        assert its[0] == 1 and its[1] == 4 and its[2] == 4
+        for its_f, off_f in outs[1:]:
+            assert np.array_equal(its_f, its) and np.array_equal(off_f, outs[0][1])
+    finally:
+        s.close()
+
+
 # ---------------------------------------------------------------------------
 # image gradient: the adjoint of predict with respect to the model image
 # ---------------------------------------------------------------------------
