@@ -268,13 +268,16 @@ __host__ __device__ constexpr int win_min_waves(int S, int MF, bool WT)
 // Workers of 2S lanes: a wavefront per sample at support 32, half a wavefront
 // at support 16.
 //
-// One block of W wavefronts per item.  The item's samples, numbered group by
-// group (each group's samples at f, then those at -f), are dealt to the
-// workers in turn: worker w takes samples w, w + NW, w + 2 NW, ...  With the
-// assignment fixed, a worker loads its next sample's entry, window and inputs
-// while it transforms and sums the current one, so the chain of dependent
-// loads (entry, then window) stays off the critical path; the float64 sums
-// are kept per worker and added in worker order.
+// One block of W wavefronts per item (in the sky frame at support 32, per
+// run of win_items_per_block consecutive items, taken one after another and
+// sharing the block's set-up).  The item's n samples, in row order (time
+// order along the baseline's uv track), are split among the workers in
+// contiguous shares: worker w takes [w n / NW, (w + 1) n / NW).  A worker
+// loads its next sample's entry, window and inputs while it transforms and
+// sums the current one, so the chain of dependent loads (entry, then
+// window) stays off the critical path, and it keeps its window transform
+// while consecutive samples share a window; the float64 sums are kept per
+// worker and added in worker order.
 //
 // Lane (h, c) of a worker loads rows [Hh, Hh + H) of column c of the reversed
 // window, H = S/2.  Each S-point transform is split in its first radix-2
