@@ -868,8 +868,9 @@ def test_support32_multi_item_blocks_ragged(torch_dev):
     items) on a ragged item count: 127 antennas of the large workload (8001
     baselines), 31 channels, one timestep in each of its first three
     intervals: 744,093 items, so the whole-batch launch ends on a block of
-    29 and has blocks that straddle two intervals.  Every visibility and
-    every per-antenna sum against the oracle at perturbed offsets; then
+    29 and has blocks that straddle two intervals.  Every visibility, every
+    per-antenna sum and the adjoint against the oracle at perturbed offsets;
+    then
     Algorithm 1 with the first interval starting at the true offsets (done
     after one step, so the later whole-batch launches skip its items inside
     blocks shared with the second interval): plain (one item per block),
@@ -892,7 +893,7 @@ def test_support32_multi_item_blocks_ragged(torch_dev):
         start = synth.perturbed_offsets(obs, 30.0, 25)
         v = oracle.predict(prob, obs.offsets_true)
         vp = s.predict(start).cpu().numpy()
-        vp_ref = oracle.predict(prob, start)
+        vp_ref, dv = oracle.predict(prob, start, want_grad=True)
         w1 = torch.ones(s.vis_shape, dtype=torch.float32, device=s.dev)
         g_v = c64(torch, s, v)
         acc = s.gradient(s.offsets(start), g_v, w1).cpu().numpy()
@@ -900,10 +901,24 @@ def test_support32_multi_item_blocks_ragged(torch_dev):
         e_v, e_el = rel(vp, vp_ref), elem_err(vp, vp_ref)
         e_a = [rel(acc[live][..., k], ref[live][..., k]) for k in range(6)]
         e_ant = per_antenna_err(acc[live], ref[live])
+        # the adjoint: sum over visibilities of Re(conj(G) dV/dp) per end
+        rng = np.random.default_rng(26)
+        G = (rng.normal(size=s.vis_shape) + 1j * rng.normal(size=s.vis_shape)).astype(np.complex64)
+        gc = G.astype(np.complex128).conj()
+        ti = (gc[..., None] * dv[..., 0:2]).real.sum(axis=1)  # [row][pol][axis], end i
+        tj = (gc[..., None] * dv[..., 2:4]).real.sum(axis=1)
+        row_int = np.searchsorted(obs.int_row_ptr, np.arange(obs.n_row), side="right") - 1
+        vjp_ref = np.zeros(s.off_shape)
+        for p in range(obs.n_pol):
+            np.add.at(vjp_ref[:, p], (row_int, obs.ant1), ti[:, p, :])
+            np.add.at(vjp_ref[:, p], (row_int, obs.ant2), tj[:, p, :])
+        vjp = s.vjp(s.offsets(start), torch.as_tensor(G, device=s.dev)).cpu().numpy()
+        e_j = rel(vjp[live], vjp_ref[live])
         print(f"multi-item blocks: vis rel {e_v:.2e}, max element {e_el:.2e}, acc rel {max(e_a):.2e}, "
-              f"per antenna {max(e_ant):.2e}", flush=True)
+              f"per antenna {max(e_ant):.2e}, adjoint rel {e_j:.2e}", flush=True)
         assert e_v <= 1e-5 and e_el <= ELEM_VIS_TOL
         assert max(e_a) <= 1e-4 and max(e_ant) <= ANT_SUM_TOL
+        assert e_j <= 1e-4
         # the first interval from the true offsets: its step is the model's
         # error alone, far below the tolerance
         start[0] = obs.offsets_true[0]
